@@ -1,0 +1,349 @@
+"""Pins of the FP64 CPU oracle against facts the paper and the mathematics fix (no GPU).
+
+Each test checks the oracle against something other than itself: closed forms, exactness
+properties, convergence orders, the paper's propositions, brute-force solves, published generator
+outputs.  They are chosen so that a dropped term, a wrong sign, a swapped index or a transposed
+operand in the oracle fails at least one of them.
+"""
+import itertools
+import math
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from oracle.asdsm_oracle import (BandedBoxSolver, Grid, Oracle, apply_operator, assemble_operator,
+                                 boolean_sum_extend, fine_direct_solve, op1d, permutation,
+                                 rhs_on_mesh, spline_matrix, splitmix64_stream)
+from paper_2303_01163_amd.workloads import make_problem
+
+GOLDEN = Path(__file__).parent / "golden"
+
+
+# ----------------------------------------------------------------------------- operators, solver
+@pytest.mark.parametrize("beta", [0.0, 0.7, -3.0, 15.0])
+def test_1d_closed_form(beta):
+    """-alpha u'' + beta u' = s (constant), u(0)=u(1)=0, centred scheme.  The discrete solution is
+    C1 + C2 q^i + (s/beta) x_i with q = (1+P)/(1-P), P = beta h/(2 alpha) (the two roots of the
+    homogeneous recurrence are 1 and sub/super); for beta = 0 it is s x(1-x)/(2 alpha) exactly."""
+    alpha, s, N = 0.35, 2.5, 40
+    h = 1.0 / (N + 1)
+    x = np.arange(1, N + 1) * h
+    co = op1d(alpha, beta, h)
+    u = BandedBoxSolver((N,), [co]).solve(np.full(N, s))
+    if beta == 0.0:
+        exact = s * x * (1 - x) / (2 * alpha)
+    else:
+        P = beta * h / (2 * alpha)
+        q = (1 + P) / (1 - P)
+        i = np.arange(1, N + 1)
+        C2 = -(s / beta) / (q ** (N + 1) - 1.0)
+        exact = -C2 + C2 * q ** i + (s / beta) * x
+    assert np.max(np.abs(u - exact)) <= 1e-11 * max(1.0, np.max(np.abs(exact)))
+
+
+def _eigvec(co, N, m):
+    a, b, c = co
+    r = math.sqrt(a / c)
+    i = np.arange(1, N + 1)
+    v = r ** i * np.sin(i * m * math.pi / (N + 1))
+    lam = b - 2.0 * math.copysign(math.sqrt(a * c), 1.0) * math.cos(m * math.pi / (N + 1))
+    return v, lam
+
+
+@pytest.mark.parametrize("dims,spacing", [((7, 9), (1 / 8, 1 / 10)), ((5, 6, 4), (1 / 6, 1 / 7, 1 / 5)),
+                                          ((3, 11, 6), (1 / 4, 1 / 12, 1 / 7))])
+def test_tensor_eigenvector_rhs(dims, spacing):
+    """Box operator (Kronecker sum, x_1 fastest): the right-hand side prod_j v_j (v_j an eigenvector
+    r_j^i sin(i m_j pi/(N_j+1)) of axis j) has the solution rhs / sum_j lambda_j.  Distinct sizes,
+    spacings and coefficients per axis catch a transposed axis order or a wrong sign of beta."""
+    rng = np.random.default_rng(5)
+    d = len(dims)
+    alpha = 10 ** rng.uniform(-1, 0, d)
+    beta = rng.uniform(-1, 1, d)
+    coeffs = [op1d(alpha[j], beta[j], spacing[j]) for j in range(d)]
+    ms = [int(rng.integers(1, n + 1)) for n in dims]
+    vecs, lam = [], 0.0
+    for j in range(d):
+        v, l = _eigvec(coeffs[j], dims[j], ms[j])
+        vecs.append(v)
+        lam += l
+    rhs = vecs[0]
+    for j in range(1, d):
+        rhs = np.multiply.outer(rhs, vecs[j])
+    x = BandedBoxSolver(dims, coeffs).solve(rhs)
+    assert np.max(np.abs(x - rhs / lam)) <= 1e-12 * np.max(np.abs(rhs / lam))
+    # the assembled matrix applied to the x_1-fastest flattening equals the stencil form
+    A = assemble_operator(dims, coeffs)
+    y = (A @ (rhs / lam).reshape(-1, order="F")).reshape(dims, order="F")
+    assert np.max(np.abs(y - rhs)) <= 1e-12 * np.max(np.abs(rhs))
+    assert np.max(np.abs(apply_operator(rhs / lam, coeffs) - rhs)) <= 1e-12 * np.max(np.abs(rhs))
+
+
+def test_stencil_pointwise_loops():
+    """The assembled A_ff equals eq. (1)'s centred differences written point by point."""
+    rng = np.random.default_rng(2)
+    N, h = 5, 1.0 / 6
+    alpha = [0.3, 0.8, 0.5]
+    beta = [1.5, -0.4, 2.0]
+    u = rng.standard_normal((N, N, N))
+    A = assemble_operator((N,) * 3, [op1d(alpha[j], beta[j], h) for j in range(3)])
+    Au = (A @ u.reshape(-1, order="F")).reshape((N,) * 3, order="F")
+
+    def val(i, j, k):
+        return u[i, j, k] if 0 <= i < N and 0 <= j < N and 0 <= k < N else 0.0
+
+    for i, j, k in itertools.product(range(N), repeat=3):
+        acc = 0.0
+        for ax, (di, dj, dk) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+            up = val(i + di, j + dj, k + dk)
+            dn = val(i - di, j - dj, k - dk)
+            acc += -alpha[ax] * (up - 2 * u[i, j, k] + dn) / h ** 2 + beta[ax] * (up - dn) / (2 * h)
+        assert abs(acc - Au[i, j, k]) <= 1e-10 * (1 + abs(acc))
+
+
+@pytest.mark.parametrize("d,L", [(2, 4), (2, 6), (3, 4)])
+def test_q2_exact_residual(d, L):
+    """Centred second differences are exact on quadratics and centred first differences on
+    quadratics too, so a product of quadratics with its analytic source has a zero fine residual
+    (Dirichlet data placed in b) -- on the fine mesh and on every submesh."""
+    P = make_problem("quadratic", L, seed=3 + d, d=d)
+    o = Oracle(d, P.alpha, P.beta, L)
+    g = o.grid
+    b = o.fine_rhs(P.s, P.g)
+    r = o.residual(P.u_exact, b)
+    assert np.max(np.abs(r)) <= 1e-11 * np.max(np.abs(b))
+    for r_ in range(1, d + 1):
+        for S in itertools.combinations(range(d), r_):
+            bS = rhs_on_mesh(g, S, P.s, P.g, P.alpha, P.beta)
+            uS = g.restrict(P.u_exact, S)
+            coeffs = [op1d(P.alpha[j], P.beta[j], sp) for j, sp in enumerate(g.mesh_spacings(S))]
+            res = bS - apply_operator(uS, coeffs)
+            assert np.max(np.abs(res)) <= 1e-11 * np.max(np.abs(bS)), S
+
+
+def test_discretisation_order_h2():
+    """||u_ff - u|| falls by ~4 per fine level (second-order scheme, Section 2.3)."""
+    errs = []
+    for L in (4, 5, 6, 7):
+        P = make_problem("sinprod2d", L, seed=1)
+        u = fine_direct_solve(2, P.alpha, P.beta, L, P.s, P.g)
+        errs.append(np.max(np.abs(u - P.u_exact)))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(3.5 < q < 4.6 for q in ratios), ratios
+
+
+# ----------------------------------------------------------------------------- geometry
+@pytest.mark.parametrize("d,L,Lc", [(2, 6, 3), (3, 5, 2), (3, 4, 1)])
+def test_mesh_relations(d, L, Lc):
+    """Proposition 2.1 (sub-mesh relations, disjoint holes, holes = fine minus skeleton) and
+    Proposition 2.4 (P P^T = I) for the d-dimensional family of Section 3.5."""
+    g = Grid(d, L, Lc)
+    assert g.Nf + 1 == g.n * (g.Nc + 1)                       # eq. (3)
+    cnt = g.coarse_count()
+    skel = cnt >= 1
+    holes = g.hole_mask()
+    assert not np.any(skel & holes) and np.all(skel | holes)
+    # holes: (N_c+1)^d disjoint boxes of (n-1)^d points
+    assert holes.sum() == (g.Nc + 1) ** d * (g.n - 1) ** d
+    cover = np.zeros_like(cnt)
+    for st in itertools.product(g.hole_starts(), repeat=d):
+        sl = tuple(slice(s0, s0 + g.hole_len) for s0 in st)
+        cover[sl] += 1
+    assert np.array_equal(cover == 1, holes) and cover.max() == 1
+    # skeleton = union of the anisotropic meshes; intersections = points with >= 2 coarse coords
+    union = np.zeros_like(skel)
+    for k in range(d):
+        union |= g.coarse_mask(k)
+    assert np.array_equal(union, skel)
+    rng = np.random.default_rng(0)
+    for r_ in range(1, d + 1):
+        for S in itertools.combinations(range(d), r_):
+            v = rng.standard_normal(g.mesh_dims(S))
+            assert np.array_equal(g.restrict(g.prolong(v, S), S), v)     # P P^T = I
+            assert g.mesh_dims(S) == tuple(g.Nc if j in S else g.Nf for j in range(d))
+
+
+# ----------------------------------------------------------------------------- spline
+def _cubic(x):
+    return x * (1 - x) * (x - 0.3)
+
+
+@pytest.mark.parametrize("L,Lc", [(6, 3), (5, 2), (7, 4)])
+def test_spline_reproduces_cubics(L, Lc):
+    """A not-a-knot cubic spline through knots 0, H, .., 1 with zero end values reproduces any cubic
+    vanishing at 0 and 1.  A natural spline would not (p''(0) != 0 here).  Rows at knots are unit."""
+    g = Grid(2, L, Lc)
+    Sp = spline_matrix(g)
+    xk = (np.arange(1, g.Nc + 1)) * g.H
+    xf = np.arange(1, g.Nf + 1) * g.h
+    assert np.max(np.abs(Sp @ _cubic(xk) - _cubic(xf))) <= 1e-13
+    for c, i in enumerate(g.cidx):
+        e = np.zeros(g.Nc)
+        e[c] = 1.0
+        assert np.array_equal(Sp[i], e)
+
+
+def test_spline_single_knot_parabola():
+    g = Grid(2, 3, 1)     # N_c = 1: the parabola through (0,0), (1/2,1), (1,0)
+    Sp = spline_matrix(g)
+    xf = np.arange(1, g.Nf + 1) * g.h
+    assert np.max(np.abs(Sp[:, 0] - 4 * xf * (1 - xf))) <= 1e-14
+
+
+def test_boolean_sum_tensor_cubics():
+    """Transfinite (Boolean-sum) extension over two fine axes: exact for f(y, z) = p(y) q(z) and for
+    p(y) + q(z) with p, q cubics vanishing at 0 and 1 (the latter only because of the -P_a P_b term:
+    a spline with zero end values does not reproduce a function constant along its axis); equal to
+    the data on every line."""
+    g = Grid(3, 5, 2)
+    Sp = spline_matrix(g)
+    x = np.arange(1, g.Nf + 1) * g.h
+    p = _cubic(x)
+    q = x * (1 - x) * (0.6 - x) * 2.0
+    for f in (np.multiply.outer(p, q), p[:, None] + q[None, :]):
+        lines = {(0,): f[g.cidx, :], (1,): f[:, g.cidx], (0, 1): f[np.ix_(g.cidx, g.cidx)]}
+        ext = boolean_sum_extend(lines, [0, 1], Sp, g, f.shape)
+        assert np.max(np.abs(ext - f)) <= 1e-13
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal((g.Nf, g.Nf))          # arbitrary line data (consistent at corners)
+    lines = {(0,): f[g.cidx, :], (1,): f[:, g.cidx], (0, 1): f[np.ix_(g.cidx, g.cidx)]}
+    ext = boolean_sum_extend(lines, [0, 1], Sp, g, f.shape)
+    assert np.max(np.abs(ext[g.cidx, :] - f[g.cidx, :])) <= 1e-13
+    assert np.max(np.abs(ext[:, g.cidx] - f[:, g.cidx])) <= 1e-13
+
+
+# ----------------------------------------------------------------------------- cross points
+def _crosspoint_errors(d, L, Lc, P, uff):
+    o = Oracle(d, P.alpha, P.beta, L, Lc)
+    g = o.grid
+    sols = {}
+    for r_ in range(1, d + 1):
+        for S in itertools.combinations(range(d), r_):
+            sols[S] = o.solve_mesh(S, o.rhs(S, P.s, P.g))
+    uhat = o.extrapolated_crosspoints(sols)
+    cnt = g.coarse_count()
+    ext = [np.max(np.abs(uhat[cnt == r] - uff[cnt == r])) for r in range(2, d + 1)]
+    single = np.max(np.abs(g.prolong(sols[(0,)], (0,)) - uff)[g.coarse_mask(0) & (cnt >= 2)])
+    return ext, single
+
+
+def test_crosspoint_extrapolation_order_2d():
+    """Initial-guess cross points: the combination u_fc + u_cf - u_cc is O(H^4)-accurate against the
+    fine discrete solution, a single anisotropic solution only O(H^2)."""
+    P = make_problem("sinprod", 7, seed=3, d=2)
+    uff = fine_direct_solve(2, P.alpha, P.beta, 7, P.s, P.g)
+    res = [_crosspoint_errors(2, 7, Lc, P, uff) for Lc in (2, 3, 4)]
+    ext = [r[0][0] for r in res]
+    single = [r[1] for r in res]
+    assert ext[0] / ext[1] > 12 and ext[1] / ext[2] > 12, ext
+    assert 2.5 < single[0] / single[1] < 6 and 2.5 < single[1] / single[2] < 6, single
+
+
+def test_crosspoint_extrapolation_order_3d():
+    """d = 3: edges (u_j + u_k - u_jk) and corners ((u_1+u_2+u_3-u_123)/2) are O(H^4)."""
+    P = make_problem("sinprod", 5, seed=3, d=3)
+    uff = fine_direct_solve(3, P.alpha, P.beta, 5, P.s, P.g)
+    e2, _ = _crosspoint_errors(3, 5, 2, P, uff)
+    e3, _ = _crosspoint_errors(3, 5, 3, P, uff)
+    assert e2[0] / e3[0] > 10 and e2[1] / e3[1] > 10, (e2, e3)
+
+
+@pytest.mark.parametrize("d,L", [(2, 5), (3, 4)])
+def test_initial_guess_exact_on_q2(d, L):
+    """Every mesh reproduces a Q2 solution exactly, so the extrapolated cross points, a zero
+    discrepancy and the filler give u^(0) = u exactly."""
+    P = make_problem("quadratic", L, seed=9, d=d)
+    o = Oracle(d, P.alpha, P.beta, L)
+    u0, _ = o.initial_guess(P.s, P.g)
+    assert np.max(np.abs(u0 - P.u_exact)) <= 1e-12 * np.max(np.abs(P.u_exact))
+
+
+@pytest.mark.parametrize("d,L,fam", [(2, 6, "sinprod2d"), (3, 4, "sinbump3d")])
+def test_filler_reproduces_fine_solution(d, L, fam):
+    """Proposition 3.2(1): filling the holes of the skeleton of u_ff gives back u_ff."""
+    P = make_problem(fam, L, seed=4)
+    o = Oracle(d, P.alpha, P.beta, L)
+    uff = fine_direct_solve(d, P.alpha, P.beta, L, P.s, P.g)
+    skel = np.where(o.grid.hole_mask(), 0.0, uff)
+    filled = o.filler(skel, o.fine_rhs(P.s, P.g))
+    assert np.max(np.abs(filled - uff)) <= 1e-12 * np.max(np.abs(uff))
+
+
+# ----------------------------------------------------------------------------- iteration
+@pytest.mark.parametrize("d,L,fam", [(2, 6, "sinprod2d"), (3, 4, "sinbump3d")])
+def test_iteration_properties(d, L, fam):
+    """Proposition 3.2(2) / Remark 3.4: the residual vanishes on the holes for every iterate, and the
+    line search s = argmin_{s>=0} ||b - A(u + s e)|| makes ||r_k|| non-increasing."""
+    P = make_problem(fam, L, seed=0)
+    o = Oracle(d, P.alpha, P.beta, L, seed=11)
+    res = o.solve(P.s, P.g, max_iter=8, rtol=0, stag_window=0, keep_iterates=True)
+    b = o.fine_rhs(P.s, P.g)
+    holes = o.grid.hole_mask()
+    for u in res.iterates:
+        r = o.residual(u, b)
+        assert np.max(np.abs(r[holes])) <= 1e-10 * np.max(np.abs(b))
+        assert np.max(np.abs(r[~holes])) > 0
+    h = res.res_hist
+    assert all(h[i + 1] <= h[i] * (1 + 1e-12) for i in range(len(h) - 1))
+    assert h[-1] < h[0]
+
+
+def test_line_search_is_the_minimiser():
+    """Step 6 of Algorithm 4: the closed-form clamped step beats a dense scan over s >= 0."""
+    P = make_problem("sinprod2d", 5, seed=2)
+    o = Oracle(2, P.alpha, P.beta, 5, seed=3)
+    u0, b = o.initial_guess(P.s, P.g)
+    r = o.residual(u0, b)
+    e, _ = o.error_guess(r, permutation(3, 0, 2))
+    q = o.apply_A(e)
+    shat = max(0.0, float(np.sum(r * q) / np.sum(q * q)))
+    f = lambda s_: np.linalg.norm(o.residual(u0 + s_ * e, b))
+    scan = np.linspace(0, 4 * shat + 1e-12, 401)
+    assert f(shat) <= min(f(s_) for s_ in scan) * (1 + 1e-12)
+    res = o.solve(P.s, P.g, max_iter=1, rtol=0, stag_window=0)
+    assert abs(res.step_hist[0] - shat) <= 1e-12 * shat
+
+
+def test_resume_equals_continuous_run():
+    """Checkpoint/resume: (u^(k), k, seed) is the whole state, so 3 + 2 iterations equal 5."""
+    P = make_problem("sinprod2d", 5, seed=6)
+    o = Oracle(2, P.alpha, P.beta, 5, seed=21)
+    full = o.solve(P.s, P.g, max_iter=5, rtol=0, stag_window=0)
+    part = o.solve(P.s, P.g, max_iter=3, rtol=0, stag_window=0)
+    rest = o.solve(P.s, P.g, max_iter=2, rtol=0, stag_window=0, u0=part.u, k0=3)
+    assert np.array_equal(full.u, rest.u)
+
+
+def test_iteration_approaches_direct_solve_on_tiny_grids():
+    """On tiny grids the refinement moves u^(k) towards the brute-force solution u_ff = A^-1 b: the
+    error after the iterations is below that of u^(0).  (The paper reports stagnation, not
+    convergence, so the level reached is recorded rather than required to be 1e-10.)"""
+    for d, L, Lc in ((2, 4, 2), (2, 5, 3), (3, 3, 1), (3, 4, 2)):
+        fam = "sinprod2d" if d == 2 else "sinbump3d"
+        P = make_problem(fam, L, seed=1)
+        o = Oracle(d, P.alpha, P.beta, L, Lc, seed=1)
+        uff = fine_direct_solve(d, P.alpha, P.beta, L, P.s, P.g)
+        res = o.solve(P.s, P.g, max_iter=30, rtol=1e-13, stag_window=0, keep_iterates=True)
+        err0 = np.linalg.norm(res.iterates[0] - uff)
+        errK = np.linalg.norm(res.iterates[-1] - uff)
+        assert errK < err0, (d, L, Lc, err0, errK)
+
+
+# ----------------------------------------------------------------------------- random choice
+def test_splitmix64_published_outputs():
+    want = [int(l, 16) for l in (GOLDEN / "splitmix64_seed0.txt").read_text().split("\n")
+            if l.startswith("0x")]
+    assert splitmix64_stream(0, len(want)) == want
+
+
+def test_permutations_are_uniform_shuffles():
+    for d in (2, 3):
+        counts = {}
+        for k in range(3000):
+            p = tuple(permutation(12345, k, d))
+            assert sorted(p) == list(range(d))
+            counts[p] = counts.get(p, 0) + 1
+        assert len(counts) == math.factorial(d)
+        expect = 3000 / math.factorial(d)
+        assert all(abs(c - expect) < 6 * math.sqrt(expect) for c in counts.values())
