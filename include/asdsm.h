@@ -1,0 +1,148 @@
+/*
+ * asdsm.h -- C ABI of the MI355X (gfx950) implementation of the Anisotropic Submeshes Domain
+ * Splitting Method (ASDSM) for the steady, constant-coefficient advection-diffusion equation
+ *
+ *     -sum_i alpha_i d^2u/dx_i^2 + sum_i beta_i du/dx_i = s   on (0,1)^d,   u = g on the boundary
+ *
+ * (eq. (1) of the paper, with one alpha_i and one beta_i per axis).  The fine mesh has
+ * N_f = 2^level - 1 interior points per axis (h = 2^-level); the anisotropic submeshes are coarse
+ * (H = 2^-coarse_level, N_c = 2^coarse_level - 1 points) along one axis and fine along the others
+ * (Section 2.1 eqs. (3)-(5); Section 3.5 for d = 3).  The nesting condition eq. (3),
+ * N_f + 1 = n (N_c + 1), holds for every 1 <= coarse_level < level.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All floating point is IEEE binary64 (double).
+ * - Fine-mesh vectors (s, u, r) are device arrays of N_f^d doubles ordered with x_1 fastest
+ *   (the ordering of Section 2.2): index = i_1 + N_f*(i_2 + N_f*i_3), 0-based.
+ * - Dirichlet data g is a device array of 2*d*N_f^(d-1) doubles: 2*d faces ordered axis j = 1..d
+ *   and, per axis, side x_j = 0 then x_j = 1.  Each face holds g at the N_f^(d-1) interior grid
+ *   points of the remaining axes, in increasing axis order, lowest axis fastest.  Boundary edges
+ *   and corners are never read (the (2d+1)-point stencil does not reach them).
+ * - Device pointers must be valid for the plan's HIP device and stay alive until the call returns.
+ *   Every call is enqueued on the stream given to asdsm_plan and returns after that stream's work
+ *   has completed (calls are blocking).
+ * - Return status: 0 = ASDSM_OK, > 0 a warning (the result is valid), < 0 an error (outputs are
+ *   unspecified).  asdsm_last_error() returns a thread-local message describing the last error.
+ * - Plans are not thread-safe; distinct plans on distinct streams are independent.  No C++
+ *   exception crosses this interface.
+ */
+#ifndef ASDSM_H
+#define ASDSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define ASDSM_OK            0
+#define ASDSM_STAGNATED     1   /* warning: the stagnation rule stopped the iteration          */
+#define ASDSM_MAXITER       2   /* warning: max_iter iterations ran without meeting rtol        */
+#define ASDSM_E_ARG        -1   /* invalid argument (d, alpha, beta, level, NULL pointer, ...)  */
+#define ASDSM_E_NESTING    -2   /* coarse_level violates 1 <= coarse_level < level (eq. (3))     */
+#define ASDSM_E_WORKSPACE  -3   /* workspace missing, too small or misaligned                   */
+#define ASDSM_E_NUMERIC    -4   /* non-finite data or a non-finite intermediate                  */
+#define ASDSM_E_DEVICE     -5   /* a HIP runtime call failed                                     */
+#define ASDSM_E_UNSUPPORTED -6  /* valid by the paper but outside what this build implements    */
+
+/* ---- mesh identifiers for asdsm_mesh_solve: bit j set = axis j+1 is coarse ---- */
+#define ASDSM_MESH_FINE     0u
+
+/* ---- phases timed when asdsm_opts.profile != 0 ---- */
+#define ASDSM_PHASE_RHS        0   /* right-hand side assembly on the fine mesh and submeshes   */
+#define ASDSM_PHASE_TRANSFORM  1   /* mode transforms of the submesh solves (FP64 MFMA)          */
+#define ASDSM_PHASE_LINE       2   /* line / small dense solves along coarse axes                */
+#define ASDSM_PHASE_SKELETON   3   /* cross points, discrepancy, spline correction, merge       */
+#define ASDSM_PHASE_FILLER     4   /* hole right-hand sides, hole solves, fine-vector write     */
+#define ASDSM_PHASE_DOTS       5   /* q = A e and the line-search inner products                */
+#define ASDSM_PHASE_UPDATE     6   /* u += s e fused with r = b - A u, gather, norm             */
+#define ASDSM_NPHASE           7
+
+typedef struct asdsm_plan_s *asdsm_plan_t;
+
+/* Options of asdsm_solve.  Stopping rule (the paper's loop condition of Algorithm 4, read as
+ * "iterate while not converged and not stagnated"): iterate while ||r_k||_2 > rtol*||b_ff||_2 and
+ * k < max_iter and not stagnated; stagnated = ||r_{k+1}||_2 > (1 - stag_eta)*||r_k||_2 for
+ * stag_window consecutive iterations (stag_window = 0 disables it), or a zero line-search step. */
+typedef struct {
+    int    max_iter;      /* >= 0; 0 returns the initial guess of Algorithm 1                   */
+    double rtol;          /* >= 0                                                                */
+    int    stag_window;   /* >= 0                                                                */
+    double stag_eta;      /* in [0, 1)                                                           */
+    int    resume;        /* 0: start from Algorithm 1; 1: u holds the iterate u^(k0) on entry  */
+    int64_t k0;           /* iteration counter of the entry iterate (selects the random stream)  */
+    double *hist;         /* optional host array, length max_iter+1: ||r_k||_2 per iterate      */
+    double *step_hist;    /* optional host array, length max_iter: the line-search step s_k     */
+    int    profile;       /* nonzero: time each phase with HIP events (adds synchronisation)    */
+} asdsm_opts;
+
+typedef struct {
+    int    status;        /* same as the return value                                            */
+    int    iterations;    /* iterations performed by this call                                   */
+    double bnorm;         /* ||b_ff||_2                                                          */
+    double r0norm;        /* ||r||_2 of the entry iterate                                        */
+    double rnorm;         /* ||r||_2 of the returned iterate                                     */
+    double phase_ms[ASDSM_NPHASE];      /* accumulated device time per phase (profile only)      */
+    int    phase_launches[ASDSM_NPHASE];/* kernel launches per phase (profile only)              */
+    double total_ms;      /* device time of the whole call (profile only)                        */
+} asdsm_stats;
+
+/* Create a plan (Section 2.1 meshes, Section 2.3 operators, Algorithms 1-4 schedule).
+ *   d            : 2 or 3 (dimensions of eq. (1)).
+ *   alpha, beta  : host arrays of d finite doubles, alpha[j] > 0 (copied).
+ *   level        : fine level L, N_f = 2^L - 1, 2 <= L <= 10.
+ *   coarse_level : L_c with 1 <= L_c < L (eq. (3)); 0 selects floor(L/2).
+ *   seed         : seed of the counter-based random cross-point choice (Algorithm 2 step 3).
+ *   hip_stream   : hipStream_t (borrowed, may be NULL for the null stream).
+ * The plan owns its small host and device tables (operator spectra, transform matrices, spline
+ * matrix); the large work arrays live in a caller-owned workspace (asdsm_set_workspace).
+ * Errors: ASDSM_E_ARG, ASDSM_E_NESTING, ASDSM_E_UNSUPPORTED (|cell Peclet| >= 1 on a fine axis, or
+ * hole boxes too large for one workgroup's LDS), ASDSM_E_DEVICE. */
+int asdsm_plan(asdsm_plan_t *out, int d, const double *alpha, const double *beta, int level,
+               int coarse_level, uint64_t seed, void *hip_stream);
+
+/* Bytes of device workspace the plan needs (>= 256-byte aligned base required). */
+int asdsm_workspace_size(asdsm_plan_t plan, size_t *bytes);
+
+/* Attach caller-owned device memory (not freed by the library).  ASDSM_E_WORKSPACE if NULL,
+ * too small or not 256-byte aligned. */
+int asdsm_set_workspace(asdsm_plan_t plan, void *dev, size_t bytes);
+
+/* ASDSM (Algorithm 4): u^(0) = InitialGuess (Algorithm 1, with Skeleton Algorithm 2 and Filler
+ * Algorithm 3) unless opts->resume, then refinement steps r = b - A u, error guess on the
+ * submeshes, line search s = argmin_{s>=0} ||b - A(u + s e)||, u += s e.
+ *   s : device, N_f^d source values at the fine points.
+ *   g : device, Dirichlet faces (layout above).
+ *   u : device, N_f^d, output iterate (input iterate u^(k0) when opts->resume).
+ *   opts : host, may be NULL (defaults: max_iter 50, rtol 1e-10, stag_window 3, stag_eta 1e-3).
+ *   stats: host, may be NULL.
+ * Returns ASDSM_OK (rtol met), ASDSM_STAGNATED, ASDSM_MAXITER, or an error. */
+int asdsm_solve(asdsm_plan_t plan, const double *s, const double *g, double *u,
+                const asdsm_opts *opts, asdsm_stats *stats);
+
+/* Fine residual r = b_ff - A_ff u (Algorithm 4 step 3), b_ff = s plus the Dirichlet terms.
+ *   r     : device output of N_f^d doubles, may be NULL.
+ *   norm2 : host output ||r||_2, may be NULL. */
+int asdsm_residual(asdsm_plan_t plan, const double *u, const double *s, const double *g,
+                   double *r, double *norm2);
+
+/* Direct solve of one mesh system A_S x = rhs with zero Dirichlet data (the submesh solves of
+ * Algorithm 1 step 1, eq. (6)).  mesh_mask: bit j set = axis j+1 coarse; ASDSM_MESH_FINE is not
+ * accepted; the all-coarse mask is the coarse mesh.  rhs and x are device arrays in the mesh's
+ * canonical layout: the fine axes in increasing order, then the coarse axes in increasing order,
+ * first listed axis fastest.  rhs and x may not alias. */
+int asdsm_mesh_solve(asdsm_plan_t plan, unsigned mesh_mask, const double *rhs, double *x);
+
+/* Release the plan and its tables (not the workspace).  NULL is ignored. */
+void asdsm_destroy(asdsm_plan_t plan);
+
+/* Thread-local description of the last error ("" if none). */
+const char *asdsm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASDSM_H */

@@ -1,0 +1,198 @@
+"""Thin Python binding of the ASDSM C ABI (``include/asdsm.h``).
+
+Argument marshalling only: every step of the method runs inside ``libasdsm.so`` on the GPU.  PyTorch
+provides the device memory (float64 tensors, the byte workspace) and the stream.  There is no CPU
+fallback: if the library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int, c_int64, c_size_t, c_uint, c_uint64, c_void_p
+from pathlib import Path
+
+LIB_PATH = Path(__file__).resolve().with_name("libasdsm.so")
+
+ASDSM_OK, ASDSM_STAGNATED, ASDSM_MAXITER = 0, 1, 2
+ASDSM_E_ARG, ASDSM_E_NESTING, ASDSM_E_WORKSPACE = -1, -2, -3
+ASDSM_E_NUMERIC, ASDSM_E_DEVICE, ASDSM_E_UNSUPPORTED = -4, -5, -6
+NPHASE = 7
+PHASES = ("rhs", "transform", "line", "skeleton", "filler", "dots", "update")
+STATUS_NAMES = {0: "ok", 1: "stagnated", 2: "maxiter"}
+
+# symbols declared in include/asdsm.h
+EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_solve",
+            "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error")
+
+
+class AsdsmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ASDSM error {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("max_iter", c_int), ("rtol", c_double), ("stag_window", c_int),
+                ("stag_eta", c_double), ("resume", c_int), ("k0", c_int64),
+                ("hist", POINTER(c_double)), ("step_hist", POINTER(c_double)), ("profile", c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", c_int), ("iterations", c_int), ("bnorm", c_double),
+                ("r0norm", c_double), ("rnorm", c_double), ("phase_ms", c_double * NPHASE),
+                ("phase_launches", c_int * NPHASE), ("total_ms", c_double)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libasdsm.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2303_01163_amd.build`")
+    lib = ctypes.CDLL(str(LIB_PATH))
+    lib.asdsm_plan.argtypes = [POINTER(c_void_p), c_int, POINTER(c_double), POINTER(c_double),
+                               c_int, c_int, c_uint64, c_void_p]
+    lib.asdsm_plan.restype = c_int
+    lib.asdsm_workspace_size.argtypes = [c_void_p, POINTER(c_size_t)]
+    lib.asdsm_workspace_size.restype = c_int
+    lib.asdsm_set_workspace.argtypes = [c_void_p, c_void_p, c_size_t]
+    lib.asdsm_set_workspace.restype = c_int
+    lib.asdsm_solve.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(Opts), POINTER(Stats)]
+    lib.asdsm_solve.restype = c_int
+    lib.asdsm_residual.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double)]
+    lib.asdsm_residual.restype = c_int
+    lib.asdsm_mesh_solve.argtypes = [c_void_p, c_uint, c_void_p, c_void_p]
+    lib.asdsm_mesh_solve.restype = c_int
+    lib.asdsm_destroy.argtypes = [c_void_p]
+    lib.asdsm_destroy.restype = None
+    lib.asdsm_last_error.argtypes = []
+    lib.asdsm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise AsdsmError(rc, load_library().asdsm_last_error().decode())
+    return rc
+
+
+def _dptr(t, n=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return c_void_p(t.data_ptr())
+
+
+class Plan:
+    """An ASDSM plan on one GPU: d in {2,3}, per-axis alpha/beta, fine level L, coarse level L_c."""
+
+    def __init__(self, d, alpha, beta, level, coarse_level=0, seed=0, device=None, stream=None):
+        import torch
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("ASDSM needs a HIP GPU; none is available")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.d = int(d)
+        self.level = int(level)
+        self.coarse_level = int(coarse_level) if coarse_level else self.level // 2
+        self.n_f = 2 ** self.level - 1
+        self.n_c = 2 ** self.coarse_level - 1
+        self.seed = int(seed)
+        a = (c_double * self.d)(*[float(x) for x in alpha])
+        b = (c_double * self.d)(*[float(x) for x in beta])
+        self._h = c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.asdsm_plan(byref(self._h), self.d, a, b, self.level, self.coarse_level,
+                                  c_uint64(self.seed & 0xFFFFFFFFFFFFFFFF),
+                                  c_void_p(self.stream.cuda_stream)))
+            nbytes = c_size_t()
+            _check(lib.asdsm_workspace_size(self._h, byref(nbytes)))
+            self.workspace_bytes = int(nbytes.value)
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            _check(lib.asdsm_set_workspace(self._h, c_void_p(aligned), c_size_t(self.workspace_bytes)))
+
+    @property
+    def n_fine(self) -> int:
+        return self.n_f ** self.d
+
+    def mesh_shape(self, mask: int) -> tuple:
+        """Canonical layout of mesh M_S: fine axes (increasing) then coarse axes, first fastest."""
+        fine = [j for j in range(self.d) if not (mask >> j) & 1]
+        coarse = [j for j in range(self.d) if (mask >> j) & 1]
+        return tuple([self.n_f] * len(fine) + [self.n_c] * len(coarse)), fine + coarse
+
+    def solve(self, s, g, u=None, max_iter=50, rtol=1e-10, stag_window=3, stag_eta=1e-3,
+              resume=False, k0=0, profile=False):
+        import torch
+        lib = load_library()
+        if u is None:
+            u = torch.empty(self.n_fine, dtype=torch.float64, device=self.device)
+        hist = (c_double * (max_iter + 1))()
+        steps = (c_double * max(max_iter, 1))()
+        o = Opts(max_iter=int(max_iter), rtol=float(rtol), stag_window=int(stag_window),
+                 stag_eta=float(stag_eta), resume=1 if resume else 0, k0=int(k0),
+                 hist=ctypes.cast(hist, POINTER(c_double)),
+                 step_hist=ctypes.cast(steps, POINTER(c_double)), profile=1 if profile else 0)
+        st = Stats()
+        with torch.cuda.device(self.device):
+            rc = _check(lib.asdsm_solve(self._h, _dptr(s, self.n_fine, "s"),
+                                        _dptr(g, 2 * self.d * self.n_f ** (self.d - 1), "g"),
+                                        _dptr(u, self.n_fine, "u"), byref(o), byref(st)))
+        it = st.iterations
+        info = {
+            "status": rc, "status_name": STATUS_NAMES.get(rc, str(rc)), "iterations": it,
+            "bnorm": st.bnorm, "r0norm": st.r0norm, "rnorm": st.rnorm,
+            "res_hist": [hist[i] for i in range(it + 1)],
+            "step_hist": [steps[i] for i in range(it)],
+        }
+        if profile:
+            info["phase_ms"] = {PHASES[q]: st.phase_ms[q] for q in range(NPHASE)}
+            info["phase_launches"] = {PHASES[q]: st.phase_launches[q] for q in range(NPHASE)}
+            info["total_ms"] = st.total_ms
+        return u, info
+
+    def residual(self, u, s, g, want_r=True):
+        import torch
+        lib = load_library()
+        r = torch.empty(self.n_fine, dtype=torch.float64, device=self.device) if want_r else None
+        nrm = c_double()
+        with torch.cuda.device(self.device):
+            _check(lib.asdsm_residual(self._h, _dptr(u, self.n_fine, "u"), _dptr(s, self.n_fine, "s"),
+                                      _dptr(g, 2 * self.d * self.n_f ** (self.d - 1), "g"),
+                                      _dptr(r, self.n_fine, "r") if want_r else None, byref(nrm)))
+        return r, nrm.value
+
+    def mesh_solve(self, mask: int, rhs):
+        import torch
+        lib = load_library()
+        shape, _ = self.mesh_shape(mask)
+        n = 1
+        for e in shape:
+            n *= e
+        x = torch.empty(n, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib.asdsm_mesh_solve(self._h, c_uint(mask), _dptr(rhs, n, "rhs"), _dptr(x, n, "x")))
+        return x
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().asdsm_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

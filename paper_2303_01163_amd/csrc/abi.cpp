@@ -1,0 +1,576 @@
+// C ABI entry points and the ASDSM driver (Algorithms 1-4) on one HIP stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "asdsm_internal.hpp"
+#include "kernels.hpp"
+
+namespace asdsm {
+const char *last_error_cstr();
+
+namespace {
+
+#define ASDSM_HIP_CHECK(expr)                                                                    \
+    do {                                                                                          \
+        hipError_t _e = (expr);                                                                   \
+        if (_e != hipSuccess) return fail(ASDSM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+int check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ASDSM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return ASDSM_OK;
+}
+
+// Phase timing (opts->profile): events around a group of launches, synchronised per phase.
+struct PhaseTimer {
+    Plan &p;
+    int phase;
+    int launches;
+    PhaseTimer(Plan &pl, int ph, int nl) : p(pl), phase(ph), launches(nl) {
+        if (p.profiling) (void)hipEventRecord(p.ev_begin, p.stream);
+    }
+    ~PhaseTimer() {
+        if (!p.profiling) return;
+        (void)hipEventRecord(p.ev_end, p.stream);
+        (void)hipEventSynchronize(p.ev_end);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p.ev_begin, p.ev_end);
+        p.phase_ms[phase] += ms;
+        p.phase_launches[phase] += launches;
+    }
+};
+
+void fine_axes(int d, int k, int &a, int &b) {
+    if (d == 2) {
+        a = 1 - k;
+        b = -1;
+    } else {
+        a = (k == 0) ? 1 : 0;
+        b = (k == 2) ? 1 : 2;
+    }
+}
+
+// Anisotropic-mesh solves, in place on X_k for every k with bit k of kbits set.
+int solve_aniso(Plan &p, unsigned kbits) {
+    const int d = p.d, Nf = p.Nf, Nc = p.Nc;
+    int ks[kMaxD], nb = 0;
+    for (int k = 0; k < d; ++k)
+        if ((kbits >> k) & 1u) ks[nb++] = k;
+    if (nb == 0) return ASDSM_OK;
+    const long long Nf2 = (long long)Nf * Nf;
+    GemmJob j{};
+    j.nbox = nb;
+    // forward transform along canonical axis 0 (contiguous): X -> Y
+    {
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
+        j.M = (d == 2) ? Nc : Nf * Nc;
+        j.N = Nf;
+        j.K = Nf;
+        j.nbatch = 1;
+        j.sAb = j.sBb = j.sCb = 0;
+        j.sAi = Nf; j.sAk = 1;
+        j.sBk = 1;  j.sBn = Nf;
+        j.sCi = Nf; j.sCn = 1;
+        for (int q = 0; q < nb; ++q) {
+            int a, b;
+            fine_axes(d, ks[q], a, b);
+            j.A[q] = p.ws.X[1u << ks[q]];
+            j.B[q] = p.dW[a];
+            j.C[q] = p.ws.Y[1u << ks[q]];
+        }
+        launch_gemm(j, p.stream);
+        if (int rc = check_launch("transform")) return rc;
+    }
+    if (d == 3) {
+        // forward along canonical axis 1, batched over the coarse slabs: Y -> X
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
+        j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc;
+        j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
+        j.sBb = Nf2; j.sBk = Nf; j.sBn = 1;
+        j.sCb = Nf2; j.sCi = Nf; j.sCn = 1;
+        for (int q = 0; q < nb; ++q) {
+            int a, b;
+            fine_axes(d, ks[q], a, b);
+            j.A[q] = p.dW[b];
+            j.B[q] = p.ws.Y[1u << ks[q]];
+            j.C[q] = p.ws.X[1u << ks[q]];
+        }
+        launch_gemm(j, p.stream);
+        if (int rc = check_launch("transform")) return rc;
+    }
+    // line elimination along the coarse axis
+    {
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
+        LineJob L{};
+        L.nbox = nb;
+        L.nmodes = (d == 2) ? Nf : Nf2;
+        L.ext_a = Nf;
+        L.ncoarse = Nc;
+        for (int q = 0; q < nb; ++q) {
+            int a, b;
+            const int k = ks[q];
+            fine_axes(d, k, a, b);
+            // d = 2: data in Y (scratch X); d = 3: data in X (scratch Y)
+            L.X[q] = (d == 2) ? p.ws.Y[1u << k] : p.ws.X[1u << k];
+            L.scratch[q] = (d == 2) ? p.ws.X[1u << k] : p.ws.Y[1u << k];
+            L.mu_a[q] = p.dmu[a];
+            L.mu_b[q] = (d == 3) ? p.dmu[b] : nullptr;
+            L.t[q] = p.geo.coarse[k];
+        }
+        launch_line(L, p.stream);
+        if (int rc = check_launch("line")) return rc;
+    }
+    if (d == 3) {
+        // backward along canonical axis 1: X -> Y
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
+        j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc;
+        j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
+        j.sBb = Nf2; j.sBk = Nf; j.sBn = 1;
+        j.sCb = Nf2; j.sCi = Nf; j.sCn = 1;
+        for (int q = 0; q < nb; ++q) {
+            int a, b;
+            fine_axes(d, ks[q], a, b);
+            j.A[q] = p.dV[b];
+            j.B[q] = p.ws.X[1u << ks[q]];
+            j.C[q] = p.ws.Y[1u << ks[q]];
+        }
+        launch_gemm(j, p.stream);
+        if (int rc = check_launch("transform")) return rc;
+    }
+    {
+        // backward along canonical axis 0: Y -> X
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
+        j.M = (d == 2) ? Nc : Nf * Nc;
+        j.N = Nf; j.K = Nf; j.nbatch = 1;
+        j.sAb = j.sBb = j.sCb = 0;
+        j.sAi = Nf; j.sAk = 1;
+        j.sBk = 1;  j.sBn = Nf;
+        j.sCi = Nf; j.sCn = 1;
+        for (int q = 0; q < nb; ++q) {
+            int a, b;
+            fine_axes(d, ks[q], a, b);
+            j.A[q] = p.ws.Y[1u << ks[q]];
+            j.B[q] = p.dV[a];
+            j.C[q] = p.ws.X[1u << ks[q]];
+        }
+        launch_gemm(j, p.stream);
+        if (int rc = check_launch("transform")) return rc;
+    }
+    return ASDSM_OK;
+}
+
+// Intersection-mesh solve (>= 2 coarse axes): X_S -> result in Y_S.
+int solve_intersection(Plan &p, unsigned mask) {
+    const MeshDesc &m = p.mesh[mask];
+    if (m.nfine == 0) {
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
+        launch_dense_modes(1, m.block, p.ddense[mask], p.ws.X[mask], p.ws.Y[mask], p.stream);
+        return check_launch("dense");
+    }
+    // one fine axis (d = 3 edge meshes): transform, per-mode dense solve, back-transform
+    const int f = m.ax[0];
+    GemmJob j{};
+    j.nbox = 1;
+    j.M = m.block; j.N = p.Nf; j.K = p.Nf; j.nbatch = 1;
+    j.sAb = j.sBb = j.sCb = 0;
+    j.sAi = p.Nf; j.sAk = 1;
+    j.sBk = 1;    j.sBn = p.Nf;
+    j.sCi = p.Nf; j.sCn = 1;
+    {
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
+        j.A[0] = p.ws.X[mask];
+        j.B[0] = p.dW[f];
+        j.C[0] = p.ws.Y[mask];
+        launch_gemm(j, p.stream);
+        if (int rc = check_launch("transform")) return rc;
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
+        launch_dense_modes(m.nmodes, m.block, p.ddense[mask], p.ws.Y[mask], p.ws.X[mask], p.stream);
+        if (int rc = check_launch("dense")) return rc;
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
+        j.A[0] = p.ws.X[mask];
+        j.B[0] = p.dV[f];
+        j.C[0] = p.ws.Y[mask];
+        launch_gemm(j, p.stream);
+        if (int rc = check_launch("transform")) return rc;
+    }
+    return ASDSM_OK;
+}
+
+// Refinement sweeps around the direct mesh solves (only where the plan asked for them):
+// save f, x = M^-1 f, then repeatedly x += M^-1 (f - A x).  The result stays where the plain solve
+// leaves it (X for the anisotropic meshes, Y for the intersection meshes).
+int copy_dd(Plan &p, double *dst, const double *src, long long n) {
+    ASDSM_HIP_CHECK(hipMemcpyAsync(dst, src, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
+    return ASDSM_OK;
+}
+
+int solve_aniso_refined(Plan &p, unsigned kbits) {
+    int ns = 0;
+    unsigned masks[kMaxD];
+    int nb = 0;
+    for (int k = 0; k < p.d; ++k)
+        if ((kbits >> k) & 1u) {
+            masks[nb++] = 1u << k;
+            ns = std::max(ns, p.sweeps[1u << k]);
+        }
+    if (ns == 0) return solve_aniso(p, kbits);
+    const long long n = p.mesh[1].size;
+    for (int q = 0; q < nb; ++q)
+        if (int rc = copy_dd(p, p.ws.Z[masks[q]], p.ws.X[masks[q]], n)) return rc;
+    if (int rc = solve_aniso(p, kbits)) return rc;
+    for (int q = 0; q < nb; ++q)
+        if (int rc = copy_dd(p, p.ws.W[masks[q]], p.ws.X[masks[q]], n)) return rc;
+    for (int sweep = 0; sweep < ns; ++sweep) {
+        BoxResJob job{};
+        job.nbox = nb;
+        double *ys[kMaxD];
+        const double *xs[kMaxD];
+        for (int q = 0; q < nb; ++q) {
+            job.f[q] = p.ws.Z[masks[q]];
+            job.x[q] = p.ws.W[masks[q]];
+            job.out[q] = p.ws.X[masks[q]];
+            job.m[q] = p.mesh[masks[q]];
+            ys[q] = p.ws.W[masks[q]];
+            xs[q] = p.ws.X[masks[q]];
+        }
+        launch_box_residual(p, job, p.stream);
+        if (int rc = check_launch("box residual")) return rc;
+        if (int rc = solve_aniso(p, kbits)) return rc;
+        launch_axpy(ys, xs, n, nb, p.stream);
+        if (int rc = check_launch("axpy")) return rc;
+    }
+    for (int q = 0; q < nb; ++q)
+        if (int rc = copy_dd(p, p.ws.X[masks[q]], p.ws.W[masks[q]], n)) return rc;
+    return ASDSM_OK;
+}
+
+int solve_intersection_refined(Plan &p, unsigned mask) {
+    const int ns = p.sweeps[mask];
+    if (ns == 0) return solve_intersection(p, mask);
+    const long long n = p.mesh[mask].size;
+    if (int rc = copy_dd(p, p.ws.Z[mask], p.ws.X[mask], n)) return rc;
+    if (int rc = solve_intersection(p, mask)) return rc;
+    if (int rc = copy_dd(p, p.ws.W[mask], p.ws.Y[mask], n)) return rc;
+    for (int sweep = 0; sweep < ns; ++sweep) {
+        BoxResJob job{};
+        job.nbox = 1;
+        job.f[0] = p.ws.Z[mask];
+        job.x[0] = p.ws.W[mask];
+        job.out[0] = p.ws.X[mask];
+        job.m[0] = p.mesh[mask];
+        launch_box_residual(p, job, p.stream);
+        if (int rc = check_launch("box residual")) return rc;
+        if (int rc = solve_intersection(p, mask)) return rc;
+        double *ys[1] = {p.ws.W[mask]};
+        const double *xs[1] = {p.ws.Y[mask]};
+        launch_axpy(ys, xs, n, 1, p.stream);
+        if (int rc = check_launch("axpy")) return rc;
+    }
+    return copy_dd(p, p.ws.Y[mask], p.ws.W[mask], n);
+}
+
+void result_pointers(const Plan &p, const double *res[kMaxMeshes]) {
+    for (unsigned s = 0; s < kMaxMeshes; ++s) res[s] = nullptr;
+    for (unsigned s = 1; s < (1u << p.d); ++s)
+        res[s] = (__builtin_popcount(s) == 1) ? p.ws.X[s] : p.ws.Y[s];
+}
+
+int read_scalars(Plan &p) {
+    ASDSM_HIP_CHECK(hipMemcpyAsync(p.hscal, p.ws.scal, kScalCount * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
+    return ASDSM_OK;
+}
+
+// Algorithm 1 with the source: u^(0) into u, then r = b - A u^(0) with its gathers.
+int initial_guess(Plan &p, const double *s, const double *g, double *u) {
+    const unsigned nm = 1u << p.d;
+    {
+        PhaseTimer t(p, ASDSM_PHASE_RHS, (int)nm);
+        launch_rhs(p, 0, s, g, p.ws.b, p.ws.scal + kScalBnorm2, p.stream);
+        for (unsigned m = 1; m < nm; ++m) launch_rhs(p, m, s, g, p.ws.X[m], nullptr, p.stream);
+        if (int rc = check_launch("rhs")) return rc;
+    }
+    if (int rc = solve_aniso_refined(p, nm - 1)) return rc;
+    for (unsigned m = 1; m < nm; ++m)
+        if (__builtin_popcount(m) >= 2)
+            if (int rc = solve_intersection_refined(p, m)) return rc;
+    const double *res[kMaxMeshes];
+    result_pointers(p, res);
+    {
+        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 3 : 2);
+        launch_crosspoints(p, 0, nullptr, res, p.stream);
+        launch_merge(p, 0, nullptr, res, p.stream);
+        if (int rc = check_launch("skeleton")) return rc;
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1);
+        launch_filler(p, p.ws.b, u, p.stream);
+        if (int rc = check_launch("filler")) return rc;
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1);
+        launch_update_residual(p, u, nullptr, nullptr, p.stream);
+        if (int rc = check_launch("residual")) return rc;
+    }
+    return ASDSM_OK;
+}
+
+// One refinement step of Algorithm 4 from u_cur (with r and its gathers current) into u_next.
+int refine_step(Plan &p, int64_t k, const double *u_cur, double *u_next) {
+    if (int rc = solve_aniso_refined(p, (1u << p.d) - 1)) return rc;
+    int perm[kMaxD];
+    axis_permutation(p.seed, k, p.d, perm);
+    const double *res[kMaxMeshes];
+    result_pointers(p, res);
+    {
+        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 4 : 3);
+        launch_box_norms(p, p.stream);
+        launch_crosspoints(p, 1, perm, res, p.stream);
+        launch_merge(p, 1, perm, res, p.stream);
+        if (int rc = check_launch("skeleton")) return rc;
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1);
+        launch_filler(p, nullptr, p.ws.e, p.stream);
+        if (int rc = check_launch("filler")) return rc;
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_DOTS, 1);
+        launch_dots(p, p.stream);
+        if (int rc = check_launch("dots")) return rc;
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1);
+        launch_update_residual(p, u_cur, p.ws.e, u_next, p.stream);
+        if (int rc = check_launch("update")) return rc;
+    }
+    return ASDSM_OK;
+}
+
+int require_ws(const Plan &p) {
+    if (!p.ws_base) return fail(ASDSM_E_WORKSPACE, "no workspace attached (asdsm_set_workspace)");
+    return ASDSM_OK;
+}
+
+int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm_opts *o,
+               asdsm_stats *st) {
+    asdsm_opts opt;
+    if (o) {
+        opt = *o;
+    } else {
+        std::memset(&opt, 0, sizeof opt);
+        opt.max_iter = 50;
+        opt.rtol = 1e-10;
+        opt.stag_window = 3;
+        opt.stag_eta = 1e-3;
+    }
+    if (!s || !g || !u) return fail(ASDSM_E_ARG, "s, g and u must be non-NULL device pointers");
+    if (opt.max_iter < 0 || !(opt.rtol >= 0.0) || opt.stag_window < 0 || !(opt.stag_eta >= 0.0) ||
+        !(opt.stag_eta < 1.0))
+        return fail(ASDSM_E_ARG, "invalid options");
+    if (int rc = require_ws(p)) return rc;
+    p.profiling = opt.profile != 0;
+    for (int q = 0; q < ASDSM_NPHASE; ++q) {
+        p.phase_ms[q] = 0.0;
+        p.phase_launches[q] = 0;
+    }
+    hipEvent_t tb = nullptr, te = nullptr;
+    if (p.profiling) {
+        ASDSM_HIP_CHECK(hipEventCreate(&tb));
+        ASDSM_HIP_CHECK(hipEventCreate(&te));
+        ASDSM_HIP_CHECK(hipEventRecord(tb, p.stream));
+    }
+    double *u_cur = u, *u_next = p.ws.u2;
+    if (!opt.resume) {
+        if (int rc = initial_guess(p, s, g, u)) return rc;
+    } else {
+        {
+            PhaseTimer t(p, ASDSM_PHASE_RHS, 1);
+            launch_rhs(p, 0, s, g, p.ws.b, p.ws.scal + kScalBnorm2, p.stream);
+            if (int rc = check_launch("rhs")) return rc;
+        }
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1);
+        launch_update_residual(p, u, nullptr, nullptr, p.stream);
+        if (int rc = check_launch("residual")) return rc;
+    }
+    if (int rc = read_scalars(p)) return rc;
+    const double bnorm = std::sqrt(p.hscal[kScalBnorm2]);
+    double rn = std::sqrt(p.hscal[kScalRnorm2]);
+    if (!std::isfinite(bnorm) || !std::isfinite(rn))
+        return fail(ASDSM_E_NUMERIC, "non-finite right-hand side or residual");
+    const double r0 = rn;
+    if (opt.hist) opt.hist[0] = rn;
+    int status = ASDSM_MAXITER;
+    int it = 0, stag = 0;
+    int64_t k = opt.resume ? opt.k0 : 0;
+    for (;;) {
+        if ((bnorm > 0.0 && rn <= opt.rtol * bnorm) || (bnorm == 0.0 && rn == 0.0)) {
+            status = ASDSM_OK;
+            break;
+        }
+        if (it >= opt.max_iter) {
+            status = ASDSM_MAXITER;
+            break;
+        }
+        if (int rc = refine_step(p, k, u_cur, u_next)) return rc;
+        if (int rc = read_scalars(p)) return rc;
+        const double rn_new = std::sqrt(p.hscal[kScalRnorm2]);
+        const double shat = p.hscal[kScalStep];
+        if (!std::isfinite(rn_new) || !std::isfinite(shat))
+            return fail(ASDSM_E_NUMERIC, "non-finite residual during refinement");
+        double *tmp = u_cur;
+        u_cur = u_next;
+        u_next = tmp;
+        if (opt.step_hist) opt.step_hist[it] = shat;
+        ++it;
+        ++k;
+        if (opt.hist) opt.hist[it] = rn_new;
+        stag = (rn_new > (1.0 - opt.stag_eta) * rn) ? stag + 1 : 0;
+        rn = rn_new;
+        if (shat == 0.0 || (opt.stag_window > 0 && stag >= opt.stag_window)) {
+            status = ASDSM_STAGNATED;
+            break;
+        }
+    }
+    if (u_cur != u) {
+        ASDSM_HIP_CHECK(hipMemcpyAsync(u, u_cur, (size_t)p.geo.NF * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
+    }
+    ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->status = status;
+        st->iterations = it;
+        st->bnorm = bnorm;
+        st->r0norm = r0;
+        st->rnorm = rn;
+        for (int q = 0; q < ASDSM_NPHASE; ++q) {
+            st->phase_ms[q] = p.phase_ms[q];
+            st->phase_launches[q] = p.phase_launches[q];
+        }
+        if (p.profiling) {
+            ASDSM_HIP_CHECK(hipEventRecord(te, p.stream));
+            ASDSM_HIP_CHECK(hipEventSynchronize(te));
+            float ms = 0.f;
+            ASDSM_HIP_CHECK(hipEventElapsedTime(&ms, tb, te));
+            st->total_ms = ms;
+        }
+    }
+    if (tb) (void)hipEventDestroy(tb);
+    if (te) (void)hipEventDestroy(te);
+    p.profiling = false;
+    set_error("");
+    return status;
+}
+
+}  // namespace
+}  // namespace asdsm
+
+using namespace asdsm;
+
+struct asdsm_plan_s {
+    Plan p;
+};
+
+extern "C" {
+
+int asdsm_plan(asdsm_plan_t *out, int d, const double *alpha, const double *beta, int level,
+               int coarse_level, uint64_t seed, void *hip_stream) {
+    if (!out) return fail(ASDSM_E_ARG, "out must be non-NULL");
+    *out = nullptr;
+    asdsm_plan_s *h = new (std::nothrow) asdsm_plan_s();
+    if (!h) return fail(ASDSM_E_ARG, "out of host memory");
+    int rc = build_plan(h->p, d, alpha, beta, level, coarse_level, seed, (hipStream_t)hip_stream);
+    if (rc != ASDSM_OK) {
+        release_plan(h->p);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    set_error("");
+    return ASDSM_OK;
+}
+
+int asdsm_workspace_size(asdsm_plan_t plan, size_t *bytes) {
+    if (!plan || !bytes) return fail(ASDSM_E_ARG, "plan and bytes must be non-NULL");
+    *bytes = plan->p.ws_need;
+    return ASDSM_OK;
+}
+
+int asdsm_set_workspace(asdsm_plan_t plan, void *dev, size_t bytes) {
+    if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
+    Plan &p = plan->p;
+    if (!dev) return fail(ASDSM_E_WORKSPACE, "workspace pointer is NULL");
+    if (((uintptr_t)dev & 255u) != 0) return fail(ASDSM_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < p.ws_need)
+        return fail(ASDSM_E_WORKSPACE, "workspace too small: need " + std::to_string(p.ws_need) + " bytes");
+    p.ws_base = dev;
+    p.ws_bytes = bytes;
+    layout_workspace(p, (char *)dev, true);
+    // the last-block tickets must start at zero
+    hipError_t e = hipMemsetAsync(p.ws.counters, 0, kCntCount * sizeof(unsigned), p.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+    if (e != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+    return ASDSM_OK;
+}
+
+int asdsm_solve(asdsm_plan_t plan, const double *s, const double *g, double *u,
+                const asdsm_opts *opts, asdsm_stats *stats) {
+    if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
+    return solve_impl(plan->p, s, g, u, opts, stats);
+}
+
+int asdsm_residual(asdsm_plan_t plan, const double *u, const double *s, const double *g, double *r,
+                   double *norm2) {
+    if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
+    Plan &p = plan->p;
+    if (!u || !s || !g) return fail(ASDSM_E_ARG, "u, s and g must be non-NULL device pointers");
+    if (int rc = require_ws(p)) return rc;
+    launch_rhs(p, 0, s, g, p.ws.b, p.ws.scal + kScalBnorm2, p.stream);
+    launch_update_residual(p, u, nullptr, nullptr, p.stream);
+    if (int rc = check_launch("residual")) return rc;
+    if (r) ASDSM_HIP_CHECK(hipMemcpyAsync(r, p.ws.r, (size_t)p.geo.NF * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
+    if (int rc = read_scalars(p)) return rc;
+    if (norm2) *norm2 = std::sqrt(p.hscal[kScalRnorm2]);
+    set_error("");
+    return ASDSM_OK;
+}
+
+int asdsm_mesh_solve(asdsm_plan_t plan, unsigned mesh_mask, const double *rhs, double *x) {
+    if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
+    Plan &p = plan->p;
+    if (!rhs || !x) return fail(ASDSM_E_ARG, "rhs and x must be non-NULL device pointers");
+    if (mesh_mask == 0 || mesh_mask >= (1u << p.d)) return fail(ASDSM_E_ARG, "invalid mesh mask");
+    if (int rc = require_ws(p)) return rc;
+    const size_t bytes = (size_t)p.mesh[mesh_mask].size * sizeof(double);
+    ASDSM_HIP_CHECK(hipMemcpyAsync(p.ws.X[mesh_mask], rhs, bytes, hipMemcpyDeviceToDevice, p.stream));
+    const double *res;
+    if (__builtin_popcount(mesh_mask) == 1) {
+        int k = __builtin_ctz(mesh_mask);
+        if (int rc = solve_aniso_refined(p, 1u << k)) return rc;
+        res = p.ws.X[mesh_mask];
+    } else {
+        if (int rc = solve_intersection_refined(p, mesh_mask)) return rc;
+        res = p.ws.Y[mesh_mask];
+    }
+    ASDSM_HIP_CHECK(hipMemcpyAsync(x, res, bytes, hipMemcpyDeviceToDevice, p.stream));
+    ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
+    set_error("");
+    return ASDSM_OK;
+}
+
+void asdsm_destroy(asdsm_plan_t plan) {
+    if (!plan) return;
+    release_plan(plan->p);
+    delete plan;
+}
+
+const char *asdsm_last_error(void) { return last_error_cstr(); }
+
+}  // extern "C"

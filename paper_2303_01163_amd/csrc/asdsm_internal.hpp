@@ -1,0 +1,151 @@
+// Internal declarations shared by the host plan, the driver and the kernel launchers.
+//
+// Meshes (Section 2.1 eqs. (3)-(5), Section 3.5): a mesh is named by the bitmask S of its coarse
+// axes.  S = 0 is the fine mesh, S = {k} the anisotropic submesh coarse along axis k, |S| >= 2 the
+// intersection meshes (S = all axes: the coarse mesh).  Inside the library every submesh vector is
+// stored in its *canonical layout*: the fine axes first (increasing), then the coarse axes
+// (increasing), first listed axis fastest.  The fine mesh keeps the paper's x_1-fastest order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/asdsm.h"
+
+namespace asdsm {
+
+constexpr int kMaxD = 3;
+constexpr int kMaxMeshes = 1 << kMaxD;
+
+// Canonical layout of mesh M_S.
+struct MeshDesc {
+    unsigned mask = 0;
+    int nd = 0;
+    int nfine = 0;                 // canonical positions [0, nfine) are fine axes
+    int ax[kMaxD] = {0, 0, 0};     // original axis at each canonical position
+    int ext[kMaxD] = {1, 1, 1};    // extent at each canonical position
+    long long stride[kMaxD] = {0, 0, 0};
+    long long size = 0;            // number of points
+    long long nmodes = 1;          // product of the fine extents
+    int block = 1;                 // product of the coarse extents
+};
+
+// (sub, diag, super) row of alpha/h^2 tridiag(-1,2,-1) + beta/(2h) tridiag(-1,0,1).
+struct Tri {
+    double a, b, c;
+};
+
+// Small per-launch constant block for the stencil / skeleton / filler kernels.
+struct Geo {
+    int d;
+    int Nf;        // fine interior points per axis
+    int Nc;        // coarse interior points per axis
+    int n;         // H / h (a power of two)
+    long long NF;  // Nf^d
+    Tri fine[kMaxD];
+    Tri coarse[kMaxD];
+};
+
+// Per-axis spectral data of a 1D fine-spacing operator of size N (fast diagonalisation).
+struct AxisSpectrum {
+    int N = 0;
+    double r = 1.0;                 // sqrt(sub/super): eigenvectors r^i sin(i m pi/(N+1))
+    double cond = 1.0;              // condition number of the eigenvector matrix, r^(N-1)
+    std::vector<double> mu;         // eigenvalues, m = 1..N
+    std::vector<double> W;          // forward transform  W[m*N + i] = V^{-1}(m, i)
+    std::vector<double> V;          // backward transform V[i*N + m] = V(i, m)
+};
+
+struct Workspace {
+    double *b = nullptr;         // fine right-hand side b_ff
+    double *r = nullptr;         // fine residual
+    double *e = nullptr;         // merged error guess (fine)
+    double *u2 = nullptr;        // second iterate buffer (ping-pong with the caller's u)
+    double *X[kMaxMeshes] = {};  // mesh buffers (canonical), per mask
+    double *Y[kMaxMeshes] = {};  // transform scratch, per mask
+    double *Z[kMaxMeshes] = {};  // saved right-hand side (refinement sweeps), per mask
+    double *W[kMaxMeshes] = {};  // accumulated solution (refinement sweeps), per mask
+    double *lines[kMaxD] = {};   // cross-point discrepancies of each anisotropic mesh
+    double *partials = nullptr;  // per-block partial sums
+    double *scal = nullptr;      // device scalars (see kScal*)
+    unsigned *counters = nullptr;// last-block tickets
+};
+
+// Device scalar slots.
+enum ScalarSlot {
+    kScalRnorm2 = 0,   // ||r||^2
+    kScalBnorm2 = 1,   // ||b||^2
+    kScalRQ = 2,       // <r, q>
+    kScalQQ = 3,       // <q, q>
+    kScalStep = 4,     // s_hat
+    kScalEnorm2 = 5,   // ||e_k||^2, k = 0..d-1  (slots 5,6,7)
+    kScalInvNorm = 8,  // 1/||e_k|| or 1 (slots 8,9,10)
+    kScalFlags = 11,   // non-finite flag accumulator
+    kScalCount = 16
+};
+
+enum CounterSlot { kCntResidual = 0, kCntRhs = 1, kCntDots = 2, kCntBox = 3, kCntCount = 8 };
+
+struct Plan {
+    int d = 0, level = 0, clevel = 0;
+    int Nf = 0, Nc = 0, n = 0;
+    double h = 0, H = 0;
+    double alpha[kMaxD] = {}, beta[kMaxD] = {};
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Geo geo{};
+
+    MeshDesc mesh[kMaxMeshes];
+    AxisSpectrum fine_spec[kMaxD];   // size N_f, used by the anisotropic / intersection meshes
+    AxisSpectrum hole_spec[kMaxD];   // size n-1, used by the hole boxes
+    int hole_line_axis = 0;          // the hole axis solved by line elimination
+    std::vector<double> Sp;          // N_f x N_c spline matrix, row major
+    std::vector<double> dense_inv[kMaxMeshes];  // per-mode inverses for |S| >= 2
+    double fdm_cond[kMaxMeshes] = {};  // product of the eigenvector condition numbers of the
+                                       // transformed axes of each mesh
+    int sweeps[kMaxMeshes] = {};       // refinement sweeps of each mesh solve
+
+    // device copies of the tables (one allocation owned by the plan)
+    void *dtab = nullptr;
+    size_t dtab_bytes = 0;
+    double *dW[kMaxD] = {}, *dV[kMaxD] = {}, *dmu[kMaxD] = {};
+    double *dWh[kMaxD] = {}, *dVh[kMaxD] = {}, *dmuh[kMaxD] = {};
+    double *dSp = nullptr;
+    double *ddense[kMaxMeshes] = {};
+
+    // caller workspace
+    void *ws_base = nullptr;
+    size_t ws_bytes = 0;
+    Workspace ws;
+    size_t ws_need = 0;
+    int max_blocks = 0;              // partial-sum capacity
+
+    // pinned host mirror of the device scalars
+    double *hscal = nullptr;
+
+    // profiling events
+    bool profiling = false;
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    double phase_ms[ASDSM_NPHASE] = {};
+    int phase_launches[ASDSM_NPHASE] = {};
+};
+
+// ---- host plan construction (plan.cpp)
+int build_plan(Plan &p, int d, const double *alpha, const double *beta, int level,
+               int coarse_level, uint64_t seed, hipStream_t stream);
+void layout_workspace(Plan &p, char *base, bool assign);
+void release_plan(Plan &p);
+MeshDesc make_mesh(int d, int Nf, int Nc, unsigned mask);
+
+// counter-based permutation of the axes for iteration k
+void axis_permutation(uint64_t seed, int64_t k, int d, int perm[kMaxD]);
+
+// ---- error reporting
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+}  // namespace asdsm

@@ -1,0 +1,214 @@
+// HBM-bound fine-mesh passes:
+//   * right-hand side assembly on the fine mesh and on any submesh (source injection plus the
+//     Dirichlet terms with the mesh's own spacing, Section 2.3);
+//   * the fused iterate update and fine residual  u' = u + s e,  r = b - A u'  (Algorithm 4 steps
+//     7 and 3), which also gathers r onto every anisotropic submesh (steps 4.1/4.2) and reduces
+//     ||r||^2;
+//   * the line-search products q = A e, <r,q>, <q,q> and the clamped step
+//     s = max(0, <r,q>/<q,q>) (Algorithm 4 step 6).
+// Thread layout of the stencil passes: a block is 4 waves; a wave covers 64 consecutive x_1 points
+// of one fine row (rows = the N_f^(d-1) lines along x_1), so loads and stores are row-coalesced.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace asdsm {
+
+// ---------------------------------------------------------------------------------------------
+// Right-hand side on mesh M_S (canonical layout).  For the fine mesh also reduces ||b||^2.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rhs(Geo g, MeshDesc m, const double *__restrict__ s,
+                                             const double *__restrict__ gf,
+                                             double *__restrict__ out, double *partials,
+                                             unsigned *counter, double *norm2_out) {
+    const int d = g.d;
+    const long long faceN = (d == 2) ? g.Nf : (long long)g.Nf * g.Nf;
+    double acc = 0.0;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < m.size;
+         idx += (long long)gridDim.x * 256) {
+        int i[kMaxD] = {0, 0, 0};
+        int cpos[kMaxD] = {0, 0, 0};
+        long long rem = idx;
+        for (int q = 0; q < d; ++q) {
+            const int pos = (int)(rem % m.ext[q]);
+            rem /= m.ext[q];
+            const int j = m.ax[q];
+            if (q < m.nfine) {
+                i[j] = pos;
+                cpos[j] = -1;
+            } else {
+                i[j] = (pos + 1) * g.n - 1;
+                cpos[j] = pos;
+            }
+        }
+        long long f = i[0] + (long long)g.Nf * (i[1] + (long long)g.Nf * (d == 3 ? i[2] : 0));
+        double v = s[f];
+        for (int j = 0; j < d; ++j) {
+            const bool coarse = (m.mask >> j) & 1u;
+            const Tri t = coarse ? g.coarse[j] : g.fine[j];
+            const bool lo = coarse ? (cpos[j] == 0) : (i[j] == 0);
+            const bool hi = coarse ? (cpos[j] == g.Nc - 1) : (i[j] == g.Nf - 1);
+            if (!lo && !hi) continue;
+            // face index over the other axes, increasing order, lowest fastest
+            long long fidx = 0, mul = 1;
+            for (int o = 0; o < d; ++o) {
+                if (o == j) continue;
+                fidx += (long long)i[o] * mul;
+                mul *= g.Nf;
+            }
+            if (lo) v -= t.a * gf[(long long)(2 * j) * faceN + fidx];
+            if (hi) v -= t.c * gf[(long long)(2 * j + 1) * faceN + fidx];
+        }
+        out[idx] = v;
+        acc += v * v;
+    }
+    if (norm2_out) {
+        double vals[1] = {acc};
+        reduce_and_finalize<256, 1>(vals, partials, counter, [&](const double *t) { *norm2_out = t[0]; });
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fused update + residual + gather.  e == nullptr: plain residual of uin (no update, uout unused).
+// ---------------------------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_update_residual(
+    Geo g, const double *__restrict__ uin, const double *__restrict__ e,
+    const double *__restrict__ scal, const double *__restrict__ b, double *__restrict__ uout,
+    double *__restrict__ r, BoxPtrs boxes, double *partials, unsigned *counter, double *norm2_out) {
+    const int Nf = g.Nf, n = g.n;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int i0 = blockIdx.y * 64 + tx;
+    const long long nrows = g.NF / Nf;
+    const double s = e ? scal[kScalStep] : 0.0;
+    const long long sy = Nf, sz = (long long)Nf * Nf;
+    double acc = 0.0;
+    for (long long rg = blockIdx.x; rg * 4 < nrows; rg += gridDim.x) {
+        const long long row = rg * 4 + ty;
+        if (i0 >= Nf || row >= nrows) continue;
+        const int i1 = (int)(row % Nf);
+        const int i2 = (D == 3) ? (int)(row / Nf) : 0;
+        const long long p = i0 + (long long)Nf * row;
+        auto val = [&](long long q) -> double { return e ? uin[q] + s * e[q] : uin[q]; };
+        const double uc = val(p);
+        double au = (g.fine[0].b + g.fine[1].b + (D == 3 ? g.fine[2].b : 0.0)) * uc;
+        if (i0 > 0) au += g.fine[0].a * val(p - 1);
+        if (i0 < Nf - 1) au += g.fine[0].c * val(p + 1);
+        if (i1 > 0) au += g.fine[1].a * val(p - sy);
+        if (i1 < Nf - 1) au += g.fine[1].c * val(p + sy);
+        if (D == 3) {
+            if (i2 > 0) au += g.fine[2].a * val(p - sz);
+            if (i2 < Nf - 1) au += g.fine[2].c * val(p + sz);
+        }
+        const double rr = b[p] - au;
+        r[p] = rr;
+        if (e) uout[p] = uc;
+        acc += rr * rr;
+        // gather onto the anisotropic submeshes (canonical layouts)
+        if (D == 2) {
+            if (on_coarse(i0, n)) boxes.p[0][i1 + (long long)Nf * coarse_of(i0, n)] = rr;
+            if (on_coarse(i1, n)) boxes.p[1][i0 + (long long)Nf * coarse_of(i1, n)] = rr;
+        } else {
+            if (on_coarse(i0, n)) boxes.p[0][i1 + sy * i2 + sz * coarse_of(i0, n)] = rr;
+            if (on_coarse(i1, n)) boxes.p[1][i0 + sy * i2 + sz * coarse_of(i1, n)] = rr;
+            if (on_coarse(i2, n)) boxes.p[2][i0 + sy * i1 + sz * coarse_of(i2, n)] = rr;
+        }
+    }
+    double vals[1] = {acc};
+    reduce_and_finalize<256, 1>(vals, partials, counter, [&](const double *t) { *norm2_out = t[0]; });
+}
+
+// ---------------------------------------------------------------------------------------------
+// Line search: q = A e (zero Dirichlet data), <r,q>, <q,q>, s = max(0, <r,q>/<q,q>) (0 if q = 0).
+// ---------------------------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_dots(Geo g, const double *__restrict__ e,
+                                              const double *__restrict__ r, double *partials,
+                                              unsigned *counter, double *scal) {
+    const int Nf = g.Nf;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int i0 = blockIdx.y * 64 + tx;
+    const long long nrows = g.NF / Nf;
+    const long long sy = Nf, sz = (long long)Nf * Nf;
+    double rq = 0.0, qq = 0.0;
+    for (long long rg = blockIdx.x; rg * 4 < nrows; rg += gridDim.x) {
+        const long long row = rg * 4 + ty;
+        if (i0 >= Nf || row >= nrows) continue;
+        const int i1 = (int)(row % Nf);
+        const int i2 = (D == 3) ? (int)(row / Nf) : 0;
+        const long long p = i0 + (long long)Nf * row;
+        double q = (g.fine[0].b + g.fine[1].b + (D == 3 ? g.fine[2].b : 0.0)) * e[p];
+        if (i0 > 0) q += g.fine[0].a * e[p - 1];
+        if (i0 < Nf - 1) q += g.fine[0].c * e[p + 1];
+        if (i1 > 0) q += g.fine[1].a * e[p - sy];
+        if (i1 < Nf - 1) q += g.fine[1].c * e[p + sy];
+        if (D == 3) {
+            if (i2 > 0) q += g.fine[2].a * e[p - sz];
+            if (i2 < Nf - 1) q += g.fine[2].c * e[p + sz];
+        }
+        rq += r[p] * q;
+        qq += q * q;
+    }
+    double vals[2] = {rq, qq};
+    reduce_and_finalize<256, 2>(vals, partials, counter, [&](const double *t) {
+        scal[kScalRQ] = t[0];
+        scal[kScalQQ] = t[1];
+        const double st = (t[1] > 0.0) ? t[0] / t[1] : 0.0;
+        scal[kScalStep] = (st > 0.0) ? st : 0.0;
+    });
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+static void stencil_grid(const Geo &g, dim3 &grid) {
+    const long long nrows = g.NF / g.Nf;
+    const int xch = (g.Nf + 63) / 64;
+    long long rgs = (nrows + 3) / 4;
+    long long cap = 16384 / xch;
+    if (cap < 1) cap = 1;
+    grid = dim3((unsigned)(rgs < cap ? rgs : cap), (unsigned)xch, 1);
+}
+
+int stencil_blocks(const Geo &g) {
+    dim3 gr;
+    stencil_grid(g, gr);
+    return (int)(gr.x * gr.y);
+}
+
+void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf, double *out,
+                double *norm2_out, hipStream_t st) {
+    const MeshDesc &m = p.mesh[mask];
+    long long blocks = (m.size + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)blocks), dim3(256), 0, st, p.geo, m, s, gf, out,
+                       p.ws.partials, p.ws.counters + kCntRhs, norm2_out);
+}
+
+void launch_update_residual(const Plan &p, const double *uin, const double *e, double *uout,
+                            hipStream_t st) {
+    dim3 grid;
+    stencil_grid(p.geo, grid);
+    BoxPtrs bx;
+    for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? p.ws.X[1u << k] : nullptr;
+    if (p.d == 2)
+        hipLaunchKernelGGL(k_update_residual<2>, grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
+                           p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.ws.counters + kCntResidual,
+                           p.ws.scal + kScalRnorm2);
+    else
+        hipLaunchKernelGGL(k_update_residual<3>, grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
+                           p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.ws.counters + kCntResidual,
+                           p.ws.scal + kScalRnorm2);
+}
+
+void launch_dots(const Plan &p, hipStream_t st) {
+    dim3 grid;
+    stencil_grid(p.geo, grid);
+    if (p.d == 2)
+        hipLaunchKernelGGL(k_dots<2>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials,
+                           p.ws.counters + kCntDots, p.ws.scal);
+    else
+        hipLaunchKernelGGL(k_dots<3>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials,
+                           p.ws.counters + kCntDots, p.ws.scal);
+}
+
+}  // namespace asdsm

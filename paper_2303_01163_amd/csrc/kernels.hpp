@@ -1,0 +1,70 @@
+// Kernel launchers (host side), implemented in the k_*.hip files.
+#pragma once
+
+#include "asdsm_internal.hpp"
+
+namespace asdsm {
+
+struct BoxPtrs {
+    double *p[kMaxD];
+};
+
+// One batched GEMM C = A * B per entry z (up to 3 boxes), FP64 MFMA; element (i, k) of A at
+// A + b*sAb + i*sAi + k*sAk, and likewise for B (k, n) and C (i, n).
+struct GemmJob {
+    const double *A[kMaxD];
+    const double *B[kMaxD];
+    double *C[kMaxD];
+    int nbox;
+    int M, N, K, nbatch;
+    long long sAb, sAi, sAk, sBb, sBk, sBn, sCb, sCi, sCn;
+};
+
+// Thomas elimination along the coarse (slowest) axis of anisotropic boxes after their fine axes
+// have been diagonalised: for each mode, (T_coarse + sigma I) x = f, sigma = sum of fine eigenvalues.
+struct LineJob {
+    double *X[kMaxD];          // data, in place
+    double *scratch[kMaxD];    // same size as X
+    const double *mu_a[kMaxD]; // eigenvalues of the first fine axis
+    const double *mu_b[kMaxD]; // eigenvalues of the second fine axis (nullptr when d = 2)
+    Tri t[kMaxD];              // coarse-axis operator of each box
+    int nbox;
+    long long nmodes;          // product of the fine extents
+    int ext_a;                 // extent of the first fine axis
+    int ncoarse;               // points along the coarse axis
+};
+
+void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf, double *out,
+                double *norm2_out, hipStream_t st);
+void launch_update_residual(const Plan &p, const double *uin, const double *e, double *uout,
+                            hipStream_t st);
+void launch_dots(const Plan &p, hipStream_t st);
+int stencil_blocks(const Geo &g);
+
+void launch_gemm(const GemmJob &job, hipStream_t st);
+void launch_line(const LineJob &job, hipStream_t st);
+void launch_dense_modes(long long nmodes, int B, const double *inv, const double *in, double *out,
+                        hipStream_t st);
+void launch_box_norms(const Plan &p, hipStream_t st);
+
+// Residual of a mesh system with zero Dirichlet data, out = f - A_S x, for up to 3 meshes at once
+// (refinement sweeps of the submesh solves).
+struct BoxResJob {
+    const double *f[kMaxD];
+    const double *x[kMaxD];
+    double *out[kMaxD];
+    MeshDesc m[kMaxD];
+    int nbox;
+};
+void launch_box_residual(const Plan &p, const BoxResJob &job, hipStream_t st);
+// y_i += x_i for up to 3 arrays of n doubles
+void launch_axpy(double *const *y, const double *const *x, long long n, int nbox, hipStream_t st);
+
+// skeleton: mode 0 = initial guess (extrapolated cross points), 1 = error phase (random choice)
+void launch_crosspoints(const Plan &p, int mode, const int *perm, const double *const *res,
+                        hipStream_t st);
+void launch_merge(const Plan &p, int mode, const int *perm, const double *const *res,
+                  hipStream_t st);
+void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st);
+
+}  // namespace asdsm

@@ -228,7 +228,11 @@ def _faces(man, d, x1d):
     return faces
 
 
-def make_problem(family: str, level: int, seed: int = 0, d: int | None = None) -> Problem:
+def make_problem(family: str, level: int, seed: int = 0, d: int | None = None,
+                 alpha=None, beta=None) -> Problem:
+    """Seeded problem of the given family; ``alpha``/``beta`` override the drawn coefficients
+    (the draws still happen, so the other seeded quantities do not change)."""
+    alpha_override, beta_override = alpha, beta
     rng = np.random.default_rng(seed)
     meta = {}
     if family == "sinprod2d":
@@ -267,6 +271,10 @@ def make_problem(family: str, level: int, seed: int = 0, d: int | None = None) -
         meta["k"] = k.tolist()
     else:
         raise ValueError(f"unknown workload family {family!r}")
+    if alpha_override is not None:
+        alpha = np.asarray(alpha_override, dtype=np.float64)
+    if beta_override is not None:
+        beta = np.asarray(beta_override, dtype=np.float64)
     x1d = fine_coords(level)
     xs = _grid(d, x1d)
     s = np.asarray(_source(man, alpha, beta, xs), dtype=np.float64)

@@ -1,0 +1,294 @@
+"""GPU parity: the HIP path (libasdsm.so through its C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 throughout; single operations (residual, submesh solves) agree to <= 1e-11
+relative L2, iterates to <= 1e-10 relative L2 (the bar fixed for the FP64 GPU path).  The two
+sides differ only in rounding order: banded LU vs fast diagonalisation, summation order of the
+stencil, spline and reductions.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.asdsm_oracle import Oracle, apply_operator, fine_direct_solve, mesh_coeffs
+from paper_2303_01163_amd.workloads import make_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = 1e-11
+TOL_ITER = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    from paper_2303_01163_amd import asdsm
+    if not asdsm.LIB_PATH.exists():
+        from paper_2303_01163_amd.build import build_library
+        build_library()
+    asdsm.load_library()
+    return torch, torch.device("cuda", 0)
+
+
+def _t(torch_dev, a):
+    torch, dev = torch_dev
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _canon(d, S, arr):
+    order = [j for j in range(d) if j not in S] + list(S)
+    return np.transpose(arr, order).reshape(-1, order="F")
+
+
+def _uncanon(grid, S, flat):
+    d = grid.d
+    order = [j for j in range(d) if j not in S] + list(S)
+    shape = [grid.Nc if j in S else grid.Nf for j in order]
+    return np.transpose(flat.reshape(shape, order="F"), np.argsort(order))
+
+
+def _plan(P, L, Lc=0, seed=0):
+    from paper_2303_01163_amd.asdsm import Plan
+    return Plan(P.d, P.alpha, P.beta, L, Lc, seed=seed)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [  # (family, level, coarse_level, d, seed)
+    ("sinprod2d", 6, 0, None, 0),      # 63^2, H = 1/8: the small 2D workload
+    ("sinprod2d", 6, 2, None, 3),      # coarser submeshes, 15^2 holes
+    ("sinprod", 5, 3, 2, 5),           # n = 4
+    ("sinbump3d", 5, 0, None, 2),      # 31^3, H = 1/4, g != 0
+    ("sinprod", 5, 3, 3, 1),           # 31^3, 7 coarse planes, 3^3 holes
+    ("sinbump3d", 6, 3, None, 4),      # 63^3
+]
+
+
+@pytest.mark.parametrize("fam,L,Lc,d,seed", CASES)
+def test_residual_parity(torch_dev, fam, L, Lc, d, seed):
+    _say("residual", fam, L, Lc, seed)
+    P = make_problem(fam, L, seed=seed, d=d)
+    o = Oracle(P.d, P.alpha, P.beta, L, Lc or None)
+    rng = np.random.default_rng(seed)
+    u = P.u_exact + 0.1 * rng.standard_normal(P.u_exact.shape)
+    b = o.fine_rhs(P.s, P.g)
+    r_or = o.residual(u, b).reshape(-1, order="F")
+    pl = _plan(P, L, Lc)
+    r, nrm = pl.residual(_t(torch_dev, u.reshape(-1, order="F")), _t(torch_dev, P.s_flat()),
+                         _t(torch_dev, P.g_flat()))
+    assert _rel(r.cpu().numpy(), r_or) <= TOL_OP
+    assert abs(nrm - np.linalg.norm(r_or)) <= 1e-12 * np.linalg.norm(r_or)
+
+
+@pytest.mark.parametrize("fam,L,Lc,d,seed", CASES)
+def test_mesh_solve_parity(torch_dev, fam, L, Lc, d, seed):
+    """Every submesh / intersection / coarse system against the oracle's banded LU."""
+    P = make_problem(fam, L, seed=seed, d=d)
+    o = Oracle(P.d, P.alpha, P.beta, L, Lc or None)
+    pl = _plan(P, L, Lc)
+    rng = np.random.default_rng(100 + seed)
+    for r_ in range(1, P.d + 1):
+        for S in itertools.combinations(range(P.d), r_):
+            _say("mesh", fam, L, Lc, seed, S)
+            mask = sum(1 << j for j in S)
+            rhs = rng.standard_normal(o.grid.mesh_dims(S))
+            x_or = o.solve_mesh(S, rhs)
+            x = pl.mesh_solve(mask, _t(torch_dev, _canon(P.d, S, rhs))).cpu().numpy()
+            assert _rel(_uncanon(o.grid, S, x), x_or) <= TOL_OP, S
+
+
+@pytest.mark.parametrize("fam,L,Lc,d,seed", CASES)
+def test_iterate_parity(torch_dev, fam, L, Lc, d, seed):
+    """u^(0) (Algorithm 1) and u^(1..5) (Algorithm 4) with the same seed, iterate by iterate."""
+    _say("iterates", fam, L, Lc, seed)
+    P = make_problem(fam, L, seed=seed, d=d)
+    o = Oracle(P.d, P.alpha, P.beta, L, Lc or None, seed=seed + 17)
+    ref = o.solve(P.s, P.g, max_iter=5, rtol=0, stag_window=0, keep_iterates=True)
+    pl = _plan(P, L, Lc, seed=seed + 17)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    for K in range(0, 6):
+        u, info = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0)
+        assert info["iterations"] == K
+        assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
+        for k in range(K + 1):
+            assert abs(info["res_hist"][k] - ref.res_hist[k]) <= 1e-9 * ref.res_hist[k]
+        for k in range(K):
+            assert abs(info["step_hist"][k] - ref.step_hist[k]) <= 1e-9 * abs(ref.step_hist[k]) + 1e-300
+
+
+def test_small_2d_workload_error_vs_fine_solution(torch_dev):
+    """The 63^2 workload with 5 refinement iterations: GPU result equals the oracle's and its error
+    against the direct fine solution is the oracle's (stagnation level of the method)."""
+    P = make_problem("sinprod2d", 6, seed=0)
+    o = Oracle(2, P.alpha, P.beta, 6, seed=0)
+    ref = o.solve(P.s, P.g, max_iter=5, rtol=0, stag_window=0)
+    pl = _plan(P, 6, 0, seed=0)
+    u, info = pl.solve(_t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat()), max_iter=5, rtol=0,
+                       stag_window=0)
+    ug = u.cpu().numpy()
+    assert _rel(ug, ref.u.reshape(-1, order="F")) <= TOL_ITER
+    uff = fine_direct_solve(2, P.alpha, P.beta, 6, P.s, P.g).reshape(-1, order="F")
+    assert abs(_rel(ug, uff) - _rel(ref.u.reshape(-1, order="F"), uff)) <= 1e-9
+
+
+def test_full_size_3d_parity(torch_dev):
+    """127^3 (h = 1/128), alpha log-uniform in [0.1,1], beta in [-5,5], sinusoids + bump: the GPU
+    iterates u^(0..2) against the oracle at full size."""
+    _say("full size 127^3")
+    P = make_problem("sinbump3d", 7, seed=0)
+    o = Oracle(3, P.alpha, P.beta, 7, seed=0)
+    ref = o.solve(P.s, P.g, max_iter=2, rtol=0, stag_window=0, keep_iterates=True)
+    pl = _plan(P, 7, 0, seed=0)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    for K in (0, 2):
+        u, info = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0)
+        assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
+
+
+def test_full_size_3d_properties(torch_dev):
+    """Properties that hold at any size, in the benchmark's configuration (127^3, default coarse
+    level, stagnation rule on): residual zero on the holes for the returned iterate
+    (Proposition 3.2(2)), non-increasing residual history (Remark 3.4), submesh solves satisfy their
+    equations."""
+    _say("full size properties 127^3")
+    P = make_problem("sinbump3d", 7, seed=0)
+    pl = _plan(P, 7, 0, seed=0)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u, info = pl.solve(s, g, max_iter=12, rtol=1e-10, stag_window=3)
+    h = info["res_hist"]
+    assert all(h[i + 1] <= h[i] * (1 + 1e-12) for i in range(len(h) - 1))
+    o = Oracle(3, P.alpha, P.beta, 7)
+    r, nrm = pl.residual(u, s, g)
+    rr = r.cpu().numpy().reshape((127,) * 3, order="F")
+    holes = o.grid.hole_mask()
+    assert np.max(np.abs(rr[holes])) <= 1e-10 * info["bnorm"] / 127 ** 1.5 * 1e3
+    assert abs(nrm - h[-1]) <= 1e-9 * h[-1]
+    rng = np.random.default_rng(7)
+    for S in ((0,), (1,), (2,), (0, 2), (0, 1, 2)):
+        mask = sum(1 << j for j in S)
+        rhs = rng.standard_normal(o.grid.mesh_dims(S))
+        x = _uncanon(o.grid, S, pl.mesh_solve(mask, _t(torch_dev, _canon(3, S, rhs))).cpu().numpy())
+        res = apply_operator(x, mesh_coeffs(o.grid, P.alpha, P.beta, S)) - rhs
+        assert np.linalg.norm(res) <= 1e-11 * np.linalg.norm(rhs) * 1e2, S
+
+
+def test_large_2d_parity(torch_dev):
+    """The largest fine level (1023^2) with 31 coarse lines per axis: iterates u^(0), u^(2)."""
+    _say("2D level 10")
+    P = make_problem("sinprod2d", 10, seed=8)
+    o = Oracle(2, P.alpha, P.beta, 10, 5, seed=8)
+    ref = o.solve(P.s, P.g, max_iter=2, rtol=0, stag_window=0, keep_iterates=True)
+    pl = _plan(P, 10, 5, seed=8)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    for K in (0, 2):
+        u, _ = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0)
+        assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
+
+
+# ----------------------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("d,L,Lc", [(2, 3, 1), (2, 5, 4), (3, 3, 1), (3, 4, 3), (3, 3, 2)])
+def test_degenerate_meshes(torch_dev, d, L, Lc):
+    """N_c = 1 (the spline is a parabola), n = 2 (one-point holes), tiny grids."""
+    _say("degenerate", d, L, Lc)
+    fam = "sinprod2d" if d == 2 else "sinbump3d"
+    P = make_problem(fam, L, seed=L + Lc)
+    o = Oracle(d, P.alpha, P.beta, L, Lc, seed=5)
+    ref = o.solve(P.s, P.g, max_iter=3, rtol=0, stag_window=0, keep_iterates=True)
+    pl = _plan(P, L, Lc, seed=5)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    for K in (0, 3):
+        u, _ = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0)
+        assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
+
+
+def test_q2_converges_at_initial_guess(torch_dev):
+    """A Q2 solution is reproduced by Algorithm 1; the stopping rule ends with status OK and 0 steps."""
+    P = make_problem("quadratic", 5, seed=2, d=3)
+    pl = _plan(P, 5, 0)
+    u, info = pl.solve(_t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat()), max_iter=10, rtol=1e-10)
+    assert info["status"] == 0 and info["iterations"] == 0
+    assert np.max(np.abs(u.cpu().numpy() - P.u_exact.reshape(-1, order="F"))) <= 1e-11
+
+
+def test_resume_and_determinism(torch_dev):
+    P = make_problem("sinbump3d", 5, seed=3)
+    pl = _plan(P, 5, 0, seed=99)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u5, _ = pl.solve(s, g, max_iter=5, rtol=0, stag_window=0)
+    u5b, _ = pl.solve(s, g, max_iter=5, rtol=0, stag_window=0)
+    assert bool((u5 == u5b).all())                       # fixed-order reductions: bitwise equal
+    u3, _ = pl.solve(s, g, max_iter=3, rtol=0, stag_window=0)
+    u32, _ = pl.solve(s, g, u=u3.clone(), max_iter=2, rtol=0, stag_window=0, resume=True, k0=3)
+    assert bool((u32 == u5).all())
+
+
+def test_stagnation_and_maxiter_status(torch_dev):
+    P = make_problem("sinprod2d", 6, seed=0)
+    pl = _plan(P, 6, 0)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    _, info = pl.solve(s, g, max_iter=3, rtol=0, stag_window=0)
+    assert info["status"] == 2 and info["iterations"] == 3
+    _, info = pl.solve(s, g, max_iter=400, rtol=0, stag_window=1, stag_eta=0.5)
+    assert info["status"] == 1 and info["iterations"] < 400
+
+
+def test_error_codes(torch_dev):
+    from paper_2303_01163_amd.asdsm import AsdsmError, Plan
+    with pytest.raises(AsdsmError) as e:
+        Plan(2, [1.0, -1.0], [0.0, 0.0], 5)
+    assert e.value.code == -1
+    with pytest.raises(AsdsmError) as e:
+        Plan(2, [1.0, 1.0], [0.0, 0.0], 5, 5)
+    assert e.value.code == -2
+    with pytest.raises(AsdsmError) as e:              # cell Peclet number 1 on a fine axis
+        Plan(2, [1.0, 1.0], [2.0 * 32.0, 0.0], 5)
+    assert e.value.code == -6
+    with pytest.raises(AsdsmError) as e:
+        Plan(4, [1.0] * 4, [0.0] * 4, 5)
+    assert e.value.code == -1
+    P = make_problem("sinprod2d", 5, seed=0)
+    pl = _plan(P, 5, 0)
+    bad = P.s_flat().copy()
+    bad[7] = np.nan
+    with pytest.raises(AsdsmError) as e:
+        pl.solve(_t(torch_dev, bad), _t(torch_dev, P.g_flat()), max_iter=2)
+    assert e.value.code == -4
+
+
+# ----------------------------------------------------------------------------- conditioning
+def test_ill_conditioned_axis_refinement(torch_dev):
+    """One fine axis with cell Peclet 0.35 (eigenvector matrix condition ~1e10 at N_f = 63): the
+    plan adds FP64 refinement sweeps around the fast-diagonalisation solves, and submesh solves and
+    iterates still match the banded-LU oracle."""
+    _say("ill-conditioned axis")
+    P = make_problem("sinbump3d", 6, seed=1, alpha=[0.1, 0.5, 0.8], beta=[4.5, 1.0, -1.0])
+    o = Oracle(3, P.alpha, P.beta, 6, seed=4)
+    pl = _plan(P, 6, 0, seed=4)
+    rng = np.random.default_rng(3)
+    for S in ((0,), (1,), (2,), (0, 1), (1, 2)):
+        mask = sum(1 << j for j in S)
+        rhs = rng.standard_normal(o.grid.mesh_dims(S))
+        x = pl.mesh_solve(mask, _t(torch_dev, _canon(3, S, rhs))).cpu().numpy()
+        assert _rel(_uncanon(o.grid, S, x), o.solve_mesh(S, rhs)) <= TOL_OP, S
+    ref = o.solve(P.s, P.g, max_iter=3, rtol=0, stag_window=0, keep_iterates=True)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    for K in (0, 3):
+        u, _ = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0)
+        assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
+
+
+def test_two_ill_conditioned_axes_are_refused(torch_dev):
+    """Two fine axes near cell Peclet 1: refinement cannot converge, the plan reports
+    ASDSM_E_UNSUPPORTED instead of returning inaccurate solves."""
+    from paper_2303_01163_amd.asdsm import AsdsmError, Plan
+    with pytest.raises(AsdsmError) as e:
+        Plan(3, [0.1, 0.1, 0.8], [6.0, -6.0, 1.0], 6)
+    assert e.value.code == -6
