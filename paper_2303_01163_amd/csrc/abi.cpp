@@ -53,8 +53,19 @@ void fine_axes(int d, int k, int &a, int &b) {
     }
 }
 
-// Anisotropic-mesh solves, in place on X_k for every k with bit k of kbits set.
-int solve_aniso(Plan &p, unsigned kbits) {
+// Buffers of mesh M_S: where its right-hand side is gathered and where its solution ends up.
+// Without refinement sweeps the anisotropic meshes solve in place in X and the intersection meshes
+// from X into Y; with sweeps the right-hand side is kept in Z and the solution accumulates in W.
+double *rhs_buf(const Plan &p, unsigned m) { return p.sweeps[m] ? p.ws.Z[m] : p.ws.X[m]; }
+double *sol_buf(const Plan &p, unsigned m) {
+    if (p.sweeps[m]) return p.ws.W[m];
+    return (__builtin_popcount(m) == 1) ? p.ws.X[m] : p.ws.Y[m];
+}
+
+// Direct solves of the anisotropic meshes k in kbits (fast diagonalisation of the fine axes, Thomas
+// along the coarse axis): in[k] -> out[k] (out += solution when accum).  X_k and Y_k are used as
+// intermediates, so in[k] may be X_k and out[k] may be X_k, but neither may be Y_k.
+int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, int accum) {
     const int d = p.d, Nf = p.Nf, Nc = p.Nc;
     int ks[kMaxD], nb = 0;
     for (int k = 0; k < d; ++k)
@@ -63,13 +74,11 @@ int solve_aniso(Plan &p, unsigned kbits) {
     const long long Nf2 = (long long)Nf * Nf;
     GemmJob j{};
     j.nbox = nb;
-    // forward transform along canonical axis 0 (contiguous): X -> Y
+    // forward transform along canonical axis 0 (contiguous): in -> Y
     {
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
         j.M = (d == 2) ? Nc : Nf * Nc;
-        j.N = Nf;
-        j.K = Nf;
-        j.nbatch = 1;
+        j.N = Nf; j.K = Nf; j.nbatch = 1; j.accum = 0;
         j.sAb = j.sBb = j.sCb = 0;
         j.sAi = Nf; j.sAk = 1;
         j.sBk = 1;  j.sBn = Nf;
@@ -77,7 +86,7 @@ int solve_aniso(Plan &p, unsigned kbits) {
         for (int q = 0; q < nb; ++q) {
             int a, b;
             fine_axes(d, ks[q], a, b);
-            j.A[q] = p.ws.X[1u << ks[q]];
+            j.A[q] = in[ks[q]];
             j.B[q] = p.dW[a];
             j.C[q] = p.ws.Y[1u << ks[q]];
         }
@@ -87,7 +96,7 @@ int solve_aniso(Plan &p, unsigned kbits) {
     if (d == 3) {
         // forward along canonical axis 1, batched over the coarse slabs: Y -> X
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
-        j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc;
+        j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc; j.accum = 0;
         j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
         j.sBb = Nf2; j.sBk = Nf; j.sBn = 1;
         j.sCb = Nf2; j.sCi = Nf; j.sCn = 1;
@@ -101,7 +110,7 @@ int solve_aniso(Plan &p, unsigned kbits) {
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
     }
-    // line elimination along the coarse axis
+    // line elimination along the coarse axis: d = 2 on Y (scratch X), d = 3 on X (scratch Y)
     {
         PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
         LineJob L{};
@@ -113,7 +122,6 @@ int solve_aniso(Plan &p, unsigned kbits) {
             int a, b;
             const int k = ks[q];
             fine_axes(d, k, a, b);
-            // d = 2: data in Y (scratch X); d = 3: data in X (scratch Y)
             L.X[q] = (d == 2) ? p.ws.Y[1u << k] : p.ws.X[1u << k];
             L.scratch[q] = (d == 2) ? p.ws.X[1u << k] : p.ws.Y[1u << k];
             L.mu_a[q] = p.dmu[a];
@@ -126,7 +134,7 @@ int solve_aniso(Plan &p, unsigned kbits) {
     if (d == 3) {
         // backward along canonical axis 1: X -> Y
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
-        j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc;
+        j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc; j.accum = 0;
         j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
         j.sBb = Nf2; j.sBk = Nf; j.sBn = 1;
         j.sCb = Nf2; j.sCi = Nf; j.sCn = 1;
@@ -141,10 +149,10 @@ int solve_aniso(Plan &p, unsigned kbits) {
         if (int rc = check_launch("transform")) return rc;
     }
     {
-        // backward along canonical axis 0: Y -> X
+        // backward along canonical axis 0: Y -> out
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
         j.M = (d == 2) ? Nc : Nf * Nc;
-        j.N = Nf; j.K = Nf; j.nbatch = 1;
+        j.N = Nf; j.K = Nf; j.nbatch = 1; j.accum = accum;
         j.sAb = j.sBb = j.sCb = 0;
         j.sAi = Nf; j.sAk = 1;
         j.sBk = 1;  j.sBn = Nf;
@@ -154,7 +162,7 @@ int solve_aniso(Plan &p, unsigned kbits) {
             fine_axes(d, ks[q], a, b);
             j.A[q] = p.ws.Y[1u << ks[q]];
             j.B[q] = p.dV[a];
-            j.C[q] = p.ws.X[1u << ks[q]];
+            j.C[q] = out[ks[q]];
         }
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
@@ -162,12 +170,14 @@ int solve_aniso(Plan &p, unsigned kbits) {
     return ASDSM_OK;
 }
 
-// Intersection-mesh solve (>= 2 coarse axes): X_S -> result in Y_S.
-int solve_intersection(Plan &p, unsigned mask) {
+// Direct solve of an intersection mesh (>= 2 coarse axes): in -> out (out += when accum).  X_S and
+// Y_S are intermediates (in may be X_S; out may be neither X_S nor Y_S unless it is the plain
+// Y_S output without accumulation).
+int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, int accum) {
     const MeshDesc &m = p.mesh[mask];
     if (m.nfine == 0) {
         PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
-        launch_dense_modes(1, m.block, p.ddense[mask], p.ws.X[mask], p.ws.Y[mask], p.stream);
+        launch_dense_modes(1, m.block, p.ddense[mask], in, out, accum, p.stream);
         return check_launch("dense");
     }
     // one fine axis (d = 3 edge meshes): transform, per-mode dense solve, back-transform
@@ -181,109 +191,225 @@ int solve_intersection(Plan &p, unsigned mask) {
     j.sCi = p.Nf; j.sCn = 1;
     {
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
-        j.A[0] = p.ws.X[mask];
+        j.A[0] = in;
         j.B[0] = p.dW[f];
         j.C[0] = p.ws.Y[mask];
+        j.accum = 0;
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
     }
     {
         PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
-        launch_dense_modes(m.nmodes, m.block, p.ddense[mask], p.ws.Y[mask], p.ws.X[mask], p.stream);
+        launch_dense_modes(m.nmodes, m.block, p.ddense[mask], p.ws.Y[mask], p.ws.X[mask], 0, p.stream);
         if (int rc = check_launch("dense")) return rc;
     }
     {
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
         j.A[0] = p.ws.X[mask];
         j.B[0] = p.dV[f];
-        j.C[0] = p.ws.Y[mask];
+        j.C[0] = out;
+        j.accum = accum;
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
     }
     return ASDSM_OK;
 }
 
-// Refinement sweeps around the direct mesh solves (only where the plan asked for them):
-// save f, x = M^-1 f, then repeatedly x += M^-1 (f - A x).  The result stays where the plain solve
-// leaves it (X for the anisotropic meshes, Y for the intersection meshes).
-int copy_dd(Plan &p, double *dst, const double *src, long long n) {
-    ASDSM_HIP_CHECK(hipMemcpyAsync(dst, src, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
-    return ASDSM_OK;
-}
-
+// Mesh solves with the plan's refinement sweeps: x = M^-1 f, then x += M^-1 (f - A x) per sweep.
+// The right-hand side is read from rhs_buf and the solution left in sol_buf.
 int solve_aniso_refined(Plan &p, unsigned kbits) {
-    int ns = 0;
+    double *in[kMaxD] = {}, *out[kMaxD] = {};
+    int ns = 0, nb = 0;
     unsigned masks[kMaxD];
-    int nb = 0;
     for (int k = 0; k < p.d; ++k)
         if ((kbits >> k) & 1u) {
-            masks[nb++] = 1u << k;
-            ns = std::max(ns, p.sweeps[1u << k]);
+            const unsigned m = 1u << k;
+            masks[nb++] = m;
+            in[k] = rhs_buf(p, m);
+            out[k] = sol_buf(p, m);
+            ns = std::max(ns, p.sweeps[m]);
         }
-    if (ns == 0) return solve_aniso(p, kbits);
-    const long long n = p.mesh[1].size;
-    for (int q = 0; q < nb; ++q)
-        if (int rc = copy_dd(p, p.ws.Z[masks[q]], p.ws.X[masks[q]], n)) return rc;
-    if (int rc = solve_aniso(p, kbits)) return rc;
-    for (int q = 0; q < nb; ++q)
-        if (int rc = copy_dd(p, p.ws.W[masks[q]], p.ws.X[masks[q]], n)) return rc;
+    if (int rc = solve_aniso(p, kbits, in, out, 0)) return rc;
     for (int sweep = 0; sweep < ns; ++sweep) {
         BoxResJob job{};
         job.nbox = nb;
-        double *ys[kMaxD];
-        const double *xs[kMaxD];
+        double *res[kMaxD] = {};
         for (int q = 0; q < nb; ++q) {
-            job.f[q] = p.ws.Z[masks[q]];
-            job.x[q] = p.ws.W[masks[q]];
-            job.out[q] = p.ws.X[masks[q]];
-            job.m[q] = p.mesh[masks[q]];
-            ys[q] = p.ws.W[masks[q]];
-            xs[q] = p.ws.X[masks[q]];
+            const unsigned m = masks[q];
+            const int k = __builtin_ctz(m);
+            job.f[q] = in[k];
+            job.x[q] = out[k];
+            job.out[q] = p.ws.X[m];
+            job.m[q] = p.mesh[m];
+            res[k] = p.ws.X[m];
         }
-        launch_box_residual(p, job, p.stream);
-        if (int rc = check_launch("box residual")) return rc;
-        if (int rc = solve_aniso(p, kbits)) return rc;
-        launch_axpy(ys, xs, n, nb, p.stream);
-        if (int rc = check_launch("axpy")) return rc;
+        {
+            PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
+            launch_box_residual(p, job, p.stream);
+            if (int rc = check_launch("box residual")) return rc;
+        }
+        if (int rc = solve_aniso(p, kbits, res, out, 1)) return rc;
     }
-    for (int q = 0; q < nb; ++q)
-        if (int rc = copy_dd(p, p.ws.X[masks[q]], p.ws.W[masks[q]], n)) return rc;
     return ASDSM_OK;
 }
 
 int solve_intersection_refined(Plan &p, unsigned mask) {
-    const int ns = p.sweeps[mask];
-    if (ns == 0) return solve_intersection(p, mask);
-    const long long n = p.mesh[mask].size;
-    if (int rc = copy_dd(p, p.ws.Z[mask], p.ws.X[mask], n)) return rc;
-    if (int rc = solve_intersection(p, mask)) return rc;
-    if (int rc = copy_dd(p, p.ws.W[mask], p.ws.Y[mask], n)) return rc;
-    for (int sweep = 0; sweep < ns; ++sweep) {
+    const double *in = rhs_buf(p, mask);
+    double *out = sol_buf(p, mask);
+    if (int rc = solve_intersection(p, mask, in, out, 0)) return rc;
+    for (int sweep = 0; sweep < p.sweeps[mask]; ++sweep) {
         BoxResJob job{};
         job.nbox = 1;
-        job.f[0] = p.ws.Z[mask];
-        job.x[0] = p.ws.W[mask];
+        job.f[0] = in;
+        job.x[0] = out;
         job.out[0] = p.ws.X[mask];
         job.m[0] = p.mesh[mask];
-        launch_box_residual(p, job, p.stream);
-        if (int rc = check_launch("box residual")) return rc;
-        if (int rc = solve_intersection(p, mask)) return rc;
-        double *ys[1] = {p.ws.W[mask]};
-        const double *xs[1] = {p.ws.Y[mask]};
-        launch_axpy(ys, xs, n, 1, p.stream);
-        if (int rc = check_launch("axpy")) return rc;
+        {
+            PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
+            launch_box_residual(p, job, p.stream);
+            if (int rc = check_launch("box residual")) return rc;
+        }
+        if (int rc = solve_intersection(p, mask, p.ws.X[mask], out, 1)) return rc;
     }
-    return copy_dd(p, p.ws.Y[mask], p.ws.W[mask], n);
+    return ASDSM_OK;
 }
 
 void result_pointers(const Plan &p, const double *res[kMaxMeshes]) {
     for (unsigned s = 0; s < kMaxMeshes; ++s) res[s] = nullptr;
-    for (unsigned s = 1; s < (1u << p.d); ++s)
-        res[s] = (__builtin_popcount(s) == 1) ? p.ws.X[s] : p.ws.Y[s];
+    for (unsigned s = 1; s < (1u << p.d); ++s) res[s] = sol_buf(p, s);
 }
+
+void gather_pointers(const Plan &p, double *g[kMaxMeshes]) {
+    for (unsigned s = 0; s < kMaxMeshes; ++s) g[s] = nullptr;
+    for (unsigned s = 1; s < (1u << p.d); ++s) g[s] = rhs_buf(p, s);
+}
+
 
 int read_scalars(Plan &p) {
     ASDSM_HIP_CHECK(hipMemcpyAsync(p.hscal, p.ws.scal, kScalCount * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
+    return ASDSM_OK;
+}
+
+// A-posteriori refinement count.  The plan's a-priori count uses eps * prod cond(V_j), which bounds
+// the worst case; the error actually reached is usually orders of magnitude smaller.  With the
+// workspace attached, each mesh group that was given sweeps is solved once for a reproducible
+// random right-hand side and refined until a sweep changes the solution by less than 1e-12
+// (relative 2-norm); the sweeps before that one are what the solves keep.
+int calibrate_sweeps(Plan &p) {
+    const int d = p.d;
+    const int kMax = 10;
+    // groups: all anisotropic meshes together, then each intersection mesh
+    unsigned groups[kMaxMeshes];
+    int ng = 0;
+    {
+        unsigned all = 0;
+        for (int k = 0; k < d; ++k)
+            if (p.sweeps[1u << k] > 0) all |= 1u << k;
+        if (all) groups[ng++] = 0x100u | all;  // tag: anisotropic batch
+        for (unsigned m = 1; m < (1u << d); ++m)
+            if (__builtin_popcount(m) >= 2 && p.sweeps[m] > 0) groups[ng++] = m;
+    }
+    for (int gi = 0; gi < ng; ++gi) {
+        const bool aniso = (groups[gi] & 0x100u) != 0;
+        const unsigned kbits = groups[gi] & 0xFFu;
+        unsigned masks[kMaxD];
+        int nb = 0;
+        if (aniso) {
+            for (int k = 0; k < d; ++k)
+                if ((kbits >> k) & 1u) masks[nb++] = 1u << k;
+        } else {
+            masks[nb++] = kbits;
+        }
+        // right-hand sides, plain solves
+        double *in[kMaxD] = {}, *out[kMaxD] = {}, *tmp[kMaxD] = {}, *resid[kMaxD] = {};
+        double *temps[2] = {p.ws.e, p.ws.r};  // fine-mesh work vectors are free at this point
+        for (int q = 0; q < nb; ++q) {
+            const unsigned m = masks[q];
+            const long long n = p.mesh[m].size;
+            const int slot = aniso ? __builtin_ctz(m) : 0;
+            in[slot] = rhs_buf(p, m);
+            out[slot] = sol_buf(p, m);
+            tmp[slot] = (q < 2) ? temps[q] : p.ws.u2;
+            resid[slot] = p.ws.X[m];
+            launch_fill_random(in[slot], n, 0x5EEDull * (m + 1), p.stream);
+        }
+        if (aniso) {
+            if (int rc = solve_aniso(p, kbits, in, out, 0)) return rc;
+        } else {
+            if (int rc = solve_intersection(p, masks[0], in[0], out[0], 0)) return rc;
+        }
+        int needed = kMax;
+        for (int sweep = 1; sweep <= kMax; ++sweep) {
+            BoxResJob job{};
+            job.nbox = nb;
+            for (int q = 0; q < nb; ++q) {
+                const unsigned m = masks[q];
+                const int slot = aniso ? __builtin_ctz(m) : 0;
+                job.f[q] = in[slot];
+                job.x[q] = out[slot];
+                job.out[q] = resid[slot];
+                job.m[q] = p.mesh[m];
+            }
+            launch_box_residual(p, job, p.stream);
+            if (aniso) {
+                if (int rc = solve_aniso(p, kbits, resid, tmp, 0)) return rc;
+            } else {
+                if (int rc = solve_intersection(p, masks[0], resid[0], tmp[0], 0)) return rc;
+            }
+            const double *xs[2 * kMaxD];
+            long long ns[2 * kMaxD];
+            int nx = 0;
+            for (int q = 0; q < nb; ++q) {
+                const unsigned m = masks[q];
+                const int slot = aniso ? __builtin_ctz(m) : 0;
+                xs[nx] = tmp[slot];
+                ns[nx++] = p.mesh[m].size;
+            }
+            launch_sumsq(p, xs, ns, nx, p.stream);
+            if (int rc = read_scalars(p)) return rc;
+            double corr[kMaxD];
+            for (int q = 0; q < nb; ++q) corr[q] = p.hscal[kScalEnorm2 + q];
+            nx = 0;
+            for (int q = 0; q < nb; ++q) {
+                const unsigned m = masks[q];
+                const int slot = aniso ? __builtin_ctz(m) : 0;
+                xs[nx] = out[slot];
+                ns[nx++] = p.mesh[m].size;
+            }
+            launch_sumsq(p, xs, ns, nx, p.stream);
+            if (int rc = read_scalars(p)) return rc;
+            double worst = 0.0;
+            for (int q = 0; q < nb; ++q) {
+                const double sol = p.hscal[kScalEnorm2 + q];
+                const double ratio = (sol > 0.0) ? std::sqrt(corr[q] / sol) : 0.0;
+                if (!std::isfinite(ratio)) return fail(ASDSM_E_NUMERIC, "non-finite value while calibrating refinement");
+                worst = std::max(worst, ratio);
+            }
+            double *ys[kMaxD];
+            const double *xa[kMaxD];
+            for (int q = 0; q < nb; ++q) {
+                const unsigned m = masks[q];
+                const int slot = aniso ? __builtin_ctz(m) : 0;
+                ys[q] = out[slot];
+                xa[q] = tmp[slot];
+            }
+            long long nmax = 0;
+            for (int q = 0; q < nb; ++q) nmax = std::max(nmax, p.mesh[masks[q]].size);
+            if (nb == 1 || aniso) {
+                // every anisotropic mesh has the same size
+                launch_axpy(ys, xa, nmax, nb, p.stream);
+            }
+            if (int rc = check_launch("calibration")) return rc;
+            if (worst < 1e-12) {
+                needed = sweep - 1;
+                break;
+            }
+        }
+        if (needed >= kMax)
+            return fail(ASDSM_E_UNSUPPORTED, "refinement of the fast-diagonalisation solves does not converge");
+        for (int q = 0; q < nb; ++q) p.sweeps[masks[q]] = needed;
+    }
     ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
     return ASDSM_OK;
 }
@@ -293,8 +419,8 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     const unsigned nm = 1u << p.d;
     {
         PhaseTimer t(p, ASDSM_PHASE_RHS, (int)nm);
-        launch_rhs(p, 0, s, g, p.ws.b, p.ws.scal + kScalBnorm2, p.stream);
-        for (unsigned m = 1; m < nm; ++m) launch_rhs(p, m, s, g, p.ws.X[m], nullptr, p.stream);
+        launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
+        for (unsigned m = 1; m < nm; ++m) launch_rhs(p, m, s, g, rhs_buf(p, m), false, p.stream);
         if (int rc = check_launch("rhs")) return rc;
     }
     if (int rc = solve_aniso_refined(p, nm - 1)) return rc;
@@ -316,7 +442,9 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     }
     {
         PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1);
-        launch_update_residual(p, u, nullptr, nullptr, p.stream);
+        double *gat[kMaxMeshes];
+        gather_pointers(p, gat);
+        launch_update_residual(p, u, nullptr, nullptr, gat, p.stream);
         if (int rc = check_launch("residual")) return rc;
     }
     return ASDSM_OK;
@@ -330,8 +458,8 @@ int refine_step(Plan &p, int64_t k, const double *u_cur, double *u_next) {
     const double *res[kMaxMeshes];
     result_pointers(p, res);
     {
-        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 4 : 3);
-        launch_box_norms(p, p.stream);
+        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 5 : 4);
+        launch_box_norms(p, res, p.stream);
         launch_crosspoints(p, 1, perm, res, p.stream);
         launch_merge(p, 1, perm, res, p.stream);
         if (int rc = check_launch("skeleton")) return rc;
@@ -348,7 +476,9 @@ int refine_step(Plan &p, int64_t k, const double *u_cur, double *u_next) {
     }
     {
         PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1);
-        launch_update_residual(p, u_cur, p.ws.e, u_next, p.stream);
+        double *gat[kMaxMeshes];
+        gather_pointers(p, gat);
+        launch_update_residual(p, u_cur, p.ws.e, u_next, gat, p.stream);
         if (int rc = check_launch("update")) return rc;
     }
     return ASDSM_OK;
@@ -393,11 +523,13 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
     } else {
         {
             PhaseTimer t(p, ASDSM_PHASE_RHS, 1);
-            launch_rhs(p, 0, s, g, p.ws.b, p.ws.scal + kScalBnorm2, p.stream);
+            launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
             if (int rc = check_launch("rhs")) return rc;
         }
         PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1);
-        launch_update_residual(p, u, nullptr, nullptr, p.stream);
+        double *gat[kMaxMeshes];
+        gather_pointers(p, gat);
+        launch_update_residual(p, u, nullptr, nullptr, gat, p.stream);
         if (int rc = check_launch("residual")) return rc;
     }
     if (int rc = read_scalars(p)) return rc;
@@ -513,11 +645,9 @@ int asdsm_set_workspace(asdsm_plan_t plan, void *dev, size_t bytes) {
     p.ws_base = dev;
     p.ws_bytes = bytes;
     layout_workspace(p, (char *)dev, true);
-    // the last-block tickets must start at zero
-    hipError_t e = hipMemsetAsync(p.ws.counters, 0, kCntCount * sizeof(unsigned), p.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
-    if (e != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
-    return ASDSM_OK;
+    // restore the a-priori sweep counts (the layout holds their buffers), then calibrate
+    for (unsigned m = 0; m < kMaxMeshes; ++m) p.sweeps[m] = p.sweeps_prior[m];
+    return calibrate_sweeps(p);
 }
 
 int asdsm_solve(asdsm_plan_t plan, const double *s, const double *g, double *u,
@@ -532,8 +662,10 @@ int asdsm_residual(asdsm_plan_t plan, const double *u, const double *s, const do
     Plan &p = plan->p;
     if (!u || !s || !g) return fail(ASDSM_E_ARG, "u, s and g must be non-NULL device pointers");
     if (int rc = require_ws(p)) return rc;
-    launch_rhs(p, 0, s, g, p.ws.b, p.ws.scal + kScalBnorm2, p.stream);
-    launch_update_residual(p, u, nullptr, nullptr, p.stream);
+    launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
+    double *gat[kMaxMeshes];
+    gather_pointers(p, gat);
+    launch_update_residual(p, u, nullptr, nullptr, gat, p.stream);
     if (int rc = check_launch("residual")) return rc;
     if (r) ASDSM_HIP_CHECK(hipMemcpyAsync(r, p.ws.r, (size_t)p.geo.NF * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
     if (int rc = read_scalars(p)) return rc;
@@ -549,16 +681,13 @@ int asdsm_mesh_solve(asdsm_plan_t plan, unsigned mesh_mask, const double *rhs, d
     if (mesh_mask == 0 || mesh_mask >= (1u << p.d)) return fail(ASDSM_E_ARG, "invalid mesh mask");
     if (int rc = require_ws(p)) return rc;
     const size_t bytes = (size_t)p.mesh[mesh_mask].size * sizeof(double);
-    ASDSM_HIP_CHECK(hipMemcpyAsync(p.ws.X[mesh_mask], rhs, bytes, hipMemcpyDeviceToDevice, p.stream));
-    const double *res;
+    ASDSM_HIP_CHECK(hipMemcpyAsync(rhs_buf(p, mesh_mask), rhs, bytes, hipMemcpyDeviceToDevice, p.stream));
     if (__builtin_popcount(mesh_mask) == 1) {
-        int k = __builtin_ctz(mesh_mask);
-        if (int rc = solve_aniso_refined(p, 1u << k)) return rc;
-        res = p.ws.X[mesh_mask];
+        if (int rc = solve_aniso_refined(p, mesh_mask)) return rc;
     } else {
         if (int rc = solve_intersection_refined(p, mesh_mask)) return rc;
-        res = p.ws.Y[mesh_mask];
     }
+    const double *res = sol_buf(p, mesh_mask);
     ASDSM_HIP_CHECK(hipMemcpyAsync(x, res, bytes, hipMemcpyDeviceToDevice, p.stream));
     ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
     set_error("");

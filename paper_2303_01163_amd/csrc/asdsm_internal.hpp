@@ -71,7 +71,6 @@ struct Workspace {
     double *lines[kMaxD] = {};   // cross-point discrepancies of each anisotropic mesh
     double *partials = nullptr;  // per-block partial sums
     double *scal = nullptr;      // device scalars (see kScal*)
-    unsigned *counters = nullptr;// last-block tickets
 };
 
 // Device scalar slots.
@@ -86,8 +85,6 @@ enum ScalarSlot {
     kScalFlags = 11,   // non-finite flag accumulator
     kScalCount = 16
 };
-
-enum CounterSlot { kCntResidual = 0, kCntRhs = 1, kCntDots = 2, kCntBox = 3, kCntCount = 8 };
 
 struct Plan {
     int d = 0, level = 0, clevel = 0;
@@ -107,7 +104,8 @@ struct Plan {
     std::vector<double> dense_inv[kMaxMeshes];  // per-mode inverses for |S| >= 2
     double fdm_cond[kMaxMeshes] = {};  // product of the eigenvector condition numbers of the
                                        // transformed axes of each mesh
-    int sweeps[kMaxMeshes] = {};       // refinement sweeps of each mesh solve
+    int sweeps[kMaxMeshes] = {};       // refinement sweeps of each mesh solve (calibrated)
+    int sweeps_prior[kMaxMeshes] = {}; // a-priori counts from the condition numbers
 
     // device copies of the tables (one allocation owned by the plan)
     void *dtab = nullptr;

@@ -41,49 +41,16 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return t;  // valid in thread 0
 }
 
-__device__ __forceinline__ double load_coherent(const double *p) {
-    unsigned long long bits = __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)bits);
-}
-
-// Each block stores NV partial sums; the last block to arrive sums all partials in block order and
-// calls fin(totals) with thread 0.  The ticket counter is returned to zero by the last block.
-template <int NT, int NV, typename Fin>
-__device__ __forceinline__ void reduce_and_finalize_slice(const double (&v)[NV], double *partials,
-                                                          unsigned *counter, unsigned bid,
-                                                          unsigned nblk, Fin fin) {
+// Each block stores its NV partial sums (fixed in-block order) at partials[bid*NV + q].  The totals
+// are formed by k_finalize in a separate launch, so no fence or atomic is needed here: on a
+// multi-XCD device an agent-scope release fence per block would write back the L2 every time.
+template <int NT, int NV>
+__device__ __forceinline__ void block_partials(const double (&v)[NV], double *partials, size_t bid) {
     __shared__ double sh[NT / 64];
-    __shared__ bool last;
     double tot[NV];
     for (int q = 0; q < NV; ++q) tot[q] = block_sum<NT>(v[q], sh);
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < NV; ++q) partials[(size_t)bid * NV + q] = tot[q];
-        __threadfence();
-        const unsigned ticket = atomicAdd(counter, 1u);
-        last = (ticket == nblk - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double acc[NV];
-    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    for (unsigned b = threadIdx.x; b < nblk; b += NT)
-        for (int q = 0; q < NV; ++q) acc[q] += load_coherent(partials + (size_t)b * NV + q);
-    double res[NV];
-    for (int q = 0; q < NV; ++q) res[q] = block_sum<NT>(acc[q], sh);
-    if (threadIdx.x == 0) {
-        fin(res);
-        *counter = 0u;
-    }
-}
-
-template <int NT, int NV, typename Fin>
-__device__ __forceinline__ void reduce_and_finalize(const double (&v)[NV], double *partials,
-                                                    unsigned *counter, Fin fin) {
-    const unsigned nblk = gridDim.x * gridDim.y * gridDim.z;
-    const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    reduce_and_finalize_slice<NT, NV>(v, partials, counter, bid, nblk, fin);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < NV; ++q) partials[bid * NV + q] = tot[q];
 }
 
 }  // namespace asdsm

@@ -14,66 +14,72 @@
 namespace asdsm {
 
 // ---------------------------------------------------------------------------------------------
-// Batched FP64 GEMM on MFMA.  Block = 4 waves, block tile 32 x 32, each wave one 16 x 16 MFMA tile,
-// K staged through LDS in chunks of 32.
+// Batched FP64 GEMM on MFMA.  Block = 4 waves, block tile 32 x 32, each wave one 16 x 16 MFMA tile.
+// The A (32 x 64) and B (64 x 32) panels of each K chunk are staged in LDS with fully coalesced
+// loads (a wave reads 64 consecutive doubles along the contiguous index of the operand), so every
+// cache line is fetched once per block; MFMA operands are then read from padded, conflict-free LDS.
 // Operand layout of v_mfma_f64_16x16x4f64 (lane l, 0..63):
 //   A: row l%16, k l/16;  B: k l/16, col l%16;  D[v]: row l/16 + 4v, col l%16.
 // ---------------------------------------------------------------------------------------------
-constexpr int GBM = 32, GBN = 32, GBK = 32;
+constexpr int GKC = 64;  // K chunk
 
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
-    __shared__ double sA[GBM][GBK + 1];
-    __shared__ double sB[GBK][GBN + 1];
+    __shared__ double sA[32][GKC + 1];
+    __shared__ double sB[GKC][32 + 1];
     const int box = blockIdx.z / job.nbatch;
     const int bat = blockIdx.z % job.nbatch;
     const double *__restrict__ A = job.A[box] + (long long)bat * job.sAb;
     const double *__restrict__ B = job.B[box] + (long long)bat * job.sBb;
-    double *__restrict__ C = job.C[box] + (long long)bat * job.sCb;
-    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w & 1, wn = w >> 1;
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
     const bool a_kfast = (job.sAk == 1);
-    const bool b_nfast = (job.sBn == 1);
-    for (int k0 = 0; k0 < job.K; k0 += GBK) {
+    const bool b_kfast = (job.sBk == 1);
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < job.K; k0 += GKC) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int e = t + 256 * j;
+        for (int j = 0; j < 8; ++j) {
+            const int e = t + 256 * j;  // 0 .. 2047
             int ii, kk;
-            if (a_kfast) { ii = e >> 5; kk = e & 31; } else { ii = e & 31; kk = e >> 5; }
+            if (a_kfast) { ii = e >> 6; kk = e & 63; } else { kk = e >> 5; ii = e & 31; }
             const int gi = m0 + ii, gk = k0 + kk;
-            sA[ii][kk] = (gi < job.M && gk < job.K) ? A[gi * job.sAi + gk * job.sAk] : 0.0;
+            sA[ii][kk] = (gi < job.M && gk < job.K) ? A[(long long)gi * job.sAi + (long long)gk * job.sAk] : 0.0;
             int nn;
-            if (b_nfast) { kk = e >> 5; nn = e & 31; } else { kk = e & 31; nn = e >> 5; }
-            const int gn = n0 + nn;
-            const int gk2 = k0 + kk;
-            sB[kk][nn] = (gn < job.N && gk2 < job.K) ? B[gk2 * job.sBk + gn * job.sBn] : 0.0;
+            if (b_kfast) { nn = e >> 6; kk = e & 63; } else { kk = e >> 5; nn = e & 31; }
+            const int gn = n0 + nn, gk2 = k0 + kk;
+            sB[kk][nn] = (gn < job.N && gk2 < job.K) ? B[(long long)gk2 * job.sBk + (long long)gn * job.sBn] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < GBK; kk += 4) {
+        for (int kk = 0; kk < GKC; kk += 4) {
             const double a = sA[wm * 16 + (lane & 15)][kk + (lane >> 4)];
             const double b = sB[kk + (lane >> 4)][wn * 16 + (lane & 15)];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
         __syncthreads();
     }
+    double *__restrict__ C = job.C[box] + (long long)bat * job.sCb;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int gi = m0 + wm * 16 + (lane >> 4) + 4 * v;
         const int gn = n0 + wn * 16 + (lane & 15);
-        if (gi < job.M && gn < job.N) C[gi * job.sCi + gn * job.sCn] = acc[v];
+        if (gi < job.M && gn < job.N) {
+            double *c = C + (long long)gi * job.sCi + (long long)gn * job.sCn;
+            *c = job.accum ? *c + acc[v] : acc[v];
+        }
     }
 }
 
 void launch_gemm(const GemmJob &job, hipStream_t st) {
-    dim3 grid((job.N + GBN - 1) / GBN, (job.M + GBM - 1) / GBM, job.nbox * job.nbatch);
+    dim3 grid((job.N + 31) / 32, (job.M + 31) / 32, job.nbox * job.nbatch);
     hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st, job);
 }
 
 // ---------------------------------------------------------------------------------------------
-// Thomas elimination along the coarse axis, one thread per mode, boxes along blockIdx.y.
+// Thomas elimination along the coarse axis, one thread per mode, boxes along blockIdx.y.  Lines of
+// up to NCR points stay in registers (loads issued together); longer lines use the scratch array.
 // ---------------------------------------------------------------------------------------------
+template <int NCR>
 __global__ __launch_bounds__(256) void k_line(LineJob job) {
     const int box = blockIdx.y;
     const long long m = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -87,21 +93,45 @@ __global__ __launch_bounds__(256) void k_line(LineJob job) {
     if (job.mu_b[box]) sigma += job.mu_b[box][mb];
     const long long st = job.nmodes;
     const double diag = t.b + sigma;
+    const int nc = job.ncoarse;
+    if (NCR > 0) {
+        double f[NCR > 0 ? NCR : 1], cp[NCR > 0 ? NCR : 1];
+#pragma unroll
+        for (int c = 0; c < NCR; ++c)
+            if (c < nc) f[c] = X[m + st * c];
+        double den = diag;
+        cp[0] = t.c / den;
+        f[0] = f[0] / den;
+#pragma unroll
+        for (int c = 1; c < NCR; ++c)
+            if (c < nc) {
+                den = diag - t.a * cp[c - 1];
+                f[c] = (f[c] - t.a * f[c - 1]) / den;
+                cp[c] = t.c / den;
+            }
+#pragma unroll
+        for (int c = NCR - 2; c >= 0; --c)
+            if (c < nc - 1) f[c] = f[c] - cp[c] * f[c + 1];
+#pragma unroll
+        for (int c = 0; c < NCR; ++c)
+            if (c < nc) X[m + st * c] = f[c];
+        return;
+    }
     double den = diag;
-    double cp = t.c / den;
+    double cq = t.c / den;
     double dp = X[m] / den;
-    S[m] = cp;
+    S[m] = cq;
     X[m] = dp;
-    for (int c = 1; c < job.ncoarse; ++c) {
-        den = diag - t.a * cp;
-        const double f = X[m + st * c];
-        dp = (f - t.a * dp) / den;
-        cp = t.c / den;
-        S[m + st * c] = cp;
+    for (int c = 1; c < nc; ++c) {
+        den = diag - t.a * cq;
+        const double fc = X[m + st * c];
+        dp = (fc - t.a * dp) / den;
+        cq = t.c / den;
+        S[m + st * c] = cq;
         X[m + st * c] = dp;
     }
     double x = dp;
-    for (int c = job.ncoarse - 2; c >= 0; --c) {
+    for (int c = nc - 2; c >= 0; --c) {
         x = X[m + st * c] - S[m + st * c] * x;
         X[m + st * c] = x;
     }
@@ -109,7 +139,14 @@ __global__ __launch_bounds__(256) void k_line(LineJob job) {
 
 void launch_line(const LineJob &job, hipStream_t st) {
     dim3 grid((unsigned)((job.nmodes + 255) / 256), job.nbox, 1);
-    hipLaunchKernelGGL(k_line, grid, dim3(256), 0, st, job);
+    if (job.ncoarse <= 7)
+        hipLaunchKernelGGL(k_line<7>, grid, dim3(256), 0, st, job);
+    else if (job.ncoarse <= 15)
+        hipLaunchKernelGGL(k_line<15>, grid, dim3(256), 0, st, job);
+    else if (job.ncoarse <= 31)
+        hipLaunchKernelGGL(k_line<31>, grid, dim3(256), 0, st, job);
+    else
+        hipLaunchKernelGGL(k_line<0>, grid, dim3(256), 0, st, job);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -118,7 +155,7 @@ void launch_line(const LineJob &job, hipStream_t st) {
 __global__ __launch_bounds__(256) void k_dense_modes(long long nmodes, int B,
                                                      const double *__restrict__ inv,
                                                      const double *__restrict__ in,
-                                                     double *__restrict__ out) {
+                                                     double *__restrict__ out, int accum) {
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= nmodes * B) return;
     const long long m = t % nmodes;
@@ -126,14 +163,14 @@ __global__ __launch_bounds__(256) void k_dense_modes(long long nmodes, int B,
     const double *__restrict__ Mi = inv + (m * B + row) * (long long)B;
     double acc = 0.0;
     for (int e = 0; e < B; ++e) acc += Mi[e] * in[m + nmodes * e];
-    out[m + nmodes * row] = acc;
+    out[m + nmodes * row] = accum ? out[m + nmodes * row] + acc : acc;
 }
 
 void launch_dense_modes(long long nmodes, int B, const double *inv, const double *in, double *out,
-                        hipStream_t st) {
+                        int accum, hipStream_t st) {
     const long long n = nmodes * B;
     hipLaunchKernelGGL(k_dense_modes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nmodes, B,
-                       inv, in, out);
+                       inv, in, out, accum);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -142,27 +179,22 @@ void launch_dense_modes(long long nmodes, int B, const double *inv, const double
 // ---------------------------------------------------------------------------------------------
 constexpr int kNormBlocks = 128;
 
-__global__ __launch_bounds__(256) void k_box_norms(BoxPtrs X, long long size, double *partials,
-                                                   unsigned *counters, double *scal) {
+__global__ __launch_bounds__(256) void k_box_norms(BoxPtrs X, long long size, double *partials) {
     const int k = blockIdx.y;
     const double *__restrict__ x = X.p[k];
     double acc = 0.0;
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < size; i += (long long)gridDim.x * 256)
         acc += x[i] * x[i];
     double vals[1] = {acc};
-    reduce_and_finalize_slice<256, 1>(vals, partials + (size_t)k * kNormBlocks, counters + k,
-                                      blockIdx.x, gridDim.x, [&](const double *t) {
-                                          scal[kScalEnorm2 + k] = t[0];
-                                          scal[kScalInvNorm + k] = (t[0] > 0.0) ? 1.0 / sqrt(t[0]) : 1.0;
-                                      });
+    block_partials<256, 1>(vals, partials + (size_t)k * kNormBlocks, blockIdx.x);
 }
 
-void launch_box_norms(const Plan &p, hipStream_t st) {
+void launch_box_norms(const Plan &p, const double *const *sol, hipStream_t st) {
     BoxPtrs bx;
-    for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? p.ws.X[1u << k] : nullptr;
+    for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? const_cast<double *>(sol[1u << k]) : nullptr;
     const long long size = p.mesh[1].size;
-    hipLaunchKernelGGL(k_box_norms, dim3(kNormBlocks, p.d, 1), dim3(256), 0, st, bx, size,
-                       p.ws.partials, p.ws.counters + kCntBox, p.ws.scal);
+    hipLaunchKernelGGL(k_box_norms, dim3(kNormBlocks, p.d, 1), dim3(256), 0, st, bx, size, p.ws.partials);
+    launch_finalize(p, kNormBlocks, kFinBoxNorms, p.d, st);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -219,6 +251,50 @@ void launch_axpy(double *const *y, const double *const *x, long long n, int nbox
     long long blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_axpy, dim3((unsigned)blocks, nbox, 1), dim3(256), 0, st, job, n);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Calibration helpers: a reproducible random right-hand side and sums of squares.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill_random(double *x, long long n, unsigned long long seed) {
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z = z ^ (z >> 31);
+        x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+}
+
+void launch_fill_random(double *x, long long n, uint64_t seed, hipStream_t st) {
+    long long blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_fill_random, dim3((unsigned)blocks), dim3(256), 0, st, x, n, (unsigned long long)seed);
+}
+
+struct SumsqJob {
+    const double *x[kMaxD];
+    long long n[kMaxD];
+};
+
+__global__ __launch_bounds__(256) void k_sumsq(SumsqJob job, double *partials) {
+    const int k = blockIdx.y;
+    const double *__restrict__ x = job.x[k];
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < job.n[k]; i += (long long)gridDim.x * 256)
+        acc += x[i] * x[i];
+    double vals[1] = {acc};
+    block_partials<256, 1>(vals, partials + (size_t)k * kNormBlocks, blockIdx.x);
+}
+
+void launch_sumsq(const Plan &p, const double *const *x, const long long *n, int nbox, hipStream_t st) {
+    SumsqJob job{};
+    for (int k = 0; k < nbox; ++k) {
+        job.x[k] = x[k];
+        job.n[k] = n[k];
+    }
+    hipLaunchKernelGGL(k_sumsq, dim3(kNormBlocks, nbox, 1), dim3(256), 0, st, job, p.ws.partials);
+    launch_finalize(p, kNormBlocks, kFinBoxNorms, nbox, st);
 }
 
 }  // namespace asdsm

@@ -239,10 +239,12 @@ struct FillArgs {
     double *out;
 };
 
-template <int D>
+template <int D, int NH>
 __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
     extern __shared__ double lds[];
-    const int n = g.n, nh = g.n - 1, Nf = g.Nf, Nc = g.Nc;
+    // NH > 0: hole edge length known at compile time (constant-divisor index arithmetic)
+    const int nh = (NH > 0) ? NH : g.n - 1;
+    const int n = nh + 1, Nf = g.Nf, Nc = g.Nc;
     int npts = 1, st[kMaxD] = {1, 1, 1};
     for (int j = 0; j < D; ++j) {
         st[j] = npts;
@@ -419,10 +421,27 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
     const size_t lds = (size_t)(2 * npts + a.ntr * (2 * nh * nh + nh)) * sizeof(double);
     int tiles = 1;
     for (int j = 0; j < d; ++j) tiles *= (p.Nc + 1);
-    if (d == 2)
-        hipLaunchKernelGGL(k_filler<2>, dim3(tiles), dim3(256), lds, st, p.geo, a);
-    else
-        hipLaunchKernelGGL(k_filler<3>, dim3(tiles), dim3(256), lds, st, p.geo, a);
+    const dim3 grid(tiles), blk(256);
+#define ASDSM_FILL(DD, NHV) hipLaunchKernelGGL((k_filler<DD, NHV>), grid, blk, lds, st, p.geo, a)
+    if (d == 2) {
+        switch (nh) {
+            case 1: ASDSM_FILL(2, 1); break;
+            case 3: ASDSM_FILL(2, 3); break;
+            case 7: ASDSM_FILL(2, 7); break;
+            case 15: ASDSM_FILL(2, 15); break;
+            case 31: ASDSM_FILL(2, 31); break;
+            default: ASDSM_FILL(2, 0); break;
+        }
+    } else {
+        switch (nh) {
+            case 1: ASDSM_FILL(3, 1); break;
+            case 3: ASDSM_FILL(3, 3); break;
+            case 7: ASDSM_FILL(3, 7); break;
+            case 15: ASDSM_FILL(3, 15); break;
+            default: ASDSM_FILL(3, 0); break;
+        }
+    }
+#undef ASDSM_FILL
 }
 
 }  // namespace asdsm

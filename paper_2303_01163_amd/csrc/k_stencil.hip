@@ -19,7 +19,7 @@ namespace asdsm {
 __global__ __launch_bounds__(256) void k_rhs(Geo g, MeshDesc m, const double *__restrict__ s,
                                              const double *__restrict__ gf,
                                              double *__restrict__ out, double *partials,
-                                             unsigned *counter, double *norm2_out) {
+                                             int with_norm) {
     const int d = g.d;
     const long long faceN = (d == 2) ? g.Nf : (long long)g.Nf * g.Nf;
     double acc = 0.0;
@@ -61,9 +61,9 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, MeshDesc m, const double *__
         out[idx] = v;
         acc += v * v;
     }
-    if (norm2_out) {
+    if (with_norm) {
         double vals[1] = {acc};
-        reduce_and_finalize<256, 1>(vals, partials, counter, [&](const double *t) { *norm2_out = t[0]; });
+        block_partials<256, 1>(vals, partials, blockIdx.x);
     }
 }
 
@@ -74,7 +74,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_update_residual(
     Geo g, const double *__restrict__ uin, const double *__restrict__ e,
     const double *__restrict__ scal, const double *__restrict__ b, double *__restrict__ uout,
-    double *__restrict__ r, BoxPtrs boxes, double *partials, unsigned *counter, double *norm2_out) {
+    double *__restrict__ r, BoxPtrs boxes, double *partials) {
     const int Nf = g.Nf, n = g.n;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int i0 = blockIdx.y * 64 + tx;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_update_residual(
         }
     }
     double vals[1] = {acc};
-    reduce_and_finalize<256, 1>(vals, partials, counter, [&](const double *t) { *norm2_out = t[0]; });
+    block_partials<256, 1>(vals, partials, blockIdx.x + (size_t)gridDim.x * blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -122,8 +122,7 @@ __global__ __launch_bounds__(256) void k_update_residual(
 // ---------------------------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(256) void k_dots(Geo g, const double *__restrict__ e,
-                                              const double *__restrict__ r, double *partials,
-                                              unsigned *counter, double *scal) {
+                                              const double *__restrict__ r, double *partials) {
     const int Nf = g.Nf;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int i0 = blockIdx.y * 64 + tx;
@@ -149,12 +148,50 @@ __global__ __launch_bounds__(256) void k_dots(Geo g, const double *__restrict__ 
         qq += q * q;
     }
     double vals[2] = {rq, qq};
-    reduce_and_finalize<256, 2>(vals, partials, counter, [&](const double *t) {
-        scal[kScalRQ] = t[0];
-        scal[kScalQQ] = t[1];
-        const double st = (t[1] > 0.0) ? t[0] / t[1] : 0.0;
-        scal[kScalStep] = (st > 0.0) ? st : 0.0;
-    });
+    block_partials<256, 2>(vals, partials, blockIdx.x + (size_t)gridDim.x * blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Totals of the per-block partial sums, in block order (deterministic), and what derives from them.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblk,
+                                                  int mode, int nbox, double *scal) {
+    __shared__ double sh[4];
+    const int tid = threadIdx.x;
+    if (mode == kFinDots) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int b = tid; b < nblk; b += 256) {
+            a0 += partials[2 * b];
+            a1 += partials[2 * b + 1];
+        }
+        const double rq = block_sum<256>(a0, sh);
+        const double qq = block_sum<256>(a1, sh);
+        if (tid == 0) {
+            scal[kScalRQ] = rq;
+            scal[kScalQQ] = qq;
+            const double st = (qq > 0.0) ? rq / qq : 0.0;
+            scal[kScalStep] = (st > 0.0) ? st : 0.0;
+        }
+    } else if (mode == kFinBoxNorms) {
+        for (int k = 0; k < nbox; ++k) {
+            double a = 0.0;
+            for (int b = tid; b < nblk; b += 256) a += partials[(size_t)k * nblk + b];
+            const double t = block_sum<256>(a, sh);
+            if (tid == 0) {
+                scal[kScalEnorm2 + k] = t;
+                scal[kScalInvNorm + k] = (t > 0.0) ? 1.0 / sqrt(t) : 1.0;
+            }
+        }
+    } else {
+        double a = 0.0;
+        for (int b = tid; b < nblk; b += 256) a += partials[b];
+        const double t = block_sum<256>(a, sh);
+        if (tid == 0) scal[mode == kFinBnorm ? kScalBnorm2 : kScalRnorm2] = t;
+    }
+}
+
+void launch_finalize(const Plan &p, int nblk, int mode, int nbox, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, p.ws.partials, nblk, mode, nbox, p.ws.scal);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -164,7 +201,7 @@ static void stencil_grid(const Geo &g, dim3 &grid) {
     const long long nrows = g.NF / g.Nf;
     const int xch = (g.Nf + 63) / 64;
     long long rgs = (nrows + 3) / 4;
-    long long cap = 16384 / xch;
+    long long cap = 2048 / xch;
     if (cap < 1) cap = 1;
     grid = dim3((unsigned)(rgs < cap ? rgs : cap), (unsigned)xch, 1);
 }
@@ -176,39 +213,38 @@ int stencil_blocks(const Geo &g) {
 }
 
 void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf, double *out,
-                double *norm2_out, hipStream_t st) {
+                bool with_norm, hipStream_t st) {
     const MeshDesc &m = p.mesh[mask];
     long long blocks = (m.size + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_rhs, dim3((unsigned)blocks), dim3(256), 0, st, p.geo, m, s, gf, out,
-                       p.ws.partials, p.ws.counters + kCntRhs, norm2_out);
+                       p.ws.partials, with_norm ? 1 : 0);
+    if (with_norm) launch_finalize(p, (int)blocks, kFinBnorm, 1, st);
 }
 
 void launch_update_residual(const Plan &p, const double *uin, const double *e, double *uout,
-                            hipStream_t st) {
+                            double *const *gather, hipStream_t st) {
     dim3 grid;
     stencil_grid(p.geo, grid);
     BoxPtrs bx;
-    for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? p.ws.X[1u << k] : nullptr;
+    for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? gather[1u << k] : nullptr;
     if (p.d == 2)
         hipLaunchKernelGGL(k_update_residual<2>, grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
-                           p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.ws.counters + kCntResidual,
-                           p.ws.scal + kScalRnorm2);
+                           p.ws.b, uout, p.ws.r, bx, p.ws.partials);
     else
         hipLaunchKernelGGL(k_update_residual<3>, grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
-                           p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.ws.counters + kCntResidual,
-                           p.ws.scal + kScalRnorm2);
+                           p.ws.b, uout, p.ws.r, bx, p.ws.partials);
+    launch_finalize(p, (int)(grid.x * grid.y), kFinRnorm, 1, st);
 }
 
 void launch_dots(const Plan &p, hipStream_t st) {
     dim3 grid;
     stencil_grid(p.geo, grid);
     if (p.d == 2)
-        hipLaunchKernelGGL(k_dots<2>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials,
-                           p.ws.counters + kCntDots, p.ws.scal);
+        hipLaunchKernelGGL(k_dots<2>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials);
     else
-        hipLaunchKernelGGL(k_dots<3>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials,
-                           p.ws.counters + kCntDots, p.ws.scal);
+        hipLaunchKernelGGL(k_dots<3>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials);
+    launch_finalize(p, (int)(grid.x * grid.y), kFinDots, 1, st);
 }
 
 }  // namespace asdsm

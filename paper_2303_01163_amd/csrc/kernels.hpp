@@ -17,6 +17,7 @@ struct GemmJob {
     double *C[kMaxD];
     int nbox;
     int M, N, K, nbatch;
+    int accum;                 // 1: C += A B, 0: C = A B
     long long sAb, sAi, sAk, sBb, sBk, sBn, sCb, sCi, sCn;
 };
 
@@ -34,18 +35,20 @@ struct LineJob {
     int ncoarse;               // points along the coarse axis
 };
 
+enum FinMode { kFinRnorm = 0, kFinBnorm = 1, kFinDots = 2, kFinBoxNorms = 3 };
+void launch_finalize(const Plan &p, int nblk, int mode, int nbox, hipStream_t st);
 void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf, double *out,
-                double *norm2_out, hipStream_t st);
+                bool with_norm, hipStream_t st);
 void launch_update_residual(const Plan &p, const double *uin, const double *e, double *uout,
-                            hipStream_t st);
+                            double *const *gather, hipStream_t st);
 void launch_dots(const Plan &p, hipStream_t st);
 int stencil_blocks(const Geo &g);
 
 void launch_gemm(const GemmJob &job, hipStream_t st);
 void launch_line(const LineJob &job, hipStream_t st);
 void launch_dense_modes(long long nmodes, int B, const double *inv, const double *in, double *out,
-                        hipStream_t st);
-void launch_box_norms(const Plan &p, hipStream_t st);
+                        int accum, hipStream_t st);
+void launch_box_norms(const Plan &p, const double *const *sol, hipStream_t st);
 
 // Residual of a mesh system with zero Dirichlet data, out = f - A_S x, for up to 3 meshes at once
 // (refinement sweeps of the submesh solves).
@@ -59,6 +62,11 @@ struct BoxResJob {
 void launch_box_residual(const Plan &p, const BoxResJob &job, hipStream_t st);
 // y_i += x_i for up to 3 arrays of n doubles
 void launch_axpy(double *const *y, const double *const *x, long long n, int nbox, hipStream_t st);
+
+// deterministic pseudo-random fill in [-1, 1) (counter-based hash of seed and index)
+void launch_fill_random(double *x, long long n, uint64_t seed, hipStream_t st);
+// sum of squares of up to 3 arrays into scal[kScalEnorm2 + k] (finalised)
+void launch_sumsq(const Plan &p, const double *const *x, const long long *n, int nbox, hipStream_t st);
 
 // skeleton: mode 0 = initial guess (extrapolated cross points), 1 = error phase (random choice)
 void launch_crosspoints(const Plan &p, int mode, const int *perm, const double *const *res,

@@ -262,7 +262,6 @@ void layout_workspace(Plan &p, char *base, bool assign) {
     for (int k = 0; k < p.d; ++k) w.lines[k] = (double *)take(nl * 8);
     w.partials = (double *)take((size_t)p.max_blocks * 4 * 8);
     w.scal = (double *)take(kScalCount * 8);
-    w.counters = (unsigned *)take(kCntCount * sizeof(unsigned));
     p.ws_need = off;
     if (assign) p.ws = w;
 }
@@ -355,7 +354,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     }
     // Fast diagonalisation of a fine axis uses the eigenvector matrix V = D Q with
     // cond(V) = r^(N-1), so a mesh solve is accurate to about eps * prod cond(V_j) over its
-    // transformed axes.  Where that exceeds 1e-12 the direct solve becomes the preconditioner of
+    // transformed axes.  Where that exceeds 2e-11 the direct solve becomes the preconditioner of
     // FP64 refinement sweeps x <- x + M^-1 (f - A x), each gaining -log10(eps * prod cond) digits;
     // the count is fixed here so that the result reaches ~1e-14.
     for (unsigned s = 1; s < (1u << d); ++s) {
@@ -363,7 +362,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         for (int q = 0; q < p.mesh[s].nfine; ++q) c *= p.fine_spec[p.mesh[s].ax[q]].cond;
         p.fdm_cond[s] = c;
         const double delta = 2.2e-16 * c;
-        if (delta <= 1e-12) {
+        if (delta <= 2e-11) {
             p.sweeps[s] = 0;
         } else if (delta >= 0.05) {
             return fail(ASDSM_E_UNSUPPORTED,
@@ -379,6 +378,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         int smax = 0;
         for (int k = 0; k < d; ++k) smax = std::max(smax, p.sweeps[1u << k]);
         for (int k = 0; k < d; ++k) p.sweeps[1u << k] = smax;
+        for (unsigned m = 0; m < kMaxMeshes; ++m) p.sweeps_prior[m] = p.sweeps[m];
     }
     {
         double ch = 1.0;
