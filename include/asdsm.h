@@ -63,7 +63,7 @@ extern "C" {
 
 typedef struct asdsm_plan_s *asdsm_plan_t;
 
-/* Options of asdsm_solve.  Stopping rule (the paper's loop condition of Algorithm 4, read as
+/* Options of asdsm_solve (max_iter < 8192).  Stopping rule (the paper's loop condition of Algorithm 4, read as
  * "iterate while not converged and not stagnated"): iterate while ||r_k||_2 > rtol*||b_ff||_2 and
  * k < max_iter and not stagnated; stagnated = ||r_{k+1}||_2 > (1 - stag_eta)*||r_k||_2 for
  * stag_window consecutive iterations (stag_window = 0 disables it), or a zero line-search step. */
@@ -77,6 +77,9 @@ typedef struct {
     double *hist;         /* optional host array, length max_iter+1: ||r_k||_2 per iterate      */
     double *step_hist;    /* optional host array, length max_iter: the line-search step s_k     */
     int    profile;       /* nonzero: time each phase with HIP events (adds synchronisation)    */
+    int    eager;         /* nonzero: launch the refinement kernels one by one and check the     */
+                          /* stopping rule after every step, instead of replaying a captured    */
+                          /* HIP graph of two steps and checking every four steps               */
 } asdsm_opts;
 
 typedef struct {

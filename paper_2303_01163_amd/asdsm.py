@@ -33,7 +33,8 @@ class AsdsmError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("max_iter", c_int), ("rtol", c_double), ("stag_window", c_int),
                 ("stag_eta", c_double), ("resume", c_int), ("k0", c_int64),
-                ("hist", POINTER(c_double)), ("step_hist", POINTER(c_double)), ("profile", c_int)]
+                ("hist", POINTER(c_double)), ("step_hist", POINTER(c_double)), ("profile", c_int),
+                ("eager", c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -134,7 +135,7 @@ class Plan:
         return tuple([self.n_f] * len(fine) + [self.n_c] * len(coarse)), fine + coarse
 
     def solve(self, s, g, u=None, max_iter=50, rtol=1e-10, stag_window=3, stag_eta=1e-3,
-              resume=False, k0=0, profile=False):
+              resume=False, k0=0, profile=False, eager=False):
         import torch
         lib = load_library()
         if u is None:
@@ -144,7 +145,8 @@ class Plan:
         o = Opts(max_iter=int(max_iter), rtol=float(rtol), stag_window=int(stag_window),
                  stag_eta=float(stag_eta), resume=1 if resume else 0, k0=int(k0),
                  hist=ctypes.cast(hist, POINTER(c_double)),
-                 step_hist=ctypes.cast(steps, POINTER(c_double)), profile=1 if profile else 0)
+                 step_hist=ctypes.cast(steps, POINTER(c_double)), profile=1 if profile else 0,
+                 eager=1 if eager else 0)
         st = Stats()
         with torch.cuda.device(self.device):
             rc = _check(lib.asdsm_solve(self._h, _dptr(s, self.n_fine, "s"),

@@ -74,6 +74,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
     const long long Nf2 = (long long)Nf * Nf;
     GemmJob j{};
     j.nbox = nb;
+    j.gate = p.gate;
     // forward transform along canonical axis 0 (contiguous): in -> Y
     {
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
@@ -115,6 +116,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
         PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
         LineJob L{};
         L.nbox = nb;
+        L.gate = p.gate;
         L.nmodes = (d == 2) ? Nf : Nf2;
         L.ext_a = Nf;
         L.ncoarse = Nc;
@@ -184,6 +186,7 @@ int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, in
     const int f = m.ax[0];
     GemmJob j{};
     j.nbox = 1;
+    j.gate = p.gate;
     j.M = m.block; j.N = p.Nf; j.K = p.Nf; j.nbatch = 1;
     j.sAb = j.sBb = j.sCb = 0;
     j.sAi = p.Nf; j.sAk = 1;
@@ -233,6 +236,7 @@ int solve_aniso_refined(Plan &p, unsigned kbits) {
     for (int sweep = 0; sweep < ns; ++sweep) {
         BoxResJob job{};
         job.nbox = nb;
+        job.gate = p.gate;
         double *res[kMaxD] = {};
         for (int q = 0; q < nb; ++q) {
             const unsigned m = masks[q];
@@ -414,11 +418,12 @@ int calibrate_sweeps(Plan &p) {
     return ASDSM_OK;
 }
 
-// Algorithm 1 with the source: u^(0) into u, then r = b - A u^(0) with its gathers.
+// Algorithm 1 with the source: u^(0) into u, then r = b - A u^(0) with its gathers, ||b||, ||r_0||
+// and the start of the device-side stopping rule.
 int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     const unsigned nm = 1u << p.d;
     {
-        PhaseTimer t(p, ASDSM_PHASE_RHS, (int)nm);
+        PhaseTimer t(p, ASDSM_PHASE_RHS, (int)nm + 1);
         launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
         for (unsigned m = 1; m < nm; ++m) launch_rhs(p, m, s, g, rhs_buf(p, m), false, p.stream);
         if (int rc = check_launch("rhs")) return rc;
@@ -431,8 +436,8 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     result_pointers(p, res);
     {
         PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 3 : 2);
-        launch_crosspoints(p, 0, nullptr, res, p.stream);
-        launch_merge(p, 0, nullptr, res, p.stream);
+        launch_crosspoints(p, 0, res, p.stream);
+        launch_merge(p, 0, res, p.stream);
         if (int rc = check_launch("skeleton")) return rc;
     }
     {
@@ -441,27 +446,27 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
         if (int rc = check_launch("filler")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1);
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2);
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
-        launch_update_residual(p, u, nullptr, nullptr, gat, p.stream);
+        launch_update_residual(p, u, nullptr, nullptr, gat, kFinInit, p.stream);
         if (int rc = check_launch("residual")) return rc;
     }
     return ASDSM_OK;
 }
 
-// One refinement step of Algorithm 4 from u_cur (with r and its gathers current) into u_next.
-int refine_step(Plan &p, int64_t k, const double *u_cur, double *u_next) {
+// One refinement step of Algorithm 4 from u_cur (with r and its gathers current) into u_next.  All
+// of its kernels return at once when the device stopping rule has fired (p.gate), so steps can be
+// queued (or replayed from a graph) ahead of the host's check.
+int refine_step(Plan &p, const double *u_cur, double *u_next) {
     if (int rc = solve_aniso_refined(p, (1u << p.d) - 1)) return rc;
-    int perm[kMaxD];
-    axis_permutation(p.seed, k, p.d, perm);
     const double *res[kMaxMeshes];
     result_pointers(p, res);
     {
         PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 5 : 4);
         launch_box_norms(p, res, p.stream);
-        launch_crosspoints(p, 1, perm, res, p.stream);
-        launch_merge(p, 1, perm, res, p.stream);
+        launch_crosspoints(p, 1, res, p.stream);
+        launch_merge(p, 1, res, p.stream);
         if (int rc = check_launch("skeleton")) return rc;
     }
     {
@@ -470,15 +475,15 @@ int refine_step(Plan &p, int64_t k, const double *u_cur, double *u_next) {
         if (int rc = check_launch("filler")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_DOTS, 1);
+        PhaseTimer t(p, ASDSM_PHASE_DOTS, 2);
         launch_dots(p, p.stream);
         if (int rc = check_launch("dots")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1);
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2);
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
-        launch_update_residual(p, u_cur, p.ws.e, u_next, gat, p.stream);
+        launch_update_residual(p, u_cur, p.ws.e, u_next, gat, kFinIter, p.stream);
         if (int rc = check_launch("update")) return rc;
     }
     return ASDSM_OK;
@@ -486,6 +491,49 @@ int refine_step(Plan &p, int64_t k, const double *u_cur, double *u_next) {
 
 int require_ws(const Plan &p) {
     if (!p.ws_base) return fail(ASDSM_E_WORKSPACE, "no workspace attached (asdsm_set_workspace)");
+    return ASDSM_OK;
+}
+
+int read_state(Plan &p) {
+    ASDSM_HIP_CHECK(hipMemcpyAsync(p.hstate, p.ws.state, sizeof(IterState), hipMemcpyDeviceToHost, p.stream));
+    ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
+    return ASDSM_OK;
+}
+
+void destroy_graph(Plan &p) {
+    if (p.graph_exec) (void)hipGraphExecDestroy(p.graph_exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    p.graph_exec = nullptr;
+    p.graph = nullptr;
+    p.graph_u = nullptr;
+}
+
+// Capture two gated refinement steps (u -> u2 -> u) into a graph, replayed by the solve loop.  The
+// capture happens on a private stream (the caller's may be the null stream); the graph is launched
+// on the plan's stream.  It holds kernel nodes only (no memset or copy nodes).
+int build_graph(Plan &p, double *u) {
+    destroy_graph(p);
+    if (!p.capture_stream) ASDSM_HIP_CHECK(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
+    hipStream_t saved = p.stream;
+    p.stream = p.capture_stream;
+    ASDSM_HIP_CHECK(hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = refine_step(p, u, p.ws.u2);
+    if (rc == ASDSM_OK) rc = refine_step(p, p.ws.u2, u);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(p.capture_stream, &graph);
+    p.stream = saved;
+    if (rc != ASDSM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    p.graph = graph;
+    e = hipGraphInstantiate(&p.graph_exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        destroy_graph(p);
+        return fail(ASDSM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    p.graph_u = u;
     return ASDSM_OK;
 }
 
@@ -502,11 +550,12 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         opt.stag_eta = 1e-3;
     }
     if (!s || !g || !u) return fail(ASDSM_E_ARG, "s, g and u must be non-NULL device pointers");
-    if (opt.max_iter < 0 || !(opt.rtol >= 0.0) || opt.stag_window < 0 || !(opt.stag_eta >= 0.0) ||
-        !(opt.stag_eta < 1.0))
-        return fail(ASDSM_E_ARG, "invalid options");
+    if (opt.max_iter < 0 || opt.max_iter >= kHistCap || !(opt.rtol >= 0.0) || opt.stag_window < 0 ||
+        !(opt.stag_eta >= 0.0) || !(opt.stag_eta < 1.0))
+        return fail(ASDSM_E_ARG, "invalid options (max_iter must be < " + std::to_string(kHistCap) + ")");
     if (int rc = require_ws(p)) return rc;
     p.profiling = opt.profile != 0;
+    const bool use_graph = !p.profiling && !opt.eager;
     for (int q = 0; q < ASDSM_NPHASE; ++q) {
         p.phase_ms[q] = 0.0;
         p.phase_launches[q] = 0;
@@ -517,69 +566,84 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         ASDSM_HIP_CHECK(hipEventCreate(&te));
         ASDSM_HIP_CHECK(hipEventRecord(tb, p.stream));
     }
-    double *u_cur = u, *u_next = p.ws.u2;
+    // loop state and the random cross-point choices of every step of this call
+    IterState &hs = *p.hstate;
+    std::memset(&hs, 0, sizeof hs);
+    hs.status = ASDSM_MAXITER;
+    hs.max_iter = opt.max_iter;
+    hs.stag_window = opt.stag_window;
+    hs.rtol = opt.rtol;
+    hs.stag_eta = opt.stag_eta;
+    const int64_t k0 = opt.resume ? opt.k0 : 0;
+    for (int i = 0; i < opt.max_iter; ++i) axis_permutation(p.seed, k0 + i, p.d, p.hperm + kMaxD * i);
+    ASDSM_HIP_CHECK(hipMemcpyAsync(p.ws.state, &hs, sizeof hs, hipMemcpyHostToDevice, p.stream));
+    if (opt.max_iter > 0)
+        ASDSM_HIP_CHECK(hipMemcpyAsync(p.ws.perm_table, p.hperm, (size_t)opt.max_iter * kMaxD * sizeof(int),
+                                       hipMemcpyHostToDevice, p.stream));
+    p.gate = nullptr;
     if (!opt.resume) {
         if (int rc = initial_guess(p, s, g, u)) return rc;
     } else {
         {
-            PhaseTimer t(p, ASDSM_PHASE_RHS, 1);
+            PhaseTimer t(p, ASDSM_PHASE_RHS, 2);
             launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
             if (int rc = check_launch("rhs")) return rc;
         }
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1);
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2);
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
-        launch_update_residual(p, u, nullptr, nullptr, gat, p.stream);
+        launch_update_residual(p, u, nullptr, nullptr, gat, kFinInit, p.stream);
         if (int rc = check_launch("residual")) return rc;
     }
-    if (int rc = read_scalars(p)) return rc;
-    const double bnorm = std::sqrt(p.hscal[kScalBnorm2]);
-    double rn = std::sqrt(p.hscal[kScalRnorm2]);
-    if (!std::isfinite(bnorm) || !std::isfinite(rn))
-        return fail(ASDSM_E_NUMERIC, "non-finite right-hand side or residual");
-    const double r0 = rn;
-    if (opt.hist) opt.hist[0] = rn;
-    int status = ASDSM_MAXITER;
-    int it = 0, stag = 0;
-    int64_t k = opt.resume ? opt.k0 : 0;
-    for (;;) {
-        if ((bnorm > 0.0 && rn <= opt.rtol * bnorm) || (bnorm == 0.0 && rn == 0.0)) {
-            status = ASDSM_OK;
-            break;
+    p.gate = &p.ws.state->done;
+    int rc = ASDSM_OK;
+    if (use_graph) {
+        if (p.graph_u != u || !p.graph_exec) rc = build_graph(p, u);
+        // two steps per replay, two replays per host check; surplus steps are gated no-ops
+        int steps = 0;
+        while (rc == ASDSM_OK) {
+            for (int rep = 0; rep < 2 && steps < opt.max_iter; ++rep, steps += 2) {
+                hipError_t e = hipGraphLaunch(p.graph_exec, p.stream);
+                if (e != hipSuccess) {
+                    rc = fail(ASDSM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+                    break;
+                }
+            }
+            if (rc != ASDSM_OK) break;
+            rc = read_state(p);
+            if (rc != ASDSM_OK || hs.done || steps >= opt.max_iter) break;
         }
-        if (it >= opt.max_iter) {
-            status = ASDSM_MAXITER;
-            break;
-        }
-        if (int rc = refine_step(p, k, u_cur, u_next)) return rc;
-        if (int rc = read_scalars(p)) return rc;
-        const double rn_new = std::sqrt(p.hscal[kScalRnorm2]);
-        const double shat = p.hscal[kScalStep];
-        if (!std::isfinite(rn_new) || !std::isfinite(shat))
-            return fail(ASDSM_E_NUMERIC, "non-finite residual during refinement");
-        double *tmp = u_cur;
-        u_cur = u_next;
-        u_next = tmp;
-        if (opt.step_hist) opt.step_hist[it] = shat;
-        ++it;
-        ++k;
-        if (opt.hist) opt.hist[it] = rn_new;
-        stag = (rn_new > (1.0 - opt.stag_eta) * rn) ? stag + 1 : 0;
-        rn = rn_new;
-        if (shat == 0.0 || (opt.stag_window > 0 && stag >= opt.stag_window)) {
-            status = ASDSM_STAGNATED;
-            break;
+    } else {
+        for (int i = 0; i < opt.max_iter && rc == ASDSM_OK; ++i) {
+            rc = (i % 2 == 0) ? refine_step(p, u, p.ws.u2) : refine_step(p, p.ws.u2, u);
+            if (rc == ASDSM_OK) rc = read_state(p);
+            if (hs.done) break;
         }
     }
-    if (u_cur != u) {
-        ASDSM_HIP_CHECK(hipMemcpyAsync(u, u_cur, (size_t)p.geo.NF * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
-    }
+    p.gate = nullptr;
+    if (rc != ASDSM_OK) return rc;
+    if (int rc2 = read_state(p)) return rc2;
+    if (int rc2 = read_scalars(p)) return rc2;
+    const int it = hs.it;
+    if (!hs.done) hs.status = ASDSM_MAXITER;
+    if (hs.status == ASDSM_E_NUMERIC) return fail(ASDSM_E_NUMERIC, "non-finite right-hand side or residual");
+    // the iterate after `it` steps is in u for even it, in the second buffer for odd it
+    if (it % 2 == 1)
+        ASDSM_HIP_CHECK(hipMemcpyAsync(u, p.ws.u2, (size_t)p.geo.NF * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
+    double r0 = 0.0, rn = 0.0;
+    ASDSM_HIP_CHECK(hipMemcpyAsync(&r0, p.ws.hist, sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    ASDSM_HIP_CHECK(hipMemcpyAsync(&rn, p.ws.hist + it, sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    if (opt.hist)
+        ASDSM_HIP_CHECK(hipMemcpyAsync(opt.hist, p.ws.hist, (size_t)(it + 1) * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    if (opt.step_hist && it > 0)
+        ASDSM_HIP_CHECK(hipMemcpyAsync(opt.step_hist, p.ws.step_hist, (size_t)it * sizeof(double), hipMemcpyDeviceToHost, p.stream));
     ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
+    const int status = hs.status;
     if (st) {
         std::memset(st, 0, sizeof *st);
         st->status = status;
         st->iterations = it;
-        st->bnorm = bnorm;
+        st->bnorm = std::sqrt(p.hscal[kScalBnorm2]);
         st->r0norm = r0;
         st->rnorm = rn;
         for (int q = 0; q < ASDSM_NPHASE; ++q) {
@@ -665,7 +729,8 @@ int asdsm_residual(asdsm_plan_t plan, const double *u, const double *s, const do
     launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
     double *gat[kMaxMeshes];
     gather_pointers(p, gat);
-    launch_update_residual(p, u, nullptr, nullptr, gat, p.stream);
+    p.gate = nullptr;
+    launch_update_residual(p, u, nullptr, nullptr, gat, kFinRnorm, p.stream);
     if (int rc = check_launch("residual")) return rc;
     if (r) ASDSM_HIP_CHECK(hipMemcpyAsync(r, p.ws.r, (size_t)p.geo.NF * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
     if (int rc = read_scalars(p)) return rc;

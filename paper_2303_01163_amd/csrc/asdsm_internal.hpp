@@ -59,6 +59,25 @@ struct AxisSpectrum {
     std::vector<double> V;          // backward transform V[i*N + m] = V(i, m)
 };
 
+// Device-resident state of the refinement loop (Algorithm 4 with the stopping rule): the loop can
+// run several iterations, or a captured graph of them, without a host round trip; every kernel of a
+// refinement step returns at once when `done` is set.
+struct IterState {
+    int done;          // 1 once the stopping rule has fired (or a non-finite value appeared)
+    int status;        // ASDSM_OK / ASDSM_STAGNATED / ASDSM_MAXITER / ASDSM_E_NUMERIC
+    int it;            // refinement steps completed by this call
+    int stag;          // consecutive steps with ||r_{k+1}|| > (1 - eta) ||r_k||
+    int max_iter;
+    int stag_window;
+    int pad0, pad1;
+    double rtol;
+    double stag_eta;
+    double rn_prev;    // ||r|| of the current iterate
+    double spare;
+};
+
+constexpr int kHistCap = 8192;   // capacity of the device residual / step histories
+
 struct Workspace {
     double *b = nullptr;         // fine right-hand side b_ff
     double *r = nullptr;         // fine residual
@@ -69,6 +88,10 @@ struct Workspace {
     double *Z[kMaxMeshes] = {};  // saved right-hand side (refinement sweeps), per mask
     double *W[kMaxMeshes] = {};  // accumulated solution (refinement sweeps), per mask
     double *lines[kMaxD] = {};   // cross-point discrepancies of each anisotropic mesh
+    IterState *state = nullptr;  // refinement-loop state
+    double *hist = nullptr;      // ||r_k||, k = 0..it
+    double *step_hist = nullptr; // s_hat_k
+    int *perm_table = nullptr;   // axis permutation of every step of this call (kMaxD ints each)
     double *partials = nullptr;  // per-block partial sums
     double *scal = nullptr;      // device scalars (see kScal*)
 };
@@ -122,8 +145,19 @@ struct Plan {
     size_t ws_need = 0;
     int max_blocks = 0;              // partial-sum capacity
 
-    // pinned host mirror of the device scalars
+    // pinned host mirror of the device scalars and of the loop state
     double *hscal = nullptr;
+    IterState *hstate = nullptr;
+    int *hperm = nullptr;        // pinned staging of the permutation table
+
+    // refinement kernels return early when *gate != 0 (nullptr outside the refinement loop)
+    const int *gate = nullptr;
+
+    // captured refinement graph (two steps: u -> u2 -> u), rebuilt when the iterate pointer changes
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const double *graph_u = nullptr;
 
     // profiling events
     bool profiling = false;

@@ -15,64 +15,107 @@ namespace asdsm {
 
 // ---------------------------------------------------------------------------------------------
 // Batched FP64 GEMM on MFMA.  Block = 4 waves, block tile 32 x 32, each wave one 16 x 16 MFMA tile.
-// The A (32 x 64) and B (64 x 32) panels of each K chunk are staged in LDS with fully coalesced
-// loads (a wave reads 64 consecutive doubles along the contiguous index of the operand), so every
-// cache line is fetched once per block; MFMA operands are then read from padded, conflict-free LDS.
+// The A (32 x 128) and B (128 x 32) panels are staged in LDS with fully coalesced loads (a wave
+// reads 64 consecutive doubles along the contiguous index of the operand); with K <= 128 (every
+// mode transform up to N_f = 127) all loads of a block are in flight together before its single
+// barrier, which matters because the operands were just written by the previous kernel and come
+// from the Infinity Cache.  Blocks are numbered so that the N-tiles sharing one A panel run on the
+// same XCD (consecutive block ids go to consecutive XCDs) and reuse that XCD's L2.
 // Operand layout of v_mfma_f64_16x16x4f64 (lane l, 0..63):
 //   A: row l%16, k l/16;  B: k l/16, col l%16;  D[v]: row l/16 + 4v, col l%16.
 // ---------------------------------------------------------------------------------------------
-constexpr int GKC = 64;  // K chunk
+constexpr int GKC = 128;  // K chunk
 
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
+// Block = 8 waves: waves (wm, wn, kh) compute the 16 x 16 tile (wm, wn) over the K half kh of the
+// staged chunk with two interleaved accumulators (dependent MFMA chains of 8 instead of 32: a
+// dependent FP64 MFMA costs ~190 cycles, so chain length, not MFMA throughput, bounds these small
+// GEMMs); the two K halves are summed through LDS.  One K chunk of 128 covers N_f <= 127, so a
+// block issues all its panel loads before a single barrier.
+__global__ __launch_bounds__(512) void k_gemm_f64(GemmJob job) {
+    if (job.gate && *job.gate) return;
     __shared__ double sA[32][GKC + 1];
     __shared__ double sB[GKC][32 + 1];
-    const int box = blockIdx.z / job.nbatch;
-    const int bat = blockIdx.z % job.nbatch;
+    // block id -> (z, tile x, tile y); see launch_gemm for the layout
+    const int tx = (job.N + 31) / 32, ty = (job.M + 31) / 32;
+    const int per_z = tx * ((ty + 7) / 8) * 8;
+    const int z = blockIdx.x / per_z;
+    const int r = blockIdx.x - z * per_z;
+    const int slot = r >> 3;
+    const int bx = slot % tx;
+    const int by = (slot / tx) * 8 + (r & 7);
+    if (by >= ty) return;  // padding slot (block-uniform)
+    const int box = z / job.nbatch;
+    const int bat = z - box * job.nbatch;
     const double *__restrict__ A = job.A[box] + (long long)bat * job.sAb;
     const double *__restrict__ B = job.B[box] + (long long)bat * job.sBb;
-    const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+    const int m0 = by * 32, n0 = bx * 32;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wm = w & 1, wn = w >> 1;
-    const bool a_kfast = (job.sAk == 1);
-    const bool b_kfast = (job.sBk == 1);
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    const int wm = w & 1, wn = (w >> 1) & 1, kh = w >> 2;
+    // Panel element e = t + 512 j, j = 0..7.  Contiguous-k operands: row (t>>7) + 4j, k = t & 127;
+    // otherwise k = (t>>5) + 16j, row = t & 31.  Offsets are 32-bit and advance by a constant per j.
+    const int sAi = (int)job.sAi, sAk = (int)job.sAk, sBk = (int)job.sBk, sBn = (int)job.sBn;
+    const bool a_kfast = (sAk == 1);
+    const bool b_kfast = (sBk == 1);
+    const int ai0 = a_kfast ? (t >> 7) : (t & 31), ak0 = a_kfast ? (t & 127) : (t >> 5);
+    const int adi = a_kfast ? 4 : 0, adk = a_kfast ? 0 : 16;
+    const int bn0 = b_kfast ? (t >> 7) : (t & 31), bk0 = b_kfast ? (t & 127) : (t >> 5);
+    const int bdn = b_kfast ? 4 : 0, bdk = b_kfast ? 0 : 16;
+    const int astep = adi * sAi + adk * sAk, bstep = bdk * sBk + bdn * sBn;
+    double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < job.K; k0 += GKC) {
+        int ao = (m0 + ai0) * sAi + (k0 + ak0) * sAk;
+        int bo = (k0 + bk0) * sBk + (n0 + bn0) * sBn;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int e = t + 256 * j;  // 0 .. 2047
-            int ii, kk;
-            if (a_kfast) { ii = e >> 6; kk = e & 63; } else { kk = e >> 5; ii = e & 31; }
-            const int gi = m0 + ii, gk = k0 + kk;
-            sA[ii][kk] = (gi < job.M && gk < job.K) ? A[(long long)gi * job.sAi + (long long)gk * job.sAk] : 0.0;
-            int nn;
-            if (b_kfast) { nn = e >> 6; kk = e & 63; } else { kk = e >> 5; nn = e & 31; }
-            const int gn = n0 + nn, gk2 = k0 + kk;
-            sB[kk][nn] = (gn < job.N && gk2 < job.K) ? B[(long long)gk2 * job.sBk + (long long)gn * job.sBn] : 0.0;
+            const int ii = ai0 + adi * j, kk = ak0 + adk * j;
+            sA[ii][kk] = (m0 + ii < job.M && k0 + kk < job.K) ? A[ao] : 0.0;
+            const int nn = bn0 + bdn * j, kb = bk0 + bdk * j;
+            sB[kb][nn] = (n0 + nn < job.N && k0 + kb < job.K) ? B[bo] : 0.0;
+            ao += astep;
+            bo += bstep;
         }
         __syncthreads();
+        const int kbeg = kh * (GKC / 2);
 #pragma unroll
-        for (int kk = 0; kk < GKC; kk += 4) {
-            const double a = sA[wm * 16 + (lane & 15)][kk + (lane >> 4)];
-            const double b = sB[kk + (lane >> 4)][wn * 16 + (lane & 15)];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int kk = 0; kk < GKC / 2; kk += 8) {
+            const double a0 = sA[wm * 16 + (lane & 15)][kbeg + kk + (lane >> 4)];
+            const double b0 = sB[kbeg + kk + (lane >> 4)][wn * 16 + (lane & 15)];
+            const double a1 = sA[wm * 16 + (lane & 15)][kbeg + kk + 4 + (lane >> 4)];
+            const double b1 = sB[kbeg + kk + 4 + (lane >> 4)][wn * 16 + (lane & 15)];
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
         }
         __syncthreads();
     }
+    // sum the two K halves: waves with kh = 1 hand their partial tile over through LDS
+    double *red = &sA[0][0];  // 4 tiles x 256 values, reusing the A panel
+    const int tile = wm + 2 * wn;
+    if (kh == 1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[tile * 256 + v * 64 + lane] = acc0[v] + acc1[v];
+    }
+    __syncthreads();
+    if (kh == 1) return;
     double *__restrict__ C = job.C[box] + (long long)bat * job.sCb;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int gi = m0 + wm * 16 + (lane >> 4) + 4 * v;
         const int gn = n0 + wn * 16 + (lane & 15);
+        const double val = (acc0[v] + acc1[v]) + red[tile * 256 + v * 64 + lane];
         if (gi < job.M && gn < job.N) {
             double *c = C + (long long)gi * job.sCi + (long long)gn * job.sCn;
-            *c = job.accum ? *c + acc[v] : acc[v];
+            *c = job.accum ? *c + val : val;
         }
     }
 }
 
 void launch_gemm(const GemmJob &job, hipStream_t st) {
-    dim3 grid((job.N + 31) / 32, (job.M + 31) / 32, job.nbox * job.nbatch);
-    hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st, job);
+    // 1D grid: for each (box, batch) z, tx * ceil(ty/8) * 8 slots; slot r maps to tile
+    // x = (r/8) % tx, y = ((r/8) / tx) * 8 + r % 8 (slots with y >= ty return at once)
+    const long long tx = (job.N + 31) / 32, ty = (job.M + 31) / 32;
+    const long long per_z = tx * ((ty + 7) / 8) * 8;
+    const long long blocks = per_z * job.nbox * job.nbatch;
+    hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)blocks), dim3(512), 0, st, job);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -81,6 +124,7 @@ void launch_gemm(const GemmJob &job, hipStream_t st) {
 // ---------------------------------------------------------------------------------------------
 template <int NCR>
 __global__ __launch_bounds__(256) void k_line(LineJob job) {
+    if (job.gate && *job.gate) return;
     const int box = blockIdx.y;
     const long long m = (long long)blockIdx.x * 256 + threadIdx.x;
     if (m >= job.nmodes) return;
@@ -179,7 +223,9 @@ void launch_dense_modes(long long nmodes, int B, const double *inv, const double
 // ---------------------------------------------------------------------------------------------
 constexpr int kNormBlocks = 128;
 
-__global__ __launch_bounds__(256) void k_box_norms(BoxPtrs X, long long size, double *partials) {
+__global__ __launch_bounds__(256) void k_box_norms(BoxPtrs X, long long size, double *partials,
+                                                   const int *gate) {
+    if (gate && *gate) return;
     const int k = blockIdx.y;
     const double *__restrict__ x = X.p[k];
     double acc = 0.0;
@@ -193,7 +239,7 @@ void launch_box_norms(const Plan &p, const double *const *sol, hipStream_t st) {
     BoxPtrs bx;
     for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? const_cast<double *>(sol[1u << k]) : nullptr;
     const long long size = p.mesh[1].size;
-    hipLaunchKernelGGL(k_box_norms, dim3(kNormBlocks, p.d, 1), dim3(256), 0, st, bx, size, p.ws.partials);
+    hipLaunchKernelGGL(k_box_norms, dim3(kNormBlocks, p.d, 1), dim3(256), 0, st, bx, size, p.ws.partials, p.gate);
     launch_finalize(p, kNormBlocks, kFinBoxNorms, p.d, st);
 }
 
@@ -201,6 +247,7 @@ void launch_box_norms(const Plan &p, const double *const *sol, hipStream_t st) {
 // Mesh residual out = f - A_S x (zero Dirichlet data) in the canonical layout of M_S.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_box_residual(Geo g, BoxResJob job) {
+    if (job.gate && *job.gate) return;
     const int box = blockIdx.y;
     const MeshDesc &m = job.m[box];
     const double *__restrict__ f = job.f[box];

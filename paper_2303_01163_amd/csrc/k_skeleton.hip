@@ -24,7 +24,9 @@ struct SkelArgs {
     const double *Sp;               // N_f x N_c spline matrix
     const double *scal;             // normalisation factors (error phase)
     int mode;                       // 0 initial guess, 1 error phase
-    int perm[kMaxD];
+    const int *perm_table;          // error phase: permutation of step it at perm_table[kMaxD*it]
+    const IterState *state;
+    const int *gate;
 };
 
 __device__ __forceinline__ double crosspoint_value(const SkelArgs &a, const Geo &g, const int *i,
@@ -41,8 +43,9 @@ __device__ __forceinline__ double crosspoint_value(const SkelArgs &a, const Geo 
         sum -= a.res[S][canon_offset(a.mesh[S], i, g.n)];
         return sum / (double)(cnt - 1);
     }
+    const int *perm = a.perm_table + kMaxD * a.state->it;
     for (int q = 0; q < g.d; ++q) {
-        const int j = a.perm[q];
+        const int j = perm[q];
         if ((S >> j) & 1u) {
             const unsigned mj = 1u << j;
             return a.scal[kScalInvNorm + j] * a.res[mj][canon_offset(a.mesh[mj], i, g.n)];
@@ -72,6 +75,7 @@ __device__ __forceinline__ void fine_axes_of(int k, int d, int &a, int &b) {
 // d = 2: lines[k][ck*Nc + ca].
 // d = 3: part A [ck][ca][ib] (Nc*Nc*Nf), part B [ck][ia][cb] (Nc*Nf*Nc), then part R (filled later).
 __global__ __launch_bounds__(256) void k_crosspoints(Geo g, SkelArgs a) {
+    if (a.gate && *a.gate) return;
     const int k = blockIdx.y;
     const int d = g.d, Nf = g.Nf, Nc = g.Nc, n = g.n;
     int fa, fb;
@@ -112,6 +116,7 @@ __global__ __launch_bounds__(256) void k_crosspoints(Geo g, SkelArgs a) {
 // d = 3 only: R[ck][ca][ib] = A[ck][ca][ib] - sum_cb Sp[ib][cb] A[ck][ca][C[cb]], so that the Boolean
 // sum P_a delta + P_b delta - P_a P_b delta = P_a R + P_b delta costs O(N_c) per point.
 __global__ __launch_bounds__(256) void k_lines_residual(Geo g, SkelArgs a) {
+    if (a.gate && *a.gate) return;
     const int k = blockIdx.y;
     const int Nf = g.Nf, Nc = g.Nc, n = g.n;
     const long long nA = (long long)Nc * Nc * Nf;
@@ -131,6 +136,7 @@ __global__ __launch_bounds__(256) void k_lines_residual(Geo g, SkelArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
+    if (a.gate && *a.gate) return;
     const int k = blockIdx.y;
     const int d = g.d, Nf = g.Nf, Nc = g.Nc, n = g.n;
     int fa, fb;
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
     }
 }
 
-static SkelArgs skel_args(const Plan &p, int mode, const int *perm, const double *const *res) {
+static SkelArgs skel_args(const Plan &p, int mode, const double *const *res) {
     SkelArgs a;
     for (unsigned s = 0; s < kMaxMeshes; ++s) {
         a.res[s] = (s < (1u << p.d)) ? res[s] : nullptr;
@@ -187,17 +193,18 @@ static SkelArgs skel_args(const Plan &p, int mode, const int *perm, const double
     for (int k = 0; k < kMaxD; ++k) {
         a.lines[k] = (k < p.d) ? p.ws.lines[k] : nullptr;
         a.skel[k] = (k < p.d) ? p.ws.Y[1u << k] : nullptr;
-        a.perm[k] = (perm && k < p.d) ? perm[k] : k;
     }
+    a.perm_table = p.ws.perm_table;
+    a.state = p.ws.state;
+    a.gate = p.gate;
     a.Sp = p.dSp;
     a.scal = p.ws.scal;
     a.mode = mode;
     return a;
 }
 
-void launch_crosspoints(const Plan &p, int mode, const int *perm, const double *const *res,
-                        hipStream_t st) {
-    SkelArgs a = skel_args(p, mode, perm, res);
+void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipStream_t st) {
+    SkelArgs a = skel_args(p, mode, res);
     const long long nA = (p.d == 2) ? (long long)p.Nc * p.Nc : (long long)p.Nc * p.Nc * p.Nf;
     const long long total = (p.d == 2) ? nA : 2 * nA;
     long long blocks = (total + 255) / 256;
@@ -210,9 +217,8 @@ void launch_crosspoints(const Plan &p, int mode, const int *perm, const double *
     }
 }
 
-void launch_merge(const Plan &p, int mode, const int *perm, const double *const *res,
-                  hipStream_t st) {
-    SkelArgs a = skel_args(p, mode, perm, res);
+void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t st) {
+    SkelArgs a = skel_args(p, mode, res);
     long long blocks = (p.mesh[1].size + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_merge, dim3((unsigned)blocks, p.d, 1), dim3(256), 0, st, p.geo, a);
@@ -237,10 +243,12 @@ struct FillArgs {
     int tr[kMaxD];
     const double *bff;
     double *out;
+    const int *gate;
 };
 
 template <int D, int NH>
 __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
+    if (a.gate && *a.gate) return;
     extern __shared__ double lds[];
     // NH > 0: hole edge length known at compile time (constant-divisor index arithmetic)
     const int nh = (NH > 0) ? NH : g.n - 1;
@@ -399,6 +407,155 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Filler for d = 3 with 15^3 holes (n = 16) on MFMA.  The hole is padded to 16^3 in one LDS buffer
+// with strides (1, 17, 289): for every axis the 16 rows of an MFMA operand fragment and the 16
+// columns of a result fragment fall in distinct banks.  A transform along axis j is an in-place GEMM
+// of the 256 lines (the other two coordinates) by the 16 x 16 matrix W_j^T (pad row/column zero),
+// 64 v_mfma_f64_16x16x4f64 per transform, 16 per wave; the W_j fragments live in registers.
+// ---------------------------------------------------------------------------------------------
+constexpr int kFS1 = 17, kFS2 = 289, kFBuf = 16 * kFS2;
+
+__device__ __forceinline__ int fstride(int j) { return j == 0 ? 1 : (j == 1 ? kFS1 : kFS2); }
+
+// one transform of the padded hole along axis j with the 16 x 16 matrix held as B fragments
+__device__ __forceinline__ void hole_transform_mfma(double *buf, int j, const double (&bfrag)[4],
+                                                    int lane, int wave) {
+    // the other two axes, increasing: row r = lp + 16 * lq
+    const int p = (j == 0) ? 1 : 0;
+    const int q = (j == 2) ? 1 : 2;
+    const int Sp = fstride(p), Sq = fstride(q), Sj = fstride(j);
+    double4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int rt = wave + 4 * t;
+        acc[t] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const double a = buf[(lane & 15) * Sp + rt * Sq + (4 * ks + (lane >> 4)) * Sj];
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bfrag[ks], acc[t], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int rt = wave + 4 * t;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) buf[((lane >> 4) + 4 * v) * Sp + rt * Sq + (lane & 15) * Sj] = acc[t][v];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_filler_mfma3(Geo g, FillArgs a) {
+    if (a.gate && *a.gate) return;
+    __shared__ double buf[kFBuf];
+    constexpr int nh = 15, n = 16;
+    const int Nf = g.Nf, Nc = g.Nc;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int L = a.line_axis, j0 = a.tr[0], j1 = a.tr[1];
+    // B fragments: B[k][m] = W[m][k] (forward) and V[m][k] (backward); zero beyond 15
+    double bw0[4], bw1[4], bv0[4], bv1[4];
+    {
+        const int m = lane & 15;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + (lane >> 4);
+            const bool ok = (m < nh) && (k < nh);
+            bw0[ks] = ok ? a.W[j0][m * nh + k] : 0.0;
+            bw1[ks] = ok ? a.W[j1][m * nh + k] : 0.0;
+            bv0[ks] = ok ? a.V[j0][m * nh + k] : 0.0;
+            bv1[ks] = ok ? a.V[j1][m * nh + k] : 0.0;
+        }
+    }
+    int tt[3];
+    {
+        int rem = blockIdx.x;
+        for (int j = 0; j < 3; ++j) {
+            tt[j] = rem % (Nc + 1);
+            rem /= (Nc + 1);
+        }
+    }
+    // Face bases: the merged skeleton values next to the hole lie on coarse planes of the anisotropic
+    // meshes; in M_j's canonical layout (fine axes a < b, coarse axis j) the point with hole-local
+    // coordinates (l_a, l_b) on plane c is at 16 t_a + l_a + Nf (16 t_b + l_b) + Nf^2 c.
+    int lo_base[3], hi_base[3];
+    const int Nf2 = Nf * Nf;
+    for (int j = 0; j < 3; ++j) {
+        const int fa = (j == 0) ? 1 : 0, fb = (j == 2) ? 1 : 2;
+        const int base = n * tt[fa] + Nf * (n * tt[fb]);
+        lo_base[j] = (tt[j] > 0) ? base + Nf2 * (tt[j] - 1) : -1;
+        hi_base[j] = (tt[j] < Nc) ? base + Nf2 * tt[j] : -1;
+    }
+    const int f0 = n * tt[0] + Nf * (n * tt[1]) + Nf2 * (n * tt[2]);  // fine index of the tile origin
+    // 1) hole right-hand side, zero in the padding
+#pragma unroll 4
+    for (int o = tid; o < 4096; o += 256) {
+        const int l0 = o & 15, l1 = (o >> 4) & 15, l2 = o >> 8;
+        double v = 0.0;
+        if (l0 < nh && l1 < nh && l2 < nh) {
+            v = a.bff ? a.bff[f0 + l0 + Nf * l1 + Nf2 * l2] : 0.0;
+            const int la[3] = {l1, l0, l0}, lb[3] = {l2, l2, l1}, lj[3] = {l0, l1, l2};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int off = la[j] + Nf * lb[j];
+                if (lj[j] == 0 && lo_base[j] >= 0) v -= g.fine[j].a * a.skel[j][lo_base[j] + off];
+                if (lj[j] == nh - 1 && hi_base[j] >= 0) v -= g.fine[j].c * a.skel[j][hi_base[j] + off];
+            }
+        }
+        buf[l0 + kFS1 * l1 + kFS2 * l2] = v;
+    }
+    __syncthreads();
+    // 2) forward transforms
+    hole_transform_mfma(buf, j0, bw0, lane, wave);
+    hole_transform_mfma(buf, j1, bw1, lane, wave);
+    // 3) Thomas along the line axis for the 225 lines of modes (m_j0, m_j1)
+    if (tid < nh * nh) {
+        const int m0 = tid % nh, m1 = tid / nh;
+        const double sigma = a.mu[j0][m0] + a.mu[j1][m1];
+        const int base = m0 * fstride(j0) + m1 * fstride(j1);
+        const int sL = fstride(L);
+        const Tri t = g.fine[L];
+        const double diag = t.b + sigma;
+        double cp[nh], f[nh];
+#pragma unroll
+        for (int c = 0; c < nh; ++c) f[c] = buf[base + c * sL];
+        double den = diag;
+        cp[0] = t.c / den;
+        f[0] = f[0] / den;
+#pragma unroll
+        for (int c = 1; c < nh; ++c) {
+            den = diag - t.a * cp[c - 1];
+            f[c] = (f[c] - t.a * f[c - 1]) / den;
+            cp[c] = t.c / den;
+        }
+#pragma unroll
+        for (int c = nh - 2; c >= 0; --c) f[c] -= cp[c] * f[c + 1];
+#pragma unroll
+        for (int c = 0; c < nh; ++c) buf[base + c * sL] = f[c];
+    }
+    __syncthreads();
+    // 4) backward transforms
+    hole_transform_mfma(buf, j1, bv1, lane, wave);
+    hole_transform_mfma(buf, j0, bv0, lane, wave);
+    // 5) write the whole tile (hole values and the skeleton planes above it), x_1 fastest
+#pragma unroll 4
+    for (int o = tid; o < 4096; o += 256) {
+        const int l0 = o & 15, l1 = (o >> 4) & 15, l2 = o >> 8;
+        if (n * tt[0] + l0 >= Nf || n * tt[1] + l1 >= Nf || n * tt[2] + l2 >= Nf) continue;
+        double v;
+        if (l0 < nh && l1 < nh && l2 < nh) {
+            v = buf[l0 + kFS1 * l1 + kFS2 * l2];
+        } else if (l0 == nh) {
+            v = a.skel[0][hi_base[0] + l1 + Nf * l2];
+        } else if (l1 == nh) {
+            v = a.skel[1][hi_base[1] + l0 + Nf * l2];
+        } else {
+            v = a.skel[2][hi_base[2] + l0 + Nf * l1];
+        }
+        a.out[f0 + l0 + Nf * l1 + Nf2 * l2] = v;
+    }
+}
+
 void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st) {
     FillArgs a;
     const int d = p.d, nh = p.n - 1;
@@ -416,12 +573,17 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
         if (j != p.hole_line_axis) a.tr[a.ntr++] = j;
     a.bff = bff;
     a.out = out;
+    a.gate = p.gate;
     int npts = 1;
     for (int j = 0; j < d; ++j) npts *= nh;
     const size_t lds = (size_t)(2 * npts + a.ntr * (2 * nh * nh + nh)) * sizeof(double);
     int tiles = 1;
     for (int j = 0; j < d; ++j) tiles *= (p.Nc + 1);
     const dim3 grid(tiles), blk(256);
+    if (d == 3 && nh == 15) {
+        hipLaunchKernelGGL(k_filler_mfma3, grid, blk, 0, st, p.geo, a);
+        return;
+    }
 #define ASDSM_FILL(DD, NHV) hipLaunchKernelGGL((k_filler<DD, NHV>), grid, blk, lds, st, p.geo, a)
     if (d == 2) {
         switch (nh) {

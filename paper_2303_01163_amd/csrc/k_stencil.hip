@@ -74,43 +74,50 @@ template <int D>
 __global__ __launch_bounds__(256) void k_update_residual(
     Geo g, const double *__restrict__ uin, const double *__restrict__ e,
     const double *__restrict__ scal, const double *__restrict__ b, double *__restrict__ uout,
-    double *__restrict__ r, BoxPtrs boxes, double *partials) {
+    double *__restrict__ r, BoxPtrs boxes, double *partials, const int *gate) {
+    if (gate && *gate) return;
     const int Nf = g.Nf, n = g.n;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int i0 = blockIdx.y * 64 + tx;
-    const long long nrows = g.NF / Nf;
+    const int nrows = (int)(g.NF / Nf);
     const double s = e ? scal[kScalStep] : 0.0;
-    const long long sy = Nf, sz = (long long)Nf * Nf;
+    const int sy = Nf, sz = Nf * Nf;
+    const double bsum = g.fine[0].b + g.fine[1].b + (D == 3 ? g.fine[2].b : 0.0);
     double acc = 0.0;
-    for (long long rg = blockIdx.x; rg * 4 < nrows; rg += gridDim.x) {
-        const long long row = rg * 4 + ty;
-        if (i0 >= Nf || row >= nrows) continue;
-        const int i1 = (int)(row % Nf);
-        const int i2 = (D == 3) ? (int)(row / Nf) : 0;
-        const long long p = i0 + (long long)Nf * row;
-        auto val = [&](long long q) -> double { return e ? uin[q] + s * e[q] : uin[q]; };
-        const double uc = val(p);
-        double au = (g.fine[0].b + g.fine[1].b + (D == 3 ? g.fine[2].b : 0.0)) * uc;
-        if (i0 > 0) au += g.fine[0].a * val(p - 1);
-        if (i0 < Nf - 1) au += g.fine[0].c * val(p + 1);
-        if (i1 > 0) au += g.fine[1].a * val(p - sy);
-        if (i1 < Nf - 1) au += g.fine[1].c * val(p + sy);
-        if (D == 3) {
-            if (i2 > 0) au += g.fine[2].a * val(p - sz);
-            if (i2 < Nf - 1) au += g.fine[2].c * val(p + sz);
-        }
-        const double rr = b[p] - au;
-        r[p] = rr;
-        if (e) uout[p] = uc;
-        acc += rr * rr;
-        // gather onto the anisotropic submeshes (canonical layouts)
-        if (D == 2) {
-            if (on_coarse(i0, n)) boxes.p[0][i1 + (long long)Nf * coarse_of(i0, n)] = rr;
-            if (on_coarse(i1, n)) boxes.p[1][i0 + (long long)Nf * coarse_of(i1, n)] = rr;
-        } else {
-            if (on_coarse(i0, n)) boxes.p[0][i1 + sy * i2 + sz * coarse_of(i0, n)] = rr;
-            if (on_coarse(i1, n)) boxes.p[1][i0 + sy * i2 + sz * coarse_of(i1, n)] = rr;
-            if (on_coarse(i2, n)) boxes.p[2][i0 + sy * i1 + sz * coarse_of(i2, n)] = rr;
+    const int stride = gridDim.x * 4;
+    // two rows per thread per pass, so the loads of both are in flight together
+    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += 2 * stride) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int row = row0 + q * stride;
+            if (i0 >= Nf || row >= nrows) continue;
+            const int i1 = row % Nf;
+            const int i2 = (D == 3) ? row / Nf : 0;
+            const int p = i0 + Nf * row;
+            auto val = [&](int qq) -> double { return e ? uin[qq] + s * e[qq] : uin[qq]; };
+            const double uc = val(p);
+            double au = bsum * uc;
+            if (i0 > 0) au += g.fine[0].a * val(p - 1);
+            if (i0 < Nf - 1) au += g.fine[0].c * val(p + 1);
+            if (i1 > 0) au += g.fine[1].a * val(p - sy);
+            if (i1 < Nf - 1) au += g.fine[1].c * val(p + sy);
+            if (D == 3) {
+                if (i2 > 0) au += g.fine[2].a * val(p - sz);
+                if (i2 < Nf - 1) au += g.fine[2].c * val(p + sz);
+            }
+            const double rr = b[p] - au;
+            r[p] = rr;
+            if (e) uout[p] = uc;
+            acc += rr * rr;
+            // gather onto the anisotropic submeshes (canonical layouts)
+            if (D == 2) {
+                if (on_coarse(i0, n)) boxes.p[0][i1 + Nf * coarse_of(i0, n)] = rr;
+                if (on_coarse(i1, n)) boxes.p[1][i0 + Nf * coarse_of(i1, n)] = rr;
+            } else {
+                if (on_coarse(i0, n)) boxes.p[0][i1 + sy * i2 + sz * coarse_of(i0, n)] = rr;
+                if (on_coarse(i1, n)) boxes.p[1][i0 + sy * i2 + sz * coarse_of(i1, n)] = rr;
+                if (on_coarse(i2, n)) boxes.p[2][i0 + sy * i1 + sz * coarse_of(i2, n)] = rr;
+            }
         }
     }
     double vals[1] = {acc};
@@ -122,30 +129,37 @@ __global__ __launch_bounds__(256) void k_update_residual(
 // ---------------------------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(256) void k_dots(Geo g, const double *__restrict__ e,
-                                              const double *__restrict__ r, double *partials) {
+                                              const double *__restrict__ r, double *partials,
+                                              const int *gate) {
+    if (gate && *gate) return;
     const int Nf = g.Nf;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int i0 = blockIdx.y * 64 + tx;
-    const long long nrows = g.NF / Nf;
-    const long long sy = Nf, sz = (long long)Nf * Nf;
+    const int nrows = (int)(g.NF / Nf);
+    const int sy = Nf, sz = Nf * Nf;
+    const double bsum = g.fine[0].b + g.fine[1].b + (D == 3 ? g.fine[2].b : 0.0);
     double rq = 0.0, qq = 0.0;
-    for (long long rg = blockIdx.x; rg * 4 < nrows; rg += gridDim.x) {
-        const long long row = rg * 4 + ty;
-        if (i0 >= Nf || row >= nrows) continue;
-        const int i1 = (int)(row % Nf);
-        const int i2 = (D == 3) ? (int)(row / Nf) : 0;
-        const long long p = i0 + (long long)Nf * row;
-        double q = (g.fine[0].b + g.fine[1].b + (D == 3 ? g.fine[2].b : 0.0)) * e[p];
-        if (i0 > 0) q += g.fine[0].a * e[p - 1];
-        if (i0 < Nf - 1) q += g.fine[0].c * e[p + 1];
-        if (i1 > 0) q += g.fine[1].a * e[p - sy];
-        if (i1 < Nf - 1) q += g.fine[1].c * e[p + sy];
-        if (D == 3) {
-            if (i2 > 0) q += g.fine[2].a * e[p - sz];
-            if (i2 < Nf - 1) q += g.fine[2].c * e[p + sz];
+    const int stride = gridDim.x * 4;
+    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += 2 * stride) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = row0 + h * stride;
+            if (i0 >= Nf || row >= nrows) continue;
+            const int i1 = row % Nf;
+            const int i2 = (D == 3) ? row / Nf : 0;
+            const int p = i0 + Nf * row;
+            double q = bsum * e[p];
+            if (i0 > 0) q += g.fine[0].a * e[p - 1];
+            if (i0 < Nf - 1) q += g.fine[0].c * e[p + 1];
+            if (i1 > 0) q += g.fine[1].a * e[p - sy];
+            if (i1 < Nf - 1) q += g.fine[1].c * e[p + sy];
+            if (D == 3) {
+                if (i2 > 0) q += g.fine[2].a * e[p - sz];
+                if (i2 < Nf - 1) q += g.fine[2].c * e[p + sz];
+            }
+            rq += r[p] * q;
+            qq += q * q;
         }
-        rq += r[p] * q;
-        qq += q * q;
     }
     double vals[2] = {rq, qq};
     block_partials<256, 2>(vals, partials, blockIdx.x + (size_t)gridDim.x * blockIdx.y);
@@ -155,7 +169,9 @@ __global__ __launch_bounds__(256) void k_dots(Geo g, const double *__restrict__ 
 // Totals of the per-block partial sums, in block order (deterministic), and what derives from them.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblk,
-                                                  int mode, int nbox, double *scal) {
+                                                  int mode, int nbox, double *scal, IterState *stt,
+                                                  double *hist, double *step_hist, const int *gate) {
+    if (gate && *gate) return;
     __shared__ double sh[4];
     const int tid = threadIdx.x;
     if (mode == kFinDots) {
@@ -186,12 +202,62 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
         double a = 0.0;
         for (int b = tid; b < nblk; b += 256) a += partials[b];
         const double t = block_sum<256>(a, sh);
-        if (tid == 0) scal[mode == kFinBnorm ? kScalBnorm2 : kScalRnorm2] = t;
+        if (tid != 0) return;
+        if (mode == kFinBnorm) {
+            scal[kScalBnorm2] = t;
+            return;
+        }
+        scal[kScalRnorm2] = t;
+        if (mode == kFinRnorm) return;
+        // stopping rule of the refinement loop
+        const double rn = sqrt(t);
+        const double bn = sqrt(scal[kScalBnorm2]);
+        if (mode == kFinInit) {
+            stt->it = 0;
+            stt->stag = 0;
+            stt->rn_prev = rn;
+            hist[0] = rn;
+            if (!isfinite(rn) || !isfinite(bn)) {
+                stt->done = 1;
+                stt->status = ASDSM_E_NUMERIC;
+            } else if ((bn > 0.0 && rn <= stt->rtol * bn) || (bn == 0.0 && rn == 0.0)) {
+                stt->done = 1;
+                stt->status = ASDSM_OK;
+            } else if (stt->max_iter <= 0) {
+                stt->done = 1;
+                stt->status = ASDSM_MAXITER;
+            }
+            return;
+        }
+        // kFinIter: one refinement step has just produced u_{k+1} and r_{k+1}
+        const double shat = scal[kScalStep];
+        const int it = stt->it + 1;
+        stt->it = it;
+        if (it < kHistCap) hist[it] = rn;
+        if (it - 1 < kHistCap) step_hist[it - 1] = shat;
+        if (!isfinite(rn) || !isfinite(shat)) {
+            stt->done = 1;
+            stt->status = ASDSM_E_NUMERIC;
+            return;
+        }
+        stt->stag = (rn > (1.0 - stt->stag_eta) * stt->rn_prev) ? stt->stag + 1 : 0;
+        stt->rn_prev = rn;
+        if (shat == 0.0 || (stt->stag_window > 0 && stt->stag >= stt->stag_window)) {
+            stt->done = 1;
+            stt->status = ASDSM_STAGNATED;
+        } else if ((bn > 0.0 && rn <= stt->rtol * bn) || (bn == 0.0 && rn == 0.0)) {
+            stt->done = 1;
+            stt->status = ASDSM_OK;
+        } else if (it >= stt->max_iter) {
+            stt->done = 1;
+            stt->status = ASDSM_MAXITER;
+        }
     }
 }
 
 void launch_finalize(const Plan &p, int nblk, int mode, int nbox, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, p.ws.partials, nblk, mode, nbox, p.ws.scal);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, p.ws.partials, nblk, mode, nbox, p.ws.scal,
+                       p.ws.state, p.ws.hist, p.ws.step_hist, p.gate);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -223,27 +289,27 @@ void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf,
 }
 
 void launch_update_residual(const Plan &p, const double *uin, const double *e, double *uout,
-                            double *const *gather, hipStream_t st) {
+                            double *const *gather, int fin_mode, hipStream_t st) {
     dim3 grid;
     stencil_grid(p.geo, grid);
     BoxPtrs bx;
     for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? gather[1u << k] : nullptr;
     if (p.d == 2)
         hipLaunchKernelGGL(k_update_residual<2>, grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
-                           p.ws.b, uout, p.ws.r, bx, p.ws.partials);
+                           p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
     else
         hipLaunchKernelGGL(k_update_residual<3>, grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
-                           p.ws.b, uout, p.ws.r, bx, p.ws.partials);
-    launch_finalize(p, (int)(grid.x * grid.y), kFinRnorm, 1, st);
+                           p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
+    launch_finalize(p, (int)(grid.x * grid.y), fin_mode, 1, st);
 }
 
 void launch_dots(const Plan &p, hipStream_t st) {
     dim3 grid;
     stencil_grid(p.geo, grid);
     if (p.d == 2)
-        hipLaunchKernelGGL(k_dots<2>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials);
+        hipLaunchKernelGGL(k_dots<2>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
     else
-        hipLaunchKernelGGL(k_dots<3>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials);
+        hipLaunchKernelGGL(k_dots<3>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
     launch_finalize(p, (int)(grid.x * grid.y), kFinDots, 1, st);
 }
 

@@ -18,6 +18,7 @@ struct GemmJob {
     int nbox;
     int M, N, K, nbatch;
     int accum;                 // 1: C += A B, 0: C = A B
+    const int *gate;           // return at once when *gate != 0 (may be nullptr)
     long long sAb, sAi, sAk, sBb, sBk, sBn, sCb, sCi, sCn;
 };
 
@@ -33,14 +34,16 @@ struct LineJob {
     long long nmodes;          // product of the fine extents
     int ext_a;                 // extent of the first fine axis
     int ncoarse;               // points along the coarse axis
+    const int *gate;
 };
 
-enum FinMode { kFinRnorm = 0, kFinBnorm = 1, kFinDots = 2, kFinBoxNorms = 3 };
+enum FinMode { kFinRnorm = 0, kFinBnorm = 1, kFinDots = 2, kFinBoxNorms = 3, kFinInit = 4, kFinIter = 5 };
 void launch_finalize(const Plan &p, int nblk, int mode, int nbox, hipStream_t st);
 void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf, double *out,
                 bool with_norm, hipStream_t st);
+// fin_mode: kFinRnorm (plain), kFinInit (start of the loop), kFinIter (after a refinement step)
 void launch_update_residual(const Plan &p, const double *uin, const double *e, double *uout,
-                            double *const *gather, hipStream_t st);
+                            double *const *gather, int fin_mode, hipStream_t st);
 void launch_dots(const Plan &p, hipStream_t st);
 int stencil_blocks(const Geo &g);
 
@@ -58,6 +61,7 @@ struct BoxResJob {
     double *out[kMaxD];
     MeshDesc m[kMaxD];
     int nbox;
+    const int *gate;
 };
 void launch_box_residual(const Plan &p, const BoxResJob &job, hipStream_t st);
 // y_i += x_i for up to 3 arrays of n doubles
@@ -69,10 +73,10 @@ void launch_fill_random(double *x, long long n, uint64_t seed, hipStream_t st);
 void launch_sumsq(const Plan &p, const double *const *x, const long long *n, int nbox, hipStream_t st);
 
 // skeleton: mode 0 = initial guess (extrapolated cross points), 1 = error phase (random choice)
-void launch_crosspoints(const Plan &p, int mode, const int *perm, const double *const *res,
-                        hipStream_t st);
-void launch_merge(const Plan &p, int mode, const int *perm, const double *const *res,
-                  hipStream_t st);
+// In the error phase the permutation of the current step is read on the device from
+// p.ws.perm_table[p.ws.state->it].
+void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipStream_t st);
+void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t st);
 void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st);
 
 }  // namespace asdsm

@@ -260,6 +260,10 @@ void layout_workspace(Plan &p, char *base, bool assign) {
     // Nc*Nc*Nf values each
     const size_t nl = (p.d == 2) ? (size_t)p.Nc * p.Nc : (size_t)3 * p.Nc * p.Nc * p.Nf;
     for (int k = 0; k < p.d; ++k) w.lines[k] = (double *)take(nl * 8);
+    w.state = (IterState *)take(sizeof(IterState));
+    w.hist = (double *)take((size_t)kHistCap * 8);
+    w.step_hist = (double *)take((size_t)kHistCap * 8);
+    w.perm_table = (int *)take((size_t)kHistCap * kMaxD * sizeof(int));
     w.partials = (double *)take((size_t)p.max_blocks * 4 * 8);
     w.scal = (double *)take(kScalCount * 8);
     p.ws_need = off;
@@ -434,6 +438,9 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     for (unsigned s = 1; s < (1u << d); ++s)
         if (__builtin_popcount(s) >= 2) p.ddense[s] = (double *)(base + oD[s]);
     err = hipHostMalloc((void **)&p.hscal, kScalCount * sizeof(double), hipHostMallocDefault);
+    if (err == hipSuccess) err = hipHostMalloc((void **)&p.hstate, sizeof(IterState), hipHostMallocDefault);
+    if (err == hipSuccess)
+        err = hipHostMalloc((void **)&p.hperm, (size_t)kHistCap * kMaxD * sizeof(int), hipHostMallocDefault);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(err));
     err = hipEventCreate(&p.ev_begin);
     if (err == hipSuccess) err = hipEventCreate(&p.ev_end);
@@ -442,8 +449,18 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
 }
 
 void release_plan(Plan &p) {
+    if (p.graph_exec) (void)hipGraphExecDestroy(p.graph_exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    if (p.capture_stream) (void)hipStreamDestroy(p.capture_stream);
+    p.graph_exec = nullptr;
+    p.graph = nullptr;
+    p.capture_stream = nullptr;
     if (p.dtab) (void)hipFree(p.dtab);
     if (p.hscal) (void)hipHostFree(p.hscal);
+    if (p.hstate) (void)hipHostFree(p.hstate);
+    if (p.hperm) (void)hipHostFree(p.hperm);
+    p.hstate = nullptr;
+    p.hperm = nullptr;
     if (p.ev_begin) (void)hipEventDestroy(p.ev_begin);
     if (p.ev_end) (void)hipEventDestroy(p.ev_end);
     p.dtab = nullptr;
