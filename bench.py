@@ -25,6 +25,61 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
+PHASE_KERNEL = {"transform": "k_gemm_f64", "update": "k_update_residual", "dots": "k_dots",
+                "filler": "k_filler_mfma3", "skeleton": "k_merge", "line": "k_line", "rhs": "k_rhs"}
+KERNEL_SOURCE = {"k_gemm_f64": "k_boxsolve.hip", "k_update_residual": "k_stencil.hip",
+                 "k_dots": "k_stencil.hip", "k_filler_mfma3": "k_skeleton.hip"}
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_asdsm3d_127.txt")
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, or None when there is none or the kernel's source changed since it was taken."""
+    import hashlib
+    src = KERNEL_SOURCE.get(kernel)
+    if src is None or not os.path.exists(PMC_SUMMARY):
+        return None
+    path = os.path.join(ROOT, "paper_2303_01163_amd", "csrc", src)
+    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    for line in open(PMC_SUMMARY):
+        f = line.split()
+        if not f or f[0] != kernel:
+            continue
+        kv = dict(x.split("=", 1) for x in f[1:] if "=" in x)
+        if kv.get("source_sha256") == digest:
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def phase_rate(phase, ph_ms, ph_n, ph_by):
+    ms, n = ph_ms[phase], max(ph_n[phase], 1)
+    return {"kernel": PHASE_KERNEL.get(phase, phase), "launches": ph_n[phase],
+            "avg_launch_ms": ms / n, "bytes_per_launch": ph_by[phase] / n,
+            "GB/s": ph_by[phase] / (ms * 1e-3) / 1e9 if ms > 0 else None}
+
+
+def roofline(phase, ph_ms, ph_n, ph_fl, ph_by):
+    """Roofline position of the phase with the largest device time: algorithmic work per launch /
+    average launch duration, against the MI355X peak of its bound (FP64 MFMA for the mode
+    transforms, HBM for the rest)."""
+    ms, n = ph_ms[phase], max(ph_n[phase], 1)
+    kernel = PHASE_KERNEL.get(phase, phase)
+    avg_ms = ms / n
+    if phase == "transform":
+        per_launch = ph_fl[phase] / n
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        bound, peak, unit = "mfma", FP64_PEAK_TFLOPS, "TFLOP/s"
+    else:
+        per_launch = ph_by[phase] / n
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": pmc_traffic(kernel), "kernel": kernel,
+            "phase": phase, "launches": ph_n[phase], "avg_launch_ms": avg_ms,
+            "algorithmic_per_launch": per_launch,
+            "algorithmic_bytes_per_launch": ph_by[phase] / n}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -36,7 +91,7 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=50)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=1, help="oracle refinement steps in the sample")
+    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle refinement steps in the sample")
     return ap.parse_args()
 
 
@@ -78,47 +133,15 @@ def main():
     n_fine = plan.n_fine
     value = n_fine / (ms_per_step * 1e-3)
 
-    # per-kernel device times: one more identical solve with HIP events around every phase
+    # per-phase device times: one more identical solve, eager, with HIP events on the library's
+    # stream around every launch group, and the algorithmic flops / bytes of those launches
     _, prof = plan.solve(s, g, u=u, profile=True, **kw)
     ph_ms, ph_n = prof["phase_ms"], prof["phase_launches"]
-    Nf, Nc = plan.n_f, plan.n_c
-    rows = Nf * Nc  # box size / Nf for d = 3
-    per_launch_flops = 2.0 * rows * Nf * Nf * 3
-    per_launch_bytes = 8.0 * (rows * Nf + Nf * Nf + rows * Nf) * 3
-    # the transform phase also holds the edge-mesh transforms of the initial guess (smaller);
-    # count them by their own launch number and size
-    tr_ms = ph_ms["transform"]
-    tr_n = ph_n["transform"]
-    upd_ms, upd_n = ph_ms["update"], ph_n["update"]
-    upd_bytes = 8.0 * n_fine * 5  # read u, e, b; write u, r (algorithmic, per launch)
-    candidates = {
-        "transform": (tr_ms, tr_n),
-        "update": (upd_ms, upd_n),
-        "filler": (ph_ms["filler"], ph_n["filler"]),
-        "line": (ph_ms["line"], ph_n["line"]),
-        "dots": (ph_ms["dots"], ph_n["dots"]),
-        "skeleton": (ph_ms["skeleton"], ph_n["skeleton"]),
-    }
-    dominant = max(candidates, key=lambda k: candidates[k][0])
-    if dominant == "transform":
-        avg_ms = tr_ms / max(tr_n, 1)
-        achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "k_gemm_f64 (mode transforms, 3 boxes per launch)",
-                "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "avg_launch_ms": avg_ms,
-                "launches": tr_n}
-    else:
-        ms, n = candidates[dominant]
-        avg_ms = ms / max(n, 1)
-        byts = {"update": upd_bytes, "dots": 8.0 * n_fine * 2, "filler": 8.0 * n_fine * 2}.get(dominant, 8.0 * n_fine)
-        achieved = byts / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "avg_launch_ms": avg_ms, "launches": n}
-    # secondary: the HBM-bound fused update/residual kernel
-    upd_avg = upd_ms / max(upd_n, 1)
-    stencil = {"kernel": "k_update_residual", "avg_launch_ms": upd_avg,
-               "achieved_GBs": upd_bytes / (upd_avg * 1e-3) / 1e9, "bytes_per_launch": upd_bytes}
+    ph_fl, ph_by = prof["phase_flops"], prof["phase_bytes"]
+    Nf = plan.n_f
+    dominant = max(ph_ms, key=lambda k: ph_ms[k])
+    roof = roofline(dominant, ph_ms, ph_n, ph_fl, ph_by)
+    stencil = {q: phase_rate(q, ph_ms, ph_n, ph_by) for q in ("update", "dots")}
 
     out = {
         "metric": METRIC,
@@ -144,9 +167,11 @@ def main():
         "unknown_iterations_per_s": n_fine * iters / (ms_per_step * 1e-3),
         "phase_ms": ph_ms,
         "phase_launches": ph_n,
+        "phase_gflop": {k: v / 1e9 for k, v in ph_fl.items()},
+        "phase_mb": {k: v / 1e6 for k, v in ph_by.items()},
         "profiled_total_ms": prof["total_ms"],
         "roofline": roof,
-        "stencil": stencil,
+        "stencil_effective": stencil,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, L, args, iters)

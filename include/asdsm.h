@@ -90,6 +90,10 @@ typedef struct {
     double rnorm;         /* ||r||_2 of the returned iterate                                     */
     double phase_ms[ASDSM_NPHASE];      /* accumulated device time per phase (profile only)      */
     int    phase_launches[ASDSM_NPHASE];/* kernel launches per phase (profile only)              */
+    double phase_flops[ASDSM_NPHASE];   /* algorithmic floating-point operations per phase       */
+                                        /* (profile only; a GEMM counts 2*M*N*K)                 */
+    double phase_bytes[ASDSM_NPHASE];   /* algorithmic bytes per phase: every operand read once  */
+                                        /* and every result written once (profile only)          */
     double total_ms;      /* device time of the whole call (profile only)                        */
 } asdsm_stats;
 

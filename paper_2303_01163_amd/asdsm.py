@@ -40,7 +40,8 @@ class Opts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("status", c_int), ("iterations", c_int), ("bnorm", c_double),
                 ("r0norm", c_double), ("rnorm", c_double), ("phase_ms", c_double * NPHASE),
-                ("phase_launches", c_int * NPHASE), ("total_ms", c_double)]
+                ("phase_launches", c_int * NPHASE), ("phase_flops", c_double * NPHASE),
+                ("phase_bytes", c_double * NPHASE), ("total_ms", c_double)]
 
 
 _lib = None
@@ -162,6 +163,8 @@ class Plan:
         if profile:
             info["phase_ms"] = {PHASES[q]: st.phase_ms[q] for q in range(NPHASE)}
             info["phase_launches"] = {PHASES[q]: st.phase_launches[q] for q in range(NPHASE)}
+            info["phase_flops"] = {PHASES[q]: st.phase_flops[q] for q in range(NPHASE)}
+            info["phase_bytes"] = {PHASES[q]: st.phase_bytes[q] for q in range(NPHASE)}
             info["total_ms"] = st.total_ms
         return u, info
 

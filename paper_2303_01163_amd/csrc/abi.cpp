@@ -24,24 +24,57 @@ int check_launch(const char *what) {
     return ASDSM_OK;
 }
 
-// Phase timing (opts->profile): events around a group of launches, synchronised per phase.
+// Phase timing (opts->profile): a pair of events around a group of launches, with the algorithmic
+// work of those launches (flops; bytes with every operand read once and every result written
+// once).  Nothing synchronises here: the pairs are read once the call has finished.
 struct PhaseTimer {
     Plan &p;
-    int phase;
-    int launches;
-    PhaseTimer(Plan &pl, int ph, int nl) : p(pl), phase(ph), launches(nl) {
-        if (p.profiling) (void)hipEventRecord(p.ev_begin, p.stream);
+    size_t idx = 0;
+    bool on = false;
+    PhaseTimer(Plan &pl, int ph, int nl, double fl = 0.0, double by = 0.0) : p(pl) {
+        if (!p.profiling || p.prof_failed) return;
+        idx = p.ev_recs.size();
+        while (p.ev_pool.size() < 2 * (idx + 1)) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) {
+                p.prof_failed = true;
+                return;
+            }
+            p.ev_pool.push_back(e);
+        }
+        p.ev_recs.push_back({ph, nl, fl, by});
+        on = hipEventRecord(p.ev_pool[2 * idx], p.stream) == hipSuccess;
+        if (!on) p.prof_failed = true;
     }
     ~PhaseTimer() {
-        if (!p.profiling) return;
-        (void)hipEventRecord(p.ev_end, p.stream);
-        (void)hipEventSynchronize(p.ev_end);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, p.ev_begin, p.ev_end);
-        p.phase_ms[phase] += ms;
-        p.phase_launches[phase] += launches;
+        if (on && hipEventRecord(p.ev_pool[2 * idx + 1], p.stream) != hipSuccess) p.prof_failed = true;
     }
 };
+
+// Sum the recorded pairs into the per-phase totals (after the stream has been synchronised).
+int collect_phases(Plan &p) {
+    if (p.prof_failed) return fail(ASDSM_E_DEVICE, "profiling events could not be recorded");
+    for (size_t i = 0; i < p.ev_recs.size(); ++i) {
+        const Plan::PhaseRec &r = p.ev_recs[i];
+        float ms = 0.f;
+        ASDSM_HIP_CHECK(hipEventElapsedTime(&ms, p.ev_pool[2 * i], p.ev_pool[2 * i + 1]));
+        p.phase_ms[r.phase] += ms;
+        p.phase_launches[r.phase] += r.launches;
+        p.phase_flops[r.phase] += r.flops;
+        p.phase_bytes[r.phase] += r.bytes;
+    }
+    return ASDSM_OK;
+}
+
+// Algorithmic work of one batched GEMM launch: 2 M N K flops per product; an operand shared by the
+// batch (batch stride 0) is counted once per box; C is read as well when accumulating.
+double gemm_flops(const GemmJob &j) { return 2.0 * j.M * j.N * j.K * j.nbatch * j.nbox; }
+double gemm_bytes(const GemmJob &j) {
+    const double a = (double)j.M * j.K * (j.sAb ? j.nbatch : 1);
+    const double b = (double)j.K * j.N * (j.sBb ? j.nbatch : 1);
+    const double c = (double)j.M * j.N * j.nbatch * (j.accum ? 2 : 1);
+    return 8.0 * j.nbox * (a + b + c);
+}
 
 void fine_axes(int d, int k, int &a, int &b) {
     if (d == 2) {
@@ -77,7 +110,6 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
     j.gate = p.gate;
     // forward transform along canonical axis 0 (contiguous): in -> Y
     {
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
         j.M = (d == 2) ? Nc : Nf * Nc;
         j.N = Nf; j.K = Nf; j.nbatch = 1; j.accum = 0;
         j.sAb = j.sBb = j.sCb = 0;
@@ -91,12 +123,12 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.B[q] = p.dW[a];
             j.C[q] = p.ws.Y[1u << ks[q]];
         }
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
     }
     if (d == 3) {
         // forward along canonical axis 1, batched over the coarse slabs: Y -> X
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
         j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc; j.accum = 0;
         j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
         j.sBb = Nf2; j.sBk = Nf; j.sBn = 1;
@@ -108,12 +140,12 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.B[q] = p.ws.Y[1u << ks[q]];
             j.C[q] = p.ws.X[1u << ks[q]];
         }
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
     }
     // line elimination along the coarse axis: d = 2 on Y (scratch X), d = 3 on X (scratch Y)
     {
-        PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
         LineJob L{};
         L.nbox = nb;
         L.gate = p.gate;
@@ -130,12 +162,13 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             L.mu_b[q] = (d == 3) ? p.dmu[b] : nullptr;
             L.t[q] = p.geo.coarse[k];
         }
+        const double lpts = (double)L.nmodes * L.ncoarse * nb;
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 8.0 * lpts, 16.0 * lpts);
         launch_line(L, p.stream);
         if (int rc = check_launch("line")) return rc;
     }
     if (d == 3) {
         // backward along canonical axis 1: X -> Y
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
         j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc; j.accum = 0;
         j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
         j.sBb = Nf2; j.sBk = Nf; j.sBn = 1;
@@ -147,12 +180,12 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.B[q] = p.ws.X[1u << ks[q]];
             j.C[q] = p.ws.Y[1u << ks[q]];
         }
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
     }
     {
         // backward along canonical axis 0: Y -> out
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
         j.M = (d == 2) ? Nc : Nf * Nc;
         j.N = Nf; j.K = Nf; j.nbatch = 1; j.accum = accum;
         j.sAb = j.sBb = j.sCb = 0;
@@ -166,6 +199,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.B[q] = p.dV[a];
             j.C[q] = out[ks[q]];
         }
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
     }
@@ -178,7 +212,8 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
 int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, int accum) {
     const MeshDesc &m = p.mesh[mask];
     if (m.nfine == 0) {
-        PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
+        const double B = m.block;
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 2.0 * B * B, 8.0 * (B * B + (accum ? 3 : 2) * B));
         launch_dense_modes(1, m.block, p.ddense[mask], in, out, accum, p.stream);
         return check_launch("dense");
     }
@@ -193,25 +228,26 @@ int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, in
     j.sBk = 1;    j.sBn = p.Nf;
     j.sCi = p.Nf; j.sCn = 1;
     {
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
         j.A[0] = in;
         j.B[0] = p.dW[f];
         j.C[0] = p.ws.Y[mask];
         j.accum = 0;
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
+        const double B = m.block, nmo = (double)m.nmodes;
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 2.0 * nmo * B * B, 8.0 * nmo * (B * B + 2 * B));
         launch_dense_modes(m.nmodes, m.block, p.ddense[mask], p.ws.Y[mask], p.ws.X[mask], 0, p.stream);
         if (int rc = check_launch("dense")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1);
         j.A[0] = p.ws.X[mask];
         j.B[0] = p.dV[f];
         j.C[0] = out;
         j.accum = accum;
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
         launch_gemm(j, p.stream);
         if (int rc = check_launch("transform")) return rc;
     }
@@ -248,7 +284,9 @@ int solve_aniso_refined(Plan &p, unsigned kbits) {
             res[k] = p.ws.X[m];
         }
         {
-            PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
+            double pts = 0.0;
+            for (int q = 0; q < job.nbox; ++q) pts += (double)job.m[q].size;
+            PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 2.0 * (2 * p.d + 1) * pts, 24.0 * pts);
             launch_box_residual(p, job, p.stream);
             if (int rc = check_launch("box residual")) return rc;
         }
@@ -269,7 +307,9 @@ int solve_intersection_refined(Plan &p, unsigned mask) {
         job.out[0] = p.ws.X[mask];
         job.m[0] = p.mesh[mask];
         {
-            PhaseTimer t(p, ASDSM_PHASE_LINE, 1);
+            double pts = 0.0;
+            for (int q = 0; q < job.nbox; ++q) pts += (double)job.m[q].size;
+            PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 2.0 * (2 * p.d + 1) * pts, 24.0 * pts);
             launch_box_residual(p, job, p.stream);
             if (int rc = check_launch("box residual")) return rc;
         }
@@ -288,6 +328,24 @@ void gather_pointers(const Plan &p, double *g[kMaxMeshes]) {
     for (unsigned s = 1; s < (1u << p.d); ++s) g[s] = rhs_buf(p, s);
 }
 
+
+// Points of the anisotropic meshes (the refinement loop's submeshes), of all submeshes, of one
+// Dirichlet face and of the holes.
+double aniso_points(const Plan &p) {
+    double n = 0.0;
+    for (int k = 0; k < p.d; ++k) n += (double)p.mesh[1u << k].size;
+    return n;
+}
+double submesh_points(const Plan &p) {
+    double n = 0.0;
+    for (unsigned m = 1; m < (1u << p.d); ++m) n += (double)p.mesh[m].size;
+    return n;
+}
+double face_points(const Plan &p) { return std::pow((double)p.Nf, p.d - 1); }
+double hole_points(const Plan &p) { return std::pow((double)(p.Nc + 1) * (p.geo.n - 1), p.d); }
+// Hole solves: forward and backward mode transforms along d-1 axes (2 (n-1) flops each per point)
+// and a Thomas line (8 flops per point).
+double filler_flops(const Plan &p) { return hole_points(p) * (4.0 * (p.d - 1) * (p.geo.n - 1) + 8.0); }
 
 int read_scalars(Plan &p) {
     ASDSM_HIP_CHECK(hipMemcpyAsync(p.hscal, p.ws.scal, kScalCount * sizeof(double), hipMemcpyDeviceToHost, p.stream));
@@ -423,7 +481,8 @@ int calibrate_sweeps(Plan &p) {
 int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     const unsigned nm = 1u << p.d;
     {
-        PhaseTimer t(p, ASDSM_PHASE_RHS, (int)nm + 1);
+        PhaseTimer t(p, ASDSM_PHASE_RHS, (int)nm + 1, 0.0,
+                     8.0 * (2.0 * (double)p.geo.NF + 2.0 * p.d * face_points(p) + submesh_points(p)));
         launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
         for (unsigned m = 1; m < nm; ++m) launch_rhs(p, m, s, g, rhs_buf(p, m), false, p.stream);
         if (int rc = check_launch("rhs")) return rc;
@@ -435,18 +494,21 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     const double *res[kMaxMeshes];
     result_pointers(p, res);
     {
-        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 3 : 2);
+        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 3 : 2, 0.0,
+                     8.0 * (submesh_points(p) + aniso_points(p)));
         launch_crosspoints(p, 0, res, p.stream);
         launch_merge(p, 0, res, p.stream);
         if (int rc = check_launch("skeleton")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1);
+        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
+                     8.0 * ((double)p.geo.NF + hole_points(p) + aniso_points(p)));
         launch_filler(p, p.ws.b, u, p.stream);
         if (int rc = check_launch("filler")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2);
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,
+                     8.0 * (3.0 * (double)p.geo.NF + aniso_points(p)));
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
         launch_update_residual(p, u, nullptr, nullptr, gat, kFinInit, p.stream);
@@ -463,24 +525,26 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
     const double *res[kMaxMeshes];
     result_pointers(p, res);
     {
-        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 5 : 4);
+        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 5 : 4, 0.0, 24.0 * aniso_points(p));
         launch_box_norms(p, res, p.stream);
         launch_crosspoints(p, 1, res, p.stream);
         launch_merge(p, 1, res, p.stream);
         if (int rc = check_launch("skeleton")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1);
+        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
+                     8.0 * ((double)p.geo.NF + aniso_points(p)));
         launch_filler(p, nullptr, p.ws.e, p.stream);
         if (int rc = check_launch("filler")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_DOTS, 2);
+        PhaseTimer t(p, ASDSM_PHASE_DOTS, 2, (4.0 * p.d + 6.0) * (double)p.geo.NF, 16.0 * (double)p.geo.NF);
         launch_dots(p, p.stream);
         if (int rc = check_launch("dots")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2);
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2, (4.0 * p.d + 6.0) * (double)p.geo.NF,
+                     8.0 * (5.0 * (double)p.geo.NF + aniso_points(p)));
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
         launch_update_residual(p, u_cur, p.ws.e, u_next, gat, kFinIter, p.stream);
@@ -555,10 +619,14 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         return fail(ASDSM_E_ARG, "invalid options (max_iter must be < " + std::to_string(kHistCap) + ")");
     if (int rc = require_ws(p)) return rc;
     p.profiling = opt.profile != 0;
+    p.prof_failed = false;
+    p.ev_recs.clear();
     const bool use_graph = !p.profiling && !opt.eager;
     for (int q = 0; q < ASDSM_NPHASE; ++q) {
         p.phase_ms[q] = 0.0;
         p.phase_launches[q] = 0;
+        p.phase_flops[q] = 0.0;
+        p.phase_bytes[q] = 0.0;
     }
     hipEvent_t tb = nullptr, te = nullptr;
     if (p.profiling) {
@@ -585,11 +653,12 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         if (int rc = initial_guess(p, s, g, u)) return rc;
     } else {
         {
-            PhaseTimer t(p, ASDSM_PHASE_RHS, 2);
+            PhaseTimer t(p, ASDSM_PHASE_RHS, 2, 0.0, 8.0 * (2.0 * (double)p.geo.NF + 2.0 * p.d * face_points(p)));
             launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
             if (int rc = check_launch("rhs")) return rc;
         }
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2);
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,
+                     8.0 * (3.0 * (double)p.geo.NF + aniso_points(p)));
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
         launch_update_residual(p, u, nullptr, nullptr, gat, kFinInit, p.stream);
@@ -638,6 +707,8 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
     if (opt.step_hist && it > 0)
         ASDSM_HIP_CHECK(hipMemcpyAsync(opt.step_hist, p.ws.step_hist, (size_t)it * sizeof(double), hipMemcpyDeviceToHost, p.stream));
     ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
+    if (p.profiling)
+        if (int rc2 = collect_phases(p)) return rc2;
     const int status = hs.status;
     if (st) {
         std::memset(st, 0, sizeof *st);
@@ -649,6 +720,8 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         for (int q = 0; q < ASDSM_NPHASE; ++q) {
             st->phase_ms[q] = p.phase_ms[q];
             st->phase_launches[q] = p.phase_launches[q];
+            st->phase_flops[q] = p.phase_flops[q];
+            st->phase_bytes[q] = p.phase_bytes[q];
         }
         if (p.profiling) {
             ASDSM_HIP_CHECK(hipEventRecord(te, p.stream));

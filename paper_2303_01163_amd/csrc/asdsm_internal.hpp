@@ -19,6 +19,7 @@ namespace asdsm {
 
 constexpr int kMaxD = 3;
 constexpr int kMaxMeshes = 1 << kMaxD;
+constexpr int kDenseMaxBlock = 4096;  // coarse points per mode of an intersection-mesh dense solve
 
 // Canonical layout of mesh M_S.
 struct MeshDesc {
@@ -159,11 +160,20 @@ struct Plan {
     hipGraphExec_t graph_exec = nullptr;
     const double *graph_u = nullptr;
 
-    // profiling events
+    // profiling: a pair of events around every timed launch group, read after the call's final
+    // synchronisation (launches stay queued back to back, so the pair brackets the kernels alone)
+    struct PhaseRec {
+        int phase, launches;
+        double flops, bytes;
+    };
     bool profiling = false;
-    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    bool prof_failed = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<PhaseRec> ev_recs;
     double phase_ms[ASDSM_NPHASE] = {};
     int phase_launches[ASDSM_NPHASE] = {};
+    double phase_flops[ASDSM_NPHASE] = {};
+    double phase_bytes[ASDSM_NPHASE] = {};
 };
 
 // ---- host plan construction (plan.cpp)

@@ -14,13 +14,13 @@
 namespace asdsm {
 
 // ---------------------------------------------------------------------------------------------
-// Batched FP64 GEMM on MFMA.  Block = 4 waves, block tile 32 x 32, each wave one 16 x 16 MFMA tile.
+// Batched FP64 GEMM on MFMA, block tile 32 x 32 (8 waves, see below).
 // The A (32 x 128) and B (128 x 32) panels are staged in LDS with fully coalesced loads (a wave
 // reads 64 consecutive doubles along the contiguous index of the operand); with K <= 128 (every
 // mode transform up to N_f = 127) all loads of a block are in flight together before its single
 // barrier, which matters because the operands were just written by the previous kernel and come
-// from the Infinity Cache.  Blocks are numbered so that the N-tiles sharing one A panel run on the
-// same XCD (consecutive block ids go to consecutive XCDs) and reuse that XCD's L2.
+// from the Infinity Cache.  Consecutive block ids go to consecutive XCDs; blocks are numbered so
+// that each XCD takes one contiguous range of tiles (tiles sharing an operand panel reuse its L2).
 // Operand layout of v_mfma_f64_16x16x4f64 (lane l, 0..63):
 //   A: row l%16, k l/16;  B: k l/16, col l%16;  D[v]: row l/16 + 4v, col l%16.
 // ---------------------------------------------------------------------------------------------
@@ -35,15 +35,19 @@ __global__ __launch_bounds__(512) void k_gemm_f64(GemmJob job) {
     if (job.gate && *job.gate) return;
     __shared__ double sA[32][GKC + 1];
     __shared__ double sB[GKC][32 + 1];
-    // block id -> (z, tile x, tile y); see launch_gemm for the layout
+    // block id -> tile: block b runs on XCD b % 8, which takes the contiguous tile range
+    // [per * (b % 8), per * (b % 8 + 1)) of the (z, tile y, tile x) order, tile x fastest; tiles that
+    // share an operand panel thus share that XCD's L2, and every XCD gets the same number of tiles.
     const int tx = (job.N + 31) / 32, ty = (job.M + 31) / 32;
-    const int per_z = tx * ((ty + 7) / 8) * 8;
-    const int z = blockIdx.x / per_z;
-    const int r = blockIdx.x - z * per_z;
-    const int slot = r >> 3;
-    const int bx = slot % tx;
-    const int by = (slot / tx) * 8 + (r & 7);
-    if (by >= ty) return;  // padding slot (block-uniform)
+    const int per_z = tx * ty;
+    const int total = per_z * job.nbox * job.nbatch;
+    const int per = (total + 7) / 8;
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if ((blockIdx.x >> 3) >= per || tile >= total) return;  // padding (block-uniform)
+    const int z = tile / per_z;
+    const int rem = tile - z * per_z;
+    const int by = rem / tx;
+    const int bx = rem - by * tx;
     const int box = z / job.nbatch;
     const int bat = z - box * job.nbatch;
     const double *__restrict__ A = job.A[box] + (long long)bat * job.sAb;
@@ -89,10 +93,10 @@ __global__ __launch_bounds__(512) void k_gemm_f64(GemmJob job) {
     }
     // sum the two K halves: waves with kh = 1 hand their partial tile over through LDS
     double *red = &sA[0][0];  // 4 tiles x 256 values, reusing the A panel
-    const int tile = wm + 2 * wn;
+    const int wt = wm + 2 * wn;
     if (kh == 1) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) red[tile * 256 + v * 64 + lane] = acc0[v] + acc1[v];
+        for (int v = 0; v < 4; ++v) red[wt * 256 + v * 64 + lane] = acc0[v] + acc1[v];
     }
     __syncthreads();
     if (kh == 1) return;
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(512) void k_gemm_f64(GemmJob job) {
     for (int v = 0; v < 4; ++v) {
         const int gi = m0 + wm * 16 + (lane >> 4) + 4 * v;
         const int gn = n0 + wn * 16 + (lane & 15);
-        const double val = (acc0[v] + acc1[v]) + red[tile * 256 + v * 64 + lane];
+        const double val = (acc0[v] + acc1[v]) + red[wt * 256 + v * 64 + lane];
         if (gi < job.M && gn < job.N) {
             double *c = C + (long long)gi * job.sCi + (long long)gn * job.sCn;
             *c = job.accum ? *c + val : val;
@@ -110,11 +114,10 @@ __global__ __launch_bounds__(512) void k_gemm_f64(GemmJob job) {
 }
 
 void launch_gemm(const GemmJob &job, hipStream_t st) {
-    // 1D grid: for each (box, batch) z, tx * ceil(ty/8) * 8 slots; slot r maps to tile
-    // x = (r/8) % tx, y = ((r/8) / tx) * 8 + r % 8 (slots with y >= ty return at once)
+    // 1D grid of 8 * ceil(tiles / 8) blocks (see the tile order in k_gemm_f64)
     const long long tx = (job.N + 31) / 32, ty = (job.M + 31) / 32;
-    const long long per_z = tx * ((ty + 7) / 8) * 8;
-    const long long blocks = per_z * job.nbox * job.nbatch;
+    const long long total = tx * ty * job.nbox * job.nbatch;
+    const long long blocks = 8 * ((total + 7) / 8);
     hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)blocks), dim3(512), 0, st, job);
 }
 
@@ -194,27 +197,42 @@ void launch_line(const LineJob &job, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Per-mode dense solve: out[m + nmodes*e] = sum_e' inv[m][e][e'] in[m + nmodes*e'].
+// Per-mode dense solve: out[m + nmodes*r] = sum_e inv_m(r, e) in[m + nmodes*e], the inverse of mode
+// m stored column by column (inv[(m*B + e)*B + r]) so that a wave reads 64 consecutive rows.  Block
+// (row chunk of 64, mode): the mode's input vector is staged in LDS, the four waves split the sum
+// over e and combine their partial sums through LDS.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_dense_modes(long long nmodes, int B,
                                                      const double *__restrict__ inv,
                                                      const double *__restrict__ in,
                                                      double *__restrict__ out, int accum) {
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= nmodes * B) return;
-    const long long m = t % nmodes;
-    const int row = (int)(t / nmodes);
-    const double *__restrict__ Mi = inv + (m * B + row) * (long long)B;
+    __shared__ double x[kDenseMaxBlock];
+    __shared__ double part[4][64];
+    const long long m = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int e = threadIdx.x; e < B; e += 256) x[e] = in[m + nmodes * e];
+    __syncthreads();
+    const int r = blockIdx.x * 64 + lane;
+    const int per = (B + 3) / 4;
+    const int e0 = w * per, e1 = min(B, e0 + per);
     double acc = 0.0;
-    for (int e = 0; e < B; ++e) acc += Mi[e] * in[m + nmodes * e];
-    out[m + nmodes * row] = accum ? out[m + nmodes * row] + acc : acc;
+    if (r < B) {
+        const double *__restrict__ col = inv + ((size_t)m * B) * B + r;
+        for (int e = e0; e < e1; ++e) acc += col[(size_t)e * B] * x[e];
+    }
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && r < B) {
+        const double v = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        double *o = out + m + nmodes * r;
+        *o = accum ? *o + v : v;
+    }
 }
 
 void launch_dense_modes(long long nmodes, int B, const double *inv, const double *in, double *out,
                         int accum, hipStream_t st) {
-    const long long n = nmodes * B;
-    hipLaunchKernelGGL(k_dense_modes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nmodes, B,
-                       inv, in, out, accum);
+    dim3 grid((unsigned)((B + 63) / 64), (unsigned)nmodes);
+    hipLaunchKernelGGL(k_dense_modes, grid, dim3(256), 0, st, nmodes, B, inv, in, out, accum);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -226,7 +226,7 @@ static bool build_dense_inverse(Plan &p, unsigned mask) {
             std::fill(col.begin(), col.end(), 0.0);
             col[j] = 1.0;
             lu_solve(B, A, piv, col.data());
-            for (int i = 0; i < B; ++i) inv[(size_t)i * B + j] = col[i];
+            for (int i = 0; i < B; ++i) inv[(size_t)j * B + i] = col[i];  // column j
         }
     }
     return true;
@@ -350,6 +350,22 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         if (p.hole_spec[j].cond > p.hole_spec[p.hole_line_axis].cond) p.hole_line_axis = j;
     build_spline(p.Nf, p.Nc, p.n, p.h, p.H, p.Sp);
     for (unsigned s = 0; s < (1u << d); ++s) p.mesh[s] = make_mesh(d, p.Nf, p.Nc, s);
+    // intersection meshes: per-mode dense inverses of at most kDenseMaxBlock coarse points, at most
+    // 512 MiB in total
+    {
+        double bytes = 0.0;
+        for (unsigned s = 1; s < (1u << d); ++s)
+            if (__builtin_popcount(s) >= 2) {
+                const MeshDesc &m = p.mesh[s];
+                if (m.block > kDenseMaxBlock)
+                    return fail(ASDSM_E_UNSUPPORTED, "intersection mesh with more than " +
+                                                         std::to_string(kDenseMaxBlock) +
+                                                         " coarse points per mode");
+                bytes += 8.0 * (double)m.nmodes * m.block * m.block;
+            }
+        if (bytes > 512.0 * 1024 * 1024)
+            return fail(ASDSM_E_UNSUPPORTED, "intersection-mesh inverses exceed 512 MiB");
+    }
     for (unsigned s = 1; s < (1u << d); ++s) {
         if (__builtin_popcount(s) >= 2) {
             if (!build_dense_inverse(p, s))
@@ -442,9 +458,6 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     if (err == hipSuccess)
         err = hipHostMalloc((void **)&p.hperm, (size_t)kHistCap * kMaxD * sizeof(int), hipHostMallocDefault);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(err));
-    err = hipEventCreate(&p.ev_begin);
-    if (err == hipSuccess) err = hipEventCreate(&p.ev_end);
-    if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipEventCreate: ") + hipGetErrorString(err));
     return ASDSM_OK;
 }
 
@@ -461,11 +474,11 @@ void release_plan(Plan &p) {
     if (p.hperm) (void)hipHostFree(p.hperm);
     p.hstate = nullptr;
     p.hperm = nullptr;
-    if (p.ev_begin) (void)hipEventDestroy(p.ev_begin);
-    if (p.ev_end) (void)hipEventDestroy(p.ev_end);
+    for (hipEvent_t e : p.ev_pool) (void)hipEventDestroy(e);
+    p.ev_pool.clear();
+    p.ev_recs.clear();
     p.dtab = nullptr;
     p.hscal = nullptr;
-    p.ev_begin = p.ev_end = nullptr;
 }
 
 }  // namespace asdsm
