@@ -28,25 +28,41 @@ FP64_PEAK_TFLOPS = 78.6
 PHASE_KERNEL = {"transform": "k_gemm_f64", "update": "k_update_residual", "dots": "k_dots",
                 "filler": "k_filler_mfma3", "skeleton": "k_merge", "line": "k_line", "rhs": "k_rhs"}
 KERNEL_SOURCE = {"k_gemm_f64": "k_boxsolve.hip", "k_update_residual": "k_stencil.hip",
-                 "k_dots": "k_stencil.hip", "k_filler_mfma3": "k_skeleton.hip"}
+                 "k_dots": "k_stencil.hip", "k_filler_mfma3": "k_skeleton.hip",
+                 "k_box_residual": "k_boxsolve.hip", "k_merge": "k_skeleton.hip",
+                 "k_line": "k_boxsolve.hip", "k_crosspoints": "k_skeleton.hip"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_asdsm3d_127.txt")
+
+
+def kernel_digest(kernel):
+    """sha256 of a kernel's source text: from the line that declares it to the first line that
+    closes a top-level block after it."""
+    import hashlib
+    src = KERNEL_SOURCE.get(kernel)
+    if src is None:
+        return None
+    lines = open(os.path.join(ROOT, "paper_2303_01163_amd", "csrc", src)).read().split("\n")
+    for i, ln in enumerate(lines):
+        if f"void {kernel}(" in ln:
+            j = i
+            while j < len(lines) and lines[j] != "}":
+                j += 1
+            return hashlib.sha256("\n".join(lines[i:j + 1]).encode()).hexdigest()
+    return None
 
 
 def pmc_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary, or None when there is none or the kernel's source changed since it was taken."""
-    import hashlib
-    src = KERNEL_SOURCE.get(kernel)
-    if src is None or not os.path.exists(PMC_SUMMARY):
+    digest = kernel_digest(kernel)
+    if digest is None or not os.path.exists(PMC_SUMMARY):
         return None
-    path = os.path.join(ROOT, "paper_2303_01163_amd", "csrc", src)
-    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
     for line in open(PMC_SUMMARY):
         f = line.split()
         if not f or f[0] != kernel:
             continue
         kv = dict(x.split("=", 1) for x in f[1:] if "=" in x)
-        if kv.get("source_sha256") == digest:
+        if kv.get("kernel_sha256") == digest:
             return float(kv["bytes_per_launch"])
     return None
 

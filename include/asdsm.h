@@ -89,7 +89,9 @@ typedef struct {
     double r0norm;        /* ||r||_2 of the entry iterate                                        */
     double rnorm;         /* ||r||_2 of the returned iterate                                     */
     double phase_ms[ASDSM_NPHASE];      /* accumulated device time per phase (profile only)      */
-    int    phase_launches[ASDSM_NPHASE];/* kernel launches per phase (profile only)              */
+    int    phase_launches[ASDSM_NPHASE];/* kernel launches per phase (profile only); a kernel    */
+                                        /* and the one-block reduction that finishes its sums    */
+                                        /* count as one launch                                   */
     double phase_flops[ASDSM_NPHASE];   /* algorithmic floating-point operations per phase       */
                                         /* (profile only; a GEMM counts 2*M*N*K)                 */
     double phase_bytes[ASDSM_NPHASE];   /* algorithmic bytes per phase: every operand read once  */

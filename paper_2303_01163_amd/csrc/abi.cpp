@@ -10,6 +10,11 @@
 namespace asdsm {
 const char *last_error_cstr();
 
+LaunchEvents &launch_events() {
+    static thread_local LaunchEvents ev;
+    return ev;
+}
+
 namespace {
 
 #define ASDSM_HIP_CHECK(expr)                                                                    \
@@ -24,9 +29,10 @@ int check_launch(const char *what) {
     return ASDSM_OK;
 }
 
-// Phase timing (opts->profile): a pair of events around a group of launches, with the algorithmic
-// work of those launches (flops; bytes with every operand read once and every result written
-// once).  Nothing synchronises here: the pairs are read once the call has finished.
+// Phase timing (opts->profile): a pair of events stamped by the kernels of a launch group (see
+// LaunchEvents), with the algorithmic work of those launches (flops; bytes with every operand read
+// once and every result written once).  Nothing synchronises here: the pairs are read once the
+// call has finished.
 struct PhaseTimer {
     Plan &p;
     size_t idx = 0;
@@ -42,12 +48,17 @@ struct PhaseTimer {
             }
             p.ev_pool.push_back(e);
         }
-        p.ev_recs.push_back({ph, nl, fl, by});
-        on = hipEventRecord(p.ev_pool[2 * idx], p.stream) == hipSuccess;
-        if (!on) p.prof_failed = true;
+        p.ev_recs.push_back({ph, nl, fl, by, false});
+        LaunchEvents &le = launch_events();
+        le.start = p.ev_pool[2 * idx];
+        le.stop = p.ev_pool[2 * idx + 1];
+        on = true;
     }
     ~PhaseTimer() {
-        if (on && hipEventRecord(p.ev_pool[2 * idx + 1], p.stream) != hipSuccess) p.prof_failed = true;
+        if (!on) return;
+        LaunchEvents &le = launch_events();
+        p.ev_recs[idx].launched = (le.start == nullptr);  // the first launch consumed `start`
+        le = LaunchEvents{};
     }
 };
 
@@ -56,6 +67,7 @@ int collect_phases(Plan &p) {
     if (p.prof_failed) return fail(ASDSM_E_DEVICE, "profiling events could not be recorded");
     for (size_t i = 0; i < p.ev_recs.size(); ++i) {
         const Plan::PhaseRec &r = p.ev_recs[i];
+        if (!r.launched) continue;
         float ms = 0.f;
         ASDSM_HIP_CHECK(hipEventElapsedTime(&ms, p.ev_pool[2 * i], p.ev_pool[2 * i + 1]));
         p.phase_ms[r.phase] += ms;
@@ -481,7 +493,7 @@ int calibrate_sweeps(Plan &p) {
 int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     const unsigned nm = 1u << p.d;
     {
-        PhaseTimer t(p, ASDSM_PHASE_RHS, (int)nm + 1, 0.0,
+        PhaseTimer t(p, ASDSM_PHASE_RHS, (int)nm, 0.0,
                      8.0 * (2.0 * (double)p.geo.NF + 2.0 * p.d * face_points(p) + submesh_points(p)));
         launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
         for (unsigned m = 1; m < nm; ++m) launch_rhs(p, m, s, g, rhs_buf(p, m), false, p.stream);
@@ -507,7 +519,7 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
         if (int rc = check_launch("filler")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,
                      8.0 * (3.0 * (double)p.geo.NF + aniso_points(p)));
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
@@ -525,7 +537,7 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
     const double *res[kMaxMeshes];
     result_pointers(p, res);
     {
-        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 5 : 4, 0.0, 24.0 * aniso_points(p));
+        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 4 : 3, 0.0, 24.0 * aniso_points(p));
         launch_box_norms(p, res, p.stream);
         launch_crosspoints(p, 1, res, p.stream);
         launch_merge(p, 1, res, p.stream);
@@ -538,12 +550,12 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
         if (int rc = check_launch("filler")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_DOTS, 2, (4.0 * p.d + 6.0) * (double)p.geo.NF, 16.0 * (double)p.geo.NF);
+        PhaseTimer t(p, ASDSM_PHASE_DOTS, 1, (4.0 * p.d + 6.0) * (double)p.geo.NF, 16.0 * (double)p.geo.NF);
         launch_dots(p, p.stream);
         if (int rc = check_launch("dots")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2, (4.0 * p.d + 6.0) * (double)p.geo.NF,
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, (4.0 * p.d + 6.0) * (double)p.geo.NF,
                      8.0 * (5.0 * (double)p.geo.NF + aniso_points(p)));
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
@@ -653,11 +665,11 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         if (int rc = initial_guess(p, s, g, u)) return rc;
     } else {
         {
-            PhaseTimer t(p, ASDSM_PHASE_RHS, 2, 0.0, 8.0 * (2.0 * (double)p.geo.NF + 2.0 * p.d * face_points(p)));
+            PhaseTimer t(p, ASDSM_PHASE_RHS, 1, 0.0, 8.0 * (2.0 * (double)p.geo.NF + 2.0 * p.d * face_points(p)));
             launch_rhs(p, 0, s, g, p.ws.b, true, p.stream);
             if (int rc = check_launch("rhs")) return rc;
         }
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 2, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,
                      8.0 * (3.0 * (double)p.geo.NF + aniso_points(p)));
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);

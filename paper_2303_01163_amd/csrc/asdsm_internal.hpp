@@ -165,6 +165,7 @@ struct Plan {
     struct PhaseRec {
         int phase, launches;
         double flops, bytes;
+        bool launched;
     };
     bool profiling = false;
     bool prof_failed = false;

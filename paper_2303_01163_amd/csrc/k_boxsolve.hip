@@ -118,7 +118,7 @@ void launch_gemm(const GemmJob &job, hipStream_t st) {
     const long long tx = (job.N + 31) / 32, ty = (job.M + 31) / 32;
     const long long total = tx * ty * job.nbox * job.nbatch;
     const long long blocks = 8 * ((total + 7) / 8);
-    hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)blocks), dim3(512), 0, st, job);
+    ASDSM_LAUNCH(k_gemm_f64, dim3((unsigned)blocks), dim3(512), 0, st, job);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -187,13 +187,13 @@ __global__ __launch_bounds__(256) void k_line(LineJob job) {
 void launch_line(const LineJob &job, hipStream_t st) {
     dim3 grid((unsigned)((job.nmodes + 255) / 256), job.nbox, 1);
     if (job.ncoarse <= 7)
-        hipLaunchKernelGGL(k_line<7>, grid, dim3(256), 0, st, job);
+        ASDSM_LAUNCH((k_line<7>), grid, dim3(256), 0, st, job);
     else if (job.ncoarse <= 15)
-        hipLaunchKernelGGL(k_line<15>, grid, dim3(256), 0, st, job);
+        ASDSM_LAUNCH((k_line<15>), grid, dim3(256), 0, st, job);
     else if (job.ncoarse <= 31)
-        hipLaunchKernelGGL(k_line<31>, grid, dim3(256), 0, st, job);
+        ASDSM_LAUNCH((k_line<31>), grid, dim3(256), 0, st, job);
     else
-        hipLaunchKernelGGL(k_line<0>, grid, dim3(256), 0, st, job);
+        ASDSM_LAUNCH((k_line<0>), grid, dim3(256), 0, st, job);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_dense_modes(long long nmodes, int B,
 void launch_dense_modes(long long nmodes, int B, const double *inv, const double *in, double *out,
                         int accum, hipStream_t st) {
     dim3 grid((unsigned)((B + 63) / 64), (unsigned)nmodes);
-    hipLaunchKernelGGL(k_dense_modes, grid, dim3(256), 0, st, nmodes, B, inv, in, out, accum);
+    ASDSM_LAUNCH(k_dense_modes, grid, dim3(256), 0, st, nmodes, B, inv, in, out, accum);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -257,7 +257,7 @@ void launch_box_norms(const Plan &p, const double *const *sol, hipStream_t st) {
     BoxPtrs bx;
     for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? const_cast<double *>(sol[1u << k]) : nullptr;
     const long long size = p.mesh[1].size;
-    hipLaunchKernelGGL(k_box_norms, dim3(kNormBlocks, p.d, 1), dim3(256), 0, st, bx, size, p.ws.partials, p.gate);
+    ASDSM_LAUNCH(k_box_norms, dim3(kNormBlocks, p.d, 1), dim3(256), 0, st, bx, size, p.ws.partials, p.gate);
     launch_finalize(p, kNormBlocks, kFinBoxNorms, p.d, st);
 }
 
@@ -293,7 +293,7 @@ void launch_box_residual(const Plan &p, const BoxResJob &job, hipStream_t st) {
     for (int q = 0; q < job.nbox; ++q) mx = job.m[q].size > mx ? job.m[q].size : mx;
     long long blocks = (mx + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_box_residual, dim3((unsigned)blocks, job.nbox, 1), dim3(256), 0, st, p.geo, job);
+    ASDSM_LAUNCH(k_box_residual, dim3((unsigned)blocks, job.nbox, 1), dim3(256), 0, st, p.geo, job);
 }
 
 struct AxpyJob {
@@ -315,7 +315,7 @@ void launch_axpy(double *const *y, const double *const *x, long long n, int nbox
     }
     long long blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_axpy, dim3((unsigned)blocks, nbox, 1), dim3(256), 0, st, job, n);
+    ASDSM_LAUNCH(k_axpy, dim3((unsigned)blocks, nbox, 1), dim3(256), 0, st, job, n);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256) void k_fill_random(double *x, long long n, uns
 void launch_fill_random(double *x, long long n, uint64_t seed, hipStream_t st) {
     long long blocks = (n + 255) / 256;
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_fill_random, dim3((unsigned)blocks), dim3(256), 0, st, x, n, (unsigned long long)seed);
+    ASDSM_LAUNCH(k_fill_random, dim3((unsigned)blocks), dim3(256), 0, st, x, n, (unsigned long long)seed);
 }
 
 struct SumsqJob {
@@ -358,7 +358,7 @@ void launch_sumsq(const Plan &p, const double *const *x, const long long *n, int
         job.x[k] = x[k];
         job.n[k] = n[k];
     }
-    hipLaunchKernelGGL(k_sumsq, dim3(kNormBlocks, nbox, 1), dim3(256), 0, st, job, p.ws.partials);
+    ASDSM_LAUNCH(k_sumsq, dim3(kNormBlocks, nbox, 1), dim3(256), 0, st, job, p.ws.partials);
     launch_finalize(p, kNormBlocks, kFinBoxNorms, nbox, st);
 }
 

@@ -209,11 +209,11 @@ void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipSt
     const long long total = (p.d == 2) ? nA : 2 * nA;
     long long blocks = (total + 255) / 256;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_crosspoints, dim3((unsigned)blocks, p.d, 1), dim3(256), 0, st, p.geo, a);
+    ASDSM_LAUNCH(k_crosspoints, dim3((unsigned)blocks, p.d, 1), dim3(256), 0, st, p.geo, a);
     if (p.d == 3) {
         long long b2 = (nA + 255) / 256;
         if (b2 > 1024) b2 = 1024;
-        hipLaunchKernelGGL(k_lines_residual, dim3((unsigned)b2, p.d, 1), dim3(256), 0, st, p.geo, a);
+        ASDSM_LAUNCH(k_lines_residual, dim3((unsigned)b2, p.d, 1), dim3(256), 0, st, p.geo, a);
     }
 }
 
@@ -221,7 +221,7 @@ void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t
     SkelArgs a = skel_args(p, mode, res);
     long long blocks = (p.mesh[1].size + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_merge, dim3((unsigned)blocks, p.d, 1), dim3(256), 0, st, p.geo, a);
+    ASDSM_LAUNCH(k_merge, dim3((unsigned)blocks, p.d, 1), dim3(256), 0, st, p.geo, a);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -581,10 +581,10 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
     for (int j = 0; j < d; ++j) tiles *= (p.Nc + 1);
     const dim3 grid(tiles), blk(256);
     if (d == 3 && nh == 15) {
-        hipLaunchKernelGGL(k_filler_mfma3, grid, blk, 0, st, p.geo, a);
+        ASDSM_LAUNCH(k_filler_mfma3, grid, blk, 0, st, p.geo, a);
         return;
     }
-#define ASDSM_FILL(DD, NHV) hipLaunchKernelGGL((k_filler<DD, NHV>), grid, blk, lds, st, p.geo, a)
+#define ASDSM_FILL(DD, NHV) ASDSM_LAUNCH((k_filler<DD, NHV>), grid, blk, lds, st, p.geo, a)
     if (d == 2) {
         switch (nh) {
             case 1: ASDSM_FILL(2, 1); break;

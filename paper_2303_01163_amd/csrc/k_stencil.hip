@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
 }
 
 void launch_finalize(const Plan &p, int nblk, int mode, int nbox, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, p.ws.partials, nblk, mode, nbox, p.ws.scal,
+    ASDSM_LAUNCH(k_finalize, dim3(1), dim3(256), 0, st, p.ws.partials, nblk, mode, nbox, p.ws.scal,
                        p.ws.state, p.ws.hist, p.ws.step_hist, p.gate);
 }
 
@@ -283,7 +283,7 @@ void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf,
     const MeshDesc &m = p.mesh[mask];
     long long blocks = (m.size + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_rhs, dim3((unsigned)blocks), dim3(256), 0, st, p.geo, m, s, gf, out,
+    ASDSM_LAUNCH(k_rhs, dim3((unsigned)blocks), dim3(256), 0, st, p.geo, m, s, gf, out,
                        p.ws.partials, with_norm ? 1 : 0);
     if (with_norm) launch_finalize(p, (int)blocks, kFinBnorm, 1, st);
 }
@@ -295,10 +295,10 @@ void launch_update_residual(const Plan &p, const double *uin, const double *e, d
     BoxPtrs bx;
     for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? gather[1u << k] : nullptr;
     if (p.d == 2)
-        hipLaunchKernelGGL(k_update_residual<2>, grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
+        ASDSM_LAUNCH((k_update_residual<2>), grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
                            p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
     else
-        hipLaunchKernelGGL(k_update_residual<3>, grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
+        ASDSM_LAUNCH((k_update_residual<3>), grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
                            p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
     launch_finalize(p, (int)(grid.x * grid.y), fin_mode, 1, st);
 }
@@ -307,9 +307,9 @@ void launch_dots(const Plan &p, hipStream_t st) {
     dim3 grid;
     stencil_grid(p.geo, grid);
     if (p.d == 2)
-        hipLaunchKernelGGL(k_dots<2>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
+        ASDSM_LAUNCH((k_dots<2>), grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
     else
-        hipLaunchKernelGGL(k_dots<3>, grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
+        ASDSM_LAUNCH((k_dots<3>), grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
     launch_finalize(p, (int)(grid.x * grid.y), kFinDots, 1, st);
 }
 

@@ -1,9 +1,32 @@
 // Kernel launchers (host side), implemented in the k_*.hip files.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "asdsm_internal.hpp"
 
 namespace asdsm {
+
+// Profiling hook.  While a launch group is timed (asdsm_opts.profile), `stop` is set: every launch
+// then goes through hipExtLaunchKernelGGL, which stamps the events with the kernel's own start and
+// end times; the group's first launch records `start` (and clears it), every launch records `stop`,
+// so the pair spans the group's kernels without the host-side launch latency.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents &launch_events();  // per host thread
+
+#define ASDSM_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                      \
+    do {                                                                                          \
+        ::asdsm::LaunchEvents &le_ = ::asdsm::launch_events();                                    \
+        if (le_.stop) {                                                                           \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, le_.start, le_.stop, 0,     \
+                                  __VA_ARGS__);                                                   \
+            le_.start = nullptr;                                                                  \
+        } else {                                                                                  \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                  \
+        }                                                                                         \
+    } while (0)
 
 struct BoxPtrs {
     double *p[kMaxD];

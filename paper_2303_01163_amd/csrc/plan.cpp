@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "asdsm_internal.hpp"
 
@@ -186,6 +187,95 @@ static void build_spline(int Nf, int Nc, int n, double h, double H, std::vector<
     }
 }
 
+// Inverse of an n x n matrix (row major, overwritten by its LU factors) by LU with partial pivoting,
+// written column by column: inv[j*n + i] = (A^-1)(i, j).  The row extents of the (pivot-widened)
+// band are tracked so that elimination and substitution skip the zeros outside it; the n right-hand
+// sides of the substitutions are split over threads by column range.
+static bool dense_inverse(int n, std::vector<double> &A, double *inv) {
+    std::vector<int> lo(n), hi(n), perm(n);
+    for (int i = 0; i < n; ++i) {
+        int l = i, h = i;
+        for (int j = 0; j < n; ++j)
+            if (A[(size_t)i * n + j] != 0.0) {
+                l = std::min(l, j);
+                h = std::max(h, j);
+            }
+        lo[i] = l;
+        hi[i] = h;
+        perm[i] = i;
+    }
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = 0.0;
+        for (int i = k; i < n; ++i)
+            if (lo[i] <= k) {
+                const double v = std::fabs(A[(size_t)i * n + k]);
+                if (v > best) {
+                    best = v;
+                    p = i;
+                }
+            }
+        if (best == 0.0) return false;
+        if (p != k) {
+            const int a = std::min(lo[k], lo[p]), b = std::max(hi[k], hi[p]);
+            for (int j = a; j <= b; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+            std::swap(lo[k], lo[p]);
+            std::swap(hi[k], hi[p]);
+            std::swap(perm[k], perm[p]);
+        }
+        const double piv = A[(size_t)k * n + k];
+        for (int i = k + 1; i < n; ++i) {
+            if (lo[i] > k) continue;
+            const double l = A[(size_t)i * n + k] / piv;
+            A[(size_t)i * n + k] = l;
+            if (l == 0.0) continue;
+            for (int j = k + 1; j <= hi[k]; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
+            hi[i] = std::max(hi[i], hi[k]);
+        }
+    }
+    // X = A^-1 (row major): X starts as P, then L and U substitutions row by row
+    std::vector<double> X((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) X[(size_t)i * n + perm[i]] = 1.0;
+    auto substitute = [&](int c0, int c1) {
+        for (int i = 0; i < n; ++i) {
+            double *xi = X.data() + (size_t)i * n;
+            for (int k = lo[i]; k < i; ++k) {
+                const double l = A[(size_t)i * n + k];
+                if (l == 0.0) continue;
+                const double *xk = X.data() + (size_t)k * n;
+                for (int j = c0; j < c1; ++j) xi[j] -= l * xk[j];
+            }
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double *xi = X.data() + (size_t)i * n;
+            for (int k = i + 1; k <= hi[i]; ++k) {
+                const double u = A[(size_t)i * n + k];
+                if (u == 0.0) continue;
+                const double *xk = X.data() + (size_t)k * n;
+                for (int j = c0; j < c1; ++j) xi[j] -= u * xk[j];
+            }
+            const double d = 1.0 / A[(size_t)i * n + i];
+            for (int j = c0; j < c1; ++j) xi[j] *= d;
+        }
+    };
+    int nt = 1;
+    if (n >= 512) nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    if (nt == 1) {
+        substitute(0, n);
+    } else {
+        std::vector<std::thread> pool;
+        const int chunk = (n + nt - 1) / nt;
+        for (int t = 0; t < nt; ++t) {
+            const int c0 = t * chunk, c1 = std::min(n, c0 + chunk);
+            if (c0 < c1) pool.emplace_back(substitute, c0, c1);
+        }
+        for (std::thread &th : pool) th.join();
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) inv[(size_t)j * n + i] = X[(size_t)i * n + j];
+    return true;
+}
+
 // Per-mode inverses for a mesh with >= 2 coarse axes: after the fine axes are diagonalised, mode m
 // couples only the coarse points through (Kronecker sum of the coarse-axis operators) + sigma_m I,
 // sigma_m = sum of the fine-axis eigenvalues of the mode.
@@ -208,8 +298,7 @@ static bool build_dense_inverse(Plan &p, unsigned mask) {
         }
         cs *= e;
     }
-    std::vector<double> A((size_t)B * B), col(B);
-    std::vector<int> piv;
+    std::vector<double> A((size_t)B * B);
     for (long long mode = 0; mode < m.nmodes; ++mode) {
         double sigma = 0.0;
         long long rem = mode;
@@ -220,14 +309,7 @@ static bool build_dense_inverse(Plan &p, unsigned mask) {
         }
         A = Kc;
         for (int i = 0; i < B; ++i) A[(size_t)i * B + i] += sigma;
-        if (!lu_factor(B, A, piv)) return false;
-        double *inv = out.data() + (size_t)mode * B * B;
-        for (int j = 0; j < B; ++j) {
-            std::fill(col.begin(), col.end(), 0.0);
-            col[j] = 1.0;
-            lu_solve(B, A, piv, col.data());
-            for (int i = 0; i < B; ++i) inv[(size_t)j * B + i] = col[i];  // column j
-        }
+        if (!dense_inverse(B, A, out.data() + (size_t)mode * B * B)) return false;
     }
     return true;
 }
