@@ -136,7 +136,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.C[q] = p.ws.Y[1u << ks[q]];
         }
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
-        launch_gemm(j, p.stream);
+        if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
     if (d == 3) {
@@ -153,7 +153,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.C[q] = p.ws.X[1u << ks[q]];
         }
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
-        launch_gemm(j, p.stream);
+        if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
     // line elimination along the coarse axis: d = 2 on Y (scratch X), d = 3 on X (scratch Y)
@@ -193,7 +193,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.C[q] = p.ws.Y[1u << ks[q]];
         }
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
-        launch_gemm(j, p.stream);
+        if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
     {
@@ -212,7 +212,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.C[q] = out[ks[q]];
         }
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
-        launch_gemm(j, p.stream);
+        if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
     return ASDSM_OK;
@@ -245,7 +245,7 @@ int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, in
         j.C[0] = p.ws.Y[mask];
         j.accum = 0;
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
-        launch_gemm(j, p.stream);
+        if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
     {
@@ -260,7 +260,7 @@ int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, in
         j.C[0] = out;
         j.accum = accum;
         PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
-        launch_gemm(j, p.stream);
+        if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
     return ASDSM_OK;

@@ -14,111 +14,137 @@
 namespace asdsm {
 
 // ---------------------------------------------------------------------------------------------
-// Batched FP64 GEMM on MFMA, block tile 32 x 32 (8 waves, see below).
-// The A (32 x 128) and B (128 x 32) panels are staged in LDS with fully coalesced loads (a wave
-// reads 64 consecutive doubles along the contiguous index of the operand); with K <= 128 (every
-// mode transform up to N_f = 127) all loads of a block are in flight together before its single
-// barrier, which matters because the operands were just written by the previous kernel and come
-// from the Infinity Cache.  Consecutive block ids go to consecutive XCDs; blocks are numbered so
-// that each XCD takes one contiguous range of tiles (tiles sharing an operand panel reuse its L2).
+// Batched FP64 GEMM on MFMA (v_mfma_f64_16x16x4f64) for the mode transforms.  Block = 4 waves, tile
+// TM x TN, each wave one (TM/2) x (TN/2) quadrant of (TM/32) x (TN/32) MFMA tiles with independent
+// accumulators.  K runs in chunks of KC staged in two LDS buffers: while the waves multiply chunk c,
+// the loads of chunk c+1 are already in flight in registers, and one barrier per chunk separates
+// the two buffers' uses.  Panels are loaded along the contiguous index of each operand (A is k-fast
+// in every transform; B is k-fast or n-fast, template BKF).  Consecutive block ids go to consecutive
+// XCDs; block b takes tile (b % 8) * per + b / 8 of the (z, tile y, tile x) order, so each XCD owns
+// one contiguous range of tiles (tiles sharing an operand panel reuse its L2) and every XCD gets
+// the same number of tiles.
 // Operand layout of v_mfma_f64_16x16x4f64 (lane l, 0..63):
 //   A: row l%16, k l/16;  B: k l/16, col l%16;  D[v]: row l/16 + 4v, col l%16.
 // ---------------------------------------------------------------------------------------------
-constexpr int GKC = 128;  // K chunk
-
-// Block = 8 waves: waves (wm, wn, kh) compute the 16 x 16 tile (wm, wn) over the K half kh of the
-// staged chunk with two interleaved accumulators (dependent MFMA chains of 8 instead of 32: a
-// dependent FP64 MFMA costs ~190 cycles, so chain length, not MFMA throughput, bounds these small
-// GEMMs); the two K halves are summed through LDS.  One K chunk of 128 covers N_f <= 127, so a
-// block issues all its panel loads before a single barrier.
-__global__ __launch_bounds__(512) void k_gemm_f64(GemmJob job) {
+template <int TM, int TN, int KC, bool BKF>
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     if (job.gate && *job.gate) return;
-    __shared__ double sA[32][GKC + 1];
-    __shared__ double sB[GKC][32 + 1];
-    // block id -> tile: block b runs on XCD b % 8, which takes the contiguous tile range
-    // [per * (b % 8), per * (b % 8 + 1)) of the (z, tile y, tile x) order, tile x fastest; tiles that
-    // share an operand panel thus share that XCD's L2, and every XCD gets the same number of tiles.
-    const int tx = (job.N + 31) / 32, ty = (job.M + 31) / 32;
+    constexpr int MI = TM / 32, NI = TN / 32;            // MFMA tiles per wave along m and n
+    constexpr int LA = TM * KC / 256, LB = KC * TN / 256;  // panel elements per thread
+    __shared__ double sA[2][TM][KC + 1];
+    __shared__ double sB[2][KC][TN + 1];
+    const int tx = (job.N + TN - 1) / TN, ty = (job.M + TM - 1) / TM;
     const int per_z = tx * ty;
     const int total = per_z * job.nbox * job.nbatch;
     const int per = (total + 7) / 8;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if ((blockIdx.x >> 3) >= per || tile >= total) return;  // padding (block-uniform)
+    if ((int)(blockIdx.x >> 3) >= per || tile >= total) return;  // padding (block-uniform)
     const int z = tile / per_z;
     const int rem = tile - z * per_z;
-    const int by = rem / tx;
-    const int bx = rem - by * tx;
-    const int box = z / job.nbatch;
-    const int bat = z - box * job.nbatch;
+    const int by = rem / tx, bx = rem - by * tx;
+    const int box = z / job.nbatch, bat = z - box * job.nbatch;
     const double *__restrict__ A = job.A[box] + (long long)bat * job.sAb;
     const double *__restrict__ B = job.B[box] + (long long)bat * job.sBb;
-    const int m0 = by * 32, n0 = bx * 32;
+    const int m0 = by * TM, n0 = bx * TN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wm = w & 1, wn = (w >> 1) & 1, kh = w >> 2;
-    // Panel element e = t + 512 j, j = 0..7.  Contiguous-k operands: row (t>>7) + 4j, k = t & 127;
-    // otherwise k = (t>>5) + 16j, row = t & 31.  Offsets are 32-bit and advance by a constant per j.
-    const int sAi = (int)job.sAi, sAk = (int)job.sAk, sBk = (int)job.sBk, sBn = (int)job.sBn;
-    const bool a_kfast = (sAk == 1);
-    const bool b_kfast = (sBk == 1);
-    const int ai0 = a_kfast ? (t >> 7) : (t & 31), ak0 = a_kfast ? (t & 127) : (t >> 5);
-    const int adi = a_kfast ? 4 : 0, adk = a_kfast ? 0 : 16;
-    const int bn0 = b_kfast ? (t >> 7) : (t & 31), bk0 = b_kfast ? (t & 127) : (t >> 5);
-    const int bdn = b_kfast ? 4 : 0, bdk = b_kfast ? 0 : 16;
-    const int astep = adi * sAi + adk * sAk, bstep = bdk * sBk + bdn * sBn;
-    double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < job.K; k0 += GKC) {
-        int ao = (m0 + ai0) * sAi + (k0 + ak0) * sAk;
-        int bo = (k0 + bk0) * sBk + (n0 + bn0) * sBn;
+    const int wm = w & 1, wn = w >> 1;
+    const int sAi = (int)job.sAi, sBk = (int)job.sBk, sBn = (int)job.sBn;
+    // panel element j of this thread: A row t/KC + (256/KC) j, k t%KC; B (k-fast) col
+    // t/KC + (256/KC) j, k t%KC; B (n-fast) k t/TN + (256/TN) j, col t%TN
+    const int ar = t / KC, ak = t % KC;
+    const int bn0 = BKF ? (t / KC) : (t % TN), bk0 = BKF ? (t % KC) : (t / TN);
+    double ra[LA], rb[LB];
+    const int nch = (job.K + KC - 1) / KC;
+    auto gload = [&](int c) {
+        const int k0 = c * KC;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int ii = ai0 + adi * j, kk = ak0 + adk * j;
-            sA[ii][kk] = (m0 + ii < job.M && k0 + kk < job.K) ? A[ao] : 0.0;
-            const int nn = bn0 + bdn * j, kb = bk0 + bdk * j;
-            sB[kb][nn] = (n0 + nn < job.N && k0 + kb < job.K) ? B[bo] : 0.0;
-            ao += astep;
-            bo += bstep;
+        for (int j = 0; j < LA; ++j) {
+            const int row = m0 + ar + (256 / KC) * j, k = k0 + ak;
+            ra[j] = (row < job.M && k < job.K) ? A[row * sAi + k] : 0.0;
         }
-        __syncthreads();
-        const int kbeg = kh * (GKC / 2);
 #pragma unroll
-        for (int kk = 0; kk < GKC / 2; kk += 8) {
-            const double a0 = sA[wm * 16 + (lane & 15)][kbeg + kk + (lane >> 4)];
-            const double b0 = sB[kbeg + kk + (lane >> 4)][wn * 16 + (lane & 15)];
-            const double a1 = sA[wm * 16 + (lane & 15)][kbeg + kk + 4 + (lane >> 4)];
-            const double b1 = sB[kbeg + kk + 4 + (lane >> 4)][wn * 16 + (lane & 15)];
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+        for (int j = 0; j < LB; ++j) {
+            const int n = n0 + (BKF ? bn0 + (256 / KC) * j : bn0);
+            const int kb = k0 + (BKF ? bk0 : bk0 + (256 / TN) * j);
+            rb[j] = (n < job.N && kb < job.K) ? B[kb * sBk + n * sBn] : 0.0;
         }
-        __syncthreads();
-    }
-    // sum the two K halves: waves with kh = 1 hand their partial tile over through LDS
-    double *red = &sA[0][0];  // 4 tiles x 256 values, reusing the A panel
-    const int wt = wm + 2 * wn;
-    if (kh == 1) {
+    };
+    auto lstore = [&](int buf) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) red[wt * 256 + v * 64 + lane] = acc0[v] + acc1[v];
-    }
+        for (int j = 0; j < LA; ++j) sA[buf][ar + (256 / KC) * j][ak] = ra[j];
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            if (BKF)
+                sB[buf][bk0][bn0 + (256 / KC) * j] = rb[j];
+            else
+                sB[buf][bk0 + (256 / TN) * j][bn0] = rb[j];
+        }
+    };
+    double4_t acc[MI][NI];
+#pragma unroll
+    for (int a = 0; a < MI; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b) acc[a][b] = {0.0, 0.0, 0.0, 0.0};
+    gload(0);
+    lstore(0);
     __syncthreads();
-    if (kh == 1) return;
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) gload(c + 1);
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            const int kq = kk + (lane >> 4);
+            double av[MI], bv[NI];
+#pragma unroll
+            for (int a = 0; a < MI; ++a) av[a] = sA[buf][wm * (TM / 2) + a * 16 + (lane & 15)][kq];
+#pragma unroll
+            for (int b = 0; b < NI; ++b) bv[b] = sB[buf][kq][wn * (TN / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < MI; ++a)
+#pragma unroll
+                for (int b = 0; b < NI; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        if (c + 1 < nch) lstore(buf ^ 1);
+        __syncthreads();
+    }
     double *__restrict__ C = job.C[box] + (long long)bat * job.sCb;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int gi = m0 + wm * 16 + (lane >> 4) + 4 * v;
-        const int gn = n0 + wn * 16 + (lane & 15);
-        const double val = (acc0[v] + acc1[v]) + red[wt * 256 + v * 64 + lane];
-        if (gi < job.M && gn < job.N) {
-            double *c = C + (long long)gi * job.sCi + (long long)gn * job.sCn;
-            *c = job.accum ? *c + val : val;
-        }
-    }
+    for (int a = 0; a < MI; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = m0 + wm * (TM / 2) + a * 16 + (lane >> 4) + 4 * v;
+                const int gn = n0 + wn * (TN / 2) + b * 16 + (lane & 15);
+                if (gi < job.M && gn < job.N) {
+                    double *cp = C + (long long)gi * job.sCi + (long long)gn * job.sCn;
+                    *cp = job.accum ? *cp + acc[a][b][v] : acc[a][b][v];
+                }
+            }
 }
 
-void launch_gemm(const GemmJob &job, hipStream_t st) {
-    // 1D grid of 8 * ceil(tiles / 8) blocks (see the tile order in k_gemm_f64)
-    const long long tx = (job.N + 31) / 32, ty = (job.M + 31) / 32;
+template <int TM, int TN, int KC>
+static void launch_gemm_tile(const GemmJob &job, hipStream_t st) {
+    const long long tx = (job.N + TN - 1) / TN, ty = (job.M + TM - 1) / TM;
     const long long total = tx * ty * job.nbox * job.nbatch;
-    const long long blocks = 8 * ((total + 7) / 8);
-    ASDSM_LAUNCH(k_gemm_f64, dim3((unsigned)blocks), dim3(512), 0, st, job);
+    const dim3 grid((unsigned)(8 * ((total + 7) / 8)));
+    if (job.sBk == 1)
+        ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, true>), grid, dim3(256), 0, st, job);
+    else
+        ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, false>), grid, dim3(256), 0, st, job);
+}
+
+bool launch_gemm(const GemmJob &job, hipStream_t st) {
+    // operand layouts of the mode transforms: A k-fast, B k-fast or n-fast
+    if (job.sAk != 1 || (job.sBk != 1 && job.sBn != 1)) return false;
+    // 64 x 64 tiles once there are enough of them to fill the chip twice, else 32 x 32
+    const long long t64 = ((job.N + 63) / 64) * ((job.M + 63) / 64) * job.nbox * job.nbatch;
+    if (t64 >= 512)
+        launch_gemm_tile<64, 64, 16>(job, st);
+    else
+        launch_gemm_tile<32, 32, 32>(job, st);
+    return true;
 }
 
 // ---------------------------------------------------------------------------------------------

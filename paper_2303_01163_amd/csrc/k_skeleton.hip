@@ -184,6 +184,67 @@ __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
     }
 }
 
+// d = 3 merge by tiles: block (64 values of i_a x 4 values of i_b, coarse plane c_k, mesh k), one
+// point per thread.  The Boolean-sum correction of the plane is two rank-N_c products,
+// Sp R_ck + B_ck Sp^T; each thread keeps its row of Sp and of B_ck in registers and reads the R_ck
+// column and the Sp row of its i_b from LDS (one value for the whole wave).  Cross points take the
+// value of crosspoint_value as in k_merge.
+template <int NC>
+__global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
+    if (a.gate && *a.gate) return;
+    __shared__ double sR[NC][4];
+    __shared__ double sS[4][NC];
+    const int Nf = g.Nf, n = g.n;
+    const int k = blockIdx.z, ck = blockIdx.y;
+    const int xtn = (Nf + 63) / 64;
+    const int ia0 = (blockIdx.x % xtn) * 64, ib0 = (blockIdx.x / xtn) * 4;
+    int fa, fb;
+    fine_axes_of(k, 3, fa, fb);
+    const unsigned mk = 1u << k;
+    const long long nA = (long long)NC * NC * Nf;
+    const double *__restrict__ B = a.lines[k] + nA;
+    const double *__restrict__ R = a.lines[k] + 2 * nA;
+    const double *__restrict__ Sp = a.Sp;
+    const int t = threadIdx.x, tx = t & 63, j = t >> 6;
+    if (t < NC * 4) {
+        const int c = t >> 2, jj = t & 3;
+        const int ib = min(ib0 + jj, Nf - 1);
+        sR[c][jj] = R[((long long)ck * NC + c) * Nf + ib];
+        sS[jj][c] = Sp[(long long)ib * NC + c];
+    }
+    const int ia = ia0 + tx, ib = ib0 + j;
+    const int iac = min(ia, Nf - 1), ibc = min(ib, Nf - 1);
+    const long long idx = (long long)iac + (long long)Nf * ibc + (long long)Nf * Nf * ck;
+    const double *__restrict__ X = a.res[mk];
+    const double x = X[idx];
+    double spa[NC], brow[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        spa[c] = Sp[(long long)iac * NC + c];
+        brow[c] = B[((long long)ck * Nf + iac) * NC + c];
+    }
+    __syncthreads();
+    if (ia >= Nf || ib >= Nf) return;
+    int i[kMaxD] = {0, 0, 0};
+    i[fa] = ia;
+    i[fb] = ib;
+    i[k] = (ck + 1) * n - 1;
+    const unsigned S = coarse_set(i, 3, n);
+    double v;
+    if (S != mk) {
+        v = crosspoint_value(a, g, i, S);
+    } else {
+        const double scale_k = (a.mode == 0) ? 1.0 : a.scal[kScalInvNorm + k];
+        double c1 = 0.0, c2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) c1 += spa[c] * sR[c][j];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) c2 += sS[j][c] * brow[c];
+        v = scale_k * x + (c1 + c2);
+    }
+    a.skel[k][idx] = v;
+}
+
 static SkelArgs skel_args(const Plan &p, int mode, const double *const *res) {
     SkelArgs a;
     for (unsigned s = 0; s < kMaxMeshes; ++s) {
@@ -219,6 +280,17 @@ void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipSt
 
 void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t st) {
     SkelArgs a = skel_args(p, mode, res);
+    if (p.d == 3 && (p.Nc == 7 || p.Nc == 15 || p.Nc == 31)) {
+        const unsigned tiles = (unsigned)(((p.Nf + 63) / 64) * ((p.Nf + 3) / 4));
+        const dim3 grid(tiles, (unsigned)p.Nc, 3);
+        if (p.Nc == 7)
+            ASDSM_LAUNCH((k_merge3<7>), grid, dim3(256), 0, st, p.geo, a);
+        else if (p.Nc == 15)
+            ASDSM_LAUNCH((k_merge3<15>), grid, dim3(256), 0, st, p.geo, a);
+        else
+            ASDSM_LAUNCH((k_merge3<31>), grid, dim3(256), 0, st, p.geo, a);
+        return;
+    }
     long long blocks = (p.mesh[1].size + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     ASDSM_LAUNCH(k_merge, dim3((unsigned)blocks, p.d, 1), dim3(256), 0, st, p.geo, a);

@@ -166,6 +166,163 @@ __global__ __launch_bounds__(256) void k_dots(Geo g, const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------------------------
+// d = 3 versions of the two passes: z-marching column tiles.  A block owns a tile of 64 (x_1) x
+// ROWS (x_2) columns and a chunk of ZC planes along x_3; tiles are ordered (z chunk, x_2 tile, x_1
+// tile) and each XCD takes one contiguous range of them, so neighbouring tiles share an L2.  Every
+// value is read from memory once per tile: the x_3 neighbours stay in registers as the tile marches
+// along x_3; the current plane (with a one-point halo loaded by the first 128 + 2 ROWS threads)
+// sits in LDS for the x_1 / x_2 neighbours; the next plane's loads are issued one step ahead.
+// Neighbours outside the domain enter as zeros (the Dirichlet data live in b).
+// ---------------------------------------------------------------------------------------------
+struct Tile3 {
+    int xtn, ytn, zcn;
+};
+
+__device__ __forceinline__ bool tile3_of(const Tile3 &t, int &xt, int &yt, int &zc) {
+    const int total = t.xtn * t.ytn * t.zcn;
+    const int per = (total + 7) / 8;
+    const int q = blockIdx.x >> 3;
+    const int tile = (blockIdx.x & 7) * per + q;
+    if (q >= per || tile >= total) return false;
+    xt = tile % t.xtn;
+    yt = (tile / t.xtn) % t.ytn;
+    zc = tile / (t.xtn * t.ytn);
+    return true;
+}
+
+template <int ROWS, int ZC>
+__global__ __launch_bounds__(64 * ROWS) void k_update_residual3(
+    Geo g, Tile3 tl, const double *__restrict__ uin, const double *__restrict__ e,
+    const double *__restrict__ scal, const double *__restrict__ b, double *__restrict__ uout,
+    double *__restrict__ r, BoxPtrs boxes, double *partials, const int *gate) {
+    if (gate && *gate) return;
+    __shared__ double pl[2][ROWS + 2][66];
+    const int Nf = g.Nf, n = g.n;
+    double acc = 0.0;
+    int xt, yt, zc;
+    if (tile3_of(tl, xt, yt, zc)) {
+        const double s = e ? scal[kScalStep] : 0.0;
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const int i0 = xt * 64 + tx, i1 = yt * ROWS + ty;
+        const bool act = i0 < Nf && i1 < Nf;
+        const int sy = Nf, sz = Nf * Nf;
+        const int base = min(i0, Nf - 1) + sy * min(i1, Nf - 1);
+        const int z0 = zc * ZC, z1 = min(Nf, z0 + ZC);
+        // halo of the plane tile: row below, row above, column left, column right
+        const int h = threadIdx.x;
+        int hx = -1, hy = -1, hlx = 0, hly = 0;
+        if (h < 64) {
+            hx = xt * 64 + h; hy = yt * ROWS - 1; hlx = h + 1; hly = 0;
+        } else if (h < 128) {
+            hx = xt * 64 + h - 64; hy = yt * ROWS + ROWS; hlx = h - 63; hly = ROWS + 1;
+        } else if (h < 128 + ROWS) {
+            hx = xt * 64 - 1; hy = yt * ROWS + (h - 128); hlx = 0; hly = h - 127;
+        } else if (h < 128 + 2 * ROWS) {
+            hx = xt * 64 + 64; hy = yt * ROWS + (h - 128 - ROWS); hlx = 65; hly = h - 127 - ROWS;
+        }
+        const bool hload = h < 128 + 2 * ROWS;
+        const bool hval = hx >= 0 && hx < Nf && hy >= 0 && hy < Nf;
+        const int hbase = hval ? hx + sy * hy : 0;
+        auto ldu = [&](bool ok, int q) -> double { return ok ? uin[q] : 0.0; };
+        auto lde = [&](bool ok, int q) -> double { return (ok && e) ? e[q] : 0.0; };
+        double vprev = 0.0, vcur = 0.0, hcur = 0.0;
+        if (act && z0 > 0) vprev = ldu(true, base + (z0 - 1) * sz) + s * lde(true, base + (z0 - 1) * sz);
+        if (act) vcur = ldu(true, base + z0 * sz) + s * lde(true, base + z0 * sz);
+        if (hval) hcur = ldu(true, hbase + z0 * sz) + s * lde(true, hbase + z0 * sz);
+        const bool ok1 = act && z0 + 1 < Nf, hok1 = hval && z0 + 1 < z1;
+        double u1 = ldu(ok1, base + (z0 + 1) * sz), e1 = lde(ok1, base + (z0 + 1) * sz);
+        double hu1 = ldu(hok1, hbase + (z0 + 1) * sz), he1 = lde(hok1, hbase + (z0 + 1) * sz);
+        double b1 = act ? b[base + z0 * sz] : 0.0;
+        int buf = 0;
+        pl[0][ty + 1][tx + 1] = vcur;
+        if (hload) pl[0][hly][hlx] = hcur;
+        __syncthreads();
+        const bool g0 = on_coarse(i0, n), g1 = on_coarse(i1, n);
+        const int k0 = coarse_of(i0, n), k1 = coarse_of(i1, n);
+        const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
+        for (int z = z0; z < z1; ++z) {
+            const int p = base + z * sz;
+            const bool ok2 = act && z + 2 < Nf, hok2 = hval && z + 2 < z1;
+            const double u2 = ldu(ok2, p + 2 * sz), e2 = lde(ok2, p + 2 * sz);
+            const double hu2 = ldu(hok2, hbase + (z + 2) * sz), he2 = lde(hok2, hbase + (z + 2) * sz);
+            const double b2 = (act && z + 1 < z1) ? b[p + sz] : 0.0;
+            const double vnext = u1 + s * e1;
+            const double hnext = hu1 + s * he1;
+            double au = bsum * vcur;
+            au += g.fine[0].a * pl[buf][ty + 1][tx];
+            au += g.fine[0].c * pl[buf][ty + 1][tx + 2];
+            au += g.fine[1].a * pl[buf][ty][tx + 1];
+            au += g.fine[1].c * pl[buf][ty + 2][tx + 1];
+            au += g.fine[2].a * vprev;
+            au += g.fine[2].c * vnext;
+            const double rr = b1 - au;
+            if (act) {
+                r[p] = rr;
+                if (e) uout[p] = vcur;
+                acc += rr * rr;
+                // gather onto the anisotropic submeshes (canonical layouts)
+                if (g0) boxes.p[0][i1 + sy * z + sz * k0] = rr;
+                if (g1) boxes.p[1][i0 + sy * z + sz * k1] = rr;
+                if (on_coarse(z, n)) boxes.p[2][i0 + sy * i1 + sz * coarse_of(z, n)] = rr;
+            }
+            vprev = vcur;
+            vcur = vnext;
+            u1 = u2; e1 = e2; hu1 = hu2; he1 = he2; b1 = b2;
+            buf ^= 1;
+            pl[buf][ty + 1][tx + 1] = vcur;
+            if (hload) pl[buf][hly][hlx] = hnext;
+            __syncthreads();
+        }
+    }
+    double vals[1] = {acc};
+    block_partials<64 * ROWS, 1>(vals, partials, blockIdx.x);
+}
+
+template <int ZC>
+__global__ __launch_bounds__(256) void k_dots3(Geo g, Tile3 tl, const double *__restrict__ e,
+                                               const double *__restrict__ r, double *partials,
+                                               const int *gate) {
+    if (gate && *gate) return;
+    const int Nf = g.Nf;
+    double rq = 0.0, qq = 0.0;
+    int xt, yt, zc;
+    if (tile3_of(tl, xt, yt, zc)) {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const int i0 = xt * 64 + tx, i1 = yt * 4 + ty;
+        if (i0 < Nf && i1 < Nf) {
+            const int sy = Nf, sz = Nf * Nf;
+            // neighbours outside the domain: zero coefficient, in-bounds address
+            const double ax = i0 > 0 ? g.fine[0].a : 0.0, cx = i0 < Nf - 1 ? g.fine[0].c : 0.0;
+            const double ay = i1 > 0 ? g.fine[1].a : 0.0, cy = i1 < Nf - 1 ? g.fine[1].c : 0.0;
+            const int oxm = i0 > 0 ? -1 : 0, oxp = i0 < Nf - 1 ? 1 : 0;
+            const int oym = i1 > 0 ? -sy : 0, oyp = i1 < Nf - 1 ? sy : 0;
+            const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
+            const int z0 = zc * ZC, z1 = min(Nf, z0 + ZC);
+            const int base = i0 + sy * i1;
+            double vprev = z0 > 0 ? e[base + (z0 - 1) * sz] : 0.0;
+            double vcur = e[base + z0 * sz];
+            for (int z = z0; z < z1; ++z) {
+                const int p = base + z * sz;
+                const double vnext = (z + 1 < Nf) ? e[p + sz] : 0.0;
+                double q = bsum * vcur;
+                q += ax * e[p + oxm];
+                q += cx * e[p + oxp];
+                q += ay * e[p + oym];
+                q += cy * e[p + oyp];
+                q += g.fine[2].a * vprev;
+                q += g.fine[2].c * vnext;
+                rq += r[p] * q;
+                qq += q * q;
+                vprev = vcur;
+                vcur = vnext;
+            }
+        }
+    }
+    double vals[2] = {rq, qq};
+    block_partials<256, 2>(vals, partials, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Totals of the per-block partial sums, in block order (deterministic), and what derives from them.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblk,
@@ -288,29 +445,60 @@ void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf,
     if (with_norm) launch_finalize(p, (int)blocks, kFinBnorm, 1, st);
 }
 
+static Tile3 tile3(const Geo &g, int rows, int zc, int &blocks) {
+    Tile3 t;
+    t.xtn = (g.Nf + 63) / 64;
+    t.ytn = (g.Nf + rows - 1) / rows;
+    t.zcn = (g.Nf + zc - 1) / zc;
+    const long long total = (long long)t.xtn * t.ytn * t.zcn;
+    blocks = (int)(8 * ((total + 7) / 8));
+    return t;
+}
+
 void launch_update_residual(const Plan &p, const double *uin, const double *e, double *uout,
                             double *const *gather, int fin_mode, hipStream_t st) {
-    dim3 grid;
-    stencil_grid(p.geo, grid);
     BoxPtrs bx;
     for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? gather[1u << k] : nullptr;
-    if (p.d == 2)
+    if (p.d == 2) {
+        dim3 grid;
+        stencil_grid(p.geo, grid);
         ASDSM_LAUNCH((k_update_residual<2>), grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
-                           p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
-    else
-        ASDSM_LAUNCH((k_update_residual<3>), grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
-                           p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
-    launch_finalize(p, (int)(grid.x * grid.y), fin_mode, 1, st);
+                     p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
+        launch_finalize(p, (int)(grid.x * grid.y), fin_mode, 1, st);
+        return;
+    }
+    int blocks = 0;
+    if (p.Nf >= 255) {
+        const Tile3 t = tile3(p.geo, 16, 16, blocks);
+        ASDSM_LAUNCH((k_update_residual3<16, 16>), dim3(blocks), dim3(1024), 0, st, p.geo, t, uin, e,
+                     p.ws.scal, p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
+    } else {
+        const Tile3 t = tile3(p.geo, 8, 8, blocks);
+        ASDSM_LAUNCH((k_update_residual3<8, 8>), dim3(blocks), dim3(512), 0, st, p.geo, t, uin, e,
+                     p.ws.scal, p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
+    }
+    launch_finalize(p, blocks, fin_mode, 1, st);
 }
 
 void launch_dots(const Plan &p, hipStream_t st) {
-    dim3 grid;
-    stencil_grid(p.geo, grid);
-    if (p.d == 2)
+    if (p.d == 2) {
+        dim3 grid;
+        stencil_grid(p.geo, grid);
         ASDSM_LAUNCH((k_dots<2>), grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
-    else
-        ASDSM_LAUNCH((k_dots<3>), grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
-    launch_finalize(p, (int)(grid.x * grid.y), kFinDots, 1, st);
+        launch_finalize(p, (int)(grid.x * grid.y), kFinDots, 1, st);
+        return;
+    }
+    int blocks = 0;
+    Tile3 t = tile3(p.geo, 4, 16, blocks);
+    if (blocks <= p.max_blocks) {
+        ASDSM_LAUNCH((k_dots3<16>), dim3(blocks), dim3(256), 0, st, p.geo, t, p.ws.e, p.ws.r,
+                     p.ws.partials, p.gate);
+    } else {  // N_f = 1023: longer chunks keep the partial sums within the workspace
+        t = tile3(p.geo, 4, 64, blocks);
+        ASDSM_LAUNCH((k_dots3<64>), dim3(blocks), dim3(256), 0, st, p.geo, t, p.ws.e, p.ws.r,
+                     p.ws.partials, p.gate);
+    }
+    launch_finalize(p, blocks, kFinDots, 1, st);
 }
 
 }  // namespace asdsm

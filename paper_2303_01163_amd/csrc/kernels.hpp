@@ -70,7 +70,7 @@ void launch_update_residual(const Plan &p, const double *uin, const double *e, d
 void launch_dots(const Plan &p, hipStream_t st);
 int stencil_blocks(const Geo &g);
 
-void launch_gemm(const GemmJob &job, hipStream_t st);
+bool launch_gemm(const GemmJob &job, hipStream_t st);  // false: unsupported operand layout
 void launch_line(const LineJob &job, hipStream_t st);
 void launch_dense_modes(long long nmodes, int B, const double *inv, const double *in, double *out,
                         int accum, hipStream_t st);
