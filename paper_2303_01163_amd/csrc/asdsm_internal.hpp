@@ -136,6 +136,10 @@ struct Plan {
     size_t dtab_bytes = 0;
     double *dW[kMaxD] = {}, *dV[kMaxD] = {}, *dmu[kMaxD] = {};
     double *dWh[kMaxD] = {}, *dVh[kMaxD] = {}, *dmuh[kMaxD] = {};
+    // hole line elimination factors (d = 3): for the mode pair q = m0 + nh m1 of the two transformed
+    // hole axes, step c: hole_inv[c nh^2 + q] = 1/pivot_c, hole_cp[...] = super / pivot_c
+    std::vector<double> hole_inv, hole_cp;
+    double *dhole_inv = nullptr, *dhole_cp = nullptr;
     double *dSp = nullptr;
     double *ddense[kMaxMeshes] = {};
 

@@ -29,36 +29,88 @@ struct SkelArgs {
     const int *gate;
 };
 
-__device__ __forceinline__ double crosspoint_value(const SkelArgs &a, const Geo &g, const int *i,
-                                                  unsigned S) {
+// A fine point as three coordinates (x2 = 0 for d = 2).  The helpers below index only with
+// compile-time constants or selects, so nothing lands in scratch memory.
+struct Pt {
+    int x0, x1, x2;
+};
+
+// Point of anisotropic mesh M_k: coordinate c on the coarse axis k, u and v on its fine axes
+// (increasing order).
+__device__ __forceinline__ Pt mesh_pt(int k, int d, int u, int v, int c) {
+    if (d == 2) return (k == 0) ? Pt{c, u, 0} : Pt{u, c, 0};
+    if (k == 0) return Pt{c, u, v};
+    if (k == 1) return Pt{u, c, v};
+    return Pt{u, v, c};
+}
+
+__device__ __forceinline__ unsigned coarse_set(const Pt &p, int d, int n) {
+    unsigned S = 0;
+    if (on_coarse(p.x0, n)) S |= 1u;
+    if (on_coarse(p.x1, n)) S |= 2u;
+    if (d == 3 && on_coarse(p.x2, n)) S |= 4u;
+    return S;
+}
+
+// Offset of a point of M_j (coarse axis j) in its canonical layout (fine axes a < b, then j).
+__device__ __forceinline__ long long aniso_offset(const Geo &g, int j, const Pt &p) {
+    const long long Nf = g.Nf;
+    if (g.d == 2) return (j == 0) ? p.x1 + Nf * coarse_of(p.x0, g.n) : p.x0 + Nf * coarse_of(p.x1, g.n);
+    if (j == 0) return p.x1 + Nf * (p.x2 + Nf * coarse_of(p.x0, g.n));
+    if (j == 1) return p.x0 + Nf * (p.x2 + Nf * coarse_of(p.x1, g.n));
+    return p.x0 + Nf * (p.x1 + Nf * coarse_of(p.x2, g.n));
+}
+
+// Offset of a point of the intersection mesh M_S (|S| >= 2) in its canonical layout: the fine axis
+// (if any) first, then the coarse axes in increasing order.
+__device__ __forceinline__ long long inter_offset(const Geo &g, unsigned S, const Pt &p) {
+    const long long Nf = g.Nf, Nc = g.Nc;
+    const int n = g.n;
+    const long long c0 = coarse_of(p.x0, n), c1 = coarse_of(p.x1, n);
+    if (g.d == 2) return c0 + Nc * c1;
+    const long long c2 = coarse_of(p.x2, n);
+    if (S == 7u) return c0 + Nc * (c1 + Nc * c2);
+    if (S == 6u) return p.x0 + Nf * (c1 + Nc * c2);  // fine x_1
+    if (S == 5u) return p.x1 + Nf * (c0 + Nc * c2);  // fine x_2
+    return p.x2 + Nf * (c0 + Nc * c1);               // S = 3, fine x_3
+}
+
+// Per-launch value of the error-phase choice, read once per thread before the point loop: this
+// step's axis permutation.
+struct XChoice {
+    int p0, p1, p2;
+};
+
+__device__ __forceinline__ XChoice load_choice(const SkelArgs &a, const Geo &g) {
+    XChoice c{0, 1, 2};
+    if (a.mode == 1) {
+        const int *perm = a.perm_table + kMaxD * a.state->it;
+        c.p0 = perm[0];
+        c.p1 = perm[1];
+        c.p2 = (g.d == 3) ? perm[2] : 2;
+    }
+    return c;
+}
+
+__device__ __forceinline__ double crosspoint_value(const SkelArgs &a, const Geo &g, const Pt &p,
+                                                  unsigned S, const XChoice &ch) {
     if (a.mode == 0) {
         double sum = 0.0;
         int cnt = 0;
-        for (int j = 0; j < g.d; ++j)
-            if ((S >> j) & 1u) {
-                const unsigned mj = 1u << j;
-                sum += a.res[mj][canon_offset(a.mesh[mj], i, g.n)];
-                ++cnt;
-            }
-        sum -= a.res[S][canon_offset(a.mesh[S], i, g.n)];
+        if (S & 1u) { sum += a.res[1][aniso_offset(g, 0, p)]; ++cnt; }
+        if (S & 2u) { sum += a.res[2][aniso_offset(g, 1, p)]; ++cnt; }
+        if (S & 4u) { sum += a.res[4][aniso_offset(g, 2, p)]; ++cnt; }
+        const double *rs = (S == 3u) ? a.res[3] : (S == 5u) ? a.res[5] : (S == 6u) ? a.res[6] : a.res[7];
+        sum -= rs[inter_offset(g, S, p)];
         return sum / (double)(cnt - 1);
     }
-    const int *perm = a.perm_table + kMaxD * a.state->it;
-    for (int q = 0; q < g.d; ++q) {
-        const int j = perm[q];
-        if ((S >> j) & 1u) {
-            const unsigned mj = 1u << j;
-            return a.scal[kScalInvNorm + j] * a.res[mj][canon_offset(a.mesh[mj], i, g.n)];
-        }
-    }
-    return 0.0;  // unreachable: S has >= 2 axes
-}
-
-__device__ __forceinline__ unsigned coarse_set(const int *i, int d, int n) {
-    unsigned S = 0;
-    for (int j = 0; j < d; ++j)
-        if (on_coarse(i[j], n)) S |= 1u << j;
-    return S;
+    // the first axis of this step's permutation that contains the point
+    int j = ch.p0;
+    if (!((S >> j) & 1u)) j = ch.p1;
+    if (!((S >> j) & 1u)) j = ch.p2;
+    const double inv = a.scal[kScalInvNorm + j];
+    const double *rj = (j == 0) ? a.res[1] : (j == 1) ? a.res[2] : a.res[4];
+    return inv * rj[aniso_offset(g, j, p)];
 }
 
 __device__ __forceinline__ void fine_axes_of(int k, int d, int &a, int &b) {
@@ -76,6 +128,7 @@ __device__ __forceinline__ void fine_axes_of(int k, int d, int &a, int &b) {
 // d = 3: part A [ck][ca][ib] (Nc*Nc*Nf), part B [ck][ia][cb] (Nc*Nf*Nc), then part R (filled later).
 __global__ __launch_bounds__(256) void k_crosspoints(Geo g, SkelArgs a) {
     if (a.gate && *a.gate) return;
+    const XChoice ch = load_choice(a, g);
     const int k = blockIdx.y;
     const int d = g.d, Nf = g.Nf, Nc = g.Nc, n = g.n;
     int fa, fb;
@@ -84,31 +137,34 @@ __global__ __launch_bounds__(256) void k_crosspoints(Geo g, SkelArgs a) {
     const double scale_k = (a.mode == 0) ? 1.0 : a.scal[kScalInvNorm + k];
     const long long nA = (d == 2) ? (long long)Nc * Nc : (long long)Nc * Nc * Nf;
     const long long total = (d == 2) ? nA : 2 * nA;
+    const double *__restrict__ Xk = (k == 0) ? a.res[1] : (k == 1) ? a.res[2] : a.res[4];
     for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
-        int i[kMaxD] = {0, 0, 0};
+        // the point: fine-axis coordinates (u, v) of mesh k and its coarse plane ck
+        int u, v, ck;
         if (d == 2) {
-            const int ca = (int)(t % Nc), ck = (int)(t / Nc);
-            i[k] = (ck + 1) * n - 1;
-            i[fa] = (ca + 1) * n - 1;
+            const int ca = (int)(t % Nc);
+            ck = (int)(t / Nc);
+            u = (ca + 1) * n - 1;
+            v = 0;
         } else if (t < nA) {
-            const int ib = (int)(t % Nf);
+            v = (int)(t % Nf);
             const int ca = (int)((t / Nf) % Nc);
-            const int ck = (int)(t / ((long long)Nf * Nc));
-            i[k] = (ck + 1) * n - 1;
-            i[fa] = (ca + 1) * n - 1;
-            i[fb] = ib;
+            ck = (int)(t / ((long long)Nf * Nc));
+            u = (ca + 1) * n - 1;
         } else {
-            const long long u = t - nA;
-            const int cb = (int)(u % Nc);
-            const int ia = (int)((u / Nc) % Nf);
-            const int ck = (int)(u / ((long long)Nc * Nf));
-            i[k] = (ck + 1) * n - 1;
-            i[fa] = ia;
-            i[fb] = (cb + 1) * n - 1;
+            const long long w = t - nA;
+            const int cb = (int)(w % Nc);
+            u = (int)((w / Nc) % Nf);
+            ck = (int)(w / ((long long)Nc * Nf));
+            v = (cb + 1) * n - 1;
         }
-        const unsigned S = coarse_set(i, d, n);
-        const double uh = crosspoint_value(a, g, i, S);
-        const double uk = scale_k * a.res[mk][canon_offset(a.mesh[mk], i, n)];
+        const Pt p = mesh_pt(k, d, u, v, (ck + 1) * n - 1);
+        const unsigned S = coarse_set(p, d, n);
+        const double uh = crosspoint_value(a, g, p, S, ch);
+        // canonical offset in M_k: u + Nf (v + Nf ck) (d = 3), u + Nf ck (d = 2)
+        const long long ok = (d == 2) ? (long long)u + (long long)Nf * ck
+                                      : (long long)u + (long long)Nf * (v + (long long)Nf * ck);
+        const double uk = scale_k * Xk[ok];
         a.lines[k][t] = uh - uk;
     }
 }
@@ -137,6 +193,7 @@ __global__ __launch_bounds__(256) void k_lines_residual(Geo g, SkelArgs a) {
 
 __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
     if (a.gate && *a.gate) return;
+    const XChoice ch = load_choice(a, g);
     const int k = blockIdx.y;
     const int d = g.d, Nf = g.Nf, Nc = g.Nc, n = g.n;
     int fa, fb;
@@ -150,22 +207,19 @@ __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
     const double *__restrict__ Sp = a.Sp;
     const long long nA = (long long)Nc * Nc * Nf;
     for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < m.size; idx += (long long)gridDim.x * 256) {
-        int i[kMaxD] = {0, 0, 0};
         const int ia = (int)(idx % Nf);
-        i[fa] = ia;
         int ib = 0, ck;
         if (d == 2) {
             ck = (int)(idx / Nf);
         } else {
             ib = (int)((idx / Nf) % Nf);
             ck = (int)(idx / ((long long)Nf * Nf));
-            i[fb] = ib;
         }
-        i[k] = (ck + 1) * n - 1;
-        const unsigned S = coarse_set(i, d, n);
+        const Pt p = mesh_pt(k, d, ia, ib, (ck + 1) * n - 1);
+        const unsigned S = coarse_set(p, d, n);
         double v;
         if (S != mk) {
-            v = crosspoint_value(a, g, i, S);
+            v = crosspoint_value(a, g, p, S, ch);
         } else if (d == 2) {
             double corr = 0.0;
             for (int ca = 0; ca < Nc; ++ca) corr += Sp[(long long)ia * Nc + ca] * L[(long long)ck * Nc + ca];
@@ -184,65 +238,73 @@ __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
     }
 }
 
-// d = 3 merge by tiles: block (64 values of i_a x 4 values of i_b, coarse plane c_k, mesh k), one
-// point per thread.  The Boolean-sum correction of the plane is two rank-N_c products,
-// Sp R_ck + B_ck Sp^T; each thread keeps its row of Sp and of B_ck in registers and reads the R_ck
-// column and the Sp row of its i_b from LDS (one value for the whole wave).  Cross points take the
-// value of crosspoint_value as in k_merge.
+// d = 3 merge by tiles: block (64 values of i_a x 8 values of i_b, coarse plane c_k, mesh k), two
+// points per thread.  The Boolean-sum correction of the plane is two rank-N_c products,
+// Sp R_ck + B_ck Sp^T: the block stages the Sp and B_ck rows of its i_a range and the R_ck columns
+// and Sp rows of its i_b range in LDS (contiguous loads).  Cross points take the value of
+// crosspoint_value as in k_merge.
 template <int NC>
 __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
     if (a.gate && *a.gate) return;
-    __shared__ double sR[NC][4];
-    __shared__ double sS[4][NC];
+    const XChoice ch = load_choice(a, g);
+    constexpr int RB = 8;
+    __shared__ double sSa[64 * NC], sBa[64 * NC], sR[NC][RB], sSb[RB][NC];
     const int Nf = g.Nf, n = g.n;
     const int k = blockIdx.z, ck = blockIdx.y;
     const int xtn = (Nf + 63) / 64;
-    const int ia0 = (blockIdx.x % xtn) * 64, ib0 = (blockIdx.x / xtn) * 4;
-    int fa, fb;
-    fine_axes_of(k, 3, fa, fb);
+    const int ia0 = (blockIdx.x % xtn) * 64, ib0 = (blockIdx.x / xtn) * RB;
     const unsigned mk = 1u << k;
     const long long nA = (long long)NC * NC * Nf;
-    const double *__restrict__ B = a.lines[k] + nA;
-    const double *__restrict__ R = a.lines[k] + 2 * nA;
+    // per-mesh pointers chosen by selects (a dynamic index into the argument struct would be
+    // copied to scratch memory)
+    const double *lk = (k == 0) ? a.lines[0] : (k == 1) ? a.lines[1] : a.lines[2];
+    double *sk = (k == 0) ? a.skel[0] : (k == 1) ? a.skel[1] : a.skel[2];
+    const double *__restrict__ B = lk + nA;
+    const double *__restrict__ R = lk + 2 * nA;
     const double *__restrict__ Sp = a.Sp;
-    const int t = threadIdx.x, tx = t & 63, j = t >> 6;
-    if (t < NC * 4) {
-        const int c = t >> 2, jj = t & 3;
+    const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
+    const int nrow = min(64, Nf - ia0);  // i_a rows of this tile
+    for (int q = t; q < nrow * NC; q += 256) {
+        sSa[q] = Sp[(long long)ia0 * NC + q];
+        sBa[q] = B[((long long)ck * Nf + ia0) * NC + q];
+    }
+    if (t < NC * RB) {
+        const int c = t / RB, jj = t % RB;
         const int ib = min(ib0 + jj, Nf - 1);
         sR[c][jj] = R[((long long)ck * NC + c) * Nf + ib];
-        sS[jj][c] = Sp[(long long)ib * NC + c];
+        sSb[jj][c] = Sp[(long long)ib * NC + c];
     }
-    const int ia = ia0 + tx, ib = ib0 + j;
-    const int iac = min(ia, Nf - 1), ibc = min(ib, Nf - 1);
-    const long long idx = (long long)iac + (long long)Nf * ibc + (long long)Nf * Nf * ck;
-    const double *__restrict__ X = a.res[mk];
-    const double x = X[idx];
-    double spa[NC], brow[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        spa[c] = Sp[(long long)iac * NC + c];
-        brow[c] = B[((long long)ck * Nf + iac) * NC + c];
-    }
+    const double *__restrict__ X = (k == 0) ? a.res[1] : (k == 1) ? a.res[2] : a.res[4];
+    const int ia = ia0 + tx;
+    const int iac = min(ia, Nf - 1);
+    auto ld = [&](int j) -> double {
+        const int ibc = min(ib0 + j, Nf - 1);
+        return X[(long long)iac + (long long)Nf * ibc + (long long)Nf * Nf * ck];
+    };
+    const double xa = ld(ty), xb = ld(ty + 4);
     __syncthreads();
-    if (ia >= Nf || ib >= Nf) return;
-    int i[kMaxD] = {0, 0, 0};
-    i[fa] = ia;
-    i[fb] = ib;
-    i[k] = (ck + 1) * n - 1;
-    const unsigned S = coarse_set(i, 3, n);
-    double v;
-    if (S != mk) {
-        v = crosspoint_value(a, g, i, S);
-    } else {
-        const double scale_k = (a.mode == 0) ? 1.0 : a.scal[kScalInvNorm + k];
-        double c1 = 0.0, c2 = 0.0;
+    if (ia >= Nf) return;
+    const double scale_k = (a.mode == 0) ? 1.0 : a.scal[kScalInvNorm + k];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) c1 += spa[c] * sR[c][j];
+    for (int h = 0; h < 2; ++h) {
+        const int j = ty + 4 * h, ib = ib0 + j;
+        const double x = h ? xb : xa;
+        if (ib >= Nf) break;
+        const Pt p = mesh_pt(k, 3, ia, ib, (ck + 1) * n - 1);
+        const unsigned S = coarse_set(p, 3, n);
+        double v;
+        if (S != mk) {
+            v = crosspoint_value(a, g, p, S, ch);
+        } else {
+            double c1 = 0.0, c2 = 0.0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) c2 += sS[j][c] * brow[c];
-        v = scale_k * x + (c1 + c2);
+            for (int c = 0; c < NC; ++c) c1 += sSa[tx * NC + c] * sR[c][j];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) c2 += sSb[j][c] * sBa[tx * NC + c];
+            v = scale_k * x + (c1 + c2);
+        }
+        sk[(long long)ia + (long long)Nf * ib + (long long)Nf * Nf * ck] = v;
     }
-    a.skel[k][idx] = v;
 }
 
 static SkelArgs skel_args(const Plan &p, int mode, const double *const *res) {
@@ -281,7 +343,7 @@ void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipSt
 void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t st) {
     SkelArgs a = skel_args(p, mode, res);
     if (p.d == 3 && (p.Nc == 7 || p.Nc == 15 || p.Nc == 31)) {
-        const unsigned tiles = (unsigned)(((p.Nf + 63) / 64) * ((p.Nf + 3) / 4));
+        const unsigned tiles = (unsigned)(((p.Nf + 63) / 64) * ((p.Nf + 7) / 8));
         const dim3 grid(tiles, (unsigned)p.Nc, 3);
         if (p.Nc == 7)
             ASDSM_LAUNCH((k_merge3<7>), grid, dim3(256), 0, st, p.geo, a);
@@ -310,6 +372,7 @@ struct FillArgs {
     const double *W[kMaxD];
     const double *V[kMaxD];
     const double *mu[kMaxD];
+    const double *hinv, *hcp;   // hole line factors (d = 3), see Plan::hole_inv
     int line_axis;
     int ntr;
     int tr[kMaxD];
@@ -518,27 +581,27 @@ __device__ __forceinline__ void hole_transform_mfma(double *buf, int j, const do
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_filler_mfma3(Geo g, FillArgs a) {
+// PREFETCH: the four transform fragments are loaded at the start (fewer exposed latencies, more
+// registers: 3 waves per SIMD); otherwise each is loaded right before its transform, which fits 4
+// waves per SIMD (the better choice once there are several holes per CU).
+template <bool PREFETCH>
+__global__ __launch_bounds__(256, PREFETCH ? 2 : 4) void k_filler_mfma3(Geo g, FillArgs a) {
     if (a.gate && *a.gate) return;
     __shared__ double buf[kFBuf];
     constexpr int nh = 15, n = 16;
     const int Nf = g.Nf, Nc = g.Nc;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int L = a.line_axis, j0 = a.tr[0], j1 = a.tr[1];
-    // B fragments: B[k][m] = W[m][k] (forward) and V[m][k] (backward); zero beyond 15
-    double bw0[4], bw1[4], bv0[4], bv1[4];
-    {
+    // B fragments of a transform matrix T (W forward, V backward): B[k][m] = T[m][k], zero beyond
+    // 15; loaded right before each transform so that they do not occupy registers in between
+    auto frag = [&](const double *T, double (&f)[4]) {
         const int m = lane & 15;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int k = 4 * ks + (lane >> 4);
-            const bool ok = (m < nh) && (k < nh);
-            bw0[ks] = ok ? a.W[j0][m * nh + k] : 0.0;
-            bw1[ks] = ok ? a.W[j1][m * nh + k] : 0.0;
-            bv0[ks] = ok ? a.V[j0][m * nh + k] : 0.0;
-            bv1[ks] = ok ? a.V[j1][m * nh + k] : 0.0;
+            f[ks] = (m < nh && k < nh) ? T[m * nh + k] : 0.0;
         }
-    }
+    };
     int tt[3];
     {
         int rem = blockIdx.x;
@@ -559,58 +622,67 @@ __global__ __launch_bounds__(256) void k_filler_mfma3(Geo g, FillArgs a) {
         hi_base[j] = (tt[j] < Nc) ? base + Nf2 * tt[j] : -1;
     }
     const int f0 = n * tt[0] + Nf * (n * tt[1]) + Nf2 * (n * tt[2]);  // fine index of the tile origin
-    // 1) hole right-hand side, zero in the padding
-#pragma unroll 4
+    double fw0[4], fw1[4], fv0[4], fv1[4];
+    if (PREFETCH) {
+        frag(a.W[j0], fw0);
+        frag(a.W[j1], fw1);
+        frag(a.V[j0], fv0);
+        frag(a.V[j1], fv1);
+    }
+    // 1) hole right-hand side: b_ff (initial guess) or 0, zero in the padding ...
+#pragma unroll 2
     for (int o = tid; o < 4096; o += 256) {
         const int l0 = o & 15, l1 = (o >> 4) & 15, l2 = o >> 8;
         double v = 0.0;
-        if (l0 < nh && l1 < nh && l2 < nh) {
-            v = a.bff ? a.bff[f0 + l0 + Nf * l1 + Nf2 * l2] : 0.0;
-            const int la[3] = {l1, l0, l0}, lb[3] = {l2, l2, l1}, lj[3] = {l0, l1, l2};
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int off = la[j] + Nf * lb[j];
-                if (lj[j] == 0 && lo_base[j] >= 0) v -= g.fine[j].a * a.skel[j][lo_base[j] + off];
-                if (lj[j] == nh - 1 && hi_base[j] >= 0) v -= g.fine[j].c * a.skel[j][hi_base[j] + off];
-            }
-        }
+        if (a.bff && l0 < nh && l1 < nh && l2 < nh) v = a.bff[f0 + l0 + Nf * l1 + Nf2 * l2];
         buf[l0 + kFS1 * l1 + kFS2 * l2] = v;
     }
     __syncthreads();
+    // ... minus the coupling to the merged skeleton values on the two faces normal to each axis
+    // (one axis per pass: the two faces of an axis never share a hole point)
+    for (int j = 0; j < 3; ++j) {
+        const int sj = fstride(j), sa = (j == 0) ? kFS1 : 1, sb = (j == 2) ? kFS1 : kFS2;
+        for (int o = tid; o < 2 * nh * nh; o += 256) {
+            const int side = o / (nh * nh), q = o - side * nh * nh;
+            const int la = q % nh, lb = q / nh;
+            const int bse = side ? hi_base[j] : lo_base[j];
+            if (bse < 0) continue;
+            const double coef = side ? g.fine[j].c : g.fine[j].a;
+            buf[la * sa + lb * sb + (side ? nh - 1 : 0) * sj] -= coef * a.skel[j][bse + la + Nf * lb];
+        }
+        __syncthreads();
+    }
     // 2) forward transforms
-    hole_transform_mfma(buf, j0, bw0, lane, wave);
-    hole_transform_mfma(buf, j1, bw1, lane, wave);
-    // 3) Thomas along the line axis for the 225 lines of modes (m_j0, m_j1)
+    if (!PREFETCH) frag(a.W[j0], fw0);
+    hole_transform_mfma(buf, j0, fw0, lane, wave);
+    if (!PREFETCH) frag(a.W[j1], fw1);
+    hole_transform_mfma(buf, j1, fw1, lane, wave);
+    // 3) Thomas along the line axis for the 225 lines of modes (m_j0, m_j1), with the pivots'
+    // reciprocals and the eliminated super-diagonal precomputed per mode pair (all holes share them)
     if (tid < nh * nh) {
         const int m0 = tid % nh, m1 = tid / nh;
-        const double sigma = a.mu[j0][m0] + a.mu[j1][m1];
         const int base = m0 * fstride(j0) + m1 * fstride(j1);
         const int sL = fstride(L);
-        const Tri t = g.fine[L];
-        const double diag = t.b + sigma;
-        double cp[nh], f[nh];
+        const double sub = g.fine[L].a;
+        double f[nh];
 #pragma unroll
         for (int c = 0; c < nh; ++c) f[c] = buf[base + c * sL];
-        double den = diag;
-        cp[0] = t.c / den;
-        f[0] = f[0] / den;
+        f[0] = f[0] * a.hinv[tid];
 #pragma unroll
-        for (int c = 1; c < nh; ++c) {
-            den = diag - t.a * cp[c - 1];
-            f[c] = (f[c] - t.a * f[c - 1]) / den;
-            cp[c] = t.c / den;
-        }
+        for (int c = 1; c < nh; ++c) f[c] = (f[c] - sub * f[c - 1]) * a.hinv[c * nh * nh + tid];
 #pragma unroll
-        for (int c = nh - 2; c >= 0; --c) f[c] -= cp[c] * f[c + 1];
+        for (int c = nh - 2; c >= 0; --c) f[c] -= a.hcp[c * nh * nh + tid] * f[c + 1];
 #pragma unroll
         for (int c = 0; c < nh; ++c) buf[base + c * sL] = f[c];
     }
     __syncthreads();
     // 4) backward transforms
-    hole_transform_mfma(buf, j1, bv1, lane, wave);
-    hole_transform_mfma(buf, j0, bv0, lane, wave);
+    if (!PREFETCH) frag(a.V[j1], fv1);
+    hole_transform_mfma(buf, j1, fv1, lane, wave);
+    if (!PREFETCH) frag(a.V[j0], fv0);
+    hole_transform_mfma(buf, j0, fv0, lane, wave);
     // 5) write the whole tile (hole values and the skeleton planes above it), x_1 fastest
-#pragma unroll 4
+#pragma unroll 2
     for (int o = tid; o < 4096; o += 256) {
         const int l0 = o & 15, l1 = (o >> 4) & 15, l2 = o >> 8;
         if (n * tt[0] + l0 >= Nf || n * tt[1] + l1 >= Nf || n * tt[2] + l2 >= Nf) continue;
@@ -640,6 +712,8 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
         a.tr[j] = 0;
     }
     a.line_axis = p.hole_line_axis;
+    a.hinv = p.dhole_inv;
+    a.hcp = p.dhole_cp;
     a.ntr = 0;
     for (int j = 0; j < d; ++j)
         if (j != p.hole_line_axis) a.tr[a.ntr++] = j;
@@ -653,7 +727,10 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
     for (int j = 0; j < d; ++j) tiles *= (p.Nc + 1);
     const dim3 grid(tiles), blk(256);
     if (d == 3 && nh == 15) {
-        ASDSM_LAUNCH(k_filler_mfma3, grid, blk, 0, st, p.geo, a);
+        if (tiles >= 4 * 256)
+            ASDSM_LAUNCH((k_filler_mfma3<false>), grid, blk, 0, st, p.geo, a);
+        else
+            ASDSM_LAUNCH((k_filler_mfma3<true>), grid, blk, 0, st, p.geo, a);
         return;
     }
 #define ASDSM_FILL(DD, NHV) ASDSM_LAUNCH((k_filler<DD, NHV>), grid, blk, lds, st, p.geo, a)
