@@ -109,6 +109,9 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle refinement steps in the sample")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
+                    help="error-phase submesh solves of the timed solves")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     return ap.parse_args()
 
 
@@ -133,7 +136,8 @@ def main():
     s = torch.from_numpy(P.s_flat()).to(dev)
     g = torch.from_numpy(P.g_flat()).to(dev)
     u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
-    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
+    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3,
+              precision=args.precision)
 
     for _ in range(args.warmup):
         plan.solve(s, g, u=u, **kw)
@@ -190,9 +194,40 @@ def main():
         "roofline": roof,
         "stencil_effective": stencil,
     }
+    out["precision_used"] = infos[-1]["precision"]
+    if not args.no_mixed:
+        out["mixed_precision"] = mixed_precision(asdsm, make_problem, L, args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, L, args, iters)
     print(json.dumps(out))
+
+
+def mixed_precision(asdsm, make_problem, L, args, dev, seed=1, steps=3):
+    """FP32 error guesses against FP64 ones on a draw of the same family whose anisotropic meshes
+    are all FP32-eligible (seed 1; the timed draw, seed 0, is not: one transform axis there has
+    cond(V) = 1.2e8, so FP32 is refused and the solve stays FP64).  Complete solves, same options."""
+    import torch
+    P = make_problem("sinbump3d", L, seed=seed)
+    plan = asdsm.Plan(3, P.alpha, P.beta, L, args.coarse_level, seed=seed, device=0)
+    s = torch.from_numpy(P.s_flat()).to(dev)
+    g = torch.from_numpy(P.g_flat()).to(dev)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
+        kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3, precision=prec)
+        plan.solve(s, g, u=u, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, info = plan.solve(s, g, u=u, **kw)
+        torch.cuda.synchronize()
+        res[prec] = (1e3 * (time.perf_counter() - t0) / steps, info, u.clone())
+    (t64, i64, u64), (t32, i32, u32) = res["fp64"], res["fp32"]
+    return {"workload": f"asdsm-3d-{plan.n_f}^3-sinbump-seed{seed}", "precision_used": i32["precision"],
+            "ms_per_solve_fp64": t64, "ms_per_solve_fp32": t32, "speedup": t64 / t32,
+            "iterations_fp64": i64["iterations"], "iterations_fp32": i32["iterations"],
+            "rel_residual_fp64": i64["rnorm"] / i64["bnorm"], "rel_residual_fp32": i32["rnorm"] / i32["bnorm"],
+            "rel_l2_fp32_vs_fp64": float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))}
 
 
 def cpu_baseline(P, L, args, gpu_iters):

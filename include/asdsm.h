@@ -80,7 +80,16 @@ typedef struct {
     int    eager;         /* nonzero: launch the refinement kernels one by one and check the     */
                           /* stopping rule after every step, instead of replaying a captured    */
                           /* HIP graph of two steps and checking every four steps               */
+    int    precision;     /* ASDSM_PREC_FP64 (0, default) or ASDSM_PREC_FP32: the error-phase  */
+                          /* submesh solves (Algorithm 1 with the residual as source) run in    */
+                          /* FP32 (FP32 MFMA transforms, FP32 line elimination, no refinement   */
+                          /* sweeps); the residual, merge, filler and line search stay FP64.    */
+                          /* The initial guess is FP64 in both modes.                           */
 } asdsm_opts;
+
+/* values of asdsm_opts.precision */
+#define ASDSM_PREC_FP64 0
+#define ASDSM_PREC_FP32 1
 
 typedef struct {
     int    status;        /* same as the return value                                            */
@@ -97,6 +106,9 @@ typedef struct {
     double phase_bytes[ASDSM_NPHASE];   /* algorithmic bytes per phase: every operand read once  */
                                         /* and every result written once (profile only)          */
     double total_ms;      /* device time of the whole call (profile only)                        */
+    int    precision;     /* precision the error-phase submesh solves ran in: FP32 is used only  */
+                          /* when requested and every anisotropic mesh's transforms are well     */
+                          /* enough conditioned (6e-8 * prod cond(V_j) <= 1e-3), else FP64       */
 } asdsm_stats;
 
 /* Create a plan (Section 2.1 meshes, Section 2.3 operators, Algorithms 1-4 schedule).

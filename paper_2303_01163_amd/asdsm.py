@@ -18,6 +18,7 @@ ASDSM_E_NUMERIC, ASDSM_E_DEVICE, ASDSM_E_UNSUPPORTED = -4, -5, -6
 NPHASE = 7
 PHASES = ("rhs", "transform", "line", "skeleton", "filler", "dots", "update")
 STATUS_NAMES = {0: "ok", 1: "stagnated", 2: "maxiter"}
+PRECISIONS = {"fp64": 0, "fp32": 1}  # asdsm_opts.precision: FP64 or FP32 error-phase submesh solves
 
 # symbols declared in include/asdsm.h
 EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_solve",
@@ -34,14 +35,14 @@ class Opts(ctypes.Structure):
     _fields_ = [("max_iter", c_int), ("rtol", c_double), ("stag_window", c_int),
                 ("stag_eta", c_double), ("resume", c_int), ("k0", c_int64),
                 ("hist", POINTER(c_double)), ("step_hist", POINTER(c_double)), ("profile", c_int),
-                ("eager", c_int)]
+                ("eager", c_int), ("precision", c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("status", c_int), ("iterations", c_int), ("bnorm", c_double),
                 ("r0norm", c_double), ("rnorm", c_double), ("phase_ms", c_double * NPHASE),
                 ("phase_launches", c_int * NPHASE), ("phase_flops", c_double * NPHASE),
-                ("phase_bytes", c_double * NPHASE), ("total_ms", c_double)]
+                ("phase_bytes", c_double * NPHASE), ("total_ms", c_double), ("precision", c_int)]
 
 
 _lib = None
@@ -136,7 +137,7 @@ class Plan:
         return tuple([self.n_f] * len(fine) + [self.n_c] * len(coarse)), fine + coarse
 
     def solve(self, s, g, u=None, max_iter=50, rtol=1e-10, stag_window=3, stag_eta=1e-3,
-              resume=False, k0=0, profile=False, eager=False):
+              resume=False, k0=0, profile=False, eager=False, precision="fp64"):
         import torch
         lib = load_library()
         if u is None:
@@ -147,7 +148,7 @@ class Plan:
                  stag_eta=float(stag_eta), resume=1 if resume else 0, k0=int(k0),
                  hist=ctypes.cast(hist, POINTER(c_double)),
                  step_hist=ctypes.cast(steps, POINTER(c_double)), profile=1 if profile else 0,
-                 eager=1 if eager else 0)
+                 eager=1 if eager else 0, precision=PRECISIONS[precision])
         st = Stats()
         with torch.cuda.device(self.device):
             rc = _check(lib.asdsm_solve(self._h, _dptr(s, self.n_fine, "s"),
@@ -159,6 +160,7 @@ class Plan:
             "bnorm": st.bnorm, "r0norm": st.r0norm, "rnorm": st.rnorm,
             "res_hist": [hist[i] for i in range(it + 1)],
             "step_hist": [steps[i] for i in range(it)],
+            "precision": {v: k for k, v in PRECISIONS.items()}[st.precision],
         }
         if profile:
             info["phase_ms"] = {PHASES[q]: st.phase_ms[q] for q in range(NPHASE)}

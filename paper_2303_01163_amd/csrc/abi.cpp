@@ -307,6 +307,117 @@ int solve_aniso_refined(Plan &p, unsigned kbits) {
     return ASDSM_OK;
 }
 
+// Mixed-precision error guesses: the anisotropic solves of Algorithm 1 with the residual as source,
+// in FP32 (FP32 MFMA transforms with FP32 accumulation, FP32 line elimination, no refinement
+// sweeps).  in[k] (FP64 right-hand side) is rounded to FP32 as the first transform stages it; the
+// last transform writes the FP64 solution out[k].  F1/F2 hold the FP32 intermediates.
+int solve_aniso32(Plan &p, const double *const *in, double *const *out) {
+    const int d = p.d, Nf = p.Nf, Nc = p.Nc;
+    const long long Nf2 = (long long)Nf * Nf;
+    const int nb = d;
+    auto f64 = [](float *x) { return reinterpret_cast<double *>(x); };
+    auto cf64 = [](const float *x) { return reinterpret_cast<const double *>(x); };
+    GemmJob j{};
+    j.nbox = nb;
+    j.gate = p.gate;
+    // forward along canonical axis 0: in (FP64) -> F1
+    j.M = (d == 2) ? Nc : Nf * Nc;
+    j.N = Nf; j.K = Nf; j.nbatch = 1; j.accum = 0;
+    j.sAb = j.sBb = j.sCb = 0;
+    j.sAi = Nf; j.sAk = 1;
+    j.sBk = 1;  j.sBn = Nf;
+    j.sCi = Nf; j.sCn = 1;
+    for (int k = 0; k < nb; ++k) {
+        int a, b;
+        fine_axes(d, k, a, b);
+        j.A[k] = in[k];
+        j.B[k] = cf64(p.dW32[a]);
+        j.C[k] = f64(p.ws.F1[k]);
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j) * 0.75);
+        if (!launch_gemm32(j, true, false, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
+        if (int rc = check_launch("transform")) return rc;
+    }
+    if (d == 3) {
+        // forward along canonical axis 1, batched over the coarse slabs: F1 -> F2
+        j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc;
+        j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
+        j.sBb = Nf2; j.sBk = Nf; j.sBn = 1;
+        j.sCb = Nf2; j.sCi = Nf; j.sCn = 1;
+        for (int k = 0; k < nb; ++k) {
+            int a, b;
+            fine_axes(d, k, a, b);
+            j.A[k] = cf64(p.dW32[b]);
+            j.B[k] = cf64(p.ws.F1[k]);
+            j.C[k] = f64(p.ws.F2[k]);
+        }
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j) * 0.5);
+        if (!launch_gemm32(j, false, false, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
+        if (int rc = check_launch("transform")) return rc;
+    }
+    {
+        // FP32 line elimination along the coarse axis: d = 2 on F1 (scratch F2), d = 3 on F2
+        LineJob L{};
+        L.nbox = nb;
+        L.gate = p.gate;
+        L.fp32 = 1;
+        L.nmodes = (d == 2) ? Nf : Nf2;
+        L.ext_a = Nf;
+        L.ncoarse = Nc;
+        for (int k = 0; k < nb; ++k) {
+            int a, b;
+            fine_axes(d, k, a, b);
+            L.X[k] = f64((d == 2) ? p.ws.F1[k] : p.ws.F2[k]);
+            L.scratch[k] = f64((d == 2) ? p.ws.F2[k] : p.ws.F1[k]);
+            L.mu_a[k] = p.dmu[a];
+            L.mu_b[k] = (d == 3) ? p.dmu[b] : nullptr;
+            L.t[k] = p.geo.coarse[k];
+        }
+        const double lpts = (double)L.nmodes * L.ncoarse * nb;
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 8.0 * lpts, 8.0 * lpts);
+        launch_line(L, p.stream);
+        if (int rc = check_launch("line")) return rc;
+    }
+    if (d == 3) {
+        // backward along canonical axis 1: F2 -> F1
+        j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc;
+        j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
+        j.sBb = Nf2; j.sBk = Nf; j.sBn = 1;
+        j.sCb = Nf2; j.sCi = Nf; j.sCn = 1;
+        for (int k = 0; k < nb; ++k) {
+            int a, b;
+            fine_axes(d, k, a, b);
+            j.A[k] = cf64(p.dV32[b]);
+            j.B[k] = cf64(p.ws.F2[k]);
+            j.C[k] = f64(p.ws.F1[k]);
+        }
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j) * 0.5);
+        if (!launch_gemm32(j, false, false, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
+        if (int rc = check_launch("transform")) return rc;
+    }
+    {
+        // backward along canonical axis 0: F1 -> out (FP64)
+        j.M = (d == 2) ? Nc : Nf * Nc;
+        j.N = Nf; j.K = Nf; j.nbatch = 1; j.accum = 0;
+        j.sAb = j.sBb = j.sCb = 0;
+        j.sAi = Nf; j.sAk = 1;
+        j.sBk = 1;  j.sBn = Nf;
+        j.sCi = Nf; j.sCn = 1;
+        for (int k = 0; k < nb; ++k) {
+            int a, b;
+            fine_axes(d, k, a, b);
+            j.A[k] = cf64(p.ws.F1[k]);
+            j.B[k] = cf64(p.dV32[a]);
+            j.C[k] = out[k];
+        }
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j) * 0.75);
+        if (!launch_gemm32(j, false, true, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
+        if (int rc = check_launch("transform")) return rc;
+    }
+    return ASDSM_OK;
+}
+
 int solve_intersection_refined(Plan &p, unsigned mask) {
     const double *in = rhs_buf(p, mask);
     double *out = sol_buf(p, mask);
@@ -533,7 +644,17 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
 // of its kernels return at once when the device stopping rule has fired (p.gate), so steps can be
 // queued (or replayed from a graph) ahead of the host's check.
 int refine_step(Plan &p, const double *u_cur, double *u_next) {
-    if (int rc = solve_aniso_refined(p, (1u << p.d) - 1)) return rc;
+    if (p.prec32) {
+        const double *in[kMaxD] = {};
+        double *out[kMaxD] = {};
+        for (int k = 0; k < p.d; ++k) {
+            in[k] = rhs_buf(p, 1u << k);
+            out[k] = sol_buf(p, 1u << k);
+        }
+        if (int rc = solve_aniso32(p, in, out)) return rc;
+    } else if (int rc = solve_aniso_refined(p, (1u << p.d) - 1)) {
+        return rc;
+    }
     const double *res[kMaxMeshes];
     result_pointers(p, res);
     {
@@ -610,6 +731,7 @@ int build_graph(Plan &p, double *u) {
         return fail(ASDSM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
     p.graph_u = u;
+    p.graph_prec32 = p.prec32;
     return ASDSM_OK;
 }
 
@@ -629,9 +751,12 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
     if (opt.max_iter < 0 || opt.max_iter >= kHistCap || !(opt.rtol >= 0.0) || opt.stag_window < 0 ||
         !(opt.stag_eta >= 0.0) || !(opt.stag_eta < 1.0))
         return fail(ASDSM_E_ARG, "invalid options (max_iter must be < " + std::to_string(kHistCap) + ")");
+    if (opt.precision != ASDSM_PREC_FP64 && opt.precision != ASDSM_PREC_FP32)
+        return fail(ASDSM_E_ARG, "invalid precision");
     if (int rc = require_ws(p)) return rc;
     p.profiling = opt.profile != 0;
     p.prof_failed = false;
+    p.prec32 = (opt.precision == ASDSM_PREC_FP32) && p.fp32_ok;
     p.ev_recs.clear();
     const bool use_graph = !p.profiling && !opt.eager;
     for (int q = 0; q < ASDSM_NPHASE; ++q) {
@@ -679,7 +804,7 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
     p.gate = &p.ws.state->done;
     int rc = ASDSM_OK;
     if (use_graph) {
-        if (p.graph_u != u || !p.graph_exec) rc = build_graph(p, u);
+        if (p.graph_u != u || !p.graph_exec || p.graph_prec32 != p.prec32) rc = build_graph(p, u);
         // two steps per replay, two replays per host check; surplus steps are gated no-ops
         int steps = 0;
         while (rc == ASDSM_OK) {
@@ -729,6 +854,7 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         st->bnorm = std::sqrt(p.hscal[kScalBnorm2]);
         st->r0norm = r0;
         st->rnorm = rn;
+        st->precision = p.prec32 ? ASDSM_PREC_FP32 : ASDSM_PREC_FP64;
         for (int q = 0; q < ASDSM_NPHASE; ++q) {
             st->phase_ms[q] = p.phase_ms[q];
             st->phase_launches[q] = p.phase_launches[q];

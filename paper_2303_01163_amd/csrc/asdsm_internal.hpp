@@ -89,6 +89,8 @@ struct Workspace {
     double *Z[kMaxMeshes] = {};  // saved right-hand side (refinement sweeps), per mask
     double *W[kMaxMeshes] = {};  // accumulated solution (refinement sweeps), per mask
     double *lines[kMaxD] = {};   // cross-point discrepancies of each anisotropic mesh
+    float *F1[kMaxD] = {};       // FP32 transform scratch of each anisotropic mesh (mixed
+    float *F2[kMaxD] = {};       // precision error guesses)
     IterState *state = nullptr;  // refinement-loop state
     double *hist = nullptr;      // ||r_k||, k = 0..it
     double *step_hist = nullptr; // s_hat_k
@@ -136,6 +138,11 @@ struct Plan {
     size_t dtab_bytes = 0;
     double *dW[kMaxD] = {}, *dV[kMaxD] = {}, *dmu[kMaxD] = {};
     double *dWh[kMaxD] = {}, *dVh[kMaxD] = {}, *dmuh[kMaxD] = {};
+    // FP32 copies of the fine-axis transforms (mixed-precision error guesses)
+    std::vector<float> W32[kMaxD], V32[kMaxD];
+    float *dW32[kMaxD] = {}, *dV32[kMaxD] = {};
+    bool prec32 = false;             // this call's error guesses run in FP32
+    bool fp32_ok = false;            // every anisotropic mesh: 6e-8 * prod cond(V_j) <= 1e-3
     // hole line elimination factors (d = 3): for the mode pair q = m0 + nh m1 of the two transformed
     // hole axes, step c: hole_inv[c nh^2 + q] = 1/pivot_c, hole_cp[...] = super / pivot_c
     std::vector<double> hole_inv, hole_cp;
@@ -163,6 +170,7 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     const double *graph_u = nullptr;
+    bool graph_prec32 = false;
 
     // profiling: a pair of events around every timed launch group, read after the call's final
     // synchronisation (launches stay queued back to back, so the pair brackets the kernels alone)

@@ -9,6 +9,7 @@
 namespace asdsm {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // A fine index i (0-based) lies on a coarse line iff i+1 is a multiple of n (n a power of two).
 __device__ __forceinline__ bool on_coarse(int i, int n) { return ((i + 1) & (n - 1)) == 0; }

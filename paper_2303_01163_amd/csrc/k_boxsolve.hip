@@ -147,40 +147,171 @@ bool launch_gemm(const GemmJob &job, hipStream_t st) {
     return true;
 }
 
+// FP32 variant for the mixed-precision error guesses (v_mfma_f32_16x16x4f32, FP32 accumulation):
+// the same tiling and double buffering; A is read as TA (double: the FP64 right-hand side is
+// rounded to FP32 while it is staged), B is FP32, C is written as TC (double: the solution goes
+// back to the FP64 buffers).  The GemmJob pointers are reinterpreted accordingly.
+// Output layout of the FP32 16x16x4 MFMA: D[v] at row 4 (l/16) + v, col l%16.
+template <int TM, int TN, int KC, bool BKF, typename TA, typename TC>
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmJob job) {
+    if (job.gate && *job.gate) return;
+    constexpr int MI = TM / 32, NI = TN / 32;
+    constexpr int LA = TM * KC / 256, LB = KC * TN / 256;
+    __shared__ float sA[2][TM][KC + 1];
+    __shared__ float sB[2][KC][TN + 1];
+    const int tx = (job.N + TN - 1) / TN, ty = (job.M + TM - 1) / TM;
+    const int per_z = tx * ty;
+    const int total = per_z * job.nbox * job.nbatch;
+    const int per = (total + 7) / 8;
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if ((int)(blockIdx.x >> 3) >= per || tile >= total) return;
+    const int z = tile / per_z;
+    const int rem = tile - z * per_z;
+    const int by = rem / tx, bx = rem - by * tx;
+    const int box = z / job.nbatch, bat = z - box * job.nbatch;
+    const TA *__restrict__ A = reinterpret_cast<const TA *>(job.A[box]) + (long long)bat * job.sAb;
+    const float *__restrict__ B = reinterpret_cast<const float *>(job.B[box]) + (long long)bat * job.sBb;
+    const int m0 = by * TM, n0 = bx * TN;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int sAi = (int)job.sAi, sBk = (int)job.sBk, sBn = (int)job.sBn;
+    const int ar = t / KC, ak = t % KC;
+    const int bn0 = BKF ? (t / KC) : (t % TN), bk0 = BKF ? (t % KC) : (t / TN);
+    float ra[LA], rb[LB];
+    const int nch = (job.K + KC - 1) / KC;
+    auto gload = [&](int c) {
+        const int k0 = c * KC;
+#pragma unroll
+        for (int j = 0; j < LA; ++j) {
+            const int row = m0 + ar + (256 / KC) * j, k = k0 + ak;
+            ra[j] = (row < job.M && k < job.K) ? (float)A[row * sAi + k] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            const int n = n0 + (BKF ? bn0 + (256 / KC) * j : bn0);
+            const int kb = k0 + (BKF ? bk0 : bk0 + (256 / TN) * j);
+            rb[j] = (n < job.N && kb < job.K) ? B[kb * sBk + n * sBn] : 0.f;
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < LA; ++j) sA[buf][ar + (256 / KC) * j][ak] = ra[j];
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            if (BKF)
+                sB[buf][bk0][bn0 + (256 / KC) * j] = rb[j];
+            else
+                sB[buf][bk0 + (256 / TN) * j][bn0] = rb[j];
+        }
+    };
+    float4_t acc[MI][NI];
+#pragma unroll
+    for (int a = 0; a < MI; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b) acc[a][b] = {0.f, 0.f, 0.f, 0.f};
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) gload(c + 1);
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            const int kq = kk + (lane >> 4);
+            float av[MI], bv[NI];
+#pragma unroll
+            for (int a = 0; a < MI; ++a) av[a] = sA[buf][wm * (TM / 2) + a * 16 + (lane & 15)][kq];
+#pragma unroll
+            for (int b = 0; b < NI; ++b) bv[b] = sB[buf][kq][wn * (TN / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < MI; ++a)
+#pragma unroll
+                for (int b = 0; b < NI; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        if (c + 1 < nch) lstore(buf ^ 1);
+        __syncthreads();
+    }
+    TC *__restrict__ C = reinterpret_cast<TC *>(job.C[box]) + (long long)bat * job.sCb;
+#pragma unroll
+    for (int a = 0; a < MI; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = m0 + wm * (TM / 2) + a * 16 + 4 * (lane >> 4) + v;
+                const int gn = n0 + wn * (TN / 2) + b * 16 + (lane & 15);
+                if (gi < job.M && gn < job.N) {
+                    TC *cp = C + (long long)gi * job.sCi + (long long)gn * job.sCn;
+                    *cp = job.accum ? (TC)(*cp + acc[a][b][v]) : (TC)acc[a][b][v];
+                }
+            }
+}
+
+template <int TM, int TN, int KC, typename TA, typename TC>
+static void launch_gemm32_tile(const GemmJob &job, hipStream_t st) {
+    const long long tx = (job.N + TN - 1) / TN, ty = (job.M + TM - 1) / TM;
+    const long long total = tx * ty * job.nbox * job.nbatch;
+    const dim3 grid((unsigned)(8 * ((total + 7) / 8)));
+    if (job.sBk == 1)
+        ASDSM_LAUNCH((k_gemm_f32<TM, TN, KC, true, TA, TC>), grid, dim3(256), 0, st, job);
+    else
+        ASDSM_LAUNCH((k_gemm_f32<TM, TN, KC, false, TA, TC>), grid, dim3(256), 0, st, job);
+}
+
+template <typename TA, typename TC>
+static void launch_gemm32_io(const GemmJob &job, hipStream_t st) {
+    const long long t64 = ((job.N + 63) / 64) * ((job.M + 63) / 64) * job.nbox * job.nbatch;
+    if (t64 >= 512)
+        launch_gemm32_tile<64, 64, 32, TA, TC>(job, st);
+    else
+        launch_gemm32_tile<32, 32, 32, TA, TC>(job, st);
+}
+
+bool launch_gemm32(const GemmJob &job, bool a_f64, bool c_f64, hipStream_t st) {
+    if (job.sAk != 1 || (job.sBk != 1 && job.sBn != 1)) return false;
+    if (a_f64 && c_f64) launch_gemm32_io<double, double>(job, st);
+    else if (a_f64) launch_gemm32_io<double, float>(job, st);
+    else if (c_f64) launch_gemm32_io<float, double>(job, st);
+    else launch_gemm32_io<float, float>(job, st);
+    return true;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Thomas elimination along the coarse axis, one thread per mode, boxes along blockIdx.y.  Lines of
 // up to NCR points stay in registers (loads issued together); longer lines use the scratch array.
 // ---------------------------------------------------------------------------------------------
-template <int NCR>
+template <int NCR, typename T>
 __global__ __launch_bounds__(256) void k_line(LineJob job) {
     if (job.gate && *job.gate) return;
     const int box = blockIdx.y;
     const long long m = (long long)blockIdx.x * 256 + threadIdx.x;
     if (m >= job.nmodes) return;
-    double *__restrict__ X = job.X[box];
-    double *__restrict__ S = job.scratch[box];
-    const Tri t = job.t[box];
+    T *__restrict__ X = reinterpret_cast<T *>(job.X[box]);
+    T *__restrict__ S = reinterpret_cast<T *>(job.scratch[box]);
+    const Tri t64 = job.t[box];
+    const T ta = (T)t64.a, tc = (T)t64.c;
     const int ma = (int)(m % job.ext_a);
     const long long mb = m / job.ext_a;
     double sigma = job.mu_a[box][ma];
     if (job.mu_b[box]) sigma += job.mu_b[box][mb];
     const long long st = job.nmodes;
-    const double diag = t.b + sigma;
+    const T diag = (T)(t64.b + sigma);
     const int nc = job.ncoarse;
     if (NCR > 0) {
-        double f[NCR > 0 ? NCR : 1], cp[NCR > 0 ? NCR : 1];
+        T f[NCR > 0 ? NCR : 1], cp[NCR > 0 ? NCR : 1];
 #pragma unroll
         for (int c = 0; c < NCR; ++c)
             if (c < nc) f[c] = X[m + st * c];
-        double den = diag;
-        cp[0] = t.c / den;
+        T den = diag;
+        cp[0] = tc / den;
         f[0] = f[0] / den;
 #pragma unroll
         for (int c = 1; c < NCR; ++c)
             if (c < nc) {
-                den = diag - t.a * cp[c - 1];
-                f[c] = (f[c] - t.a * f[c - 1]) / den;
-                cp[c] = t.c / den;
+                den = diag - ta * cp[c - 1];
+                f[c] = (f[c] - ta * f[c - 1]) / den;
+                cp[c] = tc / den;
             }
 #pragma unroll
         for (int c = NCR - 2; c >= 0; --c)
@@ -190,20 +321,20 @@ __global__ __launch_bounds__(256) void k_line(LineJob job) {
             if (c < nc) X[m + st * c] = f[c];
         return;
     }
-    double den = diag;
-    double cq = t.c / den;
-    double dp = X[m] / den;
+    T den = diag;
+    T cq = tc / den;
+    T dp = X[m] / den;
     S[m] = cq;
     X[m] = dp;
     for (int c = 1; c < nc; ++c) {
-        den = diag - t.a * cq;
-        const double fc = X[m + st * c];
-        dp = (fc - t.a * dp) / den;
-        cq = t.c / den;
+        den = diag - ta * cq;
+        const T fc = X[m + st * c];
+        dp = (fc - ta * dp) / den;
+        cq = tc / den;
         S[m + st * c] = cq;
         X[m + st * c] = dp;
     }
-    double x = dp;
+    T x = dp;
     for (int c = nc - 2; c >= 0; --c) {
         x = X[m + st * c] - S[m + st * c] * x;
         X[m + st * c] = x;
@@ -212,14 +343,25 @@ __global__ __launch_bounds__(256) void k_line(LineJob job) {
 
 void launch_line(const LineJob &job, hipStream_t st) {
     dim3 grid((unsigned)((job.nmodes + 255) / 256), job.nbox, 1);
+    if (job.fp32) {
+        if (job.ncoarse <= 7)
+            ASDSM_LAUNCH((k_line<7, float>), grid, dim3(256), 0, st, job);
+        else if (job.ncoarse <= 15)
+            ASDSM_LAUNCH((k_line<15, float>), grid, dim3(256), 0, st, job);
+        else if (job.ncoarse <= 31)
+            ASDSM_LAUNCH((k_line<31, float>), grid, dim3(256), 0, st, job);
+        else
+            ASDSM_LAUNCH((k_line<0, float>), grid, dim3(256), 0, st, job);
+        return;
+    }
     if (job.ncoarse <= 7)
-        ASDSM_LAUNCH((k_line<7>), grid, dim3(256), 0, st, job);
+        ASDSM_LAUNCH((k_line<7, double>), grid, dim3(256), 0, st, job);
     else if (job.ncoarse <= 15)
-        ASDSM_LAUNCH((k_line<15>), grid, dim3(256), 0, st, job);
+        ASDSM_LAUNCH((k_line<15, double>), grid, dim3(256), 0, st, job);
     else if (job.ncoarse <= 31)
-        ASDSM_LAUNCH((k_line<31>), grid, dim3(256), 0, st, job);
+        ASDSM_LAUNCH((k_line<31, double>), grid, dim3(256), 0, st, job);
     else
-        ASDSM_LAUNCH((k_line<0>), grid, dim3(256), 0, st, job);
+        ASDSM_LAUNCH((k_line<0, double>), grid, dim3(256), 0, st, job);
 }
 
 // ---------------------------------------------------------------------------------------------

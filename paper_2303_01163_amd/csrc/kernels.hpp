@@ -57,6 +57,7 @@ struct LineJob {
     long long nmodes;          // product of the fine extents
     int ext_a;                 // extent of the first fine axis
     int ncoarse;               // points along the coarse axis
+    int fp32;                  // 1: X and scratch hold floats (mixed-precision error guesses)
     const int *gate;
 };
 
@@ -71,6 +72,9 @@ void launch_dots(const Plan &p, hipStream_t st);
 int stencil_blocks(const Geo &g);
 
 bool launch_gemm(const GemmJob &job, hipStream_t st);  // false: unsupported operand layout
+// FP32 MFMA variant: A read as double (a_f64) or float, B float, C written as double (c_f64) or
+// float; the GemmJob pointers are reinterpreted accordingly.
+bool launch_gemm32(const GemmJob &job, bool a_f64, bool c_f64, hipStream_t st);
 void launch_line(const LineJob &job, hipStream_t st);
 void launch_dense_modes(long long nmodes, int B, const double *inv, const double *in, double *out,
                         int accum, hipStream_t st);

@@ -342,6 +342,10 @@ void layout_workspace(Plan &p, char *base, bool assign) {
     // Nc*Nc*Nf values each
     const size_t nl = (p.d == 2) ? (size_t)p.Nc * p.Nc : (size_t)3 * p.Nc * p.Nc * p.Nf;
     for (int k = 0; k < p.d; ++k) w.lines[k] = (double *)take(nl * 8);
+    for (int k = 0; k < p.d; ++k) {
+        w.F1[k] = (float *)take((size_t)p.mesh[1u << k].size * 4);
+        w.F2[k] = (float *)take((size_t)p.mesh[1u << k].size * 4);
+    }
     w.state = (IterState *)take(sizeof(IterState));
     w.hist = (double *)take((size_t)kHistCap * 8);
     w.step_hist = (double *)take((size_t)kHistCap * 8);
@@ -459,10 +463,12 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     // transformed axes.  Where that exceeds 2e-11 the direct solve becomes the preconditioner of
     // FP64 refinement sweeps x <- x + M^-1 (f - A x), each gaining -log10(eps * prod cond) digits;
     // the count is fixed here so that the result reaches ~1e-14.
+    p.fp32_ok = true;
     for (unsigned s = 1; s < (1u << d); ++s) {
         double c = 1.0;
         for (int q = 0; q < p.mesh[s].nfine; ++q) c *= p.fine_spec[p.mesh[s].ax[q]].cond;
         p.fdm_cond[s] = c;
+        if (__builtin_popcount(s) == 1 && 6e-8 * c > 1e-3) p.fp32_ok = false;
         const double delta = 2.2e-16 * c;
         if (delta <= 2e-11) {
             p.sweeps[s] = 0;
@@ -497,13 +503,31 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     hipError_t err = hipGetDevice(&p.device);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(err));
     size_t off = 0;
-    std::vector<std::pair<size_t, const std::vector<double> *>> items;
+    struct Item {
+        size_t off;
+        const void *data;
+        size_t bytes;
+    };
+    std::vector<Item> items;
     auto add = [&](const std::vector<double> &v) {
-        items.push_back({off, &v});
+        items.push_back({off, v.data(), v.size() * 8});
         size_t o = off;
         off = align256(off + v.size() * 8);
         return o;
     };
+    auto add32 = [&](const std::vector<float> &v) {
+        items.push_back({off, v.data(), v.size() * 4});
+        size_t o = off;
+        off = align256(off + v.size() * 4);
+        return o;
+    };
+    size_t oW32[kMaxD] = {}, oV32[kMaxD] = {};
+    for (int j = 0; j < d; ++j) {
+        p.W32[j].assign(p.fine_spec[j].W.begin(), p.fine_spec[j].W.end());
+        p.V32[j].assign(p.fine_spec[j].V.begin(), p.fine_spec[j].V.end());
+        oW32[j] = add32(p.W32[j]);
+        oV32[j] = add32(p.V32[j]);
+    }
     size_t oW[kMaxD], oV[kMaxD], oM[kMaxD], oWh[kMaxD], oVh[kMaxD], oMh[kMaxD], oD[kMaxMeshes];
     for (int j = 0; j < d; ++j) {
         oW[j] = add(p.fine_spec[j].W);
@@ -545,7 +569,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     err = hipMalloc(&p.dtab, p.dtab_bytes);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipMalloc(tables): ") + hipGetErrorString(err));
     std::vector<char> host(p.dtab_bytes, 0);
-    for (auto &it : items) std::memcpy(host.data() + it.first, it.second->data(), it.second->size() * 8);
+    for (auto &it : items) std::memcpy(host.data() + it.off, it.data, it.bytes);
     err = hipMemcpy(p.dtab, host.data(), p.dtab_bytes, hipMemcpyHostToDevice);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipMemcpy(tables): ") + hipGetErrorString(err));
     char *base = (char *)p.dtab;
@@ -558,6 +582,10 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         p.dmuh[j] = (double *)(base + oMh[j]);
     }
     p.dSp = (double *)(base + oS);
+    for (int j = 0; j < d; ++j) {
+        p.dW32[j] = (float *)(base + oW32[j]);
+        p.dV32[j] = (float *)(base + oV32[j]);
+    }
     if (d == 3) {
         p.dhole_inv = (double *)(base + oHI);
         p.dhole_cp = (double *)(base + oHC);

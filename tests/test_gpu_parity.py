@@ -331,3 +331,69 @@ def test_graph_replay_matches_eager(torch_dev):
     ug, ig = pl.solve(s, g, max_iter=40, rtol=0, stag_window=1, stag_eta=0.3)
     assert ie["status"] == ig["status"] == 1 and ie["iterations"] == ig["iterations"] < 40
     assert bool((ug == ue).all())
+
+
+# ---- mixed-precision error guesses (FP32 submesh solves in the refinement steps)
+MIXED_CASES = [  # (family, level, coarse_level, d, seed): every anisotropic mesh FP32-eligible
+    ("sinprod2d", 6, 0, None, 0),
+    ("sinbump3d", 6, 3, None, 4),
+    ("sinbump3d", 7, 0, None, 1),
+]
+
+
+@pytest.mark.parametrize("fam,L,Lc,d,seed", MIXED_CASES)
+def test_mixed_precision_iterates(torch_dev, fam, L, Lc, d, seed):
+    """FP32 error guesses against the FP64 oracle.  The plan admits FP32 only where the FP32
+    solves are accurate to delta <= 1e-3 (6e-8 * prod cond(V_j)), so each update s_k e_k carries an
+    error of at most ~delta of itself: u_K differs from the oracle's by at most
+    delta * sum_k ||u_{k+1} - u_k||.  The initial guess is FP64 in both modes."""
+    _say("mixed", fam, L, Lc, seed)
+    P = make_problem(fam, L, seed=seed, d=d)
+    o = Oracle(P.d, P.alpha, P.beta, L, Lc or None, seed=seed + 17)
+    K = 5
+    ref = o.solve(P.s, P.g, max_iter=K, rtol=0, stag_window=0, keep_iterates=True)
+    pl = _plan(P, L, Lc, seed=seed + 17)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u0, info0 = pl.solve(s, g, max_iter=0, rtol=0, stag_window=0, precision="fp32")
+    assert _rel(u0.cpu().numpy(), ref.iterates[0].reshape(-1, order="F")) <= TOL_ITER
+    u, info = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0, precision="fp32")
+    assert info["precision"] == "fp32" and info["iterations"] == K
+    uK = ref.iterates[K].reshape(-1, order="F")
+    path = sum(np.linalg.norm(ref.iterates[k + 1] - ref.iterates[k]) for k in range(K))
+    err = np.linalg.norm(u.cpu().numpy() - uK)
+    _say("   mixed-precision |u_K - u_K(FP64 oracle)| / |u_K| = %.3e (path %.3e)" %
+         (err / np.linalg.norm(uK), path / np.linalg.norm(uK)))
+    assert err <= 2e-3 * path + 1e-12 * np.linalg.norm(uK)
+    # the residual history follows the FP64 one to the same relative accuracy
+    for k in range(K + 1):
+        assert abs(info["res_hist"][k] - ref.res_hist[k]) <= 2e-3 * ref.res_hist[k] + 1e-12 * ref.bnorm, k
+
+
+def test_mixed_precision_falls_back_on_ill_conditioned_meshes(torch_dev):
+    """Where FP32 transforms would not be accurate (6e-8 * prod cond(V_j) > 1e-3 on some mesh) the
+    plan keeps FP64 and says so; the result is the FP64 one."""
+    from paper_2303_01163_amd.asdsm import Plan
+    P = make_problem("sinbump3d", 6, seed=0, alpha=[0.1, 0.5, 0.8], beta=[4.5, 1.0, -1.0])
+    pl = Plan(3, P.alpha, P.beta, 6, 3, seed=5)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u64, i64 = pl.solve(s, g, max_iter=3, rtol=0, stag_window=0)
+    u32, i32 = pl.solve(s, g, max_iter=3, rtol=0, stag_window=0, precision="fp32")
+    assert i32["precision"] == "fp64" and i64["precision"] == "fp64"
+    assert np.array_equal(u64.cpu().numpy(), u32.cpu().numpy())
+
+
+def test_mixed_precision_full_solve(torch_dev):
+    """A complete solve with FP32 error guesses on a 127^3 FP32-eligible draw reaches the same
+    stopping status and residual level as the FP64 solve (within 1%)."""
+    from paper_2303_01163_amd.asdsm import Plan
+    P = make_problem("sinbump3d", 7, seed=1)
+    pl = Plan(3, P.alpha, P.beta, 7, 0, seed=1)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u64, i64 = pl.solve(s, g, max_iter=50)
+    u32, i32 = pl.solve(s, g, max_iter=50, precision="fp32")
+    assert i32["precision"] == "fp32"
+    _say("   fp64: %s after %d, rel res %.4e; fp32: %s after %d, rel res %.4e; |u32-u64|/|u64| %.3e" % (
+        i64["status_name"], i64["iterations"], i64["rnorm"] / i64["bnorm"], i32["status_name"],
+        i32["iterations"], i32["rnorm"] / i32["bnorm"], _rel(u32.cpu().numpy(), u64.cpu().numpy())))
+    assert i32["status"] == i64["status"]
+    assert abs(i32["rnorm"] - i64["rnorm"]) <= 1e-2 * i64["rnorm"]
