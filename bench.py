@@ -112,6 +112,8 @@ def parse():
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="error-phase submesh solves of the timed solves")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="members of the batched comparison (half 127^3, half 63^3); 0 skips it")
     return ap.parse_args()
 
 
@@ -197,6 +199,8 @@ def main():
     out["precision_used"] = infos[-1]["precision"]
     if not args.no_mixed:
         out["mixed_precision"] = mixed_precision(asdsm, make_problem, L, args, dev)
+    if args.batch > 0:
+        out["batched"] = batched(asdsm, make_problem, args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, L, args, iters)
     print(json.dumps(out))
@@ -228,6 +232,50 @@ def mixed_precision(asdsm, make_problem, L, args, dev, seed=1, steps=3):
             "iterations_fp64": i64["iterations"], "iterations_fp32": i32["iterations"],
             "rel_residual_fp64": i64["rnorm"] / i64["bnorm"], "rel_residual_fp32": i32["rnorm"] / i32["bnorm"],
             "rel_l2_fp32_vs_fp64": float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))}
+
+
+def batched(asdsm, make_problem, args, dev, steps=3):
+    """Many independent problems: half 127^3, half 63^3 draws of the same family (seeds 100, 101,
+    ...), solved one after the other (each plan's own graph) and as one batch (one graph replay
+    advances every member two steps).  Whole-job fine unknowns/s for both."""
+    import torch
+    plans, ss, gs = [], [], []
+    for i in range(args.batch):
+        L = 7 if i % 2 == 0 else 6
+        P = make_problem("sinbump3d", L, seed=100 + i)
+        try:
+            pl = asdsm.Plan(3, P.alpha, P.beta, L, 0, seed=100 + i, device=0)
+        except asdsm.AsdsmError:
+            continue  # draw outside what the plan supports (reported below)
+        plans.append(pl)
+        ss.append(torch.from_numpy(P.s_flat()).to(dev))
+        gs.append(torch.from_numpy(P.g_flat()).to(dev))
+    us = [torch.empty(p.n_fine, dtype=torch.float64, device=dev) for p in plans]
+    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
+    unknowns = sum(p.n_fine for p in plans)
+    for pl, s, g, u in zip(plans, ss, gs, us):
+        pl.solve(s, g, u=u, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for pl, s, g, u in zip(plans, ss, gs, us):
+            pl.solve(s, g, u=u, **kw)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / steps
+    batch = asdsm.Batch(plans)
+    batch.solve(ss, gs, us=us, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, infos = batch.solve(ss, gs, us=us, **kw)
+    torch.cuda.synchronize()
+    t_bat = (time.perf_counter() - t0) / steps
+    batch.close()
+    return {"members": len(plans), "requested": args.batch, "fine_unknowns": unknowns,
+            "iterations": [i["iterations"] for i in infos],
+            "ms_sequential": 1e3 * t_seq, "ms_batched": 1e3 * t_bat,
+            "unknowns_per_s_sequential": unknowns / t_seq, "unknowns_per_s_batched": unknowns / t_bat,
+            "speedup": t_seq / t_bat}
 
 
 def cpu_baseline(P, L, args, gpu_iters):

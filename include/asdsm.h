@@ -160,6 +160,28 @@ int asdsm_mesh_solve(asdsm_plan_t plan, unsigned mesh_mask, const double *rhs, d
 /* Release the plan and its tables (not the workspace).  NULL is ignored. */
 void asdsm_destroy(asdsm_plan_t plan);
 
+/* ---- batches of independent problems (any d, sizes and coefficients) ----
+ * A batch runs the refinement loops (Algorithm 4) of its member plans together: every replay of
+ * one captured HIP graph performs two refinement steps of every member, as parallel branches; a
+ * member whose stopping rule has fired turns into no-ops while the others continue.  Results are
+ * bitwise those of asdsm_solve on each plan with the same options. */
+typedef struct asdsm_batch_s *asdsm_batch_t;
+
+/* plans: host array of n distinct plans (1 <= n <= 4096) on one device, each with its workspace
+ * attached; they are borrowed and must outlive the batch, and must not be used by another call
+ * while a batch call runs.  Errors: ASDSM_E_ARG, ASDSM_E_DEVICE. */
+int asdsm_batch_create(asdsm_batch_t *out, const asdsm_plan_t *plans, int n);
+
+/* s, g, u: host arrays of n device pointers, member i in the layouts of asdsm_solve for plan i.
+ * opts: shared by all members (may be NULL: the defaults of asdsm_solve); with profile or eager
+ * set the members are solved one after the other.  stats: host array of n (may be NULL).
+ * Returns the largest member status (0, ASDSM_STAGNATED, ASDSM_MAXITER) or the first error. */
+int asdsm_batch_solve(asdsm_batch_t batch, const double *const *s, const double *const *g,
+                      double *const *u, const asdsm_opts *opts, asdsm_stats *stats);
+
+/* Release the batch's graph, streams and events (not the plans).  NULL is ignored. */
+void asdsm_batch_destroy(asdsm_batch_t batch);
+
 /* Thread-local description of the last error ("" if none). */
 const char *asdsm_last_error(void);
 

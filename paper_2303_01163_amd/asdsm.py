@@ -22,7 +22,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1}  # asdsm_opts.precision: FP64 or FP32 error-
 
 # symbols declared in include/asdsm.h
 EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_solve",
-            "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error")
+            "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error",
+            "asdsm_batch_create", "asdsm_batch_solve", "asdsm_batch_destroy")
 
 
 class AsdsmError(RuntimeError):
@@ -72,6 +73,13 @@ def load_library():
     lib.asdsm_mesh_solve.restype = c_int
     lib.asdsm_destroy.argtypes = [c_void_p]
     lib.asdsm_destroy.restype = None
+    lib.asdsm_batch_create.argtypes = [POINTER(c_void_p), POINTER(c_void_p), c_int]
+    lib.asdsm_batch_create.restype = c_int
+    lib.asdsm_batch_solve.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                      POINTER(Opts), POINTER(Stats)]
+    lib.asdsm_batch_solve.restype = c_int
+    lib.asdsm_batch_destroy.argtypes = [c_void_p]
+    lib.asdsm_batch_destroy.restype = None
     lib.asdsm_last_error.argtypes = []
     lib.asdsm_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -93,6 +101,35 @@ def _dptr(t, n=None, name="tensor"):
     if n is not None and t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
     return c_void_p(t.data_ptr())
+
+
+def _opts(max_iter, rtol, stag_window, stag_eta, resume, k0, profile, eager, precision):
+    hist = (c_double * (max_iter + 1))()
+    steps = (c_double * max(max_iter, 1))()
+    o = Opts(max_iter=int(max_iter), rtol=float(rtol), stag_window=int(stag_window),
+             stag_eta=float(stag_eta), resume=1 if resume else 0, k0=int(k0),
+             hist=ctypes.cast(hist, POINTER(c_double)),
+             step_hist=ctypes.cast(steps, POINTER(c_double)), profile=1 if profile else 0,
+             eager=1 if eager else 0, precision=PRECISIONS[precision])
+    return o, hist, steps
+
+
+def _info(rc, st, hist, steps, profile):
+    it = st.iterations
+    info = {
+        "status": st.status if rc >= 0 else rc, "status_name": STATUS_NAMES.get(st.status, str(st.status)),
+        "iterations": it, "bnorm": st.bnorm, "r0norm": st.r0norm, "rnorm": st.rnorm,
+        "res_hist": [hist[i] for i in range(it + 1)] if hist is not None else None,
+        "step_hist": [steps[i] for i in range(it)] if steps is not None else None,
+        "precision": {v: k for k, v in PRECISIONS.items()}[st.precision],
+    }
+    if profile:
+        info["phase_ms"] = {PHASES[q]: st.phase_ms[q] for q in range(NPHASE)}
+        info["phase_launches"] = {PHASES[q]: st.phase_launches[q] for q in range(NPHASE)}
+        info["phase_flops"] = {PHASES[q]: st.phase_flops[q] for q in range(NPHASE)}
+        info["phase_bytes"] = {PHASES[q]: st.phase_bytes[q] for q in range(NPHASE)}
+        info["total_ms"] = st.total_ms
+    return info
 
 
 class Plan:
@@ -136,39 +173,22 @@ class Plan:
         coarse = [j for j in range(self.d) if (mask >> j) & 1]
         return tuple([self.n_f] * len(fine) + [self.n_c] * len(coarse)), fine + coarse
 
+    @property
+    def n_faces(self) -> int:
+        return 2 * self.d * self.n_f ** (self.d - 1)
+
     def solve(self, s, g, u=None, max_iter=50, rtol=1e-10, stag_window=3, stag_eta=1e-3,
               resume=False, k0=0, profile=False, eager=False, precision="fp64"):
         import torch
         lib = load_library()
         if u is None:
             u = torch.empty(self.n_fine, dtype=torch.float64, device=self.device)
-        hist = (c_double * (max_iter + 1))()
-        steps = (c_double * max(max_iter, 1))()
-        o = Opts(max_iter=int(max_iter), rtol=float(rtol), stag_window=int(stag_window),
-                 stag_eta=float(stag_eta), resume=1 if resume else 0, k0=int(k0),
-                 hist=ctypes.cast(hist, POINTER(c_double)),
-                 step_hist=ctypes.cast(steps, POINTER(c_double)), profile=1 if profile else 0,
-                 eager=1 if eager else 0, precision=PRECISIONS[precision])
+        o, hist, steps = _opts(max_iter, rtol, stag_window, stag_eta, resume, k0, profile, eager, precision)
         st = Stats()
         with torch.cuda.device(self.device):
-            rc = _check(lib.asdsm_solve(self._h, _dptr(s, self.n_fine, "s"),
-                                        _dptr(g, 2 * self.d * self.n_f ** (self.d - 1), "g"),
+            rc = _check(lib.asdsm_solve(self._h, _dptr(s, self.n_fine, "s"), _dptr(g, self.n_faces, "g"),
                                         _dptr(u, self.n_fine, "u"), byref(o), byref(st)))
-        it = st.iterations
-        info = {
-            "status": rc, "status_name": STATUS_NAMES.get(rc, str(rc)), "iterations": it,
-            "bnorm": st.bnorm, "r0norm": st.r0norm, "rnorm": st.rnorm,
-            "res_hist": [hist[i] for i in range(it + 1)],
-            "step_hist": [steps[i] for i in range(it)],
-            "precision": {v: k for k, v in PRECISIONS.items()}[st.precision],
-        }
-        if profile:
-            info["phase_ms"] = {PHASES[q]: st.phase_ms[q] for q in range(NPHASE)}
-            info["phase_launches"] = {PHASES[q]: st.phase_launches[q] for q in range(NPHASE)}
-            info["phase_flops"] = {PHASES[q]: st.phase_flops[q] for q in range(NPHASE)}
-            info["phase_bytes"] = {PHASES[q]: st.phase_bytes[q] for q in range(NPHASE)}
-            info["total_ms"] = st.total_ms
-        return u, info
+        return u, _info(rc, st, hist, steps, profile)
 
     def residual(self, u, s, g, want_r=True):
         import torch
@@ -196,6 +216,50 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().asdsm_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent problems solved together (asdsm_batch_*): one graph replay advances every
+    member by two refinement steps.  The plans are borrowed and must outlive the batch."""
+
+    def __init__(self, plans):
+        import torch
+        lib = load_library()
+        self.plans = list(plans)
+        arr = (c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        self._h = c_void_p()
+        with torch.cuda.device(self.plans[0].device):
+            _check(lib.asdsm_batch_create(byref(self._h), arr, len(self.plans)))
+
+    def solve(self, ss, gs, us=None, max_iter=50, rtol=1e-10, stag_window=3, stag_eta=1e-3,
+              precision="fp64", profile=False, eager=False):
+        """Returns (list of u, list of info); the histories are not collected in a batch."""
+        import torch
+        lib = load_library()
+        n = len(self.plans)
+        if us is None:
+            us = [torch.empty(p.n_fine, dtype=torch.float64, device=p.device) for p in self.plans]
+        sp = (c_void_p * n)(*[_dptr(ss[i], self.plans[i].n_fine, "s").value for i in range(n)])
+        gp = (c_void_p * n)(*[_dptr(gs[i], self.plans[i].n_faces, "g").value for i in range(n)])
+        up = (c_void_p * n)(*[_dptr(us[i], self.plans[i].n_fine, "u").value for i in range(n)])
+        o = Opts(max_iter=int(max_iter), rtol=float(rtol), stag_window=int(stag_window),
+                 stag_eta=float(stag_eta), resume=0, k0=0, hist=None, step_hist=None,
+                 profile=1 if profile else 0, eager=1 if eager else 0, precision=PRECISIONS[precision])
+        st = (Stats * n)()
+        with torch.cuda.device(self.plans[0].device):
+            _check(lib.asdsm_batch_solve(self._h, sp, gp, up, byref(o), st))
+        return us, [_info(0, st[i], None, None, profile) for i in range(n)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().asdsm_batch_destroy(self._h)
             self._h = c_void_p()
 
     def __del__(self):

@@ -735,9 +735,8 @@ int build_graph(Plan &p, double *u) {
     return ASDSM_OK;
 }
 
-int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm_opts *o,
-               asdsm_stats *st) {
-    asdsm_opts opt;
+// Options with their defaults, validated.
+int normalize_opts(const asdsm_opts *o, asdsm_opts &opt) {
     if (o) {
         opt = *o;
     } else {
@@ -747,31 +746,27 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         opt.stag_window = 3;
         opt.stag_eta = 1e-3;
     }
-    if (!s || !g || !u) return fail(ASDSM_E_ARG, "s, g and u must be non-NULL device pointers");
     if (opt.max_iter < 0 || opt.max_iter >= kHistCap || !(opt.rtol >= 0.0) || opt.stag_window < 0 ||
         !(opt.stag_eta >= 0.0) || !(opt.stag_eta < 1.0))
         return fail(ASDSM_E_ARG, "invalid options (max_iter must be < " + std::to_string(kHistCap) + ")");
     if (opt.precision != ASDSM_PREC_FP64 && opt.precision != ASDSM_PREC_FP32)
         return fail(ASDSM_E_ARG, "invalid precision");
+    return ASDSM_OK;
+}
+
+// Everything before the refinement loop, enqueued on p.stream: the loop state and the random
+// cross-point choices of every step of this call, then Algorithm 1 (or the residual of the resumed
+// iterate).  Leaves p.gate pointing at the device stopping flag.
+int begin_solve(Plan &p, const double *s, const double *g, double *u, const asdsm_opts &opt) {
+    if (!s || !g || !u) return fail(ASDSM_E_ARG, "s, g and u must be non-NULL device pointers");
     if (int rc = require_ws(p)) return rc;
-    p.profiling = opt.profile != 0;
-    p.prof_failed = false;
     p.prec32 = (opt.precision == ASDSM_PREC_FP32) && p.fp32_ok;
-    p.ev_recs.clear();
-    const bool use_graph = !p.profiling && !opt.eager;
     for (int q = 0; q < ASDSM_NPHASE; ++q) {
         p.phase_ms[q] = 0.0;
         p.phase_launches[q] = 0;
         p.phase_flops[q] = 0.0;
         p.phase_bytes[q] = 0.0;
     }
-    hipEvent_t tb = nullptr, te = nullptr;
-    if (p.profiling) {
-        ASDSM_HIP_CHECK(hipEventCreate(&tb));
-        ASDSM_HIP_CHECK(hipEventCreate(&te));
-        ASDSM_HIP_CHECK(hipEventRecord(tb, p.stream));
-    }
-    // loop state and the random cross-point choices of every step of this call
     IterState &hs = *p.hstate;
     std::memset(&hs, 0, sizeof hs);
     hs.status = ASDSM_MAXITER;
@@ -802,6 +797,79 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         if (int rc = check_launch("residual")) return rc;
     }
     p.gate = &p.ws.state->done;
+    return ASDSM_OK;
+}
+
+// After the loop (the plan's stream is synchronised here): the final iterate into u, the
+// histories, the statistics.  Returns the status.
+int end_solve(Plan &p, double *u, const asdsm_opts &opt, asdsm_stats *st) {
+    p.gate = nullptr;
+    IterState &hs = *p.hstate;
+    if (int rc = read_state(p)) return rc;
+    if (int rc = read_scalars(p)) return rc;
+    const int it = hs.it;
+    if (!hs.done) hs.status = ASDSM_MAXITER;
+    if (hs.status == ASDSM_E_NUMERIC) return fail(ASDSM_E_NUMERIC, "non-finite right-hand side or residual");
+    // the iterate after `it` steps is in u for even it, in the second buffer for odd it
+    if (it % 2 == 1)
+        ASDSM_HIP_CHECK(hipMemcpyAsync(u, p.ws.u2, (size_t)p.geo.NF * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
+    double r0 = 0.0, rn = 0.0;
+    ASDSM_HIP_CHECK(hipMemcpyAsync(&r0, p.ws.hist, sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    ASDSM_HIP_CHECK(hipMemcpyAsync(&rn, p.ws.hist + it, sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    if (opt.hist)
+        ASDSM_HIP_CHECK(hipMemcpyAsync(opt.hist, p.ws.hist, (size_t)(it + 1) * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    if (opt.step_hist && it > 0)
+        ASDSM_HIP_CHECK(hipMemcpyAsync(opt.step_hist, p.ws.step_hist, (size_t)it * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
+    if (p.profiling)
+        if (int rc = collect_phases(p)) return rc;
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->status = hs.status;
+        st->iterations = it;
+        st->bnorm = std::sqrt(p.hscal[kScalBnorm2]);
+        st->r0norm = r0;
+        st->rnorm = rn;
+        st->precision = p.prec32 ? ASDSM_PREC_FP32 : ASDSM_PREC_FP64;
+        for (int q = 0; q < ASDSM_NPHASE; ++q) {
+            st->phase_ms[q] = p.phase_ms[q];
+            st->phase_launches[q] = p.phase_launches[q];
+            st->phase_flops[q] = p.phase_flops[q];
+            st->phase_bytes[q] = p.phase_bytes[q];
+        }
+    }
+    return hs.status;
+}
+
+// Events of a profiled call, destroyed on every exit path.
+struct CallEvents {
+    hipEvent_t tb = nullptr, te = nullptr;
+    ~CallEvents() {
+        if (tb) (void)hipEventDestroy(tb);
+        if (te) (void)hipEventDestroy(te);
+    }
+};
+
+int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm_opts *o,
+               asdsm_stats *st) {
+    asdsm_opts opt;
+    if (int rc = normalize_opts(o, opt)) return rc;
+    p.profiling = opt.profile != 0;
+    p.prof_failed = false;
+    p.ev_recs.clear();
+    struct ProfilingOff {
+        Plan &p;
+        ~ProfilingOff() { p.profiling = false; }
+    } off{p};
+    const bool use_graph = !p.profiling && !opt.eager;
+    CallEvents ev;
+    if (p.profiling) {
+        ASDSM_HIP_CHECK(hipEventCreate(&ev.tb));
+        ASDSM_HIP_CHECK(hipEventCreate(&ev.te));
+        ASDSM_HIP_CHECK(hipEventRecord(ev.tb, p.stream));
+    }
+    if (int rc = begin_solve(p, s, g, u, opt)) return rc;
+    IterState &hs = *p.hstate;
     int rc = ASDSM_OK;
     if (use_graph) {
         if (p.graph_u != u || !p.graph_exec || p.graph_prec32 != p.prec32) rc = build_graph(p, u);
@@ -826,54 +894,196 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
             if (hs.done) break;
         }
     }
-    p.gate = nullptr;
-    if (rc != ASDSM_OK) return rc;
-    if (int rc2 = read_state(p)) return rc2;
-    if (int rc2 = read_scalars(p)) return rc2;
-    const int it = hs.it;
-    if (!hs.done) hs.status = ASDSM_MAXITER;
-    if (hs.status == ASDSM_E_NUMERIC) return fail(ASDSM_E_NUMERIC, "non-finite right-hand side or residual");
-    // the iterate after `it` steps is in u for even it, in the second buffer for odd it
-    if (it % 2 == 1)
-        ASDSM_HIP_CHECK(hipMemcpyAsync(u, p.ws.u2, (size_t)p.geo.NF * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
-    double r0 = 0.0, rn = 0.0;
-    ASDSM_HIP_CHECK(hipMemcpyAsync(&r0, p.ws.hist, sizeof(double), hipMemcpyDeviceToHost, p.stream));
-    ASDSM_HIP_CHECK(hipMemcpyAsync(&rn, p.ws.hist + it, sizeof(double), hipMemcpyDeviceToHost, p.stream));
-    if (opt.hist)
-        ASDSM_HIP_CHECK(hipMemcpyAsync(opt.hist, p.ws.hist, (size_t)(it + 1) * sizeof(double), hipMemcpyDeviceToHost, p.stream));
-    if (opt.step_hist && it > 0)
-        ASDSM_HIP_CHECK(hipMemcpyAsync(opt.step_hist, p.ws.step_hist, (size_t)it * sizeof(double), hipMemcpyDeviceToHost, p.stream));
-    ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
-    if (p.profiling)
-        if (int rc2 = collect_phases(p)) return rc2;
-    const int status = hs.status;
-    if (st) {
-        std::memset(st, 0, sizeof *st);
-        st->status = status;
-        st->iterations = it;
-        st->bnorm = std::sqrt(p.hscal[kScalBnorm2]);
-        st->r0norm = r0;
-        st->rnorm = rn;
-        st->precision = p.prec32 ? ASDSM_PREC_FP32 : ASDSM_PREC_FP64;
-        for (int q = 0; q < ASDSM_NPHASE; ++q) {
-            st->phase_ms[q] = p.phase_ms[q];
-            st->phase_launches[q] = p.phase_launches[q];
-            st->phase_flops[q] = p.phase_flops[q];
-            st->phase_bytes[q] = p.phase_bytes[q];
-        }
-        if (p.profiling) {
-            ASDSM_HIP_CHECK(hipEventRecord(te, p.stream));
-            ASDSM_HIP_CHECK(hipEventSynchronize(te));
-            float ms = 0.f;
-            ASDSM_HIP_CHECK(hipEventElapsedTime(&ms, tb, te));
-            st->total_ms = ms;
-        }
+    if (rc != ASDSM_OK) {
+        p.gate = nullptr;
+        return rc;
     }
-    if (tb) (void)hipEventDestroy(tb);
-    if (te) (void)hipEventDestroy(te);
-    p.profiling = false;
+    const int status = end_solve(p, u, opt, st);
+    if (status < 0) return status;
+    if (st && p.profiling) {
+        ASDSM_HIP_CHECK(hipEventRecord(ev.te, p.stream));
+        ASDSM_HIP_CHECK(hipEventSynchronize(ev.te));
+        float ms = 0.f;
+        ASDSM_HIP_CHECK(hipEventElapsedTime(&ms, ev.tb, ev.te));
+        st->total_ms = ms;
+    }
     set_error("");
     return status;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batches: independent problems (any sizes) whose refinement loops run as one graph.  Each
+// replay of the graph performs two gated refinement steps of every member, as parallel branches
+// (one capture stream per member); a member whose stopping rule has fired turns into no-ops while
+// the others continue.  The host checks every member's state after every two replays.
+// ---------------------------------------------------------------------------------------------
+struct Batch {
+    std::vector<Plan *> plans;
+    hipStream_t root = nullptr;              // launch stream of the graph
+    hipStream_t cap = nullptr;               // capture root
+    std::vector<hipStream_t> branch;         // capture stream of each member
+    std::vector<hipEvent_t> ready, joined;   // member -> root dependencies
+    hipEvent_t fork = nullptr, done = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<double *> graph_u;
+    std::vector<bool> graph_prec32;
+};
+
+void destroy_batch_graph(Batch &b) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    b.graph_u.clear();
+    b.graph_prec32.clear();
+}
+
+void release_batch(Batch &b) {
+    destroy_batch_graph(b);
+    for (hipStream_t s : b.branch) if (s) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b.ready) if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b.joined) if (e) (void)hipEventDestroy(e);
+    if (b.fork) (void)hipEventDestroy(b.fork);
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.cap) (void)hipStreamDestroy(b.cap);
+    if (b.root) (void)hipStreamDestroy(b.root);
+    b.branch.clear();
+    b.ready.clear();
+    b.joined.clear();
+    b.fork = b.done = nullptr;
+    b.cap = b.root = nullptr;
+}
+
+int build_batch(Batch &b, int n) {
+    ASDSM_HIP_CHECK(hipStreamCreateWithFlags(&b.root, hipStreamNonBlocking));
+    ASDSM_HIP_CHECK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+    ASDSM_HIP_CHECK(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
+    ASDSM_HIP_CHECK(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
+    b.branch.assign(n, nullptr);
+    b.ready.assign(n, nullptr);
+    b.joined.assign(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+        ASDSM_HIP_CHECK(hipStreamCreateWithFlags(&b.branch[i], hipStreamNonBlocking));
+        ASDSM_HIP_CHECK(hipEventCreateWithFlags(&b.ready[i], hipEventDisableTiming));
+        ASDSM_HIP_CHECK(hipEventCreateWithFlags(&b.joined[i], hipEventDisableTiming));
+    }
+    return ASDSM_OK;
+}
+
+// Capture two refinement steps of every member (u -> u2 -> u) as parallel branches.
+int capture_batch_graph(Batch &b, double *const *u) {
+    destroy_batch_graph(b);
+    const int n = (int)b.plans.size();
+    ASDSM_HIP_CHECK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
+    int rc = ASDSM_OK;
+    hipError_t e = hipEventRecord(b.fork, b.cap);
+    if (e != hipSuccess) rc = fail(ASDSM_E_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
+    for (int i = 0; i < n && rc == ASDSM_OK; ++i) {
+        Plan &p = *b.plans[i];
+        e = hipStreamWaitEvent(b.branch[i], b.fork, 0);
+        if (e != hipSuccess) {
+            rc = fail(ASDSM_E_DEVICE, std::string("hipStreamWaitEvent: ") + hipGetErrorString(e));
+            break;
+        }
+        hipStream_t saved = p.stream;
+        p.stream = b.branch[i];
+        rc = refine_step(p, u[i], p.ws.u2);
+        if (rc == ASDSM_OK) rc = refine_step(p, p.ws.u2, u[i]);
+        p.stream = saved;
+        if (rc != ASDSM_OK) break;
+        e = hipEventRecord(b.joined[i], b.branch[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b.cap, b.joined[i], 0);
+        if (e != hipSuccess) rc = fail(ASDSM_E_DEVICE, std::string("batch join: ") + hipGetErrorString(e));
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(b.cap, &graph);
+    if (rc != ASDSM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    b.graph = graph;
+    e = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        destroy_batch_graph(b);
+        return fail(ASDSM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    b.graph_u.assign(u, u + n);
+    for (int i = 0; i < n; ++i) b.graph_prec32.push_back(b.plans[i]->prec32);
+    return ASDSM_OK;
+}
+
+int batch_solve_impl(Batch &b, const double *const *s, const double *const *g, double *const *u,
+                     const asdsm_opts *o, asdsm_stats *st) {
+    asdsm_opts opt;
+    if (int rc = normalize_opts(o, opt)) return rc;
+    const int n = (int)b.plans.size();
+    if (!s || !g || !u) return fail(ASDSM_E_ARG, "s, g and u must be non-NULL arrays of n pointers");
+    if (opt.profile || opt.eager) {
+        // one member after the other, each on its own loop
+        int worst = ASDSM_OK;
+        for (int i = 0; i < n; ++i) {
+            const int rc = solve_impl(*b.plans[i], s[i], g[i], u[i], &opt, st ? st + i : nullptr);
+            if (rc < 0) return rc;
+            worst = std::max(worst, rc);
+        }
+        return worst;
+    }
+    for (int i = 0; i < n; ++i) {
+        Plan &p = *b.plans[i];
+        p.profiling = false;
+        if (int rc = begin_solve(p, s[i], g[i], u[i], opt)) return rc;
+        ASDSM_HIP_CHECK(hipEventRecord(b.ready[i], p.stream));
+        ASDSM_HIP_CHECK(hipStreamWaitEvent(b.root, b.ready[i], 0));
+    }
+    bool rebuild = !b.exec || (int)b.graph_u.size() != n;
+    for (int i = 0; i < n && !rebuild; ++i)
+        rebuild = b.graph_u[i] != u[i] || b.graph_prec32[i] != b.plans[i]->prec32;
+    int rc = rebuild ? capture_batch_graph(b, u) : ASDSM_OK;
+    int steps = 0;
+    while (rc == ASDSM_OK) {
+        for (int rep = 0; rep < 2 && steps < opt.max_iter; ++rep, steps += 2) {
+            hipError_t e = hipGraphLaunch(b.exec, b.root);
+            if (e != hipSuccess) {
+                rc = fail(ASDSM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+                break;
+            }
+        }
+        if (rc != ASDSM_OK) break;
+        for (int i = 0; i < n; ++i) {
+            Plan &p = *b.plans[i];
+            hipError_t e = hipMemcpyAsync(p.hstate, p.ws.state, sizeof(IterState), hipMemcpyDeviceToHost, b.root);
+            if (e != hipSuccess) {
+                rc = fail(ASDSM_E_DEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+                break;
+            }
+        }
+        if (rc != ASDSM_OK) break;
+        hipError_t e = hipStreamSynchronize(b.root);
+        if (e != hipSuccess) {
+            rc = fail(ASDSM_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+            break;
+        }
+        bool all = true;
+        for (int i = 0; i < n; ++i) all = all && b.plans[i]->hstate->done;
+        if (all || steps >= opt.max_iter) break;
+    }
+    // the members' streams continue after the graph's work
+    ASDSM_HIP_CHECK(hipEventRecord(b.done, b.root));
+    for (int i = 0; i < n; ++i) ASDSM_HIP_CHECK(hipStreamWaitEvent(b.plans[i]->stream, b.done, 0));
+    if (rc != ASDSM_OK) {
+        for (int i = 0; i < n; ++i) b.plans[i]->gate = nullptr;
+        return rc;
+    }
+    int worst = ASDSM_OK;
+    for (int i = 0; i < n; ++i) {
+        const int r = end_solve(*b.plans[i], u[i], opt, st ? st + i : nullptr);
+        if (r < 0) return r;
+        worst = std::max(worst, r);
+    }
+    set_error("");
+    return worst;
 }
 
 }  // namespace
@@ -968,6 +1178,45 @@ int asdsm_mesh_solve(asdsm_plan_t plan, unsigned mesh_mask, const double *rhs, d
     ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
     set_error("");
     return ASDSM_OK;
+}
+
+struct asdsm_batch_s {
+    Batch b;
+};
+
+int asdsm_batch_create(asdsm_batch_t *out, const asdsm_plan_t *plans, int n) {
+    if (!out) return fail(ASDSM_E_ARG, "out must be non-NULL");
+    *out = nullptr;
+    if (!plans || n < 1 || n > 4096) return fail(ASDSM_E_ARG, "plans must hold 1..4096 plans");
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) return fail(ASDSM_E_ARG, "NULL plan in batch");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(ASDSM_E_ARG, "a plan appears twice in the batch");
+        if (plans[i]->p.device != plans[0]->p.device) return fail(ASDSM_E_ARG, "batch plans on different devices");
+    }
+    asdsm_batch_s *h = new (std::nothrow) asdsm_batch_s();
+    if (!h) return fail(ASDSM_E_ARG, "out of host memory");
+    for (int i = 0; i < n; ++i) h->b.plans.push_back(&plans[i]->p);
+    if (int rc = build_batch(h->b, n)) {
+        release_batch(h->b);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    set_error("");
+    return ASDSM_OK;
+}
+
+int asdsm_batch_solve(asdsm_batch_t batch, const double *const *s, const double *const *g,
+                      double *const *u, const asdsm_opts *opts, asdsm_stats *stats) {
+    if (!batch) return fail(ASDSM_E_ARG, "batch must be non-NULL");
+    return batch_solve_impl(batch->b, s, g, u, opts, stats);
+}
+
+void asdsm_batch_destroy(asdsm_batch_t batch) {
+    if (!batch) return;
+    release_batch(batch->b);
+    delete batch;
 }
 
 void asdsm_destroy(asdsm_plan_t plan) {

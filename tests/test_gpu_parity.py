@@ -397,3 +397,38 @@ def test_mixed_precision_full_solve(torch_dev):
         i32["iterations"], i32["rnorm"] / i32["bnorm"], _rel(u32.cpu().numpy(), u64.cpu().numpy())))
     assert i32["status"] == i64["status"]
     assert abs(i32["rnorm"] - i64["rnorm"]) <= 1e-2 * i64["rnorm"]
+
+
+# ---- batches: independent problems advanced together by one graph
+BATCH_MEMBERS = [  # (family, level, coarse_level, d, seed, alpha, beta)
+    ("sinprod2d", 6, 0, None, 0, None, None),
+    ("sinbump3d", 5, 0, None, 2, None, None),
+    ("sinbump3d", 6, 3, None, 4, None, None),
+    ("sinprod", 5, 3, 3, 1, None, None),
+    ("sinbump3d", 6, 3, None, 0, [0.1, 0.5, 0.8], [4.5, 1.0, -1.0]),  # needs refinement sweeps
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_matches_individual_solves(torch_dev, precision):
+    """Every member of a batch ends bitwise where asdsm_solve on its own plan ends (same kernels,
+    fixed-order reductions), including members that stop earlier than others."""
+    from paper_2303_01163_amd.asdsm import Batch, Plan
+    plans, ss, gs = [], [], []
+    for fam, L, Lc, d, seed, al, be in BATCH_MEMBERS:
+        P = make_problem(fam, L, seed=seed, d=d, alpha=al, beta=be)
+        plans.append(Plan(P.d, P.alpha, P.beta, L, Lc, seed=seed + 3))
+        ss.append(_t(torch_dev, P.s_flat()))
+        gs.append(_t(torch_dev, P.g_flat()))
+    ref = [pl.solve(s, g, max_iter=40, precision=precision) for pl, s, g in zip(plans, ss, gs)]
+    iters = sorted({info["iterations"] for _, info in ref})
+    _say("   individual iteration counts", [info["iterations"] for _, info in ref])
+    assert len(iters) > 1  # members stop at different steps
+    batch = Batch(plans)
+    for rep in range(2):  # the second call replays the captured graph
+        us, infos = batch.solve(ss, gs, max_iter=40, precision=precision)
+        for (u_ref, i_ref), u, info in zip(ref, us, infos):
+            assert info["iterations"] == i_ref["iterations"] and info["status"] == i_ref["status"]
+            assert info["precision"] == i_ref["precision"]
+            assert np.array_equal(u.cpu().numpy(), u_ref.cpu().numpy())
+            assert info["rnorm"] == i_ref["rnorm"]
