@@ -112,6 +112,7 @@ def parse():
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="error-phase submesh solves of the timed solves")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the size-based transform tiles")
     ap.add_argument("--batch", type=int, default=16,
                     help="members of the batched comparison (half 127^3, half 63^3); 0 skips it")
     return ap.parse_args()
@@ -140,6 +141,7 @@ def main():
     u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
     kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3,
               precision=args.precision)
+    tuned = plan.autotune(repeats=10) if not args.no_autotune else None
 
     for _ in range(args.warmup):
         plan.solve(s, g, u=u, **kw)
@@ -197,6 +199,7 @@ def main():
         "stencil_effective": stencil,
     }
     out["precision_used"] = infos[-1]["precision"]
+    out["autotune"] = tuned
     if not args.no_mixed:
         out["mixed_precision"] = mixed_precision(asdsm, make_problem, L, args, dev)
     if args.batch > 0:

@@ -157,6 +157,18 @@ int asdsm_residual(asdsm_plan_t plan, const double *u, const double *s, const do
  * first listed axis fastest.  rhs and x may not alias. */
 int asdsm_mesh_solve(asdsm_plan_t plan, unsigned mesh_mask, const double *rhs, double *x);
 
+/* Autotuner: times the anisotropic-mesh solve (Algorithm 1 steps 1.1/1.2: the FP64 mode
+ * transforms and the coarse-axis elimination) with every transform tile shape, `repeats` solves
+ * each on reproducible random right-hand sides, and keeps the fastest for this plan (the default,
+ * before tuning, picks by problem size).  Needs the workspace; overwrites the plan's mesh buffers.
+ *   tile        : host output, may be NULL: the chosen shape (asdsm_tile_name names it).
+ *   ms_per_solve: host output, may be NULL: its time per anisotropic solve.
+ * Errors: ASDSM_E_ARG (repeats outside 1..1000), ASDSM_E_WORKSPACE, ASDSM_E_DEVICE. */
+int asdsm_autotune(asdsm_plan_t plan, int repeats, int *tile, double *ms_per_solve);
+
+/* Static name of a tile shape returned by asdsm_autotune ("auto" for unknown values). */
+const char *asdsm_tile_name(int tile);
+
 /* Release the plan and its tables (not the workspace).  NULL is ignored. */
 void asdsm_destroy(asdsm_plan_t plan);
 

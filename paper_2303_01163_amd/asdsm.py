@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1}  # asdsm_opts.precision: FP64 or FP32 error-
 # symbols declared in include/asdsm.h
 EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_solve",
             "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error",
-            "asdsm_batch_create", "asdsm_batch_solve", "asdsm_batch_destroy")
+            "asdsm_batch_create", "asdsm_batch_solve", "asdsm_batch_destroy", "asdsm_autotune",
+            "asdsm_tile_name")
 
 
 class AsdsmError(RuntimeError):
@@ -73,6 +74,10 @@ def load_library():
     lib.asdsm_mesh_solve.restype = c_int
     lib.asdsm_destroy.argtypes = [c_void_p]
     lib.asdsm_destroy.restype = None
+    lib.asdsm_autotune.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_double)]
+    lib.asdsm_autotune.restype = c_int
+    lib.asdsm_tile_name.argtypes = [c_int]
+    lib.asdsm_tile_name.restype = ctypes.c_char_p
     lib.asdsm_batch_create.argtypes = [POINTER(c_void_p), POINTER(c_void_p), c_int]
     lib.asdsm_batch_create.restype = c_int
     lib.asdsm_batch_solve.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
@@ -189,6 +194,15 @@ class Plan:
             rc = _check(lib.asdsm_solve(self._h, _dptr(s, self.n_fine, "s"), _dptr(g, self.n_faces, "g"),
                                         _dptr(u, self.n_fine, "u"), byref(o), byref(st)))
         return u, _info(rc, st, hist, steps, profile)
+
+    def autotune(self, repeats=10):
+        """Choose this plan's FP64 transform tile shape by timing (asdsm_autotune)."""
+        import torch
+        lib = load_library()
+        tile, ms = c_int(), c_double()
+        with torch.cuda.device(self.device):
+            _check(lib.asdsm_autotune(self._h, int(repeats), byref(tile), byref(ms)))
+        return {"tile": lib.asdsm_tile_name(tile.value).decode(), "ms_per_aniso_solve": ms.value}
 
     def residual(self, u, s, g, want_r=True):
         import torch

@@ -120,6 +120,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
     GemmJob j{};
     j.nbox = nb;
     j.gate = p.gate;
+    j.tile = p.tile_aniso;
     // forward transform along canonical axis 0 (contiguous): in -> Y
     {
         j.M = (d == 2) ? Nc : Nf * Nc;
@@ -735,6 +736,63 @@ int build_graph(Plan &p, double *u) {
     return ASDSM_OK;
 }
 
+// Events of a profiled call, destroyed on every exit path.
+struct CallEvents {
+    hipEvent_t tb = nullptr, te = nullptr;
+    ~CallEvents() {
+        if (tb) (void)hipEventDestroy(tb);
+        if (te) (void)hipEventDestroy(te);
+    }
+};
+
+// Autotuner: time the anisotropic solve (the four FP64 mode transforms and the line elimination)
+// with every transform tile shape on reproducible random right-hand sides and keep the fastest.
+int autotune_impl(Plan &p, int reps, int *best_tile, double *best_ms) {
+    if (int rc = require_ws(p)) return rc;
+    if (reps < 1 || reps > 1000) return fail(ASDSM_E_ARG, "repeats must be in 1..1000");
+    const unsigned kbits = (1u << p.d) - 1;
+    double *in[kMaxD] = {}, *out[kMaxD] = {};
+    for (int k = 0; k < p.d; ++k) {
+        const unsigned m = 1u << k;
+        in[k] = rhs_buf(p, m);
+        out[k] = sol_buf(p, m);
+        launch_fill_random(in[k], p.mesh[m].size, 0x7A11ull * (m + 1), p.stream);
+    }
+    p.gate = nullptr;
+    CallEvents ev;
+    ASDSM_HIP_CHECK(hipEventCreate(&ev.tb));
+    ASDSM_HIP_CHECK(hipEventCreate(&ev.te));
+    const int saved = p.tile_aniso;
+    int best = saved;
+    double best_t = 1e300;
+    for (int tile : kGemmTiles) {
+        p.tile_aniso = tile;
+        int rc = solve_aniso(p, kbits, in, out, 0);  // warm-up (code objects, caches)
+        if (rc == ASDSM_OK) {
+            ASDSM_HIP_CHECK(hipEventRecord(ev.tb, p.stream));
+            for (int r = 0; r < reps && rc == ASDSM_OK; ++r) rc = solve_aniso(p, kbits, in, out, 0);
+            ASDSM_HIP_CHECK(hipEventRecord(ev.te, p.stream));
+        }
+        if (rc != ASDSM_OK) {
+            p.tile_aniso = saved;
+            return rc;
+        }
+        ASDSM_HIP_CHECK(hipEventSynchronize(ev.te));
+        float ms = 0.f;
+        ASDSM_HIP_CHECK(hipEventElapsedTime(&ms, ev.tb, ev.te));
+        const double t = (double)ms / reps;
+        if (t < best_t) {
+            best_t = t;
+            best = tile;
+        }
+    }
+    p.tile_aniso = best;
+    destroy_graph(p);  // captured launches carry the old tile choice
+    if (best_tile) *best_tile = best;
+    if (best_ms) *best_ms = best_t;
+    return ASDSM_OK;
+}
+
 // Options with their defaults, validated.
 int normalize_opts(const asdsm_opts *o, asdsm_opts &opt) {
     if (o) {
@@ -840,15 +898,6 @@ int end_solve(Plan &p, double *u, const asdsm_opts &opt, asdsm_stats *st) {
     }
     return hs.status;
 }
-
-// Events of a profiled call, destroyed on every exit path.
-struct CallEvents {
-    hipEvent_t tb = nullptr, te = nullptr;
-    ~CallEvents() {
-        if (tb) (void)hipEventDestroy(tb);
-        if (te) (void)hipEventDestroy(te);
-    }
-};
 
 int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm_opts *o,
                asdsm_stats *st) {
@@ -1212,6 +1261,15 @@ int asdsm_batch_solve(asdsm_batch_t batch, const double *const *s, const double 
     if (!batch) return fail(ASDSM_E_ARG, "batch must be non-NULL");
     return batch_solve_impl(batch->b, s, g, u, opts, stats);
 }
+
+int asdsm_autotune(asdsm_plan_t plan, int repeats, int *tile, double *ms_per_solve) {
+    if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
+    const int rc = autotune_impl(plan->p, repeats, tile, ms_per_solve);
+    if (rc == ASDSM_OK) set_error("");
+    return rc;
+}
+
+const char *asdsm_tile_name(int tile) { return gemm_tile_name(tile); }
 
 void asdsm_batch_destroy(asdsm_batch_t batch) {
     if (!batch) return;

@@ -142,6 +142,7 @@ struct Plan {
     std::vector<float> W32[kMaxD], V32[kMaxD];
     float *dW32[kMaxD] = {}, *dV32[kMaxD] = {};
     bool prec32 = false;             // this call's error guesses run in FP32
+    int tile_aniso = 0;              // FP64 transform tile of the anisotropic solves (0: auto)
     bool fp32_ok = false;            // every anisotropic mesh: 6e-8 * prod cond(V_j) <= 1e-3
     // hole line elimination factors (d = 3): for the mode pair q = m0 + nh m1 of the two transformed
     // hole axes, step c: hole_inv[c nh^2 + q] = 1/pivot_c, hole_cp[...] = super / pivot_c

@@ -135,15 +135,31 @@ static void launch_gemm_tile(const GemmJob &job, hipStream_t st) {
         ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, false>), grid, dim3(256), 0, st, job);
 }
 
+const char *gemm_tile_name(int tile) {
+    switch (tile) {
+        case kTile32x32: return "32x32 k32";
+        case kTile64x32: return "64x32 k32";
+        case kTile32x64: return "32x64 k32";
+        case kTile64x64: return "64x64 k16";
+        default: return "auto";
+    }
+}
+
 bool launch_gemm(const GemmJob &job, hipStream_t st) {
     // operand layouts of the mode transforms: A k-fast, B k-fast or n-fast
     if (job.sAk != 1 || (job.sBk != 1 && job.sBn != 1)) return false;
-    // 64 x 64 tiles once there are enough of them to fill the chip twice, else 32 x 32
-    const long long t64 = ((job.N + 63) / 64) * ((job.M + 63) / 64) * job.nbox * job.nbatch;
-    if (t64 >= 512)
-        launch_gemm_tile<64, 64, 16>(job, st);
-    else
-        launch_gemm_tile<32, 32, 32>(job, st);
+    int tile = job.tile;
+    if (tile == kTileAuto) {
+        // 64 x 64 tiles once there are enough of them to fill the chip twice, else 32 x 32
+        const long long t64 = ((job.N + 63) / 64) * ((job.M + 63) / 64) * job.nbox * job.nbatch;
+        tile = (t64 >= 512) ? kTile64x64 : kTile32x32;
+    }
+    switch (tile) {
+        case kTile64x32: launch_gemm_tile<64, 32, 32>(job, st); break;
+        case kTile32x64: launch_gemm_tile<32, 64, 32>(job, st); break;
+        case kTile64x64: launch_gemm_tile<64, 64, 16>(job, st); break;
+        default: launch_gemm_tile<32, 32, 32>(job, st); break;
+    }
     return true;
 }
 

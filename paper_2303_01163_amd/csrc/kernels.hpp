@@ -43,7 +43,13 @@ struct GemmJob {
     int accum;                 // 1: C += A B, 0: C = A B
     const int *gate;           // return at once when *gate != 0 (may be nullptr)
     long long sAb, sAi, sAk, sBb, sBk, sBn, sCb, sCi, sCn;
+    int tile;                  // FP64 tile shape: kTileAuto or one of kGemmTiles (autotuner)
 };
+
+// FP64 transform tile shapes (TM x TN, K chunk), chosen per plan by asdsm_autotune.
+enum GemmTile { kTileAuto = 0, kTile32x32 = 1, kTile64x32 = 2, kTile32x64 = 3, kTile64x64 = 4 };
+constexpr int kGemmTiles[] = {kTile32x32, kTile64x32, kTile32x64, kTile64x64};
+const char *gemm_tile_name(int tile);
 
 // Thomas elimination along the coarse (slowest) axis of anisotropic boxes after their fine axes
 // have been diagonalised: for each mode, (T_coarse + sigma I) x = f, sigma = sum of fine eigenvalues.

@@ -432,3 +432,19 @@ def test_batch_matches_individual_solves(torch_dev, precision):
             assert info["precision"] == i_ref["precision"]
             assert np.array_equal(u.cpu().numpy(), u_ref.cpu().numpy())
             assert info["rnorm"] == i_ref["rnorm"]
+
+
+def test_autotuned_plan_keeps_parity(torch_dev):
+    """After the autotuner has picked a transform tile shape, the iterates still match the oracle."""
+    P = make_problem("sinbump3d", 6, seed=4)
+    o = Oracle(P.d, P.alpha, P.beta, 6, 3, seed=21)
+    ref = o.solve(P.s, P.g, max_iter=3, rtol=0, stag_window=0, keep_iterates=True)
+    pl = _plan(P, 6, 3, seed=21)
+    tuned = pl.autotune(repeats=3)
+    _say("   autotune:", tuned)
+    assert tuned["tile"] in ("32x32 k32", "64x32 k32", "32x64 k32", "64x64 k16")
+    assert tuned["ms_per_aniso_solve"] > 0
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    for K in (0, 3):
+        u, info = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0)
+        assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
