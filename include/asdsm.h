@@ -59,7 +59,8 @@ extern "C" {
 #define ASDSM_PHASE_FILLER     4   /* hole right-hand sides, hole solves, fine-vector write     */
 #define ASDSM_PHASE_DOTS       5   /* q = A e and the line-search inner products                */
 #define ASDSM_PHASE_UPDATE     6   /* u += s e fused with r = b - A u, gather, norm             */
-#define ASDSM_NPHASE           7
+#define ASDSM_PHASE_LEARNED    7   /* learned proposals: features, network, scaling, line search */
+#define ASDSM_NPHASE           8
 
 typedef struct asdsm_plan_s *asdsm_plan_t;
 

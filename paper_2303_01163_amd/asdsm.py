@@ -1,4 +1,4 @@
-"""Thin Python binding of the ASDSM C ABI (``include/asdsm.h``).
+"""Thin Python binding of the ASDSM C ABI (``include/asdsm.h``, ``include/asdsm_learn.h``).
 
 Argument marshalling only: every step of the method runs inside ``libasdsm.so`` on the GPU.  PyTorch
 provides the device memory (float64 tensors, the byte workspace) and the stream.  There is no CPU
@@ -15,8 +15,8 @@ LIB_PATH = Path(__file__).resolve().with_name("libasdsm.so")
 ASDSM_OK, ASDSM_STAGNATED, ASDSM_MAXITER = 0, 1, 2
 ASDSM_E_ARG, ASDSM_E_NESTING, ASDSM_E_WORKSPACE = -1, -2, -3
 ASDSM_E_NUMERIC, ASDSM_E_DEVICE, ASDSM_E_UNSUPPORTED = -4, -5, -6
-NPHASE = 7
-PHASES = ("rhs", "transform", "line", "skeleton", "filler", "dots", "update")
+NPHASE = 8
+PHASES = ("rhs", "transform", "line", "skeleton", "filler", "dots", "update", "learned")
 STATUS_NAMES = {0: "ok", 1: "stagnated", 2: "maxiter"}
 PRECISIONS = {"fp64": 0, "fp32": 1}  # asdsm_opts.precision: FP64 or FP32 error-phase submesh solves
 
@@ -25,6 +25,12 @@ EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_
             "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error",
             "asdsm_batch_create", "asdsm_batch_solve", "asdsm_batch_destroy", "asdsm_autotune",
             "asdsm_tile_name")
+# symbols declared in include/asdsm_learn.h
+EXPORTED_LEARN = ("asdsm_net_create", "asdsm_net_param_count", "asdsm_net_workspace_size",
+                  "asdsm_net_set_workspace", "asdsm_net_params", "asdsm_net_forward",
+                  "asdsm_net_gradient", "asdsm_net_bind", "asdsm_net_features",
+                  "asdsm_solve_learned", "asdsm_net_adam", "asdsm_net_destroy")
+NET_LOSSES = {"mse": 0, "residual": 1}  # asdsm_net_gradient loss kinds
 
 
 class AsdsmError(RuntimeError):
@@ -85,6 +91,32 @@ def load_library():
     lib.asdsm_batch_solve.restype = c_int
     lib.asdsm_batch_destroy.argtypes = [c_void_p]
     lib.asdsm_batch_destroy.restype = None
+    F = POINTER(ctypes.c_float)
+    lib.asdsm_net_create.argtypes = [POINTER(c_void_p), c_int, c_uint64, c_void_p]
+    lib.asdsm_net_create.restype = c_int
+    lib.asdsm_net_param_count.argtypes = [c_void_p, POINTER(c_size_t)]
+    lib.asdsm_net_param_count.restype = c_int
+    lib.asdsm_net_workspace_size.argtypes = [c_void_p, POINTER(c_size_t)]
+    lib.asdsm_net_workspace_size.restype = c_int
+    lib.asdsm_net_set_workspace.argtypes = [c_void_p, c_void_p, c_size_t]
+    lib.asdsm_net_set_workspace.restype = c_int
+    lib.asdsm_net_params.argtypes = [c_void_p, F, c_int]
+    lib.asdsm_net_params.restype = c_int
+    lib.asdsm_net_forward.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.asdsm_net_forward.restype = c_int
+    lib.asdsm_net_gradient.argtypes = [c_void_p, c_void_p, c_void_p, c_int, POINTER(c_double), F]
+    lib.asdsm_net_gradient.restype = c_int
+    lib.asdsm_net_bind.argtypes = [c_void_p, c_void_p]
+    lib.asdsm_net_bind.restype = c_int
+    lib.asdsm_net_features.argtypes = [c_void_p, c_void_p, c_double, POINTER(c_int), c_void_p, c_void_p]
+    lib.asdsm_net_features.restype = c_int
+    lib.asdsm_solve_learned.argtypes = [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p,
+                                        POINTER(Opts), POINTER(Stats), POINTER(c_int)]
+    lib.asdsm_solve_learned.restype = c_int
+    lib.asdsm_net_adam.argtypes = [c_void_p, ctypes.c_float]
+    lib.asdsm_net_adam.restype = c_int
+    lib.asdsm_net_destroy.argtypes = [c_void_p]
+    lib.asdsm_net_destroy.restype = None
     lib.asdsm_last_error.argtypes = []
     lib.asdsm_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -103,6 +135,17 @@ def _dptr(t, n=None, name="tensor"):
         raise TypeError(f"{name} must be a CUDA tensor")
     if t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return c_void_p(t.data_ptr())
+
+
+def _fptr(t, n=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 tensor")
     if n is not None and t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
     return c_void_p(t.data_ptr())
@@ -281,3 +324,128 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """Correction network of the learned solve (include/asdsm_learn.h) for n^3 volumes."""
+
+    CHANNELS = 16  # stored input channels per voxel (the first 7 are read)
+
+    def __init__(self, n, seed=0, device=None, stream=None):
+        import torch
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the correction network needs a HIP GPU; none is available")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.n = int(n)
+        self.plan = None
+        self._h = c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.asdsm_net_create(byref(self._h), self.n, c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF),
+                                        c_void_p(self.stream.cuda_stream)))
+            cnt, nbytes = c_size_t(), c_size_t()
+            _check(lib.asdsm_net_param_count(self._h, byref(cnt)))
+            _check(lib.asdsm_net_workspace_size(self._h, byref(nbytes)))
+            self.n_params = int(cnt.value)
+            self.workspace_bytes = int(nbytes.value)
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self._ws.data_ptr() + 255) // 256 * 256
+            _check(lib.asdsm_net_set_workspace(self._h, c_void_p(aligned), c_size_t(self.workspace_bytes)))
+
+    @property
+    def n_vox(self) -> int:
+        return self.n ** 3
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(load_library().asdsm_net_params(self._h, out.ctypes.data_as(POINTER(ctypes.c_float)), 1))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {a.size}")
+        _check(load_library().asdsm_net_params(self._h, a.ctypes.data_as(POINTER(ctypes.c_float)), 0))
+
+    def forward(self, x, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n_vox, dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(load_library().asdsm_net_forward(self._h, _fptr(x, self.n_vox * self.CHANNELS, "x"),
+                                                    _fptr(out, self.n_vox, "out")))
+        return out
+
+    def gradient(self, x, target, loss="mse", want_grad=True):
+        """(loss, flat parameter gradient as numpy float32 or None)."""
+        import numpy as np
+        import torch
+        g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
+        lv = c_double()
+        with torch.cuda.device(self.device):
+            _check(load_library().asdsm_net_gradient(
+                self._h, _fptr(x, self.n_vox * self.CHANNELS, "x"), _fptr(target, self.n_vox, "target"),
+                NET_LOSSES[loss], byref(lv),
+                g.ctypes.data_as(POINTER(ctypes.c_float)) if want_grad else None))
+        return lv.value, g
+
+    def adam(self, lr):
+        import torch
+        with torch.cuda.device(self.device):
+            _check(load_library().asdsm_net_adam(self._h, ctypes.c_float(lr)))
+
+    def bind(self, plan):
+        import torch
+        with torch.cuda.device(self.device):
+            _check(load_library().asdsm_net_bind(self._h, plan._h))
+        self.plan = plan
+
+    def features(self, r, rnorm2, offset=(0, 0, 0), x=None, rhat=None):
+        """Network input (n^3 x 16) and rhat (n^3) for a window of the bound plan's residual r;
+        rnorm2 = ||r||_2^2 of the whole residual (Plan.residual returns ||r||_2)."""
+        import torch
+        if self.plan is None:
+            raise RuntimeError("bind the network to a plan first")
+        if x is None:
+            x = torch.empty(self.n_vox * self.CHANNELS, dtype=torch.float32, device=self.device)
+        if rhat is None:
+            rhat = torch.empty(self.n_vox, dtype=torch.float32, device=self.device)
+        off = (c_int * 3)(*[int(o) for o in offset])
+        with torch.cuda.device(self.device):
+            _check(load_library().asdsm_net_features(self._h, _dptr(r, self.plan.n_fine, "r"), float(rnorm2), off,
+                                                     _fptr(x, self.n_vox * self.CHANNELS, "x"),
+                                                     _fptr(rhat, self.n_vox, "rhat")))
+        return x, rhat
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().asdsm_net_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_learned(plan, net, s, g, u=None, factor=4.0, max_iter=50, rtol=1e-10, stag_window=3,
+                  stag_eta=1e-3, resume=False, k0=0, profile=False, eager=False, precision="fp64"):
+    """asdsm_solve_learned: (u, info) with info["accepted"] = accepted learned proposals."""
+    import torch
+    lib = load_library()
+    if u is None:
+        u = torch.empty(plan.n_fine, dtype=torch.float64, device=plan.device)
+    o, hist, steps = _opts(max_iter, rtol, stag_window, stag_eta, resume, k0, profile, eager, precision)
+    st = Stats()
+    acc = c_int()
+    with torch.cuda.device(plan.device):
+        rc = _check(lib.asdsm_solve_learned(plan._h, net._h, float(factor), _dptr(s, plan.n_fine, "s"),
+                                            _dptr(g, plan.n_faces, "g"), _dptr(u, plan.n_fine, "u"),
+                                            byref(o), byref(st), byref(acc)))
+    info = _info(rc, st, hist, steps, profile)
+    info["accepted"] = acc.value
+    return u, info

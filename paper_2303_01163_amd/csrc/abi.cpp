@@ -1,11 +1,14 @@
 // C ABI entry points and the ASDSM driver (Algorithms 1-4) on one HIP stream.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
 
+#include "../../include/asdsm_learn.h"
 #include "asdsm_internal.hpp"
 #include "kernels.hpp"
+#include "learn_internal.hpp"
 
 namespace asdsm {
 const char *last_error_cstr();
@@ -687,6 +690,55 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
     return ASDSM_OK;
 }
 
+// A refinement step with a learned proposal (p.learn_net, bound to this plan, n = N_f): the
+// network maps r_k to a correction e, the line search of Algorithm 4 gives <r, Ae> and <Ae, Ae>, and
+// a device-side test accepts the proposal when the optimal step lowers ||r|| by p.learn_factor.  The
+// update u_next = u_cur + w e runs only if accepted, the plain step (refine_step) only if not; both
+// are gated by the test's flags, so the step needs no host round trip and can be captured.
+int learned_step(Plan &p, const double *u_cur, double *u_next) {
+    Net &net = *p.learn_net;
+    const int *done = p.gate;
+    const double nf = (double)p.geo.NF;
+    {
+        // MFMA work of the four convolutions (padded channels) and the bytes of their operands
+        double conv_flops = 0.0, conv_bytes = 0.0;
+        for (int l = 0; l < kNetLayers; ++l) {
+            conv_flops += 2.0 * 27.0 * kNetCinP[l] * kNetCoutP[l] * nf;
+            conv_bytes += 4.0 * (kNetCinP[l] + (l + 1 < kNetLayers ? kNetCinP[l + 1] : 1)) * nf;
+        }
+        PhaseTimer t(p, ASDSM_PHASE_LEARNED, kNetLayers + 4, conv_flops + (4.0 * p.d + 6.0) * nf,
+                     conv_bytes + (8.0 + 64.0) * nf + (4.0 + 8.0) * nf + 16.0 * nf);
+        const int off[3] = {0, 0, 0};
+        net_features(net.n, net.Nf, net.nsp, off, p.ws.r, p.ws.scal + kScalRnorm2, net.pe, net.act[0], nullptr,
+                     done, p.stream);
+        for (int l = 0; l < kNetLayers; ++l) {
+            const bool last = (l == kNetLayers - 1);
+            net_conv_fwd(net.n, kNetCinP[l], kNetCout[l], last ? 1 : 32, !last, net.act[l], net.Wb[l],
+                         net.P + net.bofs[l], net.act[l + 1], done, p.stream);
+        }
+        net_correction(p.geo.NF, net.act[kNetLayers], p.ws.scal + kScalRnorm2, net.h2a, p.ws.e, done, p.stream);
+        launch_dots(p, p.stream);
+        net_accept(p.ws.scal, &p.ws.state->done, &p.ws.state->learned, p.learn_factor, net.skip, p.stream);
+        if (int rc = check_launch("learned proposal")) return rc;
+    }
+    p.gate = net.skip;  // skip[0]: not accepted (or done)
+    {
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, (4.0 * p.d + 6.0) * nf, 8.0 * (5.0 * nf + aniso_points(p)));
+        double *gat[kMaxMeshes];
+        gather_pointers(p, gat);
+        launch_update_residual(p, u_cur, p.ws.e, u_next, gat, kFinIter, p.stream);
+    }
+    p.gate = net.skip + 1;  // skip[1]: accepted (or done)
+    const int rc = refine_step(p, u_cur, u_next);
+    p.gate = done;
+    if (rc != ASDSM_OK) return rc;
+    return check_launch("learned update");
+}
+
+int step(Plan &p, const double *u_cur, double *u_next) {
+    return p.learn_net ? learned_step(p, u_cur, u_next) : refine_step(p, u_cur, u_next);
+}
+
 int require_ws(const Plan &p) {
     if (!p.ws_base) return fail(ASDSM_E_WORKSPACE, "no workspace attached (asdsm_set_workspace)");
     return ASDSM_OK;
@@ -715,8 +767,8 @@ int build_graph(Plan &p, double *u) {
     hipStream_t saved = p.stream;
     p.stream = p.capture_stream;
     ASDSM_HIP_CHECK(hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal));
-    int rc = refine_step(p, u, p.ws.u2);
-    if (rc == ASDSM_OK) rc = refine_step(p, p.ws.u2, u);
+    int rc = step(p, u, p.ws.u2);
+    if (rc == ASDSM_OK) rc = step(p, p.ws.u2, u);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(p.capture_stream, &graph);
     p.stream = saved;
@@ -733,6 +785,9 @@ int build_graph(Plan &p, double *u) {
     }
     p.graph_u = u;
     p.graph_prec32 = p.prec32;
+    p.graph_net_serial = p.learn_net ? p.learn_net->serial : 0;
+    p.graph_net_ws = p.learn_net ? p.learn_net->ws : nullptr;
+    p.graph_factor = p.learn_factor;
     return ASDSM_OK;
 }
 
@@ -921,7 +976,11 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
     IterState &hs = *p.hstate;
     int rc = ASDSM_OK;
     if (use_graph) {
-        if (p.graph_u != u || !p.graph_exec || p.graph_prec32 != p.prec32) rc = build_graph(p, u);
+        const uint64_t net_serial = p.learn_net ? p.learn_net->serial : 0;
+        const void *net_ws = p.learn_net ? p.learn_net->ws : nullptr;
+        if (p.graph_u != u || !p.graph_exec || p.graph_prec32 != p.prec32 || p.graph_net_serial != net_serial ||
+            p.graph_net_ws != net_ws || (p.learn_net && p.graph_factor != p.learn_factor))
+            rc = build_graph(p, u);
         // two steps per replay, two replays per host check; surplus steps are gated no-ops
         int steps = 0;
         while (rc == ASDSM_OK) {
@@ -938,7 +997,7 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
         }
     } else {
         for (int i = 0; i < opt.max_iter && rc == ASDSM_OK; ++i) {
-            rc = (i % 2 == 0) ? refine_step(p, u, p.ws.u2) : refine_step(p, p.ws.u2, u);
+            rc = (i % 2 == 0) ? step(p, u, p.ws.u2) : step(p, p.ws.u2, u);
             if (rc == ASDSM_OK) rc = read_state(p);
             if (hs.done) break;
         }
@@ -1140,10 +1199,6 @@ int batch_solve_impl(Batch &b, const double *const *s, const double *const *g, d
 
 using namespace asdsm;
 
-struct asdsm_plan_s {
-    Plan p;
-};
-
 extern "C" {
 
 int asdsm_plan(asdsm_plan_t *out, int d, const double *alpha, const double *beta, int level,
@@ -1153,6 +1208,8 @@ int asdsm_plan(asdsm_plan_t *out, int d, const double *alpha, const double *beta
     asdsm_plan_s *h = new (std::nothrow) asdsm_plan_s();
     if (!h) return fail(ASDSM_E_ARG, "out of host memory");
     int rc = build_plan(h->p, d, alpha, beta, level, coarse_level, seed, (hipStream_t)hip_stream);
+    static std::atomic<uint64_t> serials{0};
+    h->p.serial = ++serials;
     if (rc != ASDSM_OK) {
         release_plan(h->p);
         delete h;
@@ -1188,6 +1245,28 @@ int asdsm_solve(asdsm_plan_t plan, const double *s, const double *g, double *u,
                 const asdsm_opts *opts, asdsm_stats *stats) {
     if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
     return solve_impl(plan->p, s, g, u, opts, stats);
+}
+
+int asdsm_solve_learned(asdsm_plan_t plan, asdsm_net_t net, double factor, const double *s, const double *g,
+                        double *u, const asdsm_opts *opts, asdsm_stats *stats, int *accepted) {
+    if (accepted) *accepted = 0;
+    if (!plan || !net) return fail(ASDSM_E_ARG, "plan and net must be non-NULL");
+    Plan &p = plan->p;
+    Net &nt = net->net;
+    if (nt.plan != plan || nt.plan_serial != p.serial)
+        return fail(ASDSM_E_ARG, "the network is not bound to this plan");
+    if (nt.n != p.geo.Nf) return fail(ASDSM_E_ARG, "the network's volume differs from the fine mesh");
+    if (!nt.ws) return fail(ASDSM_E_WORKSPACE, "no workspace attached to the network");
+    if (!(factor > 1.0) || !std::isfinite(factor)) return fail(ASDSM_E_ARG, "factor must be finite and > 1");
+    p.learn_net = &nt;
+    p.learn_factor = factor;
+    struct Reset {
+        Plan &p;
+        ~Reset() { p.learn_net = nullptr; }
+    } reset{p};
+    const int rc = solve_impl(p, s, g, u, opts, stats);
+    if (accepted && rc >= 0) *accepted = p.hstate->learned;
+    return rc;
 }
 
 int asdsm_residual(asdsm_plan_t plan, const double *u, const double *s, const double *g, double *r,

@@ -70,7 +70,8 @@ struct IterState {
     int stag;          // consecutive steps with ||r_{k+1}|| > (1 - eta) ||r_k||
     int max_iter;
     int stag_window;
-    int pad0, pad1;
+    int learned;       // learned proposals accepted (solves with a correction network)
+    int pad1;
     double rtol;
     double stag_eta;
     double rn_prev;    // ||r|| of the current iterate
@@ -118,6 +119,7 @@ struct Plan {
     double h = 0, H = 0;
     double alpha[kMaxD] = {}, beta[kMaxD] = {};
     uint64_t seed = 0;
+    uint64_t serial = 0;  // unique per plan object (never 0)
     hipStream_t stream = nullptr;
     int device = 0;
     Geo geo{};
@@ -172,6 +174,13 @@ struct Plan {
     hipGraphExec_t graph_exec = nullptr;
     const double *graph_u = nullptr;
     bool graph_prec32 = false;
+    // learned proposals (a correction network bound to this plan) for this call, and the network
+    // and acceptance factor of the captured graph
+    struct Net *learn_net = nullptr;
+    double learn_factor = 4.0;
+    uint64_t graph_net_serial = 0;      // 0: the graph holds plain steps
+    const void *graph_net_ws = nullptr;
+    double graph_factor = 0.0;
 
     // profiling: a pair of events around every timed launch group, read after the call's final
     // synchronisation (launches stay queued back to back, so the pair brackets the kernels alone)
@@ -205,3 +214,7 @@ void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
 
 }  // namespace asdsm
+
+struct asdsm_plan_s {
+    asdsm::Plan p;
+};

@@ -1,0 +1,421 @@
+// Learned correction network (a small 3D convolutional net proposing refinement corrections):
+// conv3d 3x3x3 with zero padding, BF16 operands on MFMA with FP32 accumulation, fused bias and
+// ReLU; its backward passes (data: the same kernel on spatially flipped, channel-transposed
+// weights; weights: FP32 sums over voxel tiles reduced in a fixed order); MSE loss; Adam.
+//
+// Layouts.  A volume of n^3 voxels, v = x + n (y + n z).  Activations are FP32, channels last,
+// padded to 16 or 32 channels: act[v * CP + c].  Weights: FP32 master and BF16 copy, as
+// w[co][tap][ci] (tap = (dz+1)*9 + (dy+1)*3 + (dx+1)), co and ci padded like the activations.
+// Operand layout of v_mfma_f32_16x16x16bf16_1k (lane l): A[l%16][4(l/16)+t], B[4(l/16)+t][l%16],
+// t = 0..3; D[v] at row 4(l/16)+v, col l%16.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "learn_internal.hpp"
+
+namespace asdsm {
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 with round-to-nearest-even (finite inputs).
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+    const unsigned u = __float_as_uint(x);
+    const unsigned r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(r >> 16);
+}
+
+__device__ __forceinline__ int tap_dx(int tap) { return tap % 3 - 1; }
+__device__ __forceinline__ int tap_dy(int tap) { return (tap / 3) % 3 - 1; }
+__device__ __forceinline__ int tap_dz(int tap) { return tap / 9 - 1; }
+
+// ---------------------------------------------------------------------------------------------
+// Forward convolution.  Block = 4 waves over 64 consecutive voxels of one x-row; wave w owns
+// voxels 16w..16w+15 of the tile and all COT * 16 output channels.  K runs over 27 taps x CIN
+// input channels in steps of 16.  out[v*COP + co] = bias[co] + sum, ReLU when RELU; only the first
+// cout channels are written (COP is the stored channel count).
+// ---------------------------------------------------------------------------------------------
+template <int CIN, int COT, bool RELU>
+__global__ __launch_bounds__(256) void k_conv_fwd(int n, const float *__restrict__ x,
+                                                  const unsigned short *__restrict__ w,
+                                                  const float *__restrict__ bias, int cout, int cop,
+                                                  float *__restrict__ out, const int *gate) {
+    if (gate && *gate) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int xtn = (n + 63) / 64;
+    const int row = blockIdx.x / xtn;  // y + n z
+    const int x0 = (blockIdx.x % xtn) * 64;
+    const int y = row % n, z = row / n;
+    const int xa = x0 + wave * 16 + (lane & 15);  // voxel of this lane's A row
+    constexpr int COP_W = COT * 16;                // padded output channels of the weights
+    float4_t acc[COT];
+#pragma unroll
+    for (int c = 0; c < COT; ++c) acc[c] = {0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 27; ++tap) {
+        const int xx = xa + tap_dx(tap), yy = y + tap_dy(tap), zz = z + tap_dz(tap);
+        const bool in = xx >= 0 && xx < n && yy >= 0 && yy < n && zz >= 0 && zz < n && xa < n;
+        const long long vn = in ? (long long)xx + (long long)n * (yy + (long long)n * zz) : 0;
+#pragma unroll
+        for (int c0 = 0; c0 < CIN; c0 += 16) {
+            const int ci = c0 + 4 * (lane >> 4);
+            short4_t a = {0, 0, 0, 0};
+            if (in) {
+                const float4_t xv = *reinterpret_cast<const float4_t *>(x + vn * CIN + ci);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a[t] = (short)to_bf16(xv[t]);
+            }
+#pragma unroll
+            for (int c = 0; c < COT; ++c) {
+                const int co = c * 16 + (lane & 15);
+                const short4_t b = *reinterpret_cast<const short4_t *>(w + ((long long)co * 27 + tap) * CIN + ci);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[c], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < COT; ++c) {
+        const int co = c * 16 + (lane & 15);
+        if (co >= cout) continue;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int xv = x0 + wave * 16 + 4 * (lane >> 4) + v;
+            if (xv >= n) continue;
+            float r = acc[c][v] + bv;
+            if (RELU) r = fmaxf(r, 0.f);
+            out[((long long)xv + (long long)n * row) * cop + co] = r;
+        }
+    }
+    (void)COP_W;
+}
+
+// Backward weights: dw[co][tap][ci] = sum_v g[v][co] x[v + off(tap)][ci], a contraction over
+// voxels on v_mfma_f32_16x16x4f32 (FP32 operands and sums).  A tile is 64 consecutive voxels of
+// one x-row; block b takes tiles b, b + gridDim.x, ... in order.  Wave w owns the 16 x 16 channel
+// tile pair w % P (P = COUT/16 * CIN/16) for all 27 taps (27 accumulators) and, when P < 4, the
+// voxel slice w / P of each tile (KS = 4 / P slices).  Every (block, slice) writes its own
+// partial gradient; k_reduce_blocks sums them in a fixed order, so the result does not depend on
+// scheduling.  g = upstream gradient (channels cop_g), x = layer input (CIN channels).
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_wgrad(int n, const float *__restrict__ g, int cop_g,
+                                                    const float *__restrict__ x,
+                                                    float *__restrict__ partial) {
+    constexpr int NCI = CIN / 16, P = (COUT / 16) * NCI, KS = 4 / P, KV = 64 / KS;
+    static_assert(P * KS == 4, "four waves cover the channel tiles");
+    __shared__ float sg[64][COUT + 1];
+    __shared__ float sx[66][CIN + 1];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int pair = wave % P, slice = wave / P;
+    const int cot = pair / NCI, cit = pair % NCI;
+    const int xtn = (n + 63) / 64;
+    const int ntiles = xtn * n * n;
+    float4_t acc[27];
+#pragma unroll
+    for (int tp = 0; tp < 27; ++tp) acc[tp] = {0.f, 0.f, 0.f, 0.f};
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int row = tile / xtn;
+        const int x0 = (tile % xtn) * 64;
+        const int y = row % n, z = row / n;
+        __syncthreads();  // the previous tile's readers of sg and sx are done
+        for (int q = t; q < 64 * COUT; q += 256) {
+            const int vv = q / COUT, co = q % COUT;
+            const int xv = x0 + vv;
+            sg[vv][co] = (xv < n) ? g[((long long)xv + (long long)n * row) * cop_g + co] : 0.f;
+        }
+#pragma unroll
+        for (int dzy = 0; dzy < 9; ++dzy) {
+            const int yy = y + dzy % 3 - 1, zz = z + dzy / 3 - 1;
+            const bool rowin = yy >= 0 && yy < n && zz >= 0 && zz < n;
+            if (dzy > 0) __syncthreads();
+            for (int q = t; q < 66 * CIN; q += 256) {
+                const int xi = q / CIN, ci = q % CIN;
+                const int xx = x0 - 1 + xi;
+                sx[xi][ci] = (rowin && xx >= 0 && xx < n)
+                                 ? x[((long long)xx + (long long)n * (yy + (long long)n * zz)) * CIN + ci]
+                                 : 0.f;
+            }
+            __syncthreads();
+            for (int k0 = slice * KV; k0 < slice * KV + KV; k0 += 4) {
+                const int vv = k0 + (lane >> 4);
+                const float a = sg[vv][cot * 16 + (lane & 15)];
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const float b = sx[vv + dx][cit * 16 + (lane & 15)];
+                    acc[dzy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[dzy * 3 + dx], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *dst = partial + ((size_t)blockIdx.x * KS + slice) * (COUT * 27 * CIN);
+    const int ci = cit * 16 + (lane & 15);
+#pragma unroll
+    for (int tp = 0; tp < 27; ++tp)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int co = cot * 16 + 4 * (lane >> 4) + v;
+            dst[((size_t)co * 27 + tp) * CIN + ci] = acc[tp][v];
+        }
+}
+
+// Bias gradient partial sums per block and channel, over the same tiles as k_conv_wgrad.
+__global__ __launch_bounds__(256) void k_bias_grad(int n, const float *__restrict__ g, int cop_g, int cout,
+                                                   float *__restrict__ partial) {
+    const int xtn = (n + 63) / 64;
+    const int ntiles = xtn * n * n;
+    const int co = threadIdx.x;
+    if (co >= cout) return;
+    float s = 0.f;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int row = tile / xtn;
+        const int x0 = (tile % xtn) * 64;
+        for (int vv = 0; vv < 64; ++vv) {
+            const int xv = x0 + vv;
+            if (xv < n) s += g[((long long)xv + (long long)n * row) * cop_g + co];
+        }
+    }
+    partial[(size_t)blockIdx.x * cout + co] = s;
+}
+
+// out[i] = sum_b partial[b * len + i], in block order.
+__global__ __launch_bounds__(256) void k_reduce_blocks(const float *__restrict__ partial, int nblk, int len,
+                                                       float *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * len + i];
+    out[i] = s;
+}
+
+// Transposed, flipped BF16 weights for the data gradient: wt[ci][tap][co] = w[co][26 - tap][ci].
+__global__ __launch_bounds__(256) void k_flip_weights(const float *__restrict__ w, int cout_p, int cin_p,
+                                                      unsigned short *__restrict__ wt) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int total = cout_p * 27 * cin_p;
+    if (i >= total) return;
+    const int co = i % cout_p;  // fastest index of wt
+    const int tap = (i / cout_p) % 27;
+    const int ci = i / (cout_p * 27);
+    wt[i] = to_bf16(w[((long long)co * 27 + (26 - tap)) * cin_p + ci]);
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float *__restrict__ a, unsigned short *__restrict__ b,
+                                                 int len) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < len) b[i] = to_bf16(a[i]);
+}
+
+// g[v*cop + c] *= (y[v*cop + c] > 0) for the first cout channels (ReLU backward), zero elsewhere.
+__global__ __launch_bounds__(256) void k_relu_mask(long long nvox, int cop, int cout, const float *__restrict__ y,
+                                                   float *__restrict__ g) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nvox * cop) return;
+    const int c = (int)(i % cop);
+    g[i] = (c < cout && y[i] > 0.f) ? g[i] : 0.f;
+}
+
+// Loss of the output o against t through a 7-point stencil K (coefficients of the centre and of
+// the x-, x+, y-, y+, z-, z+ neighbours, zero outside the volume): rho = t - K o, loss = mean rho^2.
+// K = identity gives the mean squared error.  First pass: rho and per-block sums of rho^2.
+__device__ __forceinline__ float stencil_at(int n, const float *__restrict__ f, const NetStencil &K, int x, int y,
+                                            int z) {
+    const long long v = (long long)x + (long long)n * (y + (long long)n * z);
+    const long long nn = (long long)n * n;
+    float a = K.c[0] * f[v];
+    if (x > 0) a += K.c[1] * f[v - 1];
+    if (x < n - 1) a += K.c[2] * f[v + 1];
+    if (y > 0) a += K.c[3] * f[v - n];
+    if (y < n - 1) a += K.c[4] * f[v + n];
+    if (z > 0) a += K.c[5] * f[v - nn];
+    if (z < n - 1) a += K.c[6] * f[v + nn];
+    return a;
+}
+
+__global__ __launch_bounds__(256) void k_stencil_res(int n, const float *__restrict__ o, const float *__restrict__ t,
+                                                     NetStencil K, float *__restrict__ rho,
+                                                     double *__restrict__ partial) {
+    __shared__ double sh[4];
+    const long long nv = (long long)n * n * n;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double e2 = 0.0;
+    if (i < nv) {
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+        const float e = t[i] - stencil_at(n, o, K, x, y, z);
+        rho[i] = e;
+        e2 = (double)e * e;
+    }
+    const double s = block_sum<256>(e2, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Second pass: gradient of the loss with respect to o, -(2/N) K^T rho (KT = the transposed stencil),
+// into channel 0 of a 16-channel buffer (channels 1..15 zero) for the backward pass of the last layer.
+__global__ __launch_bounds__(256) void k_stencil_grad(int n, const float *__restrict__ rho, NetStencil KT,
+                                                      float scale, float *__restrict__ d16) {
+    const long long nv = (long long)n * n * n;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nv) return;
+    const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+    float4_t *dst = reinterpret_cast<float4_t *>(d16 + i * 16);
+    dst[0] = {scale * stencil_at(n, rho, KT, x, y, z), 0.f, 0.f, 0.f};
+    dst[1] = {0.f, 0.f, 0.f, 0.f};
+    dst[2] = {0.f, 0.f, 0.f, 0.f};
+    dst[3] = {0.f, 0.f, 0.f, 0.f};
+}
+
+// Input of the learned correction for the window [o0, o0 + n)^3 (per axis offsets) of the fine grid:
+// channel 0 r / sigma with sigma^2 = ||r||^2 / N_f^3 (||r||^2 read from *rn2), channels 1..3 the
+// coarse-plane indicators of axes 0..2 (fine index i, 0-based, lies on a coarse plane when
+// (i + 1) % nsp == 0), channels 4..6 the cell Peclet numbers of axes 0..2, channels 7..15 zero.
+// rhat (optional) receives channel 0 contiguously.
+__global__ __launch_bounds__(256) void k_net_features(int n, int Nf, int nsp, int o0, int o1, int o2,
+                                                      const double *__restrict__ r, const double *__restrict__ rn2,
+                                                      float pe0, float pe1, float pe2, float *__restrict__ in16,
+                                                      float *__restrict__ rhat, const int *gate) {
+    if (gate && *gate) return;
+    const long long nv = (long long)n * n * n;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nv) return;
+    const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+    const int gx = x + o0, gy = y + o1, gz = z + o2;
+    const double nf3 = (double)Nf * Nf * Nf;
+    const double sig2 = *rn2 / nf3;
+    const double inv = sig2 > 0.0 ? 1.0 / sqrt(sig2) : 0.0;
+    const float rv = (float)(r[(long long)gx + (long long)Nf * (gy + (long long)Nf * gz)] * inv);
+    float4_t *dst = reinterpret_cast<float4_t *>(in16 + i * 16);
+    dst[0] = {rv, ((gx + 1) % nsp == 0) ? 1.f : 0.f, ((gy + 1) % nsp == 0) ? 1.f : 0.f, ((gz + 1) % nsp == 0) ? 1.f : 0.f};
+    dst[1] = {pe0, pe1, pe2, 0.f};
+    dst[2] = {0.f, 0.f, 0.f, 0.f};
+    dst[3] = {0.f, 0.f, 0.f, 0.f};
+    if (rhat) rhat[i] = rv;
+}
+
+// Correction proposed by the network in the solver's units: e = o * sigma * h^2 / mean(alpha)
+// (sigma as in k_net_features), FP64, over the whole fine grid (the network's volume).
+__global__ __launch_bounds__(256) void k_net_correction(long long nv, const float *__restrict__ o,
+                                                        const double *__restrict__ rn2, double h2a,
+                                                        double *__restrict__ e, const int *gate) {
+    if (gate && *gate) return;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nv) return;
+    const double sig2 = *rn2 / (double)nv;
+    e[i] = (double)o[i] * (sqrt(sig2) * h2a);
+}
+
+// Acceptance test of a learned proposal e with <r, Ae> = rq and <Ae, Ae> = qq: with the optimal step
+// rq / qq the new residual has ||r||^2 - rq^2 / qq; the proposal is taken when that is at most
+// ||r||^2 / factor^2 (factor2 = factor^2).  Writes skip[0] = 1 when the learned update is not to be
+// applied and skip[1] = 1 when the plain step is not to be taken (both once the loop is done), and
+// counts accepted proposals.  Runs whatever the state: its flags gate the rest of the step.
+__global__ void k_learned_accept(const double *__restrict__ scal, int *__restrict__ done, int *__restrict__ accepted,
+                                 double factor2, int *__restrict__ skip) {
+    if (threadIdx.x != 0) return;
+    const int dn = *done;
+    bool ok = false;
+    if (!dn) {
+        const double rr = scal[kScalRnorm2], rq = scal[kScalRQ], qq = scal[kScalQQ];
+        ok = qq > 0.0 && rq > 0.0 && isfinite(rq) && isfinite(qq) && (rr - rq * (rq / qq)) * factor2 <= rr;
+        if (ok) *accepted += 1;
+    }
+    skip[0] = (dn || !ok) ? 1 : 0;
+    skip[1] = (dn || ok) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_adam(int len, float *__restrict__ w, const float *__restrict__ g,
+                                              float *__restrict__ m, float *__restrict__ v, float lr, float b1,
+                                              float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+static unsigned blocks_of(int n) { return (unsigned)(((n + 63) / 64) * n * n); }
+
+unsigned net_reduce_blocks(int n) {
+    const unsigned nb = blocks_of(n);
+    return nb < (unsigned)kNetMaxReduceBlocks ? nb : (unsigned)kNetMaxReduceBlocks;
+}
+
+void net_conv_fwd(int n, int cin_p, int cout, int cop, bool relu, const float *x, const unsigned short *w,
+                  const float *bias, float *out, const int *gate, hipStream_t st) {
+    const dim3 grid(blocks_of(n));
+    const int cot = (cout + 15) / 16;
+#define ASDSM_CONV(CI, CT, R) \
+    ASDSM_LAUNCH((k_conv_fwd<CI, CT, R>), grid, dim3(256), 0, st, n, x, w, bias, cout, cop, out, gate)
+    if (cin_p == 16 && cot == 2) { if (relu) ASDSM_CONV(16, 2, true); else ASDSM_CONV(16, 2, false); }
+    else if (cin_p == 32 && cot == 2) { if (relu) ASDSM_CONV(32, 2, true); else ASDSM_CONV(32, 2, false); }
+    else if (cin_p == 32 && cot == 1) { if (relu) ASDSM_CONV(32, 1, true); else ASDSM_CONV(32, 1, false); }
+    else if (cin_p == 16 && cot == 1) { if (relu) ASDSM_CONV(16, 1, true); else ASDSM_CONV(16, 1, false); }
+#undef ASDSM_CONV
+}
+
+void net_conv_wgrad(int n, int cin_p, int cout_p, const float *g, int cop_g, const float *x, float *partial,
+                    float *dw, hipStream_t st) {
+    const unsigned nb = net_reduce_blocks(n);
+    if (cin_p == 16 && cout_p == 32)
+        ASDSM_LAUNCH((k_conv_wgrad<16, 32>), dim3(nb), dim3(256), 0, st, n, g, cop_g, x, partial);
+    else if (cin_p == 32 && cout_p == 32)
+        ASDSM_LAUNCH((k_conv_wgrad<32, 32>), dim3(nb), dim3(256), 0, st, n, g, cop_g, x, partial);
+    else if (cin_p == 32 && cout_p == 16)
+        ASDSM_LAUNCH((k_conv_wgrad<32, 16>), dim3(nb), dim3(256), 0, st, n, g, cop_g, x, partial);
+    const int len = cout_p * 27 * cin_p;
+    const int slices = 4 / ((cout_p / 16) * (cin_p / 16));  // partial gradients per block
+    ASDSM_LAUNCH(k_reduce_blocks, dim3((len + 255) / 256), dim3(256), 0, st, partial, (int)nb * slices, len, dw);
+}
+
+void net_bias_grad(int n, const float *g, int cop_g, int cout, float *partial, float *db, hipStream_t st) {
+    const unsigned nb = net_reduce_blocks(n);
+    ASDSM_LAUNCH(k_bias_grad, dim3(nb), dim3(256), 0, st, n, g, cop_g, cout, partial);
+    ASDSM_LAUNCH(k_reduce_blocks, dim3((cout + 255) / 256), dim3(256), 0, st, partial, (int)nb, cout, db);
+}
+
+void net_flip(const float *w, int cout_p, int cin_p, unsigned short *wt, hipStream_t st) {
+    const int total = cout_p * 27 * cin_p;
+    ASDSM_LAUNCH(k_flip_weights, dim3((total + 255) / 256), dim3(256), 0, st, w, cout_p, cin_p, wt);
+}
+
+void net_to_bf16(const float *a, unsigned short *b, int len, hipStream_t st) {
+    ASDSM_LAUNCH(k_to_bf16, dim3((len + 255) / 256), dim3(256), 0, st, a, b, len);
+}
+
+void net_relu_mask(long long nvox, int cop, int cout, const float *y, float *g, hipStream_t st) {
+    ASDSM_LAUNCH(k_relu_mask, dim3((unsigned)((nvox * cop + 255) / 256)), dim3(256), 0, st, nvox, cop, cout, y, g);
+}
+
+void net_stencil_loss(int n, const float *o, const float *t, const NetStencil &K, const NetStencil &KT, float *rho,
+                      float *d16, double *partial, hipStream_t st) {
+    const long long nv = (long long)n * n * n;
+    const dim3 grid((unsigned)((nv + 255) / 256));
+    ASDSM_LAUNCH(k_stencil_res, grid, dim3(256), 0, st, n, o, t, K, rho, partial);
+    ASDSM_LAUNCH(k_stencil_grad, grid, dim3(256), 0, st, n, rho, KT, (float)(-2.0 / (double)nv), d16);
+}
+
+void net_features(int n, int Nf, int nsp, const int off[3], const double *r, const double *rn2, const float pe[3],
+                  float *in16, float *rhat, const int *gate, hipStream_t st) {
+    const long long nv = (long long)n * n * n;
+    ASDSM_LAUNCH(k_net_features, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st, n, Nf, nsp, off[0], off[1],
+                 off[2], r, rn2, pe[0], pe[1], pe[2], in16, rhat, gate);
+}
+
+void net_correction(long long nv, const float *o, const double *rn2, double h2a, double *e, const int *gate,
+                    hipStream_t st) {
+    ASDSM_LAUNCH(k_net_correction, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st, nv, o, rn2, h2a, e, gate);
+}
+
+void net_accept(const double *scal, int *done, int *accepted, double factor, int *skip, hipStream_t st) {
+    ASDSM_LAUNCH(k_learned_accept, dim3(1), dim3(64), 0, st, scal, done, accepted, factor * factor, skip);
+}
+
+void net_adam(int len, float *w, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
+              float c1, float c2, hipStream_t st) {
+    ASDSM_LAUNCH(k_adam, dim3((len + 255) / 256), dim3(256), 0, st, len, w, g, m, v, lr, b1, b2, eps, c1, c2);
+}
+
+}  // namespace asdsm

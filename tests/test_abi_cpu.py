@@ -8,11 +8,15 @@ import pytest
 
 ROOT = Path(__file__).resolve().parents[1]
 HEADER = ROOT / "include" / "asdsm.h"
+HEADERS = sorted((ROOT / "include").glob("*.h"))
 
 
-def _declared():
-    text = HEADER.read_text()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(asdsm_\w+)\s*\(", text, re.M)))
+def _declared(path=None):
+    names = set()
+    for h in ([path] if path else HEADERS):
+        text = h.read_text()
+        names |= set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(asdsm_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -32,9 +36,11 @@ def test_header_declares_the_boundary():
 
 
 def test_library_exports_every_declared_symbol(lib):
-    from paper_2303_01163_amd.asdsm import EXPORTED
+    from paper_2303_01163_amd.asdsm import EXPORTED, EXPORTED_LEARN
+    assert sorted(EXPORTED) == _declared(HEADER)
+    assert sorted(EXPORTED_LEARN) == _declared(ROOT / "include" / "asdsm_learn.h")
     names = _declared()
-    assert sorted(EXPORTED) == names
+    assert sorted(EXPORTED + EXPORTED_LEARN) == names
     for n in names:
         assert hasattr(lib, n), n
 
