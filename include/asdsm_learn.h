@@ -27,7 +27,10 @@
  *   ci < cin_p(l)) and then its biases (cout_p(l) values), with (cin_p, cout_p) = (16, 32),
  *   (32, 32), (32, 32), (32, 16); weights of padded channels are kept at zero.
  * - Device pointers must be valid for the network's device; calls are enqueued on the stream given
- *   at creation (asdsm_solve_learned: the plan's stream) and return after it has completed.  Return: 0 or an ASDSM_E_* code
+ *   at creation (asdsm_solve_learned: the plan's stream).  Calls that hand results to the host
+ *   (asdsm_net_params, asdsm_net_gradient with a loss or gradient pointer, asdsm_solve_learned)
+ *   return after the stream has completed; the others return once their work is enqueued, so
+ *   their device buffers must stay valid until the stream reaches it.  Return: 0 or an ASDSM_E_* code
  *   (include/asdsm.h); asdsm_last_error() describes the last error.
  */
 #ifndef ASDSM_LEARN_H
@@ -68,8 +71,8 @@ int asdsm_net_forward(asdsm_net_t net, const float *in, float *out);
 #define ASDSM_NET_LOSS_RESIDUAL 1   /* mean_v (target_v - (A' out)_v)^2, A' of the bound plan     */
 
 /* Forward and backward pass for one sample: the loss of kind loss_kind into *loss (host, may be
- * NULL); the gradient of the loss with respect to every parameter stays in the network and is
- * copied to `grad_host` (flat layout above) when that is not NULL.  A' (ASDSM_NET_LOSS_RESIDUAL) is
+ * NULL); the gradient of the loss with respect to every parameter stays in the network (for
+ * asdsm_net_adam) and is copied to `grad_host` (flat layout above) when that is not NULL.  A' (ASDSM_NET_LOSS_RESIDUAL) is
  * the bound plan's 7-point fine operator times h^2 / mean(alpha), applied on the network's volume
  * with zero values outside it.  Errors: ASDSM_E_ARG (unknown kind, residual loss without binding). */
 int asdsm_net_gradient(asdsm_net_t net, const float *in, const float *target, int loss_kind,

@@ -379,8 +379,9 @@ class Net:
                                                     _fptr(out, self.n_vox, "out")))
         return out
 
-    def gradient(self, x, target, loss="mse", want_grad=True):
-        """(loss, flat parameter gradient as numpy float32 or None)."""
+    def gradient(self, x, target, loss="mse", want_grad=True, want_loss=True):
+        """(loss or None, flat parameter gradient as numpy float32 or None).  Without either the
+        call only enqueues the work (the gradient stays on the device for adam())."""
         import numpy as np
         import torch
         g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
@@ -388,9 +389,9 @@ class Net:
         with torch.cuda.device(self.device):
             _check(load_library().asdsm_net_gradient(
                 self._h, _fptr(x, self.n_vox * self.CHANNELS, "x"), _fptr(target, self.n_vox, "target"),
-                NET_LOSSES[loss], byref(lv),
+                NET_LOSSES[loss], byref(lv) if want_loss else None,
                 g.ctypes.data_as(POINTER(ctypes.c_float)) if want_grad else None))
-        return lv.value, g
+        return (lv.value if want_loss else None), g
 
     def adam(self, lr):
         import torch

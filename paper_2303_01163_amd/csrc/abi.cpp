@@ -709,8 +709,8 @@ int learned_step(Plan &p, const double *u_cur, double *u_next) {
         PhaseTimer t(p, ASDSM_PHASE_LEARNED, kNetLayers + 4, conv_flops + (4.0 * p.d + 6.0) * nf,
                      conv_bytes + (8.0 + 64.0) * nf + (4.0 + 8.0) * nf + 16.0 * nf);
         const int off[3] = {0, 0, 0};
-        net_features(net.n, net.Nf, net.nsp, off, p.ws.r, p.ws.scal + kScalRnorm2, net.pe, net.act[0], nullptr,
-                     done, p.stream);
+        net_features(net.n, net.Nf, net.nsp, off, p.ws.r, p.ws.scal + kScalRnorm2, 0.0, net.pe, net.act[0],
+                     nullptr, done, p.stream);
         for (int l = 0; l < kNetLayers; ++l) {
             const bool last = (l == kNetLayers - 1);
             net_conv_fwd(net.n, kNetCinP[l], kNetCout[l], last ? 1 : 32, !last, net.act[l], net.Wb[l],

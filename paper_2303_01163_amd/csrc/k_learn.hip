@@ -25,82 +25,150 @@ __device__ __forceinline__ unsigned short to_bf16(float x) {
     return (unsigned short)(r >> 16);
 }
 
-__device__ __forceinline__ int tap_dx(int tap) { return tap % 3 - 1; }
-__device__ __forceinline__ int tap_dy(int tap) { return (tap / 3) % 3 - 1; }
-__device__ __forceinline__ int tap_dz(int tap) { return tap / 9 - 1; }
 
 // ---------------------------------------------------------------------------------------------
-// Forward convolution.  Block = 4 waves over 64 consecutive voxels of one x-row; wave w owns
-// voxels 16w..16w+15 of the tile and all COT * 16 output channels.  K runs over 27 taps x CIN
-// input channels in steps of 16.  out[v*COP + co] = bias[co] + sum, ReLU when RELU; only the first
-// cout channels are written (COP is the stored channel count).
+// Forward convolution, z-marching.  A block owns a 64 (x) by 4 (y) column of output voxels over a
+// chunk of zc planes; wave w owns row y0 + w: 4 M tiles of 16 x-voxels times COT N tiles of 16
+// output channels.  The layer's BF16 weights sit in LDS for the whole block, as w[tap][co][ci]; the
+// input (FP32 in memory, rounded to BF16 when staged) passes through a ring of three LDS planes of
+// 6 x 66 voxels with their halo, the plane two steps ahead being fetched into registers while the
+// current plane is computed.  K = 27 taps x CIN channels in steps of 16 (v_mfma_f32_16x16x16bf16_1k).
+// out[v*cop + co] = bias[co] + sum, ReLU when RELU, for co < cout.  Channel strides in LDS are
+// padded by 4 BF16 values (8-byte aligned fragments, fewer bank conflicts).
 // ---------------------------------------------------------------------------------------------
+template <int CIN, int COT>
+struct ConvLds {
+    static constexpr int CS = CIN + 4;                 // padded channel stride (BF16 values)
+    static constexpr int PLANE = 6 * 66 * CS;          // one staged input plane
+    static constexpr int WSZ = 27 * COT * 16 * CS;     // the weights
+    static constexpr int LOADS = 6 * 66 * CIN / 4;     // float4 loads per plane
+    static constexpr int PER_THREAD = (LOADS + 255) / 256;
+    static constexpr size_t BYTES = 2 * (size_t)(3 * PLANE + WSZ);
+};
+
 template <int CIN, int COT, bool RELU>
-__global__ __launch_bounds__(256) void k_conv_fwd(int n, const float *__restrict__ x,
+__global__ __launch_bounds__(256) void k_conv_fwd(int n, int zc, const float *__restrict__ x,
                                                   const unsigned short *__restrict__ w,
                                                   const float *__restrict__ bias, int cout, int cop,
                                                   float *__restrict__ out, const int *gate) {
     if (gate && *gate) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int xtn = (n + 63) / 64;
-    const int row = blockIdx.x / xtn;  // y + n z
-    const int x0 = (blockIdx.x % xtn) * 64;
-    const int y = row % n, z = row / n;
-    const int xa = x0 + wave * 16 + (lane & 15);  // voxel of this lane's A row
-    constexpr int COP_W = COT * 16;                // padded output channels of the weights
-    float4_t acc[COT];
+    using Lds = ConvLds<CIN, COT>;
+    constexpr int CS = Lds::CS, CO = COT * 16;
+    extern __shared__ unsigned short lds[];
+    unsigned short *sw = lds;                       // [27][CO][CS]
+    unsigned short *sp = lds + Lds::WSZ;            // [3][6][66][CS]
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int xtn = (n + 63) / 64, ytn = (n + 3) / 4;
+    const int b = blockIdx.x;
+    const int xt = b % xtn, yt = (b / xtn) % ytn, ct = b / (xtn * ytn);
+    const int x0 = xt * 64, y0 = yt * 4, z0 = ct * zc;
+    const int z1 = min(z0 + zc, n);
+    // weights: global w[co][tap][ci] -> LDS [tap][co][ci]
+    for (int q = t; q < 27 * CO * (CIN / 4); q += 256) {
+        const int c4 = q % (CIN / 4), tap = (q / (CIN / 4)) % 27, co = q / (27 * (CIN / 4));
+        const short4_t v = *reinterpret_cast<const short4_t *>(w + ((long long)co * 27 + tap) * CIN + 4 * c4);
+        *reinterpret_cast<short4_t *>(sw + (tap * CO + co) * CS + 4 * c4) = v;
+    }
+    // input plane gz (zero outside the volume) into registers / into ring slot
+    float4_t pre[Lds::PER_THREAD];
+    auto fetch = [&](int gz) {
 #pragma unroll
-    for (int c = 0; c < COT; ++c) acc[c] = {0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 27; ++tap) {
-        const int xx = xa + tap_dx(tap), yy = y + tap_dy(tap), zz = z + tap_dz(tap);
-        const bool in = xx >= 0 && xx < n && yy >= 0 && yy < n && zz >= 0 && zz < n && xa < n;
-        const long long vn = in ? (long long)xx + (long long)n * (yy + (long long)n * zz) : 0;
+        for (int j = 0; j < Lds::PER_THREAD; ++j) {
+            const int q = t + 256 * j;
+            const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, yi = q / (66 * (CIN / 4));
+            const int gx = x0 - 1 + xi, gy = y0 - 1 + yi;
+            const bool in = q < Lds::LOADS && gz >= 0 && gz < n && gx >= 0 && gx < n && gy >= 0 && gy < n;
+            pre[j] = in ? *reinterpret_cast<const float4_t *>(
+                              x + ((long long)gx + (long long)n * (gy + (long long)n * gz)) * CIN + 4 * c4)
+                        : float4_t{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto store = [&](int slot) {
 #pragma unroll
-        for (int c0 = 0; c0 < CIN; c0 += 16) {
-            const int ci = c0 + 4 * (lane >> 4);
-            short4_t a = {0, 0, 0, 0};
-            if (in) {
-                const float4_t xv = *reinterpret_cast<const float4_t *>(x + vn * CIN + ci);
+        for (int j = 0; j < Lds::PER_THREAD; ++j) {
+            const int q = t + 256 * j;
+            if (q < Lds::LOADS) {
+                const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, yi = q / (66 * (CIN / 4));
+                short4_t v;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) a[t] = (short)to_bf16(xv[t]);
+                for (int e = 0; e < 4; ++e) v[e] = (short)to_bf16(pre[j][e]);
+                *reinterpret_cast<short4_t *>(sp + ((slot * 6 + yi) * 66 + xi) * CS + 4 * c4) = v;
             }
+        }
+    };
+    fetch(z0 - 1);
+    store((z0 + 2) % 3);
+    fetch(z0);
+    store(z0 % 3);
+    fetch(z0 + 1);
+    store((z0 + 1) % 3);
+    __syncthreads();
+    const int y = y0 + wave;
+    for (int z = z0; z < z1; ++z) {
+        if (z + 1 < z1) fetch(z + 2);  // in flight during the compute of plane z
+        float4_t acc[4][COT];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int c = 0; c < COT; ++c) acc[m][c] = {0.f, 0.f, 0.f, 0.f};
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // offsets + 1
+            const unsigned short *pa = sp + (((z + dz + 2) % 3 * 6 + wave + dy) * 66 + (lane & 15) + dx) * CS +
+                                       4 * (lane >> 4);
+            const unsigned short *pb = sw + (tap * CO + (lane & 15)) * CS + 4 * (lane >> 4);
+#pragma unroll
+            for (int c0 = 0; c0 < CIN; c0 += 16) {
+                short4_t bf[COT];
+#pragma unroll
+                for (int c = 0; c < COT; ++c) bf[c] = *reinterpret_cast<const short4_t *>(pb + c * 16 * CS + c0);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const short4_t af = *reinterpret_cast<const short4_t *>(pa + m * 16 * CS + c0);
+#pragma unroll
+                    for (int c = 0; c < COT; ++c)
+                        acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[c], acc[m][c], 0, 0, 0);
+                }
+            }
+        }
+        // epilogue: D[v] is voxel x0 + 16 m + 4 (lane / 16) + v, channel 16 c + lane % 16
+        if (y < n) {
 #pragma unroll
             for (int c = 0; c < COT; ++c) {
                 const int co = c * 16 + (lane & 15);
-                const short4_t b = *reinterpret_cast<const short4_t *>(w + ((long long)co * 27 + tap) * CIN + ci);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[c], 0, 0, 0);
+                if (co >= cout) continue;
+                const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int xv = x0 + 16 * m + 4 * (lane >> 4) + v;
+                        if (xv >= n) continue;
+                        float r = acc[m][c][v] + bv;
+                        if (RELU) r = fmaxf(r, 0.f);
+                        out[((long long)xv + (long long)n * (y + (long long)n * z)) * cop + co] = r;
+                    }
             }
         }
+        __syncthreads();               // every wave is done with slot (z - 1) % 3
+        if (z + 1 < z1) store((z + 2) % 3);
+        __syncthreads();
     }
-#pragma unroll
-    for (int c = 0; c < COT; ++c) {
-        const int co = c * 16 + (lane & 15);
-        if (co >= cout) continue;
-        const float bv = bias ? bias[co] : 0.f;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int xv = x0 + wave * 16 + 4 * (lane >> 4) + v;
-            if (xv >= n) continue;
-            float r = acc[c][v] + bv;
-            if (RELU) r = fmaxf(r, 0.f);
-            out[((long long)xv + (long long)n * row) * cop + co] = r;
-        }
-    }
-    (void)COP_W;
 }
 
-// Backward weights: dw[co][tap][ci] = sum_v g[v][co] x[v + off(tap)][ci], a contraction over
-// voxels on v_mfma_f32_16x16x4f32 (FP32 operands and sums).  A tile is 64 consecutive voxels of
-// one x-row; block b takes tiles b, b + gridDim.x, ... in order.  Wave w owns the 16 x 16 channel
-// tile pair w % P (P = COUT/16 * CIN/16) for all 27 taps (27 accumulators) and, when P < 4, the
-// voxel slice w / P of each tile (KS = 4 / P slices).  Every (block, slice) writes its own
-// partial gradient; k_reduce_blocks sums them in a fixed order, so the result does not depend on
-// scheduling.  g = upstream gradient (channels cop_g), x = layer input (CIN channels).
+// Backward weights and biases: dw[co][tap][ci] = sum_v g[v][co] x[v + off(tap)][ci] and
+// db[co] = sum_v g[v][co], a contraction over voxels on v_mfma_f32_16x16x4f32 (FP32 operands and
+// sums).  A tile is 64 consecutive voxels of one x-row; block b takes tiles b, b + gridDim.x, ... in
+// order.  Wave w owns the 16 x 16 channel tile pair w % P (P = COUT/16 * CIN/16) for all 27 taps
+// (27 accumulators) and, when P < 4, the voxel slice w / P of each tile (KS = 4 / P slices).  Every
+// (block, slice) writes its own partial gradient -- the weights, then COUT biases, the layout of
+// the parameter vector -- and k_reduce_blocks sums them in a fixed order, so the result does not
+// depend on scheduling.  g = upstream gradient (channels cop_g), x = layer input (CIN channels).
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_wgrad(int n, const float *__restrict__ g, int cop_g,
                                                     const float *__restrict__ x,
                                                     float *__restrict__ partial) {
     constexpr int NCI = CIN / 16, P = (COUT / 16) * NCI, KS = 4 / P, KV = 64 / KS;
+    constexpr int NW = COUT * 27 * CIN;
     static_assert(P * KS == 4, "four waves cover the channel tiles");
     __shared__ float sg[64][COUT + 1];
     __shared__ float sx[66][CIN + 1];
@@ -112,6 +180,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int n, const float *__restri
     float4_t acc[27];
 #pragma unroll
     for (int tp = 0; tp < 27; ++tp) acc[tp] = {0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;  // bias sum of channel `lane` over this slice's voxels (first wave of a slice)
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int row = tile / xtn;
         const int x0 = (tile % xtn) * 64;
@@ -135,6 +204,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int n, const float *__restri
                                  : 0.f;
             }
             __syncthreads();
+            if (dzy == 0 && pair == 0 && lane < COUT)
+                for (int vv = slice * KV; vv < slice * KV + KV; ++vv) bacc += sg[vv][lane];
             for (int k0 = slice * KV; k0 < slice * KV + KV; k0 += 4) {
                 const int vv = k0 + (lane >> 4);
                 const float a = sg[vv][cot * 16 + (lane & 15)];
@@ -146,7 +217,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int n, const float *__restri
             }
         }
     }
-    float *dst = partial + ((size_t)blockIdx.x * KS + slice) * (COUT * 27 * CIN);
+    float *dst = partial + ((size_t)blockIdx.x * KS + slice) * (NW + COUT);
     const int ci = cit * 16 + (lane & 15);
 #pragma unroll
     for (int tp = 0; tp < 27; ++tp)
@@ -155,35 +226,21 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int n, const float *__restri
             const int co = cot * 16 + 4 * (lane >> 4) + v;
             dst[((size_t)co * 27 + tp) * CIN + ci] = acc[tp][v];
         }
+    if (pair == 0 && lane < COUT) dst[NW + lane] = bacc;
 }
 
-// Bias gradient partial sums per block and channel, over the same tiles as k_conv_wgrad.
-__global__ __launch_bounds__(256) void k_bias_grad(int n, const float *__restrict__ g, int cop_g, int cout,
-                                                   float *__restrict__ partial) {
-    const int xtn = (n + 63) / 64;
-    const int ntiles = xtn * n * n;
-    const int co = threadIdx.x;
-    if (co >= cout) return;
-    float s = 0.f;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int row = tile / xtn;
-        const int x0 = (tile % xtn) * 64;
-        for (int vv = 0; vv < 64; ++vv) {
-            const int xv = x0 + vv;
-            if (xv < n) s += g[((long long)xv + (long long)n * row) * cop_g + co];
-        }
-    }
-    partial[(size_t)blockIdx.x * cout + co] = s;
-}
-
-// out[i] = sum_b partial[b * len + i], in block order.
+// out[i] = sum_b partial[b * len + i] for i < len: 64 columns per block, the rows split over four
+// thread groups (rows b = grp, grp + 4, ...) whose sums are added in group order.
 __global__ __launch_bounds__(256) void k_reduce_blocks(const float *__restrict__ partial, int nblk, int len,
                                                        float *__restrict__ out) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= len) return;
+    __shared__ float sh[4][64];
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * len + i];
-    out[i] = s;
+    if (col < len)
+        for (int b = grp; b < nblk; b += 4) s += partial[(size_t)b * len + col];
+    sh[grp][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (grp == 0 && col < len) out[col] = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
 }
 
 // Transposed, flipped BF16 weights for the data gradient: wt[ci][tap][co] = w[co][26 - tap][ci].
@@ -263,13 +320,15 @@ __global__ __launch_bounds__(256) void k_stencil_grad(int n, const float *__rest
 }
 
 // Input of the learned correction for the window [o0, o0 + n)^3 (per axis offsets) of the fine grid:
-// channel 0 r / sigma with sigma^2 = ||r||^2 / N_f^3 (||r||^2 read from *rn2), channels 1..3 the
+// channel 0 r / sigma with sigma^2 = ||r||^2 / N_f^3 (||r||^2 read from *rn2, or rn2_value when rn2
+// is null), channels 1..3 the
 // coarse-plane indicators of axes 0..2 (fine index i, 0-based, lies on a coarse plane when
 // (i + 1) % nsp == 0), channels 4..6 the cell Peclet numbers of axes 0..2, channels 7..15 zero.
 // rhat (optional) receives channel 0 contiguously.
 __global__ __launch_bounds__(256) void k_net_features(int n, int Nf, int nsp, int o0, int o1, int o2,
                                                       const double *__restrict__ r, const double *__restrict__ rn2,
-                                                      float pe0, float pe1, float pe2, float *__restrict__ in16,
+                                                      double rn2_value, float pe0, float pe1, float pe2,
+                                                      float *__restrict__ in16,
                                                       float *__restrict__ rhat, const int *gate) {
     if (gate && *gate) return;
     const long long nv = (long long)n * n * n;
@@ -278,7 +337,7 @@ __global__ __launch_bounds__(256) void k_net_features(int n, int Nf, int nsp, in
     const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
     const int gx = x + o0, gy = y + o1, gz = z + o2;
     const double nf3 = (double)Nf * Nf * Nf;
-    const double sig2 = *rn2 / nf3;
+    const double sig2 = (rn2 ? *rn2 : rn2_value) / nf3;
     const double inv = sig2 > 0.0 ? 1.0 / sqrt(sig2) : 0.0;
     const float rv = (float)(r[(long long)gx + (long long)Nf * (gy + (long long)Nf * gz)] * inv);
     float4_t *dst = reinterpret_cast<float4_t *>(in16 + i * 16);
@@ -343,21 +402,52 @@ unsigned net_reduce_blocks(int n) {
     return nb < (unsigned)kNetMaxReduceBlocks ? nb : (unsigned)kNetMaxReduceBlocks;
 }
 
+template <int CIN, int COT, bool RELU>
+static void conv_launch(int n, const float *x, const unsigned short *w, const float *bias, int cout, int cop,
+                        float *out, const int *gate, hipStream_t st) {
+    // z chunks: enough blocks to cover the chip twice where the volume allows, at least 4 planes each
+    const int xy = ((n + 63) / 64) * ((n + 3) / 4);
+    int zc = 16;
+    while (zc > 4 && (long long)xy * ((n + zc - 1) / zc) < 512) zc /= 2;
+    const int blocks = xy * ((n + zc - 1) / zc);
+    const size_t lds = ConvLds<CIN, COT>::BYTES;
+    ASDSM_LAUNCH((k_conv_fwd<CIN, COT, RELU>), dim3((unsigned)blocks), dim3(256), lds, st, n, zc, x, w, bias, cout,
+                 cop, out, gate);
+}
+
+void net_conv_prepare() {
+    // the kernels use more than 64 KB of dynamic LDS
+    (void)hipFuncSetAttribute((const void *)k_conv_fwd<16, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)ConvLds<16, 2>::BYTES);
+    (void)hipFuncSetAttribute((const void *)k_conv_fwd<16, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)ConvLds<16, 2>::BYTES);
+    (void)hipFuncSetAttribute((const void *)k_conv_fwd<32, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)ConvLds<32, 2>::BYTES);
+    (void)hipFuncSetAttribute((const void *)k_conv_fwd<32, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)ConvLds<32, 2>::BYTES);
+    (void)hipFuncSetAttribute((const void *)k_conv_fwd<32, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)ConvLds<32, 1>::BYTES);
+    (void)hipFuncSetAttribute((const void *)k_conv_fwd<32, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)ConvLds<32, 1>::BYTES);
+}
+
 void net_conv_fwd(int n, int cin_p, int cout, int cop, bool relu, const float *x, const unsigned short *w,
                   const float *bias, float *out, const int *gate, hipStream_t st) {
-    const dim3 grid(blocks_of(n));
     const int cot = (cout + 15) / 16;
-#define ASDSM_CONV(CI, CT, R) \
-    ASDSM_LAUNCH((k_conv_fwd<CI, CT, R>), grid, dim3(256), 0, st, n, x, w, bias, cout, cop, out, gate)
-    if (cin_p == 16 && cot == 2) { if (relu) ASDSM_CONV(16, 2, true); else ASDSM_CONV(16, 2, false); }
-    else if (cin_p == 32 && cot == 2) { if (relu) ASDSM_CONV(32, 2, true); else ASDSM_CONV(32, 2, false); }
-    else if (cin_p == 32 && cot == 1) { if (relu) ASDSM_CONV(32, 1, true); else ASDSM_CONV(32, 1, false); }
-    else if (cin_p == 16 && cot == 1) { if (relu) ASDSM_CONV(16, 1, true); else ASDSM_CONV(16, 1, false); }
-#undef ASDSM_CONV
+    if (cin_p == 16 && cot == 2) {
+        if (relu) conv_launch<16, 2, true>(n, x, w, bias, cout, cop, out, gate, st);
+        else conv_launch<16, 2, false>(n, x, w, bias, cout, cop, out, gate, st);
+    } else if (cin_p == 32 && cot == 2) {
+        if (relu) conv_launch<32, 2, true>(n, x, w, bias, cout, cop, out, gate, st);
+        else conv_launch<32, 2, false>(n, x, w, bias, cout, cop, out, gate, st);
+    } else if (cin_p == 32 && cot == 1) {
+        if (relu) conv_launch<32, 1, true>(n, x, w, bias, cout, cop, out, gate, st);
+        else conv_launch<32, 1, false>(n, x, w, bias, cout, cop, out, gate, st);
+    }
 }
 
 void net_conv_wgrad(int n, int cin_p, int cout_p, const float *g, int cop_g, const float *x, float *partial,
-                    float *dw, hipStream_t st) {
+                    float *dwb, hipStream_t st) {
     const unsigned nb = net_reduce_blocks(n);
     if (cin_p == 16 && cout_p == 32)
         ASDSM_LAUNCH((k_conv_wgrad<16, 32>), dim3(nb), dim3(256), 0, st, n, g, cop_g, x, partial);
@@ -365,15 +455,9 @@ void net_conv_wgrad(int n, int cin_p, int cout_p, const float *g, int cop_g, con
         ASDSM_LAUNCH((k_conv_wgrad<32, 32>), dim3(nb), dim3(256), 0, st, n, g, cop_g, x, partial);
     else if (cin_p == 32 && cout_p == 16)
         ASDSM_LAUNCH((k_conv_wgrad<32, 16>), dim3(nb), dim3(256), 0, st, n, g, cop_g, x, partial);
-    const int len = cout_p * 27 * cin_p;
+    const int len = cout_p * 27 * cin_p + cout_p;            // weights, then biases
     const int slices = 4 / ((cout_p / 16) * (cin_p / 16));  // partial gradients per block
-    ASDSM_LAUNCH(k_reduce_blocks, dim3((len + 255) / 256), dim3(256), 0, st, partial, (int)nb * slices, len, dw);
-}
-
-void net_bias_grad(int n, const float *g, int cop_g, int cout, float *partial, float *db, hipStream_t st) {
-    const unsigned nb = net_reduce_blocks(n);
-    ASDSM_LAUNCH(k_bias_grad, dim3(nb), dim3(256), 0, st, n, g, cop_g, cout, partial);
-    ASDSM_LAUNCH(k_reduce_blocks, dim3((cout + 255) / 256), dim3(256), 0, st, partial, (int)nb, cout, db);
+    ASDSM_LAUNCH(k_reduce_blocks, dim3((len + 63) / 64), dim3(256), 0, st, partial, (int)nb * slices, len, dwb);
 }
 
 void net_flip(const float *w, int cout_p, int cin_p, unsigned short *wt, hipStream_t st) {
@@ -397,11 +481,11 @@ void net_stencil_loss(int n, const float *o, const float *t, const NetStencil &K
     ASDSM_LAUNCH(k_stencil_grad, grid, dim3(256), 0, st, n, rho, KT, (float)(-2.0 / (double)nv), d16);
 }
 
-void net_features(int n, int Nf, int nsp, const int off[3], const double *r, const double *rn2, const float pe[3],
-                  float *in16, float *rhat, const int *gate, hipStream_t st) {
+void net_features(int n, int Nf, int nsp, const int off[3], const double *r, const double *rn2, double rn2_value,
+                  const float pe[3], float *in16, float *rhat, const int *gate, hipStream_t st) {
     const long long nv = (long long)n * n * n;
     ASDSM_LAUNCH(k_net_features, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st, n, Nf, nsp, off[0], off[1],
-                 off[2], r, rn2, pe[0], pe[1], pe[2], in16, rhat, gate);
+                 off[2], r, rn2, rn2_value, pe[0], pe[1], pe[2], in16, rhat, gate);
 }
 
 void net_correction(long long nv, const float *o, const double *rn2, double h2a, double *e, const int *gate,

@@ -8,9 +8,9 @@
 
 namespace asdsm {
 
-// Blocks of the weight and bias gradient kernels (each sums a fixed set of voxel tiles); the
-// workspace holds one partial weight gradient per block.
-constexpr int kNetMaxReduceBlocks = 1024;
+// Blocks of the weight-gradient kernel (each sums a fixed set of voxel tiles); the workspace holds
+// the partial weight and bias gradients of every block.
+constexpr int kNetMaxReduceBlocks = 512;
 unsigned net_reduce_blocks(int n);
 
 // 7-point stencil: coefficients of the centre and of the x-, x+, y-, y+, z-, z+ neighbours.
@@ -18,18 +18,18 @@ struct NetStencil {
     float c[7];
 };
 
+void net_conv_prepare();  // once per process, before the first convolution
 void net_conv_fwd(int n, int cin_p, int cout, int cop, bool relu, const float *x, const unsigned short *w,
                   const float *bias, float *out, const int *gate, hipStream_t st);
 void net_conv_wgrad(int n, int cin_p, int cout_p, const float *g, int cop_g, const float *x, float *partial,
-                    float *dw, hipStream_t st);
-void net_bias_grad(int n, const float *g, int cop_g, int cout, float *partial, float *db, hipStream_t st);
+                    float *dwb, hipStream_t st);
 void net_flip(const float *w, int cout_p, int cin_p, unsigned short *wt, hipStream_t st);
 void net_to_bf16(const float *a, unsigned short *b, int len, hipStream_t st);
 void net_relu_mask(long long nvox, int cop, int cout, const float *y, float *g, hipStream_t st);
 void net_stencil_loss(int n, const float *o, const float *t, const NetStencil &K, const NetStencil &KT, float *rho,
                       float *d16, double *partial, hipStream_t st);
-void net_features(int n, int Nf, int nsp, const int off[3], const double *r, const double *rn2, const float pe[3],
-                  float *in16, float *rhat, const int *gate, hipStream_t st);
+void net_features(int n, int Nf, int nsp, const int off[3], const double *r, const double *rn2, double rn2_value,
+                  const float pe[3], float *in16, float *rhat, const int *gate, hipStream_t st);
 void net_correction(long long nv, const float *o, const double *rn2, double h2a, double *e, const int *gate,
                     hipStream_t st);
 void net_accept(const double *scal, int *done, int *accepted, double factor, int *skip, hipStream_t st);
@@ -63,7 +63,6 @@ struct Net {
     float *partial = nullptr;
     float *rho = nullptr;     // residual of the loss (n^3)
     double *lpart = nullptr;
-    double *dscal = nullptr;  // device scalar: ||r||^2 for asdsm_net_features
     int *skip = nullptr;      // flags of the acceptance test (two ints)
     double *hloss = nullptr;  // pinned
     int nblk_loss = 0;

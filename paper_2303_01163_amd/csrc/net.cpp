@@ -67,10 +67,9 @@ void layout(Net &net, char *base) {
     net.rho = (float *)take(nv * 4);
     net.target = nullptr;
     const size_t nblk = net_reduce_blocks(net.n);
-    net.partial = (float *)take(nblk * wmax * 4);
+    net.partial = (float *)take(nblk * (wmax + 64) * 4);  // per block: weights and biases of every slice
     net.nblk_loss = (int)((nv + 255) / 256);
     net.lpart = (double *)take((size_t)net.nblk_loss * 8);
-    net.dscal = (double *)take(8);
     net.skip = (int *)take(2 * sizeof(int));
     net.ws_need = off;
 }
@@ -104,10 +103,9 @@ int backward(Net &net) {
     int cop_g = 16;
     float *bufs[2] = {net.gA, net.gB};
     for (int l = kNetLayers - 1; l >= 0; --l) {
+        // weights and biases of layer l (contiguous in the parameter vector)
         net_conv_wgrad(net.n, kNetCinP[l], kNetCoutP[l], g, cop_g, net.act[l], net.partial, net.G + net.wofs[l],
                        net.stream);
-        // all padded channels: the upstream gradient is zero beyond the real ones
-        net_bias_grad(net.n, g, cop_g, kNetCoutP[l], net.partial, net.G + net.bofs[l], net.stream);
         if (l == 0) break;
         // data gradient: transposed, flipped weights; then the ReLU of layer l-1's output
         net_flip(net.P + net.wofs[l], kNetCoutP[l], kNetCinP[l], net.Wt, net.stream);
@@ -190,6 +188,7 @@ int asdsm_net_set_workspace(asdsm_net_t h, void *dev, size_t bytes) {
     if (bytes < net.ws_need) return fail(ASDSM_E_WORKSPACE, "workspace too small: need " + std::to_string(net.ws_need) + " bytes");
     net.ws = dev;
     layout(net, (char *)dev);
+    net_conv_prepare();  // on the current device
     if (!net.hloss) NET_HIP_CHECK(hipHostMalloc((void **)&net.hloss, (size_t)net.nblk_loss * 8, hipHostMallocDefault));
     return asdsm_net_params(h, net.host_params.data(), 0);
 }
@@ -220,7 +219,6 @@ int asdsm_net_forward(asdsm_net_t h, const float *in, float *out) {
     if (int rc = require_ws(net)) return rc;
     if (int rc = forward(net, in)) return rc;
     NET_HIP_CHECK(hipMemcpyAsync(out, net.act[kNetLayers], (size_t)net.nvox * 4, hipMemcpyDeviceToDevice, net.stream));
-    NET_HIP_CHECK(hipStreamSynchronize(net.stream));
     set_error("");
     return ASDSM_OK;
 }
@@ -243,6 +241,11 @@ int asdsm_net_gradient(asdsm_net_t h, const float *in, const float *target, int 
     if (int rc = forward(net, in)) return rc;
     net_stencil_loss(net.n, net.act[kNetLayers], target, K, KT, net.rho, net.d16, net.lpart, net.stream);
     if (int rc = backward(net)) return rc;
+    if (!loss && !grad_host) {  // nothing to hand back: return once enqueued
+        NET_HIP_CHECK(hipGetLastError());
+        set_error("");
+        return ASDSM_OK;
+    }
     NET_HIP_CHECK(hipMemcpyAsync(net.hloss, net.lpart, (size_t)net.nblk_loss * 8, hipMemcpyDeviceToHost, net.stream));
     if (grad_host) NET_HIP_CHECK(hipMemcpyAsync(grad_host, net.G, net.nparam * 4, hipMemcpyDeviceToHost, net.stream));
     NET_HIP_CHECK(hipStreamSynchronize(net.stream));
@@ -294,10 +297,8 @@ int asdsm_net_features(asdsm_net_t h, const double *r, double rnorm2, const int 
         if (off[j] < 0 || off[j] + net.n > net.Nf) return fail(ASDSM_E_ARG, "window outside the fine mesh");
     }
     if (!(rnorm2 >= 0.0) || !std::isfinite(rnorm2)) return fail(ASDSM_E_ARG, "rnorm2 must be finite and >= 0");
-    NET_HIP_CHECK(hipMemcpyAsync(net.dscal, &rnorm2, sizeof(double), hipMemcpyHostToDevice, net.stream));
-    net_features(net.n, net.Nf, net.nsp, off, r, net.dscal, net.pe, in16, rhat, nullptr, net.stream);
+    net_features(net.n, net.Nf, net.nsp, off, r, nullptr, rnorm2, net.pe, in16, rhat, nullptr, net.stream);
     NET_HIP_CHECK(hipGetLastError());
-    NET_HIP_CHECK(hipStreamSynchronize(net.stream));
     set_error("");
     return ASDSM_OK;
 }
@@ -312,7 +313,6 @@ int asdsm_net_adam(asdsm_net_t h, float lr) {
     const float c1 = 1.f - std::pow(b1, (float)net.adam_t), c2 = 1.f - std::pow(b2, (float)net.adam_t);
     net_adam((int)net.nparam, net.P, net.G, net.M, net.V, lr, b1, b2, 1e-8f, c1, c2, net.stream);
     if (int rc = refresh_bf16(net)) return rc;
-    NET_HIP_CHECK(hipStreamSynchronize(net.stream));
     set_error("");
     return ASDSM_OK;
 }

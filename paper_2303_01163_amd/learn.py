@@ -22,7 +22,7 @@ import numpy as np
 from . import asdsm
 from .workloads import make_problem
 
-__all__ = ["TrainConfig", "train_correction", "problem_tensors"]
+__all__ = ["TrainConfig", "train_correction", "problem_tensors", "discrete_manufactured"]
 
 
 class TrainConfig:
@@ -30,7 +30,7 @@ class TrainConfig:
     ``iters`` plain refinement steps x ``windows`` residual windows per iterate = pairs."""
 
     def __init__(self, level=7, coarse_level=0, plans=8, sources=10, iters=32, windows=4, lr=1e-3,
-                 lr_final=5e-5, seed=1000, log_every=500):
+                 lr_final=5e-5, seed=1000, log_every=512, loss_every=8):
         self.level = int(level)
         self.coarse_level = int(coarse_level)
         self.plans = int(plans)
@@ -41,6 +41,7 @@ class TrainConfig:
         self.lr_final = float(lr_final)
         self.seed = int(seed)
         self.log_every = int(log_every)
+        self.loss_every = int(loss_every)   # the loss is read back (a host sync) every loss_every pairs
 
     @property
     def pairs(self) -> int:
@@ -54,6 +55,19 @@ def problem_tensors(P, device):
     return s, g
 
 
+def discrete_manufactured(plan, P, device):
+    """(s, g, u): the source that makes the manufactured grid function u of problem P the exact
+    solution of the discrete system (b_ff = A_ff u), so that the algebraic error of an iterate is
+    measured against u itself.  s = -(b_ff(s = 0) - A_ff u) = A_ff u - (Dirichlet terms), from the
+    library's own residual."""
+    import torch
+    g = torch.from_numpy(P.g_flat()).to(device)
+    u = torch.from_numpy(np.ascontiguousarray(P.u_exact.reshape(-1, order="F"))).to(device)
+    zero = torch.zeros_like(u)
+    r0, _ = plan.residual(u, zero, g)
+    return -r0, g, u
+
+
 def _lr(cfg: TrainConfig, step: int, total: int) -> float:
     """Cosine decay from lr to lr_final over the run."""
     c = 0.5 * (1.0 + math.cos(math.pi * min(step, total) / max(total, 1)))
@@ -62,7 +76,8 @@ def _lr(cfg: TrainConfig, step: int, total: int) -> float:
 
 def train_correction(net: "asdsm.Net", cfg: TrainConfig, log=None) -> dict:
     """Train ``net`` (built for windows of n^3 voxels, n <= N_f) in place; returns a summary with the
-    loss history (mean over each block of ``log_every`` pairs)."""
+    loss history (mean of the sampled losses -- every ``loss_every``-th pair -- over each block of
+    ``log_every`` pairs)."""
     import torch
     rng = np.random.default_rng(cfg.seed)
     total = cfg.pairs
@@ -94,13 +109,15 @@ def train_correction(net: "asdsm.Net", cfg: TrainConfig, log=None) -> dict:
                 for _ in range(cfg.windows):
                     off = rng.integers(0, nf - n + 1, size=3)
                     x, rhat = net.features(r, rn * rn, off)
-                    loss, _ = net.gradient(x, rhat, loss="residual", want_grad=False)
+                    sample = step % cfg.loss_every == 0
+                    loss, _ = net.gradient(x, rhat, loss="residual", want_grad=False, want_loss=sample)
                     net.adam(_lr(cfg, step, total))
                     if step == 0:
                         first_loss = loss
                     step += 1
-                    block.append(loss)
-                    if len(block) == cfg.log_every:
+                    if sample:
+                        block.append(loss)
+                    if step % cfg.log_every == 0 and block:
                         losses.append(float(np.mean(block)))
                         block = []
                         if log:
@@ -113,5 +130,6 @@ def train_correction(net: "asdsm.Net", cfg: TrainConfig, log=None) -> dict:
     if block:
         losses.append(float(np.mean(block)))
     net.plan = None
+    torch.cuda.synchronize(net.device)
     return {"pairs": step, "first_loss": first_loss, "loss_hist": losses, "seconds": time.perf_counter() - t0,
             "solve_seconds": solve_ms / 1e3, "config": vars(cfg).copy()}
