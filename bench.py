@@ -115,6 +115,11 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the size-based transform tiles")
     ap.add_argument("--batch", type=int, default=16,
                     help="members of the batched comparison (half 127^3, half 63^3); 0 skips it")
+    ap.add_argument("--learn-pairs", type=int, default=10240,
+                    help="training pairs of the learned-correction comparison; 0 skips it")
+    ap.add_argument("--learn-factor", type=float, default=1.1,
+                    help="acceptance factor of the learned solve (4 is also reported)")
+    ap.add_argument("--learn-iters", type=int, default=200, help="step limit of the learned comparison")
     return ap.parse_args()
 
 
@@ -204,6 +209,8 @@ def main():
         out["mixed_precision"] = mixed_precision(asdsm, make_problem, L, args, dev)
     if args.batch > 0:
         out["batched"] = batched(asdsm, make_problem, args, dev)
+    if args.learn_pairs > 0:
+        out["learned"] = learned(asdsm, make_problem, L, args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, L, args, iters)
     print(json.dumps(out))
@@ -279,6 +286,62 @@ def batched(asdsm, make_problem, args, dev, steps=3):
             "ms_sequential": 1e3 * t_seq, "ms_batched": 1e3 * t_bat,
             "unknowns_per_s_sequential": unknowns / t_seq, "unknowns_per_s_batched": unknowns / t_bat,
             "speedup": t_seq / t_bat}
+
+
+def learned(asdsm, make_problem, L, args, dev):
+    """Learned correction against the plain method.  A network is trained on the GPU on
+    args.learn_pairs residual windows (63^3 for 127^3 problems) of plain ASDSM runs (4 coefficient
+    draws, several sources each, 32 steps per run, 4 windows per step); then the bench workload's
+    coefficients with a discretely manufactured source (the manufactured grid function is the exact
+    discrete solution, so the error is the algebraic error against it) are solved plainly and with
+    learned proposals at args.learn_factor and at 4, each for up to args.learn_iters steps."""
+    import math
+    import torch
+    from paper_2303_01163_amd.learn import TrainConfig, discrete_manufactured, train_correction
+    nf = 2 ** L - 1
+    win = (nf + 1) // 2 - 1
+    plans, iters, windows = 4, 32, 4
+    sources = max(1, math.ceil(args.learn_pairs / (plans * iters * windows)))
+    net = asdsm.Net(win, seed=1, device=0)
+    cfg = TrainConfig(level=L, coarse_level=args.coarse_level, plans=plans, sources=sources, iters=iters,
+                      windows=windows, log_every=1024)
+    tr = train_correction(net, cfg)
+    big = asdsm.Net(nf, device=0)
+    big.set_params(net.get_params())
+    P = make_problem("sinbump3d", L, seed=args.seed)
+    plan = asdsm.Plan(3, P.alpha, P.beta, L, args.coarse_level, seed=args.seed, device=0)
+    big.bind(plan)
+    s, g, uex = discrete_manufactured(plan, P, dev)
+    nu = float(torch.linalg.norm(uex))
+    kw = dict(max_iter=args.learn_iters, rtol=args.rtol, stag_window=0)
+    runs = {}
+    for name, fac in (("plain", None), (f"learned_f{args.learn_factor:g}", args.learn_factor), ("learned_f4", 4.0)):
+        u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
+        for rep in range(2):  # the first call builds the graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if fac is None:
+                _, info = plan.solve(s, g, u=u, **kw)
+                info["accepted"] = 0
+            else:
+                _, info = asdsm.solve_learned(plan, big, s, g, u=u, factor=fac, **kw)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+        h = info["res_hist"]
+        runs[name] = {"factor": fac, "iterations": info["iterations"], "accepted": info["accepted"],
+                      "status": info["status_name"], "ms_per_solve": ms,
+                      "rel_residual": h[-1] / info["bnorm"], "min_rel_residual": min(h) / info["bnorm"],
+                      "rel_l2_error": float(torch.linalg.norm(u - uex)) / nu}
+    plain = runs["plain"]
+    best = runs[f"learned_f{args.learn_factor:g}"]
+    plan.close()
+    return {"workload": f"asdsm-3d-{nf}^3-sinbump-seed{args.seed}-discrete-manufactured",
+            "train": {"pairs": tr["pairs"], "window": win, "seconds": tr["seconds"],
+                      "solve_seconds": tr["solve_seconds"], "loss_first": tr["first_loss"],
+                      "loss_last_block": tr["loss_hist"][-1] if tr["loss_hist"] else None},
+            "runs": runs,
+            "error_gain": plain["rel_l2_error"] / best["rel_l2_error"],
+            "residual_gain": plain["min_rel_residual"] / best["min_rel_residual"]}
 
 
 def cpu_baseline(P, L, args, gpu_iters):
