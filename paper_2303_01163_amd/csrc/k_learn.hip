@@ -27,54 +27,69 @@ __device__ __forceinline__ unsigned short to_bf16(float x) {
 
 
 // ---------------------------------------------------------------------------------------------
-// Forward convolution, z-marching.  A block owns a 64 (x) by 4 (y) column of output voxels over a
-// chunk of zc planes; wave w owns row y0 + w: 4 M tiles of 16 x-voxels times COT N tiles of 16
-// output channels.  The layer's BF16 weights sit in LDS for the whole block, as w[tap][co][ci]; the
-// input (FP32 in memory, rounded to BF16 when staged) passes through a ring of three LDS planes of
-// 6 x 66 voxels with their halo, the plane two steps ahead being fetched into registers while the
-// current plane is computed.  K = 27 taps x CIN channels in steps of 16 (v_mfma_f32_16x16x16bf16_1k).
-// out[v*cop + co] = bias[co] + sum, ReLU when RELU, for co < cout.  Channel strides in LDS are
-// padded by 4 BF16 values (8-byte aligned fragments, fewer bank conflicts).
+// Forward convolution, z-marching.  A block (8 waves) owns a 64 (x) by 4 (y) column of output
+// voxels over a chunk of zc planes.  Wave w covers the 16 x-voxels 16 (w % 4) .. +15 and one N tile
+// of 16 output channels: with COT = 2 tiles, tile w / 4 for all 4 rows; with COT = 1, rows
+// 2 (w / 4) and 2 (w / 4) + 1.  The layer's BF16 weights sit in LDS for the whole block, as
+// w[tap][co][ci]; the input (FP32 in memory, rounded to BF16 when staged) passes through a ring of
+// three LDS planes of 6 x 66 voxels with their halo, the plane two steps ahead being fetched into
+// registers while the current plane is computed.  For each (dz, dx) a wave reads the A fragments
+// of its input rows once and uses each for up to three output rows (dy).  CIN = 32:
+// v_mfma_f32_16x16x32_bf16, one instruction per tap; CIN = 16: v_mfma_f32_16x16x16bf16_1k.
+// out[v*cop + co] = bias[co] + sum, ReLU when RELU, for co < cout.  The staged planes' channel
+// stride is padded by 8 BF16 values (aligned 16-byte fragments without bank conflicts).
+// Operand layouts (lane l): 16x16x32: A[l%16][8(l/16)+t], B[8(l/16)+t][l%16], t < 8;
+// 16x16x16: A[l%16][4(l/16)+t], B[4(l/16)+t][l%16], t < 4; both D[v] at row 4(l/16)+v, col l%16.
 // ---------------------------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+constexpr int kConvThreads = 512;
+
 template <int CIN, int COT>
 struct ConvLds {
-    static constexpr int CS = CIN + 4;                 // padded channel stride (BF16 values)
+    static constexpr int CS = CIN + 8;                 // staged plane channel stride (BF16 values)
     static constexpr int PLANE = 6 * 66 * CS;          // one staged input plane
-    static constexpr int WSZ = 27 * COT * 16 * CS;     // the weights
+    static constexpr int WSZ = 27 * COT * 16 * CIN;    // the weights, unpadded
     static constexpr int LOADS = 6 * 66 * CIN / 4;     // float4 loads per plane
-    static constexpr int PER_THREAD = (LOADS + 255) / 256;
+    static constexpr int PER_THREAD = (LOADS + kConvThreads - 1) / kConvThreads;
     static constexpr size_t BYTES = 2 * (size_t)(3 * PLANE + WSZ);
 };
 
 template <int CIN, int COT, bool RELU>
-__global__ __launch_bounds__(256) void k_conv_fwd(int n, int zc, const float *__restrict__ x,
-                                                  const unsigned short *__restrict__ w,
-                                                  const float *__restrict__ bias, int cout, int cop,
-                                                  float *__restrict__ out, const int *gate) {
+__global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const float *__restrict__ x,
+                                                           const unsigned short *__restrict__ w,
+                                                           const float *__restrict__ bias, int cout, int cop,
+                                                           float *__restrict__ out, const int *gate) {
+    static_assert(CIN == 16 || CIN == 32, "16 or 32 input channels");
+    static_assert(COT == 1 || COT == 2, "16 or 32 output channels");
     if (gate && *gate) return;
     using Lds = ConvLds<CIN, COT>;
-    constexpr int CS = Lds::CS, CO = COT * 16;
-    extern __shared__ unsigned short lds[];
-    unsigned short *sw = lds;                       // [27][CO][CS]
+    constexpr int CS = Lds::CS, CO = COT * 16, NT = kConvThreads;
+    constexpr int ROWS = (COT == 2) ? 4 : 2;  // output rows per wave
+    extern __shared__ __attribute__((aligned(16))) unsigned short lds[];
+    unsigned short *sw = lds;                       // [27][CO][CIN]
     unsigned short *sp = lds + Lds::WSZ;            // [3][6][66][CS]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int mt = wave & 3;                                   // M tile (16 x-voxels)
+    const int ct = (COT == 2) ? (wave >> 2) : 0;               // N tile
+    const int r0 = (COT == 2) ? 0 : 2 * (wave >> 2);           // first output row
     const int xtn = (n + 63) / 64, ytn = (n + 3) / 4;
     const int b = blockIdx.x;
-    const int xt = b % xtn, yt = (b / xtn) % ytn, ct = b / (xtn * ytn);
-    const int x0 = xt * 64, y0 = yt * 4, z0 = ct * zc;
+    const int xt = b % xtn, yt = (b / xtn) % ytn, zt = b / (xtn * ytn);
+    const int x0 = xt * 64, y0 = yt * 4, z0 = zt * zc;
     const int z1 = min(z0 + zc, n);
     // weights: global w[co][tap][ci] -> LDS [tap][co][ci]
-    for (int q = t; q < 27 * CO * (CIN / 4); q += 256) {
+    for (int q = t; q < 27 * CO * (CIN / 4); q += NT) {
         const int c4 = q % (CIN / 4), tap = (q / (CIN / 4)) % 27, co = q / (27 * (CIN / 4));
         const short4_t v = *reinterpret_cast<const short4_t *>(w + ((long long)co * 27 + tap) * CIN + 4 * c4);
-        *reinterpret_cast<short4_t *>(sw + (tap * CO + co) * CS + 4 * c4) = v;
+        *reinterpret_cast<short4_t *>(sw + (tap * CO + co) * CIN + 4 * c4) = v;
     }
-    // input plane gz (zero outside the volume) into registers / into ring slot
+    // input plane gz (zero outside the volume) into registers / into a ring slot
     float4_t pre[Lds::PER_THREAD];
     auto fetch = [&](int gz) {
 #pragma unroll
         for (int j = 0; j < Lds::PER_THREAD; ++j) {
-            const int q = t + 256 * j;
+            const int q = t + NT * j;
             const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, yi = q / (66 * (CIN / 4));
             const int gx = x0 - 1 + xi, gy = y0 - 1 + yi;
             const bool in = q < Lds::LOADS && gz >= 0 && gz < n && gx >= 0 && gx < n && gy >= 0 && gy < n;
@@ -86,7 +101,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(int n, int zc, const float *__
     auto store = [&](int slot) {
 #pragma unroll
         for (int j = 0; j < Lds::PER_THREAD; ++j) {
-            const int q = t + 256 * j;
+            const int q = t + NT * j;
             if (q < Lds::LOADS) {
                 const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, yi = q / (66 * (CIN / 4));
                 short4_t v;
@@ -103,50 +118,63 @@ __global__ __launch_bounds__(256) void k_conv_fwd(int n, int zc, const float *__
     fetch(z0 + 1);
     store((z0 + 1) % 3);
     __syncthreads();
-    const int y = y0 + wave;
+    constexpr int KL = (CIN == 32) ? 8 : 4;  // K values per lane and instruction
     for (int z = z0; z < z1; ++z) {
         if (z + 1 < z1) fetch(z + 2);  // in flight during the compute of plane z
-        float4_t acc[4][COT];
+        float4_t acc[ROWS];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int r = 0; r < ROWS; ++r) acc[r] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int c = 0; c < COT; ++c) acc[m][c] = {0.f, 0.f, 0.f, 0.f};
-        for (int tap = 0; tap < 27; ++tap) {
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // offsets + 1
-            const unsigned short *pa = sp + (((z + dz + 2) % 3 * 6 + wave + dy) * 66 + (lane & 15) + dx) * CS +
-                                       4 * (lane >> 4);
-            const unsigned short *pb = sw + (tap * CO + (lane & 15)) * CS + 4 * (lane >> 4);
+        for (int dz = 0; dz < 3; ++dz) {
+            const unsigned short *plane = sp + ((z + dz + 2) % 3) * Lds::PLANE;
 #pragma unroll
-            for (int c0 = 0; c0 < CIN; c0 += 16) {
-                short4_t bf[COT];
+            for (int dx = 0; dx < 3; ++dx) {
+                const unsigned short *pa = plane + (r0 * 66 + 16 * mt + (lane & 15) + dx) * CS + KL * (lane >> 4);
+                const unsigned short *pb = sw + ((dz * 9 + dx) * CO + 16 * ct + (lane & 15)) * CIN + KL * (lane >> 4);
+                if constexpr (CIN == 32) {
+                    bf16x8_t af[ROWS + 2], bf[3];
 #pragma unroll
-                for (int c = 0; c < COT; ++c) bf[c] = *reinterpret_cast<const short4_t *>(pb + c * 16 * CS + c0);
+                    for (int yi = 0; yi < ROWS + 2; ++yi)
+                        af[yi] = *reinterpret_cast<const bf16x8_t *>(pa + yi * 66 * CS);
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const short4_t af = *reinterpret_cast<const short4_t *>(pa + m * 16 * CS + c0);
+                    for (int dy = 0; dy < 3; ++dy) bf[dy] = *reinterpret_cast<const bf16x8_t *>(pb + dy * 3 * CO * CIN);
 #pragma unroll
-                    for (int c = 0; c < COT; ++c)
-                        acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[c], acc[m][c], 0, 0, 0);
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int r = 0; r < ROWS; ++r)
+                            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r + dy], bf[dy], acc[r], 0, 0, 0);
+                } else {
+                    short4_t af[ROWS + 2], bf[3];
+#pragma unroll
+                    for (int yi = 0; yi < ROWS + 2; ++yi)
+                        af[yi] = *reinterpret_cast<const short4_t *>(pa + yi * 66 * CS);
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy) bf[dy] = *reinterpret_cast<const short4_t *>(pb + dy * 3 * CO * CIN);
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int r = 0; r < ROWS; ++r)
+                            acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[r + dy], bf[dy], acc[r], 0, 0, 0);
                 }
             }
         }
-        // epilogue: D[v] is voxel x0 + 16 m + 4 (lane / 16) + v, channel 16 c + lane % 16
-        if (y < n) {
+        // epilogue: D[v] of row r is voxel x0 + 16 mt + 4 (lane / 16) + v of row y0 + r0 + r,
+        // channel 16 ct + lane % 16
+        const int co = 16 * ct + (lane & 15);
+        if (co < cout) {
+            const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
-            for (int c = 0; c < COT; ++c) {
-                const int co = c * 16 + (lane & 15);
-                if (co >= cout) continue;
-                const float bv = bias ? bias[co] : 0.f;
+            for (int r = 0; r < ROWS; ++r) {
+                const int yv = y0 + r0 + r;
+                if (yv >= n) continue;
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int xv = x0 + 16 * m + 4 * (lane >> 4) + v;
-                        if (xv >= n) continue;
-                        float r = acc[m][c][v] + bv;
-                        if (RELU) r = fmaxf(r, 0.f);
-                        out[((long long)xv + (long long)n * (y + (long long)n * z)) * cop + co] = r;
-                    }
+                for (int v = 0; v < 4; ++v) {
+                    const int xv = x0 + 16 * mt + 4 * (lane >> 4) + v;
+                    if (xv >= n) continue;
+                    float rr = acc[r][v] + bv;
+                    if (RELU) rr = fmaxf(rr, 0.f);
+                    out[((long long)xv + (long long)n * (yv + (long long)n * z)) * cop + co] = rr;
+                }
             }
         }
         __syncthreads();               // every wave is done with slot (z - 1) % 3
@@ -411,8 +439,8 @@ static void conv_launch(int n, const float *x, const unsigned short *w, const fl
     while (zc > 4 && (long long)xy * ((n + zc - 1) / zc) < 512) zc /= 2;
     const int blocks = xy * ((n + zc - 1) / zc);
     const size_t lds = ConvLds<CIN, COT>::BYTES;
-    ASDSM_LAUNCH((k_conv_fwd<CIN, COT, RELU>), dim3((unsigned)blocks), dim3(256), lds, st, n, zc, x, w, bias, cout,
-                 cop, out, gate);
+    ASDSM_LAUNCH((k_conv_fwd<CIN, COT, RELU>), dim3((unsigned)blocks), dim3(kConvThreads), lds, st, n, zc, x, w, bias,
+                 cout, cop, out, gate);
 }
 
 void net_conv_prepare() {
