@@ -43,7 +43,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("max_iter", c_int), ("rtol", c_double), ("stag_window", c_int),
                 ("stag_eta", c_double), ("resume", c_int), ("k0", c_int64),
                 ("hist", POINTER(c_double)), ("step_hist", POINTER(c_double)), ("profile", c_int),
-                ("eager", c_int), ("precision", c_int)]
+                ("eager", c_int), ("precision", c_int), ("skeleton", c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -151,14 +151,14 @@ def _fptr(t, n=None, name="tensor"):
     return c_void_p(t.data_ptr())
 
 
-def _opts(max_iter, rtol, stag_window, stag_eta, resume, k0, profile, eager, precision):
+def _opts(max_iter, rtol, stag_window, stag_eta, resume, k0, profile, eager, precision, skeleton=False):
     hist = (c_double * (max_iter + 1))()
     steps = (c_double * max(max_iter, 1))()
     o = Opts(max_iter=int(max_iter), rtol=float(rtol), stag_window=int(stag_window),
              stag_eta=float(stag_eta), resume=1 if resume else 0, k0=int(k0),
              hist=ctypes.cast(hist, POINTER(c_double)),
              step_hist=ctypes.cast(steps, POINTER(c_double)), profile=1 if profile else 0,
-             eager=1 if eager else 0, precision=PRECISIONS[precision])
+             eager=1 if eager else 0, precision=PRECISIONS[precision], skeleton=1 if skeleton else 0)
     return o, hist, steps
 
 
@@ -226,12 +226,13 @@ class Plan:
         return 2 * self.d * self.n_f ** (self.d - 1)
 
     def solve(self, s, g, u=None, max_iter=50, rtol=1e-10, stag_window=3, stag_eta=1e-3,
-              resume=False, k0=0, profile=False, eager=False, precision="fp64"):
+              resume=False, k0=0, profile=False, eager=False, precision="fp64", skeleton=False):
         import torch
         lib = load_library()
         if u is None:
             u = torch.empty(self.n_fine, dtype=torch.float64, device=self.device)
-        o, hist, steps = _opts(max_iter, rtol, stag_window, stag_eta, resume, k0, profile, eager, precision)
+        o, hist, steps = _opts(max_iter, rtol, stag_window, stag_eta, resume, k0, profile, eager, precision,
+                               skeleton)
         st = Stats()
         with torch.cuda.device(self.device):
             rc = _check(lib.asdsm_solve(self._h, _dptr(s, self.n_fine, "s"), _dptr(g, self.n_faces, "g"),
@@ -308,7 +309,8 @@ class Batch:
         up = (c_void_p * n)(*[_dptr(us[i], self.plans[i].n_fine, "u").value for i in range(n)])
         o = Opts(max_iter=int(max_iter), rtol=float(rtol), stag_window=int(stag_window),
                  stag_eta=float(stag_eta), resume=0, k0=0, hist=None, step_hist=None,
-                 profile=1 if profile else 0, eager=1 if eager else 0, precision=PRECISIONS[precision])
+                 profile=1 if profile else 0, eager=1 if eager else 0, precision=PRECISIONS[precision],
+                 skeleton=0)
         st = (Stats * n)()
         with torch.cuda.device(self.plans[0].device):
             _check(lib.asdsm_batch_solve(self._h, sp, gp, up, byref(o), st))

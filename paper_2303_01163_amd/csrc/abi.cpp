@@ -644,10 +644,9 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     return ASDSM_OK;
 }
 
-// One refinement step of Algorithm 4 from u_cur (with r and its gathers current) into u_next.  All
-// of its kernels return at once when the device stopping rule has fired (p.gate), so steps can be
-// queued (or replayed from a graph) ahead of the host's check.
-int refine_step(Plan &p, const double *u_cur, double *u_next) {
+// The error guess of a refinement step (Algorithm 1 with the residual as source): the anisotropic
+// solves, their normalisation, the cross points and the merge into the Y buffers.
+int error_guess(Plan &p) {
     if (p.prec32) {
         const double *in[kMaxD] = {};
         double *out[kMaxD] = {};
@@ -661,13 +660,18 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
     }
     const double *res[kMaxMeshes];
     result_pointers(p, res);
-    {
-        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 4 : 3, 0.0, 24.0 * aniso_points(p));
-        launch_box_norms(p, res, p.stream);
-        launch_crosspoints(p, 1, res, p.stream);
-        launch_merge(p, 1, res, p.stream);
-        if (int rc = check_launch("skeleton")) return rc;
-    }
+    PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 4 : 3, 0.0, 24.0 * aniso_points(p));
+    launch_box_norms(p, res, p.stream);
+    launch_crosspoints(p, 1, res, p.stream);
+    launch_merge(p, 1, res, p.stream);
+    return check_launch("skeleton");
+}
+
+// One refinement step of Algorithm 4 from u_cur (with r and its gathers current) into u_next.  All
+// of its kernels return at once when the device stopping rule has fired (p.gate), so steps can be
+// queued (or replayed from a graph) ahead of the host's check.
+int refine_step(Plan &p, const double *u_cur, double *u_next) {
+    if (int rc = error_guess(p)) return rc;
     {
         PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
                      8.0 * ((double)p.geo.NF + aniso_points(p)));
@@ -686,6 +690,33 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
         gather_pointers(p, gat);
         launch_update_residual(p, u_cur, p.ws.e, u_next, gat, kFinIter, p.stream);
         if (int rc = check_launch("update")) return rc;
+    }
+    return ASDSM_OK;
+}
+
+// Skeleton-sparse refinement step (d = 3): the same error guess, then only what the next step and
+// the line search need -- the error guess on the hole layers next to the coarse planes (the filler
+// in adjacent-layer mode), q = A e and <r, q>, <q, q> on the skeleton, and u += s e, r -= s q with
+// the gathers on the skeleton.  The fine u is rebuilt from the skeleton when the loop ends.
+int sparse_step(Plan &p) {
+    if (int rc = error_guess(p)) return rc;
+    const double skel = aniso_points(p);  // skeleton points counted once per mesh
+    {
+        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p), 8.0 * (3.0 * skel));
+        launch_filler(p, nullptr, nullptr, p.stream, nullptr, true);
+        if (int rc = check_launch("filler (layers)")) return rc;
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_DOTS, 1, 17.0 * skel, 8.0 * 5.0 * skel);
+        launch_skel_dots(p, p.stream);
+        if (int rc = check_launch("skeleton dots")) return rc;
+    }
+    {
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 5.0 * skel, 8.0 * 7.0 * skel);
+        double *gat[kMaxMeshes];
+        gather_pointers(p, gat);
+        launch_skel_update(p, gat, p.stream);
+        if (int rc = check_launch("skeleton update")) return rc;
     }
     return ASDSM_OK;
 }
@@ -736,7 +767,9 @@ int learned_step(Plan &p, const double *u_cur, double *u_next) {
 }
 
 int step(Plan &p, const double *u_cur, double *u_next) {
-    return p.learn_net ? learned_step(p, u_cur, u_next) : refine_step(p, u_cur, u_next);
+    if (p.learn_net) return learned_step(p, u_cur, u_next);
+    if (p.sparse) return sparse_step(p);
+    return refine_step(p, u_cur, u_next);
 }
 
 int require_ws(const Plan &p) {
@@ -785,6 +818,7 @@ int build_graph(Plan &p, double *u) {
     }
     p.graph_u = u;
     p.graph_prec32 = p.prec32;
+    p.graph_sparse = p.sparse;
     p.graph_net_serial = p.learn_net ? p.learn_net->serial : 0;
     p.graph_net_ws = p.learn_net ? p.learn_net->ws : nullptr;
     p.graph_factor = p.learn_factor;
@@ -864,6 +898,15 @@ int normalize_opts(const asdsm_opts *o, asdsm_opts &opt) {
         return fail(ASDSM_E_ARG, "invalid options (max_iter must be < " + std::to_string(kHistCap) + ")");
     if (opt.precision != ASDSM_PREC_FP64 && opt.precision != ASDSM_PREC_FP32)
         return fail(ASDSM_E_ARG, "invalid precision");
+    if (opt.skeleton != 0 && opt.skeleton != 1) return fail(ASDSM_E_ARG, "invalid skeleton flag");
+    return ASDSM_OK;
+}
+
+// The skeleton-sparse loop runs on d = 3 plans whose holes have 15 points per axis (the filler that
+// writes the layers next to the coarse planes).
+int check_sparse(const Plan &p, const asdsm_opts &opt) {
+    if (opt.skeleton && !(p.d == 3 && p.n == 16))
+        return fail(ASDSM_E_UNSUPPORTED, "skeleton-sparse refinement needs d = 3 and H/h = 16");
     return ASDSM_OK;
 }
 
@@ -874,6 +917,7 @@ int begin_solve(Plan &p, const double *s, const double *g, double *u, const asds
     if (!s || !g || !u) return fail(ASDSM_E_ARG, "s, g and u must be non-NULL device pointers");
     if (int rc = require_ws(p)) return rc;
     p.prec32 = (opt.precision == ASDSM_PREC_FP32) && p.fp32_ok;
+    p.sparse = opt.skeleton != 0;
     for (int q = 0; q < ASDSM_NPHASE; ++q) {
         p.phase_ms[q] = 0.0;
         p.phase_launches[q] = 0;
@@ -909,8 +953,32 @@ int begin_solve(Plan &p, const double *s, const double *g, double *u, const asds
         launch_update_residual(p, u, nullptr, nullptr, gat, kFinInit, p.stream);
         if (int rc = check_launch("residual")) return rc;
     }
+    if (p.sparse) {  // u and r on the skeleton, from the fine vectors
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 0.0, 8.0 * 4.0 * aniso_points(p));
+        launch_skel_gather(p, u, p.stream);
+        if (int rc = check_launch("skeleton gather")) return rc;
+    }
     p.gate = &p.ws.state->done;
     return ASDSM_OK;
+}
+
+// Skeleton-sparse loop: the fine iterate from its skeleton (Algorithm 3 with b_ff, once), then its
+// fine residual (so that r and the gathers describe the returned u).  Not gated: it runs whatever
+// the stopping rule did.
+int finish_sparse(Plan &p, double *u) {
+    p.gate = nullptr;
+    {
+        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
+                     8.0 * (2.0 * (double)p.geo.NF + aniso_points(p)));
+        launch_filler(p, p.ws.b, u, p.stream, p.ws.SU, false);
+        if (int rc = check_launch("final fill")) return rc;
+    }
+    PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,
+                 8.0 * (3.0 * (double)p.geo.NF + aniso_points(p)));
+    double *gat[kMaxMeshes];
+    gather_pointers(p, gat);
+    launch_update_residual(p, u, nullptr, nullptr, gat, kFinRnorm, p.stream);
+    return check_launch("final residual");
 }
 
 // After the loop (the plan's stream is synchronised here): the final iterate into u, the
@@ -923,8 +991,9 @@ int end_solve(Plan &p, double *u, const asdsm_opts &opt, asdsm_stats *st) {
     const int it = hs.it;
     if (!hs.done) hs.status = ASDSM_MAXITER;
     if (hs.status == ASDSM_E_NUMERIC) return fail(ASDSM_E_NUMERIC, "non-finite right-hand side or residual");
-    // the iterate after `it` steps is in u for even it, in the second buffer for odd it
-    if (it % 2 == 1)
+    // the iterate after `it` steps is in u for even it, in the second buffer for odd it (the
+    // skeleton-sparse loop has written u itself)
+    if (it % 2 == 1 && !p.sparse)
         ASDSM_HIP_CHECK(hipMemcpyAsync(u, p.ws.u2, (size_t)p.geo.NF * sizeof(double), hipMemcpyDeviceToDevice, p.stream));
     double r0 = 0.0, rn = 0.0;
     ASDSM_HIP_CHECK(hipMemcpyAsync(&r0, p.ws.hist, sizeof(double), hipMemcpyDeviceToHost, p.stream));
@@ -958,6 +1027,9 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
                asdsm_stats *st) {
     asdsm_opts opt;
     if (int rc = normalize_opts(o, opt)) return rc;
+    if (int rc = check_sparse(p, opt)) return rc;
+    if (opt.skeleton && p.learn_net)
+        return fail(ASDSM_E_ARG, "learned proposals need the fine residual: no skeleton-sparse refinement");
     p.profiling = opt.profile != 0;
     p.prof_failed = false;
     p.ev_recs.clear();
@@ -978,7 +1050,8 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
     if (use_graph) {
         const uint64_t net_serial = p.learn_net ? p.learn_net->serial : 0;
         const void *net_ws = p.learn_net ? p.learn_net->ws : nullptr;
-        if (p.graph_u != u || !p.graph_exec || p.graph_prec32 != p.prec32 || p.graph_net_serial != net_serial ||
+        if (p.graph_u != u || !p.graph_exec || p.graph_prec32 != p.prec32 || p.graph_sparse != p.sparse ||
+            p.graph_net_serial != net_serial ||
             p.graph_net_ws != net_ws || (p.learn_net && p.graph_factor != p.learn_factor))
             rc = build_graph(p, u);
         // two steps per replay, two replays per host check; surplus steps are gated no-ops
@@ -1002,6 +1075,7 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
             if (hs.done) break;
         }
     }
+    if (rc == ASDSM_OK && p.sparse) rc = finish_sparse(p, u);
     if (rc != ASDSM_OK) {
         p.gate = nullptr;
         return rc;
@@ -1126,6 +1200,8 @@ int batch_solve_impl(Batch &b, const double *const *s, const double *const *g, d
                      const asdsm_opts *o, asdsm_stats *st) {
     asdsm_opts opt;
     if (int rc = normalize_opts(o, opt)) return rc;
+    if (opt.skeleton)
+        return fail(ASDSM_E_UNSUPPORTED, "batches run the fine-mesh refinement (no skeleton-sparse mode)");
     const int n = (int)b.plans.size();
     if (!s || !g || !u) return fail(ASDSM_E_ARG, "s, g and u must be non-NULL arrays of n pointers");
     if (opt.profile || opt.eager) {

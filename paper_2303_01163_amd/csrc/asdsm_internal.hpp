@@ -92,6 +92,9 @@ struct Workspace {
     double *lines[kMaxD] = {};   // cross-point discrepancies of each anisotropic mesh
     float *F1[kMaxD] = {};       // FP32 transform scratch of each anisotropic mesh (mixed
     float *F2[kMaxD] = {};       // precision error guesses)
+    // skeleton-sparse refinement (d = 3), per anisotropic mesh in its canonical layout: u, r and
+    // q = A e on the skeleton, and the error guess on the hole layers next to each plane (2 sides)
+    double *SU[kMaxD] = {}, *SR[kMaxD] = {}, *SQ[kMaxD] = {}, *EA[kMaxD] = {};
     IterState *state = nullptr;  // refinement-loop state
     double *hist = nullptr;      // ||r_k||, k = 0..it
     double *step_hist = nullptr; // s_hat_k
@@ -144,6 +147,7 @@ struct Plan {
     std::vector<float> W32[kMaxD], V32[kMaxD];
     float *dW32[kMaxD] = {}, *dV32[kMaxD] = {};
     bool prec32 = false;             // this call's error guesses run in FP32
+    bool sparse = false;             // this call's refinement runs on the skeleton only
     int tile_aniso = 0;              // FP64 transform tile of the anisotropic solves (0: auto)
     bool fp32_ok = false;            // every anisotropic mesh: 6e-8 * prod cond(V_j) <= 1e-3
     // hole line elimination factors (d = 3): for the mode pair q = m0 + nh m1 of the two transformed
@@ -174,6 +178,7 @@ struct Plan {
     hipGraphExec_t graph_exec = nullptr;
     const double *graph_u = nullptr;
     bool graph_prec32 = false;
+    bool graph_sparse = false;
     // learned proposals (a correction network bound to this plan) for this call, and the network
     // and acceptance factor of the captured graph
     struct Net *learn_net = nullptr;

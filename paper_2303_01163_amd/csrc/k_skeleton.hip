@@ -378,6 +378,8 @@ struct FillArgs {
     int tr[kMaxD];
     const double *bff;
     double *out;
+    double *adj[kMaxD];  // adjacent-layer mode (k_filler_mfma3): the layers next to each coarse plane
+    int adj_only;        // 1: write only those layers (skeleton-sparse refinement), not the fine tile
     const int *gate;
 };
 
@@ -681,11 +683,17 @@ __global__ __launch_bounds__(256, PREFETCH ? 2 : 4) void k_filler_mfma3(Geo g, F
     hole_transform_mfma(buf, j1, fv1, lane, wave);
     if (!PREFETCH) frag(a.V[j0], fv0);
     hole_transform_mfma(buf, j0, fv0, lane, wave);
-    // 5) write the whole tile (hole values and the skeleton planes above it), x_1 fastest
+    // 5) write the whole tile (hole values and the skeleton planes above it), x_1 fastest; or, in
+    // adjacent-layer mode, only the tile points next to a coarse plane across it (the first and last
+    // hole layer along each axis, skeleton points of other planes included) into that plane's layer
+    // buffer: side 1 (above) of plane t_j - 1 for l_j = 0, side 0 (below) of plane t_j for
+    // l_j = nh - 1, at the canonical offset of the two other fine coordinates
+    const long long lay = (long long)Nc * Nf2;  // one side's layers of one mesh
 #pragma unroll 2
     for (int o = tid; o < 4096; o += 256) {
         const int l0 = o & 15, l1 = (o >> 4) & 15, l2 = o >> 8;
-        if (n * tt[0] + l0 >= Nf || n * tt[1] + l1 >= Nf || n * tt[2] + l2 >= Nf) continue;
+        const int g0 = n * tt[0] + l0, g1 = n * tt[1] + l1, g2 = n * tt[2] + l2;
+        if (g0 >= Nf || g1 >= Nf || g2 >= Nf) continue;
         double v;
         if (l0 < nh && l1 < nh && l2 < nh) {
             v = buf[l0 + kFS1 * l1 + kFS2 * l2];
@@ -696,15 +704,26 @@ __global__ __launch_bounds__(256, PREFETCH ? 2 : 4) void k_filler_mfma3(Geo g, F
         } else {
             v = a.skel[2][hi_base[2] + l0 + Nf * l1];
         }
-        a.out[f0 + l0 + Nf * l1 + Nf2 * l2] = v;
+        if (!a.adj_only) {
+            a.out[f0 + l0 + Nf * l1 + Nf2 * l2] = v;
+            continue;
+        }
+        if (l0 == 0 && tt[0] > 0) a.adj[0][lay + g1 + (long long)Nf * g2 + (long long)Nf2 * (tt[0] - 1)] = v;
+        if (l0 == nh - 1 && tt[0] < Nc) a.adj[0][g1 + (long long)Nf * g2 + (long long)Nf2 * tt[0]] = v;
+        if (l1 == 0 && tt[1] > 0) a.adj[1][lay + g0 + (long long)Nf * g2 + (long long)Nf2 * (tt[1] - 1)] = v;
+        if (l1 == nh - 1 && tt[1] < Nc) a.adj[1][g0 + (long long)Nf * g2 + (long long)Nf2 * tt[1]] = v;
+        if (l2 == 0 && tt[2] > 0) a.adj[2][lay + g0 + (long long)Nf * g1 + (long long)Nf2 * (tt[2] - 1)] = v;
+        if (l2 == nh - 1 && tt[2] < Nc) a.adj[2][g0 + (long long)Nf * g1 + (long long)Nf2 * tt[2]] = v;
     }
 }
 
-void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st) {
+void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st, double *const *skel,
+                   bool adj_only) {
     FillArgs a;
     const int d = p.d, nh = p.n - 1;
     for (int j = 0; j < kMaxD; ++j) {
-        a.skel[j] = (j < d) ? p.ws.Y[1u << j] : nullptr;
+        a.skel[j] = (j < d) ? (skel ? skel[j] : p.ws.Y[1u << j]) : nullptr;
+        a.adj[j] = (j < d && adj_only) ? p.ws.EA[j] : nullptr;
         a.mk[j] = (j < d) ? p.mesh[1u << j] : MeshDesc();
         a.W[j] = (j < d) ? p.dWh[j] : nullptr;
         a.V[j] = (j < d) ? p.dVh[j] : nullptr;
@@ -719,6 +738,7 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
         if (j != p.hole_line_axis) a.tr[a.ntr++] = j;
     a.bff = bff;
     a.out = out;
+    a.adj_only = adj_only ? 1 : 0;
     a.gate = p.gate;
     int npts = 1;
     for (int j = 0; j < d; ++j) npts *= nh;

@@ -1,0 +1,183 @@
+// Skeleton-sparse refinement (d = 3).  After the filler (Algorithm 3) every hole equation holds, so
+// the fine residual r = b - A u vanishes off the coarse planes (Proposition 3.2(2)), and so does
+// q = A e for the homogeneous error guess e.  A refinement step therefore needs r, q and u only on
+// the skeleton (the points of the anisotropic meshes M_k) and e only on the skeleton and on the
+// hole layers next to it (the stencil's neighbours across a coarse plane); the holes of u are
+// filled once, when the loop ends (Section 3.3, first and last remarks: compute only the non-zero
+// residual entries, keep only the skeleton and the elements next to it).  The skeleton lives in the
+// anisotropic meshes' canonical layouts -- point (a, b) of plane c of M_k at a + N_f b + N_f^2 c,
+// a and b the fine coordinates of the two other axes in
+// increasing order -- and the layers next to plane c on side s (s = 0: one below, s = 1: one above
+// along axis k) at the same offset plus s N_c N_f^2.  A point on several planes is stored in each
+// of their meshes with identical values; sums count it once, in the mesh of its lowest coarse axis.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace asdsm {
+
+// Fine index and ownership of point idx of M_K.
+template <int K>
+__device__ __forceinline__ void skel_point(const Geo &g, long long idx, int &x0, int &x1, int &x2, bool &owner) {
+    const int Nf = g.Nf, n = g.n;
+    const int a = (int)(idx % Nf);
+    const int b = (int)((idx / Nf) % Nf);
+    const int c = (int)(idx / ((long long)Nf * Nf));
+    const int cf = (c + 1) * n - 1;
+    if (K == 0) { x0 = cf; x1 = a; x2 = b; owner = true; }
+    if (K == 1) { x0 = a; x1 = cf; x2 = b; owner = !on_coarse(a, n); }
+    if (K == 2) { x0 = a; x1 = b; x2 = cf; owner = !on_coarse(a, n) && !on_coarse(b, n); }
+}
+
+struct SkelPtrs {
+    double *p[kMaxD];
+};
+
+// U_k = u and R_k = r on every skeleton point (from the fine vectors after the initial guess).
+__global__ __launch_bounds__(256) void k_skel_gather(Geo g, const double *__restrict__ u, const double *__restrict__ r,
+                                                     SkelPtrs U, SkelPtrs R, const int *gate) {
+    if (gate && *gate) return;
+    const long long per = (long long)g.Nc * g.Nf * g.Nf;
+    const int k = blockIdx.y;
+    double *__restrict__ Uk = (k == 0) ? U.p[0] : (k == 1) ? U.p[1] : U.p[2];
+    double *__restrict__ Rk = (k == 0) ? R.p[0] : (k == 1) ? R.p[1] : R.p[2];
+    const long long sy = g.Nf, sz = (long long)g.Nf * g.Nf;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < per; idx += (long long)gridDim.x * 256) {
+        int x0, x1, x2;
+        bool own;
+        if (k == 0) skel_point<0>(g, idx, x0, x1, x2, own);
+        else if (k == 1) skel_point<1>(g, idx, x0, x1, x2, own);
+        else skel_point<2>(g, idx, x0, x1, x2, own);
+        const long long f = x0 + sy * x1 + sz * x2;
+        Uk[idx] = u[f];
+        Rk[idx] = r[f];
+    }
+}
+
+// q = A e on the skeleton points of M_K, from E_K (the merged skeleton values of the error guess)
+// and EA_K (the hole layers on both sides of each plane), summed over the axes in the fixed order
+// of the fine-mesh pass (centre, axis 0 -, +, axis 1 -, +, axis 2 -, +) so that the copies of a
+// point in several meshes agree bit for bit; partial sums of <r, q> and <q, q> over owned points.
+template <int K>
+__device__ __forceinline__ void skel_dots_mesh(const Geo &g, const double *__restrict__ E, const double *__restrict__ EA,
+                                               const double *__restrict__ R, double *__restrict__ Q, double &rq,
+                                               double &qq, int tile, int ntile) {
+    const int Nf = g.Nf;
+    const long long per = (long long)g.Nc * Nf * Nf;
+    const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
+    for (long long idx = (long long)tile * 256 + threadIdx.x; idx < per; idx += (long long)ntile * 256) {
+        int x0, x1, x2;
+        bool own;
+        skel_point<K>(g, idx, x0, x1, x2, own);
+        const int a = (int)(idx % Nf), b = (int)((idx / Nf) % Nf);
+        // neighbours within the plane (fine axes a, b) and across it (layers)
+        const double am = a > 0 ? E[idx - 1] : 0.0, ap = a < Nf - 1 ? E[idx + 1] : 0.0;
+        const double bm = b > 0 ? E[idx - Nf] : 0.0, bp = b < Nf - 1 ? E[idx + Nf] : 0.0;
+        const double cm = EA[idx], cp = EA[idx + per];
+        double q = bsum * E[idx];
+        if (K == 0) {
+            q += g.fine[0].a * cm; q += g.fine[0].c * cp;
+            q += g.fine[1].a * am; q += g.fine[1].c * ap;
+            q += g.fine[2].a * bm; q += g.fine[2].c * bp;
+        } else if (K == 1) {
+            q += g.fine[0].a * am; q += g.fine[0].c * ap;
+            q += g.fine[1].a * cm; q += g.fine[1].c * cp;
+            q += g.fine[2].a * bm; q += g.fine[2].c * bp;
+        } else {
+            q += g.fine[0].a * am; q += g.fine[0].c * ap;
+            q += g.fine[1].a * bm; q += g.fine[1].c * bp;
+            q += g.fine[2].a * cm; q += g.fine[2].c * cp;
+        }
+        Q[idx] = q;
+        if (own) {
+            rq += R[idx] * q;
+            qq += q * q;
+        }
+    }
+}
+
+// Grid (tiles, 3): blockIdx.y selects the mesh.  Partial sums per block at blockIdx.x + tiles * y.
+__global__ __launch_bounds__(256) void k_skel_dots(Geo g, SkelPtrs E, SkelPtrs EA, SkelPtrs R, SkelPtrs Q,
+                                                   double *partials, const int *gate) {
+    if (gate && *gate) return;
+    double rq = 0.0, qq = 0.0;
+    const int k = blockIdx.y;
+    if (k == 0) skel_dots_mesh<0>(g, E.p[0], EA.p[0], R.p[0], Q.p[0], rq, qq, blockIdx.x, gridDim.x);
+    else if (k == 1) skel_dots_mesh<1>(g, E.p[1], EA.p[1], R.p[1], Q.p[1], rq, qq, blockIdx.x, gridDim.x);
+    else skel_dots_mesh<2>(g, E.p[2], EA.p[2], R.p[2], Q.p[2], rq, qq, blockIdx.x, gridDim.x);
+    double vals[2] = {rq, qq};
+    block_partials<256, 2>(vals, partials, blockIdx.x + (size_t)gridDim.x * blockIdx.y);
+}
+
+// u += s e and r -= s q on the skeleton (Algorithm 4 step 7 and the residual it implies), the
+// projections of r onto the anisotropic meshes for the next error guess (steps 4.1/4.2: r
+// restricted to M_k is R_k itself), and partial sums of ||r||^2 over owned points.
+__global__ __launch_bounds__(256) void k_skel_update(Geo g, const double *__restrict__ scal, SkelPtrs U,
+                                                     SkelPtrs E, SkelPtrs R, SkelPtrs Q, SkelPtrs G,
+                                                     double *partials, const int *gate) {
+    if (gate && *gate) return;
+    const double s = scal[kScalStep];
+    const long long per = (long long)g.Nc * g.Nf * g.Nf;
+    const int k = blockIdx.y;
+    double *__restrict__ Uk = (k == 0) ? U.p[0] : (k == 1) ? U.p[1] : U.p[2];
+    const double *__restrict__ Ek = (k == 0) ? E.p[0] : (k == 1) ? E.p[1] : E.p[2];
+    double *__restrict__ Rk = (k == 0) ? R.p[0] : (k == 1) ? R.p[1] : R.p[2];
+    const double *__restrict__ Qk = (k == 0) ? Q.p[0] : (k == 1) ? Q.p[1] : Q.p[2];
+    double *__restrict__ Gk = (k == 0) ? G.p[0] : (k == 1) ? G.p[1] : G.p[2];
+    double acc = 0.0;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < per; idx += (long long)gridDim.x * 256) {
+        int x0, x1, x2;
+        bool own;
+        if (k == 0) skel_point<0>(g, idx, x0, x1, x2, own);
+        else if (k == 1) skel_point<1>(g, idx, x0, x1, x2, own);
+        else skel_point<2>(g, idx, x0, x1, x2, own);
+        Uk[idx] += s * Ek[idx];
+        const double rr = Rk[idx] - s * Qk[idx];
+        Rk[idx] = rr;
+        Gk[idx] = rr;
+        if (own) acc += rr * rr;
+    }
+    double vals[1] = {acc};
+    block_partials<256, 1>(vals, partials, blockIdx.x + (size_t)gridDim.x * blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+static SkelPtrs skel_ptrs(double *const *v) {
+    SkelPtrs s;
+    for (int k = 0; k < kMaxD; ++k) s.p[k] = v[k];
+    return s;
+}
+
+static int skel_tiles(const Plan &p) {
+    const long long per = (long long)p.Nc * p.Nf * p.Nf;
+    long long t = (per + 255) / 256;
+    const long long cap = p.max_blocks / 3;  // three meshes' partial sums fit the workspace
+    if (t > cap) t = cap;
+    return (int)(t < 1 ? 1 : t);
+}
+
+void launch_skel_gather(const Plan &p, const double *u, hipStream_t st) {
+    const int tiles = skel_tiles(p);
+    ASDSM_LAUNCH(k_skel_gather, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, u, p.ws.r, skel_ptrs(p.ws.SU),
+                 skel_ptrs(p.ws.SR), p.gate);
+}
+
+void launch_skel_dots(const Plan &p, hipStream_t st) {
+    const int tiles = skel_tiles(p);
+    double *E[kMaxD] = {p.ws.Y[1], p.ws.Y[2], p.ws.Y[4]};
+    ASDSM_LAUNCH(k_skel_dots, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, skel_ptrs(E), skel_ptrs(p.ws.EA),
+                 skel_ptrs(p.ws.SR), skel_ptrs(p.ws.SQ), p.ws.partials, p.gate);
+    launch_finalize(p, 3 * tiles, kFinDots, 1, st);
+}
+
+void launch_skel_update(const Plan &p, double *const *gather, hipStream_t st) {
+    const int tiles = skel_tiles(p);
+    double *E[kMaxD] = {p.ws.Y[1], p.ws.Y[2], p.ws.Y[4]};
+    double *G[kMaxD] = {gather[1], gather[2], gather[4]};
+    ASDSM_LAUNCH(k_skel_update, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, p.ws.scal, skel_ptrs(p.ws.SU),
+                 skel_ptrs(E), skel_ptrs(p.ws.SR), skel_ptrs(p.ws.SQ), skel_ptrs(G), p.ws.partials, p.gate);
+    launch_finalize(p, 3 * tiles, kFinIter, 1, st);
+}
+
+}  // namespace asdsm

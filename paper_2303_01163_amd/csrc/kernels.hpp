@@ -110,6 +110,13 @@ void launch_sumsq(const Plan &p, const double *const *x, const long long *n, int
 // p.ws.perm_table[p.ws.state->it].
 void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipStream_t st);
 void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t st);
-void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st);
+// skel: the merged skeleton values per anisotropic mesh (default: the Y buffers); adj_only: write the
+// hole layers next to each coarse plane into the EA buffers instead of the fine tiles
+void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st, double *const *skel = nullptr,
+                   bool adj_only = false);
+// skeleton-sparse refinement (k_sparse.hip)
+void launch_skel_gather(const Plan &p, const double *u, hipStream_t st);
+void launch_skel_dots(const Plan &p, hipStream_t st);
+void launch_skel_update(const Plan &p, double *const *gather, hipStream_t st);
 
 }  // namespace asdsm

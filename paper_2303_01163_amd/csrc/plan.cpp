@@ -346,6 +346,15 @@ void layout_workspace(Plan &p, char *base, bool assign) {
         w.F1[k] = (float *)take((size_t)p.mesh[1u << k].size * 4);
         w.F2[k] = (float *)take((size_t)p.mesh[1u << k].size * 4);
     }
+    if (p.d == 3) {
+        for (int k = 0; k < 3; ++k) {
+            const size_t sz = (size_t)p.mesh[1u << k].size;
+            w.SU[k] = (double *)take(sz * 8);
+            w.SR[k] = (double *)take(sz * 8);
+            w.SQ[k] = (double *)take(sz * 8);
+            w.EA[k] = (double *)take(2 * sz * 8);
+        }
+    }
     w.state = (IterState *)take(sizeof(IterState));
     w.hist = (double *)take((size_t)kHistCap * 8);
     w.step_hist = (double *)take((size_t)kHistCap * 8);

@@ -448,3 +448,66 @@ def test_autotuned_plan_keeps_parity(torch_dev):
     for K in (0, 3):
         u, info = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0)
         assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
+
+
+SPARSE_CASES = [  # d = 3 with H/h = 16 (holes of 15^3): (family, level, coarse_level, seed)
+    ("sinbump3d", 5, 1, 3),   # 31^3, one coarse plane per axis
+    ("sinbump3d", 6, 2, 5),   # 63^3, 3 coarse planes per axis
+]
+
+
+@pytest.mark.parametrize("fam,L,Lc,seed", SPARSE_CASES)
+@pytest.mark.parametrize("eager", [False, True])
+def test_skeleton_sparse_iterates(torch_dev, fam, L, Lc, seed, eager):
+    """Skeleton-sparse refinement (r, q and the updates on the coarse planes only, holes filled when
+    the loop ends) against the oracle's fine-mesh iteration, iterate by iterate, with the same
+    tolerances as the fine-mesh GPU loop."""
+    _say("skeleton-sparse iterates", fam, L, Lc, seed, "eager" if eager else "graph")
+    P = make_problem(fam, L, seed=seed)
+    o = Oracle(3, P.alpha, P.beta, L, Lc, seed=seed + 17)
+    ref = o.solve(P.s, P.g, max_iter=5, rtol=0, stag_window=0, keep_iterates=True)
+    pl = _plan(P, L, Lc, seed=seed + 17)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    b = o.fine_rhs(P.s, P.g)
+    rtol_r = [100 * 2.2e-16 * _rounding_scale_of_residual(o, ref.iterates[k], b) / ref.res_hist[k]
+              for k in range(6)]
+    for K in (1, 3, 5):
+        u, info = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0, skeleton=True, eager=eager)
+        assert info["iterations"] == K
+        assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
+        for k in range(K + 1):
+            assert abs(info["res_hist"][k] - ref.res_hist[k]) <= 1e-9 * ref.res_hist[k] + rtol_r[k] * ref.res_hist[k], k
+        for k in range(K):
+            assert abs(info["step_hist"][k] - ref.step_hist[k]) <= (1e-8 + rtol_r[k]) * abs(ref.step_hist[k]) + 1e-300, k
+        # the returned iterate's own residual is the last one of the history
+        _, nrm = pl.residual(u, s, g)
+        assert abs(nrm - info["res_hist"][-1]) <= 1e-8 * nrm + rtol_r[K] * nrm
+
+
+def test_skeleton_sparse_full_solve_matches_fine_loop(torch_dev):
+    """127^3 (the benchmark's configuration, stagnation rule on): the skeleton-sparse solve takes the
+    same steps as the fine-mesh solve and returns the same iterate."""
+    _say("skeleton-sparse full solve 127^3")
+    P = make_problem("sinbump3d", 7, seed=0)
+    pl = _plan(P, 7, 0, seed=0)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u0, i0 = pl.solve(s, g, max_iter=50, rtol=1e-10, stag_window=3)
+    u1, i1 = pl.solve(s, g, max_iter=50, rtol=1e-10, stag_window=3, skeleton=True)
+    assert i1["iterations"] == i0["iterations"] and i1["status"] == i0["status"]
+    assert _rel(u1.cpu().numpy(), u0.cpu().numpy()) <= TOL_ITER
+    for a, c in zip(i0["res_hist"], i1["res_hist"]):
+        assert abs(a - c) <= 1e-8 * a
+
+
+def test_skeleton_sparse_refused_where_not_built(torch_dev):
+    from paper_2303_01163_amd.asdsm import AsdsmError
+    P = make_problem("sinbump3d", 6, seed=4)
+    pl = _plan(P, 6, 3, seed=4)  # H/h = 8
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    with pytest.raises(AsdsmError) as ei:
+        pl.solve(s, g, max_iter=2, skeleton=True)
+    assert ei.value.code == -6
+    P2 = make_problem("sinprod2d", 6, seed=0)
+    pl2 = _plan(P2, 6, 2, seed=0)
+    with pytest.raises(AsdsmError):
+        pl2.solve(_t(torch_dev, P2.s_flat()), _t(torch_dev, P2.g_flat()), max_iter=2, skeleton=True)
