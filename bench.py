@@ -32,6 +32,7 @@ KERNEL_SOURCE = {"k_gemm_f64": "k_boxsolve.hip", "k_update_residual3": "k_stenci
                  "k_dots3": "k_stencil.hip", "k_filler_mfma3": "k_skeleton.hip",
                  "k_box_residual": "k_boxsolve.hip", "k_merge3": "k_skeleton.hip",
                  "k_line": "k_boxsolve.hip", "k_crosspoints": "k_skeleton.hip"}
+SKEL_KERNEL = {"update": "k_skel_update (+ the fine residual at the ends)", "dots": "k_skel_dots"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_asdsm3d_127.txt")
 
 
@@ -113,6 +114,8 @@ def parse():
                     help="error-phase submesh solves of the timed solves")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the size-based transform tiles")
+    ap.add_argument("--fine-loop", action="store_true",
+                    help="time the fine-mesh refinement loop instead of the skeleton-sparse one")
     ap.add_argument("--batch", type=int, default=16,
                     help="members of the batched comparison (half 127^3, half 63^3); 0 skips it")
     ap.add_argument("--learn-pairs", type=int, default=10240,
@@ -144,8 +147,10 @@ def main():
     s = torch.from_numpy(P.s_flat()).to(dev)
     g = torch.from_numpy(P.g_flat()).to(dev)
     u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
+    # the skeleton-sparse loop (same iterates up to rounding) where the library builds it
+    skeleton = (not args.fine_loop) and plan.n_f + 1 == 16 * (plan.n_c + 1)
     kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3,
-              precision=args.precision)
+              precision=args.precision, skeleton=skeleton)
     tuned = plan.autotune(repeats=10) if not args.no_autotune else None
 
     for _ in range(args.warmup):
@@ -171,7 +176,16 @@ def main():
     Nf = plan.n_f
     dominant = max(ph_ms, key=lambda k: ph_ms[k])
     roof = roofline(dominant, ph_ms, ph_n, ph_fl, ph_by)
-    stencil = {q: phase_rate(q, ph_ms, ph_n, ph_by) for q in ("update", "dots")}
+    # the fine-mesh stencil passes (k_update_residual3, k_dots3) are timed in a fine-loop solve; in
+    # the skeleton-sparse solve those phases hold the compact skeleton kernels
+    if skeleton:
+        _, prof_f = plan.solve(s, g, u=torch.empty_like(u), profile=True, **dict(kw, skeleton=False))
+        stencil = {q: phase_rate(q, prof_f["phase_ms"], prof_f["phase_launches"], prof_f["phase_bytes"])
+                   for q in ("update", "dots")}
+        skel_rates = {q: dict(phase_rate(q, ph_ms, ph_n, ph_by), kernel=SKEL_KERNEL[q]) for q in ("update", "dots")}
+    else:
+        stencil = {q: phase_rate(q, ph_ms, ph_n, ph_by) for q in ("update", "dots")}
+        skel_rates = None
 
     out = {
         "metric": METRIC,
@@ -202,8 +216,12 @@ def main():
         "profiled_total_ms": prof["total_ms"],
         "roofline": roof,
         "stencil_effective": stencil,
+        "skeleton_effective": skel_rates,
     }
     out["precision_used"] = infos[-1]["precision"]
+    out["refinement_loop"] = "skeleton-sparse" if skeleton else "fine-mesh"
+    if skeleton:
+        out["fine_loop_comparison"] = fine_loop(plan, s, g, kw, u, args.steps)
     out["autotune"] = tuned
     if not args.no_mixed:
         out["mixed_precision"] = mixed_precision(asdsm, make_problem, L, args, dev)
@@ -214,6 +232,24 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, L, args, iters)
     print(json.dumps(out))
+
+
+def fine_loop(plan, s, g, kw, u_sparse, steps):
+    """The same solves with the fine-mesh refinement loop: time, steps, and how far its result is
+    from the skeleton-sparse one."""
+    import torch
+    kf = dict(kw, skeleton=False)
+    u = torch.empty_like(u_sparse)
+    plan.solve(s, g, u=u, **kf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = plan.solve(s, g, u=u, **kf)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"ms_per_solve": ms, "iterations": info["iterations"],
+            "rel_residual": info["rnorm"] / info["bnorm"],
+            "rel_l2_vs_skeleton_sparse": float(torch.linalg.norm(u - u_sparse) / torch.linalg.norm(u))}
 
 
 def mixed_precision(asdsm, make_problem, L, args, dev, seed=1, steps=3):

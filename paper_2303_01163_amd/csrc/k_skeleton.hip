@@ -688,32 +688,38 @@ __global__ __launch_bounds__(256, PREFETCH ? 2 : 4) void k_filler_mfma3(Geo g, F
     // hole layer along each axis, skeleton points of other planes included) into that plane's layer
     // buffer: side 1 (above) of plane t_j - 1 for l_j = 0, side 0 (below) of plane t_j for
     // l_j = nh - 1, at the canonical offset of the two other fine coordinates
-    const long long lay = (long long)Nc * Nf2;  // one side's layers of one mesh
+    auto tile_value = [&](int l0, int l1, int l2) -> double {
+        if (l0 < nh && l1 < nh && l2 < nh) return buf[l0 + kFS1 * l1 + kFS2 * l2];
+        if (l0 == nh) return a.skel[0][hi_base[0] + l1 + Nf * l2];
+        if (l1 == nh) return a.skel[1][hi_base[1] + l0 + Nf * l2];
+        return a.skel[2][hi_base[2] + l0 + Nf * l1];
+    };
+    if (!a.adj_only) {
 #pragma unroll 2
-    for (int o = tid; o < 4096; o += 256) {
-        const int l0 = o & 15, l1 = (o >> 4) & 15, l2 = o >> 8;
+        for (int o = tid; o < 4096; o += 256) {
+            const int l0 = o & 15, l1 = (o >> 4) & 15, l2 = o >> 8;
+            if (n * tt[0] + l0 >= Nf || n * tt[1] + l1 >= Nf || n * tt[2] + l2 >= Nf) continue;
+            a.out[f0 + l0 + Nf * l1 + Nf2 * l2] = tile_value(l0, l1, l2);
+        }
+        return;
+    }
+    const long long lay = (long long)Nc * Nf2;  // one side's layers of one mesh
+    for (int o = tid; o < 6 * 256; o += 256) {
+        const int face = o >> 8, la = o & 15, lb = (o >> 4) & 15;
+        const int j = face >> 1, side = face & 1;  // side 0: layer l_j = 0 (above plane t_j - 1)
+        if (side == 0 ? tt[j] == 0 : tt[j] == Nc) continue;
+        const int lj = side == 0 ? 0 : nh - 1;
+        const int l0 = (j == 0) ? lj : la;
+        const int l1 = (j == 1) ? lj : (j == 0 ? la : lb);
+        const int l2 = (j == 2) ? lj : lb;
         const int g0 = n * tt[0] + l0, g1 = n * tt[1] + l1, g2 = n * tt[2] + l2;
         if (g0 >= Nf || g1 >= Nf || g2 >= Nf) continue;
-        double v;
-        if (l0 < nh && l1 < nh && l2 < nh) {
-            v = buf[l0 + kFS1 * l1 + kFS2 * l2];
-        } else if (l0 == nh) {
-            v = a.skel[0][hi_base[0] + l1 + Nf * l2];
-        } else if (l1 == nh) {
-            v = a.skel[1][hi_base[1] + l0 + Nf * l2];
-        } else {
-            v = a.skel[2][hi_base[2] + l0 + Nf * l1];
-        }
-        if (!a.adj_only) {
-            a.out[f0 + l0 + Nf * l1 + Nf2 * l2] = v;
-            continue;
-        }
-        if (l0 == 0 && tt[0] > 0) a.adj[0][lay + g1 + (long long)Nf * g2 + (long long)Nf2 * (tt[0] - 1)] = v;
-        if (l0 == nh - 1 && tt[0] < Nc) a.adj[0][g1 + (long long)Nf * g2 + (long long)Nf2 * tt[0]] = v;
-        if (l1 == 0 && tt[1] > 0) a.adj[1][lay + g0 + (long long)Nf * g2 + (long long)Nf2 * (tt[1] - 1)] = v;
-        if (l1 == nh - 1 && tt[1] < Nc) a.adj[1][g0 + (long long)Nf * g2 + (long long)Nf2 * tt[1]] = v;
-        if (l2 == 0 && tt[2] > 0) a.adj[2][lay + g0 + (long long)Nf * g1 + (long long)Nf2 * (tt[2] - 1)] = v;
-        if (l2 == nh - 1 && tt[2] < Nc) a.adj[2][g0 + (long long)Nf * g1 + (long long)Nf2 * tt[2]] = v;
+        const double v = tile_value(l0, l1, l2);
+        // fine coordinates of the two other axes, increasing order
+        const int ga = (j == 0) ? g1 : g0, gb = (j == 2) ? g1 : g2;
+        double *dst = (j == 0) ? a.adj[0] : (j == 1) ? a.adj[1] : a.adj[2];
+        const long long plane = side == 0 ? tt[j] - 1 : tt[j];
+        dst[(side == 0 ? lay : 0) + ga + (long long)Nf * gb + (long long)Nf2 * plane] = v;
     }
 }
 
