@@ -278,48 +278,82 @@ __global__ __launch_bounds__(64 * ROWS) void k_update_residual3(
     block_partials<64 * ROWS, 1>(vals, partials, blockIdx.x);
 }
 
-template <int ZC>
-__global__ __launch_bounds__(256) void k_dots3(Geo g, Tile3 tl, const double *__restrict__ e,
-                                               const double *__restrict__ r, double *partials,
-                                               const int *gate) {
+// Line-search products q = A e, <r, q>, <q, q> with the same z-marching tiles as the update pass:
+// the current plane of e with its one-point halo in LDS (double-buffered), the x_3 neighbours in
+// registers, and the next plane's e, halo and r loaded one step ahead.
+template <int ROWS, int ZC>
+__global__ __launch_bounds__(64 * ROWS) void k_dots3(Geo g, Tile3 tl, const double *__restrict__ e,
+                                                     const double *__restrict__ r, double *partials,
+                                                     const int *gate) {
     if (gate && *gate) return;
+    __shared__ double pl[2][ROWS + 2][66];
     const int Nf = g.Nf;
     double rq = 0.0, qq = 0.0;
     int xt, yt, zc;
     if (tile3_of(tl, xt, yt, zc)) {
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-        const int i0 = xt * 64 + tx, i1 = yt * 4 + ty;
-        if (i0 < Nf && i1 < Nf) {
-            const int sy = Nf, sz = Nf * Nf;
-            // neighbours outside the domain: zero coefficient, in-bounds address
-            const double ax = i0 > 0 ? g.fine[0].a : 0.0, cx = i0 < Nf - 1 ? g.fine[0].c : 0.0;
-            const double ay = i1 > 0 ? g.fine[1].a : 0.0, cy = i1 < Nf - 1 ? g.fine[1].c : 0.0;
-            const int oxm = i0 > 0 ? -1 : 0, oxp = i0 < Nf - 1 ? 1 : 0;
-            const int oym = i1 > 0 ? -sy : 0, oyp = i1 < Nf - 1 ? sy : 0;
-            const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
-            const int z0 = zc * ZC, z1 = min(Nf, z0 + ZC);
-            const int base = i0 + sy * i1;
-            double vprev = z0 > 0 ? e[base + (z0 - 1) * sz] : 0.0;
-            double vcur = e[base + z0 * sz];
-            for (int z = z0; z < z1; ++z) {
-                const int p = base + z * sz;
-                const double vnext = (z + 1 < Nf) ? e[p + sz] : 0.0;
-                double q = bsum * vcur;
-                q += ax * e[p + oxm];
-                q += cx * e[p + oxp];
-                q += ay * e[p + oym];
-                q += cy * e[p + oyp];
-                q += g.fine[2].a * vprev;
-                q += g.fine[2].c * vnext;
-                rq += r[p] * q;
+        const int i0 = xt * 64 + tx, i1 = yt * ROWS + ty;
+        const bool act = i0 < Nf && i1 < Nf;
+        const int sy = Nf, sz = Nf * Nf;
+        const int base = min(i0, Nf - 1) + sy * min(i1, Nf - 1);
+        const int z0 = zc * ZC, z1 = min(Nf, z0 + ZC);
+        // halo of the plane tile: row below, row above, column left, column right
+        const int h = threadIdx.x;
+        int hx = -1, hy = -1, hlx = 0, hly = 0;
+        if (h < 64) {
+            hx = xt * 64 + h; hy = yt * ROWS - 1; hlx = h + 1; hly = 0;
+        } else if (h < 128) {
+            hx = xt * 64 + h - 64; hy = yt * ROWS + ROWS; hlx = h - 63; hly = ROWS + 1;
+        } else if (h < 128 + ROWS) {
+            hx = xt * 64 - 1; hy = yt * ROWS + (h - 128); hlx = 0; hly = h - 127;
+        } else if (h < 128 + 2 * ROWS) {
+            hx = xt * 64 + 64; hy = yt * ROWS + (h - 128 - ROWS); hlx = 65; hly = h - 127 - ROWS;
+        }
+        const bool hload = h < 128 + 2 * ROWS;
+        const bool hval = hx >= 0 && hx < Nf && hy >= 0 && hy < Nf;
+        const int hbase = hval ? hx + sy * hy : 0;
+        double vprev = (act && z0 > 0) ? e[base + (z0 - 1) * sz] : 0.0;
+        double vcur = act ? e[base + z0 * sz] : 0.0;
+        const double hcur = hval ? e[hbase + z0 * sz] : 0.0;
+        double v1 = (act && z0 + 1 < Nf) ? e[base + (z0 + 1) * sz] : 0.0;
+        double hv1 = (hval && z0 + 1 < z1) ? e[hbase + (z0 + 1) * sz] : 0.0;
+        double r1 = act ? r[base + z0 * sz] : 0.0;
+        int buf = 0;
+        pl[0][ty + 1][tx + 1] = vcur;
+        if (hload) pl[0][hly][hlx] = hcur;
+        __syncthreads();
+        const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
+        for (int z = z0; z < z1; ++z) {
+            const int p = base + z * sz;
+            // one step ahead: e two planes up (the next plane's upper neighbour), its halo, next r
+            const double v2 = (act && z + 2 < Nf) ? e[p + 2 * sz] : 0.0;
+            const double hv2 = (hval && z + 2 < z1) ? e[hbase + (z + 2) * sz] : 0.0;
+            const double r2 = (act && z + 1 < z1) ? r[p + sz] : 0.0;
+            double q = bsum * vcur;
+            q += g.fine[0].a * pl[buf][ty + 1][tx];
+            q += g.fine[0].c * pl[buf][ty + 1][tx + 2];
+            q += g.fine[1].a * pl[buf][ty][tx + 1];
+            q += g.fine[1].c * pl[buf][ty + 2][tx + 1];
+            q += g.fine[2].a * vprev;
+            q += g.fine[2].c * v1;
+            if (act) {
+                rq += r1 * q;
                 qq += q * q;
-                vprev = vcur;
-                vcur = vnext;
             }
+            vprev = vcur;
+            vcur = v1;
+            v1 = v2;
+            const double hnext = hv1;
+            hv1 = hv2;
+            r1 = r2;
+            buf ^= 1;
+            pl[buf][ty + 1][tx + 1] = vcur;
+            if (hload) pl[buf][hly][hlx] = hnext;
+            __syncthreads();
         }
     }
     double vals[2] = {rq, qq};
-    block_partials<256, 2>(vals, partials, blockIdx.x);
+    block_partials<64 * ROWS, 2>(vals, partials, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -489,13 +523,13 @@ void launch_dots(const Plan &p, hipStream_t st) {
         return;
     }
     int blocks = 0;
-    Tile3 t = tile3(p.geo, 4, 16, blocks);
-    if (blocks <= p.max_blocks) {
-        ASDSM_LAUNCH((k_dots3<16>), dim3(blocks), dim3(256), 0, st, p.geo, t, p.ws.e, p.ws.r,
+    if (p.geo.Nf >= 255) {
+        const Tile3 t = tile3(p.geo, 16, 16, blocks);
+        ASDSM_LAUNCH((k_dots3<16, 16>), dim3(blocks), dim3(1024), 0, st, p.geo, t, p.ws.e, p.ws.r,
                      p.ws.partials, p.gate);
-    } else {  // N_f = 1023: longer chunks keep the partial sums within the workspace
-        t = tile3(p.geo, 4, 64, blocks);
-        ASDSM_LAUNCH((k_dots3<64>), dim3(blocks), dim3(256), 0, st, p.geo, t, p.ws.e, p.ws.r,
+    } else {
+        const Tile3 t = tile3(p.geo, 8, 8, blocks);
+        ASDSM_LAUNCH((k_dots3<8, 8>), dim3(blocks), dim3(512), 0, st, p.geo, t, p.ws.e, p.ws.r,
                      p.ws.partials, p.gate);
     }
     launch_finalize(p, blocks, kFinDots, 1, st);
