@@ -18,9 +18,11 @@ first three.  Everything is written from the definitions, in float64:
   the finite-difference check of the backward pass).
 * Losses: mean (t - K o)^2 over the voxels with a 7-point stencil K (centre, x-, x+, y-, y+, z-, z+;
   zero outside the volume); K = identity is the mean squared error.
-* Backward: dL/do = -(2/N) K^T rho; per layer dW = sum_v g (x) in, db = sum_v g, and the data
-  gradient, a convolution of g with the spatially flipped, channel-transposed weights, computed on
-  BF16-rounded g and weights when ``rounded`` (as the GPU does), followed by the ReLU mask.
+* Backward: dL/do = -(2/N) K^T rho; per layer dW = sum_v g (x) in (in = the layer input as the
+  forward pass used it: BF16-rounded when ``rounded``; g as stored, FP32), db = sum_v g, and the
+  data gradient, a convolution of g with the spatially flipped, channel-transposed weights,
+  computed on BF16-rounded g and weights when ``rounded`` (as the GPU does), followed by the ReLU
+  mask.
 
 Parity status: conv3d is pinned by a brute-force loop and by scipy.ndimage.correlate; the rounding
 by hand-computed BF16 values (ties to even); the backward pass by central finite differences of the
@@ -179,7 +181,7 @@ def loss_and_grad(params, x16, target, K=None, rounded=True):
     gl[..., 0] = g
     for l in range(LAYERS - 1, -1, -1):
         w, _ = layers[l]
-        x = acts[l]
+        x = _q(acts[l], rounded)  # the operand the forward pass used
         n = x.shape[0]
         xp = np.zeros((n + 2, n + 2, n + 2, x.shape[3]))
         xp[1:-1, 1:-1, 1:-1] = x

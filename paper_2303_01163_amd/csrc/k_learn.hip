@@ -78,11 +78,17 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const 
     const int xt = b % xtn, yt = (b / xtn) % ytn, zt = b / (xtn * ytn);
     const int x0 = xt * 64, y0 = yt * 4, z0 = zt * zc;
     const int z1 = min(z0 + zc, n);
-    // weights: global w[co][tap][ci] -> LDS [tap][co][ci]
+    // weights: global w[co][tap][ci] -> LDS [tap][co][ci], each row's four fragment chunks (KL
+    // values) permuted by (co >> SH) & 3 so that the 16 rows one fragment read touches fall in
+    // distinct banks
+    constexpr int KL = (CIN == 32) ? 8 : 4;  // K values per lane and instruction
+    constexpr int SH = (CIN == 32) ? 2 : 3;  // rows per bank cycle: 4 (64-byte rows) or 8 (32-byte)
     for (int q = t; q < 27 * CO * (CIN / 4); q += NT) {
         const int c4 = q % (CIN / 4), tap = (q / (CIN / 4)) % 27, co = q / (27 * (CIN / 4));
         const short4_t v = *reinterpret_cast<const short4_t *>(w + ((long long)co * 27 + tap) * CIN + 4 * c4);
-        *reinterpret_cast<short4_t *>(sw + (tap * CO + co) * CIN + 4 * c4) = v;
+        const int chunk = (4 * c4) / KL, within = (4 * c4) % KL;
+        const int phys = (chunk ^ ((co >> SH) & 3)) * KL + within;
+        *reinterpret_cast<short4_t *>(sw + (tap * CO + co) * CIN + phys) = v;
     }
     // input plane gz (zero outside the volume) into registers / into a ring slot
     float4_t pre[Lds::PER_THREAD];
@@ -118,7 +124,6 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const 
     fetch(z0 + 1);
     store((z0 + 1) % 3);
     __syncthreads();
-    constexpr int KL = (CIN == 32) ? 8 : 4;  // K values per lane and instruction
     for (int z = z0; z < z1; ++z) {
         if (z + 1 < z1) fetch(z + 2);  // in flight during the compute of plane z
         float4_t acc[ROWS];
@@ -130,7 +135,9 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const 
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
                 const unsigned short *pa = plane + (r0 * 66 + 16 * mt + (lane & 15) + dx) * CS + KL * (lane >> 4);
-                const unsigned short *pb = sw + ((dz * 9 + dx) * CO + 16 * ct + (lane & 15)) * CIN + KL * (lane >> 4);
+                const int cob = 16 * ct + (lane & 15);
+                const unsigned short *pb =
+                    sw + ((dz * 9 + dx) * CO + cob) * CIN + KL * ((lane >> 4) ^ ((cob >> SH) & 3));
                 if constexpr (CIN == 32) {
                     bf16x8_t af[ROWS + 2], bf[3];
 #pragma unroll
@@ -183,66 +190,111 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const 
     }
 }
 
-// Backward weights and biases: dw[co][tap][ci] = sum_v g[v][co] x[v + off(tap)][ci] and
-// db[co] = sum_v g[v][co], a contraction over voxels on v_mfma_f32_16x16x4f32 (FP32 operands and
-// sums).  A tile is 64 consecutive voxels of one x-row; block b takes tiles b, b + gridDim.x, ... in
-// order.  Wave w owns the 16 x 16 channel tile pair w % P (P = COUT/16 * CIN/16) for all 27 taps
-// (27 accumulators) and, when P < 4, the voxel slice w / P of each tile (KS = 4 / P slices).  Every
-// (block, slice) writes its own partial gradient -- the weights, then COUT biases, the layout of
-// the parameter vector -- and k_reduce_blocks sums them in a fixed order, so the result does not
-// depend on scheduling.  g = upstream gradient (channels cop_g), x = layer input (CIN channels).
+// Backward weights and biases: dw[co][tap][ci] = sum_v g[v][co] bf16(x[v + off(tap)][ci]) and
+// db[co] = sum_v g[v][co] -- the gradient of the convolution as computed, whose operands x are the
+// BF16-rounded activations -- a contraction over voxels on v_mfma_f32_16x16x4f32 (FP32 products of
+// the FP32 gradient and the exactly widened BF16 activation, FP32 sums).  A work item is a run of
+// yc consecutive x-rows (64 voxels each) at fixed x tile and z; block b takes items b,
+// b + gridDim.x, ... in order.  Along the run the input rows pass through an LDS ring of four
+// y-slots, each holding the three planes z - 1, z, z + 1 of one row with its x halo (BF16), the row
+// two steps ahead being fetched into registers while the current row is computed, so every input
+// row is read once per item instead of nine times.  Wave w owns the 16 x 16 channel tile pair w % P
+// (P = COUT/16 * CIN/16) for all 27 taps (27 accumulators) and, when P < 4, the voxel slice w / P of
+// each row (KS = 4 / P slices).  Every (block, slice) writes its own partial gradient -- the
+// weights, then COUT biases, the layout of the parameter vector -- and k_reduce_blocks sums them in
+// a fixed order, so the result does not depend on scheduling.  g = upstream gradient (channels
+// cop_g), x = layer input (CIN channels).
+template <int CIN>
+struct WgradLds {
+    static constexpr int XS = CIN + 2;                          // staged voxel stride (BF16 values)
+    static constexpr int SLOT = 3 * 66 * XS;                    // one y-slot: 3 planes x 66 voxels
+    static constexpr int LOADS = 3 * 66 * CIN / 4;              // float4 loads per staged row
+    static constexpr int PER_THREAD = (LOADS + 255) / 256;
+};
+
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_wgrad(int n, const float *__restrict__ g, int cop_g,
+__global__ __launch_bounds__(256) void k_conv_wgrad(int n, int yc, const float *__restrict__ g, int cop_g,
                                                     const float *__restrict__ x,
                                                     float *__restrict__ partial) {
     constexpr int NCI = CIN / 16, P = (COUT / 16) * NCI, KS = 4 / P, KV = 64 / KS;
     constexpr int NW = COUT * 27 * CIN;
     static_assert(P * KS == 4, "four waves cover the channel tiles");
+    using Lds = WgradLds<CIN>;
+    constexpr int XS = Lds::XS;
     __shared__ float sg[64][COUT + 1];
-    __shared__ float sx[66][CIN + 1];
+    __shared__ unsigned short sx[4 * Lds::SLOT];  // [slot][plane][66][XS]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int pair = wave % P, slice = wave / P;
     const int cot = pair / NCI, cit = pair % NCI;
-    const int xtn = (n + 63) / 64;
-    const int ntiles = xtn * n * n;
+    const int xtn = (n + 63) / 64, ycn = (n + yc - 1) / yc;
+    const int nitems = xtn * n * ycn;
     float4_t acc[27];
 #pragma unroll
     for (int tp = 0; tp < 27; ++tp) acc[tp] = {0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;  // bias sum of channel `lane` over this slice's voxels (first wave of a slice)
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int row = tile / xtn;
-        const int x0 = (tile % xtn) * 64;
-        const int y = row % n, z = row / n;
-        __syncthreads();  // the previous tile's readers of sg and sx are done
-        for (int q = t; q < 64 * COUT; q += 256) {
-            const int vv = q / COUT, co = q % COUT;
-            const int xv = x0 + vv;
-            sg[vv][co] = (xv < n) ? g[((long long)xv + (long long)n * row) * cop_g + co] : 0.f;
-        }
+    float4_t pre[Lds::PER_THREAD];
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int xt = item % xtn, z = (item / xtn) % n, ych = item / (xtn * n);
+        const int x0 = xt * 64, y0 = ych * yc, y1 = min(y0 + yc, n);
+        // row yy (planes z - 1 .. z + 1, x halo) into registers, zero outside the volume
+        auto fetch = [&](int yy) {
 #pragma unroll
-        for (int dzy = 0; dzy < 9; ++dzy) {
-            const int yy = y + dzy % 3 - 1, zz = z + dzy / 3 - 1;
-            const bool rowin = yy >= 0 && yy < n && zz >= 0 && zz < n;
-            if (dzy > 0) __syncthreads();
-            for (int q = t; q < 66 * CIN; q += 256) {
-                const int xi = q / CIN, ci = q % CIN;
-                const int xx = x0 - 1 + xi;
-                sx[xi][ci] = (rowin && xx >= 0 && xx < n)
-                                 ? x[((long long)xx + (long long)n * (yy + (long long)n * zz)) * CIN + ci]
-                                 : 0.f;
+            for (int j = 0; j < Lds::PER_THREAD; ++j) {
+                const int q = t + 256 * j;  // float4 index
+                const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, pz = q / (66 * (CIN / 4));
+                const int xx = x0 - 1 + xi, zz = z - 1 + pz;
+                const bool in = q < Lds::LOADS && yy >= 0 && yy < n && zz >= 0 && zz < n && xx >= 0 && xx < n;
+                pre[j] = in ? *reinterpret_cast<const float4_t *>(
+                                  x + ((long long)xx + (long long)n * (yy + (long long)n * zz)) * CIN + 4 * c4)
+                            : float4_t{0.f, 0.f, 0.f, 0.f};
             }
-            __syncthreads();
-            if (dzy == 0 && pair == 0 && lane < COUT)
-                for (int vv = slice * KV; vv < slice * KV + KV; ++vv) bacc += sg[vv][lane];
-            for (int k0 = slice * KV; k0 < slice * KV + KV; k0 += 4) {
-                const int vv = k0 + (lane >> 4);
-                const float a = sg[vv][cot * 16 + (lane & 15)];
+        };
+        auto store = [&](int yy) {
+            unsigned short *dst = sx + (yy & 3) * Lds::SLOT;
 #pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const float b = sx[vv + dx][cit * 16 + (lane & 15)];
-                    acc[dzy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[dzy * 3 + dx], 0, 0, 0);
+            for (int j = 0; j < Lds::PER_THREAD; ++j) {
+                const int q = t + 256 * j;
+                if (q < Lds::LOADS) {
+                    const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, pz = q / (66 * (CIN / 4));
+                    unsigned short *p = dst + (pz * 66 + xi) * XS + 4 * c4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) p[e] = to_bf16(pre[j][e]);
                 }
             }
+        };
+        __syncthreads();  // the previous item's readers of the ring and of sg are done
+        fetch(y0 - 1);
+        store(y0 - 1);
+        fetch(y0);
+        store(y0);
+        fetch(y0 + 1);
+        store(y0 + 1);
+        for (int y = y0; y < y1; ++y) {
+            if (y + 1 < y1) fetch(y + 2);  // in flight during the compute of row y
+            for (int q = t; q < 64 * COUT; q += 256) {
+                const int vv = q / COUT, co = q % COUT;
+                const int xv = x0 + vv;
+                sg[vv][co] = (xv < n) ? g[((long long)xv + (long long)n * (y + (long long)n * z)) * cop_g + co] : 0.f;
+            }
+            __syncthreads();
+            if (pair == 0 && lane < COUT)
+                for (int vv = slice * KV; vv < slice * KV + KV; ++vv) bacc += sg[vv][lane];
+#pragma unroll
+            for (int dzy = 0; dzy < 9; ++dzy) {
+                const unsigned short *row = sx + ((y + dzy % 3 - 1) & 3) * Lds::SLOT + (dzy / 3) * 66 * XS;
+                for (int k0 = slice * KV; k0 < slice * KV + KV; k0 += 4) {
+                    const int vv = k0 + (lane >> 4);
+                    const float a = sg[vv][cot * 16 + (lane & 15)];
+                    const unsigned short *px = row + vv * XS + cit * 16 + (lane & 15);
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) {
+                        const float bv = __uint_as_float((unsigned)px[dx * XS] << 16);
+                        acc[dzy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[dzy * 3 + dx], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();  // done with sg and with the slot of row y - 1
+            if (y + 1 < y1) store(y + 2);
         }
     }
     float *dst = partial + ((size_t)blockIdx.x * KS + slice) * (NW + COUT);
@@ -258,14 +310,24 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int n, const float *__restri
 }
 
 // out[i] = sum_b partial[b * len + i] for i < len: 64 columns per block, the rows split over four
-// thread groups (rows b = grp, grp + 4, ...) whose sums are added in group order.
+// thread groups (rows b = grp, grp + 4, ...), each summing with eight independent partial sums so
+// that eight loads are in flight; all sums are combined in a fixed order.
 __global__ __launch_bounds__(256) void k_reduce_blocks(const float *__restrict__ partial, int nblk, int len,
                                                        float *__restrict__ out) {
     __shared__ float sh[4][64];
     const int col = blockIdx.x * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
     float s = 0.f;
-    if (col < len)
-        for (int b = grp; b < nblk; b += 4) s += partial[(size_t)b * len + col];
+    if (col < len) {
+        const float *p = partial + col;
+        float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int b = grp;
+        for (; b + 28 < nblk; b += 32) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] += p[(size_t)(b + 4 * j) * len];
+        }
+        for (int j = 0; b < nblk; b += 4, ++j) a[j & 7] += p[(size_t)b * len];
+        s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
     sh[grp][threadIdx.x & 63] = s;
     __syncthreads();
     if (grp == 0 && col < len) out[col] = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
@@ -474,15 +536,25 @@ void net_conv_fwd(int n, int cin_p, int cout, int cop, bool relu, const float *x
     }
 }
 
+static int wgrad_rows(int n) {
+    // rows per work item: about two items per block where the volume allows
+    const long long cols = (long long)((n + 63) / 64) * n;
+    int yc = 8;
+    while (yc < n && cols * ((n + yc - 1) / yc) > 2LL * kNetMaxReduceBlocks) yc *= 2;
+    return yc < n ? yc : n;
+}
+
 void net_conv_wgrad(int n, int cin_p, int cout_p, const float *g, int cop_g, const float *x, float *partial,
                     float *dwb, hipStream_t st) {
-    const unsigned nb = net_reduce_blocks(n);
+    const int yc = wgrad_rows(n);
+    const long long items = (long long)((n + 63) / 64) * n * ((n + yc - 1) / yc);
+    const unsigned nb = (unsigned)(items < kNetMaxReduceBlocks ? items : kNetMaxReduceBlocks);
     if (cin_p == 16 && cout_p == 32)
-        ASDSM_LAUNCH((k_conv_wgrad<16, 32>), dim3(nb), dim3(256), 0, st, n, g, cop_g, x, partial);
+        ASDSM_LAUNCH((k_conv_wgrad<16, 32>), dim3(nb), dim3(256), 0, st, n, yc, g, cop_g, x, partial);
     else if (cin_p == 32 && cout_p == 32)
-        ASDSM_LAUNCH((k_conv_wgrad<32, 32>), dim3(nb), dim3(256), 0, st, n, g, cop_g, x, partial);
+        ASDSM_LAUNCH((k_conv_wgrad<32, 32>), dim3(nb), dim3(256), 0, st, n, yc, g, cop_g, x, partial);
     else if (cin_p == 32 && cout_p == 16)
-        ASDSM_LAUNCH((k_conv_wgrad<32, 16>), dim3(nb), dim3(256), 0, st, n, g, cop_g, x, partial);
+        ASDSM_LAUNCH((k_conv_wgrad<32, 16>), dim3(nb), dim3(256), 0, st, n, yc, g, cop_g, x, partial);
     const int len = cout_p * 27 * cin_p + cout_p;            // weights, then biases
     const int slices = 4 / ((cout_p / 16) * (cin_p / 16));  // partial gradients per block
     ASDSM_LAUNCH(k_reduce_blocks, dim3((len + 63) / 64), dim3(256), 0, st, partial, (int)nb * slices, len, dwb);
