@@ -744,8 +744,8 @@ int learned_step(Plan &p, const double *u_cur, double *u_next) {
                      nullptr, done, p.stream);
         for (int l = 0; l < kNetLayers; ++l) {
             const bool last = (l == kNetLayers - 1);
-            net_conv_fwd(net.n, kNetCinP[l], kNetCout[l], last ? 1 : 32, !last, net.act[l], net.Wb[l],
-                         net.P + net.bofs[l], net.act[l + 1], done, p.stream);
+            net_conv_fwd(net.n, kNetCinP[l], kNetCout[l], last ? 1 : 32, !last, net.act[l], l > 0, net.Wb[l],
+                         net.P + net.bofs[l], net.act[l + 1], !last, done, p.stream);
         }
         net_correction(p.geo.NF, net.act[kNetLayers], p.ws.scal + kScalRnorm2, net.h2a, p.ws.e, done, p.stream);
         launch_dots(p, p.stream);

@@ -10,6 +10,8 @@
 // t = 0..3; D[v] at row 4(l/16)+v, col l%16.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "learn_internal.hpp"
@@ -55,15 +57,30 @@ struct ConvLds {
     static constexpr size_t BYTES = 2 * (size_t)(3 * PLANE + WSZ);
 };
 
-template <int CIN, int COT, bool RELU>
-__global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const float *__restrict__ x,
+// One MFMA step of the convolution: K = 32 (16x16x32, 8 values per lane) or 16 (16x16x16, 4).
+template <int CIN>
+using ConvFrag = typename std::conditional<CIN == 32, bf16x8_t, short4_t>::type;
+
+template <int CIN>
+__device__ __forceinline__ float4_t conv_mfma(const ConvFrag<CIN> &a, const ConvFrag<CIN> &b, float4_t c) {
+    if constexpr (CIN == 32)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// XB: the input is stored as BF16 (else FP32, rounded when staged); OB: the output is stored as
+// BF16 (round to nearest even, else FP32).
+template <int CIN, int COT, bool RELU, bool XB, bool OB>
+__global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const void *__restrict__ xv,
                                                            const unsigned short *__restrict__ w,
                                                            const float *__restrict__ bias, int cout, int cop,
-                                                           float *__restrict__ out, const int *gate) {
+                                                           void *__restrict__ outv, const int *gate) {
     static_assert(CIN == 16 || CIN == 32, "16 or 32 input channels");
     static_assert(COT == 1 || COT == 2, "16 or 32 output channels");
     if (gate && *gate) return;
     using Lds = ConvLds<CIN, COT>;
+    using Frag = ConvFrag<CIN>;
     constexpr int CS = Lds::CS, CO = COT * 16, NT = kConvThreads;
     constexpr int ROWS = (COT == 2) ? 4 : 2;  // output rows per wave
     extern __shared__ __attribute__((aligned(16))) unsigned short lds[];
@@ -91,7 +108,8 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const 
         *reinterpret_cast<short4_t *>(sw + (tap * CO + co) * CIN + phys) = v;
     }
     // input plane gz (zero outside the volume) into registers / into a ring slot
-    float4_t pre[Lds::PER_THREAD];
+    using Pre = typename std::conditional<XB, short4_t, float4_t>::type;
+    Pre pre[Lds::PER_THREAD];
     auto fetch = [&](int gz) {
 #pragma unroll
         for (int j = 0; j < Lds::PER_THREAD; ++j) {
@@ -99,9 +117,13 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const 
             const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, yi = q / (66 * (CIN / 4));
             const int gx = x0 - 1 + xi, gy = y0 - 1 + yi;
             const bool in = q < Lds::LOADS && gz >= 0 && gz < n && gx >= 0 && gx < n && gy >= 0 && gy < n;
-            pre[j] = in ? *reinterpret_cast<const float4_t *>(
-                              x + ((long long)gx + (long long)n * (gy + (long long)n * gz)) * CIN + 4 * c4)
-                        : float4_t{0.f, 0.f, 0.f, 0.f};
+            const long long off = ((long long)gx + (long long)n * (gy + (long long)n * gz)) * CIN + 4 * c4;
+            if constexpr (XB)
+                pre[j] = in ? *reinterpret_cast<const short4_t *>(static_cast<const unsigned short *>(xv) + off)
+                            : short4_t{0, 0, 0, 0};
+            else
+                pre[j] = in ? *reinterpret_cast<const float4_t *>(static_cast<const float *>(xv) + off)
+                            : float4_t{0.f, 0.f, 0.f, 0.f};
         }
     };
     auto store = [&](int slot) {
@@ -111,8 +133,12 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const 
             if (q < Lds::LOADS) {
                 const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, yi = q / (66 * (CIN / 4));
                 short4_t v;
+                if constexpr (XB) {
+                    v = pre[j];
+                } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = (short)to_bf16(pre[j][e]);
+                    for (int e = 0; e < 4; ++e) v[e] = (short)to_bf16(pre[j][e]);
+                }
                 *reinterpret_cast<short4_t *>(sp + ((slot * 6 + yi) * 66 + xi) * CS + 4 * c4) = v;
             }
         }
@@ -129,41 +155,41 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const 
         float4_t acc[ROWS];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) acc[r] = {0.f, 0.f, 0.f, 0.f};
+        // nine (dz, dx) groups, software-pipelined: the fragments of group g + 1 are read from LDS
+        // while the MFMAs of group g run
+        const int cob = 16 * ct + (lane & 15);
+        const int pa_off = (r0 * 66 + 16 * mt + (lane & 15)) * CS + KL * (lane >> 4);
+        const unsigned short *pb0 = sw + cob * CIN + KL * ((lane >> 4) ^ ((cob >> SH) & 3));
+        auto load = [&](int grp, Frag (&af)[ROWS + 2], Frag (&bf)[3]) {
+            const int dz = grp / 3, dx = grp % 3;
+            const unsigned short *pa = sp + ((z + dz + 2) % 3) * Lds::PLANE + pa_off + dx * CS;
+            const unsigned short *pb = pb0 + (dz * 9 + dx) * CO * CIN;
 #pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-            const unsigned short *plane = sp + ((z + dz + 2) % 3) * Lds::PLANE;
+            for (int yi = 0; yi < ROWS + 2; ++yi) af[yi] = *reinterpret_cast<const Frag *>(pa + yi * 66 * CS);
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const unsigned short *pa = plane + (r0 * 66 + 16 * mt + (lane & 15) + dx) * CS + KL * (lane >> 4);
-                const int cob = 16 * ct + (lane & 15);
-                const unsigned short *pb =
-                    sw + ((dz * 9 + dx) * CO + cob) * CIN + KL * ((lane >> 4) ^ ((cob >> SH) & 3));
-                if constexpr (CIN == 32) {
-                    bf16x8_t af[ROWS + 2], bf[3];
+            for (int dy = 0; dy < 3; ++dy) bf[dy] = *reinterpret_cast<const Frag *>(pb + dy * 3 * CO * CIN);
+        };
+        auto compute = [&](const Frag (&af)[ROWS + 2], const Frag (&bf)[3]) {
 #pragma unroll
-                    for (int yi = 0; yi < ROWS + 2; ++yi)
-                        af[yi] = *reinterpret_cast<const bf16x8_t *>(pa + yi * 66 * CS);
+            for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                    for (int dy = 0; dy < 3; ++dy) bf[dy] = *reinterpret_cast<const bf16x8_t *>(pb + dy * 3 * CO * CIN);
+                for (int r = 0; r < ROWS; ++r) acc[r] = conv_mfma<CIN>(af[r + dy], bf[dy], acc[r]);
+        };
+        Frag fa0[ROWS + 2], fb0[3], fa1[ROWS + 2], fb1[3];
+        load(0, fa0, fb0);
 #pragma unroll
-                    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                        for (int r = 0; r < ROWS; ++r)
-                            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r + dy], bf[dy], acc[r], 0, 0, 0);
-                } else {
-                    short4_t af[ROWS + 2], bf[3];
-#pragma unroll
-                    for (int yi = 0; yi < ROWS + 2; ++yi)
-                        af[yi] = *reinterpret_cast<const short4_t *>(pa + yi * 66 * CS);
-#pragma unroll
-                    for (int dy = 0; dy < 3; ++dy) bf[dy] = *reinterpret_cast<const short4_t *>(pb + dy * 3 * CO * CIN);
-#pragma unroll
-                    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                        for (int r = 0; r < ROWS; ++r)
-                            acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[r + dy], bf[dy], acc[r], 0, 0, 0);
-                }
+        for (int grp = 0; grp < 9; ++grp) {
+            // scheduling barriers keep the next group's LDS reads ahead of this group's MFMAs
+            if (grp % 2 == 0) {
+                if (grp + 1 < 9) load(grp + 1, fa1, fb1);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(fa0, fb0);
+            } else {
+                if (grp + 1 < 9) load(grp + 1, fa0, fb0);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(fa1, fb1);
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
         // epilogue: D[v] of row r is voxel x0 + 16 mt + 4 (lane / 16) + v of row y0 + r0 + r,
         // channel 16 ct + lane % 16
@@ -180,7 +206,11 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_fwd(int n, int zc, const 
                     if (xv >= n) continue;
                     float rr = acc[r][v] + bv;
                     if (RELU) rr = fmaxf(rr, 0.f);
-                    out[((long long)xv + (long long)n * (yv + (long long)n * z)) * cop + co] = rr;
+                    const long long o = ((long long)xv + (long long)n * (yv + (long long)n * z)) * cop + co;
+                    if constexpr (OB)
+                        static_cast<unsigned short *>(outv)[o] = to_bf16(rr);
+                    else
+                        static_cast<float *>(outv)[o] = rr;
                 }
             }
         }
@@ -212,9 +242,9 @@ struct WgradLds {
     static constexpr int PER_THREAD = (LOADS + 255) / 256;
 };
 
-template <int CIN, int COUT>
+template <int CIN, int COUT, bool XB>
 __global__ __launch_bounds__(256) void k_conv_wgrad(int n, int yc, const float *__restrict__ g, int cop_g,
-                                                    const float *__restrict__ x,
+                                                    const void *__restrict__ xv,
                                                     float *__restrict__ partial) {
     constexpr int NCI = CIN / 16, P = (COUT / 16) * NCI, KS = 4 / P, KV = 64 / KS;
     constexpr int NW = COUT * 27 * CIN;
@@ -232,7 +262,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int n, int yc, const float *
 #pragma unroll
     for (int tp = 0; tp < 27; ++tp) acc[tp] = {0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;  // bias sum of channel `lane` over this slice's voxels (first wave of a slice)
-    float4_t pre[Lds::PER_THREAD];
+    using Pre = typename std::conditional<XB, short4_t, float4_t>::type;
+    Pre pre[Lds::PER_THREAD];
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int xt = item % xtn, z = (item / xtn) % n, ych = item / (xtn * n);
         const int x0 = xt * 64, y0 = ych * yc, y1 = min(y0 + yc, n);
@@ -244,9 +275,13 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int n, int yc, const float *
                 const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, pz = q / (66 * (CIN / 4));
                 const int xx = x0 - 1 + xi, zz = z - 1 + pz;
                 const bool in = q < Lds::LOADS && yy >= 0 && yy < n && zz >= 0 && zz < n && xx >= 0 && xx < n;
-                pre[j] = in ? *reinterpret_cast<const float4_t *>(
-                                  x + ((long long)xx + (long long)n * (yy + (long long)n * zz)) * CIN + 4 * c4)
-                            : float4_t{0.f, 0.f, 0.f, 0.f};
+                const long long off = ((long long)xx + (long long)n * (yy + (long long)n * zz)) * CIN + 4 * c4;
+                if constexpr (XB)
+                    pre[j] = in ? *reinterpret_cast<const short4_t *>(static_cast<const unsigned short *>(xv) + off)
+                                : short4_t{0, 0, 0, 0};
+                else
+                    pre[j] = in ? *reinterpret_cast<const float4_t *>(static_cast<const float *>(xv) + off)
+                                : float4_t{0.f, 0.f, 0.f, 0.f};
             }
         };
         auto store = [&](int yy) {
@@ -258,7 +293,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int n, int yc, const float *
                     const int c4 = q % (CIN / 4), xi = (q / (CIN / 4)) % 66, pz = q / (66 * (CIN / 4));
                     unsigned short *p = dst + (pz * 66 + xi) * XS + 4 * c4;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) p[e] = to_bf16(pre[j][e]);
+                    for (int e = 0; e < 4; ++e) {
+                        if constexpr (XB)
+                            p[e] = (unsigned short)pre[j][e];
+                        else
+                            p[e] = to_bf16(pre[j][e]);
+                    }
                 }
             }
         };
@@ -351,13 +391,15 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float *__restrict__ a, un
     if (i < len) b[i] = to_bf16(a[i]);
 }
 
-// g[v*cop + c] *= (y[v*cop + c] > 0) for the first cout channels (ReLU backward), zero elsewhere.
-__global__ __launch_bounds__(256) void k_relu_mask(long long nvox, int cop, int cout, const float *__restrict__ y,
-                                                   float *__restrict__ g) {
+// g[v*cop + c] *= (y[v*cop + c] > 0) for the first cout channels (ReLU backward), zero elsewhere;
+// y is a BF16 activation (positive exactly when its FP32 value was).
+__global__ __launch_bounds__(256) void k_relu_mask(long long nvox, int cop, int cout,
+                                                   const unsigned short *__restrict__ y, float *__restrict__ g) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= nvox * cop) return;
     const int c = (int)(i % cop);
-    g[i] = (c < cout && y[i] > 0.f) ? g[i] : 0.f;
+    const float yv = __uint_as_float((unsigned)y[i] << 16);
+    g[i] = (c < cout && yv > 0.f) ? g[i] : 0.f;
 }
 
 // Loss of the output o against t through a 7-point stencil K (coefficients of the centre and of
@@ -492,48 +534,49 @@ unsigned net_reduce_blocks(int n) {
     return nb < (unsigned)kNetMaxReduceBlocks ? nb : (unsigned)kNetMaxReduceBlocks;
 }
 
-template <int CIN, int COT, bool RELU>
-static void conv_launch(int n, const float *x, const unsigned short *w, const float *bias, int cout, int cop,
-                        float *out, const int *gate, hipStream_t st) {
+template <int CIN, int COT, bool RELU, bool XB, bool OB>
+static void conv_launch(int n, const void *x, const unsigned short *w, const float *bias, int cout, int cop,
+                        void *out, const int *gate, hipStream_t st) {
     // z chunks: enough blocks to cover the chip twice where the volume allows, at least 4 planes each
     const int xy = ((n + 63) / 64) * ((n + 3) / 4);
     int zc = 16;
     while (zc > 4 && (long long)xy * ((n + zc - 1) / zc) < 512) zc /= 2;
     const int blocks = xy * ((n + zc - 1) / zc);
     const size_t lds = ConvLds<CIN, COT>::BYTES;
-    ASDSM_LAUNCH((k_conv_fwd<CIN, COT, RELU>), dim3((unsigned)blocks), dim3(kConvThreads), lds, st, n, zc, x, w, bias,
-                 cout, cop, out, gate);
+    ASDSM_LAUNCH((k_conv_fwd<CIN, COT, RELU, XB, OB>), dim3((unsigned)blocks), dim3(kConvThreads), lds, st, n, zc, x,
+                 w, bias, cout, cop, out, gate);
+}
+
+template <int CIN, int COT, bool RELU, bool XB, bool OB>
+static void conv_prepare_one() {
+    (void)hipFuncSetAttribute((const void *)k_conv_fwd<CIN, COT, RELU, XB, OB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)ConvLds<CIN, COT>::BYTES);
 }
 
 void net_conv_prepare() {
     // the kernels use more than 64 KB of dynamic LDS
-    (void)hipFuncSetAttribute((const void *)k_conv_fwd<16, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)ConvLds<16, 2>::BYTES);
-    (void)hipFuncSetAttribute((const void *)k_conv_fwd<16, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)ConvLds<16, 2>::BYTES);
-    (void)hipFuncSetAttribute((const void *)k_conv_fwd<32, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)ConvLds<32, 2>::BYTES);
-    (void)hipFuncSetAttribute((const void *)k_conv_fwd<32, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)ConvLds<32, 2>::BYTES);
-    (void)hipFuncSetAttribute((const void *)k_conv_fwd<32, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)ConvLds<32, 1>::BYTES);
-    (void)hipFuncSetAttribute((const void *)k_conv_fwd<32, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)ConvLds<32, 1>::BYTES);
+    conv_prepare_one<16, 2, true, false, true>();
+    conv_prepare_one<32, 2, true, true, true>();
+    conv_prepare_one<32, 1, false, true, false>();
+    conv_prepare_one<16, 2, false, false, false>();
+    conv_prepare_one<32, 2, false, false, false>();
 }
 
-void net_conv_fwd(int n, int cin_p, int cout, int cop, bool relu, const float *x, const unsigned short *w,
-                  const float *bias, float *out, const int *gate, hipStream_t st) {
+// The combinations the network uses: forward layers (first: FP32 input, BF16 output; hidden: BF16 in
+// and out; last: BF16 in, FP32 out) and the data gradients (FP32 in and out, no ReLU).
+void net_conv_fwd(int n, int cin_p, int cout, int cop, bool relu, const void *x, bool x_bf16, const unsigned short *w,
+                  const float *bias, void *out, bool out_bf16, const int *gate, hipStream_t st) {
     const int cot = (cout + 15) / 16;
-    if (cin_p == 16 && cot == 2) {
-        if (relu) conv_launch<16, 2, true>(n, x, w, bias, cout, cop, out, gate, st);
-        else conv_launch<16, 2, false>(n, x, w, bias, cout, cop, out, gate, st);
-    } else if (cin_p == 32 && cot == 2) {
-        if (relu) conv_launch<32, 2, true>(n, x, w, bias, cout, cop, out, gate, st);
-        else conv_launch<32, 2, false>(n, x, w, bias, cout, cop, out, gate, st);
-    } else if (cin_p == 32 && cot == 1) {
-        if (relu) conv_launch<32, 1, true>(n, x, w, bias, cout, cop, out, gate, st);
-        else conv_launch<32, 1, false>(n, x, w, bias, cout, cop, out, gate, st);
-    }
+    if (cin_p == 16 && cot == 2 && relu && !x_bf16 && out_bf16)
+        conv_launch<16, 2, true, false, true>(n, x, w, bias, cout, cop, out, gate, st);
+    else if (cin_p == 32 && cot == 2 && relu && x_bf16 && out_bf16)
+        conv_launch<32, 2, true, true, true>(n, x, w, bias, cout, cop, out, gate, st);
+    else if (cin_p == 32 && cot == 1 && !relu && x_bf16 && !out_bf16)
+        conv_launch<32, 1, false, true, false>(n, x, w, bias, cout, cop, out, gate, st);
+    else if (cin_p == 16 && cot == 2 && !relu && !x_bf16 && !out_bf16)
+        conv_launch<16, 2, false, false, false>(n, x, w, bias, cout, cop, out, gate, st);
+    else if (cin_p == 32 && cot == 2 && !relu && !x_bf16 && !out_bf16)
+        conv_launch<32, 2, false, false, false>(n, x, w, bias, cout, cop, out, gate, st);
 }
 
 static int wgrad_rows(int n) {
@@ -544,17 +587,18 @@ static int wgrad_rows(int n) {
     return yc < n ? yc : n;
 }
 
-void net_conv_wgrad(int n, int cin_p, int cout_p, const float *g, int cop_g, const float *x, float *partial,
-                    float *dwb, hipStream_t st) {
+void net_conv_wgrad(int n, int cin_p, int cout_p, const float *g, int cop_g, const void *x, bool x_bf16,
+                    float *partial, float *dwb, hipStream_t st) {
     const int yc = wgrad_rows(n);
     const long long items = (long long)((n + 63) / 64) * n * ((n + yc - 1) / yc);
     const unsigned nb = (unsigned)(items < kNetMaxReduceBlocks ? items : kNetMaxReduceBlocks);
-    if (cin_p == 16 && cout_p == 32)
-        ASDSM_LAUNCH((k_conv_wgrad<16, 32>), dim3(nb), dim3(256), 0, st, n, yc, g, cop_g, x, partial);
-    else if (cin_p == 32 && cout_p == 32)
-        ASDSM_LAUNCH((k_conv_wgrad<32, 32>), dim3(nb), dim3(256), 0, st, n, yc, g, cop_g, x, partial);
-    else if (cin_p == 32 && cout_p == 16)
-        ASDSM_LAUNCH((k_conv_wgrad<32, 16>), dim3(nb), dim3(256), 0, st, n, yc, g, cop_g, x, partial);
+    // the first layer's input is the FP32 network input, the others' the BF16 activations
+    if (cin_p == 16 && cout_p == 32 && !x_bf16)
+        ASDSM_LAUNCH((k_conv_wgrad<16, 32, false>), dim3(nb), dim3(256), 0, st, n, yc, g, cop_g, x, partial);
+    else if (cin_p == 32 && cout_p == 32 && x_bf16)
+        ASDSM_LAUNCH((k_conv_wgrad<32, 32, true>), dim3(nb), dim3(256), 0, st, n, yc, g, cop_g, x, partial);
+    else if (cin_p == 32 && cout_p == 16 && x_bf16)
+        ASDSM_LAUNCH((k_conv_wgrad<32, 16, true>), dim3(nb), dim3(256), 0, st, n, yc, g, cop_g, x, partial);
     const int len = cout_p * 27 * cin_p + cout_p;            // weights, then biases
     const int slices = 4 / ((cout_p / 16) * (cin_p / 16));  // partial gradients per block
     ASDSM_LAUNCH(k_reduce_blocks, dim3((len + 63) / 64), dim3(256), 0, st, partial, (int)nb * slices, len, dwb);
@@ -569,7 +613,7 @@ void net_to_bf16(const float *a, unsigned short *b, int len, hipStream_t st) {
     ASDSM_LAUNCH(k_to_bf16, dim3((len + 255) / 256), dim3(256), 0, st, a, b, len);
 }
 
-void net_relu_mask(long long nvox, int cop, int cout, const float *y, float *g, hipStream_t st) {
+void net_relu_mask(long long nvox, int cop, int cout, const unsigned short *y, float *g, hipStream_t st) {
     ASDSM_LAUNCH(k_relu_mask, dim3((unsigned)((nvox * cop + 255) / 256)), dim3(256), 0, st, nvox, cop, cout, y, g);
 }
 

@@ -19,13 +19,13 @@ struct NetStencil {
 };
 
 void net_conv_prepare();  // once per process, before the first convolution
-void net_conv_fwd(int n, int cin_p, int cout, int cop, bool relu, const float *x, const unsigned short *w,
-                  const float *bias, float *out, const int *gate, hipStream_t st);
-void net_conv_wgrad(int n, int cin_p, int cout_p, const float *g, int cop_g, const float *x, float *partial,
-                    float *dwb, hipStream_t st);
+void net_conv_fwd(int n, int cin_p, int cout, int cop, bool relu, const void *x, bool x_bf16, const unsigned short *w,
+                  const float *bias, void *out, bool out_bf16, const int *gate, hipStream_t st);
+void net_conv_wgrad(int n, int cin_p, int cout_p, const float *g, int cop_g, const void *x, bool x_bf16,
+                    float *partial, float *dwb, hipStream_t st);
 void net_flip(const float *w, int cout_p, int cin_p, unsigned short *wt, hipStream_t st);
 void net_to_bf16(const float *a, unsigned short *b, int len, hipStream_t st);
-void net_relu_mask(long long nvox, int cop, int cout, const float *y, float *g, hipStream_t st);
+void net_relu_mask(long long nvox, int cop, int cout, const unsigned short *y, float *g, hipStream_t st);
 void net_stencil_loss(int n, const float *o, const float *t, const NetStencil &K, const NetStencil &KT, float *rho,
                       float *d16, double *partial, hipStream_t st);
 void net_features(int n, int Nf, int nsp, const int off[3], const double *r, const double *rn2, double rn2_value,
@@ -58,7 +58,8 @@ struct Net {
     float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr;
     unsigned short *Wb[kNetLayers] = {};
     unsigned short *Wt = nullptr;
-    float *act[kNetLayers + 1] = {};  // act[0] = input copy (16 ch), act[1..3] (32 ch), act[4] output (1 ch)
+    // act[0] = input copy (16 ch, FP32), act[1..3] (32 ch, stored BF16), act[4] output (1 ch, FP32)
+    float *act[kNetLayers + 1] = {};
     float *gA = nullptr, *gB = nullptr, *d16 = nullptr, *target = nullptr;
     float *partial = nullptr;
     float *rho = nullptr;     // residual of the loss (n^3)

@@ -90,8 +90,8 @@ int forward(Net &net, const float *in) {
     NET_HIP_CHECK(hipMemcpyAsync(net.act[0], in, (size_t)net.nvox * 16 * 4, hipMemcpyDeviceToDevice, net.stream));
     for (int l = 0; l < kNetLayers; ++l) {
         const bool last = (l == kNetLayers - 1);
-        net_conv_fwd(net.n, kNetCinP[l], kNetCout[l], last ? 1 : 32, !last, net.act[l], net.Wb[l],
-                     net.P + net.bofs[l], net.act[l + 1], nullptr, net.stream);
+        net_conv_fwd(net.n, kNetCinP[l], kNetCout[l], last ? 1 : 32, !last, net.act[l], l > 0, net.Wb[l],
+                     net.P + net.bofs[l], net.act[l + 1], !last, nullptr, net.stream);
     }
     NET_HIP_CHECK(hipGetLastError());
     return ASDSM_OK;
@@ -104,15 +104,16 @@ int backward(Net &net) {
     float *bufs[2] = {net.gA, net.gB};
     for (int l = kNetLayers - 1; l >= 0; --l) {
         // weights and biases of layer l (contiguous in the parameter vector)
-        net_conv_wgrad(net.n, kNetCinP[l], kNetCoutP[l], g, cop_g, net.act[l], net.partial, net.G + net.wofs[l],
-                       net.stream);
+        net_conv_wgrad(net.n, kNetCinP[l], kNetCoutP[l], g, cop_g, net.act[l], l > 0, net.partial,
+                       net.G + net.wofs[l], net.stream);
         if (l == 0) break;
         // data gradient: transposed, flipped weights; then the ReLU of layer l-1's output
         net_flip(net.P + net.wofs[l], kNetCoutP[l], kNetCinP[l], net.Wt, net.stream);
         float *dx = bufs[l % 2];
-        net_conv_fwd(net.n, kNetCoutP[l], kNetCinP[l], kNetCinP[l], false, g, net.Wt, nullptr, dx, nullptr,
-                     net.stream);
-        net_relu_mask(net.nvox, kNetCinP[l], kNetCout[l - 1], net.act[l], dx, net.stream);
+        net_conv_fwd(net.n, kNetCoutP[l], kNetCinP[l], kNetCinP[l], false, g, false, net.Wt, nullptr, dx, false,
+                     nullptr, net.stream);
+        net_relu_mask(net.nvox, kNetCinP[l], kNetCout[l - 1], reinterpret_cast<const unsigned short *>(net.act[l]),
+                      dx, net.stream);
         g = dx;
         cop_g = kNetCinP[l];
     }

@@ -342,3 +342,27 @@ def test_net_argument_errors(torch_dev):
     net31.bind(plan)
     with pytest.raises(AsdsmError):
         solve_learned(plan, net31, s, g, factor=1.0)   # factor must exceed 1
+
+
+def test_learned_solve_with_fp32_guesses_and_resume(torch_dev):
+    """The learned step composes with FP32 error guesses and with resuming: accepted proposals still
+    meet the factor and a resumed learned solve continues from the given iterate."""
+    from paper_2303_01163_amd.asdsm import Net, solve_learned
+    P, plan = _bound_plan(5, seed=7)
+    net = Net(plan.n_f, seed=15)
+    net.bind(plan)
+    s, g = _dev64(torch_dev, P.s_flat()), _dev64(torch_dev, P.g_flat())
+    u, _ = plan.solve(s, g, max_iter=0)
+    for _ in range(20):
+        r, rn = plan.residual(u, s, g)
+        x, rhat = net.features(r, rn * rn)
+        net.gradient(x, rhat, loss="residual", want_grad=False, want_loss=False)
+        net.adam(1e-3)
+    for prec in ("fp64", "fp32"):
+        u1, info = solve_learned(plan, net, s, g, factor=1.2, max_iter=6, rtol=0, stag_window=0, precision=prec)
+        h = info["res_hist"]
+        assert sum(1 for k in range(len(h) - 1) if h[k + 1] * 1.2 <= h[k] * (1 + 1e-12)) >= info["accepted"]
+        u2, info2 = solve_learned(plan, net, s, g, u=u1.clone(), factor=1.2, max_iter=2, rtol=0, stag_window=0,
+                                  precision=prec, resume=True, k0=6)
+        assert info2["iterations"] == 2
+        assert abs(info2["res_hist"][0] - h[-1]) <= 1e-9 * h[-1]

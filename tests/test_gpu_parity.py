@@ -511,3 +511,21 @@ def test_skeleton_sparse_refused_where_not_built(torch_dev):
     pl2 = _plan(P2, 6, 2, seed=0)
     with pytest.raises(AsdsmError):
         pl2.solve(_t(torch_dev, P2.s_flat()), _t(torch_dev, P2.g_flat()), max_iter=2, skeleton=True)
+
+
+def test_skeleton_sparse_resume_and_fp32(torch_dev):
+    """Resuming a skeleton-sparse solve continues it exactly as one longer solve would (the skeleton
+    is rebuilt from the resumed fine iterate), and FP32 error guesses combine with the skeleton loop
+    as with the fine-mesh loop."""
+    P = make_problem("sinbump3d", 6, seed=5)
+    pl = _plan(P, 6, 2, seed=22)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u5, i5 = pl.solve(s, g, max_iter=5, rtol=0, stag_window=0, skeleton=True)
+    u2, _ = pl.solve(s, g, max_iter=2, rtol=0, stag_window=0, skeleton=True)
+    u2b, i3 = pl.solve(s, g, u=u2, max_iter=3, rtol=0, stag_window=0, skeleton=True, resume=True, k0=2)
+    assert i3["iterations"] == 3
+    assert _rel(u2b.cpu().numpy(), u5.cpu().numpy()) <= TOL_ITER
+    uf, if_ = pl.solve(s, g, max_iter=5, rtol=0, stag_window=0, precision="fp32")
+    us, is_ = pl.solve(s, g, max_iter=5, rtol=0, stag_window=0, precision="fp32", skeleton=True)
+    assert if_["precision"] == is_["precision"]
+    assert _rel(us.cpu().numpy(), uf.cpu().numpy()) <= TOL_ITER
