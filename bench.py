@@ -327,7 +327,7 @@ def batched(asdsm, make_problem, args, dev, steps=3):
 
 def learned(asdsm, make_problem, L, args, dev):
     """Learned correction against the plain method.  A network is trained on the GPU on
-    args.learn_pairs residual windows (63^3 for 127^3 problems) of plain ASDSM runs (4 coefficient
+    args.learn_pairs residual windows (63^3 for 127^3 problems) of plain ASDSM runs (8 coefficient
     draws, several sources each, 32 steps per run, 4 windows per step); then the bench workload's
     coefficients with a discretely manufactured source (the manufactured grid function is the exact
     discrete solution, so the error is the algebraic error against it) are solved plainly and with
@@ -337,7 +337,7 @@ def learned(asdsm, make_problem, L, args, dev):
     from paper_2303_01163_amd.learn import TrainConfig, discrete_manufactured, train_correction
     nf = 2 ** L - 1
     win = (nf + 1) // 2 - 1
-    plans, iters, windows = 4, 32, 4
+    plans, iters, windows = 8, 32, 4  # 8 coefficient draws: more variety per pair generalises better
     sources = max(1, math.ceil(args.learn_pairs / (plans * iters * windows)))
     net = asdsm.Net(win, seed=1, device=0)
     cfg = TrainConfig(level=L, coarse_level=args.coarse_level, plans=plans, sources=sources, iters=iters,
