@@ -35,6 +35,7 @@ KERNEL_SOURCE = {"k_gemm_f64": "k_boxsolve.hip", "k_update_residual3": "k_stenci
                  "k_skel_dots": "k_sparse.hip", "k_skel_update": "k_sparse.hip", "k_conv_fwd": "k_learn.hip"}
 SKEL_KERNEL = {"update": "k_skel_update (+ the fine residual at the ends)", "dots": "k_skel_dots"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_asdsm3d_127.txt")
+PMC_WORKLOAD = ("asdsm-3d-127^3-sinbump-seed0", 3)   # workload and coarse level the counters were taken on
 
 
 def kernel_digest(kernel):
@@ -54,9 +55,12 @@ def kernel_digest(kernel):
     return None
 
 
-def pmc_traffic(kernel):
+def pmc_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary, or None when there is none or the kernel's source changed since it was taken."""
+    summary, or None when there is none, the kernel's source changed since it was taken, or the
+    timed workload (name, coarse level) is not the one the counters were taken on."""
+    if tuple(workload) != PMC_WORKLOAD:
+        return None
     digest = kernel_digest(kernel)
     if digest is None or not os.path.exists(PMC_SUMMARY):
         return None
@@ -77,7 +81,7 @@ def phase_rate(phase, ph_ms, ph_n, ph_by):
             "GB/s": ph_by[phase] / (ms * 1e-3) / 1e9 if ms > 0 else None}
 
 
-def roofline(phase, ph_ms, ph_n, ph_fl, ph_by):
+def roofline(phase, ph_ms, ph_n, ph_fl, ph_by, workload):
     """Roofline position of the phase with the largest device time: algorithmic work per launch /
     average launch duration, against the MI355X peak of its bound (FP64 MFMA for the mode
     transforms, HBM for the rest)."""
@@ -93,7 +97,7 @@ def roofline(phase, ph_ms, ph_n, ph_fl, ph_by):
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": pmc_traffic(kernel), "kernel": kernel,
+            "frac": achieved / peak, "traffic": pmc_traffic(kernel, workload), "kernel": kernel,
             "phase": phase, "launches": ph_n[phase], "avg_launch_ms": avg_ms,
             "algorithmic_per_launch": per_launch,
             "algorithmic_bytes_per_launch": ph_by[phase] / n}
@@ -148,8 +152,8 @@ def main():
     s = torch.from_numpy(P.s_flat()).to(dev)
     g = torch.from_numpy(P.g_flat()).to(dev)
     u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
-    # the skeleton-sparse loop (same iterates up to rounding) where the library builds it
-    skeleton = (not args.fine_loop) and plan.n_f + 1 == 16 * (plan.n_c + 1)
+    # the skeleton-sparse loop (same iterates up to rounding) unless the fine-mesh loop is asked for
+    skeleton = not args.fine_loop
     kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3,
               precision=args.precision, skeleton=skeleton)
     tuned = plan.autotune(repeats=10) if not args.no_autotune else None
@@ -176,7 +180,8 @@ def main():
     ph_fl, ph_by = prof["phase_flops"], prof["phase_bytes"]
     Nf = plan.n_f
     dominant = max(ph_ms, key=lambda k: ph_ms[k])
-    roof = roofline(dominant, ph_ms, ph_n, ph_fl, ph_by)
+    roof = roofline(dominant, ph_ms, ph_n, ph_fl, ph_by,
+                    (f"asdsm-3d-{Nf}^3-sinbump-seed{args.seed}", plan.coarse_level))
     # the fine-mesh stencil passes (k_update_residual3, k_dots3) are timed in a fine-loop solve; in
     # the skeleton-sparse solve those phases hold the compact skeleton kernels
     if skeleton:

@@ -87,7 +87,7 @@ typedef struct {
                           /* sweeps); the residual, merge, filler and line search stay FP64.    */
                           /* The initial guess is FP64 in both modes.                           */
     int    skeleton;      /* nonzero: skeleton-sparse refinement (Section 3.3, first and last   */
-                          /* remarks; d = 3 with H/h = 16, else ASDSM_E_UNSUPPORTED): after the  */
+                          /* remarks; d = 3, else ASDSM_E_UNSUPPORTED): after the                */
                           /* initial guess every step computes r, q = A e and the updates only  */
                           /* on the coarse planes (the residual vanishes in the holes,          */
                           /* Proposition 3.2(2)) and e only there and on the hole layers next to */

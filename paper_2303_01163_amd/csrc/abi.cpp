@@ -902,11 +902,10 @@ int normalize_opts(const asdsm_opts *o, asdsm_opts &opt) {
     return ASDSM_OK;
 }
 
-// The skeleton-sparse loop runs on d = 3 plans whose holes have 15 points per axis (the filler that
-// writes the layers next to the coarse planes).
+// The skeleton-sparse loop runs on d = 3 plans (every hole size: both fillers write the layers next
+// to the coarse planes).
 int check_sparse(const Plan &p, const asdsm_opts &opt) {
-    if (opt.skeleton && !(p.d == 3 && p.n == 16))
-        return fail(ASDSM_E_UNSUPPORTED, "skeleton-sparse refinement needs d = 3 and H/h = 16");
+    if (opt.skeleton && p.d != 3) return fail(ASDSM_E_UNSUPPORTED, "skeleton-sparse refinement needs d = 3");
     return ASDSM_OK;
 }
 

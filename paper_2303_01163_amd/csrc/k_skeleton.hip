@@ -539,6 +539,21 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
             while (l[j] != n - 1) ++j;
             v = a.skel[j][canon_offset(a.mk[j], i, n)];
         }
+        if (D == 3 && a.adj_only) {
+            // adjacent-layer mode (see k_filler_mfma3): the first and last hole layer along each axis
+            const long long lay = (long long)Nc * Nf * Nf;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int ga = (j == 0) ? i[1] : i[0], gb = (j == 2) ? i[1] : i[2];
+                const int lj = (j == 0) ? l[0] : (j == 1) ? l[1] : l[2];
+                const int tj = (j == 0) ? tt[0] : (j == 1) ? tt[1] : tt[2];
+                double *dst = (j == 0) ? a.adj[0] : (j == 1) ? a.adj[1] : a.adj[2];
+                const long long inplane = ga + (long long)Nf * gb;
+                if (lj == 0 && tj > 0) dst[lay + inplane + (long long)Nf * Nf * (tj - 1)] = v;
+                if (lj == nh - 1 && tj < Nc) dst[inplane + (long long)Nf * Nf * tj] = v;
+            }
+            continue;
+        }
         const long long f = i[0] + (long long)Nf * (i[1] + (long long)Nf * (D == 3 ? i[2] : 0));
         a.out[f] = v;
     }

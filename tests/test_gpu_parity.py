@@ -450,9 +450,12 @@ def test_autotuned_plan_keeps_parity(torch_dev):
         assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
 
 
-SPARSE_CASES = [  # d = 3 with H/h = 16 (holes of 15^3): (family, level, coarse_level, seed)
-    ("sinbump3d", 5, 1, 3),   # 31^3, one coarse plane per axis
-    ("sinbump3d", 6, 2, 5),   # 63^3, 3 coarse planes per axis
+SPARSE_CASES = [  # d = 3: (family, level, coarse_level, seed)
+    ("sinbump3d", 5, 1, 3),   # 31^3, one coarse plane per axis, holes of 15^3 (MFMA filler)
+    ("sinbump3d", 6, 2, 5),   # 63^3, 3 coarse planes per axis, holes of 15^3
+    ("sinbump3d", 6, 3, 4),   # 63^3, 7 planes, holes of 7^3 (generic filler)
+    ("sinprod", 5, 3, 1),     # 31^3, 7 planes, holes of 3^3
+    ("sinprod", 4, 3, 2),     # 15^3, 7 planes, holes of one point
 ]
 
 
@@ -462,8 +465,9 @@ def test_skeleton_sparse_iterates(torch_dev, fam, L, Lc, seed, eager):
     """Skeleton-sparse refinement (r, q and the updates on the coarse planes only, holes filled when
     the loop ends) against the oracle's fine-mesh iteration, iterate by iterate, with the same
     tolerances as the fine-mesh GPU loop."""
+    d = 3
     _say("skeleton-sparse iterates", fam, L, Lc, seed, "eager" if eager else "graph")
-    P = make_problem(fam, L, seed=seed)
+    P = make_problem(fam, L, seed=seed, d=d)
     o = Oracle(3, P.alpha, P.beta, L, Lc, seed=seed + 17)
     ref = o.solve(P.s, P.g, max_iter=5, rtol=0, stag_window=0, keep_iterates=True)
     pl = _plan(P, L, Lc, seed=seed + 17)
@@ -501,16 +505,11 @@ def test_skeleton_sparse_full_solve_matches_fine_loop(torch_dev):
 
 def test_skeleton_sparse_refused_where_not_built(torch_dev):
     from paper_2303_01163_amd.asdsm import AsdsmError
-    P = make_problem("sinbump3d", 6, seed=4)
-    pl = _plan(P, 6, 3, seed=4)  # H/h = 8
-    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
-    with pytest.raises(AsdsmError) as ei:
-        pl.solve(s, g, max_iter=2, skeleton=True)
-    assert ei.value.code == -6
     P2 = make_problem("sinprod2d", 6, seed=0)
     pl2 = _plan(P2, 6, 2, seed=0)
-    with pytest.raises(AsdsmError):
+    with pytest.raises(AsdsmError) as ei:
         pl2.solve(_t(torch_dev, P2.s_flat()), _t(torch_dev, P2.g_flat()), max_iter=2, skeleton=True)
+    assert ei.value.code == -6
 
 
 def test_skeleton_sparse_resume_and_fp32(torch_dev):
