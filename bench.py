@@ -32,7 +32,8 @@ KERNEL_SOURCE = {"k_gemm_f64": "k_boxsolve.hip", "k_update_residual3": "k_stenci
                  "k_dots3": "k_stencil.hip", "k_filler_mfma3": "k_skeleton.hip",
                  "k_box_residual": "k_boxsolve.hip", "k_merge3": "k_skeleton.hip",
                  "k_line": "k_boxsolve.hip", "k_crosspoints": "k_skeleton.hip",
-                 "k_skel_dots": "k_sparse.hip", "k_skel_update": "k_sparse.hip", "k_conv_fwd": "k_learn.hip"}
+                 "k_skel_dots": "k_sparse.hip", "k_skel_update": "k_sparse.hip", "k_conv_fwd": "k_learn.hip",
+                 "k_plane2": "k_boxsolve.hip"}
 SKEL_KERNEL = {"update": "k_skel_update (+ the fine residual at the ends)", "dots": "k_skel_dots"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_asdsm3d_127.txt")
 PMC_WORKLOAD = ("asdsm-3d-127^3-sinbump-seed0", 3)   # workload and coarse level the counters were taken on
@@ -81,12 +82,13 @@ def phase_rate(phase, ph_ms, ph_n, ph_by):
             "GB/s": ph_by[phase] / (ms * 1e-3) / 1e9 if ms > 0 else None}
 
 
-def roofline(phase, ph_ms, ph_n, ph_fl, ph_by, workload):
+def roofline(phase, ph_ms, ph_n, ph_fl, ph_by, workload, transform_kernel="k_gemm_f64"):
     """Roofline position of the phase with the largest device time: algorithmic work per launch /
     average launch duration, against the MI355X peak of its bound (FP64 MFMA for the mode
-    transforms, HBM for the rest)."""
+    transforms, HBM for the rest).  The transform phase runs k_gemm_f64 (one launch per fine axis)
+    or k_plane2 (both fine axes of a coarse slab per launch), as the plan's tile choice says."""
     ms, n = ph_ms[phase], max(ph_n[phase], 1)
-    kernel = PHASE_KERNEL.get(phase, phase)
+    kernel = transform_kernel if phase == "transform" else PHASE_KERNEL.get(phase, phase)
     avg_ms = ms / n
     if phase == "transform":
         per_launch = ph_fl[phase] / n
@@ -180,8 +182,9 @@ def main():
     ph_fl, ph_by = prof["phase_flops"], prof["phase_bytes"]
     Nf = plan.n_f
     dominant = max(ph_ms, key=lambda k: ph_ms[k])
+    tkernel = "k_plane2" if plan.tile_name().startswith("plane") else "k_gemm_f64"
     roof = roofline(dominant, ph_ms, ph_n, ph_fl, ph_by,
-                    (f"asdsm-3d-{Nf}^3-sinbump-seed{args.seed}", plan.coarse_level))
+                    (f"asdsm-3d-{Nf}^3-sinbump-seed{args.seed}", plan.coarse_level), tkernel)
     # the fine-mesh stencil passes (k_update_residual3, k_dots3) are timed in a fine-loop solve; in
     # the skeleton-sparse solve those phases hold the compact skeleton kernels
     if skeleton:

@@ -178,6 +178,29 @@ int asdsm_autotune(asdsm_plan_t plan, int repeats, int *tile, double *ms_per_sol
 /* Static name of a tile shape returned by asdsm_autotune ("auto" for unknown values). */
 const char *asdsm_tile_name(int tile);
 
+/* Transform tile shapes of the anisotropic solves (values of asdsm_autotune's `tile`):
+ * ASDSM_TILE_AUTO picks by problem size; 1..4 run each fine-axis transform as its own batched GEMM
+ * launch with that output tile; ASDSM_TILE_PLANE (d = 3, N_f <= 255) runs both fine-axis transforms
+ * of every coarse slab in one launch. */
+#define ASDSM_TILE_AUTO   0
+#define ASDSM_TILE_32X32  1
+#define ASDSM_TILE_64X32  2
+#define ASDSM_TILE_32X64  3
+#define ASDSM_TILE_64X64  4
+#define ASDSM_TILE_PLANE  5
+
+/* Force the transform tile shape of this plan's anisotropic solves (the autotuner's choice is
+ * replaced).  Same iterates up to rounding for every shape.
+ * Errors: ASDSM_E_ARG (unknown tile), ASDSM_E_UNSUPPORTED (ASDSM_TILE_PLANE with d = 2 or
+ * N_f > 255). */
+int asdsm_set_tile(asdsm_plan_t plan, int tile);
+
+/* The tile shape the plan's anisotropic solves use now: ASDSM_TILE_PLANE when both fine-axis
+ * transforms run in one launch (chosen, or picked by size), else the chosen GEMM shape or
+ * ASDSM_TILE_AUTO (GEMM tiles picked per launch by size).  tile: host output.
+ * Errors: ASDSM_E_ARG (NULL argument). */
+int asdsm_get_tile(asdsm_plan_t plan, int *tile);
+
 /* Release the plan and its tables (not the workspace).  NULL is ignored. */
 void asdsm_destroy(asdsm_plan_t plan);
 

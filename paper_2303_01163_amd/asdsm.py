@@ -21,10 +21,12 @@ STATUS_NAMES = {0: "ok", 1: "stagnated", 2: "maxiter"}
 PRECISIONS = {"fp64": 0, "fp32": 1}  # asdsm_opts.precision: FP64 or FP32 error-phase submesh solves
 
 # symbols declared in include/asdsm.h
+# transform tile shapes of the anisotropic solves (ASDSM_TILE_* in include/asdsm.h)
+TILES = {"auto": 0, "32x32": 1, "64x32": 2, "32x64": 3, "64x64": 4, "plane": 5}
 EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_solve",
             "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error",
             "asdsm_batch_create", "asdsm_batch_solve", "asdsm_batch_destroy", "asdsm_autotune",
-            "asdsm_tile_name")
+            "asdsm_tile_name", "asdsm_set_tile", "asdsm_get_tile")
 # symbols declared in include/asdsm_learn.h
 EXPORTED_LEARN = ("asdsm_net_create", "asdsm_net_param_count", "asdsm_net_workspace_size",
                   "asdsm_net_set_workspace", "asdsm_net_params", "asdsm_net_forward",
@@ -84,6 +86,10 @@ def load_library():
     lib.asdsm_autotune.restype = c_int
     lib.asdsm_tile_name.argtypes = [c_int]
     lib.asdsm_tile_name.restype = ctypes.c_char_p
+    lib.asdsm_set_tile.argtypes = [c_void_p, c_int]
+    lib.asdsm_set_tile.restype = c_int
+    lib.asdsm_get_tile.argtypes = [c_void_p, POINTER(c_int)]
+    lib.asdsm_get_tile.restype = c_int
     lib.asdsm_batch_create.argtypes = [POINTER(c_void_p), POINTER(c_void_p), c_int]
     lib.asdsm_batch_create.restype = c_int
     lib.asdsm_batch_solve.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
@@ -238,6 +244,18 @@ class Plan:
             rc = _check(lib.asdsm_solve(self._h, _dptr(s, self.n_fine, "s"), _dptr(g, self.n_faces, "g"),
                                         _dptr(u, self.n_fine, "u"), byref(o), byref(st)))
         return u, _info(rc, st, hist, steps, profile)
+
+    def set_tile(self, tile):
+        """Force the transform tile shape (asdsm_set_tile): a TILES key or its integer code."""
+        code = TILES[tile] if isinstance(tile, str) else int(tile)
+        _check(load_library().asdsm_set_tile(self._h, code))
+
+    def tile_name(self):
+        """Name of the tile shape the anisotropic solves use now (asdsm_get_tile)."""
+        lib = load_library()
+        t = c_int()
+        _check(lib.asdsm_get_tile(self._h, byref(t)))
+        return lib.asdsm_tile_name(t.value).decode()
 
     def autotune(self, repeats=10):
         """Choose this plan's FP64 transform tile shape by timing (asdsm_autotune)."""

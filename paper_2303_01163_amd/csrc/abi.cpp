@@ -91,6 +91,23 @@ double gemm_bytes(const GemmJob &j) {
     return 8.0 * j.nbox * (a + b + c);
 }
 
+// two products of N_f^3 multiply-adds per slab
+double plane_flops(const PlaneJob &j) { return 4.0 * j.Nf * (double)j.Nf * j.Nf * j.nplanes * j.nbox; }
+// the slabs read and written once (C read as well when accumulating) and both matrices per box
+double plane_bytes(const PlaneJob &j) {
+    const double slab = (double)j.Nf * j.Nf;
+    return 8.0 * j.nbox * (slab * j.nplanes * (j.accum ? 3 : 2) + 2 * slab);
+}
+// Whether the anisotropic solves run both fine-axis transforms of a slab in one launch (d = 3):
+// chosen by the autotuner or asdsm_set_tile, else by size: up to N_f = 127 (one row tile per wave)
+// the plane kernel beats two batched GEMMs; at 255 the 64 x 64 GEMM tiles are faster.
+constexpr int kPlaneAutoMaxNf = 127;
+bool plane_transforms(const Plan &p) {
+    if (p.d != 3 || p.Nf > kPlaneMaxNf) return false;
+    if (p.tile_aniso == kTilePlane) return true;
+    return p.tile_aniso == kTileAuto && p.Nf <= kPlaneAutoMaxNf;
+}
+
 void fine_axes(int d, int k, int &a, int &b) {
     if (d == 2) {
         a = 1 - k;
@@ -124,8 +141,26 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
     j.nbox = nb;
     j.gate = p.gate;
     j.tile = p.tile_aniso;
+    // d = 3 with the plane kernel: both forward transforms in one launch (in -> Y), the line
+    // elimination on Y, both backward transforms in one launch (Y -> out)
+    const bool plane = plane_transforms(p);
+    if (plane) {
+        PlaneJob pj{};
+        pj.nbox = nb; pj.Nf = Nf; pj.nplanes = Nc; pj.accum = 0; pj.gate = p.gate;
+        for (int q = 0; q < nb; ++q) {
+            int a, b;
+            fine_axes(d, ks[q], a, b);
+            pj.X[q] = in[ks[q]];
+            pj.C[q] = p.ws.Y[1u << ks[q]];
+            pj.L[q] = p.dW[b];
+            pj.R[q] = p.dW[a];
+        }
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, plane_flops(pj), plane_bytes(pj));
+        if (!launch_plane2(pj, p.stream)) return fail(ASDSM_E_ARG, "plane transforms: N_f too large");
+        if (int rc = check_launch("transform")) return rc;
+    }
     // forward transform along canonical axis 0 (contiguous): in -> Y
-    {
+    if (!plane) {
         j.M = (d == 2) ? Nc : Nf * Nc;
         j.N = Nf; j.K = Nf; j.nbatch = 1; j.accum = 0;
         j.sAb = j.sBb = j.sCb = 0;
@@ -143,7 +178,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
         if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
-    if (d == 3) {
+    if (d == 3 && !plane) {
         // forward along canonical axis 1, batched over the coarse slabs: Y -> X
         j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nc; j.accum = 0;
         j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
@@ -160,7 +195,8 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
         if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
-    // line elimination along the coarse axis: d = 2 on Y (scratch X), d = 3 on X (scratch Y)
+    // line elimination along the coarse axis: on Y (scratch X) for d = 2 and the plane kernel,
+    // else on X (scratch Y)
     {
         LineJob L{};
         L.nbox = nb;
@@ -172,8 +208,9 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             int a, b;
             const int k = ks[q];
             fine_axes(d, k, a, b);
-            L.X[q] = (d == 2) ? p.ws.Y[1u << k] : p.ws.X[1u << k];
-            L.scratch[q] = (d == 2) ? p.ws.X[1u << k] : p.ws.Y[1u << k];
+            const bool onY = (d == 2) || plane;
+            L.X[q] = onY ? p.ws.Y[1u << k] : p.ws.X[1u << k];
+            L.scratch[q] = onY ? p.ws.X[1u << k] : p.ws.Y[1u << k];
             L.mu_a[q] = p.dmu[a];
             L.mu_b[q] = (d == 3) ? p.dmu[b] : nullptr;
             L.t[q] = p.geo.coarse[k];
@@ -182,6 +219,21 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
         PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 8.0 * lpts, 16.0 * lpts);
         launch_line(L, p.stream);
         if (int rc = check_launch("line")) return rc;
+    }
+    if (plane) {
+        PlaneJob pj{};
+        pj.nbox = nb; pj.Nf = Nf; pj.nplanes = Nc; pj.accum = accum; pj.gate = p.gate;
+        for (int q = 0; q < nb; ++q) {
+            int a, b;
+            fine_axes(d, ks[q], a, b);
+            pj.X[q] = p.ws.Y[1u << ks[q]];
+            pj.C[q] = out[ks[q]];
+            pj.L[q] = p.dV[b];
+            pj.R[q] = p.dV[a];
+        }
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, plane_flops(pj), plane_bytes(pj));
+        if (!launch_plane2(pj, p.stream)) return fail(ASDSM_E_ARG, "plane transforms: N_f too large");
+        return check_launch("transform");
     }
     if (d == 3) {
         // backward along canonical axis 1: X -> Y
@@ -855,6 +907,7 @@ int autotune_impl(Plan &p, int reps, int *best_tile, double *best_ms) {
     int best = saved;
     double best_t = 1e300;
     for (int tile : kGemmTiles) {
+        if (tile == kTilePlane && (p.d != 3 || p.Nf > kPlaneMaxNf)) continue;
         p.tile_aniso = tile;
         int rc = solve_aniso(p, kbits, in, out, 0);  // warm-up (code objects, caches)
         if (rc == ASDSM_OK) {
@@ -1424,6 +1477,31 @@ int asdsm_autotune(asdsm_plan_t plan, int repeats, int *tile, double *ms_per_sol
 }
 
 const char *asdsm_tile_name(int tile) { return gemm_tile_name(tile); }
+
+static_assert(ASDSM_TILE_AUTO == kTileAuto && ASDSM_TILE_32X32 == kTile32x32 && ASDSM_TILE_64X32 == kTile64x32 &&
+                  ASDSM_TILE_32X64 == kTile32x64 && ASDSM_TILE_64X64 == kTile64x64 && ASDSM_TILE_PLANE == kTilePlane,
+              "tile codes of the C ABI");
+
+int asdsm_get_tile(asdsm_plan_t plan, int *tile) {
+    if (!plan || !tile) return fail(ASDSM_E_ARG, "plan and tile must be non-NULL");
+    *tile = plane_transforms(plan->p) ? kTilePlane : plan->p.tile_aniso;
+    set_error("");
+    return ASDSM_OK;
+}
+
+int asdsm_set_tile(asdsm_plan_t plan, int tile) {
+    if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
+    Plan &p = plan->p;
+    if (tile < kTileAuto || tile > kTilePlane) return fail(ASDSM_E_ARG, "unknown tile shape");
+    if (tile == kTilePlane && (p.d != 3 || p.Nf > kPlaneMaxNf))
+        return fail(ASDSM_E_UNSUPPORTED, "plane transforms need d = 3 and N_f <= 255");
+    if (tile != p.tile_aniso) {
+        p.tile_aniso = tile;
+        destroy_graph(p);  // captured launches carry the old tile choice
+    }
+    set_error("");
+    return ASDSM_OK;
+}
 
 void asdsm_batch_destroy(asdsm_batch_t batch) {
     if (!batch) return;

@@ -141,6 +141,7 @@ const char *gemm_tile_name(int tile) {
         case kTile64x32: return "64x32 k32";
         case kTile32x64: return "32x64 k32";
         case kTile64x64: return "64x64 k16";
+        case kTilePlane: return "plane panels 16";
         default: return "auto";
     }
 }
@@ -160,6 +161,168 @@ bool launch_gemm(const GemmJob &job, hipStream_t st) {
         case kTile64x64: launch_gemm_tile<64, 64, 16>(job, st); break;
         default: launch_gemm_tile<32, 32, 32>(job, st); break;
     }
+    return true;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Both fine-axis transforms of a d = 3 anisotropic box in one launch.  Each slab of constant coarse
+// index is an N_f x N_f matrix X_c (row = second fine axis, column = first fine axis, contiguous
+// rows) and becomes C_c = L X_c R^T (forward: L = W_b, R = W_a; backward: L = V_b, R = V_a).  One
+// block (8 waves) owns a 16-column panel [m0, m0 + 16) of one slab, and the two products split
+// without recomputation:
+//     T = X_c R[m0:m0+16, :]^T  (N_f x 16, kept in LDS),   C_c[:, m0:m0+16] = L T.
+// Wave w owns row tiles w, w + 8, ... (16 rows) of both products.  The A operands (rows of X_c and
+// of L) are read from global memory straight into the fragment layout: a load covers 16 rows x 4
+// columns, and the four k-steps that share those cache lines hit the L1.  R's panel and T live in
+// LDS with a pitch of 16 doubles (a fragment read is 4 rows of 128 contiguous bytes: no conflicts).
+// Consecutive block ids go to consecutive XCDs and each XCD takes a contiguous range of (box, slab,
+// panel) items, so the panels of one slab share that XCD's L2 copy of X_c.
+// Operand layout of v_mfma_f64_16x16x4f64 (lane l): A row l%16, k l/16; B k l/16, col l%16;
+// D[v] row l/16 + 4v, col l%16.
+// ---------------------------------------------------------------------------------------------
+// A batch of KS k-steps of a row tile's A fragments (row pointer ar), issued together so that each
+// MFMA waits only for its own operand.  Column indices past the row end are clamped to its last
+// element: the B operand is zero there (R's panel and T are zero-padded), so the clamped values,
+// real entries of the same row, add nothing, and no load leaves the slab.
+template <int KS>
+__device__ __forceinline__ void plane_load(double (&a)[KS], const double *__restrict__ ar, int Nf, int lg) {
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+        const int k = 4 * q + lg;
+        a[q] = ar[k < Nf ? k : Nf - 1];
+    }
+}
+
+template <int KS>
+__device__ __forceinline__ void plane_mfma(double4_t &acc, const double (&a)[KS], const double (*sB)[16], int s0, int lg,
+                                           int ln) {
+#pragma unroll
+    for (int q = 0; q < KS; ++q)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], sB[4 * (s0 + q) + lg][ln], acc, 0, 0, 0);
+}
+
+// Row tile x 16 columns of A B (B in LDS), A's fragments in batches of H k-steps (H = KS up to 32
+// k-steps, else 16); a holds the first batch on entry.  Two register batches alternate, so the next
+// batch's loads are in flight while the current one is multiplied.
+template <int KS>
+constexpr int plane_batch() { return KS <= 32 ? KS : 16; }
+
+template <int KS>
+__device__ __forceinline__ double4_t plane_tile(double (&a)[plane_batch<KS>()], const double *__restrict__ ar, int Nf,
+                                                const double (*sB)[16], int lg, int ln) {
+    constexpr int H = plane_batch<KS>();
+    constexpr int NB = KS / H;
+    static_assert(NB * H == KS && NB % 2 == 0 || NB == 1, "whole batch pairs");
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (NB == 1) {
+        plane_mfma<H>(acc, a, sB, 0, lg, ln);
+    } else {
+        double b[H];
+#pragma unroll
+        for (int t = 0; t < NB; t += 2) {
+            plane_load<H>(b, ar + 4 * H * (t + 1), Nf - 4 * H * (t + 1), lg);
+            plane_mfma<H>(acc, a, sB, H * t, lg, ln);
+            if (t + 2 < NB) plane_load<H>(a, ar + 4 * H * (t + 2), Nf - 4 * H * (t + 2), lg);
+            plane_mfma<H>(acc, b, sB, H * (t + 1), lg, ln);
+        }
+    }
+    return acc;
+}
+
+template <int NT>
+__global__ __launch_bounds__(512) void k_plane2(PlaneJob job) {
+    if (job.gate && *job.gate) return;
+    constexpr int KP = 16 * NT;                  // contraction length padded to whole tiles
+    constexpr int KS = KP / 4;                   // MFMA k-steps
+    constexpr int RT = (NT + 7) / 8;             // row tiles per wave
+    constexpr int H = plane_batch<KS>();         // k-steps per batch of A fragments
+    __shared__ double sR[KP][16];                // sR[k][n] = R[m0 + n][k]
+    __shared__ double sT[KP][16];                // T
+    const int Nf = job.Nf;
+    const int np = (Nf + 15) >> 4;
+    const int total = job.nbox * job.nplanes * np;
+    const int per = (total + 7) / 8;
+    const int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if ((int)(blockIdx.x >> 3) >= per || item >= total) return;  // padding (block-uniform)
+    const int pan = item % np;
+    const int zc = item / np;
+    const int box = zc / job.nplanes, c = zc - box * job.nplanes;
+    const long long slab = (long long)c * Nf * Nf;
+    const double *__restrict__ X = job.X[box] + slab;
+    double *__restrict__ C = job.C[box] + slab;
+    const double *__restrict__ L = job.L[box];
+    const double *__restrict__ R = job.R[box];
+    const int m0 = pan * 16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int ln = lane & 15, lg = lane >> 4;
+    // R's panel, n fastest across threads (contiguous LDS writes); indices clamped, values selected
+#pragma unroll
+    for (int e0 = 0; e0 < 16 * KP; e0 += 512) {
+        const int e = e0 + tid, n = e & 15, k = e >> 4;
+        const bool ok = m0 + n < Nf && k < Nf;
+        sR[k][n] = R[(long long)(m0 + n < Nf ? m0 + n : Nf - 1) * Nf + (k < Nf ? k : Nf - 1)] * (ok ? 1.0 : 0.0);
+    }
+    // A rows past N_f (and the rows of idle waves) read row 0; their results are dropped
+    double a[H];
+    {
+        const int row = w * 16 + ln;
+        plane_load<H>(a, X + (long long)(row < Nf ? row : 0) * Nf, Nf, lg);
+    }
+    __syncthreads();
+    // T = X_c R_panel^T
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int rt = w + 8 * i;
+        if (rt < NT) {
+            const int row = rt * 16 + ln;
+            const double *__restrict__ xr = X + (long long)(row < Nf ? row : 0) * Nf;
+            if (i > 0) plane_load<H>(a, xr, Nf, lg);
+            const double4_t acc = plane_tile<KS>(a, xr, Nf, sR, lg, ln);
+            // rows of T past N_f are zero: they meet L's clamped columns in the second product
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int tr = rt * 16 + lg + 4 * v;
+                sT[tr][ln] = tr < Nf ? acc[v] : 0.0;
+            }
+        }
+    }
+    // L's fragments of the first row tile do not depend on T: issue them before the barrier
+    {
+        const int row = w * 16 + ln;
+        plane_load<H>(a, L + (long long)(row < Nf ? row : 0) * Nf, Nf, lg);
+    }
+    __syncthreads();
+    // C_c[:, m0:m0+16] = L T
+    const int col = m0 + ln;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int rt = w + 8 * i;
+        if (rt < NT) {
+            const int row = rt * 16 + ln;
+            const double *__restrict__ lr = L + (long long)(row < Nf ? row : 0) * Nf;
+            if (i > 0) plane_load<H>(a, lr, Nf, lg);
+            const double4_t acc = plane_tile<KS>(a, lr, Nf, sT, lg, ln);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int orow = rt * 16 + lg + 4 * v;
+                if (orow < Nf && col < Nf) {
+                    double *cp = C + (long long)orow * Nf + col;
+                    *cp = job.accum ? *cp + acc[v] : acc[v];
+                }
+            }
+        }
+    }
+}
+
+bool launch_plane2(const PlaneJob &job, hipStream_t st) {
+    const int nt = (job.Nf + 15) / 16;
+    const long long total = (long long)job.nbox * job.nplanes * nt;
+    const dim3 grid((unsigned)(8 * ((total + 7) / 8))), blk(512);
+    if (nt <= 2) ASDSM_LAUNCH((k_plane2<2>), grid, blk, 0, st, job);
+    else if (nt <= 4) ASDSM_LAUNCH((k_plane2<4>), grid, blk, 0, st, job);
+    else if (nt <= 8) ASDSM_LAUNCH((k_plane2<8>), grid, blk, 0, st, job);
+    else if (nt <= 16) ASDSM_LAUNCH((k_plane2<16>), grid, blk, 0, st, job);
+    else return false;
     return true;
 }
 

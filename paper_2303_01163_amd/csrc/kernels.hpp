@@ -47,8 +47,9 @@ struct GemmJob {
 };
 
 // FP64 transform tile shapes (TM x TN, K chunk), chosen per plan by asdsm_autotune.
-enum GemmTile { kTileAuto = 0, kTile32x32 = 1, kTile64x32 = 2, kTile32x64 = 3, kTile64x64 = 4 };
-constexpr int kGemmTiles[] = {kTile32x32, kTile64x32, kTile32x64, kTile64x64};
+// kTilePlane: both fine-axis transforms of a d = 3 anisotropic box in one launch (k_plane2).
+enum GemmTile { kTileAuto = 0, kTile32x32 = 1, kTile64x32 = 2, kTile32x64 = 3, kTile64x64 = 4, kTilePlane = 5 };
+constexpr int kGemmTiles[] = {kTile32x32, kTile64x32, kTile32x64, kTile64x64, kTilePlane};
 const char *gemm_tile_name(int tile);
 
 // Thomas elimination along the coarse (slowest) axis of anisotropic boxes after their fine axes
@@ -78,6 +79,20 @@ void launch_dots(const Plan &p, hipStream_t st);
 int stencil_blocks(const Geo &g);
 
 bool launch_gemm(const GemmJob &job, hipStream_t st);  // false: unsupported operand layout
+
+// C_c = L X_c R^T for every N_f x N_f slab c (row-major, contiguous slabs) of up to 3 boxes: the two
+// fine-axis transforms of a d = 3 anisotropic box in one launch.  L and R are N_f x N_f, row-major.
+struct PlaneJob {
+    const double *X[kMaxD];
+    double *C[kMaxD];
+    const double *L[kMaxD];
+    const double *R[kMaxD];
+    int nbox, Nf, nplanes;
+    int accum;                 // 1: C += result
+    const int *gate;
+};
+constexpr int kPlaneMaxNf = 256;  // largest N_f of k_plane2 (16 row tiles of 16, two per wave)
+bool launch_plane2(const PlaneJob &job, hipStream_t st);  // false: N_f too large
 // FP32 MFMA variant: A read as double (a_f64) or float, B float, C written as double (c_f64) or
 // float; the GemmJob pointers are reinterpreted accordingly.
 bool launch_gemm32(const GemmJob &job, bool a_f64, bool c_f64, hipStream_t st);

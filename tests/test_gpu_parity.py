@@ -442,12 +442,84 @@ def test_autotuned_plan_keeps_parity(torch_dev):
     pl = _plan(P, 6, 3, seed=21)
     tuned = pl.autotune(repeats=3)
     _say("   autotune:", tuned)
-    assert tuned["tile"] in ("32x32 k32", "64x32 k32", "32x64 k32", "64x64 k16")
+    assert tuned["tile"] in ("32x32 k32", "64x32 k32", "32x64 k32", "64x64 k16", "plane panels 16")
     assert tuned["ms_per_aniso_solve"] > 0
     s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
     for K in (0, 3):
         u, info = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0)
         assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
+
+
+ANISO_TILES = ("32x32", "64x32", "32x64", "64x64", "plane")
+
+
+@pytest.mark.parametrize("L,Lc,seed", [(5, 2, 3), (6, 3, 4)])
+def test_every_transform_tile_matches_the_oracle(torch_dev, L, Lc, seed):
+    """asdsm_set_tile: the anisotropic solves with every transform tile shape (four batched-GEMM
+    tilings, one launch per fine axis, and the plane kernel, both fine axes of a coarse slab in one
+    launch) against the oracle's banded LU, and the iterates of a short solve."""
+    P = make_problem("sinbump3d", L, seed=seed)
+    o = Oracle(3, P.alpha, P.beta, L, Lc, seed=seed + 1)
+    ref = o.solve(P.s, P.g, max_iter=2, rtol=0, stag_window=0, keep_iterates=True)
+    pl = _plan(P, L, Lc, seed=seed + 1)
+    rng = np.random.default_rng(200 + seed)
+    rhs = [rng.standard_normal(o.grid.mesh_dims((k,))) for k in range(3)]
+    x_or = [o.solve_mesh((k,), rhs[k]) for k in range(3)]
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    for tile in ANISO_TILES:
+        _say("tile", tile, L, Lc, seed)
+        pl.set_tile(tile)
+        for k in range(3):
+            x = pl.mesh_solve(1 << k, _t(torch_dev, _canon(3, (k,), rhs[k]))).cpu().numpy()
+            assert _rel(_uncanon(o.grid, (k,), x), x_or[k]) <= TOL_OP, (tile, k)
+        u, _ = pl.solve(s, g, max_iter=2, rtol=0, stag_window=0)
+        assert _rel(u.cpu().numpy(), ref.iterates[2].reshape(-1, order="F")) <= TOL_ITER, tile
+
+
+def test_every_transform_tile_at_full_size(torch_dev):
+    """127^3 (the benchmark's plan, one refinement sweep on its ill-conditioned axis): every tile
+    shape's anisotropic solves satisfy their equations, and the complete solves agree."""
+    P = make_problem("sinbump3d", 7, seed=0)
+    o = Oracle(3, P.alpha, P.beta, 7)
+    pl = _plan(P, 7, 0, seed=0)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    rng = np.random.default_rng(9)
+    rhs = [rng.standard_normal(o.grid.mesh_dims((k,))) for k in range(3)]
+    sols = {}
+    for tile in ANISO_TILES:
+        _say("tile 127^3", tile)
+        pl.set_tile(tile)
+        for k in range(3):
+            x = _uncanon(o.grid, (k,), pl.mesh_solve(1 << k, _t(torch_dev, _canon(3, (k,), rhs[k]))).cpu().numpy())
+            res = apply_operator(x, mesh_coeffs(o.grid, P.alpha, P.beta, (k,))) - rhs[k]
+            assert np.linalg.norm(res) <= 1e-9 * np.linalg.norm(rhs[k]), (tile, k)
+        u, info = pl.solve(s, g, max_iter=50, rtol=1e-10, stag_window=3)
+        sols[tile] = (u.cpu().numpy(), info["iterations"])
+    u0, it0 = sols[ANISO_TILES[0]]
+    for tile, (u1, it1) in sols.items():
+        assert it1 == it0, tile
+        assert _rel(u1, u0) <= TOL_ITER, tile
+
+
+def test_set_tile_errors(torch_dev):
+    from paper_2303_01163_amd.asdsm import AsdsmError
+    P = make_problem("sinprod2d", 5, seed=0)
+    pl = _plan(P, 5, 2)
+    with pytest.raises(AsdsmError) as ei:
+        pl.set_tile("plane")
+    assert ei.value.code == -6
+    with pytest.raises(AsdsmError) as ei:
+        pl.set_tile(9)
+    assert ei.value.code == -1
+    pl.set_tile("64x64")
+    assert pl.tile_name() == "64x64 k16"
+    pl.set_tile("auto")
+    assert pl.tile_name() == "auto"
+    P3 = make_problem("sinbump3d", 5, seed=0)
+    pl3 = _plan(P3, 5, 2)
+    assert pl3.tile_name() == "plane panels 16"    # picked by size at N_f <= 127
+    pl3.set_tile("32x32")
+    assert pl3.tile_name() == "32x32 k32"
 
 
 SPARSE_CASES = [  # d = 3: (family, level, coarse_level, seed)
