@@ -130,6 +130,8 @@ def parse():
     ap.add_argument("--learn-factor", type=float, default=1.1,
                     help="acceptance factor of the learned solve (4 is also reported)")
     ap.add_argument("--learn-iters", type=int, default=200, help="step limit of the learned comparison")
+    ap.add_argument("--d4-level", type=int, default=6,
+                    help="fine level of the d = 4 side measurement (0 skips it)")
     return ap.parse_args()
 
 
@@ -238,9 +240,44 @@ def main():
         out["batched"] = batched(asdsm, make_problem, args, dev)
     if args.learn_pairs > 0:
         out["learned"] = learned(asdsm, make_problem, L, args, dev)
+    if args.d4_level > 0:
+        out["d4"] = four_d(asdsm, make_problem, args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, L, args, iters)
     print(json.dumps(out))
+
+
+def four_d(asdsm, make_problem, args, dev, seed=0, steps=3):
+    """d = 4 (the 4D configuration): 63^4 fine unknowns, N_c = 7, the sinusoid-product family
+    (alpha_i log-uniform in [0.1, 1], beta_i uniform in [-2, 2]), FP64, the same stopping rule.
+    Plan construction (host LU of the intersection meshes' per-mode blocks) is outside the timing."""
+    import numpy as np
+    import torch
+    L = args.d4_level
+    Lc = max(1, L // 2)
+    P = make_problem("sinprod", L, seed=seed, d=4)
+    t0 = time.perf_counter()
+    plan = asdsm.Plan(4, P.alpha, P.beta, L, Lc, seed=seed, device=0)
+    plan_s = time.perf_counter() - t0
+    s = torch.from_numpy(P.s_flat()).to(dev)
+    g = torch.from_numpy(P.g_flat()).to(dev)
+    u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
+    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
+    plan.solve(s, g, u=u, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = plan.solve(s, g, u=u, **kw)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    _, prof = plan.solve(s, g, u=u, profile=True, **kw)
+    ue = torch.from_numpy(np.ascontiguousarray(P.u_exact.reshape(-1, order="F"))).to(dev)
+    return {"workload": f"asdsm-4d-{plan.n_f}^4-sinprod-seed{seed}", "coarse_level": Lc,
+            "fine_unknowns": plan.n_fine, "ms_per_solve": ms,
+            "fine_unknowns_per_s": plan.n_fine / (ms * 1e-3), "iterations": info["iterations"],
+            "status": info["status"], "rel_residual": info["rnorm"] / info["bnorm"],
+            "rel_error_vs_manufactured": float(torch.linalg.norm(u - ue) / torch.linalg.norm(ue)),
+            "plan_seconds": plan_s, "phase_ms": prof["phase_ms"], "phase_launches": prof["phase_launches"]}
 
 
 def fine_loop(plan, s, g, kw, u_sparse, steps):

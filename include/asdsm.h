@@ -121,7 +121,9 @@ typedef struct {
 } asdsm_stats;
 
 /* Create a plan (Section 2.1 meshes, Section 2.3 operators, Algorithms 1-4 schedule).
- *   d            : 2 or 3 (dimensions of eq. (1)).
+ *   d            : 2, 3 or 4 (dimensions of eq. (1); d = 4 per Section 3.5's construction of the
+ *                  submeshes for any d).  FP32 error guesses and skeleton-sparse refinement are
+ *                  built for d <= 3 and d = 3 respectively.
  *   alpha, beta  : host arrays of d finite doubles, alpha[j] > 0 (copied).
  *   level        : fine level L, N_f = 2^L - 1, 2 <= L <= 10.
  *   coarse_level : L_c with 1 <= L_c < L (eq. (3)); 0 selects floor(L/2).
@@ -191,7 +193,7 @@ const char *asdsm_tile_name(int tile);
 
 /* Force the transform tile shape of this plan's anisotropic solves (the autotuner's choice is
  * replaced).  Same iterates up to rounding for every shape.
- * Errors: ASDSM_E_ARG (unknown tile), ASDSM_E_UNSUPPORTED (ASDSM_TILE_PLANE with d = 2 or
+ * Errors: ASDSM_E_ARG (unknown tile), ASDSM_E_UNSUPPORTED (ASDSM_TILE_PLANE with d != 3 or
  * N_f > 255). */
 int asdsm_set_tile(asdsm_plan_t plan, int tile);
 

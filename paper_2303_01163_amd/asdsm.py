@@ -187,7 +187,7 @@ def _info(rc, st, hist, steps, profile):
 
 
 class Plan:
-    """An ASDSM plan on one GPU: d in {2,3}, per-axis alpha/beta, fine level L, coarse level L_c."""
+    """An ASDSM plan on one GPU: d in {2,3,4}, per-axis alpha/beta, fine level L, coarse level L_c."""
 
     def __init__(self, d, alpha, beta, level, coarse_level=0, seed=0, device=None, stream=None):
         import torch

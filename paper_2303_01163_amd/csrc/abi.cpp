@@ -127,6 +127,134 @@ double *sol_buf(const Plan &p, unsigned m) {
     return (__builtin_popcount(m) == 1) ? p.ws.X[m] : p.ws.Y[m];
 }
 
+// Mode transform along canonical position q (a fine axis of extent N_f) of nb boxes of the shape m:
+// out_b = T_b applied along q to in_b (out += when accum), T_b an N_f x N_f row-major matrix
+// (T[m][i]).  Position 0 is contiguous (one GEMM over all rows); a later position is a batch over
+// the outer positions of (N_f x N_f) times (N_f x inner) products.
+int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *const *in,
+                       const double *const *T, double *const *out, int accum) {
+    GemmJob j{};
+    j.nbox = nb;
+    j.gate = p.gate;
+    j.tile = (p.tile_aniso == kTilePlane) ? kTileAuto : p.tile_aniso;
+    j.accum = accum;
+    const long long Nf = p.Nf, inner = m.stride[q];
+    if (q == 0) {
+        j.M = (int)(m.size / Nf); j.N = (int)Nf; j.K = (int)Nf; j.nbatch = 1;
+        j.sAb = j.sBb = j.sCb = 0;
+        j.sAi = Nf; j.sAk = 1;
+        j.sBk = 1;  j.sBn = Nf;
+        j.sCi = Nf; j.sCn = 1;
+        for (int b = 0; b < nb; ++b) {
+            j.A[b] = in[b];
+            j.B[b] = T[b];
+            j.C[b] = out[b];
+        }
+    } else {
+        j.M = (int)Nf; j.N = (int)inner; j.K = (int)Nf; j.nbatch = (int)(m.size / (inner * Nf));
+        j.sAb = 0;          j.sAi = Nf;    j.sAk = 1;
+        j.sBb = inner * Nf; j.sBk = inner; j.sBn = 1;
+        j.sCb = inner * Nf; j.sCi = inner; j.sCn = 1;
+        for (int b = 0; b < nb; ++b) {
+            j.A[b] = T[b];
+            j.B[b] = in[b];
+            j.C[b] = out[b];
+        }
+    }
+    PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
+    if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
+    return check_launch("transform");
+}
+
+// Direct solve of nb meshes of one shape, any d (the d = 4 path): every fine axis diagonalised by a
+// mode transform, then per mode a Thomas elimination along the coarse axis (one coarse axis) or the
+// precomputed dense inverse of the coarse block (several), then the backward transforms.
+// in[b] -> out[b] (out += when accum); X and Y of each mesh are intermediates.  in may be X.  The
+// last backward transform reads Y when the mesh has one coarse axis and X otherwise, so out may be X
+// or W in the first case and Y or W in the second (the buffers sol_buf names).
+int solve_mesh_nd(Plan &p, int nb, const unsigned *masks, const double *const *in, double *const *out,
+                  int accum) {
+    const MeshDesc &m = p.mesh[masks[0]];
+    const int nf = m.nfine;
+    double *X[kMaxD], *Y[kMaxD];
+    const double *T[kMaxD];
+    for (int b = 0; b < nb; ++b) {
+        X[b] = p.ws.X[masks[b]];
+        Y[b] = p.ws.Y[masks[b]];
+    }
+    if (nf == 0) {  // the coarse mesh: one dense block
+        for (int b = 0; b < nb; ++b) {
+            const double B = m.block;
+            PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 2.0 * B * B, 8.0 * (B * B + (accum ? 3 : 2) * B));
+            launch_dense_modes(1, m.block, p.ddense[masks[b]], in[b], out[b], accum, p.stream);
+            if (int rc = check_launch("dense")) return rc;
+        }
+        return ASDSM_OK;
+    }
+    // forward transforms: in -> Y -> X -> Y ... (position q writes Y for even q, X for odd q)
+    const double *cur[kMaxD];
+    for (int b = 0; b < nb; ++b) cur[b] = in[b];
+    for (int q = 0; q < nf; ++q) {
+        double *dst[kMaxD];
+        for (int b = 0; b < nb; ++b) {
+            dst[b] = (q % 2 == 0) ? Y[b] : X[b];
+            T[b] = p.dW[p.mesh[masks[b]].ax[q]];
+        }
+        if (int rc = transform_position(p, m, q, nb, cur, T, dst, 0)) return rc;
+        for (int b = 0; b < nb; ++b) cur[b] = dst[b];
+    }
+    // the data sit in D = (nf odd ? Y : X); the other buffer O is free
+    double *D[kMaxD], *O[kMaxD];
+    for (int b = 0; b < nb; ++b) {
+        D[b] = (nf % 2 == 1) ? Y[b] : X[b];
+        O[b] = (nf % 2 == 1) ? X[b] : Y[b];
+    }
+    if (m.nd - nf == 1) {
+        // one coarse axis: Thomas per mode, in place on D (scratch O)
+        LineJob L{};
+        L.nbox = nb;
+        L.gate = p.gate;
+        L.nmodes = m.nmodes;
+        L.ext_a = p.Nf;
+        L.ncoarse = m.block;
+        for (int b = 0; b < nb; ++b) {
+            const MeshDesc &mb = p.mesh[masks[b]];
+            L.X[b] = D[b];
+            L.scratch[b] = O[b];
+            L.mu_a[b] = p.dmu[mb.ax[0]];
+            L.mu_b[b] = nf >= 2 ? p.dmu[mb.ax[1]] : nullptr;
+            L.mu_c[b] = nf >= 3 ? p.dmu[mb.ax[2]] : nullptr;
+            L.t[b] = p.geo.coarse[mb.ax[nf]];
+        }
+        const double lpts = (double)L.nmodes * L.ncoarse * nb;
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 8.0 * lpts, 16.0 * lpts);
+        launch_line(L, p.stream);
+        if (int rc = check_launch("line")) return rc;
+    } else {
+        // several coarse axes: the dense inverse of each mode's coarse block, D -> O
+        for (int b = 0; b < nb; ++b) {
+            const double B = m.block, nmo = (double)m.nmodes;
+            PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 2.0 * nmo * B * B, 8.0 * nmo * (B * B + 2 * B));
+            launch_dense_modes(m.nmodes, m.block, p.ddense[masks[b]], D[b], O[b], 0, p.stream);
+            if (int rc = check_launch("dense")) return rc;
+            std::swap(D[b], O[b]);
+        }
+    }
+    // backward transforms, last position first: D -> O -> D ... -> out
+    for (int q = nf - 1; q >= 0; --q) {
+        const double *src[kMaxD];
+        double *dst[kMaxD];
+        for (int b = 0; b < nb; ++b) {
+            src[b] = D[b];
+            dst[b] = (q == 0) ? out[b] : O[b];
+            T[b] = p.dV[p.mesh[masks[b]].ax[q]];
+        }
+        if (int rc = transform_position(p, m, q, nb, src, T, dst, q == 0 ? accum : 0)) return rc;
+        for (int b = 0; b < nb; ++b) std::swap(D[b], O[b]);
+    }
+    return ASDSM_OK;
+}
+
 // Direct solves of the anisotropic meshes k in kbits (fast diagonalisation of the fine axes, Thomas
 // along the coarse axis): in[k] -> out[k] (out += solution when accum).  X_k and Y_k are used as
 // intermediates, so in[k] may be X_k and out[k] may be X_k, but neither may be Y_k.
@@ -136,6 +264,17 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
     for (int k = 0; k < d; ++k)
         if ((kbits >> k) & 1u) ks[nb++] = k;
     if (nb == 0) return ASDSM_OK;
+    if (d == 4) {
+        unsigned masks[kMaxD];
+        const double *bin[kMaxD];
+        double *bout[kMaxD];
+        for (int q = 0; q < nb; ++q) {
+            masks[q] = 1u << ks[q];
+            bin[q] = in[ks[q]];
+            bout[q] = out[ks[q]];
+        }
+        return solve_mesh_nd(p, nb, masks, bin, bout, accum);
+    }
     const long long Nf2 = (long long)Nf * Nf;
     GemmJob j{};
     j.nbox = nb;
@@ -279,6 +418,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
 // Y_S output without accumulation).
 int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, int accum) {
     const MeshDesc &m = p.mesh[mask];
+    if (m.nfine >= 2) return solve_mesh_nd(p, 1, &mask, &in, &out, accum);  // d = 4, two fine axes
     if (m.nfine == 0) {
         const double B = m.block;
         PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 2.0 * B * B, 8.0 * (B * B + (accum ? 3 : 2) * B));
@@ -526,6 +666,9 @@ double hole_points(const Plan &p) { return std::pow((double)(p.Nc + 1) * (p.geo.
 // and a Thomas line (8 flops per point).
 double filler_flops(const Plan &p) { return hole_points(p) * (4.0 * (p.d - 1) * (p.geo.n - 1) + 8.0); }
 
+// Launches of the cross-point and merge kernels (Algorithm 2) for this d.
+int skeleton_launches(const Plan &p) { return p.d == 2 ? 2 : (p.d == 3 ? 3 : 4); }
+
 int read_scalars(Plan &p) {
     ASDSM_HIP_CHECK(hipMemcpyAsync(p.hscal, p.ws.scal, kScalCount * sizeof(double), hipMemcpyDeviceToHost, p.stream));
     ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
@@ -571,7 +714,8 @@ int calibrate_sweeps(Plan &p) {
             const int slot = aniso ? __builtin_ctz(m) : 0;
             in[slot] = rhs_buf(p, m);
             out[slot] = sol_buf(p, m);
-            tmp[slot] = (q < 2) ? temps[q] : p.ws.u2;
+            // one fine vector holds two meshes (N_c N_f^(d-1) points each, 2 N_c < N_f)
+            tmp[slot] = (q < 2) ? temps[q] : p.ws.u2 + (q - 2) * n;
             resid[slot] = p.ws.X[m];
             launch_fill_random(in[slot], n, 0x5EEDull * (m + 1), p.stream);
         }
@@ -673,7 +817,7 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     const double *res[kMaxMeshes];
     result_pointers(p, res);
     {
-        PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 3 : 2, 0.0,
+        PhaseTimer t(p, ASDSM_PHASE_SKELETON, skeleton_launches(p), 0.0,
                      8.0 * (submesh_points(p) + aniso_points(p)));
         launch_crosspoints(p, 0, res, p.stream);
         launch_merge(p, 0, res, p.stream);
@@ -712,7 +856,7 @@ int error_guess(Plan &p) {
     }
     const double *res[kMaxMeshes];
     result_pointers(p, res);
-    PhaseTimer t(p, ASDSM_PHASE_SKELETON, p.d == 3 ? 4 : 3, 0.0, 24.0 * aniso_points(p));
+    PhaseTimer t(p, ASDSM_PHASE_SKELETON, skeleton_launches(p) + 1, 0.0, 24.0 * aniso_points(p));
     launch_box_norms(p, res, p.stream);
     launch_crosspoints(p, 1, res, p.stream);
     launch_merge(p, 1, res, p.stream);

@@ -17,7 +17,7 @@
 
 namespace asdsm {
 
-constexpr int kMaxD = 3;
+constexpr int kMaxD = 4;
 constexpr int kMaxMeshes = 1 << kMaxD;
 constexpr int kDenseMaxBlock = 4096;  // coarse points per mode of an intersection-mesh dense solve
 
@@ -26,9 +26,9 @@ struct MeshDesc {
     unsigned mask = 0;
     int nd = 0;
     int nfine = 0;                 // canonical positions [0, nfine) are fine axes
-    int ax[kMaxD] = {0, 0, 0};     // original axis at each canonical position
-    int ext[kMaxD] = {1, 1, 1};    // extent at each canonical position
-    long long stride[kMaxD] = {0, 0, 0};
+    int ax[kMaxD] = {0, 0, 0, 0};     // original axis at each canonical position
+    int ext[kMaxD] = {1, 1, 1, 1};    // extent at each canonical position
+    long long stride[kMaxD] = {0, 0, 0, 0};
     long long size = 0;            // number of points
     long long nmodes = 1;          // product of the fine extents
     int block = 1;                 // product of the coarse extents
@@ -110,9 +110,9 @@ enum ScalarSlot {
     kScalRQ = 2,       // <r, q>
     kScalQQ = 3,       // <q, q>
     kScalStep = 4,     // s_hat
-    kScalEnorm2 = 5,   // ||e_k||^2, k = 0..d-1  (slots 5,6,7)
-    kScalInvNorm = 8,  // 1/||e_k|| or 1 (slots 8,9,10)
-    kScalFlags = 11,   // non-finite flag accumulator
+    kScalEnorm2 = 5,   // ||e_k||^2, k = 0..d-1  (slots 5..8)
+    kScalInvNorm = 9,  // 1/||e_k|| or 1 (slots 9..12)
+    kScalFlags = 13,   // non-finite flag accumulator
     kScalCount = 16
 };
 

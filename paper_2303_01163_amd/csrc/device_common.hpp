@@ -15,12 +15,18 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ bool on_coarse(int i, int n) { return ((i + 1) & (n - 1)) == 0; }
 __device__ __forceinline__ int coarse_of(int i, int n) { return (i + 1) / n - 1; }
 
-// Canonical offset of the fine point i[] inside mesh M_S (the point must lie on M_S).
+// Element j (a run-time axis) of a per-axis array of kMaxD ints, through selects: a dynamic index
+// into a local array would place the array in scratch memory.
+__device__ __forceinline__ int axis_sel(const int *v, int j) {
+    return j == 0 ? v[0] : (j == 1 ? v[1] : (j == 2 ? v[2] : v[3]));
+}
+
+// Canonical offset of the fine point i[] (kMaxD entries) inside mesh M_S (the point must lie on M_S).
 __device__ __forceinline__ long long canon_offset(const MeshDesc &m, const int *i, int n) {
     long long off = 0;
     for (int q = 0; q < m.nd; ++q) {
-        const int j = m.ax[q];
-        const int pos = (q < m.nfine) ? i[j] : coarse_of(i[j], n);
+        const int ij = axis_sel(i, m.ax[q]);
+        const int pos = (q < m.nfine) ? ij : coarse_of(ij, n);
         off += (long long)pos * m.stride[q];
     }
     return off;

@@ -471,8 +471,12 @@ __global__ __launch_bounds__(256) void k_line(LineJob job) {
     const Tri t64 = job.t[box];
     const T ta = (T)t64.a, tc = (T)t64.c;
     const int ma = (int)(m % job.ext_a);
-    const long long mb = m / job.ext_a;
+    long long mb = m / job.ext_a;
     double sigma = job.mu_a[box][ma];
+    if (job.mu_c[box]) {  // three fine axes of extent ext_a (d = 4)
+        sigma += job.mu_c[box][mb / job.ext_a];
+        mb %= job.ext_a;
+    }
     if (job.mu_b[box]) sigma += job.mu_b[box][mb];
     const long long st = job.nmodes;
     const T diag = (T)(t64.b + sigma);

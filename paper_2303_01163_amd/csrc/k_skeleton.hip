@@ -327,6 +327,10 @@ static SkelArgs skel_args(const Plan &p, int mode, const double *const *res) {
 }
 
 void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipStream_t st) {
+    if (p.d == 4) {
+        launch_crosspoints4(p, mode, res, st);
+        return;
+    }
     SkelArgs a = skel_args(p, mode, res);
     const long long nA = (p.d == 2) ? (long long)p.Nc * p.Nc : (long long)p.Nc * p.Nc * p.Nf;
     const long long total = (p.d == 2) ? nA : 2 * nA;
@@ -341,6 +345,10 @@ void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipSt
 }
 
 void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t st) {
+    if (p.d == 4) {
+        launch_merge4(p, mode, res, st);
+        return;
+    }
     SkelArgs a = skel_args(p, mode, res);
     if (p.d == 3 && (p.Nc == 7 || p.Nc == 15 || p.Nc == 31)) {
         const unsigned tiles = (unsigned)(((p.Nf + 63) / 64) * ((p.Nf + 7) / 8));
@@ -390,7 +398,7 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
     // NH > 0: hole edge length known at compile time (constant-divisor index arithmetic)
     const int nh = (NH > 0) ? NH : g.n - 1;
     const int n = nh + 1, Nf = g.Nf, Nc = g.Nc;
-    int npts = 1, st[kMaxD] = {1, 1, 1};
+    int npts = 1, st[kMaxD] = {1, 1, 1, 1};
     for (int j = 0; j < D; ++j) {
         st[j] = npts;
         npts *= nh;
@@ -408,7 +416,7 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
         }
         for (int e = tid; e < nh; e += 256) Wq[2 * nh * nh + e] = a.mu[j][e];
     }
-    int tt[kMaxD] = {0, 0, 0};
+    int tt[kMaxD] = {0, 0, 0, 0};
     {
         int rem = blockIdx.x;
         for (int j = 0; j < D; ++j) {
@@ -418,23 +426,23 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
     }
     // 1) hole right-hand side
     for (int o = tid; o < npts; o += 256) {
-        int l[kMaxD] = {0, 0, 0}, i[kMaxD] = {0, 0, 0};
+        int l[kMaxD] = {0, 0, 0, 0}, i[kMaxD] = {0, 0, 0, 0};
         int rem = o;
         for (int j = 0; j < D; ++j) {
             l[j] = rem % nh;
             rem /= nh;
             i[j] = n * tt[j] + l[j];
         }
-        long long f = i[0] + (long long)Nf * (i[1] + (long long)Nf * (D == 3 ? i[2] : 0));
+        long long f = i[0] + (long long)Nf * (i[1] + (long long)Nf * (i[2] + (long long)Nf * i[3]));
         double v = a.bff ? a.bff[f] : 0.0;
         for (int j = 0; j < D; ++j) {
             if (l[j] == 0 && tt[j] > 0) {
-                int q[kMaxD] = {i[0], i[1], i[2]};
+                int q[kMaxD] = {i[0], i[1], i[2], i[3]};
                 q[j] -= 1;
                 v -= g.fine[j].a * a.skel[j][canon_offset(a.mk[j], q, n)];
             }
             if (l[j] == nh - 1 && tt[j] < Nc) {
-                int q[kMaxD] = {i[0], i[1], i[2]};
+                int q[kMaxD] = {i[0], i[1], i[2], i[3]};
                 q[j] += 1;
                 v -= g.fine[j].c * a.skel[j][canon_offset(a.mk[j], q, n)];
             }
@@ -448,10 +456,11 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
         const int j = a.tr[q];
         const double *Wq = mat + q * (2 * nh * nh + nh);
         for (int o = tid; o < npts; o += 256) {
-            const int m = (o / st[j]) % nh;
-            const int base = o - m * st[j];
+            const int sj = axis_sel(st, j);
+            const int m = (o / sj) % nh;
+            const int base = o - m * sj;
             double acc = 0.0;
-            for (int l = 0; l < nh; ++l) acc += Wq[m * nh + l] * cur[base + l * st[j]];
+            for (int l = 0; l < nh; ++l) acc += Wq[m * nh + l] * cur[base + l * sj];
             oth[o] = acc;
         }
         __syncthreads();
@@ -476,7 +485,7 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
                 for (int q = 0; q < a.ntr; ++q)
                     if (a.tr[q] == j) sigma += mat[q * (2 * nh * nh + nh) + 2 * nh * nh + c];
             }
-            const int sL = st[L];
+            const int sL = axis_sel(st, L);
             const double diag = t.b + sigma;
             double den = diag;
             double cp = t.c / den;
@@ -503,10 +512,11 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
         const int j = a.tr[q];
         const double *Vq = mat + q * (2 * nh * nh + nh) + nh * nh;
         for (int o = tid; o < npts; o += 256) {
-            const int ii = (o / st[j]) % nh;
-            const int base = o - ii * st[j];
+            const int sj = axis_sel(st, j);
+            const int ii = (o / sj) % nh;
+            const int base = o - ii * sj;
             double acc = 0.0;
-            for (int m = 0; m < nh; ++m) acc += Vq[ii * nh + m] * cur[base + m * st[j]];
+            for (int m = 0; m < nh; ++m) acc += Vq[ii * nh + m] * cur[base + m * sj];
             oth[o] = acc;
         }
         __syncthreads();
@@ -518,7 +528,7 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
     int ntile = 1;
     for (int j = 0; j < D; ++j) ntile *= n;
     for (int o = tid; o < ntile; o += 256) {
-        int l[kMaxD] = {0, 0, 0}, i[kMaxD] = {0, 0, 0};
+        int l[kMaxD] = {0, 0, 0, 0}, i[kMaxD] = {0, 0, 0, 0};
         int rem = o;
         bool inside = true, hole = true;
         for (int j = 0; j < D; ++j) {
@@ -554,7 +564,7 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
             }
             continue;
         }
-        const long long f = i[0] + (long long)Nf * (i[1] + (long long)Nf * (D == 3 ? i[2] : 0));
+        const long long f = i[0] + (long long)Nf * (i[1] + (long long)Nf * (i[2] + (long long)Nf * i[3]));
         a.out[f] = v;
     }
 }
@@ -784,13 +794,20 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
             case 31: ASDSM_FILL(2, 31); break;
             default: ASDSM_FILL(2, 0); break;
         }
-    } else {
+    } else if (d == 3) {
         switch (nh) {
             case 1: ASDSM_FILL(3, 1); break;
             case 3: ASDSM_FILL(3, 3); break;
             case 7: ASDSM_FILL(3, 7); break;
             case 15: ASDSM_FILL(3, 15); break;
             default: ASDSM_FILL(3, 0); break;
+        }
+    } else {
+        switch (nh) {
+            case 1: ASDSM_FILL(4, 1); break;
+            case 3: ASDSM_FILL(4, 3); break;
+            case 7: ASDSM_FILL(4, 7); break;
+            default: ASDSM_FILL(4, 0); break;
         }
     }
 #undef ASDSM_FILL

@@ -21,28 +21,34 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, MeshDesc m, const double *__
                                              double *__restrict__ out, double *partials,
                                              int with_norm) {
     const int d = g.d;
-    const long long faceN = (d == 2) ? g.Nf : (long long)g.Nf * g.Nf;
+    long long faceN = 1;  // N_f^(d-1) points per face
+    for (int j = 1; j < d; ++j) faceN *= g.Nf;
     double acc = 0.0;
     for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < m.size;
          idx += (long long)gridDim.x * 256) {
-        int i[kMaxD] = {0, 0, 0};
-        int cpos[kMaxD] = {0, 0, 0};
+        // fine coordinates i[] and coarse indices cpos[] (-1 on fine axes) of the point; written
+        // through compile-time indices only (a run-time index would put the arrays in scratch)
+        int i[kMaxD] = {0, 0, 0, 0};
+        int cpos[kMaxD] = {0, 0, 0, 0};
         long long rem = idx;
         for (int q = 0; q < d; ++q) {
-            const int pos = (int)(rem % m.ext[q]);
-            rem /= m.ext[q];
-            const int j = m.ax[q];
-            if (q < m.nfine) {
-                i[j] = pos;
-                cpos[j] = -1;
-            } else {
-                i[j] = (pos + 1) * g.n - 1;
-                cpos[j] = pos;
-            }
+            const int eq = axis_sel(m.ext, q);
+            const int pos = (int)(rem % eq);
+            rem /= eq;
+            const int j = axis_sel(m.ax, q);
+            const bool fine = q < m.nfine;
+#pragma unroll
+            for (int jj = 0; jj < kMaxD; ++jj)
+                if (jj == j) {
+                    i[jj] = fine ? pos : (pos + 1) * g.n - 1;
+                    cpos[jj] = fine ? -1 : pos;
+                }
         }
-        long long f = i[0] + (long long)g.Nf * (i[1] + (long long)g.Nf * (d == 3 ? i[2] : 0));
+        long long f = i[0] + (long long)g.Nf * (i[1] + (long long)g.Nf * (i[2] + (long long)g.Nf * i[3]));
         double v = s[f];
-        for (int j = 0; j < d; ++j) {
+#pragma unroll
+        for (int j = 0; j < kMaxD; ++j) {
+            if (j >= d) break;
             const bool coarse = (m.mask >> j) & 1u;
             const Tri t = coarse ? g.coarse[j] : g.fine[j];
             const bool lo = coarse ? (cpos[j] == 0) : (i[j] == 0);
@@ -50,8 +56,9 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, MeshDesc m, const double *__
             if (!lo && !hi) continue;
             // face index over the other axes, increasing order, lowest fastest
             long long fidx = 0, mul = 1;
-            for (int o = 0; o < d; ++o) {
-                if (o == j) continue;
+#pragma unroll
+            for (int o = 0; o < kMaxD; ++o) {
+                if (o == j || o >= d) continue;
                 fidx += (long long)i[o] * mul;
                 mul *= g.Nf;
             }
@@ -81,8 +88,8 @@ __global__ __launch_bounds__(256) void k_update_residual(
     const int i0 = blockIdx.y * 64 + tx;
     const int nrows = (int)(g.NF / Nf);
     const double s = e ? scal[kScalStep] : 0.0;
-    const int sy = Nf, sz = Nf * Nf;
-    const double bsum = g.fine[0].b + g.fine[1].b + (D == 3 ? g.fine[2].b : 0.0);
+    const int sy = Nf, sz = Nf * Nf, sw = Nf * Nf * Nf;
+    const double bsum = g.fine[0].b + g.fine[1].b + (D >= 3 ? g.fine[2].b : 0.0) + (D == 4 ? g.fine[3].b : 0.0);
     double acc = 0.0;
     const int stride = gridDim.x * 4;
     // two rows per thread per pass, so the loads of both are in flight together
@@ -92,7 +99,8 @@ __global__ __launch_bounds__(256) void k_update_residual(
             const int row = row0 + q * stride;
             if (i0 >= Nf || row >= nrows) continue;
             const int i1 = row % Nf;
-            const int i2 = (D == 3) ? row / Nf : 0;
+            const int i2 = (D == 3) ? row / Nf : (D == 4) ? (row / Nf) % Nf : 0;
+            const int i3 = (D == 4) ? row / sz : 0;
             const int p = i0 + Nf * row;
             auto val = [&](int qq) -> double { return e ? uin[qq] + s * e[qq] : uin[qq]; };
             const double uc = val(p);
@@ -101,9 +109,13 @@ __global__ __launch_bounds__(256) void k_update_residual(
             if (i0 < Nf - 1) au += g.fine[0].c * val(p + 1);
             if (i1 > 0) au += g.fine[1].a * val(p - sy);
             if (i1 < Nf - 1) au += g.fine[1].c * val(p + sy);
-            if (D == 3) {
+            if (D >= 3) {
                 if (i2 > 0) au += g.fine[2].a * val(p - sz);
                 if (i2 < Nf - 1) au += g.fine[2].c * val(p + sz);
+            }
+            if (D == 4) {
+                if (i3 > 0) au += g.fine[3].a * val(p - sw);
+                if (i3 < Nf - 1) au += g.fine[3].c * val(p + sw);
             }
             const double rr = b[p] - au;
             r[p] = rr;
@@ -113,10 +125,16 @@ __global__ __launch_bounds__(256) void k_update_residual(
             if (D == 2) {
                 if (on_coarse(i0, n)) boxes.p[0][i1 + Nf * coarse_of(i0, n)] = rr;
                 if (on_coarse(i1, n)) boxes.p[1][i0 + Nf * coarse_of(i1, n)] = rr;
-            } else {
+            } else if (D == 3) {
                 if (on_coarse(i0, n)) boxes.p[0][i1 + sy * i2 + sz * coarse_of(i0, n)] = rr;
                 if (on_coarse(i1, n)) boxes.p[1][i0 + sy * i2 + sz * coarse_of(i1, n)] = rr;
                 if (on_coarse(i2, n)) boxes.p[2][i0 + sy * i1 + sz * coarse_of(i2, n)] = rr;
+            } else {
+                const long long w = sw;
+                if (on_coarse(i0, n)) boxes.p[0][i1 + sy * i2 + sz * i3 + w * coarse_of(i0, n)] = rr;
+                if (on_coarse(i1, n)) boxes.p[1][i0 + sy * i2 + sz * i3 + w * coarse_of(i1, n)] = rr;
+                if (on_coarse(i2, n)) boxes.p[2][i0 + sy * i1 + sz * i3 + w * coarse_of(i2, n)] = rr;
+                if (on_coarse(i3, n)) boxes.p[3][i0 + sy * i1 + sz * i2 + w * coarse_of(i3, n)] = rr;
             }
         }
     }
@@ -136,8 +154,8 @@ __global__ __launch_bounds__(256) void k_dots(Geo g, const double *__restrict__ 
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int i0 = blockIdx.y * 64 + tx;
     const int nrows = (int)(g.NF / Nf);
-    const int sy = Nf, sz = Nf * Nf;
-    const double bsum = g.fine[0].b + g.fine[1].b + (D == 3 ? g.fine[2].b : 0.0);
+    const int sy = Nf, sz = Nf * Nf, sw = Nf * Nf * Nf;
+    const double bsum = g.fine[0].b + g.fine[1].b + (D >= 3 ? g.fine[2].b : 0.0) + (D == 4 ? g.fine[3].b : 0.0);
     double rq = 0.0, qq = 0.0;
     const int stride = gridDim.x * 4;
     for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += 2 * stride) {
@@ -146,16 +164,21 @@ __global__ __launch_bounds__(256) void k_dots(Geo g, const double *__restrict__ 
             const int row = row0 + h * stride;
             if (i0 >= Nf || row >= nrows) continue;
             const int i1 = row % Nf;
-            const int i2 = (D == 3) ? row / Nf : 0;
+            const int i2 = (D == 3) ? row / Nf : (D == 4) ? (row / Nf) % Nf : 0;
+            const int i3 = (D == 4) ? row / sz : 0;
             const int p = i0 + Nf * row;
             double q = bsum * e[p];
             if (i0 > 0) q += g.fine[0].a * e[p - 1];
             if (i0 < Nf - 1) q += g.fine[0].c * e[p + 1];
             if (i1 > 0) q += g.fine[1].a * e[p - sy];
             if (i1 < Nf - 1) q += g.fine[1].c * e[p + sy];
-            if (D == 3) {
+            if (D >= 3) {
                 if (i2 > 0) q += g.fine[2].a * e[p - sz];
                 if (i2 < Nf - 1) q += g.fine[2].c * e[p + sz];
+            }
+            if (D == 4) {
+                if (i3 > 0) q += g.fine[3].a * e[p - sw];
+                if (i3 < Nf - 1) q += g.fine[3].c * e[p + sw];
             }
             rq += r[p] * q;
             qq += q * q;
@@ -493,11 +516,15 @@ void launch_update_residual(const Plan &p, const double *uin, const double *e, d
                             double *const *gather, int fin_mode, hipStream_t st) {
     BoxPtrs bx;
     for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? gather[1u << k] : nullptr;
-    if (p.d == 2) {
+    if (p.d == 2 || p.d == 4) {
         dim3 grid;
         stencil_grid(p.geo, grid);
-        ASDSM_LAUNCH((k_update_residual<2>), grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
-                     p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
+        if (p.d == 2)
+            ASDSM_LAUNCH((k_update_residual<2>), grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
+                         p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
+        else
+            ASDSM_LAUNCH((k_update_residual<4>), grid, dim3(256), 0, st, p.geo, uin, e, p.ws.scal,
+                         p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
         launch_finalize(p, (int)(grid.x * grid.y), fin_mode, 1, st);
         return;
     }
@@ -515,10 +542,13 @@ void launch_update_residual(const Plan &p, const double *uin, const double *e, d
 }
 
 void launch_dots(const Plan &p, hipStream_t st) {
-    if (p.d == 2) {
+    if (p.d == 2 || p.d == 4) {
         dim3 grid;
         stencil_grid(p.geo, grid);
-        ASDSM_LAUNCH((k_dots<2>), grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
+        if (p.d == 2)
+            ASDSM_LAUNCH((k_dots<2>), grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
+        else
+            ASDSM_LAUNCH((k_dots<4>), grid, dim3(256), 0, st, p.geo, p.ws.e, p.ws.r, p.ws.partials, p.gate);
         launch_finalize(p, (int)(grid.x * grid.y), kFinDots, 1, st);
         return;
     }

@@ -59,6 +59,7 @@ struct LineJob {
     double *scratch[kMaxD];    // same size as X
     const double *mu_a[kMaxD]; // eigenvalues of the first fine axis
     const double *mu_b[kMaxD]; // eigenvalues of the second fine axis (nullptr when d = 2)
+    const double *mu_c[kMaxD]; // eigenvalues of the third fine axis (d = 4 only, else nullptr)
     Tri t[kMaxD];              // coarse-axis operator of each box
     int nbox;
     long long nmodes;          // product of the fine extents
@@ -125,6 +126,9 @@ void launch_sumsq(const Plan &p, const double *const *x, const long long *n, int
 // p.ws.perm_table[p.ws.state->it].
 void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipStream_t st);
 void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t st);
+// d = 4 (k_skel4.hip): the discrepancy families and Boolean-sum remainders, then the merge
+void launch_crosspoints4(const Plan &p, int mode, const double *const *res, hipStream_t st);
+void launch_merge4(const Plan &p, int mode, const double *const *res, hipStream_t st);
 // skel: the merged skeleton values per anisotropic mesh (default: the Y buffers); adj_only: write the
 // hole layers next to each coarse plane into the EA buffers instead of the fine tiles
 void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st, double *const *skel = nullptr,

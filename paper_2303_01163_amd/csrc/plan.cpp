@@ -298,19 +298,48 @@ static bool build_dense_inverse(Plan &p, unsigned mask) {
         }
         cs *= e;
     }
-    std::vector<double> A((size_t)B * B);
-    for (long long mode = 0; mode < m.nmodes; ++mode) {
-        double sigma = 0.0;
-        long long rem = mode;
-        for (int q = 0; q < m.nfine; ++q) {
-            int mq = (int)(rem % m.ext[q]);
-            rem /= m.ext[q];
-            sigma += p.fine_spec[m.ax[q]].mu[mq];
+    // modes are independent: small blocks (many modes) are spread over host threads; large blocks
+    // thread their own substitutions
+    auto run = [&](long long m0, long long m1, bool *ok) {
+        std::vector<double> A((size_t)B * B);
+        for (long long mode = m0; mode < m1; ++mode) {
+            double sigma = 0.0;
+            long long rem = mode;
+            for (int q = 0; q < m.nfine; ++q) {
+                int mq = (int)(rem % m.ext[q]);
+                rem /= m.ext[q];
+                sigma += p.fine_spec[m.ax[q]].mu[mq];
+            }
+            A = Kc;
+            for (int i = 0; i < B; ++i) A[(size_t)i * B + i] += sigma;
+            if (!dense_inverse(B, A, out.data() + (size_t)mode * B * B)) {
+                *ok = false;
+                return;
+            }
         }
-        A = Kc;
-        for (int i = 0; i < B; ++i) A[(size_t)i * B + i] += sigma;
-        if (!dense_inverse(B, A, out.data() + (size_t)mode * B * B)) return false;
+    };
+    int nt = 1;
+    if (B < 512 && m.nmodes >= 16 && (double)m.nmodes * B * B * B > 1e7)
+        nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    if (nt == 1) {
+        bool ok = true;
+        run(0, m.nmodes, &ok);
+        return ok;
     }
+    std::vector<std::thread> pool;
+    std::vector<char> oks(nt, 1);
+    const long long chunk = (m.nmodes + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+        const long long m0 = t * chunk, m1 = std::min<long long>(m.nmodes, m0 + chunk);
+        if (m0 < m1) pool.emplace_back([&, t, m0, m1] {
+            bool ok = true;
+            run(m0, m1, &ok);
+            oks[t] = ok;
+        });
+    }
+    for (std::thread &th : pool) th.join();
+    for (char o : oks)
+        if (!o) return false;
     return true;
 }
 
@@ -338,9 +367,12 @@ void layout_workspace(Plan &p, char *base, bool assign) {
             w.W[s] = (double *)take((size_t)p.mesh[s].size * 8);
         }
     }
-    // cross-point discrepancy lines of each anisotropic mesh: d=2: Nc*Nc; d=3: parts A, B, R of
-    // Nc*Nc*Nf values each
-    const size_t nl = (p.d == 2) ? (size_t)p.Nc * p.Nc : (size_t)3 * p.Nc * p.Nc * p.Nf;
+    // cross-point discrepancies of each anisotropic mesh: d=2: Nc*Nc; d=3: parts A, B, R of
+    // Nc*Nc*Nf values each; d=4: three plane families and two Boolean-sum remainders of
+    // Nc*Nc*Nf*Nf values each
+    const size_t nl = (p.d == 2)   ? (size_t)p.Nc * p.Nc
+                      : (p.d == 3) ? (size_t)3 * p.Nc * p.Nc * p.Nf
+                                   : (size_t)5 * p.Nc * p.Nc * p.Nf * p.Nf;
     for (int k = 0; k < p.d; ++k) w.lines[k] = (double *)take(nl * 8);
     for (int k = 0; k < p.d; ++k) {
         w.F1[k] = (float *)take((size_t)p.mesh[1u << k].size * 4);
@@ -382,7 +414,7 @@ void axis_permutation(uint64_t seed, int64_t k, int d, int perm[kMaxD]) {
 
 int build_plan(Plan &p, int d, const double *alpha, const double *beta, int level,
                int coarse_level, uint64_t seed, hipStream_t stream) {
-    if (d < 2 || d > kMaxD) return fail(ASDSM_E_ARG, "d must be 2 or 3");
+    if (d < 2 || d > kMaxD) return fail(ASDSM_E_ARG, "d must be 2, 3 or 4");
     if (!alpha || !beta) return fail(ASDSM_E_ARG, "alpha and beta must be non-NULL");
     if (level < 2 || level > 10) return fail(ASDSM_E_ARG, "level must be in [2, 10]");
     if (coarse_level == 0) coarse_level = level / 2;
@@ -446,7 +478,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     build_spline(p.Nf, p.Nc, p.n, p.h, p.H, p.Sp);
     for (unsigned s = 0; s < (1u << d); ++s) p.mesh[s] = make_mesh(d, p.Nf, p.Nc, s);
     // intersection meshes: per-mode dense inverses of at most kDenseMaxBlock coarse points, at most
-    // 512 MiB in total
+    // 2 GiB in total (d = 4 at 63^4 with N_c = 7 needs 0.74 GB)
     {
         double bytes = 0.0;
         for (unsigned s = 1; s < (1u << d); ++s)
@@ -458,8 +490,8 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
                                                          " coarse points per mode");
                 bytes += 8.0 * (double)m.nmodes * m.block * m.block;
             }
-        if (bytes > 512.0 * 1024 * 1024)
-            return fail(ASDSM_E_UNSUPPORTED, "intersection-mesh inverses exceed 512 MiB");
+        if (bytes > 2048.0 * 1024 * 1024)
+            return fail(ASDSM_E_UNSUPPORTED, "intersection-mesh inverses exceed 2 GiB");
     }
     for (unsigned s = 1; s < (1u << d); ++s) {
         if (__builtin_popcount(s) >= 2) {
@@ -472,7 +504,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     // transformed axes.  Where that exceeds 2e-11 the direct solve becomes the preconditioner of
     // FP64 refinement sweeps x <- x + M^-1 (f - A x), each gaining -log10(eps * prod cond) digits;
     // the count is fixed here so that the result reaches ~1e-14.
-    p.fp32_ok = true;
+    p.fp32_ok = (d <= 3);  // the FP32 error guesses are built for d = 2 and 3
     for (unsigned s = 1; s < (1u << d); ++s) {
         double c = 1.0;
         for (int q = 0; q < p.mesh[s].nfine; ++q) c *= p.fine_spec[p.mesh[s].ax[q]].cond;
@@ -581,6 +613,8 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     for (auto &it : items) std::memcpy(host.data() + it.off, it.data, it.bytes);
     err = hipMemcpy(p.dtab, host.data(), p.dtab_bytes, hipMemcpyHostToDevice);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipMemcpy(tables): ") + hipGetErrorString(err));
+    // the per-mode inverses live on the device only (up to 2 GiB)
+    for (unsigned s = 0; s < kMaxMeshes; ++s) std::vector<double>().swap(p.dense_inv[s]);
     char *base = (char *)p.dtab;
     for (int j = 0; j < d; ++j) {
         p.dW[j] = (double *)(base + oW[j]);

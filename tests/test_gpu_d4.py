@@ -1,0 +1,134 @@
+"""d = 4 through the C ABI at sizes the CPU oracle cannot reach (the oracle comparisons at 7^4 and 15^4
+are in test_gpu_parity.py's CASES).  63^4 with N_c = 7 is the 4D configuration of the benchmark's
+side measurement: 15.75 M fine unknowns, four anisotropic meshes of 1.75 M points, eleven
+intersection meshes.  Properties that hold at any size:
+
+* Q2 exactness: for a manufactured solution of degree <= 2 per variable every submesh solve is
+  the exact grid function, every discrepancy is zero, so u^(0) is the exact solution;
+* Proposition 3.2(2): the fine residual of every iterate vanishes on the holes;
+* Remark 3.4: the residual history does not increase;
+* every mesh solve satisfies its own equations.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.asdsm_oracle import Grid, apply_operator, mesh_coeffs
+from paper_2303_01163_amd.workloads import make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(dev, a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _canon(d, S, arr):
+    order = [j for j in range(d) if j not in S] + list(S)
+    return np.transpose(arr, order).reshape(-1, order="F")
+
+
+def _uncanon(grid, S, flat):
+    d = grid.d
+    order = [j for j in range(d) if j not in S] + list(S)
+    shape = [grid.Nc if j in S else grid.Nf for j in order]
+    arr = flat.reshape(shape, order="F")
+    return np.transpose(arr, np.argsort(order))
+
+
+def _plan(P, L, Lc, seed=0):
+    from paper_2303_01163_amd.asdsm import Plan
+    return Plan(P.d, P.alpha, P.beta, L, Lc, seed=seed)
+
+
+@pytest.mark.parametrize("L,Lc,seed", [(5, 2, 0), (6, 3, 1)])
+def test_d4_q2_initial_guess_is_exact(torch_dev, L, Lc, seed):
+    _say("d4 Q2 exactness", L, Lc, seed)
+    P = make_problem("quadratic", L, seed=seed, d=4)
+    pl = _plan(P, L, Lc, seed=seed)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u, info = pl.solve(s, g, max_iter=0)
+    ue = P.u_exact.reshape(-1, order="F")
+    err = np.linalg.norm(u.cpu().numpy() - ue) / np.linalg.norm(ue)
+    _say("   rel error", err)
+    assert err <= 1e-10
+
+
+def test_d4_full_size_properties(torch_dev):
+    _say("d4 properties 63^4")
+    L, Lc = 6, 3
+    P = make_problem("sinprod", L, seed=0, d=4)
+    pl = _plan(P, L, Lc, seed=5)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u, info = pl.solve(s, g, max_iter=8, rtol=1e-12, stag_window=0)
+    h = info["res_hist"]
+    _say("   residuals", h)
+    assert info["iterations"] == 8
+    assert all(h[i + 1] <= h[i] * (1 + 1e-12) for i in range(len(h) - 1))
+    assert h[-1] < h[0]
+    r, nrm = pl.residual(u, s, g)
+    assert abs(nrm - h[-1]) <= 1e-9 * h[-1]
+    grid = Grid(4, L, Lc)
+    rr = r.cpu().numpy().reshape((grid.Nf,) * 4, order="F")
+    holes = grid.hole_mask()
+    scale = np.linalg.norm(rr) / np.sqrt(rr.size)
+    assert np.max(np.abs(rr[holes])) <= 1e-9 * max(scale, info["bnorm"] / np.sqrt(rr.size))
+    # the residual lives on the skeleton
+    assert np.linalg.norm(rr[~holes]) >= 0.999 * np.linalg.norm(rr)
+
+
+def test_d4_mesh_solves_satisfy_their_equations(torch_dev):
+    _say("d4 mesh solves 63^4")
+    L, Lc = 6, 3
+    P = make_problem("sinprod", L, seed=2, d=4)
+    pl = _plan(P, L, Lc)
+    grid = Grid(4, L, Lc)
+    rng = np.random.default_rng(11)
+    for S in ((0,), (3,), (0, 1), (1, 3), (0, 2, 3), (0, 1, 2, 3)):
+        mask = sum(1 << j for j in S)
+        rhs = rng.standard_normal(grid.mesh_dims(S))
+        x = _uncanon(grid, S, pl.mesh_solve(mask, _t(torch_dev, _canon(4, S, rhs))).cpu().numpy())
+        res = apply_operator(x, mesh_coeffs(grid, P.alpha, P.beta, S)) - rhs
+        _say("   mesh", S, np.linalg.norm(res) / np.linalg.norm(rhs))
+        assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(rhs), S
+
+
+def test_d4_graph_replay_matches_eager(torch_dev):
+    L, Lc = 5, 2
+    P = make_problem("sinprod", L, seed=3, d=4)
+    pl = _plan(P, L, Lc, seed=9)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u0, i0 = pl.solve(s, g, max_iter=6, rtol=0, stag_window=0, eager=True)
+    u1, i1 = pl.solve(s, g, max_iter=6, rtol=0, stag_window=0)
+    assert np.array_equal(u0.cpu().numpy(), u1.cpu().numpy())
+    assert i0["res_hist"] == i1["res_hist"]
+
+
+def test_d4_refuses_the_fp32_and_skeleton_modes(torch_dev):
+    from paper_2303_01163_amd.asdsm import AsdsmError
+    P = make_problem("sinprod", 4, seed=6, d=4)
+    pl = _plan(P, 4, 2)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    _, info = pl.solve(s, g, max_iter=2, precision="fp32")
+    assert info["precision"] == "fp64"   # the FP32 error guesses are built for d <= 3
+    with pytest.raises(AsdsmError) as ei:
+        pl.solve(s, g, max_iter=2, skeleton=True)
+    assert ei.value.code == -6
+    with pytest.raises(AsdsmError) as ei:
+        pl.set_tile("plane")
+    assert ei.value.code == -6

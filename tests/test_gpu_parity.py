@@ -71,6 +71,9 @@ CASES = [  # (family, level, coarse_level, d, seed)
     ("sinbump3d", 6, 3, None, 4),      # 63^3
     ("sinbump3d", 6, 4, None, 6),      # 63^3, 15 coarse planes per axis, 3^3 holes
     ("sinprod2d", 8, 4, None, 1),      # 255^2, 15 coarse lines per axis, 15^2 holes
+    ("sinprod", 3, 1, 4, 14),          # d = 4: 7^4, one coarse plane per axis, 3^4 holes
+    ("sinprod", 4, 2, 4, 6),           # 15^4, 3 coarse planes per axis, 3^4 holes
+    ("sinprod", 4, 3, 4, 7),           # 15^4, 7 coarse planes per axis, single-point holes
 ]
 
 
@@ -266,8 +269,8 @@ def test_error_codes(torch_dev):
     with pytest.raises(AsdsmError) as e:              # cell Peclet number 1 on a fine axis
         Plan(2, [1.0, 1.0], [2.0 * 32.0, 0.0], 5)
     assert e.value.code == -6
-    with pytest.raises(AsdsmError) as e:
-        Plan(4, [1.0] * 4, [0.0] * 4, 5)
+    with pytest.raises(AsdsmError) as e:             # d outside 2..4
+        Plan(5, [1.0] * 5, [0.0] * 5, 3)
     assert e.value.code == -1
     P = make_problem("sinprod2d", 5, seed=0)
     pl = _plan(P, 5, 0)
