@@ -362,6 +362,9 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
     if (plane) {
         PlaneJob pj{};
         pj.nbox = nb; pj.Nf = Nf; pj.nplanes = Nc; pj.accum = accum; pj.gate = p.gate;
+        // the last backward launch of an error guess leaves the norms' partial sums (a later
+        // sweep's launch overwrites those of the first)
+        pj.norm_partials = (p.norm_partials && nb == d) ? p.norm_partials : nullptr;
         for (int q = 0; q < nb; ++q) {
             int a, b;
             fine_axes(d, ks[q], a, b);
@@ -851,15 +854,27 @@ int error_guess(Plan &p) {
             out[k] = sol_buf(p, 1u << k);
         }
         if (int rc = solve_aniso32(p, in, out)) return rc;
-    } else if (int rc = solve_aniso_refined(p, (1u << p.d) - 1)) {
-        return rc;
+    } else {
+        // with the plane kernel the backward transforms also leave the partial sums of ||e_k||^2
+        // that the skeleton kernels reduce themselves (no separate norm launches)
+        const bool fused = plane_transforms(p);
+        p.norm_partials = fused ? p.ws.partials : nullptr;
+        p.norm_nblk = p.Nc * ((p.Nf + 15) / 16);
+        const int rc = solve_aniso_refined(p, (1u << p.d) - 1);
+        if (!fused) p.norm_partials = nullptr;
+        if (rc) {
+            p.norm_partials = nullptr;
+            return rc;
+        }
     }
     const double *res[kMaxMeshes];
     result_pointers(p, res);
-    PhaseTimer t(p, ASDSM_PHASE_SKELETON, skeleton_launches(p) + 1, 0.0, 24.0 * aniso_points(p));
-    launch_box_norms(p, res, p.stream);
+    PhaseTimer t(p, ASDSM_PHASE_SKELETON, skeleton_launches(p) + (p.norm_partials ? 0 : 1), 0.0,
+                 24.0 * aniso_points(p));
+    if (!p.norm_partials) launch_box_norms(p, res, p.stream);
     launch_crosspoints(p, 1, res, p.stream);
     launch_merge(p, 1, res, p.stream);
+    p.norm_partials = nullptr;
     return check_launch("skeleton");
 }
 

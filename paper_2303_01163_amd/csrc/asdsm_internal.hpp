@@ -149,6 +149,10 @@ struct Plan {
     bool prec32 = false;             // this call's error guesses run in FP32
     bool sparse = false;             // this call's refinement runs on the skeleton only
     int tile_aniso = 0;              // FP64 transform tile of the anisotropic solves (0: auto)
+    // error phase with the plane kernel: its backward launch leaves per-block sums of squares of the
+    // solutions here (norm_nblk per mesh) for the cross-point and merge kernels; else nullptr
+    double *norm_partials = nullptr;
+    int norm_nblk = 0;
     bool fp32_ok = false;            // every anisotropic mesh: 6e-8 * prod cond(V_j) <= 1e-3
     // hole line elimination factors (d = 3): for the mode pair q = m0 + nh m1 of the two transformed
     // hole axes, step c: hole_inv[c nh^2 + q] = 1/pivot_c, hole_cp[...] = super / pivot_c

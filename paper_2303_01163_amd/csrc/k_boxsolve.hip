@@ -171,73 +171,34 @@ bool launch_gemm(const GemmJob &job, hipStream_t st) {
 // block (8 waves) owns a 16-column panel [m0, m0 + 16) of one slab, and the two products split
 // without recomputation:
 //     T = X_c R[m0:m0+16, :]^T  (N_f x 16, kept in LDS),   C_c[:, m0:m0+16] = L T.
-// Wave w owns row tiles w, w + 8, ... (16 rows) of both products.  The A operands (rows of X_c and
-// of L) are read from global memory straight into the fragment layout: a load covers 16 rows x 4
-// columns, and the four k-steps that share those cache lines hit the L1.  R's panel and T live in
-// LDS with a pitch of 16 doubles (a fragment read is 4 rows of 128 contiguous bytes: no conflicts).
-// Consecutive block ids go to consecutive XCDs and each XCD takes a contiguous range of (box, slab,
-// panel) items, so the panels of one slab share that XCD's L2 copy of X_c.
+// Wave w owns row tiles w, w + 8, ... (16 rows) of both products.  A row tile of the A operand
+// (X_c or L) is staged through the wave's own LDS area in chunks of KC columns: sixteen row
+// segments of KC contiguous doubles, one coalesced load per row, the next chunk's loads in flight
+// in registers while the current chunk is multiplied; the MFMA fragments are then read from LDS.
+// R's panel and T are LDS-resident for the whole block.  Consecutive block ids go to consecutive
+// XCDs and each XCD takes a contiguous range of (box, slab, panel) items, so the panels of one slab
+// share that XCD's L2 copy of X_c.  Indices past the row ends or the last row are clamped into the
+// data: the B operand (R's panel, T) is zero there, and rows of T past N_f are set to zero.
 // Operand layout of v_mfma_f64_16x16x4f64 (lane l): A row l%16, k l/16; B k l/16, col l%16;
 // D[v] row l/16 + 4v, col l%16.
 // ---------------------------------------------------------------------------------------------
-// A batch of KS k-steps of a row tile's A fragments (row pointer ar), issued together so that each
-// MFMA waits only for its own operand.  Column indices past the row end are clamped to its last
-// element: the B operand is zero there (R's panel and T are zero-padded), so the clamped values,
-// real entries of the same row, add nothing, and no load leaves the slab.
-template <int KS>
-__device__ __forceinline__ void plane_load(double (&a)[KS], const double *__restrict__ ar, int Nf, int lg) {
-#pragma unroll
-    for (int q = 0; q < KS; ++q) {
-        const int k = 4 * q + lg;
-        a[q] = ar[k < Nf ? k : Nf - 1];
-    }
-}
-
-template <int KS>
-__device__ __forceinline__ void plane_mfma(double4_t &acc, const double (&a)[KS], const double (*sB)[16], int s0, int lg,
-                                           int ln) {
-#pragma unroll
-    for (int q = 0; q < KS; ++q)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], sB[4 * (s0 + q) + lg][ln], acc, 0, 0, 0);
-}
-
-// Row tile x 16 columns of A B (B in LDS), A's fragments in batches of H k-steps (H = KS up to 32
-// k-steps, else 16); a holds the first batch on entry.  Two register batches alternate, so the next
-// batch's loads are in flight while the current one is multiplied.
-template <int KS>
-constexpr int plane_batch() { return KS <= 32 ? KS : 16; }
-
-template <int KS>
-__device__ __forceinline__ double4_t plane_tile(double (&a)[plane_batch<KS>()], const double *__restrict__ ar, int Nf,
-                                                const double (*sB)[16], int lg, int ln) {
-    constexpr int H = plane_batch<KS>();
-    constexpr int NB = KS / H;
-    static_assert(NB * H == KS && NB % 2 == 0 || NB == 1, "whole batch pairs");
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    if constexpr (NB == 1) {
-        plane_mfma<H>(acc, a, sB, 0, lg, ln);
-    } else {
-        double b[H];
-#pragma unroll
-        for (int t = 0; t < NB; t += 2) {
-            plane_load<H>(b, ar + 4 * H * (t + 1), Nf - 4 * H * (t + 1), lg);
-            plane_mfma<H>(acc, a, sB, H * t, lg, ln);
-            if (t + 2 < NB) plane_load<H>(a, ar + 4 * H * (t + 2), Nf - 4 * H * (t + 2), lg);
-            plane_mfma<H>(acc, b, sB, H * (t + 1), lg, ln);
-        }
-    }
-    return acc;
-}
+template <int NT>
+struct PlaneLds {
+    static constexpr int KP = 16 * NT;                 // contraction length padded to whole tiles
+    static constexpr int KC = KP < 64 ? KP : 64;       // staged columns per chunk
+    static constexpr int PITCH = KC + 4;               // row pitch of a staged tile (doubles)
+    static constexpr int STAGE = 16 * PITCH;           // one wave's staging area
+    static constexpr size_t BYTES = (size_t)(2 * KP * 16 + 8 * STAGE) * sizeof(double);
+};
 
 template <int NT>
 __global__ __launch_bounds__(512) void k_plane2(PlaneJob job) {
     if (job.gate && *job.gate) return;
-    constexpr int KP = 16 * NT;                  // contraction length padded to whole tiles
-    constexpr int KS = KP / 4;                   // MFMA k-steps
-    constexpr int RT = (NT + 7) / 8;             // row tiles per wave
-    constexpr int H = plane_batch<KS>();         // k-steps per batch of A fragments
-    __shared__ double sR[KP][16];                // sR[k][n] = R[m0 + n][k]
-    __shared__ double sT[KP][16];                // T
+    using S = PlaneLds<NT>;
+    constexpr int KP = S::KP, KC = S::KC, NCH = KP / KC, RT = (NT + 7) / 8;
+    extern __shared__ double smem[];
+    double(*sR)[16] = reinterpret_cast<double(*)[16]>(smem);            // sR[k][n] = R[m0 + n][k]
+    double(*sT)[16] = reinterpret_cast<double(*)[16]>(smem + KP * 16);  // T
     const int Nf = job.Nf;
     const int np = (Nf + 15) >> 4;
     const int total = job.nbox * job.nplanes * np;
@@ -255,6 +216,7 @@ __global__ __launch_bounds__(512) void k_plane2(PlaneJob job) {
     const int m0 = pan * 16;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int ln = lane & 15, lg = lane >> 4;
+    double *__restrict__ sA = smem + 2 * KP * 16 + w * S::STAGE;  // this wave's staging area
     // R's panel, n fastest across threads (contiguous LDS writes); indices clamped, values selected
 #pragma unroll
     for (int e0 = 0; e0 < 16 * KP; e0 += 512) {
@@ -262,66 +224,107 @@ __global__ __launch_bounds__(512) void k_plane2(PlaneJob job) {
         const bool ok = m0 + n < Nf && k < Nf;
         sR[k][n] = R[(long long)(m0 + n < Nf ? m0 + n : Nf - 1) * Nf + (k < Nf ? k : Nf - 1)] * (ok ? 1.0 : 0.0);
     }
-    // A rows past N_f (and the rows of idle waves) read row 0; their results are dropped
-    double a[H];
-    {
-        const int row = w * 16 + ln;
-        plane_load<H>(a, X + (long long)(row < Nf ? row : 0) * Nf, Nf, lg);
-    }
-    __syncthreads();
-    // T = X_c R_panel^T
+    // chunk ch of row tile rt of matrix A into registers: row r of the tile, column ch*KC + lane
+    // (lanes past KC idle when KC < 64)
+    double xr[16];
+    auto fetch = [&](const double *__restrict__ A, int rt, int ch) {
+        const int col = ch * KC + lane;
+        const int cc = col < Nf ? col : Nf - 1;
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        const int rt = w + 8 * i;
-        if (rt < NT) {
-            const int row = rt * 16 + ln;
-            const double *__restrict__ xr = X + (long long)(row < Nf ? row : 0) * Nf;
-            if (i > 0) plane_load<H>(a, xr, Nf, lg);
-            const double4_t acc = plane_tile<KS>(a, xr, Nf, sR, lg, ln);
-            // rows of T past N_f are zero: they meet L's clamped columns in the second product
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int tr = rt * 16 + lg + 4 * v;
-                sT[tr][ln] = tr < Nf ? acc[v] : 0.0;
-            }
+        for (int r = 0; r < 16; ++r) {
+            const int row = rt * 16 + r;
+            xr[r] = A[(long long)(row < Nf ? row : 0) * Nf + cc];
         }
-    }
-    // L's fragments of the first row tile do not depend on T: issue them before the barrier
-    {
-        const int row = w * 16 + ln;
-        plane_load<H>(a, L + (long long)(row < Nf ? row : 0) * Nf, Nf, lg);
-    }
-    __syncthreads();
-    // C_c[:, m0:m0+16] = L T
+    };
+    auto stage = [&]() {
+        if (lane < KC) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) sA[r * S::PITCH + lane] = xr[r];
+        }
+    };
+    auto mfma_chunk = [&](double4_t &acc, const double (*sB)[16], int ch) {
+#pragma unroll
+        for (int q = 0; q < KC / 4; ++q)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[ln * S::PITCH + 4 * q + lg], sB[ch * KC + 4 * q + lg][ln],
+                                                       acc, 0, 0, 0);
+    };
+    // one product over this wave's row tiles: A (global, staged) times B (LDS); every wave runs the
+    // same number of chunk steps, so the block barriers are uniform
+    auto product = [&](const double *__restrict__ A, const double (*sB)[16], auto &&epilogue) {
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const int rt = w + 8 * i;
+            double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                __syncthreads();  // the previous chunk's fragment reads are done
+                stage();
+                __syncthreads();  // the staged chunk is visible
+                // next loads in flight during the MFMAs: the next chunk, or the next tile's first
+                if (ch + 1 < NCH)
+                    fetch(A, rt < NT ? rt : 0, ch + 1);
+                else if (i + 1 < RT)
+                    fetch(A, rt + 8 < NT ? rt + 8 : 0, 0);
+                if (rt < NT) mfma_chunk(acc, sB, ch);
+            }
+            if (rt < NT) epilogue(rt, acc);
+        }
+    };
+    // T = X_c R_panel^T; rows of T past N_f are zero
+    fetch(X, w < NT ? w : 0, 0);
+    product(X, sR, [&](int rt, const double4_t &acc) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int tr = rt * 16 + lg + 4 * v;
+            sT[tr][ln] = tr < Nf ? acc[v] : 0.0;
+        }
+    });
+    // C_c[:, m0:m0+16] = L T (the first chunk of L is fetched before the barrier that publishes T,
+    // which the first chunk step of the product provides)
+    fetch(L, w < NT ? w : 0, 0);
     const int col = m0 + ln;
+    double ss = 0.0;  // sum of squares of the values this thread writes
+    product(L, sT, [&](int rt, const double4_t &acc) {
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        const int rt = w + 8 * i;
-        if (rt < NT) {
-            const int row = rt * 16 + ln;
-            const double *__restrict__ lr = L + (long long)(row < Nf ? row : 0) * Nf;
-            if (i > 0) plane_load<H>(a, lr, Nf, lg);
-            const double4_t acc = plane_tile<KS>(a, lr, Nf, sT, lg, ln);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int orow = rt * 16 + lg + 4 * v;
-                if (orow < Nf && col < Nf) {
-                    double *cp = C + (long long)orow * Nf + col;
-                    *cp = job.accum ? *cp + acc[v] : acc[v];
-                }
+        for (int v = 0; v < 4; ++v) {
+            const int orow = rt * 16 + lg + 4 * v;
+            if (orow < Nf && col < Nf) {
+                double *cp = C + (long long)orow * Nf + col;
+                const double val = job.accum ? *cp + acc[v] : acc[v];
+                *cp = val;
+                ss += val * val;
             }
         }
+    });
+    if (job.norm_partials) {
+        __shared__ double sh[8];
+        const double t = block_sum<512>(ss, sh);
+        if (tid == 0) job.norm_partials[item] = t;
     }
+}
+
+template <int NT>
+static void plane_prepare_one() {
+    (void)hipFuncSetAttribute((const void *)k_plane2<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)PlaneLds<NT>::BYTES);
+}
+
+void plane_prepare() {
+    // the staging areas take the kernels past 64 KB of dynamic LDS
+    plane_prepare_one<2>();
+    plane_prepare_one<4>();
+    plane_prepare_one<8>();
+    plane_prepare_one<16>();
 }
 
 bool launch_plane2(const PlaneJob &job, hipStream_t st) {
     const int nt = (job.Nf + 15) / 16;
     const long long total = (long long)job.nbox * job.nplanes * nt;
     const dim3 grid((unsigned)(8 * ((total + 7) / 8))), blk(512);
-    if (nt <= 2) ASDSM_LAUNCH((k_plane2<2>), grid, blk, 0, st, job);
-    else if (nt <= 4) ASDSM_LAUNCH((k_plane2<4>), grid, blk, 0, st, job);
-    else if (nt <= 8) ASDSM_LAUNCH((k_plane2<8>), grid, blk, 0, st, job);
-    else if (nt <= 16) ASDSM_LAUNCH((k_plane2<16>), grid, blk, 0, st, job);
+    if (nt <= 2) ASDSM_LAUNCH((k_plane2<2>), grid, blk, PlaneLds<2>::BYTES, st, job);
+    else if (nt <= 4) ASDSM_LAUNCH((k_plane2<4>), grid, blk, PlaneLds<4>::BYTES, st, job);
+    else if (nt <= 8) ASDSM_LAUNCH((k_plane2<8>), grid, blk, PlaneLds<8>::BYTES, st, job);
+    else if (nt <= 16) ASDSM_LAUNCH((k_plane2<16>), grid, blk, PlaneLds<16>::BYTES, st, job);
     else return false;
     return true;
 }

@@ -27,6 +27,11 @@ struct SkelArgs {
     const int *perm_table;          // error phase: permutation of step it at perm_table[kMaxD*it]
     const IterState *state;
     const int *gate;
+    // error phase with the plane kernel: per-block partial sums of squares of each anisotropic
+    // solution (norm_nblk per mesh, mesh-major), from which every block forms the normalisation
+    // itself; nullptr: the factors are in scal (k_box_norms)
+    const double *norm_partials;
+    int norm_nblk;
 };
 
 // A fine point as three coordinates (x2 = 0 for d = 2).  The helpers below index only with
@@ -75,25 +80,55 @@ __device__ __forceinline__ long long inter_offset(const Geo &g, unsigned S, cons
     return p.x2 + Nf * (c0 + Nc * c1);               // S = 3, fine x_3
 }
 
-// Per-launch value of the error-phase choice, read once per thread before the point loop: this
-// step's axis permutation.
+// Per-launch values of the error phase, read once per block before the point loop: this step's
+// axis permutation and the normalisation factors 1/||e_k||.  Must be called by every thread of the
+// block (the factors may come from a block reduction).
 struct XChoice {
     int p0, p1, p2;
+    double inv0, inv1, inv2;
 };
 
 __device__ __forceinline__ XChoice load_choice(const SkelArgs &a, const Geo &g) {
-    XChoice c{0, 1, 2};
+    XChoice c{0, 1, 2, 1.0, 1.0, 1.0};
     if (a.mode == 1) {
         const int *perm = a.perm_table + kMaxD * a.state->it;
         c.p0 = perm[0];
         c.p1 = perm[1];
         c.p2 = (g.d == 3) ? perm[2] : 2;
+        if (a.norm_partials) {
+            __shared__ double sh[16], sinv[kMaxD];
+            for (int k = 0; k < g.d; ++k) {
+                double v = 0.0;
+                for (int b = threadIdx.x; b < a.norm_nblk; b += blockDim.x)
+                    v += a.norm_partials[(size_t)k * a.norm_nblk + b];
+                // fixed-order block sum (every block of every launch gets the same value)
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+                __syncthreads();
+                if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double t = 0.0;
+                    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+                    sinv[k] = (t > 0.0) ? 1.0 / sqrt(t) : 1.0;
+                }
+            }
+            __syncthreads();
+            c.inv0 = sinv[0];
+            c.inv1 = sinv[1];
+            c.inv2 = (g.d == 3) ? sinv[2] : 1.0;
+        } else {
+            c.inv0 = a.scal[kScalInvNorm + 0];
+            c.inv1 = a.scal[kScalInvNorm + 1];
+            c.inv2 = (g.d == 3) ? a.scal[kScalInvNorm + 2] : 1.0;
+        }
     }
     return c;
 }
 
+__device__ __forceinline__ double inv_of(const XChoice c, int k) { return k == 0 ? c.inv0 : (k == 1 ? c.inv1 : c.inv2); }
+
 __device__ __forceinline__ double crosspoint_value(const SkelArgs &a, const Geo &g, const Pt &p,
-                                                  unsigned S, const XChoice &ch) {
+                                                  unsigned S, const XChoice ch) {
     if (a.mode == 0) {
         double sum = 0.0;
         int cnt = 0;
@@ -108,7 +143,7 @@ __device__ __forceinline__ double crosspoint_value(const SkelArgs &a, const Geo 
     int j = ch.p0;
     if (!((S >> j) & 1u)) j = ch.p1;
     if (!((S >> j) & 1u)) j = ch.p2;
-    const double inv = a.scal[kScalInvNorm + j];
+    const double inv = inv_of(ch, j);
     const double *rj = (j == 0) ? a.res[1] : (j == 1) ? a.res[2] : a.res[4];
     return inv * rj[aniso_offset(g, j, p)];
 }
@@ -134,7 +169,7 @@ __global__ __launch_bounds__(256) void k_crosspoints(Geo g, SkelArgs a) {
     int fa, fb;
     fine_axes_of(k, d, fa, fb);
     const unsigned mk = 1u << k;
-    const double scale_k = (a.mode == 0) ? 1.0 : a.scal[kScalInvNorm + k];
+    const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
     const long long nA = (d == 2) ? (long long)Nc * Nc : (long long)Nc * Nc * Nf;
     const long long total = (d == 2) ? nA : 2 * nA;
     const double *__restrict__ Xk = (k == 0) ? a.res[1] : (k == 1) ? a.res[2] : a.res[4];
@@ -200,7 +235,7 @@ __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
     fine_axes_of(k, d, fa, fb);
     const unsigned mk = 1u << k;
     const MeshDesc &m = a.mesh[mk];
-    const double scale_k = (a.mode == 0) ? 1.0 : a.scal[kScalInvNorm + k];
+    const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
     const double *__restrict__ X = a.res[mk];
     double *__restrict__ out = a.skel[k];
     const double *__restrict__ L = a.lines[k];
@@ -284,7 +319,7 @@ __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
     const double xa = ld(ty), xb = ld(ty + 4);
     __syncthreads();
     if (ia >= Nf) return;
-    const double scale_k = (a.mode == 0) ? 1.0 : a.scal[kScalInvNorm + k];
+    const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int j = ty + 4 * h, ib = ib0 + j;
@@ -323,6 +358,8 @@ static SkelArgs skel_args(const Plan &p, int mode, const double *const *res) {
     a.Sp = p.dSp;
     a.scal = p.ws.scal;
     a.mode = mode;
+    a.norm_partials = (mode == 1) ? p.norm_partials : nullptr;
+    a.norm_nblk = p.norm_nblk;
     return a;
 }
 

@@ -10,6 +10,8 @@
 // increasing order -- and the layers next to plane c on side s (s = 0: one below, s = 1: one above
 // along axis k) at the same offset plus s N_c N_f^2.  A point on several planes is stored in each
 // of their meshes with identical values; sums count it once, in the mesh of its lowest coarse axis.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -110,12 +112,34 @@ __global__ __launch_bounds__(256) void k_skel_dots(Geo g, SkelPtrs E, SkelPtrs E
 
 // u += s e and r -= s q on the skeleton (Algorithm 4 step 7 and the residual it implies), the
 // projections of r onto the anisotropic meshes for the next error guess (steps 4.1/4.2: r
-// restricted to M_k is R_k itself), and partial sums of ||r||^2 over owned points.
-__global__ __launch_bounds__(256) void k_skel_update(Geo g, const double *__restrict__ scal, SkelPtrs U,
-                                                     SkelPtrs E, SkelPtrs R, SkelPtrs Q, SkelPtrs G,
-                                                     double *partials, const int *gate) {
+// restricted to M_k is R_k itself), and partial sums of ||r||^2 over owned points.  The step
+// s = max(0, <r,q>/<q,q>) (step 6) is formed by every block from k_skel_dots' partial sums in one
+// fixed order, so all blocks agree bit for bit; block 0 records <r,q>, <q,q> and s in scal.
+__global__ __launch_bounds__(256) void k_skel_update(Geo g, double *__restrict__ scal, const double *__restrict__ dots,
+                                                     int ndots, SkelPtrs U, SkelPtrs E, SkelPtrs R, SkelPtrs Q,
+                                                     SkelPtrs G, double *partials, const int *gate) {
     if (gate && *gate) return;
-    const double s = scal[kScalStep];
+    __shared__ double sh[4], sstep;
+    {
+        double a0 = 0.0, a1 = 0.0;
+        for (int b = threadIdx.x; b < ndots; b += 256) {
+            a0 += dots[2 * b];
+            a1 += dots[2 * b + 1];
+        }
+        const double rq = block_sum<256>(a0, sh);
+        const double qq = block_sum<256>(a1, sh);
+        if (threadIdx.x == 0) {
+            const double st = (qq > 0.0) ? rq / qq : 0.0;
+            sstep = (st > 0.0) ? st : 0.0;
+            if (blockIdx.x == 0 && blockIdx.y == 0) {
+                scal[kScalRQ] = rq;
+                scal[kScalQQ] = qq;
+                scal[kScalStep] = sstep;
+            }
+        }
+        __syncthreads();
+    }
+    const double s = sstep;
     const long long per = (long long)g.Nc * g.Nf * g.Nf;
     const int k = blockIdx.y;
     double *__restrict__ Uk = (k == 0) ? U.p[0] : (k == 1) ? U.p[1] : U.p[2];
@@ -157,6 +181,11 @@ static int skel_tiles(const Plan &p) {
     return (int)(t < 1 ? 1 : t);
 }
 
+// k_skel_dots runs on at most 3 x 128 blocks: every block of k_skel_update sums their partials.
+static int dots_tiles(const Plan &p) { return std::min(skel_tiles(p), 128); }
+// the dots partials sit behind the update's own partials (one value per block) in the workspace
+static double *dots_partials(const Plan &p) { return p.ws.partials + 2 * (size_t)p.max_blocks; }
+
 void launch_skel_gather(const Plan &p, const double *u, hipStream_t st) {
     const int tiles = skel_tiles(p);
     ASDSM_LAUNCH(k_skel_gather, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, u, p.ws.r, skel_ptrs(p.ws.SU),
@@ -164,19 +193,19 @@ void launch_skel_gather(const Plan &p, const double *u, hipStream_t st) {
 }
 
 void launch_skel_dots(const Plan &p, hipStream_t st) {
-    const int tiles = skel_tiles(p);
+    const int tiles = dots_tiles(p);
     double *E[kMaxD] = {p.ws.Y[1], p.ws.Y[2], p.ws.Y[4]};
     ASDSM_LAUNCH(k_skel_dots, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, skel_ptrs(E), skel_ptrs(p.ws.EA),
-                 skel_ptrs(p.ws.SR), skel_ptrs(p.ws.SQ), p.ws.partials, p.gate);
-    launch_finalize(p, 3 * tiles, kFinDots, 1, st);
+                 skel_ptrs(p.ws.SR), skel_ptrs(p.ws.SQ), dots_partials(p), p.gate);
 }
 
 void launch_skel_update(const Plan &p, double *const *gather, hipStream_t st) {
     const int tiles = skel_tiles(p);
     double *E[kMaxD] = {p.ws.Y[1], p.ws.Y[2], p.ws.Y[4]};
     double *G[kMaxD] = {gather[1], gather[2], gather[4]};
-    ASDSM_LAUNCH(k_skel_update, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, p.ws.scal, skel_ptrs(p.ws.SU),
-                 skel_ptrs(E), skel_ptrs(p.ws.SR), skel_ptrs(p.ws.SQ), skel_ptrs(G), p.ws.partials, p.gate);
+    ASDSM_LAUNCH(k_skel_update, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, p.ws.scal, dots_partials(p),
+                 3 * dots_tiles(p), skel_ptrs(p.ws.SU), skel_ptrs(E), skel_ptrs(p.ws.SR), skel_ptrs(p.ws.SQ),
+                 skel_ptrs(G), p.ws.partials, p.gate);
     launch_finalize(p, 3 * tiles, kFinIter, 1, st);
 }
 

@@ -91,9 +91,12 @@ struct PlaneJob {
     int nbox, Nf, nplanes;
     int accum;                 // 1: C += result
     const int *gate;
+    double *norm_partials;     // non-null: one sum of squares of the written C values per block,
+                               // at the block's (box, slab, panel) item index
 };
 constexpr int kPlaneMaxNf = 256;  // largest N_f of k_plane2 (16 row tiles of 16, two per wave)
 bool launch_plane2(const PlaneJob &job, hipStream_t st);  // false: N_f too large
+void plane_prepare();  // once per process, device current: the kernels' dynamic LDS limit
 // FP32 MFMA variant: A read as double (a_f64) or float, B float, C written as double (c_f64) or
 // float; the GemmJob pointers are reinterpreted accordingly.
 bool launch_gemm32(const GemmJob &job, bool a_f64, bool c_f64, hipStream_t st);

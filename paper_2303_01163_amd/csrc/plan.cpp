@@ -7,9 +7,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <thread>
 
 #include "asdsm_internal.hpp"
+#include "kernels.hpp"
 
 namespace asdsm {
 
@@ -542,6 +544,10 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
 
     // device tables
     hipError_t err = hipGetDevice(&p.device);
+    {
+        static std::once_flag plane_once;
+        std::call_once(plane_once, plane_prepare);
+    }
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(err));
     size_t off = 0;
     struct Item {
