@@ -31,7 +31,7 @@ PHASE_KERNEL = {"transform": "k_gemm_f64", "update": "k_update_residual3", "dots
 KERNEL_SOURCE = {"k_gemm_f64": "k_boxsolve.hip", "k_update_residual3": "k_stencil.hip",
                  "k_dots3": "k_stencil.hip", "k_filler_mfma3": "k_skeleton.hip",
                  "k_box_residual": "k_boxsolve.hip", "k_merge3": "k_skeleton.hip",
-                 "k_line": "k_boxsolve.hip", "k_crosspoints": "k_skeleton.hip",
+                 "k_line": "k_boxsolve.hip", "k_crosspoints3": "k_skeleton.hip",
                  "k_skel_dots": "k_sparse.hip", "k_skel_update": "k_sparse.hip", "k_conv_fwd": "k_learn.hip",
                  "k_plane2": "k_boxsolve.hip"}
 SKEL_KERNEL = {"update": "k_skel_update (+ the fine residual at the ends)", "dots": "k_skel_dots"}

@@ -100,7 +100,9 @@ double plane_bytes(const PlaneJob &j) {
 }
 // Whether the anisotropic solves run both fine-axis transforms of a slab in one launch (d = 3):
 // chosen by the autotuner or asdsm_set_tile, else by size: up to N_f = 127 (one row tile per wave)
-// the plane kernel beats two batched GEMMs; at 255 the 64 x 64 GEMM tiles are faster.
+// the plane kernel beats two batched GEMMs; at 255 the 64 x 64 GEMM tiles are faster.  (Batches
+// keep the rule too: with GEMM transforms the 15-problem batch of the bench took 47.4 ms instead
+// of 43.0.)
 constexpr int kPlaneAutoMaxNf = 127;
 bool plane_transforms(const Plan &p) {
     if (p.d != 3 || p.Nf > kPlaneMaxNf) return false;
@@ -670,7 +672,7 @@ double hole_points(const Plan &p) { return std::pow((double)(p.Nc + 1) * (p.geo.
 double filler_flops(const Plan &p) { return hole_points(p) * (4.0 * (p.d - 1) * (p.geo.n - 1) + 8.0); }
 
 // Launches of the cross-point and merge kernels (Algorithm 2) for this d.
-int skeleton_launches(const Plan &p) { return p.d == 2 ? 2 : (p.d == 3 ? 3 : 4); }
+int skeleton_launches(const Plan &p) { return p.d == 4 ? 4 : 2; }
 
 int read_scalars(Plan &p) {
     ASDSM_HIP_CHECK(hipMemcpyAsync(p.hscal, p.ws.scal, kScalCount * sizeof(double), hipMemcpyDeviceToHost, p.stream));

@@ -11,6 +11,8 @@
 // added; the merged skeleton value is the corrected u_k on points of one mesh only and uhat on cross
 // points (step 6).  The merged values are written per anisotropic mesh (canonical layout); the
 // filler reads them as Dirichlet data of the holes and writes whole fine tiles.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -96,26 +98,37 @@ __device__ __forceinline__ XChoice load_choice(const SkelArgs &a, const Geo &g) 
         c.p1 = perm[1];
         c.p2 = (g.d == 3) ? perm[2] : 2;
         if (a.norm_partials) {
-            __shared__ double sh[16], sinv[kMaxD];
-            for (int k = 0; k < g.d; ++k) {
-                double v = 0.0;
-                for (int b = threadIdx.x; b < a.norm_nblk; b += blockDim.x)
-                    v += a.norm_partials[(size_t)k * a.norm_nblk + b];
-                // fixed-order block sum (every block of every launch gets the same value)
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-                __syncthreads();
-                if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    double t = 0.0;
-                    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
-                    sinv[k] = (t > 0.0) ? 1.0 / sqrt(t) : 1.0;
-                }
+            // the three sums in one pass: their loads are issued together, one reduction in a
+            // fixed order (every block of every launch gets the same values)
+            __shared__ double sh[3][16];
+            const int nb = a.norm_nblk;
+            const bool three = (g.d == 3);
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+            for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+                v0 += a.norm_partials[b];
+                v1 += a.norm_partials[(size_t)nb + b];
+                if (three) v2 += a.norm_partials[2 * (size_t)nb + b];
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                v0 += __shfl_down(v0, off, 64);
+                v1 += __shfl_down(v1, off, 64);
+                v2 += __shfl_down(v2, off, 64);
+            }
+            if ((threadIdx.x & 63) == 0) {
+                sh[0][threadIdx.x >> 6] = v0;
+                sh[1][threadIdx.x >> 6] = v1;
+                sh[2][threadIdx.x >> 6] = v2;
             }
             __syncthreads();
-            c.inv0 = sinv[0];
-            c.inv1 = sinv[1];
-            c.inv2 = (g.d == 3) ? sinv[2] : 1.0;
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                t0 += sh[0][w];
+                t1 += sh[1][w];
+                t2 += sh[2][w];
+            }
+            c.inv0 = (t0 > 0.0) ? 1.0 / sqrt(t0) : 1.0;
+            c.inv1 = (t1 > 0.0) ? 1.0 / sqrt(t1) : 1.0;
+            c.inv2 = three ? ((t2 > 0.0) ? 1.0 / sqrt(t2) : 1.0) : 1.0;
         } else {
             c.inv0 = a.scal[kScalInvNorm + 0];
             c.inv1 = a.scal[kScalInvNorm + 1];
@@ -158,71 +171,77 @@ __device__ __forceinline__ void fine_axes_of(int k, int d, int &a, int &b) {
     }
 }
 
-// delta_k on the cross-point lines of each anisotropic mesh.
-// d = 2: lines[k][ck*Nc + ca].
-// d = 3: part A [ck][ca][ib] (Nc*Nc*Nf), part B [ck][ia][cb] (Nc*Nf*Nc), then part R (filled later).
+// d = 2: delta_k on the cross points of each anisotropic mesh, lines[k][ck*Nc + ca].
 __global__ __launch_bounds__(256) void k_crosspoints(Geo g, SkelArgs a) {
     if (a.gate && *a.gate) return;
     const XChoice ch = load_choice(a, g);
     const int k = blockIdx.y;
-    const int d = g.d, Nf = g.Nf, Nc = g.Nc, n = g.n;
-    int fa, fb;
-    fine_axes_of(k, d, fa, fb);
-    const unsigned mk = 1u << k;
+    const int Nf = g.Nf, Nc = g.Nc, n = g.n;
     const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
-    const long long nA = (d == 2) ? (long long)Nc * Nc : (long long)Nc * Nc * Nf;
-    const long long total = (d == 2) ? nA : 2 * nA;
-    const double *__restrict__ Xk = (k == 0) ? a.res[1] : (k == 1) ? a.res[2] : a.res[4];
+    const long long total = (long long)Nc * Nc;
+    const double *__restrict__ Xk = (k == 0) ? a.res[1] : a.res[2];
     for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
-        // the point: fine-axis coordinates (u, v) of mesh k and its coarse plane ck
-        int u, v, ck;
-        if (d == 2) {
-            const int ca = (int)(t % Nc);
-            ck = (int)(t / Nc);
-            u = (ca + 1) * n - 1;
-            v = 0;
-        } else if (t < nA) {
-            v = (int)(t % Nf);
-            const int ca = (int)((t / Nf) % Nc);
-            ck = (int)(t / ((long long)Nf * Nc));
-            u = (ca + 1) * n - 1;
-        } else {
-            const long long w = t - nA;
-            const int cb = (int)(w % Nc);
-            u = (int)((w / Nc) % Nf);
-            ck = (int)(w / ((long long)Nc * Nf));
-            v = (cb + 1) * n - 1;
-        }
-        const Pt p = mesh_pt(k, d, u, v, (ck + 1) * n - 1);
-        const unsigned S = coarse_set(p, d, n);
-        const double uh = crosspoint_value(a, g, p, S, ch);
-        // canonical offset in M_k: u + Nf (v + Nf ck) (d = 3), u + Nf ck (d = 2)
-        const long long ok = (d == 2) ? (long long)u + (long long)Nf * ck
-                                      : (long long)u + (long long)Nf * (v + (long long)Nf * ck);
-        const double uk = scale_k * Xk[ok];
-        a.lines[k][t] = uh - uk;
+        const int ca = (int)(t % Nc), ck = (int)(t / Nc);
+        const int u = (ca + 1) * n - 1;
+        const Pt p = mesh_pt(k, 2, u, 0, (ck + 1) * n - 1);
+        const double uh = crosspoint_value(a, g, p, coarse_set(p, 2, n), ch);
+        a.lines[k][t] = uh - scale_k * Xk[(long long)u + (long long)Nf * ck];
     }
 }
 
-// d = 3 only: R[ck][ca][ib] = A[ck][ca][ib] - sum_cb Sp[ib][cb] A[ck][ca][C[cb]], so that the Boolean
-// sum P_a delta + P_b delta - P_a P_b delta = P_a R + P_b delta costs O(N_c) per point.
-__global__ __launch_bounds__(256) void k_lines_residual(Geo g, SkelArgs a) {
+// d = 3 layout of the discrepancy lines of M_k: part A [ck][ca][ib] (Nc*Nc*Nf), part B
+// [ck][ia][cb] (Nc*Nf*Nc), then part R [ck][ca][ib] = A[ck][ca][ib] - sum_cb Sp[ib][cb]
+// A[ck][ca][C[cb]], so that the Boolean sum P_a delta + P_b delta - P_a P_b delta = P_a R + P_b delta
+// costs O(N_c) per point.
+// d = 3: the discrepancies of part A row by row -- one block per (c_k, c_a) row of N_f values, kept
+// in LDS -- together with that row's Boolean-sum remainder R (below), and part B by the remaining
+// blocks: one launch where k_crosspoints and k_lines_residual take two.
+__global__ __launch_bounds__(256) void k_crosspoints3(Geo g, SkelArgs a, int nrowblk) {
     if (a.gate && *a.gate) return;
+    const XChoice ch = load_choice(a, g);
+    __shared__ double row[1024];  // N_f <= 1023
     const int k = blockIdx.y;
     const int Nf = g.Nf, Nc = g.Nc, n = g.n;
+    const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
     const long long nA = (long long)Nc * Nc * Nf;
-    const double *__restrict__ A = a.lines[k];
-    double *__restrict__ R = a.lines[k] + 2 * nA;
-    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < nA; t += (long long)gridDim.x * 256) {
-        const int ib = (int)(t % Nf);
-        const long long rowbase = t - ib;  // (ck*Nc + ca)*Nf
-        double v = A[t];
-        if (on_coarse(ib, n)) {
-            R[t] = 0.0;
-            continue;
+    const double *__restrict__ Xk = (k == 0) ? a.res[1] : (k == 1) ? a.res[2] : a.res[4];
+    double *__restrict__ lk = (k == 0) ? a.lines[0] : (k == 1) ? a.lines[1] : a.lines[2];
+    auto delta = [&](int u, int v, int ck) -> double {
+        const Pt p = mesh_pt(k, 3, u, v, (ck + 1) * n - 1);
+        const double uh = crosspoint_value(a, g, p, coarse_set(p, 3, n), ch);
+        return uh - scale_k * Xk[(long long)u + (long long)Nf * (v + (long long)Nf * ck)];
+    };
+    if ((int)blockIdx.x < nrowblk) {
+        for (int rw = blockIdx.x; rw < Nc * Nc; rw += nrowblk) {
+            const int ca = rw % Nc, ck = rw / Nc;
+            const int u = (ca + 1) * n - 1;
+            double *__restrict__ A = lk + (long long)rw * Nf;
+            double *__restrict__ R = lk + 2 * nA + (long long)rw * Nf;
+            for (int ib = threadIdx.x; ib < Nf; ib += 256) {
+                const double dv = delta(u, ib, ck);
+                A[ib] = dv;
+                row[ib] = dv;
+            }
+            __syncthreads();
+            for (int ib = threadIdx.x; ib < Nf; ib += 256) {
+                double v = 0.0;
+                if (!on_coarse(ib, n)) {
+                    v = row[ib];
+                    for (int cb = 0; cb < Nc; ++cb) v -= a.Sp[(long long)ib * Nc + cb] * row[(cb + 1) * n - 1];
+                }
+                R[ib] = v;
+            }
+            __syncthreads();
         }
-        for (int cb = 0; cb < Nc; ++cb) v -= a.Sp[(long long)ib * Nc + cb] * A[rowbase + (cb + 1) * n - 1];
-        R[t] = v;
+        return;
+    }
+    // part B: [ck][ia][cb]
+    for (long long w = (long long)(blockIdx.x - nrowblk) * 256 + threadIdx.x; w < nA;
+         w += (long long)(gridDim.x - nrowblk) * 256) {
+        const int cb = (int)(w % Nc);
+        const int u = (int)((w / Nc) % Nf);
+        const int ck = (int)(w / ((long long)Nc * Nf));
+        lk[nA + w] = delta(u, (cb + 1) * n - 1, ck);
     }
 }
 
@@ -369,16 +388,17 @@ void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipSt
         return;
     }
     SkelArgs a = skel_args(p, mode, res);
-    const long long nA = (p.d == 2) ? (long long)p.Nc * p.Nc : (long long)p.Nc * p.Nc * p.Nf;
-    const long long total = (p.d == 2) ? nA : 2 * nA;
+    if (p.d == 3) {
+        const int nrow = std::min(p.Nc * p.Nc, 512);
+        long long nb = ((long long)p.Nc * p.Nc * p.Nf + 255) / 256;
+        if (nb > 1024) nb = 1024;
+        ASDSM_LAUNCH(k_crosspoints3, dim3((unsigned)(nrow + nb), 3, 1), dim3(256), 0, st, p.geo, a, nrow);
+        return;
+    }
+    const long long total = (long long)p.Nc * p.Nc;
     long long blocks = (total + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     ASDSM_LAUNCH(k_crosspoints, dim3((unsigned)blocks, p.d, 1), dim3(256), 0, st, p.geo, a);
-    if (p.d == 3) {
-        long long b2 = (nA + 255) / 256;
-        if (b2 > 1024) b2 = 1024;
-        ASDSM_LAUNCH(k_lines_residual, dim3((unsigned)b2, p.d, 1), dim3(256), 0, st, p.geo, a);
-    }
 }
 
 void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t st) {

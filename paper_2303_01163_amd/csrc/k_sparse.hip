@@ -176,7 +176,7 @@ static SkelPtrs skel_ptrs(double *const *v) {
 static int skel_tiles(const Plan &p) {
     const long long per = (long long)p.Nc * p.Nf * p.Nf;
     long long t = (per + 255) / 256;
-    const long long cap = p.max_blocks / 3;  // three meshes' partial sums fit the workspace
+    const long long cap = 1024;  // per mesh (grid-stride beyond); three meshes' partials fit easily
     if (t > cap) t = cap;
     return (int)(t < 1 ? 1 : t);
 }
