@@ -102,7 +102,7 @@ def test_stencil_pointwise_loops():
         assert abs(acc - Au[i, j, k]) <= 1e-10 * (1 + abs(acc))
 
 
-@pytest.mark.parametrize("d,L", [(2, 4), (2, 6), (3, 4)])
+@pytest.mark.parametrize("d,L", [(2, 4), (2, 6), (3, 4), (4, 3)])
 def test_q2_exact_residual(d, L):
     """Centred second differences are exact on quadratics and centred first differences on
     quadratics too, so a product of quadratics with its analytic source has a zero fine residual
@@ -134,7 +134,7 @@ def test_discretisation_order_h2():
 
 
 # ----------------------------------------------------------------------------- geometry
-@pytest.mark.parametrize("d,L,Lc", [(2, 6, 3), (3, 5, 2), (3, 4, 1)])
+@pytest.mark.parametrize("d,L,Lc", [(2, 6, 3), (3, 5, 2), (3, 4, 1), (4, 4, 2)])
 def test_mesh_relations(d, L, Lc):
     """Proposition 2.1 (sub-mesh relations, disjoint holes, holes = fine minus skeleton) and
     Proposition 2.4 (P P^T = I) for the d-dimensional family of Section 3.5."""
@@ -213,6 +213,37 @@ def test_boolean_sum_tensor_cubics():
     assert np.max(np.abs(ext[:, g.cidx] - f[:, g.cidx])) <= 1e-13
 
 
+def test_boolean_sum_three_axes():
+    """Three fine axes (the anisotropic meshes of d = 4): the transfinite extension is exact for
+    p(x) q(y) r(z) and for sums of such factors over one or two axes, with p, q, r cubics
+    vanishing at 0 and 1, and equals the data on every coarse plane of each axis."""
+    g = Grid(3, 4, 2)
+    Sp = spline_matrix(g)
+    x = np.arange(1, g.Nf + 1) * g.h
+    p = _cubic(x)
+    q = x * (1 - x) * (0.6 - x) * 2.0
+    r = x * (1 - x) * (x + 0.2)
+    c = g.cidx
+
+    def planes(f):
+        out = {}
+        for k in range(1, 4):
+            for T in itertools.combinations(range(3), k):
+                out[T] = f[np.ix_(*[c if j in T else np.arange(g.Nf) for j in range(3)])]
+        return out
+
+    pq = np.multiply.outer(p, q)
+    for f in (np.multiply.outer(pq, r), pq[:, :, None] + r[None, None, :],
+              p[:, None, None] + np.multiply.outer(q, r)[None, :, :]):
+        ext = boolean_sum_extend(planes(f), [0, 1, 2], Sp, g, f.shape)
+        assert np.max(np.abs(ext - f)) <= 1e-13
+    f = np.random.default_rng(5).standard_normal((g.Nf,) * 3)
+    ext = boolean_sum_extend(planes(f), [0, 1, 2], Sp, g, f.shape)
+    assert np.max(np.abs(ext[c, :, :] - f[c, :, :])) <= 1e-13
+    assert np.max(np.abs(ext[:, c, :] - f[:, c, :])) <= 1e-13
+    assert np.max(np.abs(ext[:, :, c] - f[:, :, c])) <= 1e-13
+
+
 # ----------------------------------------------------------------------------- cross points
 def _crosspoint_errors(d, L, Lc, P, uff):
     o = Oracle(d, P.alpha, P.beta, L, Lc)
@@ -249,7 +280,7 @@ def test_crosspoint_extrapolation_order_3d():
     assert e2[0] / e3[0] > 10 and e2[1] / e3[1] > 10, (e2, e3)
 
 
-@pytest.mark.parametrize("d,L", [(2, 5), (3, 4)])
+@pytest.mark.parametrize("d,L", [(2, 5), (3, 4), (4, 3)])
 def test_initial_guess_exact_on_q2(d, L):
     """Every mesh reproduces a Q2 solution exactly, so the extrapolated cross points, a zero
     discrepancy and the filler give u^(0) = u exactly."""
@@ -259,10 +290,10 @@ def test_initial_guess_exact_on_q2(d, L):
     assert np.max(np.abs(u0 - P.u_exact)) <= 1e-12 * np.max(np.abs(P.u_exact))
 
 
-@pytest.mark.parametrize("d,L,fam", [(2, 6, "sinprod2d"), (3, 4, "sinbump3d")])
+@pytest.mark.parametrize("d,L,fam", [(2, 6, "sinprod2d"), (3, 4, "sinbump3d"), (4, 3, "sinprod")])
 def test_filler_reproduces_fine_solution(d, L, fam):
     """Proposition 3.2(1): filling the holes of the skeleton of u_ff gives back u_ff."""
-    P = make_problem(fam, L, seed=4)
+    P = make_problem(fam, L, seed=4, d=d)
     o = Oracle(d, P.alpha, P.beta, L)
     uff = fine_direct_solve(d, P.alpha, P.beta, L, P.s, P.g)
     skel = np.where(o.grid.hole_mask(), 0.0, uff)
@@ -271,11 +302,11 @@ def test_filler_reproduces_fine_solution(d, L, fam):
 
 
 # ----------------------------------------------------------------------------- iteration
-@pytest.mark.parametrize("d,L,fam", [(2, 6, "sinprod2d"), (3, 4, "sinbump3d")])
+@pytest.mark.parametrize("d,L,fam", [(2, 6, "sinprod2d"), (3, 4, "sinbump3d"), (4, 3, "sinprod")])
 def test_iteration_properties(d, L, fam):
     """Proposition 3.2(2) / Remark 3.4: the residual vanishes on the holes for every iterate, and the
     line search s = argmin_{s>=0} ||b - A(u + s e)|| makes ||r_k|| non-increasing."""
-    P = make_problem(fam, L, seed=0)
+    P = make_problem(fam, L, seed=0, d=d)
     o = Oracle(d, P.alpha, P.beta, L, seed=11)
     res = o.solve(P.s, P.g, max_iter=8, rtol=0, stag_window=0, keep_iterates=True)
     b = o.fine_rhs(P.s, P.g)
