@@ -486,12 +486,6 @@ static void stencil_grid(const Geo &g, dim3 &grid) {
     grid = dim3((unsigned)(rgs < cap ? rgs : cap), (unsigned)xch, 1);
 }
 
-int stencil_blocks(const Geo &g) {
-    dim3 gr;
-    stencil_grid(g, gr);
-    return (int)(gr.x * gr.y);
-}
-
 void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf, double *out,
                 bool with_norm, hipStream_t st) {
     const MeshDesc &m = p.mesh[mask];

@@ -77,7 +77,6 @@ void launch_rhs(const Plan &p, unsigned mask, const double *s, const double *gf,
 void launch_update_residual(const Plan &p, const double *uin, const double *e, double *uout,
                             double *const *gather, int fin_mode, hipStream_t st);
 void launch_dots(const Plan &p, hipStream_t st);
-int stencil_blocks(const Geo &g);
 
 bool launch_gemm(const GemmJob &job, hipStream_t st);  // false: unsupported operand layout
 
