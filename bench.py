@@ -132,6 +132,7 @@ def parse():
     ap.add_argument("--learn-iters", type=int, default=200, help="step limit of the learned comparison")
     ap.add_argument("--d4-level", type=int, default=6,
                     help="fine level of the d = 4 side measurement (0 skips it)")
+    ap.add_argument("--d4-batch", type=int, default=8, help="members of the d = 4 batch (0 skips it)")
     return ap.parse_args()
 
 
@@ -234,6 +235,13 @@ def main():
     if skeleton:
         out["fine_loop_comparison"] = fine_loop(plan, s, g, kw, u, args.steps)
     out["autotune"] = tuned
+    # the device's own ceilings next to the datasheet peaks of the roofline
+    ceil = {"mfma_f64_tflops": asdsm.probe_mfma_f64(), "copy_tbps": asdsm.probe_copy()}
+    out["measured_ceilings"] = ceil
+    if roof["bound"] == "mfma":
+        roof["frac_of_measured"] = roof["achieved"] / ceil["mfma_f64_tflops"]
+    elif roof["bound"] == "hbm":
+        roof["frac_of_measured"] = roof["achieved"] / (1e3 * ceil["copy_tbps"])
     if not args.no_mixed:
         out["mixed_precision"] = mixed_precision(asdsm, make_problem, L, args, dev)
     if args.batch > 0:
@@ -272,12 +280,50 @@ def four_d(asdsm, make_problem, args, dev, seed=0, steps=3):
     ms = 1e3 * (time.perf_counter() - t0) / steps
     _, prof = plan.solve(s, g, u=u, profile=True, **kw)
     ue = torch.from_numpy(np.ascontiguousarray(P.u_exact.reshape(-1, order="F"))).to(dev)
-    return {"workload": f"asdsm-4d-{plan.n_f}^4-sinprod-seed{seed}", "coarse_level": Lc,
-            "fine_unknowns": plan.n_fine, "ms_per_solve": ms,
-            "fine_unknowns_per_s": plan.n_fine / (ms * 1e-3), "iterations": info["iterations"],
-            "status": info["status"], "rel_residual": info["rnorm"] / info["bnorm"],
-            "rel_error_vs_manufactured": float(torch.linalg.norm(u - ue) / torch.linalg.norm(ue)),
-            "plan_seconds": plan_s, "phase_ms": prof["phase_ms"], "phase_launches": prof["phase_launches"]}
+    res = {"workload": f"asdsm-4d-{plan.n_f}^4-sinprod-seed{seed}", "coarse_level": Lc,
+           "fine_unknowns": plan.n_fine, "ms_per_solve": ms,
+           "fine_unknowns_per_s": plan.n_fine / (ms * 1e-3), "iterations": info["iterations"],
+           "status": info["status"], "rel_residual": info["rnorm"] / info["bnorm"],
+           "rel_error_vs_manufactured": float(torch.linalg.norm(u - ue) / torch.linalg.norm(ue)),
+           "plan_seconds": plan_s, "phase_ms": prof["phase_ms"], "phase_launches": prof["phase_launches"]}
+    del plan, s, g, u, ue
+    if getattr(args, "d4_batch", 0) > 0:
+        res["batch"] = four_d_batch(asdsm, make_problem, args, dev, L, Lc)
+    return res
+
+
+def four_d_batch(asdsm, make_problem, args, dev, L, Lc, steps=2):
+    """The 4D configuration's batch: args.d4_batch independent 63^4 draws (seeds 100, 101, ...),
+    one after the other and as one batch (one graph replay advances every member two steps)."""
+    import torch
+    plans, ss, gs = [], [], []
+    for i in range(args.d4_batch):
+        P = make_problem("sinprod", L, seed=100 + i, d=4)
+        plans.append(asdsm.Plan(4, P.alpha, P.beta, L, Lc, seed=100 + i, device=0))
+        ss.append(torch.from_numpy(P.s_flat()).to(dev))
+        gs.append(torch.from_numpy(P.g_flat()).to(dev))
+    us = [torch.empty(p.n_fine, dtype=torch.float64, device=dev) for p in plans]
+    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
+    for p, s, g, u in zip(plans, ss, gs, us):
+        p.solve(s, g, u=u, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = [p.solve(s, g, u=u, **kw)[1] for p, s, g, u in zip(plans, ss, gs, us)]
+    torch.cuda.synchronize()
+    t_seq = 1e3 * (time.perf_counter() - t0) / steps
+    batch = asdsm.Batch(plans)
+    batch.solve(ss, gs, us, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, binfos = batch.solve(ss, gs, us, **kw)
+    torch.cuda.synchronize()
+    t_bat = 1e3 * (time.perf_counter() - t0) / steps
+    n = sum(p.n_fine for p in plans)
+    return {"members": len(plans), "fine_unknowns": n, "iterations": [i["iterations"] for i in binfos],
+            "ms_sequential": t_seq, "ms_batched": t_bat, "unknowns_per_s_sequential": n / (t_seq * 1e-3),
+            "unknowns_per_s_batched": n / (t_bat * 1e-3), "speedup": t_seq / t_bat}
 
 
 def fine_loop(plan, s, g, kw, u_sparse, steps):

@@ -203,6 +203,18 @@ int asdsm_set_tile(asdsm_plan_t plan, int tile);
  * Errors: ASDSM_E_ARG (NULL argument). */
 int asdsm_get_tile(asdsm_plan_t plan, int *tile);
 
+/* ---- measured ceilings of the device (for the roofline; the solver never calls these) ----
+ * asdsm_probe_mfma_f64: back-to-back v_mfma_f64_16x16x4f64 (eight independent chains per wave, 8
+ *   workgroups of 4 waves per CU) for `iters` rounds; *tflops = achieved FP64 matrix rate.
+ *   scratch: device buffer of at least asdsm_probe_mfma_scratch_bytes() bytes (caller-owned).
+ * asdsm_probe_copy: `reps` streaming copies src -> dst of `bytes` (rounded down to 16), 16-byte
+ *   accesses, four in flight per thread; *tbps = (read + written bytes) / time.  src, dst: device, 16-byte aligned, no overlap.
+ * Both run on hip_stream (may be NULL), synchronise, and return ASDSM_E_ARG for NULL pointers or
+ * non-positive counts, ASDSM_E_DEVICE if a HIP call fails. */
+size_t asdsm_probe_mfma_scratch_bytes(void);
+int asdsm_probe_mfma_f64(void *scratch, int iters, void *hip_stream, double *tflops);
+int asdsm_probe_copy(const void *src, void *dst, size_t bytes, int reps, void *hip_stream, double *tbps);
+
 /* Release the plan and its tables (not the workspace).  NULL is ignored. */
 void asdsm_destroy(asdsm_plan_t plan);
 

@@ -26,7 +26,8 @@ TILES = {"auto": 0, "32x32": 1, "64x32": 2, "32x64": 3, "64x64": 4, "plane": 5}
 EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_solve",
             "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error",
             "asdsm_batch_create", "asdsm_batch_solve", "asdsm_batch_destroy", "asdsm_autotune",
-            "asdsm_tile_name", "asdsm_set_tile", "asdsm_get_tile")
+            "asdsm_tile_name", "asdsm_set_tile", "asdsm_get_tile", "asdsm_probe_mfma_scratch_bytes",
+            "asdsm_probe_mfma_f64", "asdsm_probe_copy")
 # symbols declared in include/asdsm_learn.h
 EXPORTED_LEARN = ("asdsm_net_create", "asdsm_net_param_count", "asdsm_net_workspace_size",
                   "asdsm_net_set_workspace", "asdsm_net_params", "asdsm_net_forward",
@@ -90,6 +91,12 @@ def load_library():
     lib.asdsm_set_tile.restype = c_int
     lib.asdsm_get_tile.argtypes = [c_void_p, POINTER(c_int)]
     lib.asdsm_get_tile.restype = c_int
+    lib.asdsm_probe_mfma_scratch_bytes.argtypes = []
+    lib.asdsm_probe_mfma_scratch_bytes.restype = c_size_t
+    lib.asdsm_probe_mfma_f64.argtypes = [c_void_p, c_int, c_void_p, POINTER(c_double)]
+    lib.asdsm_probe_mfma_f64.restype = c_int
+    lib.asdsm_probe_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_int, c_void_p, POINTER(c_double)]
+    lib.asdsm_probe_copy.restype = c_int
     lib.asdsm_batch_create.argtypes = [POINTER(c_void_p), POINTER(c_void_p), c_int]
     lib.asdsm_batch_create.restype = c_int
     lib.asdsm_batch_solve.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
@@ -470,3 +477,32 @@ def solve_learned(plan, net, s, g, u=None, factor=4.0, max_iter=50, rtol=1e-10, 
     info = _info(rc, st, hist, steps, profile)
     info["accepted"] = acc.value
     return u, info
+
+
+def probe_mfma_f64(iters=20000, device=0):
+    """Measured FP64 MFMA rate of the device in TFLOP/s (asdsm_probe_mfma_f64)."""
+    import torch
+    lib = load_library()
+    dev = torch.device("cuda", device)
+    scratch = torch.empty(int(lib.asdsm_probe_mfma_scratch_bytes()), dtype=torch.uint8, device=dev)
+    out = c_double()
+    st = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        _check(lib.asdsm_probe_mfma_f64(c_void_p(scratch.data_ptr()), int(iters), c_void_p(st.cuda_stream),
+                                        byref(out)))
+    return out.value
+
+
+def probe_copy(nbytes=1 << 30, reps=5, device=0):
+    """Measured streaming-copy rate of the device in TB/s, reads plus writes (asdsm_probe_copy)."""
+    import torch
+    lib = load_library()
+    dev = torch.device("cuda", device)
+    src = torch.zeros(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    out = c_double()
+    st = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        _check(lib.asdsm_probe_copy(c_void_p(src.data_ptr()), c_void_p(dst.data_ptr()), c_size_t(src.numel() * 8),
+                                    int(reps), c_void_p(st.cuda_stream), byref(out)))
+    return out.value

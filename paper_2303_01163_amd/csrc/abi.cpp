@@ -1639,6 +1639,25 @@ int asdsm_autotune(asdsm_plan_t plan, int repeats, int *tile, double *ms_per_sol
 
 const char *asdsm_tile_name(int tile) { return gemm_tile_name(tile); }
 
+size_t asdsm_probe_mfma_scratch_bytes(void) { return probe_mfma_scratch_bytes(); }
+
+int asdsm_probe_mfma_f64(void *scratch, int iters, void *hip_stream, double *tflops) {
+    if (!scratch || !tflops || iters < 1) return fail(ASDSM_E_ARG, "probe: NULL pointer or iters < 1");
+    if (int rc = probe_mfma_f64((double *)scratch, iters, (hipStream_t)hip_stream, tflops))
+        return fail(rc, "probe: HIP call failed");
+    set_error("");
+    return ASDSM_OK;
+}
+
+int asdsm_probe_copy(const void *src, void *dst, size_t bytes, int reps, void *hip_stream, double *tbps) {
+    if (!src || !dst || !tbps || reps < 1 || bytes < 16) return fail(ASDSM_E_ARG, "probe: bad arguments");
+    if ((((uintptr_t)src) | ((uintptr_t)dst)) & 15u) return fail(ASDSM_E_ARG, "probe: buffers must be 16-byte aligned");
+    if (int rc = probe_copy((const double *)src, (double *)dst, bytes, reps, (hipStream_t)hip_stream, tbps))
+        return fail(rc, "probe: HIP call failed");
+    set_error("");
+    return ASDSM_OK;
+}
+
 static_assert(ASDSM_TILE_AUTO == kTileAuto && ASDSM_TILE_32X32 == kTile32x32 && ASDSM_TILE_64X32 == kTile64x32 &&
                   ASDSM_TILE_32X64 == kTile32x64 && ASDSM_TILE_64X64 == kTile64x64 && ASDSM_TILE_PLANE == kTilePlane,
               "tile codes of the C ABI");

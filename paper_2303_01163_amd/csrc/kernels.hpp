@@ -96,6 +96,11 @@ struct PlaneJob {
 constexpr int kPlaneMaxNf = 256;  // largest N_f of k_plane2 (16 row tiles of 16, two per wave)
 bool launch_plane2(const PlaneJob &job, hipStream_t st);  // false: N_f too large
 void plane_prepare();  // once per process, device current: the kernels' dynamic LDS limit
+
+// Measured ceilings (k_probe.hip): FP64 MFMA rate and streaming-copy rate of the device.
+size_t probe_mfma_scratch_bytes();
+int probe_mfma_f64(double *scratch, int iters, hipStream_t st, double *tflops);
+int probe_copy(const double *src, double *dst, size_t bytes, int reps, hipStream_t st, double *tbps);
 // FP32 MFMA variant: A read as double (a_f64) or float, B float, C written as double (c_f64) or
 // float; the GemmJob pointers are reinterpreted accordingly.
 bool launch_gemm32(const GemmJob &job, bool a_f64, bool c_f64, hipStream_t st);

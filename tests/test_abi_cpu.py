@@ -15,7 +15,7 @@ def _declared(path=None):
     names = set()
     for h in ([path] if path else HEADERS):
         text = h.read_text()
-        names |= set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(asdsm_\w+)\s*\(", text, re.M))
+        names |= set(re.findall(r"^\s*(?:int|void|size_t|const char \*)\s*\*?\s*(asdsm_\w+)\s*\(", text, re.M))
     return sorted(names)
 
 

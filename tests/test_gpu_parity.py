@@ -437,6 +437,22 @@ def test_batch_matches_individual_solves(torch_dev, precision):
             assert info["rnorm"] == i_ref["rnorm"]
 
 
+def test_probes_measure_plausible_ceilings(torch_dev):
+    """The measured ceilings the bench reports next to the datasheet peaks (78.6 TFLOP/s FP64
+    matrix, 8 TB/s HBM): positive and below them, and argument errors rejected."""
+    from paper_2303_01163_amd import asdsm
+    tf = asdsm.probe_mfma_f64(iters=2000)
+    tb = asdsm.probe_copy(nbytes=1 << 28, reps=3)
+    _say("   probes: FP64 MFMA %.1f TFLOP/s, copy %.2f TB/s" % (tf, tb))
+    assert 5.0 < tf < 80.0
+    assert 0.5 < tb < 8.5
+    lib = asdsm.load_library()
+    import ctypes
+    out = ctypes.c_double()
+    assert lib.asdsm_probe_mfma_f64(None, 10, None, ctypes.byref(out)) == -1
+    assert lib.asdsm_probe_copy(None, None, 1024, 1, None, ctypes.byref(out)) == -1
+
+
 def test_autotuned_plan_keeps_parity(torch_dev):
     """After the autotuner has picked a transform tile shape, the iterates still match the oracle."""
     P = make_problem("sinbump3d", 6, seed=4)
