@@ -627,6 +627,256 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Filler for d = 3, 4 with small holes (n - 1 = NH in {1, 3, 7}), the same hole solve as k_filler
+// with every size known at compile time.  The hole sits in one LDS buffer (no second buffer):
+// each transform and the line elimination go line by line in place -- a lane loads a line of NH
+// values into registers, maps it and stores it back -- so twice as many holes fit on a CU.  The
+// global loads of the right-hand side and of the skeleton values written with the tile are issued
+// together (fully unrolled loops of constant length) instead of one wait per loop trip.
+// ---------------------------------------------------------------------------------------------
+constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
+
+// Offset in the canonical layout of M_{j} (fine axes in increasing order, then coarse axis j) of
+// the point with fine coordinates i[] off axis j and coarse index cj on axis j.
+template <int D, int J>
+__device__ __forceinline__ long long skel_offset(const int (&i)[D], int cj, int Nf) {
+    long long off = cj, mul = 1;
+    for (int q = 0; q < D - 1; ++q) mul *= Nf;
+    off *= mul;
+    long long s = 1;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        if (q == J) continue;
+        off += (long long)i[q] * s;
+        s *= Nf;
+    }
+    return off;
+}
+
+// Transform of every line along axis J of the hole buffer by the NH x NH matrix M (out, in).  A
+// lane holds all its lines at once (NR of them), so each matrix entry is read once per lane.
+template <int D, int NH, int J>
+__device__ __forceinline__ void hole_lines_map(double *buf, const double *M) {
+    constexpr int N = ipow_c(NH, D), NL = N / NH, SJ = ipow_c(NH, J), NR = (NL + 255) / 256;
+    double x[NR][NH];
+    int base[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int ln = min((int)threadIdx.x + 256 * r, NL - 1);
+        base[r] = ln % SJ + (ln / SJ) * SJ * NH;
+#pragma unroll
+        for (int l = 0; l < NH; ++l) x[r][l] = buf[base[r] + l * SJ];
+    }
+    __syncthreads();  // lanes whose second line is clamped read a line another lane rewrites
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+        double acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+#pragma unroll
+        for (int l = 0; l < NH; ++l) {
+            const double w = M[m * NH + l];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r] += w * x[r][l];
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if ((int)threadIdx.x + 256 * r < NL) buf[base[r] + m * SJ] = acc[r];
+    }
+}
+
+// Tridiagonal solve of every line along axis J (the line axis) with the diagonal shifted by the
+// eigenvalues of the transformed axes at the line's modes.
+template <int D, int NH, int J>
+__device__ __forceinline__ void hole_lines_solve(double *buf, const double (*mu)[NH], Tri t) {
+    constexpr int N = ipow_c(NH, D), NL = N / NH, SJ = ipow_c(NH, J), NR = (NL + 255) / 256;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int ln = (int)threadIdx.x + 256 * r;
+        if (ln >= NL) continue;
+        const int base = ln % SJ + (ln / SJ) * SJ * NH;
+        double sigma = 0.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            if (q == J) continue;
+            sigma += mu[q][(base / ipow_c(NH, q)) % NH];
+        }
+        const double diag = t.b + sigma;
+        double x[NH], cp[NH];
+#pragma unroll
+        for (int l = 0; l < NH; ++l) x[l] = buf[base + l * SJ];
+        double inv = 1.0 / diag;
+        cp[0] = t.c * inv;
+        x[0] *= inv;
+#pragma unroll
+        for (int c = 1; c < NH; ++c) {
+            inv = 1.0 / (diag - t.a * cp[c - 1]);
+            cp[c] = t.c * inv;
+            x[c] = (x[c] - t.a * x[c - 1]) * inv;
+        }
+#pragma unroll
+        for (int c = NH - 2; c >= 0; --c) x[c] -= cp[c] * x[c + 1];
+#pragma unroll
+        for (int l = 0; l < NH; ++l) buf[base + l * SJ] = x[l];
+    }
+}
+
+template <int D, int NH>
+__device__ __forceinline__ void hole_map_axis(double *buf, const double *M, int j) {
+    switch (j) {
+        case 0: hole_lines_map<D, NH, 0>(buf, M); break;
+        case 1: hole_lines_map<D, NH, 1>(buf, M); break;
+        case 2: hole_lines_map<D, NH, 2>(buf, M); break;
+        default: if constexpr (D == 4) hole_lines_map<D, NH, 3>(buf, M); break;
+    }
+}
+
+template <int D, int NH>
+__global__ __launch_bounds__(256) void k_filler_lines(Geo g, FillArgs a) {
+    if (a.gate && *a.gate) return;
+    constexpr int n = NH + 1, N = ipow_c(NH, D), NT = ipow_c(n, D);
+    constexpr int K1 = (N + 255) / 256, K5 = (NT + 255) / 256;
+    __shared__ double buf[N];
+    __shared__ double sW[D][NH * NH], sV[D][NH * NH], smu[D][NH];
+    const int Nf = g.Nf, Nc = g.Nc, tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        for (int e = tid; e < NH * NH; e += 256) {
+            sW[j][e] = a.W[j][e];
+            sV[j][e] = a.V[j][e];
+        }
+        if (tid < NH) smu[j][tid] = a.mu[j][tid];
+    }
+    int tt[D];
+    {
+        int rem = blockIdx.x;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            tt[j] = rem % (Nc + 1);
+            rem /= (Nc + 1);
+        }
+    }
+    long long fs[D];
+    fs[0] = 1;
+#pragma unroll
+    for (int j = 1; j < D; ++j) fs[j] = fs[j - 1] * Nf;
+    // 1) hole right-hand side: b_ff (initial guess) minus the coupling to the skeleton faces, in
+    // batches of KA points per lane
+    constexpr int KA = K1 < 5 ? K1 : 5;
+#pragma unroll 1
+    for (int kc = 0; kc < K1; kc += KA) {
+        double v[KA];
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {
+            const int o = tid + 256 * (kc + k);
+            v[k] = 0.0;
+            if (o < N) {
+                int i[D];
+                long long f = 0;
+                int rem = o;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    i[j] = n * tt[j] + rem % NH;
+                    rem /= NH;
+                    f += i[j] * fs[j];
+                }
+                double s = a.bff ? a.bff[f] : 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const int l = i[j] - n * tt[j];
+                    const double *sk = a.skel[j];
+                    long long off = -1;
+                    double cf = 0.0;
+                    if (l == 0 && tt[j] > 0) {
+                        cf = g.fine[j].a;
+                        off = (j == 0) ? skel_offset<D, 0>(i, tt[j] - 1, Nf)
+                            : (j == 1) ? skel_offset<D, 1>(i, tt[j] - 1, Nf)
+                            : (j == 2) ? skel_offset<D, 2>(i, tt[j] - 1, Nf)
+                                       : skel_offset<D, D - 1>(i, tt[j] - 1, Nf);
+                    }
+                    if (l == NH - 1 && tt[j] < Nc) {
+                        // NH = 1: both faces of the same point; the upper one is added below
+                        if (off >= 0) s -= cf * sk[off];
+                        cf = g.fine[j].c;
+                        off = (j == 0) ? skel_offset<D, 0>(i, tt[j], Nf)
+                            : (j == 1) ? skel_offset<D, 1>(i, tt[j], Nf)
+                            : (j == 2) ? skel_offset<D, 2>(i, tt[j], Nf)
+                                       : skel_offset<D, D - 1>(i, tt[j], Nf);
+                    }
+                    if (off >= 0) s -= cf * sk[off];
+                }
+                v[k] = s;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KA; ++k)
+            if (tid + 256 * (kc + k) < N) buf[tid + 256 * (kc + k)] = v[k];
+    }
+    __syncthreads();
+    // 2) forward transforms, 3) line elimination, 4) backward transforms
+    for (int q = 0; q < a.ntr; ++q) {
+        hole_map_axis<D, NH>(buf, sW[a.tr[q]], a.tr[q]);
+        __syncthreads();
+    }
+    switch (a.line_axis) {
+        case 0: hole_lines_solve<D, NH, 0>(buf, smu, g.fine[0]); break;
+        case 1: hole_lines_solve<D, NH, 1>(buf, smu, g.fine[1]); break;
+        case 2: hole_lines_solve<D, NH, 2>(buf, smu, g.fine[2]); break;
+        default: if constexpr (D == 4) hole_lines_solve<D, NH, 3>(buf, smu, g.fine[3]); break;
+    }
+    __syncthreads();
+    for (int q = a.ntr - 1; q >= 0; --q) {
+        hole_map_axis<D, NH>(buf, sV[a.tr[q]], a.tr[q]);
+        __syncthreads();
+    }
+    // 5) the whole tile: hole values and the skeleton planes above it (merged values), in batches
+    // of KB points per lane whose loads are in flight together
+    constexpr int KB = K5 < 8 ? K5 : 8;
+#pragma unroll 1
+    for (int kc = 0; kc < K5; kc += KB) {
+        double w[KB];
+        long long fo[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int o = tid + 256 * (kc + k);
+            w[k] = 0.0;
+            fo[k] = -1;
+            if (o < NT) {
+                int i[D], l[D];
+                bool inside = true, hole = true;
+                long long f = 0;
+                int lo = 0, rem = o;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    l[j] = rem % n;
+                    rem /= n;
+                    i[j] = n * tt[j] + l[j];
+                    inside = inside && i[j] < Nf;
+                    hole = hole && l[j] < NH;
+                    f += i[j] * fs[j];
+                    lo += l[j] * ipow_c(NH, j);
+                }
+                if (inside) {
+                    fo[k] = f;
+                    if (hole) {
+                        w[k] = buf[lo];
+                    } else {
+                        // the first axis whose coordinate lies on a coarse plane
+                        if (l[0] == NH) w[k] = a.skel[0][skel_offset<D, 0>(i, tt[0], Nf)];
+                        else if (l[1] == NH) w[k] = a.skel[1][skel_offset<D, 1>(i, tt[1], Nf)];
+                        else if (D == 3 || l[2] == NH) w[k] = a.skel[2][skel_offset<D, 2>(i, tt[2], Nf)];
+                        else w[k] = a.skel[D - 1][skel_offset<D, D - 1>(i, tt[D - 1], Nf)];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+            if (fo[k] >= 0) a.out[fo[k]] = w[k];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Filler for d = 3 with 15^3 holes (n = 16) on MFMA.  The hole is padded to 16^3 in one LDS buffer
 // with strides (1, 17, 289): for every axis the 16 rows of an MFMA operand fragment and the 16
 // columns of a result fragment fall in distinct banks.  A transform along axis j is an in-place GEMM
@@ -839,6 +1089,20 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
             ASDSM_LAUNCH((k_filler_mfma3<false>), grid, blk, 0, st, p.geo, a);
         else
             ASDSM_LAUNCH((k_filler_mfma3<true>), grid, blk, 0, st, p.geo, a);
+        return;
+    }
+    if (!adj_only && (d == 3 || d == 4) && (nh == 1 || nh == 3 || nh == 7)) {
+#define ASDSM_FILL_LINES(DD, NHV) ASDSM_LAUNCH((k_filler_lines<DD, NHV>), grid, blk, 0, st, p.geo, a)
+        if (d == 3) {
+            if (nh == 1) ASDSM_FILL_LINES(3, 1);
+            else if (nh == 3) ASDSM_FILL_LINES(3, 3);
+            else ASDSM_FILL_LINES(3, 7);
+        } else {
+            if (nh == 1) ASDSM_FILL_LINES(4, 1);
+            else if (nh == 3) ASDSM_FILL_LINES(4, 3);
+            else ASDSM_FILL_LINES(4, 7);
+        }
+#undef ASDSM_FILL_LINES
         return;
     }
 #define ASDSM_FILL(DD, NHV) ASDSM_LAUNCH((k_filler<DD, NHV>), grid, blk, lds, st, p.geo, a)

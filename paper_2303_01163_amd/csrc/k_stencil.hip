@@ -198,22 +198,27 @@ __global__ __launch_bounds__(256) void k_dots(Geo g, const double *__restrict__ 
 // Neighbours outside the domain enter as zeros (the Dirichlet data live in b).
 // ---------------------------------------------------------------------------------------------
 struct Tile3 {
-    int xtn, ytn, zcn;
+    int xtn, ytn, zcn, wn;  // wn: N_f at d = 4 (one x_4 index per tile), 1 at d = 3
 };
 
-__device__ __forceinline__ bool tile3_of(const Tile3 &t, int &xt, int &yt, int &zc) {
-    const int total = t.xtn * t.ytn * t.zcn;
+// d = 4 runs the same tiles over x_1..x_3 for every x_4 index w, with w fastest in the tile order:
+// the x_4 neighbours of a tile are the tiles running beside it on the same XCD, so those loads
+// (the only ones not covered by the registers and the LDS plane) are served by its L2.
+__device__ __forceinline__ bool tile3_of(const Tile3 &t, int &xt, int &yt, int &zc, int &w) {
+    const int total = t.xtn * t.ytn * t.zcn * t.wn;
     const int per = (total + 7) / 8;
     const int q = blockIdx.x >> 3;
-    const int tile = (blockIdx.x & 7) * per + q;
+    int tile = (blockIdx.x & 7) * per + q;
     if (q >= per || tile >= total) return false;
+    w = tile % t.wn;
+    tile /= t.wn;
     xt = tile % t.xtn;
     yt = (tile / t.xtn) % t.ytn;
     zc = tile / (t.xtn * t.ytn);
     return true;
 }
 
-template <int ROWS, int ZC>
+template <int D, int ROWS, int ZC>
 __global__ __launch_bounds__(64 * ROWS) void k_update_residual3(
     Geo g, Tile3 tl, const double *__restrict__ uin, const double *__restrict__ e,
     const double *__restrict__ scal, const double *__restrict__ b, double *__restrict__ uout,
@@ -222,15 +227,16 @@ __global__ __launch_bounds__(64 * ROWS) void k_update_residual3(
     __shared__ double pl[2][ROWS + 2][66];
     const int Nf = g.Nf, n = g.n;
     double acc = 0.0;
-    int xt, yt, zc;
-    if (tile3_of(tl, xt, yt, zc)) {
+    int xt, yt, zc, w;
+    if (tile3_of(tl, xt, yt, zc, w)) {
         const double s = e ? scal[kScalStep] : 0.0;
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
         const int i0 = xt * 64 + tx, i1 = yt * ROWS + ty;
         const bool act = i0 < Nf && i1 < Nf;
-        const int sy = Nf, sz = Nf * Nf;
-        const int base = min(i0, Nf - 1) + sy * min(i1, Nf - 1);
+        const int sy = Nf, sz = Nf * Nf, sw = Nf * Nf * Nf;
+        const int base = min(i0, Nf - 1) + sy * min(i1, Nf - 1) + (D == 4 ? sw * w : 0);
         const int z0 = zc * ZC, z1 = min(Nf, z0 + ZC);
+        const bool wlo = D == 4 && act && w > 0, whi = D == 4 && act && w < Nf - 1;
         // halo of the plane tile: row below, row above, column left, column right
         const int h = threadIdx.x;
         int hx = -1, hy = -1, hlx = 0, hly = 0;
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(64 * ROWS) void k_update_residual3(
         }
         const bool hload = h < 128 + 2 * ROWS;
         const bool hval = hx >= 0 && hx < Nf && hy >= 0 && hy < Nf;
-        const int hbase = hval ? hx + sy * hy : 0;
+        const int hbase = hval ? hx + sy * hy + (D == 4 ? sw * w : 0) : 0;
         auto ldu = [&](bool ok, int q) -> double { return ok ? uin[q] : 0.0; };
         auto lde = [&](bool ok, int q) -> double { return (ok && e) ? e[q] : 0.0; };
         double vprev = 0.0, vcur = 0.0, hcur = 0.0;
@@ -256,15 +262,27 @@ __global__ __launch_bounds__(64 * ROWS) void k_update_residual3(
         double u1 = ldu(ok1, base + (z0 + 1) * sz), e1 = lde(ok1, base + (z0 + 1) * sz);
         double hu1 = ldu(hok1, hbase + (z0 + 1) * sz), he1 = lde(hok1, hbase + (z0 + 1) * sz);
         double b1 = act ? b[base + z0 * sz] : 0.0;
+        // x_4 neighbours of the current plane (d = 4), loaded one plane ahead
+        double wl = 0.0, wh = 0.0;
+        if (D == 4) {
+            wl = ldu(wlo, base + z0 * sz - sw) + s * lde(wlo, base + z0 * sz - sw);
+            wh = ldu(whi, base + z0 * sz + sw) + s * lde(whi, base + z0 * sz + sw);
+        }
         int buf = 0;
         pl[0][ty + 1][tx + 1] = vcur;
         if (hload) pl[0][hly][hlx] = hcur;
         __syncthreads();
         const bool g0 = on_coarse(i0, n), g1 = on_coarse(i1, n);
         const int k0 = coarse_of(i0, n), k1 = coarse_of(i1, n);
-        const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
+        const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b + (D == 4 ? g.fine[3].b : 0.0);
         for (int z = z0; z < z1; ++z) {
             const int p = base + z * sz;
+            double wl1 = 0.0, wh1 = 0.0;
+            if (D == 4) {
+                const bool nz = z + 1 < z1;
+                wl1 = ldu(wlo && nz, p + sz - sw) + s * lde(wlo && nz, p + sz - sw);
+                wh1 = ldu(whi && nz, p + sz + sw) + s * lde(whi && nz, p + sz + sw);
+            }
             const bool ok2 = act && z + 2 < Nf, hok2 = hval && z + 2 < z1;
             const double u2 = ldu(ok2, p + 2 * sz), e2 = lde(ok2, p + 2 * sz);
             const double hu2 = ldu(hok2, hbase + (z + 2) * sz), he2 = lde(hok2, hbase + (z + 2) * sz);
@@ -278,16 +296,29 @@ __global__ __launch_bounds__(64 * ROWS) void k_update_residual3(
             au += g.fine[1].c * pl[buf][ty + 2][tx + 1];
             au += g.fine[2].a * vprev;
             au += g.fine[2].c * vnext;
+            if (D == 4) {
+                au += g.fine[3].a * wl;
+                au += g.fine[3].c * wh;
+            }
             const double rr = b1 - au;
             if (act) {
                 r[p] = rr;
                 if (e) uout[p] = vcur;
                 acc += rr * rr;
                 // gather onto the anisotropic submeshes (canonical layouts)
-                if (g0) boxes.p[0][i1 + sy * z + sz * k0] = rr;
-                if (g1) boxes.p[1][i0 + sy * z + sz * k1] = rr;
-                if (on_coarse(z, n)) boxes.p[2][i0 + sy * i1 + sz * coarse_of(z, n)] = rr;
+                if (D == 3) {
+                    if (g0) boxes.p[0][i1 + sy * z + sz * k0] = rr;
+                    if (g1) boxes.p[1][i0 + sy * z + sz * k1] = rr;
+                    if (on_coarse(z, n)) boxes.p[2][i0 + sy * i1 + sz * coarse_of(z, n)] = rr;
+                } else {
+                    if (g0) boxes.p[0][i1 + sy * z + sz * w + sw * k0] = rr;
+                    if (g1) boxes.p[1][i0 + sy * z + sz * w + sw * k1] = rr;
+                    if (on_coarse(z, n)) boxes.p[2][i0 + sy * i1 + sz * w + sw * coarse_of(z, n)] = rr;
+                    if (on_coarse(w, n)) boxes.p[3][i0 + sy * i1 + sz * z + sw * coarse_of(w, n)] = rr;
+                }
             }
+            wl = wl1;
+            wh = wh1;
             vprev = vcur;
             vcur = vnext;
             u1 = u2; e1 = e2; hu1 = hu2; he1 = he2; b1 = b2;
@@ -304,7 +335,7 @@ __global__ __launch_bounds__(64 * ROWS) void k_update_residual3(
 // Line-search products q = A e, <r, q>, <q, q> with the same z-marching tiles as the update pass:
 // the current plane of e with its one-point halo in LDS (double-buffered), the x_3 neighbours in
 // registers, and the next plane's e, halo and r loaded one step ahead.
-template <int ROWS, int ZC>
+template <int D, int ROWS, int ZC>
 __global__ __launch_bounds__(64 * ROWS) void k_dots3(Geo g, Tile3 tl, const double *__restrict__ e,
                                                      const double *__restrict__ r, double *partials,
                                                      const int *gate) {
@@ -312,14 +343,15 @@ __global__ __launch_bounds__(64 * ROWS) void k_dots3(Geo g, Tile3 tl, const doub
     __shared__ double pl[2][ROWS + 2][66];
     const int Nf = g.Nf;
     double rq = 0.0, qq = 0.0;
-    int xt, yt, zc;
-    if (tile3_of(tl, xt, yt, zc)) {
+    int xt, yt, zc, w;
+    if (tile3_of(tl, xt, yt, zc, w)) {
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
         const int i0 = xt * 64 + tx, i1 = yt * ROWS + ty;
         const bool act = i0 < Nf && i1 < Nf;
-        const int sy = Nf, sz = Nf * Nf;
-        const int base = min(i0, Nf - 1) + sy * min(i1, Nf - 1);
+        const int sy = Nf, sz = Nf * Nf, sw = Nf * Nf * Nf;
+        const int base = min(i0, Nf - 1) + sy * min(i1, Nf - 1) + (D == 4 ? sw * w : 0);
         const int z0 = zc * ZC, z1 = min(Nf, z0 + ZC);
+        const bool wlo = D == 4 && act && w > 0, whi = D == 4 && act && w < Nf - 1;
         // halo of the plane tile: row below, row above, column left, column right
         const int h = threadIdx.x;
         int hx = -1, hy = -1, hlx = 0, hly = 0;
@@ -334,20 +366,24 @@ __global__ __launch_bounds__(64 * ROWS) void k_dots3(Geo g, Tile3 tl, const doub
         }
         const bool hload = h < 128 + 2 * ROWS;
         const bool hval = hx >= 0 && hx < Nf && hy >= 0 && hy < Nf;
-        const int hbase = hval ? hx + sy * hy : 0;
+        const int hbase = hval ? hx + sy * hy + (D == 4 ? sw * w : 0) : 0;
         double vprev = (act && z0 > 0) ? e[base + (z0 - 1) * sz] : 0.0;
         double vcur = act ? e[base + z0 * sz] : 0.0;
         const double hcur = hval ? e[hbase + z0 * sz] : 0.0;
         double v1 = (act && z0 + 1 < Nf) ? e[base + (z0 + 1) * sz] : 0.0;
         double hv1 = (hval && z0 + 1 < z1) ? e[hbase + (z0 + 1) * sz] : 0.0;
         double r1 = act ? r[base + z0 * sz] : 0.0;
+        double wl = wlo ? e[base + z0 * sz - sw] : 0.0, wh = whi ? e[base + z0 * sz + sw] : 0.0;
         int buf = 0;
         pl[0][ty + 1][tx + 1] = vcur;
         if (hload) pl[0][hly][hlx] = hcur;
         __syncthreads();
-        const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
+        const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b + (D == 4 ? g.fine[3].b : 0.0);
         for (int z = z0; z < z1; ++z) {
             const int p = base + z * sz;
+            const bool nz = z + 1 < z1;
+            const double wl1 = (wlo && nz) ? e[p + sz - sw] : 0.0;
+            const double wh1 = (whi && nz) ? e[p + sz + sw] : 0.0;
             // one step ahead: e two planes up (the next plane's upper neighbour), its halo, next r
             const double v2 = (act && z + 2 < Nf) ? e[p + 2 * sz] : 0.0;
             const double hv2 = (hval && z + 2 < z1) ? e[hbase + (z + 2) * sz] : 0.0;
@@ -359,6 +395,12 @@ __global__ __launch_bounds__(64 * ROWS) void k_dots3(Geo g, Tile3 tl, const doub
             q += g.fine[1].c * pl[buf][ty + 2][tx + 1];
             q += g.fine[2].a * vprev;
             q += g.fine[2].c * v1;
+            if (D == 4) {
+                q += g.fine[3].a * wl;
+                q += g.fine[3].c * wh;
+            }
+            wl = wl1;
+            wh = wh1;
             if (act) {
                 rq += r1 * q;
                 qq += q * q;
@@ -501,7 +543,8 @@ static Tile3 tile3(const Geo &g, int rows, int zc, int &blocks) {
     t.xtn = (g.Nf + 63) / 64;
     t.ytn = (g.Nf + rows - 1) / rows;
     t.zcn = (g.Nf + zc - 1) / zc;
-    const long long total = (long long)t.xtn * t.ytn * t.zcn;
+    t.wn = (g.d == 4) ? g.Nf : 1;
+    const long long total = (long long)t.xtn * t.ytn * t.zcn * t.wn;
     blocks = (int)(8 * ((total + 7) / 8));
     return t;
 }
@@ -510,6 +553,16 @@ void launch_update_residual(const Plan &p, const double *uin, const double *e, d
                             double *const *gather, int fin_mode, hipStream_t st) {
     BoxPtrs bx;
     for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? gather[1u << k] : nullptr;
+    int blocks = 0;
+    if (p.d == 4) {
+        const Tile3 t = tile3(p.geo, 8, 8, blocks);
+        if (blocks <= p.max_blocks) {
+            ASDSM_LAUNCH((k_update_residual3<4, 8, 8>), dim3(blocks), dim3(512), 0, st, p.geo, t, uin, e,
+                         p.ws.scal, p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
+            launch_finalize(p, blocks, fin_mode, 1, st);
+            return;
+        }
+    }
     if (p.d == 2 || p.d == 4) {
         dim3 grid;
         stencil_grid(p.geo, grid);
@@ -522,20 +575,29 @@ void launch_update_residual(const Plan &p, const double *uin, const double *e, d
         launch_finalize(p, (int)(grid.x * grid.y), fin_mode, 1, st);
         return;
     }
-    int blocks = 0;
     if (p.Nf >= 255) {
         const Tile3 t = tile3(p.geo, 16, 16, blocks);
-        ASDSM_LAUNCH((k_update_residual3<16, 16>), dim3(blocks), dim3(1024), 0, st, p.geo, t, uin, e,
+        ASDSM_LAUNCH((k_update_residual3<3, 16, 16>), dim3(blocks), dim3(1024), 0, st, p.geo, t, uin, e,
                      p.ws.scal, p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
     } else {
         const Tile3 t = tile3(p.geo, 8, 8, blocks);
-        ASDSM_LAUNCH((k_update_residual3<8, 8>), dim3(blocks), dim3(512), 0, st, p.geo, t, uin, e,
+        ASDSM_LAUNCH((k_update_residual3<3, 8, 8>), dim3(blocks), dim3(512), 0, st, p.geo, t, uin, e,
                      p.ws.scal, p.ws.b, uout, p.ws.r, bx, p.ws.partials, p.gate);
     }
     launch_finalize(p, blocks, fin_mode, 1, st);
 }
 
 void launch_dots(const Plan &p, hipStream_t st) {
+    int blocks = 0;
+    if (p.d == 4) {
+        const Tile3 t = tile3(p.geo, 8, 8, blocks);
+        if (2 * blocks <= p.max_blocks) {
+            ASDSM_LAUNCH((k_dots3<4, 8, 8>), dim3(blocks), dim3(512), 0, st, p.geo, t, p.ws.e, p.ws.r,
+                         p.ws.partials, p.gate);
+            launch_finalize(p, blocks, kFinDots, 1, st);
+            return;
+        }
+    }
     if (p.d == 2 || p.d == 4) {
         dim3 grid;
         stencil_grid(p.geo, grid);
@@ -546,14 +608,13 @@ void launch_dots(const Plan &p, hipStream_t st) {
         launch_finalize(p, (int)(grid.x * grid.y), kFinDots, 1, st);
         return;
     }
-    int blocks = 0;
     if (p.geo.Nf >= 255) {
         const Tile3 t = tile3(p.geo, 16, 16, blocks);
-        ASDSM_LAUNCH((k_dots3<16, 16>), dim3(blocks), dim3(1024), 0, st, p.geo, t, p.ws.e, p.ws.r,
+        ASDSM_LAUNCH((k_dots3<3, 16, 16>), dim3(blocks), dim3(1024), 0, st, p.geo, t, p.ws.e, p.ws.r,
                      p.ws.partials, p.gate);
     } else {
         const Tile3 t = tile3(p.geo, 8, 8, blocks);
-        ASDSM_LAUNCH((k_dots3<8, 8>), dim3(blocks), dim3(512), 0, st, p.geo, t, p.ws.e, p.ws.r,
+        ASDSM_LAUNCH((k_dots3<3, 8, 8>), dim3(blocks), dim3(512), 0, st, p.geo, t, p.ws.e, p.ws.r,
                      p.ws.partials, p.gate);
     }
     launch_finalize(p, blocks, kFinDots, 1, st);

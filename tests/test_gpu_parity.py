@@ -74,6 +74,8 @@ CASES = [  # (family, level, coarse_level, d, seed)
     ("sinprod", 3, 1, 4, 14),          # d = 4: 7^4, one coarse plane per axis, 3^4 holes
     ("sinprod", 4, 2, 4, 6),           # 15^4, 3 coarse planes per axis, 3^4 holes
     ("sinprod", 4, 3, 4, 7),           # 15^4, 7 coarse planes per axis, single-point holes
+    ("sinprod", 4, 1, 4, 8),           # 15^4, one coarse plane per axis, 7^4 holes
+    ("sinprod", 5, 4, 3, 9),           # 31^3, 15 coarse planes per axis, single-point holes
 ]
 
 
