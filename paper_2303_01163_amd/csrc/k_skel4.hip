@@ -16,6 +16,8 @@
 //     family 2        : i0 + N_f (i1 + N_f (c2 + N_c ck))
 // with i_j the fine coordinate along f_j, c_j the coarse index of a coordinate on a coarse plane and
 // ck the coarse plane of M_k; buffer order: family 0, 1, 2, R_12, R_0.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -119,122 +121,146 @@ __device__ __forceinline__ double *lines_k(const Skel4Args &a, int k) {
     return (k == 0) ? a.lines[0] : (k == 1) ? a.lines[1] : (k == 2) ? a.lines[2] : a.lines[3];
 }
 
-// delta on the three plane families of every M_k.  Grid (blocks, 4).
+// delta on the three plane families of every M_k.  Grid (blocks, 4): one wave per row of N_f
+// values along the family's first free axis; the row's (family, second free coordinate, coarse
+// indices) are wave-uniform 32-bit values.
 __global__ __launch_bounds__(256) void k_cross4(Geo g, Skel4Args a) {
     if (a.gate && *a.gate) return;
     const Perm4 pm = load_perm4(a);
     const int k = blockIdx.y;
     const int Nf = g.Nf, Nc = g.Nc, n = g.n;
-    const long long F = (long long)Nc * Nc * Nf * Nf, Nf2 = (long long)Nf * Nf;
+    const long long F = (long long)Nc * Nc * Nf * Nf;
+    const int rows_fam = Nf * Nc * Nc, nrows = 3 * rows_fam;
     const double scale_k = (a.mode == 0) ? 1.0 : a.scal[kScalInvNorm + k];
     const double *__restrict__ Xk = res_k(a, k);
     double *__restrict__ L = lines_k(a, k);
-    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < 3 * F; t += (long long)gridDim.x * 256) {
-        const int fam = (int)(t / F);
-        const long long r = t - fam * F;
-        const int u = (int)(r % Nf), v = (int)((r / Nf) % Nf);
-        const int cf = (int)((r / Nf2) % Nc), ck = (int)(r / (Nf2 * Nc));
+    double *__restrict__ out = (k == 0) ? a.skel[0] : (k == 1) ? a.skel[1] : (k == 2) ? a.skel[2] : a.skel[3];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
+        const int row = __builtin_amdgcn_readfirstlane(row0);
+        const int fam = row / rows_fam, rw = row - fam * rows_fam;
+        const int v = rw % Nf, q = rw / Nf, cf = q % Nc, ck = q / Nc;
         const int C = (cf + 1) * n - 1;
-        const int i0 = fam == 0 ? C : u;
-        const int i1 = fam == 0 ? u : (fam == 1 ? C : v);
-        const int i2 = fam == 2 ? C : v;
-        const int4 p = pt4(k, i0, i1, i2, ck, n);
-        const double uh = xval4(a, p, cset4(p, n), Nf, Nc, n, pm);
-        L[t] = uh - scale_k * Xk[i0 + Nf * (i1 + (long long)Nf * (i2 + (long long)Nf * ck))];
+        double *__restrict__ dst = L + fam * F + (long long)Nf * rw;
+        for (int u = tx; u < Nf; u += 64) {
+            const int i0 = fam == 0 ? C : u;
+            const int i1 = fam == 0 ? u : (fam == 1 ? C : v);
+            const int i2 = fam == 2 ? C : v;
+            const int4 p = pt4(k, i0, i1, i2, ck, n);
+            const double uh = xval4(a, p, cset4(p, n), Nf, Nc, n, pm);
+            const long long idx = i0 + Nf * (i1 + (long long)Nf * (i2 + (long long)Nf * ck));
+            dst[u] = uh - scale_k * Xk[idx];
+            // the merged value of a cross point is uhat itself: written here, skipped by k_merge4
+            // (a point on two or three families gets the same value from each)
+            out[idx] = uh;
+        }
     }
 }
 
-// R_12 on family 1: delta - P_2 delta (zero where f2 is on a coarse plane).
+// R_12 on family 1: delta - P_2 delta (zero where f2 is on a coarse plane).  One wave per row of
+// N_f values along f0, as in k_cross4.
 __global__ __launch_bounds__(256) void k_rem12(Geo g, Skel4Args a) {
     if (a.gate && *a.gate) return;
     const int k = blockIdx.y;
     const int Nf = g.Nf, Nc = g.Nc, n = g.n;
-    const long long F = (long long)Nc * Nc * Nf * Nf, Nf2 = (long long)Nf * Nf;
+    const long long F = (long long)Nc * Nc * Nf * Nf;
+    const int nrows = Nf * Nc * Nc;
     double *__restrict__ L = lines_k(a, k);
-    const double *__restrict__ D1 = L + F;
-    const double *__restrict__ D2 = L + 2 * F;
-    double *__restrict__ R12 = L + 3 * F;
     const double *__restrict__ Sp = a.Sp;
-    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < F; t += (long long)gridDim.x * 256) {
-        const int i0 = (int)(t % Nf), i2 = (int)((t / Nf) % Nf);
-        const int c1 = (int)((t / Nf2) % Nc), ck = (int)(t / (Nf2 * Nc));
-        double v = 0.0;
-        if (!on_coarse(i2, n)) {
-            const int i1 = (c1 + 1) * n - 1;
-            v = D1[t];
-            for (int c2 = 0; c2 < Nc; ++c2)
-                v -= Sp[(long long)i2 * Nc + c2] * D2[i0 + Nf * (i1 + (long long)Nf * (c2 + (long long)Nc * ck))];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
+        const int row = __builtin_amdgcn_readfirstlane(row0);
+        const int i2 = row % Nf, q = row / Nf, c1 = q % Nc, ck = q / Nc;
+        const int i1 = (c1 + 1) * n - 1;
+        const double *__restrict__ D1 = L + F + (long long)Nf * row;
+        const double *__restrict__ D2 = L + 2 * F + (long long)Nf * i1 + (long long)Nf * Nf * Nc * ck;
+        double *__restrict__ R12 = L + 3 * F + (long long)Nf * row;
+        const bool live = !on_coarse(i2, n);
+        for (int i0 = tx; i0 < Nf; i0 += 64) {
+            double v = 0.0;
+            if (live) {
+                v = D1[i0];
+                for (int c2 = 0; c2 < Nc; ++c2) v -= Sp[i2 * Nc + c2] * D2[i0 + (long long)Nf * Nf * c2];
+            }
+            R12[i0] = v;
         }
-        R12[t] = v;
     }
 }
 
-// R_0 on family 0: delta - (P_2 delta + P_1 R_12) (zero where f1 or f2 is on a coarse plane).
+// R_0 on family 0: delta - (P_2 delta + P_1 R_12) (zero where f1 or f2 is on a coarse plane).  One
+// wave per row of N_f values along f1.
 __global__ __launch_bounds__(256) void k_rem0(Geo g, Skel4Args a) {
     if (a.gate && *a.gate) return;
     const int k = blockIdx.y;
     const int Nf = g.Nf, Nc = g.Nc, n = g.n;
-    const long long F = (long long)Nc * Nc * Nf * Nf, Nf2 = (long long)Nf * Nf;
+    const long long F = (long long)Nc * Nc * Nf * Nf;
+    const int nrows = Nf * Nc * Nc;
     double *__restrict__ L = lines_k(a, k);
-    const double *__restrict__ D0 = L;
-    const double *__restrict__ D2 = L + 2 * F;
-    const double *__restrict__ R12 = L + 3 * F;
-    double *__restrict__ R0 = L + 4 * F;
     const double *__restrict__ Sp = a.Sp;
-    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < F; t += (long long)gridDim.x * 256) {
-        const int i1 = (int)(t % Nf), i2 = (int)((t / Nf) % Nf);
-        const int c0 = (int)((t / Nf2) % Nc), ck = (int)(t / (Nf2 * Nc));
-        double v = 0.0;
-        if (!on_coarse(i1, n) && !on_coarse(i2, n)) {
-            const int i0 = (c0 + 1) * n - 1;
-            double b = 0.0;
-            for (int c2 = 0; c2 < Nc; ++c2)
-                b += Sp[(long long)i2 * Nc + c2] * D2[i0 + Nf * (i1 + (long long)Nf * (c2 + (long long)Nc * ck))];
-            for (int c1 = 0; c1 < Nc; ++c1)
-                b += Sp[(long long)i1 * Nc + c1] * R12[i0 + Nf * (i2 + (long long)Nf * (c1 + (long long)Nc * ck))];
-            v = D0[t] - b;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
+        const int row = __builtin_amdgcn_readfirstlane(row0);
+        const int i2 = row % Nf, q = row / Nf, c0 = q % Nc, ck = q / Nc;
+        const int i0 = (c0 + 1) * n - 1;
+        const long long cb = (long long)Nf * Nf * Nc * ck;
+        const double *__restrict__ D0 = L + (long long)Nf * row;
+        const double *__restrict__ D2 = L + 2 * F + cb + i0;
+        const double *__restrict__ R12 = L + 3 * F + cb + i0 + (long long)Nf * i2;
+        double *__restrict__ R0 = L + 4 * F + (long long)Nf * row;
+        const bool live2 = !on_coarse(i2, n);
+        for (int i1 = tx; i1 < Nf; i1 += 64) {
+            double v = 0.0;
+            if (live2 && !on_coarse(i1, n)) {
+                double b = 0.0;
+                for (int c2 = 0; c2 < Nc; ++c2)
+                    b += Sp[i2 * Nc + c2] * D2[(long long)Nf * (i1 + (long long)Nf * c2)];
+                for (int c1 = 0; c1 < Nc; ++c1) b += Sp[i1 * Nc + c1] * R12[(long long)Nf * Nf * c1];
+                v = D0[i1] - b;
+            }
+            R0[i1] = v;
         }
-        R0[t] = v;
     }
 }
 
-// Merged skeleton values of every M_k: uhat on cross points, u_k + B delta elsewhere (Algorithm 2
-// steps 5 and 6).
+// Merged skeleton values of every M_k off the cross points: u_k + B delta (Algorithm 2 steps 5 and
+// 6; the cross points' uhat is written by k_cross4).  Grid (blocks, 4): one wave per row of N_f points along f0, so the row's other
+// coordinates (i1, i2, ck) are 32-bit and uniform in the wave; NC > 0 fixes N_c at compile time
+// and the three N_c-term sums are unrolled (all their loads in flight together).
+template <int NC>
 __global__ __launch_bounds__(256) void k_merge4(Geo g, Skel4Args a) {
     if (a.gate && *a.gate) return;
-    const Perm4 pm = load_perm4(a);
     const int k = blockIdx.y;
-    const int Nf = g.Nf, Nc = g.Nc, n = g.n;
-    const long long F = (long long)Nc * Nc * Nf * Nf, Nf2 = (long long)Nf * Nf;
-    const long long size = Nf2 * Nf * Nc;
+    const int Nf = g.Nf, Nc = (NC > 0) ? NC : g.Nc, n = g.n;
+    const long long Nf2 = (long long)Nf * Nf, F = (long long)Nc * Nc * Nf2;
+    const int nrows = Nf * Nf * Nc;
     const unsigned mk = 1u << k;
     const double scale_k = (a.mode == 0) ? 1.0 : a.scal[kScalInvNorm + k];
     const double *__restrict__ X = res_k(a, k);
     const double *__restrict__ L = lines_k(a, k);
-    const double *__restrict__ D2 = L + 2 * F;
-    const double *__restrict__ R12 = L + 3 * F;
-    const double *__restrict__ R0 = L + 4 * F;
-    double *__restrict__ out = (k == 0) ? a.skel[0] : (k == 1) ? a.skel[1] : (k == 2) ? a.skel[2] : a.skel[3];
     const double *__restrict__ Sp = a.Sp;
-    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < size; idx += (long long)gridDim.x * 256) {
-        const int i0 = (int)(idx % Nf), i1 = (int)((idx / Nf) % Nf), i2 = (int)((idx / Nf2) % Nf);
-        const int ck = (int)(idx / (Nf2 * Nf));
-        const int4 p = pt4(k, i0, i1, i2, ck, n);
-        const unsigned S = cset4(p, n);
-        double v;
-        if (S != mk) {
-            v = xval4(a, p, S, Nf, Nc, n, pm);
-        } else {
+    double *__restrict__ out = (k == 0) ? a.skel[0] : (k == 1) ? a.skel[1] : (k == 2) ? a.skel[2] : a.skel[3];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
+        // the row is the same for the whole wave: make that visible (scalar address arithmetic)
+        const int row = __builtin_amdgcn_readfirstlane(row0);
+        const int i1 = row % Nf, q = row / Nf, i2 = q % Nf, ck = q / Nf;
+        const long long cb = Nf2 * Nc * ck;
+        const double *__restrict__ D2 = L + 2 * F + cb + (long long)Nf * i1;
+        const double *__restrict__ R12 = L + 3 * F + cb + (long long)Nf * i2;
+        const double *__restrict__ R0 = L + 4 * F + cb + i1 + (long long)Nf * i2;
+        for (int i0 = tx; i0 < Nf; i0 += 64) {
+            const long long idx = i0 + (long long)Nf * row;
+            const int4 p = pt4(k, i0, i1, i2, ck, n);
+            if (cset4(p, n) != mk) continue;  // cross point: uhat, written by k_cross4
             double c2s = 0.0, c1s = 0.0, c0s = 0.0;
+#pragma unroll(NC > 0 ? NC : 1)
             for (int c = 0; c < Nc; ++c) {
-                const long long base = (long long)Nf * Nf * (c + (long long)Nc * ck);
-                c2s += Sp[(long long)i2 * Nc + c] * D2[i0 + (long long)Nf * i1 + base];
-                c1s += Sp[(long long)i1 * Nc + c] * R12[i0 + (long long)Nf * i2 + base];
-                c0s += Sp[(long long)i0 * Nc + c] * R0[i1 + (long long)Nf * i2 + base];
+                c2s += Sp[i2 * Nc + c] * D2[i0 + Nf2 * c];
+                c1s += Sp[i1 * Nc + c] * R12[i0 + Nf2 * c];
+                c0s += Sp[i0 * Nc + c] * R0[Nf2 * c];
             }
-            v = scale_k * X[idx] + (c2s + c1s + c0s);
+            out[idx] = scale_k * X[idx] + (c2s + c1s + c0s);
         }
-        out[idx] = v;
     }
 }
 
@@ -263,14 +289,22 @@ static unsigned blocks_for(long long n, long long cap) {
 void launch_crosspoints4(const Plan &p, int mode, const double *const *res, hipStream_t st) {
     const Skel4Args a = skel4_args(p, mode, res);
     const long long F = (long long)p.Nc * p.Nc * p.Nf * p.Nf;
-    ASDSM_LAUNCH(k_cross4, dim3(blocks_for(3 * F, 1024), 4, 1), dim3(256), 0, st, p.geo, a);
-    ASDSM_LAUNCH(k_rem12, dim3(blocks_for(F, 1024), 4, 1), dim3(256), 0, st, p.geo, a);
-    ASDSM_LAUNCH(k_rem0, dim3(blocks_for(F, 1024), 4, 1), dim3(256), 0, st, p.geo, a);
+    const long long rows = F / p.Nf;  // rows of N_f values per family
+    ASDSM_LAUNCH(k_cross4, dim3(blocks_for(3 * rows * 64, 8192), 4, 1), dim3(256), 0, st, p.geo, a);
+    ASDSM_LAUNCH(k_rem12, dim3(blocks_for(rows * 64, 8192), 4, 1), dim3(256), 0, st, p.geo, a);
+    ASDSM_LAUNCH(k_rem0, dim3(blocks_for(rows * 64, 8192), 4, 1), dim3(256), 0, st, p.geo, a);
 }
 
 void launch_merge4(const Plan &p, int mode, const double *const *res, hipStream_t st) {
     const Skel4Args a = skel4_args(p, mode, res);
-    ASDSM_LAUNCH(k_merge4, dim3(blocks_for(p.mesh[1].size, 4096), 4, 1), dim3(256), 0, st, p.geo, a);
+    long long rows = (long long)p.Nf * p.Nf * p.Nc;
+    const dim3 grid((unsigned)std::min<long long>((rows + 3) / 4, 8192), 4, 1);
+    switch (p.Nc) {
+        case 3: ASDSM_LAUNCH((k_merge4<3>), grid, dim3(256), 0, st, p.geo, a); break;
+        case 7: ASDSM_LAUNCH((k_merge4<7>), grid, dim3(256), 0, st, p.geo, a); break;
+        case 15: ASDSM_LAUNCH((k_merge4<15>), grid, dim3(256), 0, st, p.geo, a); break;
+        default: ASDSM_LAUNCH((k_merge4<0>), grid, dim3(256), 0, st, p.geo, a); break;
+    }
 }
 
 }  // namespace asdsm

@@ -654,10 +654,14 @@ __device__ __forceinline__ long long skel_offset(const int (&i)[D], int cj, int 
 }
 
 // Transform of every line along axis J of the hole buffer by the NH x NH matrix M (out, in).  A
-// lane holds all its lines at once (NR of them), so each matrix entry is read once per lane.
+// lane holds all its lines at once (NR of them), so each matrix entry is read once per lane; the
+// entries are read at wave-uniform addresses from global memory (scalar loads into SGPR operands),
+// which leaves the LDS bandwidth to the hole values.
 template <int D, int NH, int J>
-__device__ __forceinline__ void hole_lines_map(double *buf, const double *M) {
+__device__ __forceinline__ void hole_lines_map(double *buf, const double *__restrict__ M) {
     constexpr int N = ipow_c(NH, D), NL = N / NH, SJ = ipow_c(NH, J), NR = (NL + 255) / 256;
+    // read-only for the kernel's lifetime: the constant address space makes the loads scalar
+    const __attribute__((address_space(4))) double *Mc = (const __attribute__((address_space(4))) double *)M;
     double x[NR][NH];
     int base[NR];
 #pragma unroll
@@ -675,7 +679,7 @@ __device__ __forceinline__ void hole_lines_map(double *buf, const double *M) {
         for (int r = 0; r < NR; ++r) acc[r] = 0.0;
 #pragma unroll
         for (int l = 0; l < NH; ++l) {
-            const double w = M[m * NH + l];
+            const double w = Mc[m * NH + l];
 #pragma unroll
             for (int r = 0; r < NR; ++r) acc[r] += w * x[r][l];
         }
@@ -688,7 +692,7 @@ __device__ __forceinline__ void hole_lines_map(double *buf, const double *M) {
 // Tridiagonal solve of every line along axis J (the line axis) with the diagonal shifted by the
 // eigenvalues of the transformed axes at the line's modes.
 template <int D, int NH, int J>
-__device__ __forceinline__ void hole_lines_solve(double *buf, const double (*mu)[NH], Tri t) {
+__device__ __forceinline__ void hole_lines_solve(double *buf, const FillArgs &a, Tri t) {
     constexpr int N = ipow_c(NH, D), NL = N / NH, SJ = ipow_c(NH, J), NR = (NL + 255) / 256;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -699,7 +703,7 @@ __device__ __forceinline__ void hole_lines_solve(double *buf, const double (*mu)
 #pragma unroll
         for (int q = 0; q < D; ++q) {
             if (q == J) continue;
-            sigma += mu[q][(base / ipow_c(NH, q)) % NH];
+            sigma += a.mu[q][(base / ipow_c(NH, q)) % NH];
         }
         const double diag = t.b + sigma;
         double x[NH], cp[NH];
@@ -722,7 +726,7 @@ __device__ __forceinline__ void hole_lines_solve(double *buf, const double (*mu)
 }
 
 template <int D, int NH>
-__device__ __forceinline__ void hole_map_axis(double *buf, const double *M, int j) {
+__device__ __forceinline__ void hole_map_axis(double *buf, const double *__restrict__ M, int j) {
     switch (j) {
         case 0: hole_lines_map<D, NH, 0>(buf, M); break;
         case 1: hole_lines_map<D, NH, 1>(buf, M); break;
@@ -737,16 +741,12 @@ __global__ __launch_bounds__(256) void k_filler_lines(Geo g, FillArgs a) {
     constexpr int n = NH + 1, N = ipow_c(NH, D), NT = ipow_c(n, D);
     constexpr int K1 = (N + 255) / 256, K5 = (NT + 255) / 256;
     __shared__ double buf[N];
-    __shared__ double sW[D][NH * NH], sV[D][NH * NH], smu[D][NH];
     const int Nf = g.Nf, Nc = g.Nc, tid = threadIdx.x;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        for (int e = tid; e < NH * NH; e += 256) {
-            sW[j][e] = a.W[j][e];
-            sV[j][e] = a.V[j][e];
-        }
-        if (tid < NH) smu[j][tid] = a.mu[j][tid];
-    }
+    // the matrices of axis j, through selects (a dynamic index into the argument struct would be
+    // copied to scratch)
+    auto pick = [&](const double *const *m, int j) -> const double * {
+        return j == 0 ? m[0] : (j == 1 ? m[1] : (j == 2 ? m[2] : m[D - 1]));
+    };
     int tt[D];
     {
         int rem = blockIdx.x;
@@ -815,18 +815,18 @@ __global__ __launch_bounds__(256) void k_filler_lines(Geo g, FillArgs a) {
     __syncthreads();
     // 2) forward transforms, 3) line elimination, 4) backward transforms
     for (int q = 0; q < a.ntr; ++q) {
-        hole_map_axis<D, NH>(buf, sW[a.tr[q]], a.tr[q]);
+        hole_map_axis<D, NH>(buf, pick(a.W, a.tr[q]), a.tr[q]);
         __syncthreads();
     }
     switch (a.line_axis) {
-        case 0: hole_lines_solve<D, NH, 0>(buf, smu, g.fine[0]); break;
-        case 1: hole_lines_solve<D, NH, 1>(buf, smu, g.fine[1]); break;
-        case 2: hole_lines_solve<D, NH, 2>(buf, smu, g.fine[2]); break;
-        default: if constexpr (D == 4) hole_lines_solve<D, NH, 3>(buf, smu, g.fine[3]); break;
+        case 0: hole_lines_solve<D, NH, 0>(buf, a, g.fine[0]); break;
+        case 1: hole_lines_solve<D, NH, 1>(buf, a, g.fine[1]); break;
+        case 2: hole_lines_solve<D, NH, 2>(buf, a, g.fine[2]); break;
+        default: if constexpr (D == 4) hole_lines_solve<D, NH, 3>(buf, a, g.fine[3]); break;
     }
     __syncthreads();
     for (int q = a.ntr - 1; q >= 0; --q) {
-        hole_map_axis<D, NH>(buf, sV[a.tr[q]], a.tr[q]);
+        hole_map_axis<D, NH>(buf, pick(a.V, a.tr[q]), a.tr[q]);
         __syncthreads();
     }
     // 5) the whole tile: hole values and the skeleton planes above it (merged values), in batches

@@ -432,6 +432,8 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
     const int tid = threadIdx.x;
     if (mode == kFinDots) {
         double a0 = 0.0, a1 = 0.0;
+        // unrolled: the loads of several trips in flight, the additions in the same order
+#pragma unroll 8
         for (int b = tid; b < nblk; b += 256) {
             a0 += partials[2 * b];
             a1 += partials[2 * b + 1];
@@ -447,6 +449,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
     } else if (mode == kFinBoxNorms) {
         for (int k = 0; k < nbox; ++k) {
             double a = 0.0;
+#pragma unroll 8
             for (int b = tid; b < nblk; b += 256) a += partials[(size_t)k * nblk + b];
             const double t = block_sum<256>(a, sh);
             if (tid == 0) {
@@ -456,6 +459,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
         }
     } else {
         double a = 0.0;
+#pragma unroll 8
         for (int b = tid; b < nblk; b += 256) a += partials[b];
         const double t = block_sum<256>(a, sh);
         if (tid != 0) return;
