@@ -593,26 +593,28 @@ void launch_dense_modes(long long nmodes, int B, const double *inv, const double
 // ||e_k||^2 of each anisotropic box and the normalisation factor 1/||e_k|| (Algorithm 1 steps
 // 2.1/2.2; a zero vector is left unscaled).
 // ---------------------------------------------------------------------------------------------
-constexpr int kNormBlocks = 128;
-
 __global__ __launch_bounds__(256) void k_box_norms(BoxPtrs X, long long size, double *partials,
                                                    const int *gate) {
     if (gate && *gate) return;
     const int k = blockIdx.y;
     const double *__restrict__ x = X.p[k];
     double acc = 0.0;
+    // unrolled: the loads of several trips in flight, the additions in order
+#pragma unroll 8
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < size; i += (long long)gridDim.x * 256)
         acc += x[i] * x[i];
     double vals[1] = {acc};
-    block_partials<256, 1>(vals, partials + (size_t)k * kNormBlocks, blockIdx.x);
+    block_partials<256, 1>(vals, partials + (size_t)k * gridDim.x, blockIdx.x);
 }
 
 void launch_box_norms(const Plan &p, const double *const *sol, hipStream_t st) {
     BoxPtrs bx;
     for (int k = 0; k < kMaxD; ++k) bx.p[k] = (k < p.d) ? const_cast<double *>(sol[1u << k]) : nullptr;
     const long long size = p.mesh[1].size;
-    ASDSM_LAUNCH(k_box_norms, dim3(kNormBlocks, p.d, 1), dim3(256), 0, st, bx, size, p.ws.partials, p.gate);
-    launch_finalize(p, kNormBlocks, kFinBoxNorms, p.d, st);
+    // about 16 values per thread, 128 to 1024 blocks per mesh
+    const int nblk = (int)std::min<long long>(1024, std::max<long long>(128, (size + 4095) / 4096));
+    ASDSM_LAUNCH(k_box_norms, dim3(nblk, p.d, 1), dim3(256), 0, st, bx, size, p.ws.partials, p.gate);
+    launch_finalize(p, nblk, kFinBoxNorms, p.d, st);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -690,6 +692,8 @@ void launch_fill_random(double *x, long long n, uint64_t seed, hipStream_t st) {
     if (blocks > 2048) blocks = 2048;
     ASDSM_LAUNCH(k_fill_random, dim3((unsigned)blocks), dim3(256), 0, st, x, n, (unsigned long long)seed);
 }
+
+constexpr int kNormBlocks = 128;
 
 struct SumsqJob {
     const double *x[kMaxD];
