@@ -114,6 +114,15 @@ __device__ __forceinline__ double xval4(const Skel4Args &a, const int4 &p, unsig
     return a.scal[kScalInvNorm + j] * pick4(a, mj)[off4(mj, p, Nf, Nc, n)];
 }
 
+// Block index with each XCD owning one contiguous range of the (row-ordered) blocks: the hardware
+// deals the blocks of a launch to the eight XCDs in turn, so consecutive rows would otherwise land
+// on different XCDs and every XCD's L2 would fetch all of the (small, much re-read) family arrays.
+// The launchers round gridDim.x up to a multiple of 8, which makes this a permutation.
+__device__ __forceinline__ int xcd_block() {
+    const int per = (int)gridDim.x >> 3;
+    return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
 __device__ __forceinline__ const double *res_k(const Skel4Args &a, int k) {
     return (k == 0) ? a.res[1] : (k == 1) ? a.res[2] : (k == 2) ? a.res[4] : a.res[8];
 }
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(256) void k_cross4(Geo g, Skel4Args a) {
     double *__restrict__ L = lines_k(a, k);
     double *__restrict__ out = (k == 0) ? a.skel[0] : (k == 1) ? a.skel[1] : (k == 2) ? a.skel[2] : a.skel[3];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
+    for (int row0 = xcd_block() * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
         const int row = __builtin_amdgcn_readfirstlane(row0);
         const int fam = row / rows_fam, rw = row - fam * rows_fam;
         const int v = rw % Nf, q = rw / Nf, cf = q % Nc, ck = q / Nc;
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(256) void k_rem12(Geo g, Skel4Args a) {
     double *__restrict__ L = lines_k(a, k);
     const double *__restrict__ Sp = a.Sp;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
+    for (int row0 = xcd_block() * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
         const int row = __builtin_amdgcn_readfirstlane(row0);
         const int i2 = row % Nf, q = row / Nf, c1 = q % Nc, ck = q / Nc;
         const int i1 = (c1 + 1) * n - 1;
@@ -198,7 +207,7 @@ __global__ __launch_bounds__(256) void k_rem0(Geo g, Skel4Args a) {
     double *__restrict__ L = lines_k(a, k);
     const double *__restrict__ Sp = a.Sp;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
+    for (int row0 = xcd_block() * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
         const int row = __builtin_amdgcn_readfirstlane(row0);
         const int i2 = row % Nf, q = row / Nf, c0 = q % Nc, ck = q / Nc;
         const int i0 = (c0 + 1) * n - 1;
@@ -240,7 +249,7 @@ __global__ __launch_bounds__(256) void k_merge4(Geo g, Skel4Args a) {
     const double *__restrict__ Sp = a.Sp;
     double *__restrict__ out = (k == 0) ? a.skel[0] : (k == 1) ? a.skel[1] : (k == 2) ? a.skel[2] : a.skel[3];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int row0 = blockIdx.x * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
+    for (int row0 = xcd_block() * 4 + ty; row0 < nrows; row0 += gridDim.x * 4) {
         // the row is the same for the whole wave: make that visible (scalar address arithmetic)
         const int row = __builtin_amdgcn_readfirstlane(row0);
         const int i1 = row % Nf, q = row / Nf, i2 = q % Nf, ck = q / Nf;
@@ -283,7 +292,8 @@ static Skel4Args skel4_args(const Plan &p, int mode, const double *const *res) {
 static unsigned blocks_for(long long n, long long cap) {
     long long b = (n + 255) / 256;
     if (b > cap) b = cap;
-    return (unsigned)(b < 1 ? 1 : b);
+    if (b < 1) b = 1;
+    return (unsigned)((b + 7) / 8 * 8);  // a multiple of 8 (see xcd_block)
 }
 
 void launch_crosspoints4(const Plan &p, int mode, const double *const *res, hipStream_t st) {
@@ -298,7 +308,7 @@ void launch_crosspoints4(const Plan &p, int mode, const double *const *res, hipS
 void launch_merge4(const Plan &p, int mode, const double *const *res, hipStream_t st) {
     const Skel4Args a = skel4_args(p, mode, res);
     long long rows = (long long)p.Nf * p.Nf * p.Nc;
-    const dim3 grid((unsigned)std::min<long long>((rows + 3) / 4, 8192), 4, 1);
+    const dim3 grid(blocks_for(rows * 64, 8192), 4, 1);
     switch (p.Nc) {
         case 3: ASDSM_LAUNCH((k_merge4<3>), grid, dim3(256), 0, st, p.geo, a); break;
         case 7: ASDSM_LAUNCH((k_merge4<7>), grid, dim3(256), 0, st, p.geo, a); break;
