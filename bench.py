@@ -287,9 +287,36 @@ def four_d(asdsm, make_problem, args, dev, seed=0, steps=3):
            "rel_error_vs_manufactured": float(torch.linalg.norm(u - ue) / torch.linalg.norm(ue)),
            "plan_seconds": plan_s, "phase_ms": prof["phase_ms"], "phase_launches": prof["phase_launches"]}
     del plan, s, g, u, ue
+    res["mixed_precision"] = four_d_mixed(asdsm, make_problem, args, dev, L, Lc)
     if getattr(args, "d4_batch", 0) > 0:
         res["batch"] = four_d_batch(asdsm, make_problem, args, dev, L, Lc)
     return res
+
+
+def four_d_mixed(asdsm, make_problem, args, dev, L, Lc, seed=1, steps=3):
+    """FP32 against FP64 error guesses at d = 4 on a draw whose transforms admit FP32 (seed 1: the
+    plan's conditioning rule 6e-8 prod cond(V_j) <= 1e-3 holds; the seed-0 draw does not)."""
+    import torch
+    P = make_problem("sinprod", L, seed=seed, d=4)
+    plan = asdsm.Plan(4, P.alpha, P.beta, L, Lc, seed=seed, device=0)
+    s = torch.from_numpy(P.s_flat()).to(dev)
+    g = torch.from_numpy(P.g_flat()).to(dev)
+    out = {"workload": f"asdsm-4d-{plan.n_f}^4-sinprod-seed{seed}"}
+    us = {}
+    for prec in ("fp64", "fp32"):
+        u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
+        kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3, precision=prec)
+        plan.solve(s, g, u=u, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, info = plan.solve(s, g, u=u, **kw)
+        torch.cuda.synchronize()
+        out[prec] = {"ms_per_solve": 1e3 * (time.perf_counter() - t0) / steps, "iterations": info["iterations"],
+                     "rel_residual": info["rnorm"] / info["bnorm"], "precision_used": info["precision"]}
+        us[prec] = u
+    out["rel_l2_fp32_vs_fp64"] = float(torch.linalg.norm(us["fp32"] - us["fp64"]) / torch.linalg.norm(us["fp64"]))
+    return out
 
 
 def four_d_batch(asdsm, make_problem, args, dev, L, Lc, steps=2):

@@ -122,8 +122,7 @@ typedef struct {
 
 /* Create a plan (Section 2.1 meshes, Section 2.3 operators, Algorithms 1-4 schedule).
  *   d            : 2, 3 or 4 (dimensions of eq. (1); d = 4 per Section 3.5's construction of the
- *                  submeshes for any d).  FP32 error guesses and skeleton-sparse refinement are
- *                  built for d <= 3 and d = 3 respectively.
+ *                  submeshes for any d).  Skeleton-sparse refinement is built for d = 3.
  *   alpha, beta  : host arrays of d finite doubles, alpha[j] > 0 (copied).
  *   level        : fine level L, N_f = 2^L - 1, 2 <= L <= 10.
  *   coarse_level : L_c with 1 <= L_c < L (eq. (3)); 0 selects floor(L/2).

@@ -512,8 +512,108 @@ int solve_aniso_refined(Plan &p, unsigned kbits) {
 // in FP32 (FP32 MFMA transforms with FP32 accumulation, FP32 line elimination, no refinement
 // sweeps).  in[k] (FP64 right-hand side) is rounded to FP32 as the first transform stages it; the
 // last transform writes the FP64 solution out[k].  F1/F2 hold the FP32 intermediates.
+// FP32 error guess on the four anisotropic meshes of a d = 4 plan: the same fast diagonalisation as
+// the FP64 solve (each fine axis by its mode transform, Thomas along the coarse axis per mode), in
+// FP32 with FP32 MFMA products; the input is rounded while the first product stages it and the last
+// product writes the FP64 solution.  Canonical layout of M_k: f0 + N_f (f1 + N_f (f2 + N_f c_k)).
+static int solve_aniso32_4(Plan &p, const double *const *in, double *const *out) {
+    const int Nf = p.Nf, Nc = p.Nc, nb = 4;
+    const long long Nf2 = (long long)Nf * Nf, Nf3 = Nf2 * Nf;
+    auto f64 = [](float *x) { return reinterpret_cast<double *>(x); };
+    auto cf64 = [](const float *x) { return reinterpret_cast<const double *>(x); };
+    int ax[4][3];
+    for (int k = 0; k < nb; ++k)
+        for (int j = 0, q = 0; j < 4; ++j)
+            if (j != k) ax[k][q++] = j;
+    auto run = [&](GemmJob &j, bool a64, bool c64, double byte_share) -> int {
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j) * byte_share);
+        if (!launch_gemm32(j, a64, c64, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
+        return check_launch("transform");
+    };
+    GemmJob j{};
+    j.nbox = nb;
+    j.gate = p.gate;
+    // position 0 (f0), all rows at once: in (FP64) -> F1; backward: F1 -> out (FP64)
+    auto pos0 = [&](bool fwd) {
+        j.M = (int)(Nf2 * Nc); j.N = Nf; j.K = Nf; j.nbatch = 1; j.accum = 0;
+        j.sAb = j.sBb = j.sCb = 0;
+        j.sAi = Nf; j.sAk = 1;
+        j.sBk = 1;  j.sBn = Nf;
+        j.sCi = Nf; j.sCn = 1;
+        for (int k = 0; k < nb; ++k) {
+            j.A[k] = fwd ? in[k] : cf64(p.ws.F1[k]);
+            j.B[k] = cf64(fwd ? p.dW32[ax[k][0]] : p.dV32[ax[k][0]]);
+            j.C[k] = fwd ? f64(p.ws.F1[k]) : out[k];
+        }
+    };
+    // position 1 (f1), batched over the N_f N_c slabs (f2, c_k): src -> dst
+    auto pos1 = [&](bool fwd, float *const *src, float *const *dst) {
+        j.M = Nf; j.N = Nf; j.K = Nf; j.nbatch = Nf * Nc; j.accum = 0;
+        j.sAb = 0;   j.sAi = Nf; j.sAk = 1;
+        j.sBb = Nf2; j.sBk = Nf; j.sBn = 1;
+        j.sCb = Nf2; j.sCi = Nf; j.sCn = 1;
+        for (int k = 0; k < nb; ++k) {
+            j.A[k] = cf64(fwd ? p.dW32[ax[k][1]] : p.dV32[ax[k][1]]);
+            j.B[k] = cf64(src[k]);
+            j.C[k] = f64(dst[k]);
+        }
+    };
+    // position 2 (f2), batched over the N_c coarse planes: (N_f x N_f) by (N_f x N_f^2) products
+    auto pos2 = [&](bool fwd, float *const *src, float *const *dst) {
+        j.M = Nf; j.N = (int)Nf2; j.K = Nf; j.nbatch = Nc; j.accum = 0;
+        j.sAb = 0;   j.sAi = Nf;  j.sAk = 1;
+        j.sBb = Nf3; j.sBk = Nf2; j.sBn = 1;
+        j.sCb = Nf3; j.sCi = Nf2; j.sCn = 1;
+        for (int k = 0; k < nb; ++k) {
+            j.A[k] = cf64(fwd ? p.dW32[ax[k][2]] : p.dV32[ax[k][2]]);
+            j.B[k] = cf64(src[k]);
+            j.C[k] = f64(dst[k]);
+        }
+    };
+    float *F1[4], *F2[4];
+    for (int k = 0; k < nb; ++k) {
+        F1[k] = p.ws.F1[k];
+        F2[k] = p.ws.F2[k];
+    }
+    pos0(true);
+    if (int rc = run(j, true, false, 0.75)) return rc;
+    pos1(true, F1, F2);
+    if (int rc = run(j, false, false, 0.5)) return rc;
+    pos2(true, F2, F1);
+    if (int rc = run(j, false, false, 0.5)) return rc;
+    {
+        // FP32 line elimination along the coarse axis on F1 (scratch F2); modes f0 + N_f (f1 + N_f f2)
+        LineJob L{};
+        L.nbox = nb;
+        L.gate = p.gate;
+        L.fp32 = 1;
+        L.nmodes = Nf3;
+        L.ext_a = Nf;
+        L.ncoarse = Nc;
+        for (int k = 0; k < nb; ++k) {
+            L.X[k] = f64(F1[k]);
+            L.scratch[k] = f64(F2[k]);
+            L.mu_a[k] = p.dmu[ax[k][0]];
+            L.mu_b[k] = p.dmu[ax[k][1]];
+            L.mu_c[k] = p.dmu[ax[k][2]];
+            L.t[k] = p.geo.coarse[k];
+        }
+        const double lpts = (double)L.nmodes * L.ncoarse * nb;
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 8.0 * lpts, 8.0 * lpts);
+        launch_line(L, p.stream);
+        if (int rc = check_launch("line")) return rc;
+    }
+    pos2(false, F1, F2);
+    if (int rc = run(j, false, false, 0.5)) return rc;
+    pos1(false, F2, F1);
+    if (int rc = run(j, false, false, 0.5)) return rc;
+    pos0(false);
+    return run(j, false, true, 0.75);
+}
+
 int solve_aniso32(Plan &p, const double *const *in, double *const *out) {
     const int d = p.d, Nf = p.Nf, Nc = p.Nc;
+    if (d == 4) return solve_aniso32_4(p, in, out);
     const long long Nf2 = (long long)Nf * Nf;
     const int nb = d;
     auto f64 = [](float *x) { return reinterpret_cast<double *>(x); };

@@ -506,7 +506,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     // transformed axes.  Where that exceeds 2e-11 the direct solve becomes the preconditioner of
     // FP64 refinement sweeps x <- x + M^-1 (f - A x), each gaining -log10(eps * prod cond) digits;
     // the count is fixed here so that the result reaches ~1e-14.
-    p.fp32_ok = (d <= 3);  // the FP32 error guesses are built for d = 2 and 3
+    p.fp32_ok = true;  // FP32 error guesses: every d, if the conditioning below allows
     for (unsigned s = 1; s < (1u << d); ++s) {
         double c = 1.0;
         for (int q = 0; q < p.mesh[s].nfine; ++q) c *= p.fine_spec[p.mesh[s].ax[q]].cond;
