@@ -343,6 +343,8 @@ MIXED_CASES = [  # (family, level, coarse_level, d, seed): every anisotropic mes
     ("sinprod2d", 6, 0, None, 0),
     ("sinbump3d", 6, 3, None, 4),
     ("sinbump3d", 7, 0, None, 1),
+    ("sinprod", 4, 1, 4, 8),           # d = 4: 15^4, holes of 7^4
+    ("sinprod", 4, 2, 4, 6),           # d = 4: 15^4, 3 coarse planes per axis
 ]
 
 
