@@ -22,6 +22,9 @@ bump centre):
   u = prod_i sin(pi k_i x_i)  (so g = 0).
 * ``sinbump3d``: d=3, alpha_i = 10**U[-1,0], beta_i ~ U[-5,5], k_i in {1..8};
   u = prod_i sin(pi k_i x_i) + exp(-|x-c|^2 / (2*0.1^2)), c ~ U[0.2,0.8]^3 (g != 0).
+* ``sinbump_wide``: d = 3 or 4 (default 3), the advection-dominated batch draws: alpha_i =
+  10**U[-2,0], beta_i ~ U[-10,10], k_i in {1..8}; u = prod_i sin(pi k_i x_i) + a Gaussian bump of
+  width 0.1 at c ~ U[0.2,0.8]^d (g != 0).
 * ``paper_smooth``: alpha_i = beta_i = 1, u = sin(pi*sum_i x_i) (Example 1 / Example 4, setting 1).
 * ``quadratic``: a product of quadratics with seeded coefficients (exact for the centred scheme).
 """
@@ -249,6 +252,15 @@ def make_problem(family: str, level: int, seed: int = 0, d: int | None = None,
         k = rng.integers(1, 9, size=3)
         c = rng.uniform(0.2, 0.8, size=3)
         man = _Sum([_SinProduct(3, k), _Bump(3, c, 0.1)])
+        meta["k"] = k.tolist()
+        meta["centre"] = c.tolist()
+    elif family == "sinbump_wide":
+        d = d or 3
+        alpha = 10.0 ** rng.uniform(-2.0, 0.0, size=d)
+        beta = rng.uniform(-10.0, 10.0, size=d)
+        k = rng.integers(1, 9, size=d)
+        c = rng.uniform(0.2, 0.8, size=d)
+        man = _Sum([_SinProduct(d, k), _Bump(d, c, 0.1)])
         meta["k"] = k.tolist()
         meta["centre"] = c.tolist()
     elif family == "paper_smooth":

@@ -378,3 +378,130 @@ def test_permutations_are_uniform_shuffles():
         assert len(counts) == math.factorial(d)
         expect = 3000 / math.factorial(d)
         assert all(abs(c - expect) < 6 * math.sqrt(expect) for c in counts.values())
+
+
+# ----------------------------------------------------------------------------- skeleton builder
+def _vanishing_cubic(x, shift, nc):
+    """A cubic with value 0 at x = 0 and x = 1, reproduced exactly by the not-a-knot spline of
+    Algorithm 2 step 5; with one interior knot (nc = 1) the spline is the parabola through the three
+    knots, so the parabola x (1 - x) is used there."""
+    if nc == 1:
+        return x * (1.0 - x) * (1.0 + shift)
+    return x * (1.0 - x) * (x - shift)
+
+
+@pytest.mark.parametrize("d,L,Lc", [(2, 5, 2), (3, 4, 2), (3, 4, 1), (4, 3, 1)])
+def test_skeleton_restores_submesh_values_shifted_by_splines(d, L, Lc):
+    """Algorithm 2 steps 4-6.  Take any fine vector F, set the cross-point values to F, and give each
+    anisotropic mesh M_k the solution F|M_k - c_k, where c_k is a product of cubics vanishing at 0 and 1
+    along M_k's fine axes times arbitrary values along its coarse axis.  The discrepancy at the
+    intersection points is then c_k (step 4), its spline extension over M_k is c_k again (step 5,
+    exact on such cubics), so the corrected solutions are F|M_k and the merge (step 6) returns F on
+    the whole skeleton and zero on the holes.  A dropped correction, a sign error in the
+    discrepancy or a correction taken from another mesh all leave c_k behind."""
+    g = Grid(d, L, Lc)
+    rng = np.random.default_rng(40 + d)
+    F = rng.standard_normal((g.Nf,) * d)
+    x = np.arange(1, g.Nf + 1) * g.h
+    o = Oracle(d, np.ones(d), np.zeros(d), L, Lc)
+    sols = {}
+    for k in range(d):
+        c = np.ones(g.mesh_dims((k,)))
+        for j in range(d):
+            shape = [1] * d
+            if j == k:
+                shape[j] = g.Nc
+                c = c * rng.uniform(0.5, 2.0, g.Nc).reshape(shape)
+            else:
+                shape[j] = g.Nf
+                c = c * _vanishing_cubic(x, 0.2 + 0.15 * j + 0.1 * k, g.Nc).reshape(shape)
+        assert np.max(np.abs(c)) > 1e-3
+        sols[(k,)] = g.restrict(F, (k,)) - 25.0 * c
+    out = o.skeleton(sols, F)
+    holes = g.hole_mask()
+    assert np.max(np.abs(out[~holes] - F[~holes])) <= 1e-12 * np.max(np.abs(F))
+    assert np.all(out[holes] == 0.0)
+
+
+@pytest.mark.parametrize("d,L,Lcs", [(2, 7, (2, 3, 4)), (3, 5, (2, 3))])
+def test_initial_guess_skeleton_error_is_fourth_order(d, L, Lcs):
+    """On a smooth solution that the scheme does not reproduce exactly, the skeleton of u^(0) is
+    O(H^4)-close to the fine discrete solution u_ff: the cross points are O(H^4) (Algorithm 2 step 2),
+    each submesh solution is O(H^2) off along its lines, and the spline correction of the discrepancy
+    (steps 4-5) removes that smooth O(H^2) part.  Without the correction, or with the discrepancy's
+    sign reversed, the error on the lines stays O(H^2) (ratio about 4 per halving of H)."""
+    P = make_problem("sinprod", L, seed=3, d=d)
+    uff = fine_direct_solve(d, P.alpha, P.beta, L, P.s, P.g)
+    errs = []
+    for Lc in Lcs:
+        o = Oracle(d, P.alpha, P.beta, L, Lc)
+        u0, _ = o.initial_guess(P.s, P.g)
+        skel = ~o.grid.hole_mask()
+        errs.append(np.max(np.abs(u0 - uff)[skel]))
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert all(q > 12.0 for q in ratios), (errs, ratios)
+
+
+# ----------------------------------------------------------------------------- error phase
+@pytest.mark.parametrize("d,L,Lc", [(2, 5, 2), (3, 4, 2)])
+def test_error_guess_normalises_each_submesh_solution(d, L, Lc):
+    """Algorithm 1 steps 2.1/2.2 in the error phase: each submesh solution is divided by its
+    Euclidean norm over the submesh's points.  With the axis order pi = (0, 1, ..) every
+    intersection point of M_0 takes M_0's own value, so the discrepancy on M_0 vanishes and the
+    merged guess restricted to M_0 is e_0 / ||e_0||_2: its 2-norm over M_0 is exactly 1.  The guess
+    is therefore also unchanged when the residual is scaled; an unnormalised guess would scale with
+    it and its norm over M_0 would be arbitrary."""
+    P = make_problem("sinprod", L, seed=2, d=d)
+    o = Oracle(d, P.alpha, P.beta, L, Lc, seed=5)
+    r = np.random.default_rng(9).standard_normal((o.grid.Nf,) * d)
+    perm = list(range(d))
+    e, norms = o.error_guess(r, perm)
+    on0 = o.grid.coarse_mask(0)
+    assert abs(np.linalg.norm(e[on0]) - 1.0) <= 1e-12
+    assert abs(norms[0] - 1.0) > 1e-3          # the raw solution is not already of unit norm
+    e_big, norms_big = o.error_guess(1234.5 * r, perm)
+    assert np.max(np.abs(e_big - e)) <= 1e-12 * np.max(np.abs(e))
+    assert abs(norms_big[0] / norms[0] - 1234.5) <= 1e-9 * 1234.5
+
+
+def test_chosen_crosspoints_hand_computed():
+    """Algorithm 2 step 3 with reading A5 (one choice per iteration, given by an axis order pi; a
+    point on several submeshes takes the value of the FIRST submesh of pi that contains it).  d = 3,
+    N_f = 3, N_c = 1: the coarse planes are the middle index 1 of each axis.  Submesh M_k holds the
+    value 100 (k+1) + 10 a + b at fine positions (a, b) of its two fine axes (in increasing axis
+    order).  With pi = (2, 0, 1): the corner (1,1,1) and the points of the x_0- and x_1-directed
+    edges lie on M_2 and take M_2's values; the x_2-directed edge (1,1,l) lies on M_0 and M_1 only
+    and takes M_0's values (0 comes before 1 in pi).  Every other point is 0."""
+    o = Oracle(3, np.ones(3), np.zeros(3), 2, 1, seed=0)
+    g = o.grid
+    assert g.Nf == 3 and g.Nc == 1 and list(g.cidx) == [1]
+    sols = {}
+    for k in range(3):
+        arr = np.zeros(g.mesh_dims((k,)))
+        fa, fb = [j for j in range(3) if j != k]
+        for a in range(3):
+            for b in range(3):
+                idx = [0, 0, 0]
+                idx[fa], idx[fb] = a, b
+                arr[tuple(idx)] = 100 * (k + 1) + 10 * a + b
+        sols[(k,)] = arr
+    uhat = o.chosen_crosspoints(sols, [2, 0, 1])
+    expect = np.zeros((3, 3, 3))
+    # corner: M_2 at fine positions (x_0, x_1) = (1, 1)
+    expect[1, 1, 1] = 311
+    # x_0-directed edge (i, 1, 1): M_2 at (i, 1)
+    expect[0, 1, 1], expect[2, 1, 1] = 301, 321
+    # x_1-directed edge (1, j, 1): M_2 at (1, j)
+    expect[1, 0, 1], expect[1, 2, 1] = 310, 312
+    # x_2-directed edge (1, 1, l): M_0 at fine positions (x_1, x_2) = (1, l)
+    expect[1, 1, 0], expect[1, 1, 2] = 110, 112
+    assert np.array_equal(uhat, expect)
+    # the same points with pi = (1, 2, 0): corner and x_0-, x_2-directed edges from M_1, the
+    # x_1-directed edge (on M_0 and M_2) from M_2
+    uhat = o.chosen_crosspoints(sols, [1, 2, 0])
+    expect = np.zeros((3, 3, 3))
+    expect[1, 1, 1] = 211                       # M_1 at (x_0, x_2) = (1, 1)
+    expect[0, 1, 1], expect[2, 1, 1] = 201, 221
+    expect[1, 1, 0], expect[1, 1, 2] = 210, 212
+    expect[1, 0, 1], expect[1, 2, 1] = 310, 312  # M_2 at (x_0, x_1) = (1, j)
+    assert np.array_equal(uhat, expect)
