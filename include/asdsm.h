@@ -67,7 +67,9 @@ typedef struct asdsm_plan_s *asdsm_plan_t;
 /* Options of asdsm_solve (max_iter < 8192).  Stopping rule (the paper's loop condition of Algorithm 4, read as
  * "iterate while not converged and not stagnated"): iterate while ||r_k||_2 > rtol*||b_ff||_2 and
  * k < max_iter and not stagnated; stagnated = ||r_{k+1}||_2 > (1 - stag_eta)*||r_k||_2 for
- * stag_window consecutive iterations (stag_window = 0 disables it), or a zero line-search step. */
+ * stag_window consecutive iterations (stag_window = 0 disables it).  A zero line-search step leaves
+ * u unchanged and counts as one such iteration; the next iteration draws another random choice of
+ * the cross points (Algorithm 2 step 3), so it does not end the loop by itself. */
 typedef struct {
     int    max_iter;      /* >= 0; 0 returns the initial guess of Algorithm 1                   */
     double rtol;          /* >= 0                                                                */

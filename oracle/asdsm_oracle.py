@@ -32,6 +32,11 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   spline_matrix -- exact on cubics vanishing at 0 and 1; unit rows at knots.
   boolean_sum_extend -- exact on tensor products of such cubics; reproduces data on every line.
   cross-point extrapolation -- O(H^4) convergence to the fine discrete solution; exact on Q2.
+  skeleton (Algorithm 2 steps 4-6) -- submesh values shifted by spline-reproducible functions are
+      restored exactly; the skeleton of u^(0) is O(H^4)-close to u_ff on smooth non-Q2 solutions.
+  chosen cross points (Algorithm 2 step 3) -- a hand-computed d = 3 case for two axis orders.
+  error-phase normalisation (Algorithm 1 steps 2.1/2.2) -- unit 2-norm over the submesh, invariance
+      under scaling of the residual.
   filler -- Proposition 3.2(1): Filler(skeleton of u_ff) = u_ff.
   asdsm iteration -- Proposition 3.2(2) (zero hole residual), Remark 3.4 (monotone residual),
       convergence towards a direct fine solve on tiny grids.
@@ -544,7 +549,9 @@ class Oracle:
               keep_iterates=False, u0=None, k0=0) -> AsdsmResult:
         """Outer iteration.  Continue while ||r_k||/||b|| > rtol, k < max_iter and not stagnated;
         stagnated means ||r_{k+1}|| > (1 - eta) ||r_k|| for stag_window consecutive iterations
-        (stag_window = 0 disables the test), or s_hat = 0."""
+        (stag_window = 0 disables the test).  A zero step s_hat = 0 leaves u unchanged and counts as
+        one such iteration; it does not end the loop by itself, since the next iteration draws a
+        new random choice of the cross points (Algorithm 2 step 3)."""
         if u0 is None:
             u, b_ff = self.initial_guess(s_fine, g_faces)
         else:
@@ -588,7 +595,7 @@ class Oracle:
             rn = rn_new
             k += 1
             it += 1
-            if shat == 0.0 or (stag_window > 0 and stag >= stag_window):
+            if stag_window > 0 and stag >= stag_window:
                 status = STATUS_STAGNATED
                 break
         res.u = u

@@ -502,7 +502,9 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
         }
         stt->stag = (rn > (1.0 - stt->stag_eta) * stt->rn_prev) ? stt->stag + 1 : 0;
         stt->rn_prev = rn;
-        if (shat == 0.0 || (stt->stag_window > 0 && stt->stag >= stt->stag_window)) {
+        // a zero step leaves u unchanged and counts towards the window like any step that does
+        // not reduce ||r|| enough; the next step draws another cross-point choice
+        if (stt->stag_window > 0 && stt->stag >= stt->stag_window) {
             stt->done = 1;
             stt->status = ASDSM_STAGNATED;
         } else if ((bn > 0.0 && rn <= stt->rtol * bn) || (bn == 0.0 && rn == 0.0)) {
