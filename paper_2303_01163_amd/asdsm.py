@@ -224,6 +224,17 @@ class Plan:
             aligned = (base + 255) // 256 * 256
             _check(lib.asdsm_set_workspace(self._h, c_void_p(aligned), c_size_t(self.workspace_bytes)))
 
+    def attach_workspace(self):
+        """Allocate a fresh device workspace and attach it (asdsm_set_workspace); returns the
+        previous workspace tensor, which the plan no longer uses."""
+        import torch
+        old = self._ws
+        with torch.cuda.device(self.device):
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self._ws.data_ptr() + 255) // 256 * 256
+            _check(load_library().asdsm_set_workspace(self._h, c_void_p(aligned), c_size_t(self.workspace_bytes)))
+        return old
+
     @property
     def n_fine(self) -> int:
         return self.n_f ** self.d

@@ -1102,6 +1102,14 @@ void destroy_graph(Plan &p) {
     p.graph_exec = nullptr;
     p.graph = nullptr;
     p.graph_u = nullptr;
+    p.graph_gen = 0;
+}
+
+// Something the captured launches depend on changed (workspace, tile, sweep counts): drop the
+// plan's graph and let every batch graph holding this plan see the new generation.
+void plan_changed(Plan &p) {
+    ++p.generation;
+    destroy_graph(p);
 }
 
 // Capture two gated refinement steps (u -> u2 -> u) into a graph, replayed by the solve loop.  The
@@ -1130,6 +1138,7 @@ int build_graph(Plan &p, double *u) {
         return fail(ASDSM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
     p.graph_u = u;
+    p.graph_gen = p.generation;
     p.graph_prec32 = p.prec32;
     p.graph_sparse = p.sparse;
     p.graph_net_serial = p.learn_net ? p.learn_net->serial : 0;
@@ -1190,7 +1199,7 @@ int autotune_impl(Plan &p, int reps, int *best_tile, double *best_ms) {
         }
     }
     p.tile_aniso = best;
-    destroy_graph(p);  // captured launches carry the old tile choice
+    plan_changed(p);  // captured launches carry the old tile choice
     if (best_tile) *best_tile = best;
     if (best_ms) *best_ms = best_t;
     return ASDSM_OK;
@@ -1266,6 +1275,29 @@ int begin_solve(Plan &p, const double *s, const double *g, double *u, const asds
         launch_update_residual(p, u, nullptr, nullptr, gat, kFinInit, p.stream);
         if (int rc = check_launch("residual")) return rc;
     }
+    if (p.sparse && opt.resume) {
+        // The skeleton-sparse loop relies on a zero residual in the holes (Proposition 3.2(2)),
+        // which every ASDSM iterate has.  A resumed iterate that may come from elsewhere gets its
+        // holes re-filled from its own skeleton first (Algorithm 3 with b_ff); for an ASDSM
+        // iterate that changes nothing beyond rounding.
+        {
+            PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 0.0, 8.0 * 4.0 * aniso_points(p));
+            launch_skel_gather(p, u, p.stream);
+            if (int rc = check_launch("skeleton gather")) return rc;
+        }
+        {
+            PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
+                         8.0 * (2.0 * (double)p.geo.NF + aniso_points(p)));
+            launch_filler(p, p.ws.b, u, p.stream, p.ws.SU, false);
+            if (int rc = check_launch("resume fill")) return rc;
+        }
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,
+                     8.0 * (3.0 * (double)p.geo.NF + aniso_points(p)));
+        double *gat[kMaxMeshes];
+        gather_pointers(p, gat);
+        launch_update_residual(p, u, nullptr, nullptr, gat, kFinInit, p.stream);
+        if (int rc = check_launch("residual")) return rc;
+    }
     if (p.sparse) {  // u and r on the skeleton, from the fine vectors
         PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 0.0, 8.0 * 4.0 * aniso_points(p));
         launch_skel_gather(p, u, p.stream);
@@ -1324,7 +1356,8 @@ int end_solve(Plan &p, double *u, const asdsm_opts &opt, asdsm_stats *st) {
         st->iterations = it;
         st->bnorm = std::sqrt(p.hscal[kScalBnorm2]);
         st->r0norm = r0;
-        st->rnorm = rn;
+        // the skeleton-sparse loop recomputes the residual of the rebuilt fine iterate at the end
+        st->rnorm = p.sparse ? std::sqrt(p.hscal[kScalRnorm2]) : rn;
         st->precision = p.prec32 ? ASDSM_PREC_FP32 : ASDSM_PREC_FP64;
         for (int q = 0; q < ASDSM_NPHASE; ++q) {
             st->phase_ms[q] = p.phase_ms[q];
@@ -1363,7 +1396,8 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
     if (use_graph) {
         const uint64_t net_serial = p.learn_net ? p.learn_net->serial : 0;
         const void *net_ws = p.learn_net ? p.learn_net->ws : nullptr;
-        if (p.graph_u != u || !p.graph_exec || p.graph_prec32 != p.prec32 || p.graph_sparse != p.sparse ||
+        if (p.graph_u != u || !p.graph_exec || p.graph_gen != p.generation || p.graph_prec32 != p.prec32 ||
+            p.graph_sparse != p.sparse ||
             p.graph_net_serial != net_serial ||
             p.graph_net_ws != net_ws || (p.learn_net && p.graph_factor != p.learn_factor))
             rc = build_graph(p, u);
@@ -1423,6 +1457,7 @@ struct Batch {
     hipGraphExec_t exec = nullptr;
     std::vector<double *> graph_u;
     std::vector<bool> graph_prec32;
+    std::vector<uint64_t> graph_gen;         // each member's plan generation at capture
 };
 
 void destroy_batch_graph(Batch &b) {
@@ -1432,6 +1467,7 @@ void destroy_batch_graph(Batch &b) {
     b.graph = nullptr;
     b.graph_u.clear();
     b.graph_prec32.clear();
+    b.graph_gen.clear();
 }
 
 void release_batch(Batch &b) {
@@ -1505,7 +1541,10 @@ int capture_batch_graph(Batch &b, double *const *u) {
         return fail(ASDSM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
     b.graph_u.assign(u, u + n);
-    for (int i = 0; i < n; ++i) b.graph_prec32.push_back(b.plans[i]->prec32);
+    for (int i = 0; i < n; ++i) {
+        b.graph_prec32.push_back(b.plans[i]->prec32);
+        b.graph_gen.push_back(b.plans[i]->generation);
+    }
     return ASDSM_OK;
 }
 
@@ -1536,7 +1575,8 @@ int batch_solve_impl(Batch &b, const double *const *s, const double *const *g, d
     }
     bool rebuild = !b.exec || (int)b.graph_u.size() != n;
     for (int i = 0; i < n && !rebuild; ++i)
-        rebuild = b.graph_u[i] != u[i] || b.graph_prec32[i] != b.plans[i]->prec32;
+        rebuild = b.graph_u[i] != u[i] || b.graph_prec32[i] != b.plans[i]->prec32 ||
+                  b.graph_gen[i] != b.plans[i]->generation;
     int rc = rebuild ? capture_batch_graph(b, u) : ASDSM_OK;
     int steps = 0;
     while (rc == ASDSM_OK) {
@@ -1622,6 +1662,7 @@ int asdsm_set_workspace(asdsm_plan_t plan, void *dev, size_t bytes) {
     if (((uintptr_t)dev & 255u) != 0) return fail(ASDSM_E_WORKSPACE, "workspace must be 256-byte aligned");
     if (bytes < p.ws_need)
         return fail(ASDSM_E_WORKSPACE, "workspace too small: need " + std::to_string(p.ws_need) + " bytes");
+    plan_changed(p);  // a captured graph points into the previous workspace
     p.ws_base = dev;
     p.ws_bytes = bytes;
     layout_workspace(p, (char *)dev, true);
@@ -1777,7 +1818,7 @@ int asdsm_set_tile(asdsm_plan_t plan, int tile) {
         return fail(ASDSM_E_UNSUPPORTED, "plane transforms need d = 3 and N_f <= 255");
     if (tile != p.tile_aniso) {
         p.tile_aniso = tile;
-        destroy_graph(p);  // captured launches carry the old tile choice
+        plan_changed(p);  // captured launches carry the old tile choice
     }
     set_error("");
     return ASDSM_OK;

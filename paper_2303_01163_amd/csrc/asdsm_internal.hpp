@@ -123,6 +123,9 @@ struct Plan {
     double alpha[kMaxD] = {}, beta[kMaxD] = {};
     uint64_t seed = 0;
     uint64_t serial = 0;  // unique per plan object (never 0)
+    // bumped whenever something that captured launches depend on changes (the workspace layout, the
+    // transform tile, the sweep counts); a captured graph is replayed only while it matches
+    uint64_t generation = 1;
     hipStream_t stream = nullptr;
     int device = 0;
     Geo geo{};
@@ -181,6 +184,7 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     const double *graph_u = nullptr;
+    uint64_t graph_gen = 0;          // generation the graph was captured at
     bool graph_prec32 = false;
     bool graph_sparse = false;
     // learned proposals (a correction network bound to this plan) for this call, and the network

@@ -623,3 +623,58 @@ def test_skeleton_sparse_resume_and_fp32(torch_dev):
     us, is_ = pl.solve(s, g, max_iter=5, rtol=0, stag_window=0, precision="fp32", skeleton=True)
     assert if_["precision"] == is_["precision"]
     assert _rel(us.cpu().numpy(), uf.cpu().numpy()) <= TOL_ITER
+
+
+def test_new_workspace_rebuilds_the_captured_graph(torch_dev):
+    """A plan's captured refinement graph points into its workspace: after asdsm_set_workspace the
+    next solve (same iterate pointer) must use the new workspace.  The old one is overwritten with
+    NaN before that solve; the result must equal a fresh plan's bit for bit, for a single plan and
+    for a member of a batch."""
+    import torch
+    from paper_2303_01163_amd import asdsm
+    P = make_problem("sinbump3d", 5, seed=4)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    kw = dict(max_iter=6, rtol=0, stag_window=0)
+    fresh = _plan(P, 5, 2, seed=4)
+    want, _ = fresh.solve(s, g, **kw)
+    pl = _plan(P, 5, 2, seed=4)
+    u = torch.empty_like(want)
+    pl.solve(s, g, u=u, **kw)                     # captures the graph
+    old = pl.attach_workspace()
+    old.fill_(255)                                # all-ones bytes: NaN doubles
+    pl.solve(s, g, u=u, **kw)
+    assert torch.equal(u, want)
+    # batch member: the batch graph is rebuilt when a member's workspace changes
+    P2 = make_problem("sinbump3d", 5, seed=6)
+    s2, g2 = _t(torch_dev, P2.s_flat()), _t(torch_dev, P2.g_flat())
+    want2, _ = _plan(P2, 5, 2, seed=6).solve(s2, g2, **kw)
+    pl2 = _plan(P2, 5, 2, seed=6)
+    u2 = torch.empty_like(want2)
+    batch = asdsm.Batch([pl, pl2])
+    batch.solve([s, s2], [g, g2], us=[u, u2], **kw)
+    old2 = pl2.attach_workspace()
+    old2.fill_(255)
+    batch.solve([s, s2], [g, g2], us=[u, u2], **kw)
+    batch.close()
+    assert torch.equal(u, want) and torch.equal(u2, want2)
+
+
+def test_skeleton_sparse_resume_from_any_iterate(torch_dev):
+    """Resuming the skeleton-sparse loop from an iterate that did not come from ASDSM: its holes are
+    re-filled from its skeleton first (Algorithm 3), so the loop's assumption of a zero hole
+    residual (Proposition 3.2(2)) holds; the returned iterate has a zero hole residual and the
+    reported residual norm is that of the returned iterate."""
+    P = make_problem("sinbump3d", 5, seed=5)
+    pl = _plan(P, 5, 2, seed=3)
+    o = Oracle(3, P.alpha, P.beta, 5, 2)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    rng = np.random.default_rng(1)
+    u0 = _t(torch_dev, (P.u_exact + 0.01 * rng.standard_normal(P.u_exact.shape)).reshape(-1, order="F"))
+    u, info = pl.solve(s, g, u=u0.clone(), max_iter=4, rtol=0, stag_window=0, skeleton=True, resume=True, k0=0)
+    r, nrm = pl.residual(u, s, g)
+    assert abs(info["rnorm"] - nrm) <= 1e-12 * nrm
+    rr = r.cpu().numpy().reshape((31,) * 3, order="F")
+    holes = o.grid.hole_mask()
+    assert np.max(np.abs(rr[holes])) <= 1e-11 * info["bnorm"]
+    h = info["res_hist"]
+    assert all(h[i + 1] <= h[i] * (1 + 1e-12) for i in range(len(h) - 1))
