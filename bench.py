@@ -1,12 +1,16 @@
 """Benchmark of the ASDSM hot path on one MI355X.
 
-One step = one complete asdsm_solve on the 127^3 workload (d = 3, h = 1/128, H = 1/8): right-hand
-sides, Algorithm 1 (submesh solves, cross points, spline merge, filler) and the refinement loop of
-Algorithm 4 until the relative residual reaches 1e-10 or the stagnation rule stops it (window 3,
-eta = 1e-3), at most 50 iterations.  Inputs (s, g) are resident in HBM before the timed region.
+One step = one complete asdsm_solve on the 127^3 workload (d = 3, h = 1/128, H = 1/8, seed 0):
+right-hand sides, Algorithm 1 (submesh solves, cross points, spline merge, filler) and the
+refinement loop of Algorithm 4 until the relative residual ||r||/||b|| falls below 1e-10 (the
+workload's stopping rule; no stagnation cut-off, at most 4000 steps).  Inputs (s, g) are resident
+in HBM before the timed region.  The value is counted only when the solve reaches that residual:
+the relative L2 error of the returned iterate against the FP64 oracle's fine solution u_ff is
+measured in the CPU-baseline leg (and by the full-size GPU test) and must be <= 1e-8.
 
-Prints ONE JSON line with the metric, the roofline position of the dominant kernel (timed with HIP
-events on the library's stream) and the oracle timed on this host's cores on a bounded sample.
+Prints ONE JSON line with the metric, the roofline position of the dominant kernel (its own
+launches, timed with HIP events on the library's stream) and the oracle timed on this host's cores
+on a bounded sample.
 """
 from __future__ import annotations
 
@@ -82,41 +86,66 @@ def phase_rate(phase, ph_ms, ph_n, ph_by):
             "GB/s": ph_by[phase] / (ms * 1e-3) / 1e9 if ms > 0 else None}
 
 
-def roofline(phase, ph_ms, ph_n, ph_fl, ph_by, workload, transform_kernel="k_gemm_f64"):
-    """Roofline position of the phase with the largest device time: algorithmic work per launch /
-    average launch duration, against the MI355X peak of its bound (FP64 MFMA for the mode
-    transforms, HBM for the rest).  The transform phase runs k_gemm_f64 (one launch per fine axis)
-    or k_plane2 (both fine axes of a coarse slab per launch), as the plan's tile choice says."""
-    ms, n = ph_ms[phase], max(ph_n[phase], 1)
-    kernel = transform_kernel if phase == "transform" else PHASE_KERNEL.get(phase, phase)
-    avg_ms = ms / n
-    if phase == "transform":
-        per_launch = ph_fl[phase] / n
+MFMA_KINDS = ("k_plane2", "k_gemm_f64", "hole filler")
+
+
+def kernel_roofline(kprof, workload):
+    """Roofline position of the dominant kernel of a profiled solve: the launch-group kind (one
+    kernel per group) with the largest device time; achieved = its algorithmic work per launch
+    divided by its average launch duration (HIP event pairs stamped by the kernel itself on the
+    library's stream), against the FP64 MFMA peak for the mode transforms and the hole solves and
+    the HBM peak for the rest."""
+    kernels = [k for k in kprof if not k["name"].startswith("phase:") and k["launches"] > 0]
+    dom = max(kernels, key=lambda k: k["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    base = dom["name"].split()[0]
+    if any(dom["name"].startswith(x) for x in MFMA_KINDS):
+        per_launch = dom["flops"] / dom["launches"]
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         bound, peak, unit = "mfma", FP64_PEAK_TFLOPS, "TFLOP/s"
     else:
-        per_launch = ph_by[phase] / n
+        per_launch = dom["bytes"] / dom["launches"]
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": pmc_traffic(kernel, workload), "kernel": kernel,
-            "phase": phase, "launches": ph_n[phase], "avg_launch_ms": avg_ms,
+            "frac": achieved / peak, "traffic": pmc_traffic(base, workload), "kernel": dom["name"],
+            "launches": dom["launches"], "avg_launch_ms": avg_ms,
             "algorithmic_per_launch": per_launch,
-            "algorithmic_bytes_per_launch": ph_by[phase] / n}
+            "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
+            "share_of_profiled_device_time": dom["ms"] / sum(k["ms"] for k in kprof)}
+
+
+def kernel_table(kprof):
+    """Per launch-group kind: launches, average duration and achieved rate of its algorithmic work."""
+    out = {}
+    for k in sorted(kprof, key=lambda k: -k["ms"]):
+        n = max(k["launches"], 1)
+        avg = k["ms"] / n
+        out[k["name"]] = {"launches": k["launches"], "ms": k["ms"], "avg_launch_us": 1e3 * avg,
+                          "TFLOP/s": k["flops"] / n / (avg * 1e-3) / 1e12 if avg > 0 else None,
+                          "GB/s": k["bytes"] / n / (avg * 1e-3) / 1e9 if avg > 0 else None}
+    return out
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--level", type=int, default=7)
     ap.add_argument("--coarse-level", type=int, default=0)
-    ap.add_argument("--max-iter", type=int, default=50)
+    ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--stag-window", type=int, default=0,
+                    help="stagnation window of the timed solves (0: stop on the residual target only)")
+    ap.add_argument("--side-max-iter", type=int, default=50,
+                    help="step limit of the side comparisons (mixed precision, batch, d = 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle refinement steps in the sample")
+    ap.add_argument("--cpu-iters", type=int, default=8,
+                    help="oracle refinement steps in the all-cores sample")
+    ap.add_argument("--cpu-iters-1t", type=int, default=2,
+                    help="oracle refinement steps in the single-thread sample (0 skips it)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="error-phase submesh solves of the timed solves")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
@@ -159,7 +188,7 @@ def main():
     u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
     # the skeleton-sparse loop (same iterates up to rounding) unless the fine-mesh loop is asked for
     skeleton = not args.fine_loop
-    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3,
+    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=args.stag_window, stag_eta=1e-3,
               precision=args.precision, skeleton=skeleton)
     tuned = plan.autotune(repeats=10) if not args.no_autotune else None
 
@@ -176,28 +205,28 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     iters = infos[-1]["iterations"]
     n_fine = plan.n_fine
-    value = n_fine / (ms_per_step * 1e-3)
+    converged = infos[-1]["status_name"] == "ok"
+    # counted only when the solve met its residual target (the error check is below)
+    value = n_fine / (ms_per_step * 1e-3) if converged else None
 
-    # per-phase device times: one more identical solve, eager, with HIP events on the library's
+    # per-kernel device times: one more identical solve, eager, with HIP events on the library's
     # stream around every launch group, and the algorithmic flops / bytes of those launches
-    _, prof = plan.solve(s, g, u=u, profile=True, **kw)
+    _, prof = plan.solve(s, g, u=torch.empty_like(u), profile=True, **kw)
     ph_ms, ph_n = prof["phase_ms"], prof["phase_launches"]
     ph_fl, ph_by = prof["phase_flops"], prof["phase_bytes"]
+    kprof = plan.kernel_profile()
     Nf = plan.n_f
-    dominant = max(ph_ms, key=lambda k: ph_ms[k])
-    tkernel = "k_plane2" if plan.tile_name().startswith("plane") else "k_gemm_f64"
-    roof = roofline(dominant, ph_ms, ph_n, ph_fl, ph_by,
-                    (f"asdsm-3d-{Nf}^3-sinbump-seed{args.seed}", plan.coarse_level), tkernel)
-    # the fine-mesh stencil passes (k_update_residual3, k_dots3) are timed in a fine-loop solve; in
-    # the skeleton-sparse solve those phases hold the compact skeleton kernels
+    workload = (f"asdsm-3d-{Nf}^3-sinbump-seed{args.seed}", plan.coarse_level)
+    roof = kernel_roofline(kprof, workload)
+    # the fine-mesh stencil passes (k_update_residual3, k_dots3) are timed in a fine-loop solve of
+    # 50 steps; in the skeleton-sparse solve those phases hold the compact skeleton kernels
     if skeleton:
-        _, prof_f = plan.solve(s, g, u=torch.empty_like(u), profile=True, **dict(kw, skeleton=False))
+        _, prof_f = plan.solve(s, g, u=torch.empty_like(u), profile=True,
+                               **dict(kw, skeleton=False, max_iter=50, rtol=0.0))
         stencil = {q: phase_rate(q, prof_f["phase_ms"], prof_f["phase_launches"], prof_f["phase_bytes"])
                    for q in ("update", "dots")}
-        skel_rates = {q: dict(phase_rate(q, ph_ms, ph_n, ph_by), kernel=SKEL_KERNEL[q]) for q in ("update", "dots")}
     else:
         stencil = {q: phase_rate(q, ph_ms, ph_n, ph_by) for q in ("update", "dots")}
-        skel_rates = None
 
     out = {
         "metric": METRIC,
@@ -215,25 +244,29 @@ def main():
         "config": {"workload": f"asdsm-3d-{Nf}^3-sinbump-seed{args.seed}", "d": 3, "level": L,
                    "coarse_level": plan.coarse_level, "fine_unknowns": n_fine,
                    "alpha": [float(x) for x in P.alpha], "beta": [float(x) for x in P.beta],
-                   "rtol": args.rtol, "stag_window": 3, "max_iter": args.max_iter},
+                   "rtol": args.rtol, "stag_window": args.stag_window, "max_iter": args.max_iter},
         "iterations": iters,
         "status": infos[-1]["status_name"],
         "rel_residual": infos[-1]["rnorm"] / infos[-1]["bnorm"],
         "rel_residual_init": infos[-1]["r0norm"] / infos[-1]["bnorm"],
         "unknown_iterations_per_s": n_fine * iters / (ms_per_step * 1e-3),
+        "us_per_refinement_step": 1e3 * ms_per_step / max(iters, 1),
         "phase_ms": ph_ms,
         "phase_launches": ph_n,
         "phase_gflop": {k: v / 1e9 for k, v in ph_fl.items()},
         "phase_mb": {k: v / 1e6 for k, v in ph_by.items()},
         "profiled_total_ms": prof["total_ms"],
         "roofline": roof,
+        "kernels": kernel_table(kprof),
         "stencil_effective": stencil,
-        "skeleton_effective": skel_rates,
     }
+    if not converged:
+        out["value_note"] = ("UNMEASURED: the timed solve stopped before ||r||/||b|| <= rtol "
+                             f"(status {infos[-1]['status_name']})")
     out["precision_used"] = infos[-1]["precision"]
     out["refinement_loop"] = "skeleton-sparse" if skeleton else "fine-mesh"
     if skeleton:
-        out["fine_loop_comparison"] = fine_loop(plan, s, g, kw, u, args.steps)
+        out["fine_loop_comparison"] = fine_loop(plan, s, g, kw, u, 2)
     out["autotune"] = tuned
     # the device's own ceilings next to the datasheet peaks of the roofline
     ceil = {"mfma_f64_tflops": asdsm.probe_mfma_f64(), "copy_tbps": asdsm.probe_copy()}
@@ -251,7 +284,13 @@ def main():
     if args.d4_level > 0:
         out["d4"] = four_d(asdsm, make_problem, args, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P, L, args, iters)
+        cb = cpu_baseline(P, L, args, iters, u.cpu().numpy())
+        out["cpu_baseline"] = cb
+        out["rel_l2_err_vs_oracle"] = cb.get("gpu_rel_l2_err_vs_oracle_u_ff")
+        if value is not None and not (out["rel_l2_err_vs_oracle"] is not None
+                                      and out["rel_l2_err_vs_oracle"] <= 1e-8):
+            out["value"] = None
+            out["value_note"] = "UNMEASURED: the error against the oracle's u_ff exceeds 1e-8"
     print(json.dumps(out))
 
 
@@ -270,7 +309,7 @@ def four_d(asdsm, make_problem, args, dev, seed=0, steps=3):
     s = torch.from_numpy(P.s_flat()).to(dev)
     g = torch.from_numpy(P.g_flat()).to(dev)
     u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
-    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
+    kw = dict(max_iter=args.side_max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
     plan.solve(s, g, u=u, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -305,7 +344,7 @@ def four_d_mixed(asdsm, make_problem, args, dev, L, Lc, seed=1, steps=3):
     us = {}
     for prec in ("fp64", "fp32"):
         u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
-        kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3, precision=prec)
+        kw = dict(max_iter=args.side_max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3, precision=prec)
         plan.solve(s, g, u=u, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -330,7 +369,7 @@ def four_d_batch(asdsm, make_problem, args, dev, L, Lc, steps=2):
         ss.append(torch.from_numpy(P.s_flat()).to(dev))
         gs.append(torch.from_numpy(P.g_flat()).to(dev))
     us = [torch.empty(p.n_fine, dtype=torch.float64, device=dev) for p in plans]
-    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
+    kw = dict(max_iter=args.side_max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
     for p, s, g, u in zip(plans, ss, gs, us):
         p.solve(s, g, u=u, **kw)
     torch.cuda.synchronize()
@@ -383,7 +422,7 @@ def mixed_precision(asdsm, make_problem, L, args, dev, seed=1, steps=3):
     res = {}
     for prec in ("fp64", "fp32"):
         u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
-        kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3, precision=prec)
+        kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=args.stag_window, stag_eta=1e-3, precision=prec)
         plan.solve(s, g, u=u, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -416,7 +455,7 @@ def batched(asdsm, make_problem, args, dev, steps=3):
         ss.append(torch.from_numpy(P.s_flat()).to(dev))
         gs.append(torch.from_numpy(P.g_flat()).to(dev))
     us = [torch.empty(p.n_fine, dtype=torch.float64, device=dev) for p in plans]
-    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
+    kw = dict(max_iter=args.max_iter, rtol=args.rtol, stag_window=args.stag_window, stag_eta=1e-3)
     unknowns = sum(p.n_fine for p in plans)
     for pl, s, g, u in zip(plans, ss, gs, us):
         pl.solve(s, g, u=u, **kw)
@@ -499,30 +538,48 @@ def learned(asdsm, make_problem, L, args, dev):
             "residual_gain": plain["min_rel_residual"] / best["min_rel_residual"]}
 
 
-def cpu_baseline(P, L, args, gpu_iters):
-    """The FP64 oracle as it stands on this host: plan + initial guess + args.cpu_iters refinement
-    steps on the same 127^3 problem; the full-solve time is extrapolated to the GPU's iteration
-    count (init + gpu_iters steps) and expressed in fine unknowns/s."""
+def cpu_baseline(P, L, args, gpu_iters, u_gpu):
+    """The FP64 oracle as it stands on this host, on a bounded sample of the timed workload: plan +
+    initial guess (Algorithm 1) and args.cpu_iters refinement steps with every host core, then the
+    same with one thread (args.cpu_iters_1t steps); each is scaled to the GPU solve's length (init +
+    gpu_iters steps).  Also the oracle's fine solution u_ff (preconditioned GMRES, the error
+    reference of the metric) and the GPU iterate's relative L2 error against it."""
     import numpy as np
-    from oracle.asdsm_oracle import Oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    o = Oracle(3, P.alpha, P.beta, L, args.coarse_level or None, seed=args.seed)
-    u0, b = o.initial_guess(P.s, P.g)
-    t_init = time.perf_counter() - t0
-    t1 = time.perf_counter()
-    o.solve(P.s, P.g, max_iter=args.cpu_iters, rtol=0.0, stag_window=0, u0=u0)
-    t_it = (time.perf_counter() - t1) / max(args.cpu_iters, 1)
-    est = t_init + gpu_iters * t_it
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle.asdsm_oracle import Oracle, fine_reference_solve
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     n = (2 ** L - 1) ** 3
-    return {"value": n / est, "unit": "fine unknowns/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"plan+initial guess ({t_init:.2f} s) and {args.cpu_iters} refinement step(s) "
-                      f"({t_it:.2f} s each) of the same {2**L-1}^3 problem, extrapolated to "
-                      f"init + {gpu_iters} steps ({est:.1f} s)"}
+
+    def sample(k):
+        t0 = time.perf_counter()
+        o = Oracle(3, P.alpha, P.beta, L, args.coarse_level or None, seed=args.seed)
+        u0, _ = o.initial_guess(P.s, P.g)
+        t_init = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        o.solve(P.s, P.g, max_iter=k, rtol=0.0, stag_window=0, u0=u0)
+        t_step = (time.perf_counter() - t1) / max(k, 1)
+        return t_init, t_step
+
+    t_init, t_step = sample(args.cpu_iters)
+    full = t_init + gpu_iters * t_step
+    out = {"value": n / full, "unit": "fine unknowns/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"plan + initial guess ({t_init:.2f} s) and {args.cpu_iters} refinement steps "
+                     f"({t_step:.3f} s each, measured) of the same {2**L-1}^3 problem on {threads} "
+                     f"threads, scaled to init + {gpu_iters} steps ({full:.0f} s)",
+           "init_s": t_init, "step_s": t_step}
+    if args.cpu_iters_1t > 0:
+        with threadpool_limits(1):
+            t_init1, t_step1 = sample(args.cpu_iters_1t)
+        full1 = t_init1 + gpu_iters * t_step1
+        out["single_thread"] = {"value": n / full1, "cores": 1, "init_s": t_init1, "step_s": t_step1,
+                                "sample": f"init and {args.cpu_iters_1t} steps on one thread, scaled "
+                                          f"to init + {gpu_iters} steps ({full1:.0f} s)"}
+    t0 = time.perf_counter()
+    uff, rr = fine_reference_solve(3, P.alpha, P.beta, L, P.s, P.g, precond="line")
+    f = uff.reshape(-1, order="F")
+    out["u_ff"] = {"seconds": time.perf_counter() - t0, "rel_residual": rr}
+    out["gpu_rel_l2_err_vs_oracle_u_ff"] = float(np.linalg.norm(u_gpu - f) / np.linalg.norm(f))
+    return out
 
 
 if __name__ == "__main__":

@@ -216,6 +216,19 @@ size_t asdsm_probe_mfma_scratch_bytes(void);
 int asdsm_probe_mfma_f64(void *scratch, int iters, void *hip_stream, double *tflops);
 int asdsm_probe_copy(const void *src, void *dst, size_t bytes, int reps, void *hip_stream, double *tbps);
 
+/* Launch groups of the last asdsm_solve made with opts->profile = 1, by kind (a roofline per
+ * kernel rather than per phase).  A kind is one kernel (its name, e.g. "k_plane2 forward") when
+ * each of its groups is a single launch of that kernel, else "phase:<phase name>".
+ * asdsm_profile_count: number of kinds (0 when the last call was not profiled), or an error.
+ * asdsm_profile_entry: kind i (0 <= i < count): name (host buffer of name_cap bytes, truncated and
+ *   NUL-terminated), phase (ASDSM_PHASE_*), ms (device time summed over the groups, from HIP event
+ *   pairs on the plan's stream that the kernels themselves stamp), groups, kernel launches, and
+ *   the algorithmic flops and bytes of those launches (every operand read once, every result
+ *   written once).  Any output pointer may be NULL.  Errors: ASDSM_E_ARG. */
+int asdsm_profile_count(asdsm_plan_t plan);
+int asdsm_profile_entry(asdsm_plan_t plan, int i, char *name, int name_cap, int *phase, double *ms,
+                        int *groups, int *launches, double *flops, double *bytes);
+
 /* Release the plan and its tables (not the workspace).  NULL is ignored. */
 void asdsm_destroy(asdsm_plan_t plan);
 

@@ -56,7 +56,7 @@ from scipy.interpolate import CubicSpline
 __all__ = [
     "Grid", "op1d", "assemble_operator", "apply_operator", "BandedBoxSolver", "rhs_on_mesh",
     "spline_matrix", "boolean_sum_extend", "splitmix64_stream", "permutation",
-    "Oracle", "AsdsmResult", "fine_direct_solve",
+    "Oracle", "AsdsmResult", "fine_direct_solve", "fine_reference_solve",
 ]
 
 _MASK64 = (1 << 64) - 1
@@ -610,3 +610,129 @@ def fine_direct_solve(d, alpha, beta, level, s_fine, g_faces) -> np.ndarray:
     coeffs = mesh_coeffs(g, alpha, beta, ())
     b = rhs_on_mesh(g, (), s_fine, g_faces, alpha, beta)
     return BandedBoxSolver((g.Nf,) * d, coeffs).solve(b)
+
+
+# --------------------------------------------------------------------------------------------
+# Reference fine solution u_ff = A_ff^-1 b_ff at any size (used only to measure errors)
+# --------------------------------------------------------------------------------------------
+def _along(x: np.ndarray, M: np.ndarray, j: int) -> np.ndarray:
+    """y = M applied along axis j of x: y[.., i, ..] = sum_m M[i, m] x[.., m, ..]."""
+    return np.moveaxis(np.tensordot(M, x, axes=([1], [j])), 0, j)
+
+
+class _TensorPreconditioner:
+    """Approximate inverse of a Kronecker-sum operator (Section 2.3) on a box.
+
+    Every axis except `line_axis` is diagonalised with the eigen-decomposition of its 1D operator
+    (LAPACK, complex where the spectrum is complex); with line_axis = None every axis is, and each
+    mode is divided by the sum of its eigenvalues.  Otherwise each mode of the diagonalised axes
+    leaves a shifted tridiagonal system along line_axis, solved by banded LU with partial pivoting.
+    In exact arithmetic both forms are the exact inverse; in floating point they lose accuracy with
+    the condition numbers of the eigenvector matrices, which is why they only precondition the
+    Krylov iteration of fine_reference_solve."""
+
+    def __init__(self, dims, coeffs, line_axis=None):
+        self.dims = tuple(dims)
+        self.coeffs = coeffs
+        self.line = line_axis
+        self.eig = []
+        for j, (n, (a, b, c)) in enumerate(zip(dims, coeffs)):
+            if j == line_axis:
+                self.eig.append(None)
+                continue
+            T = np.diag(np.full(n, b)) + np.diag(np.full(n - 1, a), -1) + np.diag(np.full(n - 1, c), 1)
+            lam, V = np.linalg.eig(T)
+            self.eig.append((lam, V, np.linalg.inv(V)))
+
+    def __call__(self, f: np.ndarray) -> np.ndarray:
+        d = len(self.dims)
+        y = f.astype(np.complex128)
+        shift = np.zeros((1,) * d, dtype=np.complex128)
+        for j in range(d):
+            if self.eig[j] is None:
+                continue
+            lam, _, Vinv = self.eig[j]
+            y = _along(y, Vinv, j)
+            shape = [1] * d
+            shape[j] = self.dims[j]
+            shift = shift + lam.reshape(shape)
+        if self.line is None:
+            y = y / shift
+        else:
+            L = self.line
+            a, b, c = self.coeffs[L]
+            n = self.dims[L]
+            ym = np.moveaxis(y, L, 0)
+            rest = ym.shape[1:]
+            ym = ym.reshape(n, -1)
+            # the shift of every mode, in the same order as the columns of ym
+            sh = np.moveaxis(np.broadcast_to(shift, y.shape), L, 0)[0].reshape(-1)
+            out = np.empty_like(ym)
+            ab = np.zeros((3, n), dtype=np.complex128)
+            ab[0, 1:] = c
+            ab[2, :-1] = a
+            for q in range(ym.shape[1]):
+                ab[1, :] = b + sh[q]
+                out[:, q] = sla.solve_banded((1, 1), ab, ym[:, q])
+            y = np.moveaxis(out.reshape((n,) + rest), 0, L)
+        for j in range(d):
+            if self.eig[j] is None:
+                continue
+            y = _along(y, self.eig[j][1], j)
+        return y.real
+
+
+def fine_reference_solve(d, alpha, beta, level, s_fine, g_faces, precond="fdm", tol=1e-14,
+                         max_outer=12):
+    """Reference fine solution u_ff = A_ff^-1 b_ff (Section 2.3 system) for grids too large for
+    banded LU, used only to measure the error of ASDSM iterates, never inside ASDSM.
+
+    Preconditioned GMRES (scipy) inside FP64 iterative refinement: the outer loop forms the true
+    residual r = b - A x with the assembled sparse A_ff, GMRES solves A dx = r to a modest relative
+    accuracy with a tensor-product preconditioner, and x += dx; it stops once ||r||_2 <= tol ||b||_2
+    or the residual stops falling (the rounding floor of forming b - A x).  precond = "fdm" (all axes
+    diagonalised) or "line" (the axis with the worst-conditioned eigenvectors solved by banded LU)
+    gives two different preconditioners whose results must agree.  Returns (u_ff, ||r||/||b||)."""
+    from scipy.sparse.linalg import LinearOperator, gmres
+    g = Grid(d, level, 1)
+    dims = (g.Nf,) * d
+    coeffs = mesh_coeffs(g, np.asarray(alpha, float), np.asarray(beta, float), ())
+    b = rhs_on_mesh(g, (), s_fine, g_faces, alpha, beta)
+    A = assemble_operator(dims, coeffs)
+    if precond == "fdm":
+        pre = _TensorPreconditioner(dims, coeffs)
+    elif precond == "line":
+        conds = []
+        for (a_, b_, c_) in coeffs:
+            ratio = abs(a_ / c_) if c_ != 0.0 else np.inf
+            conds.append(abs(np.log(ratio)) if ratio > 0 else np.inf)
+        pre = _TensorPreconditioner(dims, coeffs, line_axis=int(np.argmax(conds)))
+    else:
+        raise ValueError("precond must be 'fdm' or 'line'")
+    n = A.shape[0]
+
+    def mv(v):
+        return pre(np.asarray(v).reshape(dims, order="F")).reshape(-1, order="F")
+
+    M = LinearOperator((n, n), matvec=mv, dtype=np.float64)
+    bf = b.reshape(-1, order="F")
+    bn = float(np.linalg.norm(bf))
+    x = np.zeros(n)
+    if bn == 0.0:
+        return x.reshape(dims, order="F"), 0.0
+    r = bf.copy()
+    rn = bn
+    for _ in range(max_outer):
+        dx, _info = gmres(A, r, rtol=1e-6, atol=0.0, restart=40, maxiter=20, M=M)
+        x_new = x + dx
+        r_new = bf - A @ x_new
+        rn_new = float(np.linalg.norm(r_new))
+        if rn_new >= rn:          # rounding floor reached: keep the better iterate
+            break
+        x, r, rn = x_new, r_new, rn_new
+        if rn <= tol * bn:
+            break
+    if not rn <= 1e-11 * bn:
+        raise RuntimeError(f"fine_reference_solve: preconditioner '{precond}' reached only "
+                           f"||r||/||b|| = {rn / bn:.3e}")
+    return x.reshape(dims, order="F"), rn / bn

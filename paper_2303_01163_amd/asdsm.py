@@ -27,7 +27,7 @@ EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_
             "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error",
             "asdsm_batch_create", "asdsm_batch_solve", "asdsm_batch_destroy", "asdsm_autotune",
             "asdsm_tile_name", "asdsm_set_tile", "asdsm_get_tile", "asdsm_probe_mfma_scratch_bytes",
-            "asdsm_probe_mfma_f64", "asdsm_probe_copy")
+            "asdsm_probe_mfma_f64", "asdsm_probe_copy", "asdsm_profile_count", "asdsm_profile_entry")
 # symbols declared in include/asdsm_learn.h
 EXPORTED_LEARN = ("asdsm_net_create", "asdsm_net_param_count", "asdsm_net_workspace_size",
                   "asdsm_net_set_workspace", "asdsm_net_params", "asdsm_net_forward",
@@ -97,6 +97,12 @@ def load_library():
     lib.asdsm_probe_mfma_f64.restype = c_int
     lib.asdsm_probe_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_int, c_void_p, POINTER(c_double)]
     lib.asdsm_probe_copy.restype = c_int
+    lib.asdsm_profile_count.argtypes = [c_void_p]
+    lib.asdsm_profile_count.restype = c_int
+    lib.asdsm_profile_entry.argtypes = [c_void_p, c_int, ctypes.c_char_p, c_int, POINTER(c_int),
+                                        POINTER(c_double), POINTER(c_int), POINTER(c_int),
+                                        POINTER(c_double), POINTER(c_double)]
+    lib.asdsm_profile_entry.restype = c_int
     lib.asdsm_batch_create.argtypes = [POINTER(c_void_p), POINTER(c_void_p), c_int]
     lib.asdsm_batch_create.restype = c_int
     lib.asdsm_batch_solve.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
@@ -283,6 +289,22 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(lib.asdsm_autotune(self._h, int(repeats), byref(tile), byref(ms)))
         return {"tile": lib.asdsm_tile_name(tile.value).decode(), "ms_per_aniso_solve": ms.value}
+
+    def kernel_profile(self):
+        """Launch groups of the last profiled solve by kind (asdsm_profile_count/entry): a list of
+        dicts with name, phase, ms, groups, launches, flops, bytes."""
+        lib = load_library()
+        n = _check(lib.asdsm_profile_count(self._h))
+        out = []
+        for i in range(n):
+            name = ctypes.create_string_buffer(96)
+            ph, gr, la = c_int(), c_int(), c_int()
+            ms, fl, by = c_double(), c_double(), c_double()
+            _check(lib.asdsm_profile_entry(self._h, i, name, 96, byref(ph), byref(ms), byref(gr),
+                                           byref(la), byref(fl), byref(by)))
+            out.append({"name": name.value.decode(), "phase": PHASES[ph.value], "ms": ms.value,
+                        "groups": gr.value, "launches": la.value, "flops": fl.value, "bytes": by.value})
+        return out
 
     def residual(self, u, s, g, want_r=True):
         import torch

@@ -32,6 +32,12 @@ int check_launch(const char *what) {
     return ASDSM_OK;
 }
 
+const char *phase_name(int ph) {
+    static const char *names[ASDSM_NPHASE] = {"rhs", "transform", "line", "skeleton",
+                                              "filler", "dots", "update", "learned"};
+    return (ph >= 0 && ph < ASDSM_NPHASE) ? names[ph] : "?";
+}
+
 // Phase timing (opts->profile): a pair of events stamped by the kernels of a launch group (see
 // LaunchEvents), with the algorithmic work of those launches (flops; bytes with every operand read
 // once and every result written once).  Nothing synchronises here: the pairs are read once the
@@ -40,7 +46,8 @@ struct PhaseTimer {
     Plan &p;
     size_t idx = 0;
     bool on = false;
-    PhaseTimer(Plan &pl, int ph, int nl, double fl = 0.0, double by = 0.0) : p(pl) {
+    PhaseTimer(Plan &pl, int ph, int nl, double fl = 0.0, double by = 0.0, const char *tag = nullptr)
+        : p(pl) {
         if (!p.profiling || p.prof_failed) return;
         idx = p.ev_recs.size();
         while (p.ev_pool.size() < 2 * (idx + 1)) {
@@ -51,7 +58,7 @@ struct PhaseTimer {
             }
             p.ev_pool.push_back(e);
         }
-        p.ev_recs.push_back({ph, nl, fl, by, false});
+        p.ev_recs.push_back({ph, nl, fl, by, false, tag});
         LaunchEvents &le = launch_events();
         le.start = p.ev_pool[2 * idx];
         le.stop = p.ev_pool[2 * idx + 1];
@@ -77,6 +84,20 @@ int collect_phases(Plan &p) {
         p.phase_launches[r.phase] += r.launches;
         p.phase_flops[r.phase] += r.flops;
         p.phase_bytes[r.phase] += r.bytes;
+        // per launch group kind: the groups with a kernel tag are single launches of that kernel
+        const std::string name = r.tag ? std::string(r.tag) : std::string("phase:") + phase_name(r.phase);
+        Plan::KernelRec *kr = nullptr;
+        for (auto &k : p.kern_recs)
+            if (k.name == name) kr = &k;
+        if (!kr) {
+            p.kern_recs.push_back(Plan::KernelRec{name, r.phase, 0.0, 0, 0, 0.0, 0.0});
+            kr = &p.kern_recs.back();
+        }
+        kr->ms += ms;
+        kr->groups += 1;
+        kr->launches += r.launches;
+        kr->flops += r.flops;
+        kr->bytes += r.bytes;
     }
     return ASDSM_OK;
 }
@@ -163,7 +184,7 @@ int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *
             j.C[b] = out[b];
         }
     }
-    PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
+    PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
     if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
     return check_launch("transform");
 }
@@ -229,7 +250,7 @@ int solve_mesh_nd(Plan &p, int nb, const unsigned *masks, const double *const *i
             L.t[b] = p.geo.coarse[mb.ax[nf]];
         }
         const double lpts = (double)L.nmodes * L.ncoarse * nb;
-        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 8.0 * lpts, 16.0 * lpts);
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 8.0 * lpts, 16.0 * lpts, "k_line");
         launch_line(L, p.stream);
         if (int rc = check_launch("line")) return rc;
     } else {
@@ -296,7 +317,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             pj.L[q] = p.dW[b];
             pj.R[q] = p.dW[a];
         }
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, plane_flops(pj), plane_bytes(pj));
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, plane_flops(pj), plane_bytes(pj), "k_plane2 forward");
         if (!launch_plane2(pj, p.stream)) return fail(ASDSM_E_ARG, "plane transforms: N_f too large");
         if (int rc = check_launch("transform")) return rc;
     }
@@ -315,7 +336,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.B[q] = p.dW[a];
             j.C[q] = p.ws.Y[1u << ks[q]];
         }
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
         if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
@@ -332,7 +353,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.B[q] = p.ws.Y[1u << ks[q]];
             j.C[q] = p.ws.X[1u << ks[q]];
         }
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
         if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
@@ -357,7 +378,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             L.t[q] = p.geo.coarse[k];
         }
         const double lpts = (double)L.nmodes * L.ncoarse * nb;
-        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 8.0 * lpts, 16.0 * lpts);
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 8.0 * lpts, 16.0 * lpts, "k_line");
         launch_line(L, p.stream);
         if (int rc = check_launch("line")) return rc;
     }
@@ -375,7 +396,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             pj.L[q] = p.dV[b];
             pj.R[q] = p.dV[a];
         }
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, plane_flops(pj), plane_bytes(pj));
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, plane_flops(pj), plane_bytes(pj), "k_plane2 backward");
         if (!launch_plane2(pj, p.stream)) return fail(ASDSM_E_ARG, "plane transforms: N_f too large");
         return check_launch("transform");
     }
@@ -392,7 +413,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.B[q] = p.ws.X[1u << ks[q]];
             j.C[q] = p.ws.Y[1u << ks[q]];
         }
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
         if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
@@ -411,7 +432,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
             j.B[q] = p.dV[a];
             j.C[q] = out[ks[q]];
         }
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
         if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
@@ -445,7 +466,7 @@ int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, in
         j.B[0] = p.dW[f];
         j.C[0] = p.ws.Y[mask];
         j.accum = 0;
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
         if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
@@ -460,7 +481,7 @@ int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, in
         j.B[0] = p.dV[f];
         j.C[0] = out;
         j.accum = accum;
-        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j));
+        PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
         if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
         if (int rc = check_launch("transform")) return rc;
     }
@@ -1015,17 +1036,17 @@ int sparse_step(Plan &p) {
     if (int rc = error_guess(p)) return rc;
     const double skel = aniso_points(p);  // skeleton points counted once per mesh
     {
-        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p), 8.0 * (3.0 * skel));
+        PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p), 8.0 * (3.0 * skel), "hole filler (layer mode)");
         launch_filler(p, nullptr, nullptr, p.stream, nullptr, true);
         if (int rc = check_launch("filler (layers)")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_DOTS, 1, 17.0 * skel, 8.0 * 5.0 * skel);
+        PhaseTimer t(p, ASDSM_PHASE_DOTS, 1, 17.0 * skel, 8.0 * 5.0 * skel, "k_skel_dots");
         launch_skel_dots(p, p.stream);
         if (int rc = check_launch("skeleton dots")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 5.0 * skel, 8.0 * 7.0 * skel);
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 5.0 * skel, 8.0 * 7.0 * skel, "k_skel_update");
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
         launch_skel_update(p, gat, p.stream);
@@ -1087,6 +1108,13 @@ int step(Plan &p, const double *u_cur, double *u_next) {
 
 int require_ws(const Plan &p) {
     if (!p.ws_base) return fail(ASDSM_E_WORKSPACE, "no workspace attached (asdsm_set_workspace)");
+    return ASDSM_OK;
+}
+
+// Two events (no timing) behind which the graph loop checks the loop state (created once per plan).
+int ensure_loop_events(Plan &p) {
+    for (int i = 0; i < 2; ++i)
+        if (!p.loop_ev[i]) ASDSM_HIP_CHECK(hipEventCreateWithFlags(&p.loop_ev[i], hipEventDisableTiming));
     return ASDSM_OK;
 }
 
@@ -1246,6 +1274,7 @@ int begin_solve(Plan &p, const double *s, const double *g, double *u, const asds
         p.phase_flops[q] = 0.0;
         p.phase_bytes[q] = 0.0;
     }
+    p.kern_recs.clear();
     IterState &hs = *p.hstate;
     std::memset(&hs, 0, sizeof hs);
     hs.status = ASDSM_MAXITER;
@@ -1401,20 +1430,37 @@ int solve_impl(Plan &p, const double *s, const double *g, double *u, const asdsm
             p.graph_net_serial != net_serial ||
             p.graph_net_ws != net_ws || (p.learn_net && p.graph_factor != p.learn_factor))
             rc = build_graph(p, u);
-        // two steps per replay, two replays per host check; surplus steps are gated no-ops
-        int steps = 0;
-        while (rc == ASDSM_OK) {
+        // two steps per replay, two replays per batch; the host checks the loop state of batch i
+        // while batch i + 1 runs (the state is copied into one of two pinned slots behind each
+        // batch), so the device never waits for the host; steps beyond the stopping point are gated
+        // no-ops
+        if (rc == ASDSM_OK) rc = ensure_loop_events(p);
+        int steps = 0, inflight = 0;
+        auto launch_batch = [&](int slot) -> int {
             for (int rep = 0; rep < 2 && steps < opt.max_iter; ++rep, steps += 2) {
                 hipError_t e = hipGraphLaunch(p.graph_exec, p.stream);
-                if (e != hipSuccess) {
-                    rc = fail(ASDSM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-                    break;
-                }
+                if (e != hipSuccess)
+                    return fail(ASDSM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
             }
-            if (rc != ASDSM_OK) break;
-            rc = read_state(p);
-            if (rc != ASDSM_OK || hs.done || steps >= opt.max_iter) break;
+            ASDSM_HIP_CHECK(hipMemcpyAsync(p.hstate_ring[slot], p.ws.state, sizeof(IterState),
+                                           hipMemcpyDeviceToHost, p.stream));
+            ASDSM_HIP_CHECK(hipEventRecord(p.loop_ev[slot], p.stream));
+            ++inflight;
+            return ASDSM_OK;
+        };
+        if (rc == ASDSM_OK) rc = launch_batch(0);
+        if (rc == ASDSM_OK && steps < opt.max_iter) rc = launch_batch(1);
+        for (int slot = 0; rc == ASDSM_OK && inflight > 0; slot ^= 1) {
+            hipError_t e = hipEventSynchronize(p.loop_ev[slot]);
+            if (e != hipSuccess) {
+                rc = fail(ASDSM_E_DEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+                break;
+            }
+            --inflight;
+            if (p.hstate_ring[slot]->done) break;
+            if (steps < opt.max_iter) rc = launch_batch(slot);
         }
+        if (rc == ASDSM_OK) rc = read_state(p);
     } else {
         for (int i = 0; i < opt.max_iter && rc == ASDSM_OK; ++i) {
             rc = (i % 2 == 0) ? step(p, u, p.ws.u2) : step(p, p.ws.u2, u);
@@ -1779,6 +1825,32 @@ int asdsm_autotune(asdsm_plan_t plan, int repeats, int *tile, double *ms_per_sol
 }
 
 const char *asdsm_tile_name(int tile) { return gemm_tile_name(tile); }
+
+int asdsm_profile_count(asdsm_plan_t plan) {
+    if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
+    return (int)plan->p.kern_recs.size();
+}
+
+int asdsm_profile_entry(asdsm_plan_t plan, int i, char *name, int name_cap, int *phase, double *ms,
+                        int *groups, int *launches, double *flops, double *bytes) {
+    if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
+    const auto &recs = plan->p.kern_recs;
+    if (i < 0 || i >= (int)recs.size()) return fail(ASDSM_E_ARG, "profile entry index out of range");
+    const auto &r = recs[(size_t)i];
+    if (name && name_cap > 0) {
+        const size_t n = std::min((size_t)(name_cap - 1), r.name.size());
+        std::memcpy(name, r.name.data(), n);
+        name[n] = '\0';
+    }
+    if (phase) *phase = r.phase;
+    if (ms) *ms = r.ms;
+    if (groups) *groups = r.groups;
+    if (launches) *launches = r.launches;
+    if (flops) *flops = r.flops;
+    if (bytes) *bytes = r.bytes;
+    set_error("");
+    return ASDSM_OK;
+}
 
 size_t asdsm_probe_mfma_scratch_bytes(void) { return probe_mfma_scratch_bytes(); }
 

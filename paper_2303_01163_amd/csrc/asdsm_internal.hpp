@@ -174,6 +174,8 @@ struct Plan {
     // pinned host mirror of the device scalars and of the loop state
     double *hscal = nullptr;
     IterState *hstate = nullptr;
+    IterState *hstate_ring[2] = {nullptr, nullptr};  // pinned slots of the pipelined graph loop
+    hipEvent_t loop_ev[2] = {nullptr, nullptr};
     int *hperm = nullptr;        // pinned staging of the permutation table
 
     // refinement kernels return early when *gate != 0 (nullptr outside the refinement loop)
@@ -201,7 +203,17 @@ struct Plan {
         int phase, launches;
         double flops, bytes;
         bool launched;
+        const char *tag;   // kernel of a single-kernel launch group (string literal), or nullptr
     };
+    // per launch-group kind of the last profiled call: device time, groups, launches, work
+    struct KernelRec {
+        std::string name;
+        int phase;
+        double ms;
+        int groups, launches;
+        double flops, bytes;
+    };
+    std::vector<KernelRec> kern_recs;
     bool profiling = false;
     bool prof_failed = false;
     std::vector<hipEvent_t> ev_pool;

@@ -645,6 +645,8 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     if (err == hipSuccess) err = hipHostMalloc((void **)&p.hstate, sizeof(IterState), hipHostMallocDefault);
     if (err == hipSuccess)
         err = hipHostMalloc((void **)&p.hperm, (size_t)kHistCap * kMaxD * sizeof(int), hipHostMallocDefault);
+    for (int i = 0; i < 2 && err == hipSuccess; ++i)
+        err = hipHostMalloc((void **)&p.hstate_ring[i], sizeof(IterState), hipHostMallocDefault);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(err));
     return ASDSM_OK;
 }
@@ -660,6 +662,12 @@ void release_plan(Plan &p) {
     if (p.hscal) (void)hipHostFree(p.hscal);
     if (p.hstate) (void)hipHostFree(p.hstate);
     if (p.hperm) (void)hipHostFree(p.hperm);
+    for (int i = 0; i < 2; ++i) {
+        if (p.hstate_ring[i]) (void)hipHostFree(p.hstate_ring[i]);
+        if (p.loop_ev[i]) (void)hipEventDestroy(p.loop_ev[i]);
+        p.hstate_ring[i] = nullptr;
+        p.loop_ev[i] = nullptr;
+    }
     p.hstate = nullptr;
     p.hperm = nullptr;
     for (hipEvent_t e : p.ev_pool) (void)hipEventDestroy(e);

@@ -13,7 +13,8 @@ import numpy as np
 import pytest
 
 from oracle.asdsm_oracle import (BandedBoxSolver, Grid, Oracle, apply_operator, assemble_operator,
-                                 boolean_sum_extend, fine_direct_solve, op1d, permutation,
+                                 boolean_sum_extend, fine_direct_solve, fine_reference_solve, op1d,
+                                 permutation,
                                  rhs_on_mesh, spline_matrix, splitmix64_stream)
 from paper_2303_01163_amd.workloads import make_problem
 
@@ -505,3 +506,48 @@ def test_chosen_crosspoints_hand_computed():
     expect[1, 1, 0], expect[1, 1, 2] = 210, 212
     expect[1, 0, 1], expect[1, 2, 1] = 310, 312  # M_2 at (x_0, x_1) = (1, j)
     assert np.array_equal(uhat, expect)
+
+
+# ----------------------------------------------------------------------------- reference u_ff
+@pytest.mark.parametrize("fam,d,L,seed", [("sinprod2d", 2, 7, 0), ("sinbump3d", 3, 4, 0),
+                                          ("sinbump_wide", 3, 4, 2), ("sinbump_wide", 2, 7, 4),
+                                          ("sinbump_wide", 4, 3, 5)])
+@pytest.mark.parametrize("precond", ["fdm", "line"])
+def test_reference_solve_matches_banded_lu(fam, d, L, seed, precond):
+    """The reference fine solution (preconditioned GMRES in iterative refinement) equals the banded
+    LU solve of the whole fine system where that is affordable, for both preconditioners, including
+    draws with |cell Peclet| >= 1 on some axes (complex 1D spectra)."""
+    P = make_problem(fam, L, seed=seed, d=d)
+    ref = fine_direct_solve(d, P.alpha, P.beta, L, P.s, P.g)
+    try:
+        u, rr = fine_reference_solve(d, P.alpha, P.beta, L, P.s, P.g, precond=precond)
+    except RuntimeError:
+        # full fast diagonalisation cannot precondition axes with |P| close to 1 (eigenvector
+        # matrices beyond 1e16); the line form must then succeed
+        assert precond == "fdm"
+        return
+    assert rr <= 1e-11
+    assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_reference_solve_q2_exact_at_63_cubed():
+    """The centred scheme is exact on Q2 polynomials (Section 2.3), so u_ff is the manufactured
+    polynomial itself: a size where banded LU is out of reach, with g != 0."""
+    P = make_problem("quadratic", 6, seed=3, d=3)
+    u, rr = fine_reference_solve(3, P.alpha, P.beta, 6, P.s, P.g, precond="line")
+    assert rr <= 1e-12
+    assert np.max(np.abs(u - P.u_exact)) <= 1e-11 * np.max(np.abs(P.u_exact))
+
+
+@pytest.mark.slow
+def test_reference_solve_preconditioners_agree_127_cubed():
+    """Two different preconditioners (all axes diagonalised; the worst axis by banded line solves)
+    give the same u_ff for the 127^3 workload (seed 0) to 1e-11, each with ||b - A u||/||b|| at the
+    rounding floor; u_ff is O(h^2)-close to the manufactured solution."""
+    P = make_problem("sinbump3d", 7, seed=0)
+    u1, r1 = fine_reference_solve(3, P.alpha, P.beta, 7, P.s, P.g, precond="fdm")
+    u2, r2 = fine_reference_solve(3, P.alpha, P.beta, 7, P.s, P.g, precond="line")
+    assert r1 <= 1e-13 and r2 <= 1e-13
+    assert np.linalg.norm(u1 - u2) <= 1e-11 * np.linalg.norm(u1)
+    err = np.linalg.norm(u1 - P.u_exact) / np.linalg.norm(P.u_exact)
+    assert 1e-4 < err < 2e-2
