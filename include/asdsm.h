@@ -132,8 +132,12 @@ typedef struct {
  *   hip_stream   : hipStream_t (borrowed, may be NULL for the null stream).
  * The plan owns its small host and device tables (operator spectra, transform matrices, spline
  * matrix); the large work arrays live in a caller-owned workspace (asdsm_set_workspace).
- * Errors: ASDSM_E_ARG, ASDSM_E_NESTING, ASDSM_E_UNSUPPORTED (|cell Peclet| >= 1 on a fine axis, or
- * hole boxes too large for one workgroup's LDS), ASDSM_E_DEVICE. */
+ * A fine axis that fast diagonalisation cannot handle (|cell Peclet| >= 1: complex spectrum; or an
+ * eigenvector matrix too ill-conditioned for FP64) is solved along lines by block cyclic reduction
+ * (asdsm_line_axes reports which).
+ * Errors: ASDSM_E_ARG, ASDSM_E_NESTING, ASDSM_E_UNSUPPORTED (a submesh or the hole boxes with two
+ * such axes, or hole boxes too large for one workgroup's LDS), ASDSM_E_NUMERIC (a singular block),
+ * ASDSM_E_DEVICE. */
 int asdsm_plan(asdsm_plan_t *out, int d, const double *alpha, const double *beta, int level,
                int coarse_level, uint64_t seed, void *hip_stream);
 
@@ -194,8 +198,8 @@ const char *asdsm_tile_name(int tile);
 
 /* Force the transform tile shape of this plan's anisotropic solves (the autotuner's choice is
  * replaced).  Same iterates up to rounding for every shape.
- * Errors: ASDSM_E_ARG (unknown tile), ASDSM_E_UNSUPPORTED (ASDSM_TILE_PLANE with d != 3 or
- * N_f > 255). */
+ * Errors: ASDSM_E_ARG (unknown tile), ASDSM_E_UNSUPPORTED (ASDSM_TILE_PLANE with d != 3,
+ * N_f > 255 or anisotropic meshes solved with line axes). */
 int asdsm_set_tile(asdsm_plan_t plan, int tile);
 
 /* The tile shape the plan's anisotropic solves use now: ASDSM_TILE_PLANE when both fine-axis
@@ -215,6 +219,16 @@ int asdsm_get_tile(asdsm_plan_t plan, int *tile);
 size_t asdsm_probe_mfma_scratch_bytes(void);
 int asdsm_probe_mfma_f64(void *scratch, int iters, void *hip_stream, double *tflops);
 int asdsm_probe_copy(const void *src, void *dst, size_t bytes, int reps, void *hip_stream, double *tbps);
+
+/* Which fine axis of each mesh is solved by block cyclic reduction along it (a "line axis": its
+ * 1D operator has a complex spectrum, |cell Peclet| >= 1, or an eigenvector matrix too
+ * ill-conditioned for fast diagonalisation; or line axes save the refinement sweeps).
+ *   axis : host output of 2^d ints indexed by mesh mask (bit j set = axis j+1 coarse); entry S is
+ *          the 0-based axis solved along lines in mesh M_S, or -1 when every fine axis of M_S is
+ *          diagonalised (always -1 for the fine mesh, S = 0).
+ *   sweeps: host output of 2^d ints, may be NULL: refinement sweeps of each mesh solve.
+ * Errors: ASDSM_E_ARG. */
+int asdsm_line_axes(asdsm_plan_t plan, int *axis, int *sweeps);
 
 /* Launch groups of the last asdsm_solve made with opts->profile = 1, by kind (a roofline per
  * kernel rather than per phase).  A kind is one kernel (its name, e.g. "k_plane2 forward") when

@@ -27,7 +27,7 @@ EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_
             "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error",
             "asdsm_batch_create", "asdsm_batch_solve", "asdsm_batch_destroy", "asdsm_autotune",
             "asdsm_tile_name", "asdsm_set_tile", "asdsm_get_tile", "asdsm_probe_mfma_scratch_bytes",
-            "asdsm_probe_mfma_f64", "asdsm_probe_copy", "asdsm_profile_count", "asdsm_profile_entry")
+            "asdsm_probe_mfma_f64", "asdsm_probe_copy", "asdsm_profile_count", "asdsm_profile_entry", "asdsm_line_axes")
 # symbols declared in include/asdsm_learn.h
 EXPORTED_LEARN = ("asdsm_net_create", "asdsm_net_param_count", "asdsm_net_workspace_size",
                   "asdsm_net_set_workspace", "asdsm_net_params", "asdsm_net_forward",
@@ -97,6 +97,8 @@ def load_library():
     lib.asdsm_probe_mfma_f64.restype = c_int
     lib.asdsm_probe_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_int, c_void_p, POINTER(c_double)]
     lib.asdsm_probe_copy.restype = c_int
+    lib.asdsm_line_axes.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int)]
+    lib.asdsm_line_axes.restype = c_int
     lib.asdsm_profile_count.argtypes = [c_void_p]
     lib.asdsm_profile_count.restype = c_int
     lib.asdsm_profile_entry.argtypes = [c_void_p, c_int, ctypes.c_char_p, c_int, POINTER(c_int),
@@ -289,6 +291,14 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(lib.asdsm_autotune(self._h, int(repeats), byref(tile), byref(ms)))
         return {"tile": lib.asdsm_tile_name(tile.value).decode(), "ms_per_aniso_solve": ms.value}
+
+    def line_axes(self):
+        """{mesh mask: (line axis or -1, refinement sweeps)} for every submesh (asdsm_line_axes)."""
+        lib = load_library()
+        n = 1 << self.d
+        ax, sw = (c_int * n)(), (c_int * n)()
+        _check(lib.asdsm_line_axes(self._h, ax, sw))
+        return {m: (ax[m], sw[m]) for m in range(1, n)}
 
     def kernel_profile(self):
         """Launch groups of the last profiled solve by kind (asdsm_profile_count/entry): a list of

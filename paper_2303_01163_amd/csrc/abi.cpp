@@ -126,7 +126,7 @@ double plane_bytes(const PlaneJob &j) {
 // of 43.0.)
 constexpr int kPlaneAutoMaxNf = 127;
 bool plane_transforms(const Plan &p) {
-    if (p.d != 3 || p.Nf > kPlaneMaxNf) return false;
+    if (p.d != 3 || p.Nf > kPlaneMaxNf || p.line_aniso) return false;
     if (p.tile_aniso == kTilePlane) return true;
     return p.tile_aniso == kTileAuto && p.Nf <= kPlaneAutoMaxNf;
 }
@@ -189,6 +189,117 @@ int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *
     return check_launch("transform");
 }
 
+// Direct solve of nb meshes of one shape that have a line axis (Plan::line_pos, any d): the other
+// fine axes are diagonalised by mode transforms, then block cyclic reduction runs along the line
+// axis with the mesh's coarse block as blocks (k_blockcr.hip), then the backward transforms.
+// in[b] -> out[b] (out += when accum); X and Y of each mesh are intermediates, in may be X, and out
+// may be X (no transform) or X, Y or W as sol_buf names them.  The meshes' line axes may sit at
+// different canonical positions: the transforms run per group of equal positions, the reduction
+// for all meshes in one launch.
+int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const *in, double *const *out,
+                    int accum) {
+    const MeshDesc &m = p.mesh[masks[0]];
+    const int nt = m.nfine - 1;  // transformed positions per mesh
+    int fq[kMaxD][kMaxD];        // [box][t]: the transformed canonical positions, ascending
+    for (int b = 0; b < nb; ++b) {
+        int t = 0;
+        for (int q = 0; q < m.nfine; ++q)
+            if (q != p.line_pos[masks[b]]) fq[b][t++] = q;
+    }
+    // forward transforms: in -> Y -> X ... (transform t writes Y for even t, X for odd t)
+    const double *cur[kMaxD];
+    double *X[kMaxD], *Y[kMaxD];
+    for (int b = 0; b < nb; ++b) {
+        cur[b] = in[b];
+        X[b] = p.ws.X[masks[b]];
+        Y[b] = p.ws.Y[masks[b]];
+    }
+    auto run_grouped = [&](int t, const double *const *src, double *const *dst, bool fwd, int acc) -> int {
+        bool done[kMaxD] = {};
+        for (int b = 0; b < nb; ++b) {
+            if (done[b]) continue;
+            const int q = fq[b][t];
+            const double *gs[kMaxD], *gT[kMaxD];
+            double *gd[kMaxD];
+            int ng = 0;
+            for (int c = b; c < nb; ++c)
+                if (!done[c] && fq[c][t] == q) {
+                    done[c] = true;
+                    gs[ng] = src[c];
+                    gd[ng] = dst[c];
+                    const int ax = p.mesh[masks[c]].ax[q];
+                    gT[ng] = fwd ? p.dW[ax] : p.dV[ax];
+                    ++ng;
+                }
+            if (int rc = transform_position(p, m, q, ng, gs, gT, gd, acc)) return rc;
+        }
+        return ASDSM_OK;
+    };
+    for (int t = 0; t < nt; ++t) {
+        double *dst[kMaxD];
+        for (int b = 0; b < nb; ++b) dst[b] = (t % 2 == 0) ? Y[b] : X[b];
+        if (int rc = run_grouped(t, cur, dst, true, 0)) return rc;
+        for (int b = 0; b < nb; ++b) cur[b] = dst[b];
+    }
+    // the reduction: in place on the transformed data, or in -> out when nothing was transformed
+    double *D[kMaxD], *O[kMaxD];
+    for (int b = 0; b < nb; ++b) {
+        D[b] = (nt % 2 == 1) ? Y[b] : X[b];
+        O[b] = (nt % 2 == 1) ? X[b] : Y[b];
+    }
+    {
+        CrJob job{};
+        job.nbox = nb;
+        job.N = p.Nf;
+        job.L = p.level;
+        job.NB = m.block;
+        job.gate = p.gate;
+        job.accum = (nt == 0) ? accum : 0;
+        long long nm = 0;
+        for (int b = 0; b < nb; ++b) {
+            const unsigned mk = masks[b];
+            const MeshDesc &mb = p.mesh[mk];
+            CrBox &bx = job.box[b];
+            bx.src = (nt == 0) ? in[b] : D[b];
+            bx.dst = (nt == 0) ? out[b] : D[b];
+            bx.tab = p.dcr[mk];
+            bx.nmodes = mb.nmodes / mb.ext[p.line_pos[mk]];
+            bx.mext0 = nt >= 1 ? mb.ext[fq[b][0]] : 1;
+            bx.ms0 = nt >= 1 ? mb.stride[fq[b][0]] : 0;
+            bx.ms1 = nt >= 2 ? mb.stride[fq[b][1]] : 0;
+            bx.sw = mb.stride[p.line_pos[mk]];
+            bx.sc = mb.stride[mb.nfine];
+            nm = std::max(nm, bx.nmodes);
+        }
+        // modes per workgroup: 8 when the first mode axis is contiguous (coalesced loads), else 2;
+        // fewer when the LDS does not hold them; the global-memory form when not even one fits
+        int tm = (job.box[0].ms0 == 1) ? 8 : 2;
+        while (tm > 1 && cr_lds_bytes(job.N, job.NB, tm) > kCrMaxLds) tm /= 2;
+        if (!cr_lds_supported(job.NB) || cr_lds_bytes(job.N, job.NB, tm) > kCrMaxLds) tm = 0;
+        if (tm == 0 && job.accum)
+            return fail(ASDSM_E_UNSUPPORTED, "line solve: accumulation needs the LDS form");
+        job.tm = tm;
+        const double B = m.block;
+        const double pts = (double)nm * nb * job.N * B;
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 6.0 * pts * B, 8.0 * (2.0 * pts + 3.0 * nm * nb * job.L * B * B),
+                     "k_block_cr");
+        if (!launch_block_cr(job, p.stream)) return fail(ASDSM_E_ARG, "line solve: unsupported shape");
+        if (int rc = check_launch("block cyclic reduction")) return rc;
+    }
+    // backward transforms, last first: D -> O -> D ... -> out
+    for (int t = nt - 1; t >= 0; --t) {
+        const double *src[kMaxD];
+        double *dst[kMaxD];
+        for (int b = 0; b < nb; ++b) {
+            src[b] = D[b];
+            dst[b] = (t == 0) ? out[b] : O[b];
+        }
+        if (int rc = run_grouped(t, src, dst, false, t == 0 ? accum : 0)) return rc;
+        for (int b = 0; b < nb; ++b) std::swap(D[b], O[b]);
+    }
+    return ASDSM_OK;
+}
+
 // Direct solve of nb meshes of one shape, any d (the d = 4 path): every fine axis diagonalised by a
 // mode transform, then per mode a Thomas elimination along the coarse axis (one coarse axis) or the
 // precomputed dense inverse of the coarse block (several), then the backward transforms.
@@ -197,6 +308,7 @@ int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *
 // or W in the first case and Y or W in the second (the buffers sol_buf names).
 int solve_mesh_nd(Plan &p, int nb, const unsigned *masks, const double *const *in, double *const *out,
                   int accum) {
+    if (p.line_pos[masks[0]] >= 0) return solve_mesh_line(p, nb, masks, in, out, accum);
     const MeshDesc &m = p.mesh[masks[0]];
     const int nf = m.nfine;
     double *X[kMaxD], *Y[kMaxD];
@@ -287,7 +399,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
     for (int k = 0; k < d; ++k)
         if ((kbits >> k) & 1u) ks[nb++] = k;
     if (nb == 0) return ASDSM_OK;
-    if (d == 4) {
+    if (d == 4 || p.line_aniso) {
         unsigned masks[kMaxD];
         const double *bin[kMaxD];
         double *bout[kMaxD];
@@ -444,6 +556,7 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
 // Y_S output without accumulation).
 int solve_intersection(Plan &p, unsigned mask, const double *in, double *out, int accum) {
     const MeshDesc &m = p.mesh[mask];
+    if (p.line_pos[mask] >= 0) return solve_mesh_line(p, 1, &mask, &in, &out, accum);
     if (m.nfine >= 2) return solve_mesh_nd(p, 1, &mask, &in, &out, accum);  // d = 4, two fine axes
     if (m.nfine == 0) {
         const double B = m.block;
@@ -1205,7 +1318,7 @@ int autotune_impl(Plan &p, int reps, int *best_tile, double *best_ms) {
     int best = saved;
     double best_t = 1e300;
     for (int tile : kGemmTiles) {
-        if (tile == kTilePlane && (p.d != 3 || p.Nf > kPlaneMaxNf)) continue;
+        if (tile == kTilePlane && (p.d != 3 || p.Nf > kPlaneMaxNf || p.line_aniso)) continue;
         p.tile_aniso = tile;
         int rc = solve_aniso(p, kbits, in, out, 0);  // warm-up (code objects, caches)
         if (rc == ASDSM_OK) {
@@ -1826,6 +1939,17 @@ int asdsm_autotune(asdsm_plan_t plan, int repeats, int *tile, double *ms_per_sol
 
 const char *asdsm_tile_name(int tile) { return gemm_tile_name(tile); }
 
+int asdsm_line_axes(asdsm_plan_t plan, int *axis, int *sweeps) {
+    if (!plan || !axis) return fail(ASDSM_E_ARG, "plan and axis must be non-NULL");
+    const Plan &p = plan->p;
+    for (unsigned s = 0; s < (1u << p.d); ++s) {
+        axis[s] = (s > 0 && p.line_pos[s] >= 0) ? p.mesh[s].ax[p.line_pos[s]] : -1;
+        if (sweeps) sweeps[s] = p.sweeps[s];
+    }
+    set_error("");
+    return ASDSM_OK;
+}
+
 int asdsm_profile_count(asdsm_plan_t plan) {
     if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
     return (int)plan->p.kern_recs.size();
@@ -1886,8 +2010,8 @@ int asdsm_set_tile(asdsm_plan_t plan, int tile) {
     if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
     Plan &p = plan->p;
     if (tile < kTileAuto || tile > kTilePlane) return fail(ASDSM_E_ARG, "unknown tile shape");
-    if (tile == kTilePlane && (p.d != 3 || p.Nf > kPlaneMaxNf))
-        return fail(ASDSM_E_UNSUPPORTED, "plane transforms need d = 3 and N_f <= 255");
+    if (tile == kTilePlane && (p.d != 3 || p.Nf > kPlaneMaxNf || p.line_aniso))
+        return fail(ASDSM_E_UNSUPPORTED, "plane transforms need d = 3, N_f <= 255 and no line axes");
     if (tile != p.tile_aniso) {
         p.tile_aniso = tile;
         plan_changed(p);  // captured launches carry the old tile choice

@@ -20,6 +20,7 @@ namespace asdsm {
 constexpr int kMaxD = 4;
 constexpr int kMaxMeshes = 1 << kMaxD;
 constexpr int kDenseMaxBlock = 4096;  // coarse points per mode of an intersection-mesh dense solve
+constexpr int kCrMaxBlock = 512;      // coarse points per position of a line solve
 
 // Canonical layout of mesh M_S.
 struct MeshDesc {
@@ -138,6 +139,12 @@ struct Plan {
     std::vector<double> dense_inv[kMaxMeshes];  // per-mode inverses for |S| >= 2
     double fdm_cond[kMaxMeshes] = {};  // product of the eigenvector condition numbers of the
                                        // transformed axes of each mesh
+    // line axes: canonical position of the fine axis of each mesh that is solved by block cyclic
+    // reduction (together with the coarse block) instead of being transformed, or -1
+    int line_pos[kMaxMeshes] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+    bool line_aniso = false;           // the anisotropic meshes use line axes
+    std::vector<double> cr_tab[kMaxMeshes];  // host copies while the plan is built
+    double *dcr[kMaxMeshes] = {};      // per mode and level: G, P, Q (device)
     int sweeps[kMaxMeshes] = {};       // refinement sweeps of each mesh solve (calibrated)
     int sweeps_prior[kMaxMeshes] = {}; // a-priori counts from the condition numbers
 

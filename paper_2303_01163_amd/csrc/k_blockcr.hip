@@ -1,0 +1,322 @@
+// Block cyclic reduction along the line axis of a submesh (Section 2.3 operators, Algorithm 1's
+// submesh solves), for fine axes that fast diagonalisation cannot handle: |cell Peclet| >= 1
+// (complex spectrum) or an eigenvector matrix too ill-conditioned for FP64.
+//
+// The submesh's other fine axes are diagonalised first (mode transforms, k_gemm_f64), so every mode
+// of them leaves an independent system along the line axis w.  Its unknowns at position i are the
+// points of the coarse block (all coarse axes, flattened), x_i in R^NB:
+//     a_w x_{i-1} + B x_i + c_w x_{i+1} = f_i,   B = T_block + (b_w + sigma_mode) I,
+// with T_block the Kronecker sum of the coarse axes' operators.  The line has N = 2^L - 1 positions,
+// so odd-even (cyclic) reduction closes without boundary cases: level l keeps the equations at
+// multiples of 2^(l+1) and eliminates the odd multiples of 2^l,
+//     f_i <- f_i - P_l f_(i-s) - Q_l f_(i+s)               (forward, s = 2^l)
+//     x_i  = G_l f_i - P_l x_(i-s) - Q_l x_(i+s)            (back substitution)
+// with G_l = B_l^-1, P_l = G_l A_l, Q_l = G_l C_l and the reduced blocks of every level precomputed
+// per mode on the host (all blocks are functions of T_block, so they commute).  2 (L - 1) + 1
+// dependent levels instead of 2 N for block Thomas; every level is a batch of independent NB x NB
+// matrix-vector products.
+//
+// One workgroup holds `tm` consecutive modes: the kept equations of level 0 (half the line) and the
+// current level's matrices are staged in LDS; a thread owns one (mode, equation) row-block at a
+// time, so every level is updated in place without hazards.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace asdsm {
+
+namespace {
+
+// Row r of G f - P x1 - Q x2 (f[r] - ... when G is nullptr), NB x NB row-major matrices.  The
+// operands are in registers (compile-time indices), the row index is a run-time value, so the rows
+// can be produced one at a time without holding the whole result.
+template <int NB>
+__device__ __forceinline__ double cr_row(int r, const double *__restrict__ G, const double *__restrict__ P,
+                                         const double *__restrict__ Q, const double (&f)[NB],
+                                         const double (&x1)[NB], const double (&x2)[NB]) {
+    double acc = 0.0;
+    if (G) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc += G[r * NB + c] * f[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (c == r) acc = f[c];
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc -= P[r * NB + c] * x1[c];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc -= Q[r * NB + c] * x2[c];
+    return acc;
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_block_cr(CrJob job) {
+    if (job.gate && *job.gate) return;
+    extern __shared__ double lds[];
+    const int box = blockIdx.y;
+    const CrBox &bx = job.box[box];
+    const long long mode0 = (long long)blockIdx.x * job.tm;
+    if (mode0 >= bx.nmodes) return;
+    const int tm = (int)((bx.nmodes - mode0) < job.tm ? (bx.nmodes - mode0) : job.tm);
+    const int N = job.N, L = job.L;
+    const int Nk = (N - 1) / 2;                       // kept equations of level 0 (1-based i = 2j)
+    double *S = lds;                                  // [tm][Nk][NB]
+    double *M = lds + (size_t)job.tm * Nk * NB;       // [tm][3][NB*NB] matrices of the level
+    const double *src = bx.src;  // may be dst (in place): no restrict
+    double *dst = bx.dst;
+    const int tid = threadIdx.x;
+    constexpr int MM = NB * NB;
+    // global offset of (mode, position i0 (0-based), coarse c)
+    auto goff = [&](long long mode, int i0) -> long long {
+        const long long m0 = mode % bx.mext0, m1 = mode / bx.mext0;
+        return m0 * bx.ms0 + m1 * bx.ms1 + (long long)i0 * bx.sw;
+    };
+    auto load_mats = [&](int l) {
+        for (int e = tid; e < tm * 3 * MM; e += 256) {
+            const int ml = e / (3 * MM), rem = e - ml * 3 * MM;
+            M[(size_t)ml * 3 * MM + rem] = bx.tab[((size_t)(mode0 + ml) * L + l) * 3 * MM + rem];
+        }
+    };
+    // task order: modes fastest when they are contiguous in memory, else the line position
+    const bool modes_fast = bx.ms0 == 1;
+
+    // ---- level 0, forward: S[j] = f_2j - P0 f_(2j-1) - Q0 f_(2j+1) (1-based), read from src
+    load_mats(0);
+    __syncthreads();
+    for (int t = tid; t < tm * Nk; t += 256) {
+        const int ml = modes_fast ? t % tm : t / Nk;
+        const int j = modes_fast ? t / tm : t % Nk;  // 0-based kept index: i = 2(j+1), 0-based 2j+1
+        const long long base = goff(mode0 + ml, 2 * j + 1);
+        double f[NB], x1[NB], x2[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            f[c] = src[base + c * bx.sc];
+            x1[c] = src[base - bx.sw + c * bx.sc];
+            x2[c] = src[base + bx.sw + c * bx.sc];
+        }
+        const double *Mm = M + (size_t)ml * 3 * MM;
+        double *sj = S + ((size_t)ml * Nk + j) * NB;
+#pragma unroll 1
+        for (int r = 0; r < NB; ++r) sj[r] = cr_row<NB>(r, nullptr, Mm + MM, Mm + 2 * MM, f, x1, x2);
+    }
+    __syncthreads();
+    // ---- levels 1 .. L-2, forward, on the kept equations (even i, stored at j = i/2 - 1)
+    for (int l = 1; l <= L - 2; ++l) {
+        load_mats(l);
+        __syncthreads();
+        const int step = 1 << l;              // neighbour distance in i; in j-units step/2
+        const int nkeep = (1 << (L - l - 1)) - 1;
+        for (int t = tid; t < tm * nkeep; t += 256) {
+            const int ml = t % tm, q = t / tm;
+            const int i = (q + 1) * 2 * step;  // 1-based kept index of this level
+            const int j = i / 2 - 1, h = step / 2;
+            double *Sm = S + (size_t)ml * Nk * NB;
+            double f[NB], x1[NB], x2[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                f[c] = Sm[j * NB + c];
+                x1[c] = Sm[(j - h) * NB + c];
+                x2[c] = Sm[(j + h) * NB + c];
+            }
+            const double *Mm = M + (size_t)ml * 3 * MM;
+#pragma unroll 1
+            for (int r = 0; r < NB; ++r) Sm[j * NB + r] = cr_row<NB>(r, nullptr, Mm + MM, Mm + 2 * MM, f, x1, x2);
+        }
+        __syncthreads();
+    }
+    // ---- the last equation (i = 2^(L-1)): x = G f
+    load_mats(L - 1);
+    __syncthreads();
+    if (L >= 2) {
+        for (int ml = tid; ml < tm; ml += 256) {
+            const int j = (1 << (L - 2)) - 1;
+            double *Sm = S + (size_t)ml * Nk * NB;
+            double f[NB], z[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                f[c] = Sm[j * NB + c];
+                z[c] = 0.0;
+            }
+            const double *Mm = M + (size_t)ml * 3 * MM;
+#pragma unroll 1
+            for (int r = 0; r < NB; ++r) Sm[j * NB + r] = cr_row<NB>(r, Mm, Mm + MM, Mm + 2 * MM, f, z, z);
+        }
+    }
+    __syncthreads();
+    // ---- back substitution, levels L-2 .. 1, in LDS
+    for (int l = L - 2; l >= 1; --l) {
+        load_mats(l);
+        __syncthreads();
+        const int step = 1 << l;
+        const int nel = 1 << (L - l - 1);     // eliminated equations of this level
+        for (int t = tid; t < tm * nel; t += 256) {
+            const int ml = t % tm, q = t / tm;
+            const int i = (2 * q + 1) * step;  // 1-based
+            const int j = i / 2 - 1, h = step / 2;
+            double *Sm = S + (size_t)ml * Nk * NB;
+            double f[NB], x1[NB], x2[NB];
+            const bool has1 = i - step >= 1, has2 = i + step <= N;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                f[c] = Sm[j * NB + c];
+                x1[c] = has1 ? Sm[(j - h) * NB + c] : 0.0;
+                x2[c] = has2 ? Sm[(j + h) * NB + c] : 0.0;
+            }
+            const double *Mm = M + (size_t)ml * 3 * MM;
+#pragma unroll 1
+            for (int r = 0; r < NB; ++r) Sm[j * NB + r] = cr_row<NB>(r, Mm, Mm + MM, Mm + 2 * MM, f, x1, x2);
+        }
+        __syncthreads();
+    }
+    // ---- level 0 back substitution: odd i from src (their level-0 right-hand sides) and the kept
+    // neighbours; every position written to dst (added when accumulating)
+    load_mats(0);
+    __syncthreads();
+    for (int t = tid; t < tm * N; t += 256) {
+        const int ml = modes_fast ? t % tm : t / N;
+        const int i0 = modes_fast ? t / tm : t % N;  // 0-based position; 1-based i = i0 + 1
+        const long long base = goff(mode0 + ml, i0);
+        const double *Sm = S + (size_t)ml * Nk * NB;
+        const int acc = job.accum;
+        if ((i0 & 1) == 1) {  // even 1-based i: kept, solved in LDS
+            const int j = (i0 + 1) / 2 - 1;
+#pragma unroll 1
+            for (int r = 0; r < NB; ++r) {
+                const long long a = base + r * bx.sc;
+                const double v = Sm[j * NB + r];
+                dst[a] = acc ? dst[a] + v : v;
+            }
+        } else {
+            // kept neighbours: 1-based i-1 = i0 at j = i0/2 - 1, i+1 = i0 + 2 at j = i0/2; the whole
+            // right-hand side row-block is read before any of it is overwritten (src may be dst)
+            double f[NB], x1[NB], x2[NB];
+            const bool has1 = i0 >= 1, has2 = i0 + 1 < N;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                f[c] = src[base + c * bx.sc];
+                x1[c] = has1 ? Sm[(i0 / 2 - 1) * NB + c] : 0.0;
+                x2[c] = has2 ? Sm[(i0 / 2) * NB + c] : 0.0;
+            }
+            const double *Mm = M + (size_t)ml * 3 * MM;
+#pragma unroll 1
+            for (int r = 0; r < NB; ++r) {
+                const long long a = base + r * bx.sc;
+                const double v = cr_row<NB>(r, Mm, Mm + MM, Mm + 2 * MM, f, x1, x2);
+                dst[a] = acc ? dst[a] + v : v;
+            }
+        }
+    }
+}
+
+// Any block size (intersection meshes of the initial guess, whose coarse block holds N_c^|S|
+// points): one workgroup per mode, the line solved in place in dst (canonical layout) after src is
+// copied there; one (equation, row) pair per task.  Back substitution reads a whole row-block of the
+// equation it writes, so each chunk of tasks is computed into registers, then written after a
+// barrier.  No accumulation (the host never asks for it here).
+constexpr int kCrChunk = 16;
+
+__global__ __launch_bounds__(256) void k_block_cr_global(CrJob job) {
+    if (job.gate && *job.gate) return;
+    const int box = blockIdx.y;
+    const CrBox &bx = job.box[box];
+    const long long mode = blockIdx.x;
+    if (mode >= bx.nmodes) return;
+    const int N = job.N, L = job.L, NB = job.NB, tid = threadIdx.x;
+    const long long MM = (long long)NB * NB;
+    const double *tabm = bx.tab + (size_t)mode * L * 3 * MM;
+    const long long m0 = mode % bx.mext0, m1 = mode / bx.mext0;
+    const long long gbase = m0 * bx.ms0 + m1 * bx.ms1;
+    double *W = bx.dst + gbase;  // element (i, c) at W[i sw + c sc]
+    const long long sw = bx.sw, sc = bx.sc;
+    if (bx.src != bx.dst) {
+        const double *S = bx.src + gbase;
+        for (int e = tid; e < N * NB; e += 256) {
+            const int i0 = e / NB, c = e - i0 * NB;
+            W[i0 * sw + c * sc] = S[i0 * sw + c * sc];
+        }
+        __syncthreads();
+    }
+    // forward: a kept equation's row r depends on its own row r and the eliminated neighbours only
+    for (int l = 0; l <= L - 2; ++l) {
+        const double *P = tabm + ((size_t)l * 3 + 1) * MM, *Q = tabm + ((size_t)l * 3 + 2) * MM;
+        const int step = 1 << l, nkeep = (1 << (L - l - 1)) - 1;
+        for (int t = tid; t < nkeep * NB; t += 256) {
+            const int q = t / NB, r = t - q * NB;
+            const long long i0 = (long long)(q + 1) * 2 * step - 1;
+            double acc = W[i0 * sw + r * sc];
+            for (int c = 0; c < NB; ++c)
+                acc -= P[r * NB + c] * W[(i0 - step) * sw + c * sc] + Q[r * NB + c] * W[(i0 + step) * sw + c * sc];
+            W[i0 * sw + r * sc] = acc;
+        }
+        __syncthreads();
+    }
+    // back substitution from the last level down: x_i = G f_i - P x_(i-s) - Q x_(i+s).  Chunks hold
+    // whole equations, so no task reads a row-block that another task of its chunk has overwritten.
+    const int eq_chunk = (256 * kCrChunk) / NB;
+    for (int l = L - 1; l >= 0; --l) {
+        const double *G = tabm + ((size_t)l * 3) * MM;
+        const double *P = G + MM, *Q = G + 2 * MM;
+        const int step = 1 << l, nel = 1 << (L - l - 1);
+        for (int q0 = 0; q0 < nel; q0 += eq_chunk) {
+            const int ntask = (nel - q0 < eq_chunk ? nel - q0 : eq_chunk) * NB;
+            double res[kCrChunk];
+#pragma unroll
+            for (int u = 0; u < kCrChunk; ++u) {
+                const int t = u * 256 + tid;
+                res[u] = 0.0;
+                if (t >= ntask) continue;
+                const int q = q0 + t / NB, r = t % NB;
+                const long long i = (long long)(2 * q + 1) * step;  // 1-based
+                const bool has1 = i - step >= 1, has2 = i + step <= N;
+                double acc = 0.0;
+                for (int c = 0; c < NB; ++c) {
+                    acc += G[r * NB + c] * W[(i - 1) * sw + c * sc];
+                    if (has1) acc -= P[r * NB + c] * W[(i - 1 - step) * sw + c * sc];
+                    if (has2) acc -= Q[r * NB + c] * W[(i - 1 + step) * sw + c * sc];
+                }
+                res[u] = acc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kCrChunk; ++u) {
+                const int t = u * 256 + tid;
+                if (t >= ntask) continue;
+                const int q = q0 + t / NB, r = t % NB;
+                const long long i = (long long)(2 * q + 1) * step;
+                W[(i - 1) * sw + r * sc] = res[u];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace
+
+size_t cr_lds_bytes(int N, int NB, int tm) {
+    const int Nk = (N - 1) / 2;
+    return 8ull * ((size_t)tm * Nk * NB + (size_t)tm * 3 * NB * NB);
+}
+
+bool cr_lds_supported(int NB) { return NB == 1 || NB == 3 || NB == 7 || NB == 9 || NB == 15; }
+
+bool launch_block_cr(const CrJob &job, hipStream_t st) {
+    long long maxm = 0;
+    for (int b = 0; b < job.nbox; ++b) maxm = std::max(maxm, job.box[b].nmodes);
+    if (job.tm == 0) {  // the global-memory form, in place in dst
+        ASDSM_LAUNCH(k_block_cr_global, dim3((unsigned)maxm, (unsigned)job.nbox), dim3(256), 0, st, job);
+        return true;
+    }
+    const dim3 grid((unsigned)((maxm + job.tm - 1) / job.tm), (unsigned)job.nbox);
+    const size_t lds = cr_lds_bytes(job.N, job.NB, job.tm);
+    if (lds > kCrMaxLds) return false;
+    switch (job.NB) {
+        case 1: ASDSM_LAUNCH((k_block_cr<1>), grid, dim3(256), lds, st, job); return true;
+        case 3: ASDSM_LAUNCH((k_block_cr<3>), grid, dim3(256), lds, st, job); return true;
+        case 7: ASDSM_LAUNCH((k_block_cr<7>), grid, dim3(256), lds, st, job); return true;
+        case 9: ASDSM_LAUNCH((k_block_cr<9>), grid, dim3(256), lds, st, job); return true;
+        case 15: ASDSM_LAUNCH((k_block_cr<15>), grid, dim3(256), lds, st, job); return true;
+        default: return false;
+    }
+}
+
+}  // namespace asdsm

@@ -28,6 +28,31 @@ LaunchEvents &launch_events();  // per host thread
         }                                                                                         \
     } while (0)
 
+// Block cyclic reduction along a submesh's line axis (k_blockcr.hip): per mode of the diagonalised
+// fine axes, the line's N = 2^L - 1 positions each hold the mesh's coarse block (NB points).
+// Element (mode, i, c) of a box lives at (mode % mext0) ms0 + (mode / mext0) ms1 + i sw + c sc.
+// tab holds, per mode and level l = 0..L-1, the row-major NB x NB matrices G_l, P_l, Q_l.
+struct CrBox {
+    const double *src;   // right-hand sides (may equal dst)
+    double *dst;         // solution (dst += solution when accumulating)
+    const double *tab;
+    long long nmodes;
+    long long mext0, ms0, ms1, sw, sc;
+};
+struct CrJob {
+    CrBox box[kMaxD];
+    int nbox;
+    int N, L, NB;
+    int tm;              // modes per workgroup (LDS form); 0: the global-memory form (in place
+                         // in dst after copying src there; no accumulation)
+    int accum;
+    const int *gate;
+};
+constexpr size_t kCrMaxLds = 64 * 1024;
+size_t cr_lds_bytes(int N, int NB, int tm);
+bool cr_lds_supported(int NB);  // block sizes with an LDS-staged kernel
+bool launch_block_cr(const CrJob &job, hipStream_t st);
+
 struct BoxPtrs {
     double *p[kMaxD];
 };

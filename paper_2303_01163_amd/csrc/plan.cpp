@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <thread>
 
@@ -68,6 +69,14 @@ MeshDesc make_mesh(int d, int Nf, int Nc, unsigned mask) {
 // D = diag(r^(i - c0)), c0 = (N+1)/2 (centred to keep the scaling symmetric); V^-1 = Q D^-1.
 static void spectrum(const Tri &t, int N, AxisSpectrum &s) {
     s.N = N;
+    if (N == 1) {  // a 1 x 1 operator, whatever its off-diagonal coefficients
+        s.r = 1.0;
+        s.mu.assign(1, t.b);
+        s.W.assign(1, 1.0);
+        s.V.assign(1, 1.0);
+        s.cond = 1.0;
+        return;
+    }
     s.r = std::sqrt(t.a / t.c);
     const double sq = std::sqrt(t.a * t.c);
     const double PI = M_PI;
@@ -345,6 +354,118 @@ static bool build_dense_inverse(Plan &p, unsigned mask) {
     return true;
 }
 
+// Row-major products and inverse of small dense NB x NB matrices (CR tables).
+static void matmul(int n, const double *A, const double *B, double *C) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += A[(size_t)i * n + k] * B[(size_t)k * n + j];
+            C[(size_t)i * n + j] = acc;
+        }
+}
+
+// Reduced blocks of block cyclic reduction along the line axis of mesh `mask` (k_blockcr.hip): per
+// mode of the other fine axes, B_0 = T_block + (b_w + sigma) I, A_0 = a_w I, C_0 = c_w I and per
+// level G_l = B_l^-1, P_l = G_l A_l, Q_l = G_l C_l, then B_(l+1) = B_l - A_l G_l C_l - C_l G_l A_l,
+// A_(l+1) = -A_l G_l A_l, C_(l+1) = -C_l G_l C_l (elimination of the odd equations of the level).
+// Stored per mode and level as G, P, Q, row major.
+static bool build_cr_tables(Plan &p, unsigned mask) {
+    const MeshDesc &m = p.mesh[mask];
+    const int lp = p.line_pos[mask];
+    const int NB = m.block, L = p.level;
+    const size_t MM = (size_t)NB * NB;
+    const long long nmodes = m.nmodes / m.ext[lp];
+    const Tri tw = p.geo.fine[m.ax[lp]];
+    // Kronecker-sum matrix of the coarse axes on the block (coarse canonical order, first fastest)
+    std::vector<double> Kc(MM, 0.0);
+    long long cs = 1;
+    for (int q = m.nfine; q < m.nd; ++q) {
+        const Tri t = p.geo.coarse[m.ax[q]];
+        const int e = m.ext[q];
+        for (int idx = 0; idx < NB; ++idx) {
+            const int pos = (int)((idx / cs) % e);
+            Kc[(size_t)idx * NB + idx] += t.b;
+            if (pos > 0) Kc[(size_t)idx * NB + (idx - cs)] += t.a;
+            if (pos < e - 1) Kc[(size_t)idx * NB + (idx + cs)] += t.c;
+        }
+        cs *= e;
+    }
+    int fq[kMaxD], nfq = 0;  // fine positions other than the line axis (the mode axes)
+    for (int q = 0; q < m.nfine; ++q)
+        if (q != lp) fq[nfq++] = q;
+    std::vector<double> &out = p.cr_tab[mask];
+    out.assign((size_t)nmodes * L * 3 * MM, 0.0);
+    auto run = [&](long long m0, long long m1, bool *ok) {
+        std::vector<double> B(MM), A(MM), C(MM), G(MM), T1(MM), T2(MM), LU(MM), inv(MM);
+        for (long long mode = m0; mode < m1; ++mode) {
+            double sigma = 0.0;
+            long long rem = mode;
+            for (int t = 0; t < nfq; ++t) {
+                const int mq = (int)(rem % m.ext[fq[t]]);
+                rem /= m.ext[fq[t]];
+                sigma += p.fine_spec[m.ax[fq[t]]].mu[mq];
+            }
+            B = Kc;
+            std::fill(A.begin(), A.end(), 0.0);
+            std::fill(C.begin(), C.end(), 0.0);
+            for (int i = 0; i < NB; ++i) {
+                B[(size_t)i * NB + i] += tw.b + sigma;
+                A[(size_t)i * NB + i] = tw.a;
+                C[(size_t)i * NB + i] = tw.c;
+            }
+            for (int l = 0; l < L; ++l) {
+                LU = B;
+                if (!dense_inverse(NB, LU, inv.data())) {
+                    *ok = false;
+                    return;
+                }
+                for (int i = 0; i < NB; ++i)  // dense_inverse writes column by column
+                    for (int j = 0; j < NB; ++j) G[(size_t)i * NB + j] = inv[(size_t)j * NB + i];
+                double *dst = out.data() + ((size_t)mode * L + l) * 3 * MM;
+                std::copy(G.begin(), G.end(), dst);
+                matmul(NB, G.data(), A.data(), dst + MM);
+                matmul(NB, G.data(), C.data(), dst + 2 * MM);
+                if (l == L - 1) break;
+                // B -= A G C + C G A;  A = -A G A;  C = -C G C
+                matmul(NB, A.data(), dst + 2 * MM, T1.data());   // A (G C)
+                matmul(NB, C.data(), dst + MM, T2.data());       // C (G A)
+                for (size_t e = 0; e < MM; ++e) B[e] -= T1[e] + T2[e];
+                matmul(NB, A.data(), dst + MM, T1.data());       // A G A
+                matmul(NB, C.data(), dst + 2 * MM, T2.data());   // C G C
+                for (size_t e = 0; e < MM; ++e) {
+                    A[e] = -T1[e];
+                    C[e] = -T2[e];
+                }
+            }
+        }
+    };
+    int nt = 1;
+    if (nmodes >= 16 && (double)nmodes * L * MM * NB > 1e7)
+        nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    std::vector<char> oks(nt, 1);
+    std::vector<std::thread> pool;
+    const long long chunk = (nmodes + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+        const long long a = t * chunk, b = std::min<long long>(nmodes, a + chunk);
+        if (a >= b) continue;
+        if (nt == 1) {
+            bool ok = true;
+            run(a, b, &ok);
+            oks[t] = ok;
+        } else {
+            pool.emplace_back([&, t, a, b] {
+                bool ok = true;
+                run(a, b, &ok);
+                oks[t] = ok;
+            });
+        }
+    }
+    for (std::thread &th : pool) th.join();
+    for (char o : oks)
+        if (!o) return false;
+    return true;
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 void layout_workspace(Plan &p, char *base, bool assign) {
@@ -464,80 +585,147 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         g.fine[j] = (j < d) ? op1d(alpha[j], beta[j], p.h) : Tri{0, 0, 0};
         g.coarse[j] = (j < d) ? op1d(alpha[j], beta[j], p.H) : Tri{0, 0, 0};
     }
-    // fast diagonalisation needs real spectra on the fine axes: |beta h / (2 alpha)| < 1
+    // Per fine axis: fast diagonalisation needs a real spectrum (|beta h / (2 alpha)| < 1) and is
+    // accurate to about eps * cond(V) with cond(V) = r^(N-1), V = D Q the eigenvector matrix.  An axis
+    // with a complex spectrum gets cond = inf; such axes are solved by line elimination instead.
+    const double kInf = std::numeric_limits<double>::infinity();
+    double cond_f[kMaxD], cond_h[kMaxD];
     for (int j = 0; j < d; ++j) {
         const double P = std::fabs(beta[j] * p.h / (2.0 * alpha[j]));
-        if (!(P < 1.0))
-            return fail(ASDSM_E_UNSUPPORTED, "cell Peclet number >= 1 on fine axis " +
-                                                 std::to_string(j) + " (complex spectrum)");
-        spectrum(g.fine[j], p.Nf, p.fine_spec[j]);
-        spectrum(g.fine[j], p.n - 1, p.hole_spec[j]);
+        if (P < 1.0) {
+            spectrum(g.fine[j], p.Nf, p.fine_spec[j]);
+            cond_f[j] = p.fine_spec[j].cond;
+        } else {
+            cond_f[j] = kInf;
+        }
+        if (P < 1.0 || p.n - 1 == 1) {
+            spectrum(g.fine[j], p.n - 1, p.hole_spec[j]);
+            cond_h[j] = p.hole_spec[j].cond;
+        } else {
+            cond_h[j] = kInf;
+        }
     }
     // hole line axis: the worst-conditioned axis is eliminated, the others are transformed
     p.hole_line_axis = 0;
     for (int j = 1; j < d; ++j)
-        if (p.hole_spec[j].cond > p.hole_spec[p.hole_line_axis].cond) p.hole_line_axis = j;
+        if (cond_h[j] > cond_h[p.hole_line_axis]) p.hole_line_axis = j;
+    {
+        double ch = 1.0;
+        for (int j = 0; j < d; ++j)
+            if (j != p.hole_line_axis) ch *= cond_h[j];
+        if (!(2.2e-16 * ch <= 1e-12))
+            return fail(ASDSM_E_UNSUPPORTED, "hole boxes: more than one axis too ill-conditioned for "
+                                             "fast diagonalisation (|cell Peclet| near or above 1)");
+    }
     build_spline(p.Nf, p.Nc, p.n, p.h, p.H, p.Sp);
     for (unsigned s = 0; s < (1u << d); ++s) p.mesh[s] = make_mesh(d, p.Nf, p.Nc, s);
-    // intersection meshes: per-mode dense inverses of at most kDenseMaxBlock coarse points, at most
-    // 2 GiB in total (d = 4 at 63^4 with N_c = 7 needs 0.74 GB)
+    // Refinement sweeps x <- x + M^-1 (f - A x) around a solve accurate to delta = eps * prod cond
+    // over its transformed axes, each gaining -log10(delta) digits, so that the result reaches
+    // ~1e-14; none where delta <= 2e-11; impossible (-1) from delta >= 0.05.
+    auto sweeps_for = [](double c) -> int {
+        const double delta = 2.2e-16 * c;
+        if (delta <= 2e-11) return 0;
+        if (!(delta < 0.05)) return -1;
+        return std::max(1, (int)std::ceil(std::log(1e-14) / std::log(delta)) - 1);
+    };
+    auto worse = [](int a, int b) { return a < 0 || (b >= 0 && a > b); };  // a needs more than b
+    // Anisotropic meshes: either every fine axis is transformed and the coarse axis eliminated
+    // (Thomas), or the worst fine axis of each becomes its line axis, solved together with the
+    // coarse axis by block cyclic reduction, and the others are transformed.  Line axes are used
+    // when the transforms alone cannot reach the accuracy, or need more sweeps.
+    int swA = 0, swB = 0;
+    int lineq[kMaxD];
+    double condB[kMaxD];
+    for (int k = 0; k < d; ++k) {
+        const MeshDesc &m = p.mesh[1u << k];
+        double cA = 1.0;
+        int wq = 0;
+        for (int q = 0; q < m.nfine; ++q) {
+            cA *= cond_f[m.ax[q]];
+            if (cond_f[m.ax[q]] > cond_f[m.ax[wq]]) wq = q;
+        }
+        double cB = 1.0;
+        for (int q = 0; q < m.nfine; ++q)
+            if (q != wq) cB *= cond_f[m.ax[q]];
+        lineq[k] = wq;
+        condB[k] = cB;
+        const int a = sweeps_for(cA), b = sweeps_for(cB);
+        if (worse(a, swA)) swA = a;
+        if (worse(b, swB)) swB = b;
+    }
+    if (swB < 0)
+        return fail(ASDSM_E_UNSUPPORTED, "a submesh has two fine axes that fast diagonalisation cannot "
+                                         "handle (|cell Peclet| near or above 1 on two axes)");
+    p.line_aniso = worse(swA, swB);
+    for (unsigned s = 0; s < kMaxMeshes; ++s) p.line_pos[s] = -1;
+    for (int k = 0; k < d; ++k) {
+        const unsigned m = 1u << k;
+        if (p.line_aniso) {
+            p.line_pos[m] = lineq[k];
+            p.fdm_cond[m] = condB[k];
+            p.sweeps[m] = swB;
+        } else {
+            double c = 1.0;
+            for (int q = 0; q < p.mesh[m].nfine; ++q) c *= cond_f[p.mesh[m].ax[q]];
+            p.fdm_cond[m] = c;
+            p.sweeps[m] = swA;  // the anisotropic meshes are solved together: the largest count
+        }
+    }
+    // FP32 error guesses: transformed fine axes only, if the conditioning allows
+    p.fp32_ok = !p.line_aniso;
+    for (int k = 0; k < d && p.fp32_ok; ++k)
+        if (6e-8 * p.fdm_cond[1u << k] > 1e-3) p.fp32_ok = false;
+    // Intersection meshes: transforms of the fine axes and per-mode dense inverses of the coarse
+    // block, unless a fine axis cannot be transformed: then it is the line axis (block cyclic
+    // reduction with the coarse block as blocks).
     {
         double bytes = 0.0;
-        for (unsigned s = 1; s < (1u << d); ++s)
-            if (__builtin_popcount(s) >= 2) {
-                const MeshDesc &m = p.mesh[s];
+        for (unsigned s = 1; s < (1u << d); ++s) {
+            if (__builtin_popcount(s) < 2) continue;
+            const MeshDesc &m = p.mesh[s];
+            double cA = 1.0;
+            int wq = 0;
+            for (int q = 0; q < m.nfine; ++q) {
+                cA *= cond_f[m.ax[q]];
+                if (cond_f[m.ax[q]] > cond_f[m.ax[wq]]) wq = q;
+            }
+            int sw = sweeps_for(cA);
+            if (sw >= 0) {
+                p.fdm_cond[s] = cA;
+                p.sweeps[s] = sw;
                 if (m.block > kDenseMaxBlock)
                     return fail(ASDSM_E_UNSUPPORTED, "intersection mesh with more than " +
                                                          std::to_string(kDenseMaxBlock) +
                                                          " coarse points per mode");
                 bytes += 8.0 * (double)m.nmodes * m.block * m.block;
+                continue;
             }
+            double cB = 1.0;
+            for (int q = 0; q < m.nfine; ++q)
+                if (q != wq) cB *= cond_f[m.ax[q]];
+            sw = sweeps_for(cB);
+            if (sw < 0)
+                return fail(ASDSM_E_UNSUPPORTED, "an intersection mesh has two fine axes that fast "
+                                                 "diagonalisation cannot handle");
+            if (m.block > kCrMaxBlock)
+                return fail(ASDSM_E_UNSUPPORTED, "intersection mesh with a line axis and more than " +
+                                                     std::to_string(kCrMaxBlock) + " coarse points");
+            p.line_pos[s] = wq;
+            p.fdm_cond[s] = cB;
+            p.sweeps[s] = sw;
+        }
         if (bytes > 2048.0 * 1024 * 1024)
             return fail(ASDSM_E_UNSUPPORTED, "intersection-mesh inverses exceed 2 GiB");
     }
     for (unsigned s = 1; s < (1u << d); ++s) {
-        if (__builtin_popcount(s) >= 2) {
+        if (p.line_pos[s] >= 0) {
+            if (!build_cr_tables(p, s)) return fail(ASDSM_E_NUMERIC, "singular block in the line solve");
+        } else if (__builtin_popcount(s) >= 2) {
             if (!build_dense_inverse(p, s))
                 return fail(ASDSM_E_NUMERIC, "singular intersection-mesh operator");
         }
     }
-    // Fast diagonalisation of a fine axis uses the eigenvector matrix V = D Q with
-    // cond(V) = r^(N-1), so a mesh solve is accurate to about eps * prod cond(V_j) over its
-    // transformed axes.  Where that exceeds 2e-11 the direct solve becomes the preconditioner of
-    // FP64 refinement sweeps x <- x + M^-1 (f - A x), each gaining -log10(eps * prod cond) digits;
-    // the count is fixed here so that the result reaches ~1e-14.
-    p.fp32_ok = true;  // FP32 error guesses: every d, if the conditioning below allows
-    for (unsigned s = 1; s < (1u << d); ++s) {
-        double c = 1.0;
-        for (int q = 0; q < p.mesh[s].nfine; ++q) c *= p.fine_spec[p.mesh[s].ax[q]].cond;
-        p.fdm_cond[s] = c;
-        if (__builtin_popcount(s) == 1 && 6e-8 * c > 1e-3) p.fp32_ok = false;
-        const double delta = 2.2e-16 * c;
-        if (delta <= 2e-11) {
-            p.sweeps[s] = 0;
-        } else if (delta >= 0.05) {
-            return fail(ASDSM_E_UNSUPPORTED,
-                        "fine-axis eigenvector matrices too ill-conditioned for fast diagonalisation "
-                        "(|cell Peclet| close to 1 on two axes)");
-        } else {
-            p.sweeps[s] = (int)std::ceil(std::log(1e-14) / std::log(delta)) - 1;
-            if (p.sweeps[s] < 1) p.sweeps[s] = 1;
-        }
-    }
-    {
-        // the anisotropic meshes are solved together: they share the largest sweep count
-        int smax = 0;
-        for (int k = 0; k < d; ++k) smax = std::max(smax, p.sweeps[1u << k]);
-        for (int k = 0; k < d; ++k) p.sweeps[1u << k] = smax;
-        for (unsigned m = 0; m < kMaxMeshes; ++m) p.sweeps_prior[m] = p.sweeps[m];
-    }
-    {
-        double ch = 1.0;
-        for (int j = 0; j < d; ++j)
-            if (j != p.hole_line_axis) ch *= p.hole_spec[j].cond;
-        if (2.2e-16 * ch > 1e-12)
-            return fail(ASDSM_E_UNSUPPORTED, "hole-box transforms too ill-conditioned");
-    }
+    for (unsigned m = 0; m < kMaxMeshes; ++m) p.sweeps_prior[m] = p.sweeps[m];
     // partial-sum capacity: the largest grid used by a reducing kernel
     p.max_blocks = 1 << 16;
     layout_workspace(p, nullptr, false);
@@ -610,8 +798,11 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         oHC = add(p.hole_cp);
     }
     size_t oS = add(p.Sp);
-    for (unsigned s = 1; s < (1u << d); ++s)
-        if (__builtin_popcount(s) >= 2) oD[s] = add(p.dense_inv[s]);
+    size_t oCR[kMaxMeshes] = {};
+    for (unsigned s = 1; s < (1u << d); ++s) {
+        if (p.line_pos[s] >= 0) oCR[s] = add(p.cr_tab[s]);
+        else if (__builtin_popcount(s) >= 2) oD[s] = add(p.dense_inv[s]);
+    }
     p.dtab_bytes = off;
     err = hipMalloc(&p.dtab, p.dtab_bytes);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipMalloc(tables): ") + hipGetErrorString(err));
@@ -639,8 +830,11 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         p.dhole_inv = (double *)(base + oHI);
         p.dhole_cp = (double *)(base + oHC);
     }
-    for (unsigned s = 1; s < (1u << d); ++s)
-        if (__builtin_popcount(s) >= 2) p.ddense[s] = (double *)(base + oD[s]);
+    for (unsigned s = 1; s < (1u << d); ++s) {
+        if (p.line_pos[s] >= 0) p.dcr[s] = (double *)(base + oCR[s]);
+        else if (__builtin_popcount(s) >= 2) p.ddense[s] = (double *)(base + oD[s]);
+    }
+    for (unsigned s = 0; s < kMaxMeshes; ++s) std::vector<double>().swap(p.cr_tab[s]);
     err = hipHostMalloc((void **)&p.hscal, kScalCount * sizeof(double), hipHostMallocDefault);
     if (err == hipSuccess) err = hipHostMalloc((void **)&p.hstate, sizeof(IterState), hipHostMallocDefault);
     if (err == hipSuccess)

@@ -268,8 +268,8 @@ def test_error_codes(torch_dev):
     with pytest.raises(AsdsmError) as e:
         Plan(2, [1.0, 1.0], [0.0, 0.0], 5, 5)
     assert e.value.code == -2
-    with pytest.raises(AsdsmError) as e:              # cell Peclet number 1 on a fine axis
-        Plan(2, [1.0, 1.0], [2.0 * 32.0, 0.0], 5)
+    with pytest.raises(AsdsmError) as e:              # cell Peclet number 1.25 on two fine axes
+        Plan(3, [1.0, 1.0, 1.0], [80.0, 80.0, 0.0], 5)
     assert e.value.code == -6
     with pytest.raises(AsdsmError) as e:             # d outside 2..4
         Plan(5, [1.0] * 5, [0.0] * 5, 3)
@@ -305,12 +305,36 @@ def test_ill_conditioned_axis_refinement(torch_dev):
         assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, K
 
 
-def test_two_ill_conditioned_axes_are_refused(torch_dev):
-    """Two fine axes near cell Peclet 1: refinement cannot converge, the plan reports
-    ASDSM_E_UNSUPPORTED instead of returning inaccurate solves."""
+def test_two_ill_conditioned_axes_use_a_line_axis(torch_dev):
+    """Two fine axes with cell Peclet 0.47 at N_f = 63 (eigenvector matrices of condition 5.6e13
+    each): the submesh with both as fine axes cannot be diagonalised on both, so each anisotropic
+    mesh eliminates its worst fine axis by block cyclic reduction and transforms the other (with
+    refinement sweeps); submesh solves and iterates match the banded-LU oracle."""
+    _say("two ill-conditioned axes")
+    P = make_problem("sinbump3d", 6, seed=1, alpha=[0.1, 0.1, 0.8], beta=[6.0, -6.0, 1.0])
+    o = Oracle(3, P.alpha, P.beta, 6, seed=4)
+    pl = _plan(P, 6, 0, seed=4)
+    info = pl.line_axes()
+    assert info[1 << 2][0] in (0, 1) and info[1 << 2][1] >= 1   # M_2: one of the two, with sweeps
+    rng = np.random.default_rng(5)
+    for S in ((0,), (1,), (2,), (0, 1), (1, 2), (0, 2)):
+        mask = sum(1 << j for j in S)
+        rhs = rng.standard_normal(o.grid.mesh_dims(S))
+        x = pl.mesh_solve(mask, _t(torch_dev, _canon(3, S, rhs))).cpu().numpy()
+        assert _rel(_uncanon(o.grid, S, x), o.solve_mesh(S, rhs)) <= TOL_OP, S
+    ref = o.solve(P.s, P.g, max_iter=3, rtol=0, stag_window=0, keep_iterates=True)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    u, _ = pl.solve(s, g, max_iter=3, rtol=0, stag_window=0)
+    assert _rel(u.cpu().numpy(), ref.iterates[3].reshape(-1, order="F")) <= TOL_ITER
+
+
+def test_two_complex_axes_are_refused(torch_dev):
+    """Two fine axes with |cell Peclet| > 1 (complex 1D spectra): the submesh with both as fine
+    axes needs two line axes, which the plan does not build; it reports ASDSM_E_UNSUPPORTED instead
+    of returning inaccurate solves."""
     from paper_2303_01163_amd.asdsm import AsdsmError, Plan
     with pytest.raises(AsdsmError) as e:
-        Plan(3, [0.1, 0.1, 0.8], [6.0, -6.0, 1.0], 6)
+        Plan(3, [0.1, 0.1, 0.8], [13.0, -13.0, 1.0], 6)
     assert e.value.code == -6
 
 
@@ -489,7 +513,10 @@ def test_every_transform_tile_matches_the_oracle(torch_dev, L, Lc, seed):
     rhs = [rng.standard_normal(o.grid.mesh_dims((k,))) for k in range(3)]
     x_or = [o.solve_mesh((k,), rhs[k]) for k in range(3)]
     s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    line = any(ax >= 0 for ax, _ in pl.line_axes().values())
     for tile in ANISO_TILES:
+        if tile == "plane" and line:
+            continue  # the plane kernel transforms both fine axes; line-axis plans refuse it
         _say("tile", tile, L, Lc, seed)
         pl.set_tile(tile)
         for k in range(3):
@@ -500,8 +527,8 @@ def test_every_transform_tile_matches_the_oracle(torch_dev, L, Lc, seed):
 
 
 def test_every_transform_tile_at_full_size(torch_dev):
-    """127^3 (the benchmark's plan, one refinement sweep on its ill-conditioned axis): every tile
-    shape's anisotropic solves satisfy their equations, and the complete solves agree."""
+    """127^3 (the benchmark's plan: line axes on its ill-conditioned fine axis): every tile shape's
+    anisotropic solves satisfy their equations, and the complete solves agree."""
     P = make_problem("sinbump3d", 7, seed=0)
     o = Oracle(3, P.alpha, P.beta, 7)
     pl = _plan(P, 7, 0, seed=0)
@@ -509,7 +536,10 @@ def test_every_transform_tile_at_full_size(torch_dev):
     rng = np.random.default_rng(9)
     rhs = [rng.standard_normal(o.grid.mesh_dims((k,))) for k in range(3)]
     sols = {}
+    line = any(ax >= 0 for ax, _ in pl.line_axes().values())
     for tile in ANISO_TILES:
+        if tile == "plane" and line:
+            continue  # the plane kernel transforms both fine axes; line-axis plans refuse it
         _say("tile 127^3", tile)
         pl.set_tile(tile)
         for k in range(3):
@@ -538,11 +568,19 @@ def test_set_tile_errors(torch_dev):
     assert pl.tile_name() == "64x64 k16"
     pl.set_tile("auto")
     assert pl.tile_name() == "auto"
-    P3 = make_problem("sinbump3d", 5, seed=0)
+    P3 = make_problem("sinbump3d", 5, seed=4)
     pl3 = _plan(P3, 5, 2)
+    assert all(ax < 0 for ax, _ in pl3.line_axes().values())
     assert pl3.tile_name() == "plane panels 16"    # picked by size at N_f <= 127
     pl3.set_tile("32x32")
     assert pl3.tile_name() == "32x32 k32"
+    # a plan whose anisotropic meshes use line axes refuses the plane kernel
+    P4 = make_problem("sinbump3d", 5, seed=0)
+    pl4 = _plan(P4, 5, 2)
+    assert any(ax >= 0 for ax, _ in pl4.line_axes().values())
+    with pytest.raises(AsdsmError) as ei:
+        pl4.set_tile("plane")
+    assert ei.value.code == -6
 
 
 SPARSE_CASES = [  # d = 3: (family, level, coarse_level, seed)
