@@ -166,6 +166,22 @@ int asdsm_solve(asdsm_plan_t plan, const double *s, const double *g, double *u,
 int asdsm_residual(asdsm_plan_t plan, const double *u, const double *s, const double *g,
                    double *r, double *norm2);
 
+/* Allocation-free variant of asdsm_residual, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * r = b_ff - A_ff u and ||r||_2, formed in one stencil pass that assembles b_ff on the fly, without
+ * the plan's workspace (none need be attached) and without any allocating call.  Its per-block
+ * partial sums live in a 16 KiB file-scope device array, one copy per device, resolved when a plan is
+ * created on that device; every call on a device shares that copy and overwrites it, so calls that
+ * overlap on one device (other streams or threads) race.  Runs on the plan's stream and returns
+ * after it has finished.
+ *   u, s, g : device, layouts of asdsm_solve (not modified).
+ *   r       : device output of N_f^d doubles, may be NULL (then only the norm is formed).
+ *   norm2   : host output ||r||_2, may be NULL.
+ * Errors: ASDSM_E_ARG (NULL plan, u, s or g), ASDSM_E_UNSUPPORTED (more than 2^31 - 2^19 - 1 fine
+ * points: 32-bit indexing), ASDSM_E_DEVICE. */
+int asdsm_residual_noalloc(asdsm_plan_t plan, const double *u, const double *s, const double *g,
+                           double *r, double *norm2);
+
 /* Direct solve of one mesh system A_S x = rhs with zero Dirichlet data (the submesh solves of
  * Algorithm 1 step 1, eq. (6)).  mesh_mask: bit j set = axis j+1 coarse; ASDSM_MESH_FINE is not
  * accepted; the all-coarse mask is the coarse mesh.  rhs and x are device arrays in the mesh's

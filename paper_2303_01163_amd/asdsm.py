@@ -27,7 +27,8 @@ EXPORTED = ("asdsm_plan", "asdsm_workspace_size", "asdsm_set_workspace", "asdsm_
             "asdsm_residual", "asdsm_mesh_solve", "asdsm_destroy", "asdsm_last_error",
             "asdsm_batch_create", "asdsm_batch_solve", "asdsm_batch_destroy", "asdsm_autotune",
             "asdsm_tile_name", "asdsm_set_tile", "asdsm_get_tile", "asdsm_probe_mfma_scratch_bytes",
-            "asdsm_probe_mfma_f64", "asdsm_probe_copy", "asdsm_profile_count", "asdsm_profile_entry", "asdsm_line_axes")
+            "asdsm_probe_mfma_f64", "asdsm_probe_copy", "asdsm_profile_count", "asdsm_profile_entry", "asdsm_line_axes",
+            "asdsm_residual_noalloc")
 # symbols declared in include/asdsm_learn.h
 EXPORTED_LEARN = ("asdsm_net_create", "asdsm_net_param_count", "asdsm_net_workspace_size",
                   "asdsm_net_set_workspace", "asdsm_net_params", "asdsm_net_forward",
@@ -97,6 +98,8 @@ def load_library():
     lib.asdsm_probe_mfma_f64.restype = c_int
     lib.asdsm_probe_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_int, c_void_p, POINTER(c_double)]
     lib.asdsm_probe_copy.restype = c_int
+    lib.asdsm_residual_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double)]
+    lib.asdsm_residual_noalloc.restype = c_int
     lib.asdsm_line_axes.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int)]
     lib.asdsm_line_axes.restype = c_int
     lib.asdsm_profile_count.argtypes = [c_void_p]
@@ -325,6 +328,19 @@ class Plan:
             _check(lib.asdsm_residual(self._h, _dptr(u, self.n_fine, "u"), _dptr(s, self.n_fine, "s"),
                                       _dptr(g, 2 * self.d * self.n_f ** (self.d - 1), "g"),
                                       _dptr(r, self.n_fine, "r") if want_r else None, byref(nrm)))
+        return r, nrm.value
+
+    def residual_noalloc(self, u, s, g, r=None):
+        """r = b - A u and ||r||_2 through the allocation-free entry point (asdsm_residual_noalloc):
+        r, if given, is a caller-owned device tensor of N_f^d doubles; returns (r, ||r||_2)."""
+        import torch
+        lib = load_library()
+        nrm = c_double()
+        with torch.cuda.device(self.device):
+            _check(lib.asdsm_residual_noalloc(self._h, _dptr(u, self.n_fine, "u"), _dptr(s, self.n_fine, "s"),
+                                              _dptr(g, 2 * self.d * self.n_f ** (self.d - 1), "g"),
+                                              _dptr(r, self.n_fine, "r") if r is not None else None,
+                                              byref(nrm)))
         return r, nrm.value
 
     def mesh_solve(self, mask: int, rhs):

@@ -1877,6 +1877,15 @@ int asdsm_residual(asdsm_plan_t plan, const double *u, const double *s, const do
     return ASDSM_OK;
 }
 
+int asdsm_residual_noalloc(asdsm_plan_t plan, const double *u, const double *s, const double *g,
+                           double *r, double *norm2) {
+    if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
+    if (!u || !s || !g) return fail(ASDSM_E_ARG, "u, s and g must be non-NULL device pointers");
+    if (int rc = residual_noalloc(plan->p, u, s, g, r, norm2)) return rc;
+    set_error("");
+    return ASDSM_OK;
+}
+
 int asdsm_mesh_solve(asdsm_plan_t plan, unsigned mesh_mask, const double *rhs, double *x) {
     if (!plan) return fail(ASDSM_E_ARG, "plan must be non-NULL");
     Plan &p = plan->p;

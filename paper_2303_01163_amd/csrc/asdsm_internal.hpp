@@ -114,6 +114,7 @@ enum ScalarSlot {
     kScalEnorm2 = 5,   // ||e_k||^2, k = 0..d-1  (slots 5..8)
     kScalInvNorm = 9,  // 1/||e_k|| or 1 (slots 9..12)
     kScalFlags = 13,   // non-finite flag accumulator
+    kScalNoalloc = 14, // host mirror only: ||r||^2 of asdsm_residual_noalloc
     kScalCount = 16
 };
 

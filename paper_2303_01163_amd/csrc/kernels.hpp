@@ -28,6 +28,12 @@ LaunchEvents &launch_events();  // per host thread
         }                                                                                         \
     } while (0)
 
+// Allocation-free residual (k_noalloc.hip): resolve the device's copy of its scratch array (once
+// per device, from the plan constructor), and r = b_ff - A_ff u with ||r||_2 on the plan's stream.
+int noalloc_setup(int device);
+int residual_noalloc(const Plan &p, const double *u, const double *s, const double *g, double *r,
+                     double *norm2_host);
+
 // Block cyclic reduction along a submesh's line axis (k_blockcr.hip): per mode of the diagonalised
 // fine axes, the line's N = 2^L - 1 positions each hold the mesh's coarse block (NB points).
 // Element (mode, i, c) of a box lives at (mode % mext0) ms0 + (mode / mext0) ms1 + i sw + c sc.

@@ -737,6 +737,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         std::call_once(plane_once, plane_prepare);
     }
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(err));
+    if (int rc = noalloc_setup(p.device)) return rc;
     size_t off = 0;
     struct Item {
         size_t off;
