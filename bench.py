@@ -162,6 +162,8 @@ def parse():
     ap.add_argument("--d4-level", type=int, default=6,
                     help="fine level of the d = 4 side measurement (0 skips it)")
     ap.add_argument("--d4-batch", type=int, default=8, help="members of the d = 4 batch (0 skips it)")
+    ap.add_argument("--hbm-level", type=int, default=8,
+                    help="fine level of the stencil-bandwidth leg beyond the Infinity Cache (0 skips it)")
     return ap.parse_args()
 
 
@@ -281,6 +283,8 @@ def main():
         out["batched"] = batched(asdsm, make_problem, args, dev)
     if args.learn_pairs > 0:
         out["learned"] = learned(asdsm, make_problem, L, args, dev)
+    if args.hbm_level > 0:
+        out["hbm_stencils"] = hbm_stencils(asdsm, make_problem, args, dev)
     if args.d4_level > 0:
         out["d4"] = four_d(asdsm, make_problem, args, dev)
     if not args.no_cpu_baseline:
@@ -294,15 +298,81 @@ def main():
     print(json.dumps(out))
 
 
-def four_d(asdsm, make_problem, args, dev, seed=0, steps=3):
-    """d = 4 (the 4D configuration): 63^4 fine unknowns, N_c = 7, the sinusoid-product family
-    (alpha_i log-uniform in [0.1, 1], beta_i uniform in [-2, 2]), FP64, the same stopping rule.
-    Plan construction (host LU of the intersection meshes' per-mode blocks) is outside the timing."""
+def hbm_stencils(asdsm, make_problem, args, dev, steps=20):
+    """The fine-mesh passes where the working set exceeds the 256 MB Infinity Cache (255^3: five
+    live 133 MB vectors): a profiled fine-mesh refinement loop of `steps` steps of the 255^3 draw
+    of the workload family (seed 0), each pass's algorithmic bytes over its own launches' event
+    time, against the 8 TB/s HBM peak; and the skeleton-sparse loop's time per step at that size."""
+    import torch
+    L = args.hbm_level
+    P = make_problem("sinbump3d", L, seed=0)
+    plan = asdsm.Plan(3, P.alpha, P.beta, L, 0, seed=0, device=0)
+    s = torch.from_numpy(P.s_flat()).to(dev)
+    g = torch.from_numpy(P.g_flat()).to(dev)
+    u = torch.empty(plan.n_fine, dtype=torch.float64, device=dev)
+    kw = dict(max_iter=steps, rtol=0.0, stag_window=0)
+    plan.solve(s, g, u=u, profile=True, **kw)
+    kp = {k["name"]: k for k in plan.kernel_profile()}
+    passes = {}
+    for name in ("fine update pass (+ its finalize)", "fine dots pass (+ its finalize)",
+                 "hole filler (error guess)"):
+        k = kp.get(name)
+        if not k or k["launches"] == 0:
+            continue
+        avg = k["ms"] / k["launches"]
+        gbs = k["bytes"] / k["launches"] / (avg * 1e-3) / 1e9
+        passes[name] = {"launches": k["launches"], "avg_launch_us": 1e3 * avg,
+                        "algorithmic_MB_per_launch": k["bytes"] / k["launches"] / 1e6,
+                        "GB/s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    times = {}
+    for skel in (False, True):
+        plan.solve(s, g, u=u, skeleton=skel, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            plan.solve(s, g, u=u, skeleton=skel, **kw)
+        torch.cuda.synchronize()
+        times["skeleton-sparse" if skel else "fine-mesh"] = 1e3 * (time.perf_counter() - t0) / 3
+    out = {"workload": f"asdsm-3d-{plan.n_f}^3-sinbump-seed0", "fine_unknowns": plan.n_fine,
+           "steps": steps, "passes": passes,
+           "ms_per_solve_of_the_steps": times,
+           "line_axes": {str(m): v[0] for m, v in plan.line_axes().items() if m in (1, 2, 4)}}
+    plan.close()
+    return out
+
+
+def admitted_draws(asdsm, make_problem, family, d, L, Lc, seeds, count):
+    """The first `count` seeds of `seeds` whose coefficient draw the plan accepts (a submesh with two
+    fine axes that need line solves is refused), and the refused seeds.  The coefficients are the
+    first draws of a problem's generator, so they are read from a tiny instance."""
+    ok, refused = [], []
+    for sd in seeds:
+        if len(ok) >= count:
+            break
+        c = make_problem(family, 2, seed=sd, d=d)
+        try:
+            pl = asdsm.Plan(d, c.alpha, c.beta, L, Lc, seed=sd, device=0)
+        except asdsm.AsdsmError:
+            refused.append(sd)
+            continue
+        pl.close()
+        ok.append(sd)
+    return ok, refused
+
+
+def four_d(asdsm, make_problem, args, dev, steps=3):
+    """d = 4 (the 4D configuration): 63^4 fine unknowns, N_c = 7, the advection-dominated family of
+    that configuration (alpha_i log-uniform in [0.01, 1], beta_i uniform in [-10, 10]), FP64, a
+    fixed budget of args.side_max_iter steps with the stagnation rule.  The first seed the plan
+    accepts is timed; refused seeds are reported.  Plan construction (host LU of the intersection
+    meshes' per-mode blocks and the line-solve tables) is outside the timing."""
     import numpy as np
     import torch
     L = args.d4_level
     Lc = max(1, L // 2)
-    P = make_problem("sinprod", L, seed=seed, d=4)
+    ok, refused = admitted_draws(asdsm, make_problem, "sinbump_wide", 4, L, Lc, range(0, 64), 1)
+    seed = ok[0]
+    P = make_problem("sinbump_wide", L, seed=seed, d=4)
     t0 = time.perf_counter()
     plan = asdsm.Plan(4, P.alpha, P.beta, L, Lc, seed=seed, device=0)
     plan_s = time.perf_counter() - t0
@@ -319,12 +389,16 @@ def four_d(asdsm, make_problem, args, dev, seed=0, steps=3):
     ms = 1e3 * (time.perf_counter() - t0) / steps
     _, prof = plan.solve(s, g, u=u, profile=True, **kw)
     ue = torch.from_numpy(np.ascontiguousarray(P.u_exact.reshape(-1, order="F"))).to(dev)
-    res = {"workload": f"asdsm-4d-{plan.n_f}^4-sinprod-seed{seed}", "coarse_level": Lc,
+    res = {"workload": f"asdsm-4d-{plan.n_f}^4-sinbump_wide-seed{seed}", "coarse_level": Lc,
+           "alpha": [float(x) for x in P.alpha], "beta": [float(x) for x in P.beta],
+           "refused_seeds_before": refused,
+           "line_axes": {str(m): v[0] for m, v in plan.line_axes().items() if bin(m).count("1") == 1},
            "fine_unknowns": plan.n_fine, "ms_per_solve": ms,
            "fine_unknowns_per_s": plan.n_fine / (ms * 1e-3), "iterations": info["iterations"],
            "status": info["status"], "rel_residual": info["rnorm"] / info["bnorm"],
            "rel_error_vs_manufactured": float(torch.linalg.norm(u - ue) / torch.linalg.norm(ue)),
-           "plan_seconds": plan_s, "phase_ms": prof["phase_ms"], "phase_launches": prof["phase_launches"]}
+           "plan_seconds": plan_s, "phase_ms": prof["phase_ms"], "phase_launches": prof["phase_launches"],
+           "kernels": kernel_table(plan.kernel_profile())}
     del plan, s, g, u, ue
     res["mixed_precision"] = four_d_mixed(asdsm, make_problem, args, dev, L, Lc)
     if getattr(args, "d4_batch", 0) > 0:
@@ -333,8 +407,10 @@ def four_d(asdsm, make_problem, args, dev, seed=0, steps=3):
 
 
 def four_d_mixed(asdsm, make_problem, args, dev, L, Lc, seed=1, steps=3):
-    """FP32 against FP64 error guesses at d = 4 on a draw whose transforms admit FP32 (seed 1: the
-    plan's conditioning rule 6e-8 prod cond(V_j) <= 1e-3 holds; the seed-0 draw does not)."""
+    """FP32 against FP64 error guesses at d = 4 on a draw whose transforms admit FP32: the narrower
+    sinusoid family (alpha_i log-uniform in [0.1, 1], beta_i in [-2, 2]), seed 1, where the plan's
+    conditioning rule 6e-8 prod cond(V_j) <= 1e-3 holds; the advection-dominated draws rarely admit
+    FP32 transforms (line axes or ill-conditioned eigenvectors)."""
     import torch
     P = make_problem("sinprod", L, seed=seed, d=4)
     plan = asdsm.Plan(4, P.alpha, P.beta, L, Lc, seed=seed, device=0)
@@ -359,15 +435,19 @@ def four_d_mixed(asdsm, make_problem, args, dev, L, Lc, seed=1, steps=3):
 
 
 def four_d_batch(asdsm, make_problem, args, dev, L, Lc, steps=2):
-    """The 4D configuration's batch: args.d4_batch independent 63^4 draws (seeds 100, 101, ...),
-    one after the other and as one batch (one graph replay advances every member two steps)."""
+    """The 4D configuration's batch: the first args.d4_batch draws of the advection-dominated family
+    (seeds 100, 101, ...) that the plan accepts, one after the other and as one batch (one graph
+    replay advances every member two steps); refused seeds reported."""
     import torch
+    seeds, refused = admitted_draws(asdsm, make_problem, "sinbump_wide", 4, L, Lc, range(100, 200),
+                                    args.d4_batch)
     plans, ss, gs = [], [], []
-    for i in range(args.d4_batch):
-        P = make_problem("sinprod", L, seed=100 + i, d=4)
-        plans.append(asdsm.Plan(4, P.alpha, P.beta, L, Lc, seed=100 + i, device=0))
+    for sd in seeds:
+        P = make_problem("sinbump_wide", L, seed=sd, d=4)
+        plans.append(asdsm.Plan(4, P.alpha, P.beta, L, Lc, seed=sd, device=0))
         ss.append(torch.from_numpy(P.s_flat()).to(dev))
         gs.append(torch.from_numpy(P.g_flat()).to(dev))
+        del P
     us = [torch.empty(p.n_fine, dtype=torch.float64, device=dev) for p in plans]
     kw = dict(max_iter=args.side_max_iter, rtol=args.rtol, stag_window=3, stag_eta=1e-3)
     for p, s, g, u in zip(plans, ss, gs, us):
@@ -387,7 +467,8 @@ def four_d_batch(asdsm, make_problem, args, dev, L, Lc, steps=2):
     torch.cuda.synchronize()
     t_bat = 1e3 * (time.perf_counter() - t0) / steps
     n = sum(p.n_fine for p in plans)
-    return {"members": len(plans), "fine_unknowns": n, "iterations": [i["iterations"] for i in binfos],
+    return {"members": len(plans), "seeds": seeds, "refused_seeds": refused, "fine_unknowns": n,
+            "iterations": [i["iterations"] for i in binfos],
             "ms_sequential": t_seq, "ms_batched": t_bat, "unknowns_per_s_sequential": n / (t_seq * 1e-3),
             "unknowns_per_s_batched": n / (t_bat * 1e-3), "speedup": t_seq / t_bat}
 

@@ -273,9 +273,13 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
         }
         // modes per workgroup: 8 when the first mode axis is contiguous (coalesced loads), else 2;
         // fewer when the LDS does not hold them; the global-memory form when not even one fits
-        int tm = (job.box[0].ms0 == 1) ? 8 : 2;
-        while (tm > 1 && cr_lds_bytes(job.N, job.NB, tm) > kCrMaxLds) tm /= 2;
-        if (!cr_lds_supported(job.NB) || cr_lds_bytes(job.N, job.NB, tm) > kCrMaxLds) tm = 0;
+        int tm = cr2_modes_per_group(job.N, job.L, job.NB, nm, nb);
+        job.fast = tm > 0 ? 1 : 0;
+        if (!job.fast) {
+            tm = (job.box[0].ms0 == 1) ? 8 : 2;
+            while (tm > 1 && cr_lds_bytes(job.N, job.NB, tm) > kCrMaxLds) tm /= 2;
+            if (!cr_lds_supported(job.NB) || cr_lds_bytes(job.N, job.NB, tm) > kCrMaxLds) tm = 0;
+        }
         if (tm == 0 && job.accum)
             return fail(ASDSM_E_UNSUPPORTED, "line solve: accumulation needs the LDS form");
         job.tm = tm;
@@ -1121,18 +1125,19 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
     if (int rc = error_guess(p)) return rc;
     {
         PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
-                     8.0 * ((double)p.geo.NF + aniso_points(p)));
+                     8.0 * ((double)p.geo.NF + aniso_points(p)), "hole filler (error guess)");
         launch_filler(p, nullptr, p.ws.e, p.stream);
         if (int rc = check_launch("filler")) return rc;
     }
     {
-        PhaseTimer t(p, ASDSM_PHASE_DOTS, 1, (4.0 * p.d + 6.0) * (double)p.geo.NF, 16.0 * (double)p.geo.NF);
+        PhaseTimer t(p, ASDSM_PHASE_DOTS, 1, (4.0 * p.d + 6.0) * (double)p.geo.NF, 16.0 * (double)p.geo.NF,
+                     "fine dots pass (+ its finalize)");
         launch_dots(p, p.stream);
         if (int rc = check_launch("dots")) return rc;
     }
     {
         PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, (4.0 * p.d + 6.0) * (double)p.geo.NF,
-                     8.0 * (5.0 * (double)p.geo.NF + aniso_points(p)));
+                     8.0 * (5.0 * (double)p.geo.NF + aniso_points(p)), "fine update pass (+ its finalize)");
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
         launch_update_residual(p, u_cur, p.ws.e, u_next, gat, kFinIter, p.stream);

@@ -208,6 +208,148 @@ __global__ __launch_bounds__(256) void k_block_cr(CrJob job) {
     }
 }
 
+// The fast form: the whole line of `tm` modes and every level's matrices of those modes staged in
+// LDS once (one burst of global loads, the matrices of consecutive modes being contiguous), then
+// the 2 (L - 1) + 1 levels run from LDS.  Thread (mode, row r, group e) produces row r of the
+// equations q = e, e + E, ... of a level (E = 256 / (tm RB) groups, RB = NB rounded up to a power
+// of two), so a level costs about (equations / E) * 2 NB multiply-adds per thread.  Forward
+// reduction writes only the thread's own row of a kept equation and reads eliminated neighbours,
+// so it runs in place; back substitution reads a whole row-block of the equation it overwrites, so
+// its results are held in registers until a barrier.  The solved line is copied to dst at the end.
+constexpr int kCrMaxPerThread = 16;
+
+template <int NB, int RB>
+__global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
+    if (job.gate && *job.gate) return;
+    extern __shared__ double lds[];
+    const int box = blockIdx.y;
+    const CrBox &bx = job.box[box];
+    const long long mode0 = (long long)blockIdx.x * job.tm;
+    if (mode0 >= bx.nmodes) return;
+    const int tmw = job.tm;                                  // modes per workgroup (layout)
+    const int tm = (int)((bx.nmodes - mode0) < tmw ? (bx.nmodes - mode0) : tmw);
+    const int N = job.N, L = job.L, tid = threadIdx.x;
+    constexpr int MM = NB * NB;
+    double *D = lds;                                         // [tmw][N][NB]
+    double *Mt = lds + (size_t)tmw * N * NB;                 // [tmw][L][3][MM]
+    const size_t mats = (size_t)tm * L * 3 * MM;
+    const double *tsrc = bx.tab + (size_t)mode0 * L * 3 * MM;
+    for (size_t e = tid; e < mats; e += 256) Mt[e] = tsrc[e];
+    const bool modes_fast = bx.ms0 == 1;
+    for (int t = tid; t < tm * N * NB; t += 256) {
+        int ml, i, c;
+        if (modes_fast) {
+            ml = t % tm;
+            const int rest = t / tm;
+            i = rest % N;
+            c = rest / N;
+        } else {
+            i = t % N;
+            const int rest = t / N;
+            ml = rest % tm;
+            c = rest / tm;
+        }
+        const long long mode = mode0 + ml;
+        const long long m0 = mode % bx.mext0, m1 = mode / bx.mext0;
+        D[((size_t)ml * N + i) * NB + c] = bx.src[m0 * bx.ms0 + m1 * bx.ms1 + (long long)i * bx.sw + (long long)c * bx.sc];
+    }
+    __syncthreads();
+    const int E = 256 / (tmw * RB);
+    const int ml = tid / (RB * E), rem = tid % (RB * E), r = rem % RB, eg = rem / RB;
+    const bool act = ml < tm && r < NB;
+    double *Dm = D + (size_t)(ml < tm ? ml : 0) * N * NB;
+    const double *Mm = Mt + (size_t)(ml < tm ? ml : 0) * L * 3 * MM;
+    // ---- forward reduction, levels 0 .. L-2: f_i[r] -= P[r,:] f_(i-s) + Q[r,:] f_(i+s)
+    for (int l = 0; l <= L - 2; ++l) {
+        const int step = 1 << l, nkeep = (1 << (L - l - 1)) - 1;
+        if (act) {
+            double pr[NB], qr[NB];
+            const double *P = Mm + ((size_t)l * 3 + 1) * MM + r * NB, *Q = P + MM;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                pr[c] = P[c];
+                qr[c] = Q[c];
+            }
+            for (int q = eg; q < nkeep; q += E) {
+                const int i0 = (q + 1) * 2 * step - 1;   // 0-based
+                const double *a = Dm + (size_t)(i0 - step) * NB, *b = Dm + (size_t)(i0 + step) * NB;
+                double acc = Dm[(size_t)i0 * NB + r];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) acc -= pr[c] * a[c] + qr[c] * b[c];
+                Dm[(size_t)i0 * NB + r] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    // ---- back substitution, levels L-1 .. 0: x_i[r] = G[r,:] f_i - P[r,:] x_(i-s) - Q[r,:] x_(i+s)
+    for (int l = L - 1; l >= 0; --l) {
+        const int step = 1 << l, nel = 1 << (L - l - 1);
+        double res[kCrMaxPerThread];
+        if (act) {
+            double gr[NB], pr[NB], qr[NB];
+            const double *G = Mm + ((size_t)l * 3) * MM + r * NB, *P = G + MM, *Q = G + 2 * MM;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                gr[c] = G[c];
+                pr[c] = P[c];
+                qr[c] = Q[c];
+            }
+#pragma unroll
+            for (int k = 0; k < kCrMaxPerThread; ++k) {
+                const int q = eg + k * E;
+                if (q >= nel) break;
+                const int i = (2 * q + 1) * step;        // 1-based
+                const double *f = Dm + (size_t)(i - 1) * NB;
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c < NB; ++c) acc += gr[c] * f[c];
+                if (i - step >= 1) {
+                    const double *a = Dm + (size_t)(i - 1 - step) * NB;
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) acc -= pr[c] * a[c];
+                }
+                if (i + step <= N) {
+                    const double *b = Dm + (size_t)(i - 1 + step) * NB;
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) acc -= qr[c] * b[c];
+                }
+                res[k] = acc;
+            }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < kCrMaxPerThread; ++k) {
+                const int q = eg + k * E;
+                if (q >= nel) break;
+                const int i = (2 * q + 1) * step;
+                Dm[(size_t)(i - 1) * NB + r] = res[k];
+            }
+        }
+        __syncthreads();
+    }
+    // ---- the solved line to dst (added when accumulating), in the load's coalesced order
+    for (int t = tid; t < tm * N * NB; t += 256) {
+        int mlw, i, c;
+        if (modes_fast) {
+            mlw = t % tm;
+            const int rest = t / tm;
+            i = rest % N;
+            c = rest / N;
+        } else {
+            i = t % N;
+            const int rest = t / N;
+            mlw = rest % tm;
+            c = rest / tm;
+        }
+        const long long mode = mode0 + mlw;
+        const long long m0 = mode % bx.mext0, m1 = mode / bx.mext0;
+        const long long a = m0 * bx.ms0 + m1 * bx.ms1 + (long long)i * bx.sw + (long long)c * bx.sc;
+        const double v = D[((size_t)mlw * N + i) * NB + c];
+        bx.dst[a] = job.accum ? bx.dst[a] + v : v;
+    }
+}
+
 // Any block size (intersection meshes of the initial guess, whose coarse block holds N_c^|S|
 // points): one workgroup per mode, the line solved in place in dst (canonical layout) after src is
 // copied there; one (equation, row) pair per task.  Back substitution reads a whole row-block of the
@@ -297,11 +439,53 @@ size_t cr_lds_bytes(int N, int NB, int tm) {
     return 8ull * ((size_t)tm * Nk * NB + (size_t)tm * 3 * NB * NB);
 }
 
+// LDS of the fast form: the whole line and all levels' matrices of tm modes
+size_t cr2_lds_bytes(int N, int L, int NB, int tm) {
+    return 8ull * (size_t)tm * ((size_t)N * NB + (size_t)L * 3 * NB * NB);
+}
+
+static int cr_rb(int NB) {
+    int rb = 1;
+    while (rb < NB) rb *= 2;
+    return rb;
+}
+
+// modes per workgroup of the fast form, or 0 when it does not apply: 256 threads hold tm * RB rows
+// with at least one equation group, the back substitution's per-thread results fit the register
+// array, and the LDS holds the lines and matrices
+int cr2_modes_per_group(int N, int L, int NB, long long nmodes, int nbox) {
+    if (!(NB == 1 || NB == 3 || NB == 7 || NB == 9 || NB == 15)) return 0;
+    const int rb = cr_rb(NB);
+    for (int tm = 8; tm >= 1; tm /= 2) {
+        if (tm * rb > 256) continue;
+        const int E = 256 / (tm * rb);
+        if ((1 << (L - 1)) > E * kCrMaxPerThread) continue;
+        if (cr2_lds_bytes(N, L, NB, tm) > kCrMaxLds) continue;
+        // fewer modes per group while that still leaves under one group per CU
+        if (tm > 1 && (nmodes * nbox + tm - 1) / tm < 256 && cr2_lds_bytes(N, L, NB, tm / 2) <= kCrMaxLds) continue;
+        return tm;
+    }
+    return 0;
+}
+
 bool cr_lds_supported(int NB) { return NB == 1 || NB == 3 || NB == 7 || NB == 9 || NB == 15; }
 
 bool launch_block_cr(const CrJob &job, hipStream_t st) {
     long long maxm = 0;
     for (int b = 0; b < job.nbox; ++b) maxm = std::max(maxm, job.box[b].nmodes);
+    if (job.fast) {
+        const dim3 grid((unsigned)((maxm + job.tm - 1) / job.tm), (unsigned)job.nbox);
+        const size_t lds = cr2_lds_bytes(job.N, job.L, job.NB, job.tm);
+        if (lds > kCrMaxLds) return false;
+        switch (job.NB) {
+            case 1: ASDSM_LAUNCH((k_block_cr2<1, 1>), grid, dim3(256), lds, st, job); return true;
+            case 3: ASDSM_LAUNCH((k_block_cr2<3, 4>), grid, dim3(256), lds, st, job); return true;
+            case 7: ASDSM_LAUNCH((k_block_cr2<7, 8>), grid, dim3(256), lds, st, job); return true;
+            case 9: ASDSM_LAUNCH((k_block_cr2<9, 16>), grid, dim3(256), lds, st, job); return true;
+            case 15: ASDSM_LAUNCH((k_block_cr2<15, 16>), grid, dim3(256), lds, st, job); return true;
+            default: return false;
+        }
+    }
     if (job.tm == 0) {  // the global-memory form, in place in dst
         ASDSM_LAUNCH(k_block_cr_global, dim3((unsigned)maxm, (unsigned)job.nbox), dim3(256), 0, st, job);
         return true;

@@ -52,10 +52,12 @@ struct CrJob {
     int tm;              // modes per workgroup (LDS form); 0: the global-memory form (in place
                          // in dst after copying src there; no accumulation)
     int accum;
+    int fast;            // 1: the form with the whole line and all levels' matrices in LDS
     const int *gate;
 };
 constexpr size_t kCrMaxLds = 64 * 1024;
 size_t cr_lds_bytes(int N, int NB, int tm);
+int cr2_modes_per_group(int N, int L, int NB, long long nmodes, int nbox);
 bool cr_lds_supported(int NB);  // block sizes with an LDS-staged kernel
 bool launch_block_cr(const CrJob &job, hipStream_t st);
 

@@ -203,7 +203,8 @@ class _Sum(_Manufactured):
 
 
 def _grid(d, x1d):
-    return list(np.meshgrid(*([x1d] * d), indexing="ij"))
+    # one broadcastable coordinate array per axis (no full meshgrid copies)
+    return [x1d.reshape([-1 if i == j else 1 for i in range(d)]) for j in range(d)]
 
 
 def _source(man, alpha, beta, xs):
@@ -219,13 +220,12 @@ def _faces(man, d, x1d):
     faces = np.empty((2 * d, n ** (d - 1)), dtype=np.float64)
     for j in range(d):
         others = [i for i in range(d) if i != j]
-        sub = np.meshgrid(*([x1d] * (d - 1)), indexing="ij")
         for side in (0, 1):
             xs = [None] * d
             for pos, ax in enumerate(others):
-                xs[ax] = sub[pos]
-            xs[j] = np.full(sub[0].shape if d > 1 else (), float(side))
-            val = man.value(xs)
+                xs[ax] = x1d.reshape([-1 if q == pos else 1 for q in range(d - 1)])
+            xs[j] = np.full((1,) * (d - 1), float(side))
+            val = np.broadcast_to(man.value(xs), (n,) * (d - 1))
             # lowest remaining axis fastest -> Fortran flatten of an array indexed by those axes
             faces[2 * j + side] = np.asarray(val, dtype=np.float64).reshape(-1, order="F")
     return faces
@@ -289,8 +289,9 @@ def make_problem(family: str, level: int, seed: int = 0, d: int | None = None,
         beta = np.asarray(beta_override, dtype=np.float64)
     x1d = fine_coords(level)
     xs = _grid(d, x1d)
-    s = np.asarray(_source(man, alpha, beta, xs), dtype=np.float64)
-    u = np.asarray(man.value(xs), dtype=np.float64)
+    shape = (x1d.size,) * d
+    s = np.array(np.broadcast_to(_source(man, alpha, beta, xs), shape), dtype=np.float64)
+    u = np.array(np.broadcast_to(man.value(xs), shape), dtype=np.float64)
     g = _faces(man, d, x1d)
     return Problem(d=d, level=level, alpha=np.asarray(alpha, np.float64),
                    beta=np.asarray(beta, np.float64), s=s, g=g, u_exact=u,
