@@ -94,8 +94,9 @@ typedef struct {
                           /* on the coarse planes (the residual vanishes in the holes,          */
                           /* Proposition 3.2(2)) and e only there and on the hole layers next to */
                           /* them; the holes of u are filled once when the loop ends.  Same     */
-                          /* iterates as the fine-mesh loop up to rounding.  Not in batches or  */
-                          /* learned solves.                                                     */
+                          /* iterates as the fine-mesh loop up to rounding.  In batches the d = 3 */
+                          /* members use it and the others the fine-mesh loop; not in learned    */
+                          /* solves.                                                             */
 } asdsm_opts;
 
 /* values of asdsm_opts.precision */
@@ -264,9 +265,10 @@ void asdsm_destroy(asdsm_plan_t plan);
 
 /* ---- batches of independent problems (any d, sizes and coefficients) ----
  * A batch runs the refinement loops (Algorithm 4) of its member plans together: every replay of
- * one captured HIP graph performs two refinement steps of every member, as parallel branches; a
- * member whose stopping rule has fired turns into no-ops while the others continue.  Results are
- * bitwise those of asdsm_solve on each plan with the same options. */
+ * one captured HIP graph performs two refinement steps of every member that is still running, as
+ * parallel branches; the host reads the members' loop states behind one pair of replays while the
+ * next runs, and captures the graph again without the members whose stopping rule has fired.
+ * Results are bitwise those of asdsm_solve on each plan with the same options. */
 typedef struct asdsm_batch_s *asdsm_batch_t;
 
 /* plans: host array of n distinct plans (1 <= n <= 4096) on one device, each with its workspace

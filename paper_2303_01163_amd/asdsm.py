@@ -381,8 +381,9 @@ class Batch:
             _check(lib.asdsm_batch_create(byref(self._h), arr, len(self.plans)))
 
     def solve(self, ss, gs, us=None, max_iter=50, rtol=1e-10, stag_window=3, stag_eta=1e-3,
-              precision="fp64", profile=False, eager=False):
-        """Returns (list of u, list of info); the histories are not collected in a batch."""
+              precision="fp64", profile=False, eager=False, skeleton=False):
+        """Returns (list of u, list of info); the histories are not collected in a batch.  With
+        skeleton=True the d = 3 members run the skeleton-sparse loop."""
         import torch
         lib = load_library()
         n = len(self.plans)
@@ -394,7 +395,7 @@ class Batch:
         o = Opts(max_iter=int(max_iter), rtol=float(rtol), stag_window=int(stag_window),
                  stag_eta=float(stag_eta), resume=0, k0=0, hist=None, step_hist=None,
                  profile=1 if profile else 0, eager=1 if eager else 0, precision=PRECISIONS[precision],
-                 skeleton=0)
+                 skeleton=1 if skeleton else 0)
         st = (Stats * n)()
         with torch.cuda.device(self.plans[0].device):
             _check(lib.asdsm_batch_solve(self._h, sp, gp, up, byref(o), st))

@@ -155,7 +155,8 @@ double *sol_buf(const Plan &p, unsigned m) {
 // (T[m][i]).  Position 0 is contiguous (one GEMM over all rows); a later position is a batch over
 // the outer positions of (N_f x N_f) times (N_f x inner) products.
 int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *const *in,
-                       const double *const *T, double *const *out, int accum) {
+                       const double *const *T, double *const *out, int accum,
+                       const int *norm_slot = nullptr) {
     GemmJob j{};
     j.nbox = nb;
     j.gate = p.gate;
@@ -183,6 +184,11 @@ int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *
             j.B[b] = in[b];
             j.C[b] = out[b];
         }
+    }
+    if (norm_slot && p.norm_partials) {
+        // the error guesses' sums of squares, norm_nblk per mesh in the order of the coarse axis
+        p.norm_nblk = gemm_tiles_per_box(j);
+        for (int b = 0; b < nb; ++b) j.norm_out[b] = p.norm_partials + (size_t)norm_slot[b] * p.norm_nblk;
     }
     PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
     if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
@@ -214,6 +220,12 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
         X[b] = p.ws.X[masks[b]];
         Y[b] = p.ws.Y[masks[b]];
     }
+    // the backward transforms of all anisotropic meshes in one launch leave the error guesses'
+    // sums of squares for the skeleton kernels (norm_partials, set by error_guess)
+    bool one_group = true;
+    for (int b = 1; b < nb && nt == 1; ++b) one_group = one_group && fq[b][0] == fq[0][0];
+    const bool fuse_norms = p.norm_partials && nt == 1 && one_group && nb == p.d &&
+                            __builtin_popcount(masks[0]) == 1;
     auto run_grouped = [&](int t, const double *const *src, double *const *dst, bool fwd, int acc) -> int {
         bool done[kMaxD] = {};
         for (int b = 0; b < nb; ++b) {
@@ -221,17 +233,20 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
             const int q = fq[b][t];
             const double *gs[kMaxD], *gT[kMaxD];
             double *gd[kMaxD];
+            int slot[kMaxD];
             int ng = 0;
             for (int c = b; c < nb; ++c)
                 if (!done[c] && fq[c][t] == q) {
                     done[c] = true;
                     gs[ng] = src[c];
                     gd[ng] = dst[c];
+                    slot[ng] = __builtin_ctz(masks[c]);
                     const int ax = p.mesh[masks[c]].ax[q];
                     gT[ng] = fwd ? p.dW[ax] : p.dV[ax];
                     ++ng;
                 }
-            if (int rc = transform_position(p, m, q, ng, gs, gT, gd, acc)) return rc;
+            const bool norms = !fwd && t == 0 && fuse_norms;
+            if (int rc = transform_position(p, m, q, ng, gs, gT, gd, acc, norms ? slot : nullptr)) return rc;
         }
         return ASDSM_OK;
     };
@@ -273,7 +288,9 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
         }
         // modes per workgroup: 8 when the first mode axis is contiguous (coalesced loads), else 2;
         // fewer when the LDS does not hold them; the global-memory form when not even one fits
-        int tm = cr2_modes_per_group(job.N, job.L, job.NB, nm, nb);
+        const bool aniso = __builtin_popcount(masks[0]) == 1;
+        int tm = cr2_modes_per_group(job.N, job.L, job.NB, nm, nb, aniso ? p.cr_tm : 0);
+        if (tm == 0 && aniso && p.cr_tm) tm = cr2_modes_per_group(job.N, job.L, job.NB, nm, nb);
         job.fast = tm > 0 ? 1 : 0;
         if (!job.fast) {
             tm = (job.box[0].ms0 == 1) ? 8 : 2;
@@ -1095,11 +1112,16 @@ int error_guess(Plan &p) {
         }
         if (int rc = solve_aniso32(p, in, out)) return rc;
     } else {
-        // with the plane kernel the backward transforms also leave the partial sums of ||e_k||^2
-        // that the skeleton kernels reduce themselves (no separate norm launches)
-        const bool fused = plane_transforms(p);
+        // with the plane kernel, or with line axes whose backward transforms run in one GEMM launch
+        // (d = 3), the backward transforms also leave the partial sums of ||e_k||^2 that the
+        // skeleton kernels reduce themselves (no separate norm launches)
+        bool fused = plane_transforms(p);
+        if (!fused && p.line_aniso && p.d == 3) {
+            fused = true;
+            for (int k = 1; k < 3; ++k) fused = fused && p.line_pos[1u << k] == p.line_pos[1u];
+        }
         p.norm_partials = fused ? p.ws.partials : nullptr;
-        p.norm_nblk = p.Nc * ((p.Nf + 15) / 16);
+        p.norm_nblk = p.Nc * ((p.Nf + 15) / 16);  // the plane kernel's count (the GEMM sets its own)
         const int rc = solve_aniso_refined(p, (1u << p.d) - 1);
         if (!fused) p.norm_partials = nullptr;
         if (rc) {
@@ -1236,6 +1258,12 @@ int ensure_loop_events(Plan &p) {
     return ASDSM_OK;
 }
 
+int read_state_on(Plan &p, hipStream_t st) {
+    ASDSM_HIP_CHECK(hipMemcpyAsync(p.hstate, p.ws.state, sizeof(IterState), hipMemcpyDeviceToHost, st));
+    ASDSM_HIP_CHECK(hipStreamSynchronize(st));
+    return ASDSM_OK;
+}
+
 int read_state(Plan &p) {
     ASDSM_HIP_CHECK(hipMemcpyAsync(p.hstate, p.ws.state, sizeof(IterState), hipMemcpyDeviceToHost, p.stream));
     ASDSM_HIP_CHECK(hipStreamSynchronize(p.stream));
@@ -1345,6 +1373,36 @@ int autotune_impl(Plan &p, int reps, int *best_tile, double *best_ms) {
         }
     }
     p.tile_aniso = best;
+    if (p.line_aniso) {
+        // modes per workgroup of the line solve: from the size rule, then each valid count
+        const int saved_tm = p.cr_tm;
+        int best_tm = 0;
+        const MeshDesc &m = p.mesh[1];
+        const long long nmodes = m.nmodes / m.ext[p.line_pos[1]];
+        for (int tm : {0, 1, 2, 4, 8}) {
+            if (tm > 0 && cr2_modes_per_group(p.Nf, p.level, m.block, nmodes, p.d, tm) != tm) continue;
+            p.cr_tm = tm;
+            int rc = solve_aniso(p, kbits, in, out, 0);
+            if (rc == ASDSM_OK) {
+                ASDSM_HIP_CHECK(hipEventRecord(ev.tb, p.stream));
+                for (int r = 0; r < reps && rc == ASDSM_OK; ++r) rc = solve_aniso(p, kbits, in, out, 0);
+                ASDSM_HIP_CHECK(hipEventRecord(ev.te, p.stream));
+            }
+            if (rc != ASDSM_OK) {
+                p.cr_tm = saved_tm;
+                return rc;
+            }
+            ASDSM_HIP_CHECK(hipEventSynchronize(ev.te));
+            float ms = 0.f;
+            ASDSM_HIP_CHECK(hipEventElapsedTime(&ms, ev.tb, ev.te));
+            const double t = (double)ms / reps;
+            if (t < best_t) {
+                best_t = t;
+                best_tm = tm;
+            }
+        }
+        p.cr_tm = best_tm;
+    }
     plan_changed(p);  // captured launches carry the old tile choice
     if (best_tile) *best_tile = best;
     if (best_ms) *best_ms = best_t;
@@ -1621,7 +1679,10 @@ struct Batch {
     hipGraphExec_t exec = nullptr;
     std::vector<double *> graph_u;
     std::vector<bool> graph_prec32;
+    std::vector<bool> graph_sparse;
     std::vector<uint64_t> graph_gen;         // each member's plan generation at capture
+    std::vector<int> graph_members;          // members whose steps the graph holds
+    hipEvent_t slot_ev[2] = {nullptr, nullptr};  // the pipelined state checks
 };
 
 void destroy_batch_graph(Batch &b) {
@@ -1631,7 +1692,9 @@ void destroy_batch_graph(Batch &b) {
     b.graph = nullptr;
     b.graph_u.clear();
     b.graph_prec32.clear();
+    b.graph_sparse.clear();
     b.graph_gen.clear();
+    b.graph_members.clear();
 }
 
 void release_batch(Batch &b) {
@@ -1641,6 +1704,10 @@ void release_batch(Batch &b) {
     for (hipEvent_t e : b.joined) if (e) (void)hipEventDestroy(e);
     if (b.fork) (void)hipEventDestroy(b.fork);
     if (b.done) (void)hipEventDestroy(b.done);
+    for (int i = 0; i < 2; ++i) {
+        if (b.slot_ev[i]) (void)hipEventDestroy(b.slot_ev[i]);
+        b.slot_ev[i] = nullptr;
+    }
     if (b.cap) (void)hipStreamDestroy(b.cap);
     if (b.root) (void)hipStreamDestroy(b.root);
     b.branch.clear();
@@ -1655,6 +1722,7 @@ int build_batch(Batch &b, int n) {
     ASDSM_HIP_CHECK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
     ASDSM_HIP_CHECK(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
     ASDSM_HIP_CHECK(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i) ASDSM_HIP_CHECK(hipEventCreateWithFlags(&b.slot_ev[i], hipEventDisableTiming));
     b.branch.assign(n, nullptr);
     b.ready.assign(n, nullptr);
     b.joined.assign(n, nullptr);
@@ -1667,14 +1735,18 @@ int build_batch(Batch &b, int n) {
 }
 
 // Capture two refinement steps of every member (u -> u2 -> u) as parallel branches.
-int capture_batch_graph(Batch &b, double *const *u) {
+// Capture two gated refinement steps of each member in `members` as parallel branches of one graph
+// (fork/join events; each branch runs on its own capture stream).  Members that have stopped are
+// left out: their steps would be gated no-ops that still cost a launch each.
+int capture_batch_graph(Batch &b, double *const *u, const std::vector<int> &members) {
     destroy_batch_graph(b);
     const int n = (int)b.plans.size();
     ASDSM_HIP_CHECK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
     int rc = ASDSM_OK;
     hipError_t e = hipEventRecord(b.fork, b.cap);
     if (e != hipSuccess) rc = fail(ASDSM_E_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
-    for (int i = 0; i < n && rc == ASDSM_OK; ++i) {
+    for (int i : members) {
+        if (rc != ASDSM_OK) break;
         Plan &p = *b.plans[i];
         e = hipStreamWaitEvent(b.branch[i], b.fork, 0);
         if (e != hipSuccess) {
@@ -1683,8 +1755,9 @@ int capture_batch_graph(Batch &b, double *const *u) {
         }
         hipStream_t saved = p.stream;
         p.stream = b.branch[i];
-        rc = refine_step(p, u[i], p.ws.u2);
-        if (rc == ASDSM_OK) rc = refine_step(p, p.ws.u2, u[i]);
+        // plain steps (a correction network bound to a member plays no part in batches)
+        rc = p.sparse ? sparse_step(p) : refine_step(p, u[i], p.ws.u2);
+        if (rc == ASDSM_OK) rc = p.sparse ? sparse_step(p) : refine_step(p, p.ws.u2, u[i]);
         p.stream = saved;
         if (rc != ASDSM_OK) break;
         e = hipEventRecord(b.joined[i], b.branch[i]);
@@ -1707,8 +1780,10 @@ int capture_batch_graph(Batch &b, double *const *u) {
     b.graph_u.assign(u, u + n);
     for (int i = 0; i < n; ++i) {
         b.graph_prec32.push_back(b.plans[i]->prec32);
+        b.graph_sparse.push_back(b.plans[i]->sparse);
         b.graph_gen.push_back(b.plans[i]->generation);
     }
+    b.graph_members = members;
     return ASDSM_OK;
 }
 
@@ -1716,15 +1791,15 @@ int batch_solve_impl(Batch &b, const double *const *s, const double *const *g, d
                      const asdsm_opts *o, asdsm_stats *st) {
     asdsm_opts opt;
     if (int rc = normalize_opts(o, opt)) return rc;
-    if (opt.skeleton)
-        return fail(ASDSM_E_UNSUPPORTED, "batches run the fine-mesh refinement (no skeleton-sparse mode)");
     const int n = (int)b.plans.size();
     if (!s || !g || !u) return fail(ASDSM_E_ARG, "s, g and u must be non-NULL arrays of n pointers");
     if (opt.profile || opt.eager) {
         // one member after the other, each on its own loop
         int worst = ASDSM_OK;
         for (int i = 0; i < n; ++i) {
-            const int rc = solve_impl(*b.plans[i], s[i], g[i], u[i], &opt, st ? st + i : nullptr);
+            asdsm_opts oi = opt;
+            oi.skeleton = (opt.skeleton && b.plans[i]->d == 3) ? 1 : 0;
+            const int rc = solve_impl(*b.plans[i], s[i], g[i], u[i], &oi, st ? st + i : nullptr);
             if (rc < 0) return rc;
             worst = std::max(worst, rc);
         }
@@ -1733,46 +1808,95 @@ int batch_solve_impl(Batch &b, const double *const *s, const double *const *g, d
     for (int i = 0; i < n; ++i) {
         Plan &p = *b.plans[i];
         p.profiling = false;
-        if (int rc = begin_solve(p, s[i], g[i], u[i], opt)) return rc;
+        // skeleton-sparse refinement where it is built (d = 3), the fine-mesh loop elsewhere
+        asdsm_opts oi = opt;
+        oi.skeleton = (opt.skeleton && p.d == 3) ? 1 : 0;
+        if (int rc = begin_solve(p, s[i], g[i], u[i], oi)) return rc;
         ASDSM_HIP_CHECK(hipEventRecord(b.ready[i], p.stream));
         ASDSM_HIP_CHECK(hipStreamWaitEvent(b.root, b.ready[i], 0));
     }
-    bool rebuild = !b.exec || (int)b.graph_u.size() != n;
-    for (int i = 0; i < n && !rebuild; ++i)
-        rebuild = b.graph_u[i] != u[i] || b.graph_prec32[i] != b.plans[i]->prec32 ||
-                  b.graph_gen[i] != b.plans[i]->generation;
-    int rc = rebuild ? capture_batch_graph(b, u) : ASDSM_OK;
-    int steps = 0;
-    while (rc == ASDSM_OK) {
+    std::vector<int> active;
+    for (int i = 0; i < n; ++i) active.push_back(i);
+    auto stale = [&]() {
+        if (!b.exec || (int)b.graph_u.size() != n || b.graph_members != active) return true;
+        for (int i = 0; i < n; ++i)
+            if (b.graph_u[i] != u[i] || b.graph_prec32[i] != b.plans[i]->prec32 ||
+                b.graph_sparse[i] != b.plans[i]->sparse || b.graph_gen[i] != b.plans[i]->generation)
+                return true;
+        return false;
+    };
+    int rc = stale() ? capture_batch_graph(b, u, active) : ASDSM_OK;
+    // two replays per batch of work; the host reads every active member's loop state behind batch i
+    // (one of two pinned slots per member) while batch i + 1 runs; when members have stopped, the
+    // graph is captured again without them
+    int steps = 0, inflight = 0;
+    auto launch_batch = [&](int slot) -> int {
         for (int rep = 0; rep < 2 && steps < opt.max_iter; ++rep, steps += 2) {
             hipError_t e = hipGraphLaunch(b.exec, b.root);
-            if (e != hipSuccess) {
-                rc = fail(ASDSM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-                break;
-            }
+            if (e != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         }
-        if (rc != ASDSM_OK) break;
-        for (int i = 0; i < n; ++i) {
+        for (int i : b.graph_members) {
             Plan &p = *b.plans[i];
-            hipError_t e = hipMemcpyAsync(p.hstate, p.ws.state, sizeof(IterState), hipMemcpyDeviceToHost, b.root);
-            if (e != hipSuccess) {
-                rc = fail(ASDSM_E_DEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
-                break;
-            }
+            ASDSM_HIP_CHECK(hipMemcpyAsync(p.hstate_ring[slot], p.ws.state, sizeof(IterState),
+                                           hipMemcpyDeviceToHost, b.root));
         }
-        if (rc != ASDSM_OK) break;
-        hipError_t e = hipStreamSynchronize(b.root);
+        ASDSM_HIP_CHECK(hipEventRecord(b.slot_ev[slot], b.root));
+        ++inflight;
+        return ASDSM_OK;
+    };
+    std::vector<int> slot_members[2];
+    if (rc == ASDSM_OK) {
+        slot_members[0] = b.graph_members;
+        rc = launch_batch(0);
+    }
+    if (rc == ASDSM_OK && steps < opt.max_iter) {
+        slot_members[1] = b.graph_members;
+        rc = launch_batch(1);
+    }
+    for (int slot = 0; rc == ASDSM_OK && inflight > 0; slot ^= 1) {
+        hipError_t e = hipEventSynchronize(b.slot_ev[slot]);
         if (e != hipSuccess) {
-            rc = fail(ASDSM_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+            rc = fail(ASDSM_E_DEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
             break;
         }
-        bool all = true;
-        for (int i = 0; i < n; ++i) all = all && b.plans[i]->hstate->done;
-        if (all || steps >= opt.max_iter) break;
+        --inflight;
+        std::vector<int> still;
+        for (int i : slot_members[slot])
+            if (!b.plans[i]->hstate_ring[slot]->done) still.push_back(i);
+        if (still.empty()) break;
+        if (steps >= opt.max_iter) continue;
+        if (still.size() < active.size()) {
+            // members stopped: wait for the batch in flight, then leave them out of the graph
+            e = hipStreamSynchronize(b.root);
+            if (e != hipSuccess) {
+                rc = fail(ASDSM_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+                break;
+            }
+            inflight = 0;
+            std::vector<int> alive;
+            for (int i : still) {
+                Plan &p = *b.plans[i];
+                if ((rc = read_state_on(p, b.root))) break;
+                if (!p.hstate->done) alive.push_back(i);
+            }
+            if (rc != ASDSM_OK || alive.empty()) break;
+            active = alive;
+            rc = capture_batch_graph(b, u, active);
+            if (rc != ASDSM_OK) break;
+        }
+        slot_members[slot] = b.graph_members;
+        rc = launch_batch(slot);
     }
-    // the members' streams continue after the graph's work
+    if (rc == ASDSM_OK) {
+        hipError_t e = hipStreamSynchronize(b.root);
+        if (e != hipSuccess) rc = fail(ASDSM_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    }
+    // the members' streams continue after the graph's work (the skeleton-sparse members then
+    // rebuild their fine iterate on their own streams)
     ASDSM_HIP_CHECK(hipEventRecord(b.done, b.root));
     for (int i = 0; i < n; ++i) ASDSM_HIP_CHECK(hipStreamWaitEvent(b.plans[i]->stream, b.done, 0));
+    for (int i = 0; i < n && rc == ASDSM_OK; ++i)
+        if (b.plans[i]->sparse) rc = finish_sparse(*b.plans[i], u[i]);
     if (rc != ASDSM_OK) {
         for (int i = 0; i < n; ++i) b.plans[i]->gate = nullptr;
         return rc;

@@ -144,6 +144,7 @@ struct Plan {
     // reduction (together with the coarse block) instead of being transformed, or -1
     int line_pos[kMaxMeshes] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
     bool line_aniso = false;           // the anisotropic meshes use line axes
+    int cr_tm = 0;                     // modes per workgroup of their line solve (0: by size)
     std::vector<double> cr_tab[kMaxMeshes];  // host copies while the plan is built
     double *dcr[kMaxMeshes] = {};      // per mode and level: G, P, Q (device)
     int sweeps[kMaxMeshes] = {};       // refinement sweeps of each mesh solve (calibrated)

@@ -232,12 +232,19 @@ __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
     constexpr int MM = NB * NB;
     double *D = lds;                                         // [tmw][N][NB]
     double *Mt = lds + (size_t)tmw * N * NB;                 // [tmw][L][3][MM]
-    const size_t mats = (size_t)tm * L * 3 * MM;
+    __shared__ long long mbase[8];                           // offset of each mode's line
+    if (tid < tm) {
+        const long long mode = mode0 + tid;
+        mbase[tid] = (mode % bx.mext0) * bx.ms0 + (mode / bx.mext0) * bx.ms1;
+    }
+    const int mats = tm * L * 3 * MM;
     const double *tsrc = bx.tab + (size_t)mode0 * L * 3 * MM;
-    for (size_t e = tid; e < mats; e += 256) Mt[e] = tsrc[e];
+    for (int e = tid; e < mats; e += 256) Mt[e] = tsrc[e];
+    __syncthreads();
     const bool modes_fast = bx.ms0 == 1;
-    for (int t = tid; t < tm * N * NB; t += 256) {
-        int ml, i, c;
+    const long long sw = bx.sw, sc = bx.sc;
+    // element t of the coalesced order: modes fastest when they are contiguous, else the line
+    auto elem = [&](int t, int &ml, int &i, int &c) {
         if (modes_fast) {
             ml = t % tm;
             const int rest = t / tm;
@@ -249,9 +256,11 @@ __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
             ml = rest % tm;
             c = rest / tm;
         }
-        const long long mode = mode0 + ml;
-        const long long m0 = mode % bx.mext0, m1 = mode / bx.mext0;
-        D[((size_t)ml * N + i) * NB + c] = bx.src[m0 * bx.ms0 + m1 * bx.ms1 + (long long)i * bx.sw + (long long)c * bx.sc];
+    };
+    for (int t = tid; t < tm * N * NB; t += 256) {
+        int ml, i, c;
+        elem(t, ml, i, c);
+        D[(ml * N + i) * NB + c] = bx.src[mbase[ml] + i * sw + c * sc];
     }
     __syncthreads();
     const int E = 256 / (tmw * RB);
@@ -329,24 +338,13 @@ __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
         __syncthreads();
     }
     // ---- the solved line to dst (added when accumulating), in the load's coalesced order
+    const int acc = job.accum;
     for (int t = tid; t < tm * N * NB; t += 256) {
         int mlw, i, c;
-        if (modes_fast) {
-            mlw = t % tm;
-            const int rest = t / tm;
-            i = rest % N;
-            c = rest / N;
-        } else {
-            i = t % N;
-            const int rest = t / N;
-            mlw = rest % tm;
-            c = rest / tm;
-        }
-        const long long mode = mode0 + mlw;
-        const long long m0 = mode % bx.mext0, m1 = mode / bx.mext0;
-        const long long a = m0 * bx.ms0 + m1 * bx.ms1 + (long long)i * bx.sw + (long long)c * bx.sc;
-        const double v = D[((size_t)mlw * N + i) * NB + c];
-        bx.dst[a] = job.accum ? bx.dst[a] + v : v;
+        elem(t, mlw, i, c);
+        const long long a = mbase[mlw] + i * sw + c * sc;
+        const double v = D[(mlw * N + i) * NB + c];
+        bx.dst[a] = acc ? bx.dst[a] + v : v;
     }
 }
 
@@ -453,14 +451,17 @@ static int cr_rb(int NB) {
 // modes per workgroup of the fast form, or 0 when it does not apply: 256 threads hold tm * RB rows
 // with at least one equation group, the back substitution's per-thread results fit the register
 // array, and the LDS holds the lines and matrices
-int cr2_modes_per_group(int N, int L, int NB, long long nmodes, int nbox) {
+int cr2_modes_per_group(int N, int L, int NB, long long nmodes, int nbox, int want) {
     if (!(NB == 1 || NB == 3 || NB == 7 || NB == 9 || NB == 15)) return 0;
     const int rb = cr_rb(NB);
-    for (int tm = 8; tm >= 1; tm /= 2) {
-        if (tm * rb > 256) continue;
+    auto valid = [&](int tm) {
+        if (tm < 1 || tm > 8 || (tm & (tm - 1)) || tm * rb > 256) return false;
         const int E = 256 / (tm * rb);
-        if ((1 << (L - 1)) > E * kCrMaxPerThread) continue;
-        if (cr2_lds_bytes(N, L, NB, tm) > kCrMaxLds) continue;
+        return (1 << (L - 1)) <= E * kCrMaxPerThread && cr2_lds_bytes(N, L, NB, tm) <= kCrMaxLds;
+    };
+    if (want > 0) return valid(want) ? want : 0;
+    for (int tm = 8; tm >= 1; tm /= 2) {
+        if (!valid(tm)) continue;
         // fewer modes per group while that still leaves under one group per CU
         if (tm > 1 && (nmodes * nbox + tm - 1) / tm < 256 && cr2_lds_bytes(N, L, NB, tm / 2) <= kCrMaxLds) continue;
         return tm;

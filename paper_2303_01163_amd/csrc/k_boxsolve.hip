@@ -109,6 +109,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
         __syncthreads();
     }
     double *__restrict__ C = job.C[box] + (long long)bat * job.sCb;
+    double ss = 0.0;  // sum of squares of the values this thread writes (norm_out only)
 #pragma unroll
     for (int a = 0; a < MI; ++a)
 #pragma unroll
@@ -119,9 +120,16 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
                 const int gn = n0 + wn * (TN / 2) + b * 16 + (lane & 15);
                 if (gi < job.M && gn < job.N) {
                     double *cp = C + (long long)gi * job.sCi + (long long)gn * job.sCn;
-                    *cp = job.accum ? *cp + acc[a][b][v] : acc[a][b][v];
+                    const double val = job.accum ? *cp + acc[a][b][v] : acc[a][b][v];
+                    *cp = val;
+                    ss += val * val;
                 }
             }
+    if (job.norm_out[box]) {  // block-uniform
+        __shared__ double sh[4];
+        const double tot = block_sum<256>(ss, sh);
+        if (t == 0) job.norm_out[box][bat * per_z + rem] = tot;
+    }
 }
 
 template <int TM, int TN, int KC>
@@ -146,15 +154,31 @@ const char *gemm_tile_name(int tile) {
     }
 }
 
-bool launch_gemm(const GemmJob &job, hipStream_t st) {
-    // operand layouts of the mode transforms: A k-fast, B k-fast or n-fast
-    if (job.sAk != 1 || (job.sBk != 1 && job.sBn != 1)) return false;
+static int gemm_pick_tile(const GemmJob &job) {
     int tile = job.tile;
     if (tile == kTileAuto) {
         // 64 x 64 tiles once there are enough of them to fill the chip twice, else 32 x 32
         const long long t64 = ((job.N + 63) / 64) * ((job.M + 63) / 64) * job.nbox * job.nbatch;
         tile = (t64 >= 512) ? kTile64x64 : kTile32x32;
     }
+    return tile;
+}
+
+int gemm_tiles_per_box(const GemmJob &job) {
+    int tm = 32, tn = 32;
+    switch (gemm_pick_tile(job)) {
+        case kTile64x32: tm = 64; break;
+        case kTile32x64: tn = 64; break;
+        case kTile64x64: tm = tn = 64; break;
+        default: break;
+    }
+    return ((job.N + tn - 1) / tn) * ((job.M + tm - 1) / tm) * job.nbatch;
+}
+
+bool launch_gemm(const GemmJob &job, hipStream_t st) {
+    // operand layouts of the mode transforms: A k-fast, B k-fast or n-fast
+    if (job.sAk != 1 || (job.sBk != 1 && job.sBn != 1)) return false;
+    const int tile = gemm_pick_tile(job);
     switch (tile) {
         case kTile64x32: launch_gemm_tile<64, 32, 32>(job, st); break;
         case kTile32x64: launch_gemm_tile<32, 64, 32>(job, st); break;

@@ -57,7 +57,9 @@ struct CrJob {
 };
 constexpr size_t kCrMaxLds = 64 * 1024;
 size_t cr_lds_bytes(int N, int NB, int tm);
-int cr2_modes_per_group(int N, int L, int NB, long long nmodes, int nbox);
+// modes per workgroup of the fast form (want > 0: that count if it is valid), or 0 when the fast
+// form does not apply
+int cr2_modes_per_group(int N, int L, int NB, long long nmodes, int nbox, int want = 0);
 bool cr_lds_supported(int NB);  // block sizes with an LDS-staged kernel
 bool launch_block_cr(const CrJob &job, hipStream_t st);
 
@@ -77,7 +79,11 @@ struct GemmJob {
     const int *gate;           // return at once when *gate != 0 (may be nullptr)
     long long sAb, sAi, sAk, sBb, sBk, sBn, sCb, sCi, sCn;
     int tile;                  // FP64 tile shape: kTileAuto or one of kGemmTiles (autotuner)
+    // non-null for box b: each output tile's block stores the sum of squares of the C values it
+    // wrote at norm_out[b][batch * tiles_per_batch + tile index] (the error-guess norms)
+    double *norm_out[kMaxD];
 };
+int gemm_tiles_per_box(const GemmJob &job);  // output tiles of one box (all batches) as launched
 
 // FP64 transform tile shapes (TM x TN, K chunk), chosen per plan by asdsm_autotune.
 // kTilePlane: both fine-axis transforms of a d = 3 anisotropic box in one launch (k_plane2).

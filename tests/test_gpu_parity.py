@@ -465,6 +465,29 @@ def test_batch_matches_individual_solves(torch_dev, precision):
             assert info["rnorm"] == i_ref["rnorm"]
 
 
+def test_batch_skeleton_sparse_matches_individual_solves(torch_dev):
+    """With skeleton-sparse refinement requested, the d = 3 members of a batch run it and the others
+    the fine-mesh loop; every member ends bitwise where its own asdsm_solve with the same request
+    ends, although members stop at different steps and the graph is captured again without them."""
+    from paper_2303_01163_amd.asdsm import Batch, Plan
+    plans, ss, gs = [], [], []
+    for fam, L, Lc, d, seed, al, be in BATCH_MEMBERS:
+        P = make_problem(fam, L, seed=seed, d=d, alpha=al, beta=be)
+        plans.append(Plan(P.d, P.alpha, P.beta, L, Lc, seed=seed + 3))
+        ss.append(_t(torch_dev, P.s_flat()))
+        gs.append(_t(torch_dev, P.g_flat()))
+    ref = [pl.solve(s, g, max_iter=40, skeleton=(pl.d == 3)) for pl, s, g in zip(plans, ss, gs)]
+    assert len({info["iterations"] for _, info in ref}) > 1
+    assert any(pl.d == 3 for pl in plans) and any(pl.d != 3 for pl in plans)
+    batch = Batch(plans)
+    for rep in range(2):
+        us, infos = batch.solve(ss, gs, max_iter=40, skeleton=True)
+        for (u_ref, i_ref), u, info in zip(ref, us, infos):
+            assert info["iterations"] == i_ref["iterations"] and info["status"] == i_ref["status"]
+            assert np.array_equal(u.cpu().numpy(), u_ref.cpu().numpy())
+            assert info["rnorm"] == i_ref["rnorm"]
+
+
 def test_probes_measure_plausible_ceilings(torch_dev):
     """The measured ceilings the bench reports next to the datasheet peaks (78.6 TFLOP/s FP64
     matrix, 8 TB/s HBM): positive and below them, and argument errors rejected."""
