@@ -195,6 +195,52 @@ int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *
     return check_launch("transform");
 }
 
+// Mode transform along canonical position 0 of nb d = 3 boxes whose lines (the line axis at
+// position 1, with the coarse axis) the block cyclic reduction reads whole: the forward transform
+// writes mode-major, each mode's N_f x N_c line contiguous (C = T X^T, coalesced stores along the
+// line), and the backward transform reads that layout back as an m-fast A operand and writes the
+// canonical layout.  norm_slot as in transform_position.
+int transform_pos0_modes_major(Plan &p, const MeshDesc &m, int nb, const double *const *in,
+                               const double *const *T, double *const *out, bool fwd, int accum,
+                               const int *norm_slot) {
+    GemmJob j{};
+    j.nbox = nb;
+    j.gate = p.gate;
+    j.tile = (p.tile_aniso == kTilePlane) ? kTileAuto : p.tile_aniso;
+    j.accum = accum;
+    j.nbatch = 1;
+    j.sAb = j.sBb = j.sCb = 0;
+    const long long Nf = p.Nf, rows = m.size / Nf;
+    if (fwd) {
+        j.M = (int)Nf; j.N = (int)rows; j.K = (int)Nf;
+        j.sAi = Nf; j.sAk = 1;      // A = W (mode, position)
+        j.sBk = 1;  j.sBn = Nf;     // B[k, row] = x(position k of the row)
+        j.sCi = rows; j.sCn = 1;    // C[mode, row], mode-major
+        for (int b = 0; b < nb; ++b) {
+            j.A[b] = T[b];
+            j.B[b] = in[b];
+            j.C[b] = out[b];
+        }
+    } else {
+        j.M = (int)rows; j.N = (int)Nf; j.K = (int)Nf;
+        j.sAi = 1; j.sAk = rows;    // A[row, mode], mode-major data
+        j.sBk = 1; j.sBn = Nf;      // B[mode, position] = V(position, mode)
+        j.sCi = Nf; j.sCn = 1;      // canonical layout
+        for (int b = 0; b < nb; ++b) {
+            j.A[b] = in[b];
+            j.B[b] = T[b];
+            j.C[b] = out[b];
+        }
+    }
+    if (norm_slot && p.norm_partials) {
+        p.norm_nblk = gemm_tiles_per_box(j);
+        for (int b = 0; b < nb; ++b) j.norm_out[b] = p.norm_partials + (size_t)norm_slot[b] * p.norm_nblk;
+    }
+    PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
+    if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
+    return check_launch("transform");
+}
+
 // Direct solve of nb meshes of one shape that have a line axis (Plan::line_pos, any d): the other
 // fine axes are diagonalised by mode transforms, then block cyclic reduction runs along the line
 // axis with the mesh's coarse block as blocks (k_blockcr.hip), then the backward transforms.
@@ -226,6 +272,9 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
     for (int b = 1; b < nb && nt == 1; ++b) one_group = one_group && fq[b][0] == fq[0][0];
     const bool fuse_norms = p.norm_partials && nt == 1 && one_group && nb == p.d &&
                             __builtin_popcount(masks[0]) == 1;
+    // d = 3 with the transformed axis at position 0: the line solve reads and writes mode-major
+    // whole lines (transform_pos0_modes_major)
+    const bool modes_major = nt == 1 && m.nd == 3 && one_group && fq[0][0] == 0;
     auto run_grouped = [&](int t, const double *const *src, double *const *dst, bool fwd, int acc) -> int {
         bool done[kMaxD] = {};
         for (int b = 0; b < nb; ++b) {
@@ -246,7 +295,12 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
                     ++ng;
                 }
             const bool norms = !fwd && t == 0 && fuse_norms;
-            if (int rc = transform_position(p, m, q, ng, gs, gT, gd, acc, norms ? slot : nullptr)) return rc;
+            if (modes_major) {
+                if (int rc = transform_pos0_modes_major(p, m, ng, gs, gT, gd, fwd, acc, norms ? slot : nullptr))
+                    return rc;
+            } else if (int rc = transform_position(p, m, q, ng, gs, gT, gd, acc, norms ? slot : nullptr)) {
+                return rc;
+            }
         }
         return ASDSM_OK;
     };
@@ -284,6 +338,11 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
             bx.ms1 = nt >= 2 ? mb.stride[fq[b][1]] : 0;
             bx.sw = mb.stride[p.line_pos[mk]];
             bx.sc = mb.stride[mb.nfine];
+            if (modes_major) {  // element (mode, i, c) at mode (N_f N_c) + i + N_f c
+                bx.ms0 = mb.size / mb.ext[0];
+                bx.sw = 1;
+                bx.sc = mb.ext[0];
+            }
             nm = std::max(nm, bx.nmodes);
         }
         // modes per workgroup: 8 when the first mode axis is contiguous (coalesced loads), else 2;

@@ -282,10 +282,14 @@ __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
             for (int q = eg; q < nkeep; q += E) {
                 const int i0 = (q + 1) * 2 * step - 1;   // 0-based
                 const double *a = Dm + (size_t)(i0 - step) * NB, *b = Dm + (size_t)(i0 + step) * NB;
-                double acc = Dm[(size_t)i0 * NB + r];
+                // two independent chains (the P and the Q products) shorten the dependent FMAs
+                double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-                for (int c = 0; c < NB; ++c) acc -= pr[c] * a[c] + qr[c] * b[c];
-                Dm[(size_t)i0 * NB + r] = acc;
+                for (int c = 0; c < NB; ++c) {
+                    s1 += pr[c] * a[c];
+                    s2 += qr[c] * b[c];
+                }
+                Dm[(size_t)i0 * NB + r] = Dm[(size_t)i0 * NB + r] - (s1 + s2);
             }
         }
         __syncthreads();
@@ -309,20 +313,21 @@ __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
                 if (q >= nel) break;
                 const int i = (2 * q + 1) * step;        // 1-based
                 const double *f = Dm + (size_t)(i - 1) * NB;
-                double acc = 0.0;
+                // three independent chains (G, P and Q products)
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
-                for (int c = 0; c < NB; ++c) acc += gr[c] * f[c];
+                for (int c = 0; c < NB; ++c) s0 += gr[c] * f[c];
                 if (i - step >= 1) {
                     const double *a = Dm + (size_t)(i - 1 - step) * NB;
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) acc -= pr[c] * a[c];
+                    for (int c = 0; c < NB; ++c) s1 += pr[c] * a[c];
                 }
                 if (i + step <= N) {
                     const double *b = Dm + (size_t)(i - 1 + step) * NB;
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) acc -= qr[c] * b[c];
+                    for (int c = 0; c < NB; ++c) s2 += qr[c] * b[c];
                 }
-                res[k] = acc;
+                res[k] = s0 - (s1 + s2);
             }
         }
         __syncthreads();

@@ -26,7 +26,7 @@ namespace asdsm {
 // Operand layout of v_mfma_f64_16x16x4f64 (lane l, 0..63):
 //   A: row l%16, k l/16;  B: k l/16, col l%16;  D[v]: row l/16 + 4v, col l%16.
 // ---------------------------------------------------------------------------------------------
-template <int TM, int TN, int KC, bool BKF>
+template <int TM, int TN, int KC, bool BKF, bool AKF>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     if (job.gate && *job.gate) return;
     constexpr int MI = TM / 32, NI = TN / 32;            // MFMA tiles per wave along m and n
@@ -48,10 +48,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     const int m0 = by * TM, n0 = bx * TN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w & 1, wn = w >> 1;
-    const int sAi = (int)job.sAi, sBk = (int)job.sBk, sBn = (int)job.sBn;
-    // panel element j of this thread: A row t/KC + (256/KC) j, k t%KC; B (k-fast) col
-    // t/KC + (256/KC) j, k t%KC; B (n-fast) k t/TN + (256/TN) j, col t%TN
-    const int ar = t / KC, ak = t % KC;
+    const int sAi = (int)job.sAi, sAk = (int)job.sAk, sBk = (int)job.sBk, sBn = (int)job.sBn;
+    // panel element j of this thread: A (k-fast) row t/KC + (256/KC) j, k t%KC; A (m-fast) row
+    // t%TM, k t/TM + (256/TM) j; B (k-fast) col t/KC + (256/KC) j, k t%KC; B (n-fast) k
+    // t/TN + (256/TN) j, col t%TN
+    const int ar = AKF ? t / KC : t % TM, ak = AKF ? t % KC : t / TM;
     const int bn0 = BKF ? (t / KC) : (t % TN), bk0 = BKF ? (t % KC) : (t / TN);
     double ra[LA], rb[LB];
     const int nch = (job.K + KC - 1) / KC;
@@ -59,8 +60,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
         const int k0 = c * KC;
 #pragma unroll
         for (int j = 0; j < LA; ++j) {
-            const int row = m0 + ar + (256 / KC) * j, k = k0 + ak;
-            ra[j] = (row < job.M && k < job.K) ? A[row * sAi + k] : 0.0;
+            const int row = m0 + ar + (AKF ? (256 / KC) * j : 0);
+            const int k = k0 + ak + (AKF ? 0 : (256 / TM) * j);
+            ra[j] = (row < job.M && k < job.K) ? (AKF ? A[row * sAi + k] : A[row + k * sAk]) : 0.0;
         }
 #pragma unroll
         for (int j = 0; j < LB; ++j) {
@@ -71,7 +73,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int j = 0; j < LA; ++j) sA[buf][ar + (256 / KC) * j][ak] = ra[j];
+        for (int j = 0; j < LA; ++j) {
+            if (AKF)
+                sA[buf][ar + (256 / KC) * j][ak] = ra[j];
+            else
+                sA[buf][ar][ak + (256 / TM) * j] = ra[j];
+        }
 #pragma unroll
         for (int j = 0; j < LB; ++j) {
             if (BKF)
@@ -137,10 +144,14 @@ static void launch_gemm_tile(const GemmJob &job, hipStream_t st) {
     const long long tx = (job.N + TN - 1) / TN, ty = (job.M + TM - 1) / TM;
     const long long total = tx * ty * job.nbox * job.nbatch;
     const dim3 grid((unsigned)(8 * ((total + 7) / 8)));
-    if (job.sBk == 1)
-        ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, true>), grid, dim3(256), 0, st, job);
-    else
-        ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, false>), grid, dim3(256), 0, st, job);
+    const bool akf = job.sAk == 1;
+    if (job.sBk == 1) {
+        if (akf) ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, true, true>), grid, dim3(256), 0, st, job);
+        else ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, true, false>), grid, dim3(256), 0, st, job);
+    } else {
+        if (akf) ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, false, true>), grid, dim3(256), 0, st, job);
+        else ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, false, false>), grid, dim3(256), 0, st, job);
+    }
 }
 
 const char *gemm_tile_name(int tile) {
@@ -176,8 +187,8 @@ int gemm_tiles_per_box(const GemmJob &job) {
 }
 
 bool launch_gemm(const GemmJob &job, hipStream_t st) {
-    // operand layouts of the mode transforms: A k-fast, B k-fast or n-fast
-    if (job.sAk != 1 || (job.sBk != 1 && job.sBn != 1)) return false;
+    // operand layouts of the mode transforms: A k-fast or m-fast, B k-fast or n-fast
+    if ((job.sAk != 1 && job.sAi != 1) || (job.sBk != 1 && job.sBn != 1)) return false;
     const int tile = gemm_pick_tile(job);
     switch (tile) {
         case kTile64x32: launch_gemm_tile<64, 32, 32>(job, st); break;
@@ -361,6 +372,7 @@ bool launch_plane2(const PlaneJob &job, hipStream_t st) {
 template <int TM, int TN, int KC, bool BKF, typename TA, typename TC>
 __global__ __launch_bounds__(256) void k_gemm_f32(GemmJob job) {
     if (job.gate && *job.gate) return;
+    constexpr bool AKF = true;  // the FP32 transforms take k-fast A operands only
     constexpr int MI = TM / 32, NI = TN / 32;
     constexpr int LA = TM * KC / 256, LB = KC * TN / 256;
     __shared__ float sA[2][TM][KC + 1];
@@ -401,7 +413,12 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmJob job) {
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int j = 0; j < LA; ++j) sA[buf][ar + (256 / KC) * j][ak] = ra[j];
+        for (int j = 0; j < LA; ++j) {
+            if (AKF)
+                sA[buf][ar + (256 / KC) * j][ak] = ra[j];
+            else
+                sA[buf][ar][ak + (256 / TM) * j] = ra[j];
+        }
 #pragma unroll
         for (int j = 0; j < LB; ++j) {
             if (BKF)
