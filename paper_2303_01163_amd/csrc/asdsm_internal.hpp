@@ -166,10 +166,6 @@ struct Plan {
     double *norm_partials = nullptr;
     int norm_nblk = 0;
     bool fp32_ok = false;            // every anisotropic mesh: 6e-8 * prod cond(V_j) <= 1e-3
-    // hole line elimination factors (d = 3): for the mode pair q = m0 + nh m1 of the two transformed
-    // hole axes, step c: hole_inv[c nh^2 + q] = 1/pivot_c, hole_cp[...] = super / pivot_c
-    std::vector<double> hole_inv, hole_cp;
-    double *dhole_inv = nullptr, *dhole_cp = nullptr;
     double *dSp = nullptr;
     double *ddense[kMaxMeshes] = {};
 

@@ -437,7 +437,6 @@ struct FillArgs {
     const double *W[kMaxD];
     const double *V[kMaxD];
     const double *mu[kMaxD];
-    const double *hinv, *hcp;   // hole line factors (d = 3), see Plan::hole_inv
     int line_axis;
     int ntr;
     int tr[kMaxD];
@@ -877,65 +876,101 @@ __global__ __launch_bounds__(256) void k_filler_lines(Geo g, FillArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Filler for d = 3 with 15^3 holes (n = 16) on MFMA.  The hole is padded to 16^3 in one LDS buffer
-// with strides (1, 17, 289): for every axis the 16 rows of an MFMA operand fragment and the 16
-// columns of a result fragment fall in distinct banks.  A transform along axis j is an in-place GEMM
-// of the 256 lines (the other two coordinates) by the 16 x 16 matrix W_j^T (pad row/column zero),
-// 64 v_mfma_f64_16x16x4f64 per transform, 16 per wave; the W_j fragments live in registers.
+// Filler for d = 3 with 15^3 holes (n = 16) on MFMA: line axis L (eliminated by Thomas), the two
+// other axes j0 < j1 diagonalised.  The hole is padded to 16^3 in one LDS buffer with strides
+// (1, 17, 289): for every axis the 16 rows of an MFMA operand fragment and the 16 columns of a
+// result fragment fall in distinct banks.  Wave w owns the slabs l_L = w, w + 4, w + 8 and w + 12
+// (slab 15 is padding that no step reads).  A transform along a diagonalised axis j is, per slab,
+// the GEMM of its 16 lines along j (rows: the third coordinate) by the 16 x 16 matrix W_j^T (pad
+// row and column zero), 4 v_mfma_f64_16x16x4f64; it never leaves the slab, so the two transforms
+// of each side run without a workgroup barrier.
+//
+// Global traffic per hole is the face values, the four 15 x 15 transform matrices (read once per
+// block into LDS) and two eigenvalues per line; the line factors are formed in registers while
+// the face values are in flight, and the first barrier orders LDS only.
 // ---------------------------------------------------------------------------------------------
 constexpr int kFS1 = 17, kFS2 = 289, kFBuf = 16 * kFS2;
+constexpr int kFMat = 16 * 17;  // one transform matrix in LDS: T[m][k] at m * 17 + k, zero beyond 15
 
-__device__ __forceinline__ int fstride(int j) { return j == 0 ? 1 : (j == 1 ? kFS1 : kFS2); }
+__host__ __device__ constexpr int fstride(int j) { return j == 0 ? 1 : (j == 1 ? kFS1 : kFS2); }
 
-// one transform of the padded hole along axis j with the 16 x 16 matrix held as B fragments
-__device__ __forceinline__ void hole_transform_mfma(double *buf, int j, const double (&bfrag)[4],
-                                                    int lane, int wave) {
-    // the other two axes, increasing: row r = lp + 16 * lq
-    const int p = (j == 0) ? 1 : 0;
-    const int q = (j == 2) ? 1 : 2;
-    const int Sp = fstride(p), Sq = fstride(q), Sj = fstride(j);
-    double4_t acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int rt = wave + 4 * t;
-        acc[t] = double4_t{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const double a = buf[(lane & 15) * Sp + rt * Sq + (4 * ks + (lane >> 4)) * Sj];
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bfrag[ks], acc[t], 0, 0, 0);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int rt = wave + 4 * t;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) buf[((lane >> 4) + 4 * v) * Sp + rt * Sq + (lane & 15) * Sj] = acc[t][v];
-    }
-    __syncthreads();
+// Workgroup barrier that orders LDS accesses only: global loads in flight stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// PREFETCH: the four transform fragments are loaded at the start (fewer exposed latencies, more
-// registers: 3 waves per SIMD); otherwise each is loaded right before its transform, which fits 4
-// waves per SIMD (the better choice once there are several holes per CU).
-template <bool PREFETCH>
-__global__ __launch_bounds__(256, PREFETCH ? 2 : 4) void k_filler_mfma3(Geo g, FillArgs a) {
+// In-slab transform along axis J of the slabs of one wave (L the slab axis, P the third axis):
+// A rows l_P, K and the result columns along J; B[k][m] = T[m][k] from the LDS copy of T.  The
+// four slabs' accumulator chains are interleaved.  The slabs are private to the wave, whose LDS
+// instructions execute in order; the wavefront-scope fences keep the compiler from moving a lane's
+// writes above another lane's reads of the same slab.
+template <int J, int L>
+__device__ __forceinline__ void slab_transform(double *buf, const double *T, int lane, int wave) {
+    constexpr int P = 3 - J - L;
+    constexpr int Sp = fstride(P), Ss = fstride(L), Sj = fstride(J);
+    double b[4], x[4][4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) b[ks] = T[(lane & 15) * 17 + 4 * ks + (lane >> 4)];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int s = wave + 4 * t;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            x[t][ks] = (s < 15) ? buf[(lane & 15) * Sp + s * Ss + (4 * ks + (lane >> 4)) * Sj] : 0.0;
+    }
+    double4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t][ks], b[ks], acc[t], 0, 0, 0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int s = wave + 4 * t;
+        if (s < 15) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) buf[((lane >> 4) + 4 * v) * Sp + s * Ss + (lane & 15) * Sj] = acc[t][v];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Face values in LDS: face f = 2 j + side (side 0 below the hole, on coarse plane t_j - 1; side 1
+// above it, on plane t_j), entry (la, lb) at f * 256 + la + 16 lb, la and lb the hole-local
+// coordinates of the two other axes in increasing order; zero where the face is the domain boundary.
+__device__ __forceinline__ int face_at(int f, int la, int lb) { return f * 256 + la + 16 * lb; }
+
+// The hole's right-hand side at (l0, l1, l2) < 15 from v = b_ff there (or 0): minus, axis by axis,
+// the coupling to the face value below (coefficient a_j) or above (c_j) a point of the first or
+// last layer.
+__device__ __forceinline__ double hole_rhs(const Geo &g, const double *fa, int l0, int l1, int l2,
+                                           double v) {
+    constexpr int last = 14;
+    if (l0 == 0) v -= g.fine[0].a * fa[face_at(0, l1, l2)];
+    else if (l0 == last) v -= g.fine[0].c * fa[face_at(1, l1, l2)];
+    if (l1 == 0) v -= g.fine[1].a * fa[face_at(2, l0, l2)];
+    else if (l1 == last) v -= g.fine[1].c * fa[face_at(3, l0, l2)];
+    if (l2 == 0) v -= g.fine[2].a * fa[face_at(4, l0, l1)];
+    else if (l2 == last) v -= g.fine[2].c * fa[face_at(5, l0, l1)];
+    return v;
+}
+
+// LAYERS: adjacent-layer mode (skeleton-sparse refinement; the hole's right-hand side is zero).
+template <int L, bool LAYERS>
+__global__ __launch_bounds__(256, 2) void k_filler_mfma3(Geo g, FillArgs a) {
     if (a.gate && *a.gate) return;
     __shared__ double buf[kFBuf];
+    __shared__ double fa[6 * 256];
+    __shared__ double mats[4 * kFMat];  // W_j0, W_j1, V_j1, V_j0
     constexpr int nh = 15, n = 16;
+    constexpr int j0 = (L == 0) ? 1 : 0, j1 = (L == 2) ? 1 : 2;
     const int Nf = g.Nf, Nc = g.Nc;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int L = a.line_axis, j0 = a.tr[0], j1 = a.tr[1];
-    // B fragments of a transform matrix T (W forward, V backward): B[k][m] = T[m][k], zero beyond
-    // 15; loaded right before each transform so that they do not occupy registers in between
-    auto frag = [&](const double *T, double (&f)[4]) {
-        const int m = lane & 15;
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + (lane >> 4);
-            f[ks] = (m < nh && k < nh) ? T[m * nh + k] : 0.0;
-        }
-    };
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     int tt[3];
     {
         int rem = blockIdx.x;
@@ -949,85 +984,129 @@ __global__ __launch_bounds__(256, PREFETCH ? 2 : 4) void k_filler_mfma3(Geo g, F
     // coordinates (l_a, l_b) on plane c is at 16 t_a + l_a + Nf (16 t_b + l_b) + Nf^2 c.
     int lo_base[3], hi_base[3];
     const int Nf2 = Nf * Nf;
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
-        const int fa = (j == 0) ? 1 : 0, fb = (j == 2) ? 1 : 2;
-        const int base = n * tt[fa] + Nf * (n * tt[fb]);
+        const int fa_ = (j == 0) ? 1 : 0, fb_ = (j == 2) ? 1 : 2;
+        const int base = n * tt[fa_] + Nf * (n * tt[fb_]);
         lo_base[j] = (tt[j] > 0) ? base + Nf2 * (tt[j] - 1) : -1;
         hi_base[j] = (tt[j] < Nc) ? base + Nf2 * tt[j] : -1;
     }
     const int f0 = n * tt[0] + Nf * (n * tt[1]) + Nf2 * (n * tt[2]);  // fine index of the tile origin
-    double fw0[4], fw1[4], fv0[4], fv1[4];
-    if (PREFETCH) {
-        frag(a.W[j0], fw0);
-        frag(a.W[j1], fw1);
-        frag(a.V[j0], fv0);
-        frag(a.V[j1], fv1);
+    // 1) the loads.  Every lane issues every load (a lane without a value reads an in-bounds
+    // stand-in and discards it), so the compiler waits for exactly the ones needed next.  First the
+    // two eigenvalues of this thread's line (mode pair m_j0 = tid % 15, m_j1 = tid / 15), then the
+    // face values around the tile (16 x 16 per face, the last row and column being points on two
+    // planes, used only by the output), b_ff at this thread's points (x_1 fastest), and the
+    // transform matrices.
+    const bool thomas = tid < nh * nh;
+    const int m0 = thomas ? tid % nh : 0, m1 = thomas ? tid / nh : 0;
+    const double mu0 = a.mu[j0][m0], mu1 = a.mu[j1][m1];
+    const int la = tid & 15, lb = tid >> 4;
+    // (the raw values; the stand-ins are zeroed where the values are stored, below the line factors)
+    double fvals[6];
+    bool fin[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int j = f >> 1, fa_ = (j == 0) ? 1 : 0, fb_ = (j == 2) ? 1 : 2;
+        const int bse = (f & 1) ? hi_base[j] : lo_base[j];
+        fin[f] = bse >= 0 && n * tt[fa_] + la < Nf && n * tt[fb_] + lb < Nf;
+        fvals[f] = a.skel[j][fin[f] ? bse + la + Nf * lb : 0];
     }
-    // 1) hole right-hand side: b_ff (initial guess) or 0, zero in the padding ...
-#pragma unroll 2
-    for (int o = tid; o < 4096; o += 256) {
-        const int l0 = o & 15, l1 = (o >> 4) & 15, l2 = o >> 8;
-        double v = 0.0;
-        if (a.bff && l0 < nh && l1 < nh && l2 < nh) v = a.bff[f0 + l0 + Nf * l1 + Nf2 * l2];
-        buf[l0 + kFS1 * l1 + kFS2 * l2] = v;
+    double bv[16];
+    const bool has_b = !LAYERS && a.bff;
+    const double *bsrc = has_b ? a.bff : a.mu[j0];  // an in-bounds stand-in when there is no b_ff
+    const bool bin = has_b && la < nh && lb < nh;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) bv[k] = (k < nh) ? bsrc[bin ? f0 + la + Nf * lb + Nf2 * k : 0] : 0.0;
+    double mv[4];  // element e = tid + 256 q of the four matrices, padded to 16 x 17
+    const bool min_ = (tid >> 4) < nh && (tid & 15) < nh;  // the same (m, k) for every q
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double *T = (q == 0) ? a.W[j0] : (q == 1) ? a.W[j1] : (q == 2) ? a.V[j1] : a.V[j0];
+        mv[q] = T[min_ ? (tid >> 4) * nh + (tid & 15) : 0];
     }
-    __syncthreads();
-    // ... minus the coupling to the merged skeleton values on the two faces normal to each axis
-    // (one axis per pass: the two faces of an axis never share a hole point)
-    for (int j = 0; j < 3; ++j) {
-        const int sj = fstride(j), sa = (j == 0) ? kFS1 : 1, sb = (j == 2) ? kFS1 : kFS2;
-        for (int o = tid; o < 2 * nh * nh; o += 256) {
-            const int side = o / (nh * nh), q = o - side * nh * nh;
-            const int la = q % nh, lb = q / nh;
-            const int bse = side ? hi_base[j] : lo_base[j];
-            if (bse < 0) continue;
-            const double coef = side ? g.fine[j].c : g.fine[j].a;
-            buf[la * sa + lb * sb + (side ? nh - 1 : 0) * sj] -= coef * a.skel[j][bse + la + Nf * lb];
+    // the line factors of Thomas along L for this mode pair, while the loads are in flight:
+    // pivots p_0 = b_L + mu_j0 + mu_j1, p_c = p_0 - a_L c_L / p_(c-1); hinv_c = 1 / p_c
+    const double sub = g.fine[L].a, sup = g.fine[L].c;
+    double hinv[nh];
+    {
+        const double diag = g.fine[L].b + (mu0 + mu1);
+        double cp = 0.0;
+#pragma unroll
+        for (int c = 0; c < nh; ++c) {
+            const double den = (c == 0) ? diag : diag - sub * cp;
+            hinv[c] = 1.0 / den;
+            cp = sup * hinv[c];
         }
-        __syncthreads();
+        // keep the chain here, in the shadow of the loads, rather than next to its use, and keep
+        // the uses of the loaded values below it (the chain waits for the eigenvalues only)
+#pragma unroll
+        for (int c = 0; c < nh; ++c) asm volatile("" ::"v"(hinv[c]));
+        __builtin_amdgcn_sched_barrier(0);
     }
-    // 2) forward transforms
-    if (!PREFETCH) frag(a.W[j0], fw0);
-    hole_transform_mfma(buf, j0, fw0, lane, wave);
-    if (!PREFETCH) frag(a.W[j1], fw1);
-    hole_transform_mfma(buf, j1, fw1, lane, wave);
-    // 3) Thomas along the line axis for the 225 lines of modes (m_j0, m_j1), with the pivots'
-    // reciprocals and the eliminated super-diagonal precomputed per mode pair (all holes share them)
-    if (tid < nh * nh) {
-        const int m0 = tid % nh, m1 = tid / nh;
+    // 2) the hole's right-hand side: b_ff (or 0, and 0 in the padding) everywhere, then each point
+    // of the first or last layer along some axis completed by one thread, that of its lowest such
+    // axis' face at its two other coordinates (axis by axis, as hole_rhs subtracts)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) buf[la + kFS1 * lb + kFS2 * k] = bin ? bv[k] : 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) fa[face_at(f, la, lb)] = fin[f] ? fvals[f] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) mats[q * kFMat + (tid >> 4) * 17 + (tid & 15)] = min_ ? mv[q] : 0.0;
+    lds_barrier();
+    if (la < nh && lb < nh) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int j = f >> 1;
+            const int lj = (f & 1) ? nh - 1 : 0;
+            const int l0 = (j == 0) ? lj : la;
+            const int l1 = (j == 1) ? lj : (j == 0 ? la : lb);
+            const int l2 = (j == 2) ? lj : lb;
+            const bool lower = (j >= 1 && (l0 == 0 || l0 == nh - 1)) || (j == 2 && (l1 == 0 || l1 == nh - 1));
+            if (lower) continue;
+            double *pt = buf + l0 + kFS1 * l1 + kFS2 * l2;
+            *pt = hole_rhs(g, fa, l0, l1, l2, *pt);
+        }
+    }
+    lds_barrier();
+    // 3) forward transforms (slab-private)
+    slab_transform<j0, L>(buf, mats, lane, wave);
+    slab_transform<j1, L>(buf, mats + kFMat, lane, wave);
+    __syncthreads();
+    // 4) Thomas along the line axis for the 225 lines of modes (m_j0, m_j1)
+    if (thomas) {
+        constexpr int sL = fstride(L);
         const int base = m0 * fstride(j0) + m1 * fstride(j1);
-        const int sL = fstride(L);
-        const double sub = g.fine[L].a;
         double f[nh];
 #pragma unroll
         for (int c = 0; c < nh; ++c) f[c] = buf[base + c * sL];
-        f[0] = f[0] * a.hinv[tid];
+        f[0] = f[0] * hinv[0];
 #pragma unroll
-        for (int c = 1; c < nh; ++c) f[c] = (f[c] - sub * f[c - 1]) * a.hinv[c * nh * nh + tid];
+        for (int c = 1; c < nh; ++c) f[c] = (f[c] - sub * f[c - 1]) * hinv[c];
 #pragma unroll
-        for (int c = nh - 2; c >= 0; --c) f[c] -= a.hcp[c * nh * nh + tid] * f[c + 1];
+        for (int c = nh - 2; c >= 0; --c) f[c] -= (sup * hinv[c]) * f[c + 1];
 #pragma unroll
         for (int c = 0; c < nh; ++c) buf[base + c * sL] = f[c];
     }
     __syncthreads();
-    // 4) backward transforms
-    if (!PREFETCH) frag(a.V[j1], fv1);
-    hole_transform_mfma(buf, j1, fv1, lane, wave);
-    if (!PREFETCH) frag(a.V[j0], fv0);
-    hole_transform_mfma(buf, j0, fv0, lane, wave);
-    // 5) write the whole tile (hole values and the skeleton planes above it), x_1 fastest; or, in
+    // 5) backward transforms (slab-private)
+    slab_transform<j1, L>(buf, mats + 2 * kFMat, lane, wave);
+    slab_transform<j0, L>(buf, mats + 3 * kFMat, lane, wave);
+    __syncthreads();
+    // 6) write the whole tile (hole values and the skeleton planes above it), x_1 fastest; or, in
     // adjacent-layer mode, only the tile points next to a coarse plane across it (the first and last
     // hole layer along each axis, skeleton points of other planes included) into that plane's layer
     // buffer: side 1 (above) of plane t_j - 1 for l_j = 0, side 0 (below) of plane t_j for
-    // l_j = nh - 1, at the canonical offset of the two other fine coordinates
+    // l_j = nh - 1, at the canonical offset of the two other fine coordinates.  Tile points on a
+    // coarse plane come from the face values.
     auto tile_value = [&](int l0, int l1, int l2) -> double {
         if (l0 < nh && l1 < nh && l2 < nh) return buf[l0 + kFS1 * l1 + kFS2 * l2];
-        if (l0 == nh) return a.skel[0][hi_base[0] + l1 + Nf * l2];
-        if (l1 == nh) return a.skel[1][hi_base[1] + l0 + Nf * l2];
-        return a.skel[2][hi_base[2] + l0 + Nf * l1];
+        if (l0 == nh) return fa[face_at(1, l1, l2)];
+        if (l1 == nh) return fa[face_at(3, l0, l2)];
+        return fa[face_at(5, l0, l1)];
     };
-    if (!a.adj_only) {
-#pragma unroll 2
+    if (!LAYERS) {
+#pragma unroll 4
         for (int o = tid; o < 4096; o += 256) {
             const int l0 = o & 15, l1 = (o >> 4) & 15, l2 = o >> 8;
             if (n * tt[0] + l0 >= Nf || n * tt[1] + l1 >= Nf || n * tt[2] + l2 >= Nf) continue;
@@ -1036,8 +1115,8 @@ __global__ __launch_bounds__(256, PREFETCH ? 2 : 4) void k_filler_mfma3(Geo g, F
         return;
     }
     const long long lay = (long long)Nc * Nf2;  // one side's layers of one mesh
-    for (int o = tid; o < 6 * 256; o += 256) {
-        const int face = o >> 8, la = o & 15, lb = (o >> 4) & 15;
+#pragma unroll
+    for (int face = 0; face < 6; ++face) {
         const int j = face >> 1, side = face & 1;  // side 0: layer l_j = 0 (above plane t_j - 1)
         if (side == 0 ? tt[j] == 0 : tt[j] == Nc) continue;
         const int lj = side == 0 ? 0 : nh - 1;
@@ -1049,7 +1128,7 @@ __global__ __launch_bounds__(256, PREFETCH ? 2 : 4) void k_filler_mfma3(Geo g, F
         const double v = tile_value(l0, l1, l2);
         // fine coordinates of the two other axes, increasing order
         const int ga = (j == 0) ? g1 : g0, gb = (j == 2) ? g1 : g2;
-        double *dst = (j == 0) ? a.adj[0] : (j == 1) ? a.adj[1] : a.adj[2];
+        double *dst = a.adj[j];
         const long long plane = side == 0 ? tt[j] - 1 : tt[j];
         dst[(side == 0 ? lay : 0) + ga + (long long)Nf * gb + (long long)Nf2 * plane] = v;
     }
@@ -1069,8 +1148,6 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
         a.tr[j] = 0;
     }
     a.line_axis = p.hole_line_axis;
-    a.hinv = p.dhole_inv;
-    a.hcp = p.dhole_cp;
     a.ntr = 0;
     for (int j = 0; j < d; ++j)
         if (j != p.hole_line_axis) a.tr[a.ntr++] = j;
@@ -1085,10 +1162,15 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
     for (int j = 0; j < d; ++j) tiles *= (p.Nc + 1);
     const dim3 grid(tiles), blk(256);
     if (d == 3 && nh == 15) {
-        if (tiles >= 4 * 256)
-            ASDSM_LAUNCH((k_filler_mfma3<false>), grid, blk, 0, st, p.geo, a);
-        else
-            ASDSM_LAUNCH((k_filler_mfma3<true>), grid, blk, 0, st, p.geo, a);
+#define ASDSM_FILL3(LL)                                                                   \
+    do {                                                                                  \
+        if (adj_only) ASDSM_LAUNCH((k_filler_mfma3<LL, true>), grid, blk, 0, st, p.geo, a); \
+        else ASDSM_LAUNCH((k_filler_mfma3<LL, false>), grid, blk, 0, st, p.geo, a);         \
+    } while (0)
+        if (p.hole_line_axis == 0) ASDSM_FILL3(0);
+        else if (p.hole_line_axis == 1) ASDSM_FILL3(1);
+        else ASDSM_FILL3(2);
+#undef ASDSM_FILL3
         return;
     }
     if (!adj_only && (d == 3 || d == 4) && (nh == 1 || nh == 3 || nh == 7)) {

@@ -176,7 +176,8 @@ void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t
 void launch_crosspoints4(const Plan &p, int mode, const double *const *res, hipStream_t st);
 void launch_merge4(const Plan &p, int mode, const double *const *res, hipStream_t st);
 // skel: the merged skeleton values per anisotropic mesh (default: the Y buffers); adj_only: write the
-// hole layers next to each coarse plane into the EA buffers instead of the fine tiles
+// hole layers next to each coarse plane into the EA buffers instead of the fine tiles (the error
+// equation of the skeleton-sparse step: bff must be null, the holes' right-hand side is zero)
 void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st, double *const *skel = nullptr,
                    bool adj_only = false);
 // skeleton-sparse refinement (k_sparse.hip)

@@ -773,31 +773,6 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         oVh[j] = add(p.hole_spec[j].V);
         oMh[j] = add(p.hole_spec[j].mu);
     }
-    // hole line factors: Thomas along the line axis for every mode pair of the transformed axes
-    size_t oHI = 0, oHC = 0;
-    if (d == 3) {
-        const int nh = p.n - 1, L = p.hole_line_axis;
-        int tr[2], nt = 0;
-        for (int j = 0; j < d; ++j)
-            if (j != L) tr[nt++] = j;
-        const Tri t = p.geo.fine[L];
-        p.hole_inv.assign((size_t)nh * nh * nh, 0.0);
-        p.hole_cp.assign((size_t)nh * nh * nh, 0.0);
-        for (int m1 = 0; m1 < nh; ++m1)
-            for (int m0 = 0; m0 < nh; ++m0) {
-                const size_t q = (size_t)m0 + (size_t)nh * m1;
-                const double diag = t.b + (p.hole_spec[tr[0]].mu[m0] + p.hole_spec[tr[1]].mu[m1]);
-                double cp = 0.0;
-                for (int c = 0; c < nh; ++c) {
-                    const double den = (c == 0) ? diag : diag - t.a * cp;
-                    cp = t.c / den;
-                    p.hole_inv[(size_t)c * nh * nh + q] = 1.0 / den;
-                    p.hole_cp[(size_t)c * nh * nh + q] = cp;
-                }
-            }
-        oHI = add(p.hole_inv);
-        oHC = add(p.hole_cp);
-    }
     size_t oS = add(p.Sp);
     size_t oCR[kMaxMeshes] = {};
     for (unsigned s = 1; s < (1u << d); ++s) {
@@ -826,10 +801,6 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     for (int j = 0; j < d; ++j) {
         p.dW32[j] = (float *)(base + oW32[j]);
         p.dV32[j] = (float *)(base + oV32[j]);
-    }
-    if (d == 3) {
-        p.dhole_inv = (double *)(base + oHI);
-        p.dhole_cp = (double *)(base + oHC);
     }
     for (unsigned s = 1; s < (1u << d); ++s) {
         if (p.line_pos[s] >= 0) p.dcr[s] = (double *)(base + oCR[s]);
