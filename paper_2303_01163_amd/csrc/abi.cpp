@@ -1519,6 +1519,7 @@ int begin_solve(Plan &p, const double *s, const double *g, double *u, const asds
     hs.stag_eta = opt.stag_eta;
     const int64_t k0 = opt.resume ? opt.k0 : 0;
     for (int i = 0; i < opt.max_iter; ++i) axis_permutation(p.seed, k0 + i, p.d, p.hperm + kMaxD * i);
+    for (int j = 0; j < kMaxD; ++j) hs.perm[j] = (opt.max_iter > 0) ? p.hperm[j] : j;
     ASDSM_HIP_CHECK(hipMemcpyAsync(p.ws.state, &hs, sizeof hs, hipMemcpyHostToDevice, p.stream));
     if (opt.max_iter > 0)
         ASDSM_HIP_CHECK(hipMemcpyAsync(p.ws.perm_table, p.hperm, (size_t)opt.max_iter * kMaxD * sizeof(int),

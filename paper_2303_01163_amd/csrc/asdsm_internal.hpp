@@ -77,6 +77,8 @@ struct IterState {
     double stag_eta;
     double rn_prev;    // ||r|| of the current iterate
     double spare;
+    int perm[kMaxD];   // axis permutation of step `it` (Algorithm 2 step 3), kept beside the counter
+                       // so that the error-phase kernels read it with one load
 };
 
 constexpr int kHistCap = 8192;   // capacity of the device residual / step histories

@@ -28,7 +28,8 @@ namespace asdsm {
 // ---------------------------------------------------------------------------------------------
 template <int TM, int TN, int KC, bool BKF, bool AKF>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
-    if (job.gate && *job.gate) return;
+    // the stopping flag is read with the first panel loads and tested once they have arrived
+    const bool live = !(job.gate && *job.gate);
     constexpr int MI = TM / 32, NI = TN / 32;            // MFMA tiles per wave along m and n
     constexpr int LA = TM * KC / 256, LB = KC * TN / 256;  // panel elements per thread
     __shared__ double sA[2][TM][KC + 1];
@@ -95,6 +96,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     gload(0);
     lstore(0);
     __syncthreads();
+    if (!live) return;  // block-uniform
     for (int c = 0; c < nch; ++c) {
         const int buf = c & 1;
         if (c + 1 < nch) gload(c + 1);

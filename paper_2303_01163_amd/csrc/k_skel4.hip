@@ -30,7 +30,6 @@ struct Skel4Args {
     const double *Sp;               // N_f x N_c spline matrix
     const double *scal;             // normalisation factors (error phase)
     int mode;                       // 0 initial guess, 1 error phase
-    const int *perm_table;          // error phase: permutation of step it at perm_table[kMaxD*it]
     const IterState *state;
     const int *gate;
 };
@@ -85,7 +84,7 @@ struct Perm4 {
 __device__ __forceinline__ Perm4 load_perm4(const Skel4Args &a) {
     Perm4 c{0, 1, 2, 3};
     if (a.mode == 1) {
-        const int *perm = a.perm_table + kMaxD * a.state->it;
+        const int *perm = a.state->perm;
         c = Perm4{perm[0], perm[1], perm[2], perm[3]};
     }
     return c;
@@ -280,7 +279,6 @@ static Skel4Args skel4_args(const Plan &p, int mode, const double *const *res) {
         a.lines[k] = (k < p.d) ? p.ws.lines[k] : nullptr;
         a.skel[k] = (k < p.d) ? p.ws.Y[1u << k] : nullptr;
     }
-    a.perm_table = p.ws.perm_table;
     a.state = p.ws.state;
     a.gate = p.gate;
     a.Sp = p.dSp;

@@ -26,7 +26,6 @@ struct SkelArgs {
     const double *Sp;               // N_f x N_c spline matrix
     const double *scal;             // normalisation factors (error phase)
     int mode;                       // 0 initial guess, 1 error phase
-    const int *perm_table;          // error phase: permutation of step it at perm_table[kMaxD*it]
     const IterState *state;
     const int *gate;
     // error phase with the plane kernel: per-block partial sums of squares of each anisotropic
@@ -93,7 +92,7 @@ struct XChoice {
 __device__ __forceinline__ XChoice load_choice(const SkelArgs &a, const Geo &g) {
     XChoice c{0, 1, 2, 1.0, 1.0, 1.0};
     if (a.mode == 1) {
-        const int *perm = a.perm_table + kMaxD * a.state->it;
+        const int *perm = a.state->perm;
         c.p0 = perm[0];
         c.p1 = perm[1];
         c.p2 = (g.d == 3) ? perm[2] : 2;
@@ -161,6 +160,28 @@ __device__ __forceinline__ double crosspoint_value(const SkelArgs &a, const Geo 
     return inv * rj[aniso_offset(g, j, p)];
 }
 
+// Error phase, in two halves so that the loads can be issued before this step's choice is known:
+// the solutions of the anisotropic meshes that contain a cross point (0 for the others), then the
+// value of the first axis of the permutation among them, normalised.
+struct XCand {
+    double v0, v1, v2;
+};
+
+__device__ __forceinline__ XCand cross_candidates(const SkelArgs &a, const Geo &g, const Pt &p, unsigned S) {
+    XCand c{0.0, 0.0, 0.0};
+    if (S & 1u) c.v0 = a.res[1][aniso_offset(g, 0, p)];
+    if (S & 2u) c.v1 = a.res[2][aniso_offset(g, 1, p)];
+    if (S & 4u) c.v2 = a.res[4][aniso_offset(g, 2, p)];
+    return c;
+}
+
+__device__ __forceinline__ double cross_pick(const XChoice ch, unsigned S, const XCand c) {
+    int j = ch.p0;
+    if (!((S >> j) & 1u)) j = ch.p1;
+    if (!((S >> j) & 1u)) j = ch.p2;
+    return inv_of(ch, j) * ((j == 0) ? c.v0 : (j == 1) ? c.v1 : c.v2);
+}
+
 __device__ __forceinline__ void fine_axes_of(int k, int d, int &a, int &b) {
     if (d == 2) {
         a = 1 - k;
@@ -197,30 +218,71 @@ __global__ __launch_bounds__(256) void k_crosspoints(Geo g, SkelArgs a) {
 // in LDS -- together with that row's Boolean-sum remainder R (below), and part B by the remaining
 // blocks: one launch where k_crosspoints and k_lines_residual take two.
 __global__ __launch_bounds__(256) void k_crosspoints3(Geo g, SkelArgs a, int nrowblk) {
-    if (a.gate && *a.gate) return;
-    const XChoice ch = load_choice(a, g);
+    // the stopping flag is read with the first loads and tested once they have arrived; a gated
+    // launch writes nothing
+    const bool live = !(a.gate && *a.gate);
     __shared__ double row[1024];  // N_f <= 1023
     const int k = blockIdx.y;
     const int Nf = g.Nf, Nc = g.Nc, n = g.n;
-    const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
     const long long nA = (long long)Nc * Nc * Nf;
     const double *__restrict__ Xk = (k == 0) ? a.res[1] : (k == 1) ? a.res[2] : a.res[4];
     double *__restrict__ lk = (k == 0) ? a.lines[0] : (k == 1) ? a.lines[1] : a.lines[2];
-    auto delta = [&](int u, int v, int ck) -> double {
-        const Pt p = mesh_pt(k, 3, u, v, (ck + 1) * n - 1);
-        const double uh = crosspoint_value(a, g, p, coarse_set(p, 3, n), ch);
-        return uh - scale_k * Xk[(long long)u + (long long)Nf * (v + (long long)Nf * ck)];
+    const bool err = a.mode == 1;
+    // the loads of one discrepancy: M_k's own value and, in the error phase, the candidates
+    struct Ld {
+        double x;
+        XCand c;
     };
-    if ((int)blockIdx.x < nrowblk) {
-        for (int rw = blockIdx.x; rw < Nc * Nc; rw += nrowblk) {
+    auto fetch = [&](int u, int v, int ck) -> Ld {
+        Ld l;
+        l.x = Xk[(long long)u + (long long)Nf * (v + (long long)Nf * ck)];
+        l.c = XCand{0.0, 0.0, 0.0};
+        if (err) {
+            const Pt p = mesh_pt(k, 3, u, v, (ck + 1) * n - 1);
+            l.c = cross_candidates(a, g, p, coarse_set(p, 3, n));
+        }
+        return l;
+    };
+    auto delta = [&](int u, int v, int ck, const Ld &l, const XChoice &ch, double scale_k) -> double {
+        const Pt p = mesh_pt(k, 3, u, v, (ck + 1) * n - 1);
+        const unsigned S = coarse_set(p, 3, n);
+        const double uh = err ? cross_pick(ch, S, l.c) : crosspoint_value(a, g, p, S, ch);
+        return uh - scale_k * l.x;
+    };
+    // this block's first row (part A) or first entry (part B) is loaded before the choice
+    constexpr int KP = 4;  // entries of a row per thread (N_f <= 1023)
+    const bool partA = (int)blockIdx.x < nrowblk;
+    Ld pre[KP];
+    if (partA) {
+        const int rw = blockIdx.x;  // < N_c^2: nrowblk <= N_c^2
+        const int u = (rw % Nc + 1) * n - 1, ck = rw / Nc;
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+            const int ib = threadIdx.x + 256 * j;
+            if (ib < Nf) pre[j] = fetch(u, ib, ck);
+        }
+    } else {
+        const long long w = (long long)(blockIdx.x - nrowblk) * 256 + threadIdx.x;
+        if (w < nA) pre[0] = fetch((int)((w / Nc) % Nf), ((int)(w % Nc) + 1) * n - 1, (int)(w / ((long long)Nc * Nf)));
+    }
+    const XChoice ch = load_choice(a, g);
+    if (!live) return;  // block-uniform
+    const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
+    if (partA) {
+        bool first = true;
+        for (int rw = blockIdx.x; rw < Nc * Nc; rw += nrowblk, first = false) {
             const int ca = rw % Nc, ck = rw / Nc;
             const int u = (ca + 1) * n - 1;
             double *__restrict__ A = lk + (long long)rw * Nf;
             double *__restrict__ R = lk + 2 * nA + (long long)rw * Nf;
-            for (int ib = threadIdx.x; ib < Nf; ib += 256) {
-                const double dv = delta(u, ib, ck);
-                A[ib] = dv;
-                row[ib] = dv;
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+                const int ib = threadIdx.x + 256 * j;
+                if (ib < Nf) {
+                    const double dv = delta(u, ib, ck, first ? pre[j] : fetch(u, ib, ck), ch, scale_k);
+                    A[ib] = dv;
+                    row[ib] = dv;
+                }
             }
             __syncthreads();
             for (int ib = threadIdx.x; ib < Nf; ib += 256) {
@@ -236,12 +298,14 @@ __global__ __launch_bounds__(256) void k_crosspoints3(Geo g, SkelArgs a, int nro
         return;
     }
     // part B: [ck][ia][cb]
+    bool first = true;
     for (long long w = (long long)(blockIdx.x - nrowblk) * 256 + threadIdx.x; w < nA;
-         w += (long long)(gridDim.x - nrowblk) * 256) {
+         w += (long long)(gridDim.x - nrowblk) * 256, first = false) {
         const int cb = (int)(w % Nc);
         const int u = (int)((w / Nc) % Nf);
         const int ck = (int)(w / ((long long)Nc * Nf));
-        lk[nA + w] = delta(u, (cb + 1) * n - 1, ck);
+        const int v = (cb + 1) * n - 1;
+        lk[nA + w] = delta(u, v, ck, first ? pre[0] : fetch(u, v, ck), ch, scale_k);
     }
 }
 
@@ -299,8 +363,8 @@ __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
 // crosspoint_value as in k_merge.
 template <int NC>
 __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
-    if (a.gate && *a.gate) return;
-    const XChoice ch = load_choice(a, g);
+    // the stopping flag is read with the first loads and tested once they have arrived
+    const bool live = !(a.gate && *a.gate);
     constexpr int RB = 8;
     __shared__ double sSa[64 * NC], sBa[64 * NC], sR[NC][RB], sSb[RB][NC];
     const int Nf = g.Nf, n = g.n;
@@ -336,8 +400,20 @@ __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
         return X[(long long)iac + (long long)Nf * ibc + (long long)Nf * Nf * ck];
     };
     const double xa = ld(ty), xb = ld(ty + 4);
+    // cross points of the error phase: the candidates, before this step's choice is known
+    const bool err = a.mode == 1;
+    XCand cand[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int ib = min(ib0 + ty + 4 * h, Nf - 1);
+        const Pt p = mesh_pt(k, 3, min(ia, Nf - 1), ib, (ck + 1) * n - 1);
+        const unsigned S = coarse_set(p, 3, n);
+        cand[h] = XCand{0.0, 0.0, 0.0};
+        if (err && S != mk) cand[h] = cross_candidates(a, g, p, S);
+    }
+    const XChoice ch = load_choice(a, g);
     __syncthreads();
-    if (ia >= Nf) return;
+    if (!live || ia >= Nf) return;
     const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -348,7 +424,7 @@ __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
         const unsigned S = coarse_set(p, 3, n);
         double v;
         if (S != mk) {
-            v = crosspoint_value(a, g, p, S, ch);
+            v = err ? cross_pick(ch, S, cand[h]) : crosspoint_value(a, g, p, S, ch);
         } else {
             double c1 = 0.0, c2 = 0.0;
 #pragma unroll
@@ -371,7 +447,6 @@ static SkelArgs skel_args(const Plan &p, int mode, const double *const *res) {
         a.lines[k] = (k < p.d) ? p.ws.lines[k] : nullptr;
         a.skel[k] = (k < p.d) ? p.ws.Y[1u << k] : nullptr;
     }
-    a.perm_table = p.ws.perm_table;
     a.state = p.ws.state;
     a.gate = p.gate;
     a.Sp = p.dSp;
@@ -962,7 +1037,8 @@ __device__ __forceinline__ double hole_rhs(const Geo &g, const double *fa, int l
 // LAYERS: adjacent-layer mode (skeleton-sparse refinement; the hole's right-hand side is zero).
 template <int L, bool LAYERS>
 __global__ __launch_bounds__(256, 2) void k_filler_mfma3(Geo g, FillArgs a) {
-    if (a.gate && *a.gate) return;
+    // the stopping flag is read with the other loads and tested after the first barrier
+    const bool live = !(a.gate && *a.gate);
     __shared__ double buf[kFBuf];
     __shared__ double fa[6 * 256];
     __shared__ double mats[4 * kFMat];  // W_j0, W_j1, V_j1, V_j0
@@ -1054,6 +1130,7 @@ __global__ __launch_bounds__(256, 2) void k_filler_mfma3(Geo g, FillArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) mats[q * kFMat + (tid >> 4) * 17 + (tid & 15)] = min_ ? mv[q] : 0.0;
     lds_barrier();
+    if (!live) return;  // block-uniform
     if (la < nh && lb < nh) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {

@@ -17,13 +17,14 @@
 
 namespace asdsm {
 
-// Fine index and ownership of point idx of M_K.
+// Fine index and ownership of point idx of M_K (N_c N_f^2 < 2^31 points: 32-bit arithmetic).
 template <int K>
-__device__ __forceinline__ void skel_point(const Geo &g, long long idx, int &x0, int &x1, int &x2, bool &owner) {
+__device__ __forceinline__ void skel_point(const Geo &g, int idx, int &x0, int &x1, int &x2, bool &owner) {
     const int Nf = g.Nf, n = g.n;
-    const int a = (int)(idx % Nf);
-    const int b = (int)((idx / Nf) % Nf);
-    const int c = (int)(idx / ((long long)Nf * Nf));
+    const unsigned row = (unsigned)idx / (unsigned)Nf;
+    const int a = idx - (int)row * Nf;
+    const int c = (int)(row / (unsigned)Nf);
+    const int b = (int)row - c * Nf;
     const int cf = (c + 1) * n - 1;
     if (K == 0) { x0 = cf; x1 = a; x2 = b; owner = true; }
     if (K == 1) { x0 = a; x1 = cf; x2 = b; owner = !on_coarse(a, n); }
@@ -38,12 +39,12 @@ struct SkelPtrs {
 __global__ __launch_bounds__(256) void k_skel_gather(Geo g, const double *__restrict__ u, const double *__restrict__ r,
                                                      SkelPtrs U, SkelPtrs R, const int *gate) {
     if (gate && *gate) return;
-    const long long per = (long long)g.Nc * g.Nf * g.Nf;
+    const int per = g.Nc * g.Nf * g.Nf;
     const int k = blockIdx.y;
     double *__restrict__ Uk = (k == 0) ? U.p[0] : (k == 1) ? U.p[1] : U.p[2];
     double *__restrict__ Rk = (k == 0) ? R.p[0] : (k == 1) ? R.p[1] : R.p[2];
     const long long sy = g.Nf, sz = (long long)g.Nf * g.Nf;
-    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < per; idx += (long long)gridDim.x * 256) {
+    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < per; idx += gridDim.x * 256) {
         int x0, x1, x2;
         bool own;
         if (k == 0) skel_point<0>(g, idx, x0, x1, x2, own);
@@ -62,15 +63,16 @@ __global__ __launch_bounds__(256) void k_skel_gather(Geo g, const double *__rest
 template <int K>
 __device__ __forceinline__ void skel_dots_mesh(const Geo &g, const double *__restrict__ E, const double *__restrict__ EA,
                                                const double *__restrict__ R, double *__restrict__ Q, double &rq,
-                                               double &qq, int tile, int ntile) {
+                                               double &qq, int tile, int ntile, bool live) {
     const int Nf = g.Nf;
-    const long long per = (long long)g.Nc * Nf * Nf;
+    const int per = g.Nc * Nf * Nf;
     const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
-    for (long long idx = (long long)tile * 256 + threadIdx.x; idx < per; idx += (long long)ntile * 256) {
+    for (int idx = tile * 256 + threadIdx.x; idx < per; idx += ntile * 256) {
         int x0, x1, x2;
         bool own;
         skel_point<K>(g, idx, x0, x1, x2, own);
-        const int a = (int)(idx % Nf), b = (int)((idx / Nf) % Nf);
+        const unsigned row = (unsigned)idx / (unsigned)Nf;
+        const int a = idx - (int)row * Nf, b = (int)(row % (unsigned)Nf);
         // neighbours within the plane (fine axes a, b) and across it (layers)
         const double am = a > 0 ? E[idx - 1] : 0.0, ap = a < Nf - 1 ? E[idx + 1] : 0.0;
         const double bm = b > 0 ? E[idx - Nf] : 0.0, bp = b < Nf - 1 ? E[idx + Nf] : 0.0;
@@ -89,7 +91,7 @@ __device__ __forceinline__ void skel_dots_mesh(const Geo &g, const double *__res
             q += g.fine[1].a * bm; q += g.fine[1].c * bp;
             q += g.fine[2].a * cm; q += g.fine[2].c * cp;
         }
-        Q[idx] = q;
+        if (live) Q[idx] = q;
         if (own) {
             rq += R[idx] * q;
             qq += q * q;
@@ -100,14 +102,15 @@ __device__ __forceinline__ void skel_dots_mesh(const Geo &g, const double *__res
 // Grid (tiles, 3): blockIdx.y selects the mesh.  Partial sums per block at blockIdx.x + tiles * y.
 __global__ __launch_bounds__(256) void k_skel_dots(Geo g, SkelPtrs E, SkelPtrs EA, SkelPtrs R, SkelPtrs Q,
                                                    double *partials, const int *gate) {
-    if (gate && *gate) return;
+    // the stopping flag is read with the operands; a gated launch writes nothing
+    const bool live = !(gate && *gate);
     double rq = 0.0, qq = 0.0;
     const int k = blockIdx.y;
-    if (k == 0) skel_dots_mesh<0>(g, E.p[0], EA.p[0], R.p[0], Q.p[0], rq, qq, blockIdx.x, gridDim.x);
-    else if (k == 1) skel_dots_mesh<1>(g, E.p[1], EA.p[1], R.p[1], Q.p[1], rq, qq, blockIdx.x, gridDim.x);
-    else skel_dots_mesh<2>(g, E.p[2], EA.p[2], R.p[2], Q.p[2], rq, qq, blockIdx.x, gridDim.x);
+    if (k == 0) skel_dots_mesh<0>(g, E.p[0], EA.p[0], R.p[0], Q.p[0], rq, qq, blockIdx.x, gridDim.x, live);
+    else if (k == 1) skel_dots_mesh<1>(g, E.p[1], EA.p[1], R.p[1], Q.p[1], rq, qq, blockIdx.x, gridDim.x, live);
+    else skel_dots_mesh<2>(g, E.p[2], EA.p[2], R.p[2], Q.p[2], rq, qq, blockIdx.x, gridDim.x, live);
     double vals[2] = {rq, qq};
-    block_partials<256, 2>(vals, partials, blockIdx.x + (size_t)gridDim.x * blockIdx.y);
+    if (live) block_partials<256, 2>(vals, partials, blockIdx.x + (size_t)gridDim.x * blockIdx.y);  // block-uniform
 }
 
 // u += s e and r -= s q on the skeleton (Algorithm 4 step 7 and the residual it implies), the
@@ -118,7 +121,19 @@ __global__ __launch_bounds__(256) void k_skel_dots(Geo g, SkelPtrs E, SkelPtrs E
 __global__ __launch_bounds__(256) void k_skel_update(Geo g, double *__restrict__ scal, const double *__restrict__ dots,
                                                      int ndots, SkelPtrs U, SkelPtrs E, SkelPtrs R, SkelPtrs Q,
                                                      SkelPtrs G, double *partials, const int *gate) {
-    if (gate && *gate) return;
+    // the stopping flag, the operands of this thread's first point and the partial sums are all
+    // loaded before the first barrier; a gated launch writes nothing
+    const bool live = !(gate && *gate);
+    const int per = g.Nc * g.Nf * g.Nf;
+    const int k = blockIdx.y;
+    double *__restrict__ Uk = (k == 0) ? U.p[0] : (k == 1) ? U.p[1] : U.p[2];
+    const double *__restrict__ Ek = (k == 0) ? E.p[0] : (k == 1) ? E.p[1] : E.p[2];
+    double *__restrict__ Rk = (k == 0) ? R.p[0] : (k == 1) ? R.p[1] : R.p[2];
+    const double *__restrict__ Qk = (k == 0) ? Q.p[0] : (k == 1) ? Q.p[1] : Q.p[2];
+    double *__restrict__ Gk = (k == 0) ? G.p[0] : (k == 1) ? G.p[1] : G.p[2];
+    const int idx0 = blockIdx.x * 256 + threadIdx.x;
+    const int i0 = idx0 < per ? idx0 : 0;
+    const double u0 = Uk[i0], e0 = Ek[i0], r0 = Rk[i0], q0 = Qk[i0];
     __shared__ double sh[4], sstep;
     {
         double a0 = 0.0, a1 = 0.0;
@@ -131,7 +146,7 @@ __global__ __launch_bounds__(256) void k_skel_update(Geo g, double *__restrict__
         if (threadIdx.x == 0) {
             const double st = (qq > 0.0) ? rq / qq : 0.0;
             sstep = (st > 0.0) ? st : 0.0;
-            if (blockIdx.x == 0 && blockIdx.y == 0) {
+            if (live && blockIdx.x == 0 && blockIdx.y == 0) {
                 scal[kScalRQ] = rq;
                 scal[kScalQQ] = qq;
                 scal[kScalStep] = sstep;
@@ -139,27 +154,23 @@ __global__ __launch_bounds__(256) void k_skel_update(Geo g, double *__restrict__
         }
         __syncthreads();
     }
+    if (!live) return;  // block-uniform
     const double s = sstep;
-    const long long per = (long long)g.Nc * g.Nf * g.Nf;
-    const int k = blockIdx.y;
-    double *__restrict__ Uk = (k == 0) ? U.p[0] : (k == 1) ? U.p[1] : U.p[2];
-    const double *__restrict__ Ek = (k == 0) ? E.p[0] : (k == 1) ? E.p[1] : E.p[2];
-    double *__restrict__ Rk = (k == 0) ? R.p[0] : (k == 1) ? R.p[1] : R.p[2];
-    const double *__restrict__ Qk = (k == 0) ? Q.p[0] : (k == 1) ? Q.p[1] : Q.p[2];
-    double *__restrict__ Gk = (k == 0) ? G.p[0] : (k == 1) ? G.p[1] : G.p[2];
     double acc = 0.0;
-    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < per; idx += (long long)gridDim.x * 256) {
+    auto update = [&](int idx, double uv, double ev, double rv, double qv) {
         int x0, x1, x2;
         bool own;
         if (k == 0) skel_point<0>(g, idx, x0, x1, x2, own);
         else if (k == 1) skel_point<1>(g, idx, x0, x1, x2, own);
         else skel_point<2>(g, idx, x0, x1, x2, own);
-        Uk[idx] += s * Ek[idx];
-        const double rr = Rk[idx] - s * Qk[idx];
+        Uk[idx] = uv + s * ev;
+        const double rr = rv - s * qv;
         Rk[idx] = rr;
         Gk[idx] = rr;
         if (own) acc += rr * rr;
-    }
+    };
+    if (idx0 < per) update(idx0, u0, e0, r0, q0);
+    for (int idx = idx0 + gridDim.x * 256; idx < per; idx += gridDim.x * 256) update(idx, Uk[idx], Ek[idx], Rk[idx], Qk[idx]);
     double vals[1] = {acc};
     block_partials<256, 1>(vals, partials, blockIdx.x + (size_t)gridDim.x * blockIdx.y);
 }

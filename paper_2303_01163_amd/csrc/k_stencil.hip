@@ -426,8 +426,10 @@ __global__ __launch_bounds__(64 * ROWS) void k_dots3(Geo g, Tile3 tl, const doub
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblk,
                                                   int mode, int nbox, double *scal, IterState *stt,
-                                                  double *hist, double *step_hist, const int *gate) {
-    if (gate && *gate) return;
+                                                  double *hist, double *step_hist, const int *perm_table,
+                                                  const int *gate) {
+    // the stopping flag is read with the partial sums and tested before anything is written
+    const bool live = !(gate && *gate);
     __shared__ double sh[4];
     const int tid = threadIdx.x;
     if (mode == kFinDots) {
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
         }
         const double rq = block_sum<256>(a0, sh);
         const double qq = block_sum<256>(a1, sh);
-        if (tid == 0) {
+        if (tid == 0 && live) {
             scal[kScalRQ] = rq;
             scal[kScalQQ] = qq;
             const double st = (qq > 0.0) ? rq / qq : 0.0;
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
 #pragma unroll 8
             for (int b = tid; b < nblk; b += 256) a += partials[(size_t)k * nblk + b];
             const double t = block_sum<256>(a, sh);
-            if (tid == 0) {
+            if (tid == 0 && live) {
                 scal[kScalEnorm2 + k] = t;
                 scal[kScalInvNorm + k] = (t > 0.0) ? 1.0 / sqrt(t) : 1.0;
             }
@@ -462,7 +464,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
 #pragma unroll 8
         for (int b = tid; b < nblk; b += 256) a += partials[b];
         const double t = block_sum<256>(a, sh);
-        if (tid != 0) return;
+        if (tid != 0 || !live) return;
         if (mode == kFinBnorm) {
             scal[kScalBnorm2] = t;
             return;
@@ -493,6 +495,9 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
         const double shat = scal[kScalStep];
         const int it = stt->it + 1;
         stt->it = it;
+        // the next step's axis permutation (the table holds max_iter < kHistCap entries)
+        if (it < stt->max_iter)
+            for (int j = 0; j < kMaxD; ++j) stt->perm[j] = perm_table[kMaxD * it + j];
         if (it < kHistCap) hist[it] = rn;
         if (it - 1 < kHistCap) step_hist[it - 1] = shat;
         if (!isfinite(rn) || !isfinite(shat)) {
@@ -519,7 +524,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
 
 void launch_finalize(const Plan &p, int nblk, int mode, int nbox, hipStream_t st) {
     ASDSM_LAUNCH(k_finalize, dim3(1), dim3(256), 0, st, p.ws.partials, nblk, mode, nbox, p.ws.scal,
-                       p.ws.state, p.ws.hist, p.ws.step_hist, p.gate);
+                       p.ws.state, p.ws.hist, p.ws.step_hist, p.ws.perm_table, p.gate);
 }
 
 // ---------------------------------------------------------------------------------------------
