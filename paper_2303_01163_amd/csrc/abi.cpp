@@ -986,7 +986,7 @@ double hole_points(const Plan &p) { return std::pow((double)(p.Nc + 1) * (p.geo.
 double filler_flops(const Plan &p) { return hole_points(p) * (4.0 * (p.d - 1) * (p.geo.n - 1) + 8.0); }
 
 // Launches of the cross-point and merge kernels (Algorithm 2) for this d.
-int skeleton_launches(const Plan &p) { return p.d == 4 ? 4 : 2; }
+int skeleton_launches(const Plan &p) { return p.d == 4 ? 4 : (merge_forms_discrepancies(p) ? 1 : 2); }
 
 int read_scalars(Plan &p) {
     ASDSM_HIP_CHECK(hipMemcpyAsync(p.hscal, p.ws.scal, kScalCount * sizeof(double), hipMemcpyDeviceToHost, p.stream));

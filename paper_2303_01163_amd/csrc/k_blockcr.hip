@@ -238,58 +238,30 @@ __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
         const long long mode = mode0 + tid;
         mbase[tid] = (mode % bx.mext0) * bx.ms0 + (mode / bx.mext0) * bx.ms1;
     }
-    // LDS-only barrier: nothing is in flight yet that the offsets would have to wait for
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     const int mats = tm * L * 3 * MM;
     const double *tsrc = bx.tab + (size_t)mode0 * L * 3 * MM;
+    for (int e = tid; e < mats; e += 256) Mt[e] = tsrc[e];
+    __syncthreads();
     const bool modes_fast = bx.ms0 == 1;
     const long long sw = bx.sw, sc = bx.sc;
-    // quotients of the small index divisions through a double reciprocal (exact here: t < 2^31,
-    // divisors below 2^15)
-    const double rtm = 1.0 / tm, rN = 1.0 / N;
-    auto qdiv = [](int a, int b, double rb) -> int { (void)b; return (int)(((double)a + 0.5) * rb); };
     // element t of the coalesced order: modes fastest when they are contiguous, else the line
     auto elem = [&](int t, int &ml, int &i, int &c) {
         if (modes_fast) {
-            const int rest = qdiv(t, tm, rtm);
-            ml = t - rest * tm;
-            c = qdiv(rest, N, rN);
-            i = rest - c * N;
+            ml = t % tm;
+            const int rest = t / tm;
+            i = rest % N;
+            c = rest / N;
         } else {
-            const int rest = qdiv(t, N, rN);
-            i = t - rest * N;
-            c = qdiv(rest, tm, rtm);
-            ml = rest - c * tm;
+            i = t % N;
+            const int rest = t / N;
+            ml = rest % tm;
+            c = rest / tm;
         }
     };
-    // the matrices and the lines in rounds of kLd values each per thread, all loads of a round in
-    // flight together (a lane beyond the end reads element 0 and discards it)
-    constexpr int kLd = 12;
-    const int nline = tm * N * NB;
-    for (int r0 = 0; r0 < mats || r0 < nline; r0 += 256 * kLd) {
-        double tv[kLd], lv[kLd];
-        int li[kLd];
-#pragma unroll
-        for (int j = 0; j < kLd; ++j) {
-            const int e = r0 + tid + 256 * j;
-            tv[j] = tsrc[e < mats ? e : 0];
-        }
-#pragma unroll
-        for (int j = 0; j < kLd; ++j) {
-            const int t = r0 + tid + 256 * j;
-            int ml, i, c;
-            elem(t < nline ? t : 0, ml, i, c);
-            li[j] = (ml * N + i) * NB + c;
-            lv[j] = bx.src[mbase[ml] + i * sw + c * sc];
-        }
-#pragma unroll
-        for (int j = 0; j < kLd; ++j) {
-            const int e = r0 + tid + 256 * j;
-            if (e < mats) Mt[e] = tv[j];
-            if (r0 + tid + 256 * j < nline) D[li[j]] = lv[j];
-        }
+    for (int t = tid; t < tm * N * NB; t += 256) {
+        int ml, i, c;
+        elem(t, ml, i, c);
+        D[(ml * N + i) * NB + c] = bx.src[mbase[ml] + i * sw + c * sc];
     }
     __syncthreads();
     if (!live) return;  // block-uniform

@@ -147,7 +147,12 @@ __device__ __forceinline__ double crosspoint_value(const SkelArgs &a, const Geo 
         if (S & 1u) { sum += a.res[1][aniso_offset(g, 0, p)]; ++cnt; }
         if (S & 2u) { sum += a.res[2][aniso_offset(g, 1, p)]; ++cnt; }
         if (S & 4u) { sum += a.res[4][aniso_offset(g, 2, p)]; ++cnt; }
-        const double *rs = (S == 3u) ? a.res[3] : (S == 5u) ? a.res[5] : (S == 6u) ? a.res[6] : a.res[7];
+        // the intersection mesh's solution by integer arithmetic on the four pointers: a chain of
+        // selects among the argument struct's fields becomes one load at a computed offset, which
+        // copies the struct to scratch memory
+        const unsigned long long r3 = (unsigned long long)a.res[3], r5 = (unsigned long long)a.res[5],
+                                 r6 = (unsigned long long)a.res[6], r7 = (unsigned long long)a.res[7];
+        const double *rs = (const double *)((S == 3u) * r3 + (S == 5u) * r5 + (S == 6u) * r6 + (S == 7u) * r7);
         sum -= rs[inter_offset(g, S, p)];
         return sum / (double)(cnt - 1);
     }
@@ -356,43 +361,73 @@ __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
     }
 }
 
-// d = 3 merge by tiles: block (64 values of i_a x 8 values of i_b, coarse plane c_k, mesh k), two
-// points per thread.  The Boolean-sum correction of the plane is two rank-N_c products,
-// Sp R_ck + B_ck Sp^T: the block stages the Sp and B_ck rows of its i_a range and the R_ck columns
-// and Sp rows of its i_b range in LDS (contiguous loads).  Cross points take the value of
-// crosspoint_value as in k_merge.
+// d = 3 merge by tiles, with the discrepancies of the tile formed in place: block (64 values of
+// i_a x 8 values of i_b, coarse plane c_k, mesh k), two points per thread.  The Boolean-sum
+// correction of the plane is two rank-N_c products, Sp R_ck + B_ck Sp^T, with A, B and R as in
+// k_crosspoints3; instead of reading them from a launch of their own, the block forms the
+// discrepancies it needs -- A at its 8 rows i_b and at the N_c coarse rows for every c_a, B at its
+// 64 values of i_a for every c_b -- and the R of its rows from them, in LDS, with the arithmetic
+// of k_crosspoints3 (the same values bit for bit).  Their loads, the tile's own values and the
+// cross-point candidates are all issued before this step's choice is read.  Cross points take the
+// value of crosspoint_value as in k_merge.
 template <int NC>
 __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
     // the stopping flag is read with the first loads and tested once they have arrived
     const bool live = !(a.gate && *a.gate);
     constexpr int RB = 8;
-    __shared__ double sSa[64 * NC], sBa[64 * NC], sR[NC][RB], sSb[RB][NC];
+    constexpr int NA = NC * (RB + NC);  // A: [c_a][the 8 rows, then the N_c coarse rows]
+    constexpr int ND = NA + 64 * NC;    // then B: [i_a][c_b]
+    constexpr int DPT = (ND + 255) / 256;
+    __shared__ double sSa[64 * NC], sSb[RB][NC], sA[NC][RB + NC], sB[64][NC + 1], sR[NC][RB];
     const int Nf = g.Nf, n = g.n;
     const int k = blockIdx.z, ck = blockIdx.y;
     const int xtn = (Nf + 63) / 64;
     const int ia0 = (blockIdx.x % xtn) * 64, ib0 = (blockIdx.x / xtn) * RB;
     const unsigned mk = 1u << k;
-    const long long nA = (long long)NC * NC * Nf;
     // per-mesh pointers chosen by selects (a dynamic index into the argument struct would be
     // copied to scratch memory)
-    const double *lk = (k == 0) ? a.lines[0] : (k == 1) ? a.lines[1] : a.lines[2];
     double *sk = (k == 0) ? a.skel[0] : (k == 1) ? a.skel[1] : a.skel[2];
-    const double *__restrict__ B = lk + nA;
-    const double *__restrict__ R = lk + 2 * nA;
     const double *__restrict__ Sp = a.Sp;
+    const double *__restrict__ X = (k == 0) ? a.res[1] : (k == 1) ? a.res[2] : a.res[4];
     const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
     const int nrow = min(64, Nf - ia0);  // i_a rows of this tile
-    for (int q = t; q < nrow * NC; q += 256) {
-        sSa[q] = Sp[(long long)ia0 * NC + q];
-        sBa[q] = B[((long long)ck * Nf + ia0) * NC + q];
-    }
+    const bool err = a.mode == 1;
+    for (int q = t; q < nrow * NC; q += 256) sSa[q] = Sp[(long long)ia0 * NC + q];
     if (t < NC * RB) {
         const int c = t / RB, jj = t % RB;
-        const int ib = min(ib0 + jj, Nf - 1);
-        sR[c][jj] = R[((long long)ck * NC + c) * Nf + ib];
-        sSb[jj][c] = Sp[(long long)ib * NC + c];
+        sSb[jj][c] = Sp[(long long)min(ib0 + jj, Nf - 1) * NC + c];
     }
-    const double *__restrict__ X = (k == 0) ? a.res[1] : (k == 1) ? a.res[2] : a.res[4];
+    // discrepancy d of the block at (u, v) of plane c_k: d < NA is A at c_a = d / (RB + NC), column
+    // w = d % (RB + NC) (row i_b = ib0 + w for w < RB, else coarse row w - RB); else B at
+    // i_a = ia0 + (d - NA) / N_c, c_b = (d - NA) % N_c (rows past N_f - 1 clamped, never used)
+    auto dpoint = [&](int d, int &u, int &v) {
+        if (d < NA) {
+            const int ca = d / (RB + NC), w = d - ca * (RB + NC);
+            u = (ca + 1) * n - 1;
+            v = (w < RB) ? min(ib0 + w, Nf - 1) : (w - RB + 1) * n - 1;
+        } else {
+            const int e = d - NA, ia = e / NC, cb = e - ia * NC;
+            u = min(ia0 + ia, Nf - 1);
+            v = (cb + 1) * n - 1;
+        }
+    };
+    double dx[DPT];
+    XCand dc[DPT];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = t + 256 * j;
+        dx[j] = 0.0;
+        dc[j] = XCand{0.0, 0.0, 0.0};
+        if (d < ND) {
+            int u, v;
+            dpoint(d, u, v);
+            dx[j] = X[(long long)u + (long long)Nf * (v + (long long)Nf * ck)];
+            if (err) {
+                const Pt p = mesh_pt(k, 3, u, v, (ck + 1) * n - 1);
+                dc[j] = cross_candidates(a, g, p, coarse_set(p, 3, n));
+            }
+        }
+    }
     const int ia = ia0 + tx;
     const int iac = min(ia, Nf - 1);
     auto ld = [&](int j) -> double {
@@ -400,21 +435,52 @@ __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
         return X[(long long)iac + (long long)Nf * ibc + (long long)Nf * Nf * ck];
     };
     const double xa = ld(ty), xb = ld(ty + 4);
-    // cross points of the error phase: the candidates, before this step's choice is known
-    const bool err = a.mode == 1;
+    // cross points of the error phase among the tile's own points: the candidates
     XCand cand[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int ib = min(ib0 + ty + 4 * h, Nf - 1);
-        const Pt p = mesh_pt(k, 3, min(ia, Nf - 1), ib, (ck + 1) * n - 1);
+        const Pt p = mesh_pt(k, 3, iac, ib, (ck + 1) * n - 1);
         const unsigned S = coarse_set(p, 3, n);
         cand[h] = XCand{0.0, 0.0, 0.0};
         if (err && S != mk) cand[h] = cross_candidates(a, g, p, S);
     }
     const XChoice ch = load_choice(a, g);
-    __syncthreads();
-    if (!live || ia >= Nf) return;
+    if (!live) return;  // block-uniform
     const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
+    // the discrepancies (cross-point value minus the scaled solution of M_k) into LDS
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = t + 256 * j;
+        if (d < ND) {
+            int u, v;
+            dpoint(d, u, v);
+            const Pt p = mesh_pt(k, 3, u, v, (ck + 1) * n - 1);
+            const unsigned S = coarse_set(p, 3, n);
+            const double uh = err ? cross_pick(ch, S, dc[j]) : crosspoint_value(a, g, p, S, ch);
+            const double dv = uh - scale_k * dx[j];
+            if (d < NA) {
+                const int ca = d / (RB + NC);
+                sA[ca][d - ca * (RB + NC)] = dv;
+            } else {
+                const int e = d - NA, ib = e / NC;
+                sB[ib][e - ib * NC] = dv;
+            }
+        }
+    }
+    __syncthreads();
+    // R of the tile's rows: 0 on a coarse row, else A minus the spline of the row's coarse values
+    if (t < NC * RB) {
+        const int ca = t / RB, j = t % RB;
+        double v = 0.0;
+        if (!on_coarse(ib0 + j, n)) {
+            v = sA[ca][j];
+            for (int cb = 0; cb < NC; ++cb) v -= sSb[j][cb] * sA[ca][RB + cb];
+        }
+        sR[ca][j] = v;
+    }
+    __syncthreads();
+    if (ia >= Nf) return;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int j = ty + 4 * h, ib = ib0 + j;
@@ -430,12 +496,15 @@ __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) c1 += sSa[tx * NC + c] * sR[c][j];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) c2 += sSb[j][c] * sBa[tx * NC + c];
+            for (int c = 0; c < NC; ++c) c2 += sSb[j][c] * sB[tx][c];
             v = scale_k * x + (c1 + c2);
         }
         sk[(long long)ia + (long long)Nf * ib + (long long)Nf * Nf * ck] = v;
     }
 }
+
+// k_merge3 forms its own discrepancies for these coarse sizes
+bool merge_forms_discrepancies(const Plan &p) { return p.d == 3 && (p.Nc == 7 || p.Nc == 15 || p.Nc == 31); }
 
 static SkelArgs skel_args(const Plan &p, int mode, const double *const *res) {
     SkelArgs a;
@@ -462,6 +531,7 @@ void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipSt
         launch_crosspoints4(p, mode, res, st);
         return;
     }
+    if (merge_forms_discrepancies(p)) return;
     SkelArgs a = skel_args(p, mode, res);
     if (p.d == 3) {
         const int nrow = std::min(p.Nc * p.Nc, 512);
@@ -482,7 +552,7 @@ void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t
         return;
     }
     SkelArgs a = skel_args(p, mode, res);
-    if (p.d == 3 && (p.Nc == 7 || p.Nc == 15 || p.Nc == 31)) {
+    if (merge_forms_discrepancies(p)) {
         const unsigned tiles = (unsigned)(((p.Nf + 63) / 64) * ((p.Nf + 7) / 8));
         const dim3 grid(tiles, (unsigned)p.Nc, 3);
         if (p.Nc == 7)

@@ -172,6 +172,9 @@ void launch_sumsq(const Plan &p, const double *const *x, const long long *n, int
 // p.ws.perm_table[p.ws.state->it].
 void launch_crosspoints(const Plan &p, int mode, const double *const *res, hipStream_t st);
 void launch_merge(const Plan &p, int mode, const double *const *res, hipStream_t st);
+// d = 3 with N_c in {7, 15, 31}: the merge forms the cross-point discrepancies itself and
+// launch_crosspoints launches nothing
+bool merge_forms_discrepancies(const Plan &p);
 // d = 4 (k_skel4.hip): the discrepancy families and Boolean-sum remainders, then the merge
 void launch_crosspoints4(const Plan &p, int mode, const double *const *res, hipStream_t st);
 void launch_merge4(const Plan &p, int mode, const double *const *res, hipStream_t st);
