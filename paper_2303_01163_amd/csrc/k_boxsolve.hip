@@ -26,6 +26,8 @@ namespace asdsm {
 // Operand layout of v_mfma_f64_16x16x4f64 (lane l, 0..63):
 //   A: row l%16, k l/16;  B: k l/16, col l%16;  D[v]: row l/16 + 4v, col l%16.
 // ---------------------------------------------------------------------------------------------
+constexpr int kGemmPrefetch = 4;  // chunks whose loads k_gemm_f64 issues together
+
 template <int TM, int TN, int KC, bool BKF, bool AKF>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     // the stopping flag is read with the first panel loads and tested once they have arrived
@@ -93,13 +95,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     for (int a = 0; a < MI; ++a)
 #pragma unroll
         for (int b = 0; b < NI; ++b) acc[a][b] = {0.0, 0.0, 0.0, 0.0};
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    if (!live) return;  // block-uniform
-    for (int c = 0; c < nch; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nch) gload(c + 1);
+    auto mma = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
             const int kq = kk + (lane >> 4);
@@ -114,8 +110,64 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
                 for (int b = 0; b < NI; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
-        if (c + 1 < nch) lstore(buf ^ 1);
+    };
+    if (nch <= kGemmPrefetch) {
+        // short contractions (the mode transforms, K = N_f <= kGemmPrefetch * KC): every chunk's
+        // loads are issued at once into registers, so the block waits for memory once; the chunks
+        // then pass through the two LDS buffers in turn
+        // (every lane loads every element, an out-of-range one from the operand's first element,
+        // and zeroes it: straight-line loads, all in flight together)
+        double pa[kGemmPrefetch][LA], pb[kGemmPrefetch][LB];
+#pragma unroll
+        for (int c = 0; c < kGemmPrefetch; ++c) {
+            const int k0 = c * KC;
+#pragma unroll
+            for (int j = 0; j < LA; ++j) {
+                const int row = m0 + ar + (AKF ? (256 / KC) * j : 0);
+                const int k = k0 + ak + (AKF ? 0 : (256 / TM) * j);
+                const bool in = row < job.M && k < job.K;
+                const double x = A[in ? (AKF ? row * sAi + k : row + k * sAk) : 0];
+                pa[c][j] = in ? x : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < LB; ++j) {
+                const int nn = n0 + (BKF ? bn0 + (256 / KC) * j : bn0);
+                const int kb = k0 + (BKF ? bk0 : bk0 + (256 / TN) * j);
+                const bool in = nn < job.N && kb < job.K;
+                const double x = B[in ? kb * sBk + nn * sBn : 0];
+                pb[c][j] = in ? x : 0.0;
+            }
+        }
+        auto put = [&](int c) {
+#pragma unroll
+            for (int j = 0; j < LA; ++j) ra[j] = pa[c][j];
+#pragma unroll
+            for (int j = 0; j < LB; ++j) rb[j] = pb[c][j];
+            lstore(c & 1);
+        };
+        put(0);
         __syncthreads();
+        if (!live) return;  // block-uniform
+#pragma unroll
+        for (int c = 0; c < kGemmPrefetch; ++c) {
+            if (c < nch) {
+                mma(c & 1);
+                if (c + 1 < nch) put(c + 1);
+                __syncthreads();
+            }
+        }
+    } else {
+        gload(0);
+        lstore(0);
+        __syncthreads();
+        if (!live) return;  // block-uniform
+        for (int c = 0; c < nch; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < nch) gload(c + 1);
+            mma(buf);
+            if (c + 1 < nch) lstore(buf ^ 1);
+            __syncthreads();
+        }
     }
     double *__restrict__ C = job.C[box] + (long long)bat * job.sCb;
     double ss = 0.0;  // sum of squares of the values this thread writes (norm_out only)
