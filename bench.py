@@ -37,7 +37,7 @@ KERNEL_SOURCE = {"k_gemm_f64": "k_boxsolve.hip", "k_update_residual3": "k_stenci
                  "k_box_residual": "k_boxsolve.hip", "k_merge3": "k_skeleton.hip",
                  "k_line": "k_boxsolve.hip", "k_crosspoints3": "k_skeleton.hip",
                  "k_skel_dots": "k_sparse.hip", "k_skel_update": "k_sparse.hip", "k_conv_fwd": "k_learn.hip",
-                 "k_plane2": "k_boxsolve.hip"}
+                 "k_plane2": "k_boxsolve.hip", "k_block_cr2": "k_blockcr.hip"}
 SKEL_KERNEL = {"update": "k_skel_update (+ the fine residual at the ends)", "dots": "k_skel_dots"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_asdsm3d_127.txt")
 PMC_WORKLOAD = ("asdsm-3d-127^3-sinbump-seed0", 3)   # workload and coarse level the counters were taken on
