@@ -13,7 +13,9 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // A fine index i (0-based) lies on a coarse line iff i+1 is a multiple of n (n a power of two).
 __device__ __forceinline__ bool on_coarse(int i, int n) { return ((i + 1) & (n - 1)) == 0; }
-__device__ __forceinline__ int coarse_of(int i, int n) { return (i + 1) / n - 1; }
+// Its coarse index, (i + 1) / n - 1, by a shift: a division by the run-time n costs tens of
+// instructions, and the index maps of the skeleton kernels take several per point.
+__device__ __forceinline__ int coarse_of(int i, int n) { return ((i + 1) >> __builtin_ctz((unsigned)n)) - 1; }
 
 // Element j (a run-time axis) of a per-axis array of kMaxD ints, through selects: a dynamic index
 // into a local array would place the array in scratch memory.

@@ -173,11 +173,11 @@ struct XCand {
 };
 
 __device__ __forceinline__ XCand cross_candidates(const SkelArgs &a, const Geo &g, const Pt &p, unsigned S) {
-    XCand c{0.0, 0.0, 0.0};
-    if (S & 1u) c.v0 = a.res[1][aniso_offset(g, 0, p)];
-    if (S & 2u) c.v1 = a.res[2][aniso_offset(g, 1, p)];
-    if (S & 4u) c.v2 = a.res[4][aniso_offset(g, 2, p)];
-    return c;
+    // every lane issues all three loads, with offset 0 for a mesh that does not hold the point:
+    // no branches and no use of the values here, so they stay in flight with the caller's other
+    // loads; cross_pick only ever takes the value of a mesh that holds the point
+    return XCand{a.res[1][(S & 1u) ? aniso_offset(g, 0, p) : 0], a.res[2][(S & 2u) ? aniso_offset(g, 1, p) : 0],
+                 a.res[4][(S & 4u) ? aniso_offset(g, 2, p) : 0]};
 }
 
 __device__ __forceinline__ double cross_pick(const XChoice ch, unsigned S, const XCand c) {
@@ -392,11 +392,18 @@ __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
     const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
     const int nrow = min(64, Nf - ia0);  // i_a rows of this tile
     const bool err = a.mode == 1;
-    for (int q = t; q < nrow * NC; q += 256) sSa[q] = Sp[(long long)ia0 * NC + q];
-    if (t < NC * RB) {
-        const int c = t / RB, jj = t % RB;
-        sSb[jj][c] = Sp[(long long)min(ib0 + jj, Nf - 1) * NC + c];
+    // the spline rows of the tile into registers first (stored to LDS after the choice, so that
+    // every load of the block, the choice's included, is in flight at once; a load followed by its
+    // store in one loop would wait for each load in turn)
+    constexpr int SPT = (64 * NC + 255) / 256;
+    double spa[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int q = t + 256 * j;
+        spa[j] = Sp[(long long)ia0 * NC + (q < nrow * NC ? q : 0)];
     }
+    const bool sbt = t < NC * RB;
+    const double spb = Sp[sbt ? (long long)min(ib0 + t % RB, Nf - 1) * NC + t / RB : 0];
     // discrepancy d of the block at (u, v) of plane c_k: d < NA is A at c_a = d / (RB + NC), column
     // w = d % (RB + NC) (row i_b = ib0 + w for w < RB, else coarse row w - RB); else B at
     // i_a = ia0 + (d - NA) / N_c, c_b = (d - NA) % N_c (rows past N_f - 1 clamped, never used)
@@ -415,17 +422,15 @@ __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
     XCand dc[DPT];
 #pragma unroll
     for (int j = 0; j < DPT; ++j) {
-        const int d = t + 256 * j;
-        dx[j] = 0.0;
+        // a lane past the block's last discrepancy loads that one's operands (discarded later)
+        const int d = min(t + 256 * j, ND - 1);
+        int u, v;
+        dpoint(d, u, v);
+        dx[j] = X[(long long)u + (long long)Nf * (v + (long long)Nf * ck)];
         dc[j] = XCand{0.0, 0.0, 0.0};
-        if (d < ND) {
-            int u, v;
-            dpoint(d, u, v);
-            dx[j] = X[(long long)u + (long long)Nf * (v + (long long)Nf * ck)];
-            if (err) {
-                const Pt p = mesh_pt(k, 3, u, v, (ck + 1) * n - 1);
-                dc[j] = cross_candidates(a, g, p, coarse_set(p, 3, n));
-            }
+        if (err) {  // launch-uniform
+            const Pt p = mesh_pt(k, 3, u, v, (ck + 1) * n - 1);
+            dc[j] = cross_candidates(a, g, p, coarse_set(p, 3, n));
         }
     }
     const int ia = ia0 + tx;
@@ -443,10 +448,16 @@ __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
         const Pt p = mesh_pt(k, 3, iac, ib, (ck + 1) * n - 1);
         const unsigned S = coarse_set(p, 3, n);
         cand[h] = XCand{0.0, 0.0, 0.0};
-        if (err && S != mk) cand[h] = cross_candidates(a, g, p, S);
+        if (err) cand[h] = cross_candidates(a, g, p, S);  // launch-uniform; used at cross points only
     }
     const XChoice ch = load_choice(a, g);
     if (!live) return;  // block-uniform
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int q = t + 256 * j;
+        if (q < nrow * NC) sSa[q] = spa[j];
+    }
+    if (sbt) sSb[t % RB][t / RB] = spb;
     const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
     // the discrepancies (cross-point value minus the scaled solution of M_k) into LDS
 #pragma unroll
