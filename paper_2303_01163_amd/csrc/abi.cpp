@@ -150,6 +150,15 @@ double *sol_buf(const Plan &p, unsigned m) {
     return (__builtin_popcount(m) == 1) ? p.ws.X[m] : p.ws.Y[m];
 }
 
+// The first transform GEMM of a skeleton-sparse step carries the previous step's pending stopping
+// rule (one extra block; a no-op on the device when nothing is pending).
+void carry_finalize(Plan &p, GemmJob &j) {
+    if (!p.fin_carry) return;
+    j.fin_on = 1;
+    j.fin = pending_fin_args(p);
+    p.fin_carry = false;
+}
+
 // Mode transform along canonical position q (a fine axis of extent N_f) of nb boxes of the shape m:
 // out_b = T_b applied along q to in_b (out += when accum), T_b an N_f x N_f row-major matrix
 // (T[m][i]).  Position 0 is contiguous (one GEMM over all rows); a later position is a batch over
@@ -190,6 +199,7 @@ int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *
         p.norm_nblk = gemm_tiles_per_box(j);
         for (int b = 0; b < nb; ++b) j.norm_out[b] = p.norm_partials + (size_t)norm_slot[b] * p.norm_nblk;
     }
+    carry_finalize(p, j);
     PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
     if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
     return check_launch("transform");
@@ -236,6 +246,7 @@ int transform_pos0_modes_major(Plan &p, const MeshDesc &m, int nb, const double 
         p.norm_nblk = gemm_tiles_per_box(j);
         for (int b = 0; b < nb; ++b) j.norm_out[b] = p.norm_partials + (size_t)norm_slot[b] * p.norm_nblk;
     }
+    carry_finalize(p, j);
     PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
     if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
     return check_launch("transform");
@@ -1232,7 +1243,21 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
 // in adjacent-layer mode), q = A e and <r, q>, <q, q> on the skeleton, and u += s e, r -= s q with
 // the gathers on the skeleton.  The fine u is rebuilt from the skeleton when the loop ends.
 int sparse_step(Plan &p) {
-    if (int rc = error_guess(p)) return rc;
+    // The previous step's stopping rule is still pending on the device (k_skel_update leaves it).
+    // With line-axis meshes (FP64) this step's first launch is a transform GEMM, which applies it in
+    // one extra block beside its tiles; otherwise a launch of its own applies it first.
+    const bool carry = p.line_aniso && !p.prec32;
+    if (carry) {
+        p.fin_carry = true;
+    } else {
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 0.0, 0.0, "k_finalize_pending");
+        launch_finalize_pending(p, p.stream);
+    }
+    const int erc = error_guess(p);
+    const bool missed = p.fin_carry;
+    p.fin_carry = false;
+    if (erc) return erc;
+    if (missed) return fail(ASDSM_E_UNSUPPORTED, "skeleton-sparse step: no transform carried the stopping rule");
     const double skel = aniso_points(p);  // skeleton points counted once per mesh
     {
         PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p), 8.0 * (3.0 * skel), "hole filler (layer mode)");
@@ -1576,6 +1601,12 @@ int begin_solve(Plan &p, const double *s, const double *g, double *u, const asds
 // fine residual (so that r and the gathers describe the returned u).  Not gated: it runs whatever
 // the stopping rule did.
 int finish_sparse(Plan &p, double *u) {
+    {
+        // the last step's stopping rule (gated: nothing to do once the loop has stopped)
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 0.0, 0.0, "k_finalize_pending");
+        launch_finalize_pending(p, p.stream);
+        if (int rc = check_launch("finalize")) return rc;
+    }
     p.gate = nullptr;
     {
         PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),

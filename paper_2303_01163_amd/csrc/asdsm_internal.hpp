@@ -72,7 +72,8 @@ struct IterState {
     int max_iter;
     int stag_window;
     int learned;       // learned proposals accepted (solves with a correction network)
-    int pad1;
+    int pending;       // 1: a skeleton-sparse step has left its residual partial sums for the
+                       // stopping rule, which the next step's first transform launch applies
     double rtol;
     double stag_eta;
     double rn_prev;    // ||r|| of the current iterate
@@ -118,6 +119,16 @@ enum ScalarSlot {
     kScalFlags = 13,   // non-finite flag accumulator
     kScalNoalloc = 14, // host mirror only: ||r||^2 of asdsm_residual_noalloc
     kScalCount = 16
+};
+
+// Arguments of a deferred stopping rule (a skeleton-sparse step's, applied by a later launch).
+struct FinArgs {
+    const double *partials;  // the step's per-block sums of ||r||^2 over owned skeleton points
+    int nblk;
+    double *scal;
+    IterState *stt;
+    double *hist, *step_hist;
+    const int *perm_table;
 };
 
 struct Plan {
@@ -187,6 +198,9 @@ struct Plan {
 
     // refinement kernels return early when *gate != 0 (nullptr outside the refinement loop)
     const int *gate = nullptr;
+    // a skeleton-sparse step is being launched whose first launch, a transform GEMM, applies the
+    // previous step's stopping rule (pending on the device); cleared by the launch that carries it
+    bool fin_carry = false;
 
     // captured refinement graph (two steps: u -> u2 -> u), rebuilt when the iterate pointer changes
     hipStream_t capture_stream = nullptr;

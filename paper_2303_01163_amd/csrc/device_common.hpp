@@ -62,4 +62,56 @@ __device__ __forceinline__ void block_partials(const double (&v)[NV], double *pa
         for (int q = 0; q < NV; ++q) partials[bid * NV + q] = tot[q];
 }
 
+// The stopping rule after one refinement step has produced r_{k+1} (thread 0; t = ||r_{k+1}||^2,
+// s_hat in scal): step count, the next step's axis permutation, the histories, stagnation, and
+// the done flag with the status.
+__device__ __forceinline__ void finalize_step(double t, double *scal, IterState *stt, double *hist,
+                                              double *step_hist, const int *perm_table) {
+    scal[kScalRnorm2] = t;
+    const double rn = sqrt(t);
+    const double bn = sqrt(scal[kScalBnorm2]);
+    const double shat = scal[kScalStep];
+    const int it = stt->it + 1;
+    stt->it = it;
+    // the next step's axis permutation (the table holds max_iter < kHistCap entries)
+    if (it < stt->max_iter)
+        for (int j = 0; j < kMaxD; ++j) stt->perm[j] = perm_table[kMaxD * it + j];
+    if (it < kHistCap) hist[it] = rn;
+    if (it - 1 < kHistCap) step_hist[it - 1] = shat;
+    if (!isfinite(rn) || !isfinite(shat)) {
+        stt->done = 1;
+        stt->status = ASDSM_E_NUMERIC;
+        return;
+    }
+    stt->stag = (rn > (1.0 - stt->stag_eta) * stt->rn_prev) ? stt->stag + 1 : 0;
+    stt->rn_prev = rn;
+    // a zero step leaves u unchanged and counts towards the window like any step that does
+    // not reduce ||r|| enough; the next step draws another cross-point choice
+    if (stt->stag_window > 0 && stt->stag >= stt->stag_window) {
+        stt->done = 1;
+        stt->status = ASDSM_STAGNATED;
+    } else if ((bn > 0.0 && rn <= stt->rtol * bn) || (bn == 0.0 && rn == 0.0)) {
+        stt->done = 1;
+        stt->status = ASDSM_OK;
+    } else if (it >= stt->max_iter) {
+        stt->done = 1;
+        stt->status = ASDSM_MAXITER;
+    }
+}
+
+// One 256-thread block applies the pending stopping rule, if any: the partial sums in the fixed
+// order of k_finalize, then finalize_step; clears the pending flag.  Does nothing once the loop
+// has stopped (live false) or when no step is pending.
+__device__ __forceinline__ void finalize_pending(const FinArgs &f, bool live) {
+    __shared__ double sh[4];
+    if (!live || !f.stt->pending) return;  // block-uniform
+    double a = 0.0;
+#pragma unroll 8
+    for (int b = threadIdx.x; b < f.nblk; b += 256) a += f.partials[b];
+    const double t = block_sum<256>(a, sh);
+    if (threadIdx.x != 0) return;
+    f.stt->pending = 0;
+    finalize_step(t, f.scal, f.stt, f.hist, f.step_hist, f.perm_table);
+}
+
 }  // namespace asdsm

@@ -41,7 +41,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     const int total = per_z * job.nbox * job.nbatch;
     const int per = (total + 7) / 8;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if ((int)(blockIdx.x >> 3) >= per || tile >= total) return;  // padding (block-uniform)
+    if ((int)(blockIdx.x >> 3) >= per || tile >= total) {  // padding (block-uniform)
+        // the block after the tiles: a pending stopping rule, concurrently with the tiles
+        if (job.fin_on && (int)blockIdx.x == 8 * per) finalize_pending(job.fin, live);
+        return;
+    }
     const int z = tile / per_z;
     const int rem = tile - z * per_z;
     const int by = rem / tx, bx = rem - by * tx;
@@ -197,7 +201,7 @@ template <int TM, int TN, int KC>
 static void launch_gemm_tile(const GemmJob &job, hipStream_t st) {
     const long long tx = (job.N + TN - 1) / TN, ty = (job.M + TM - 1) / TM;
     const long long total = tx * ty * job.nbox * job.nbatch;
-    const dim3 grid((unsigned)(8 * ((total + 7) / 8)));
+    const dim3 grid((unsigned)(8 * ((total + 7) / 8) + (job.fin_on ? 1 : 0)));
     const bool akf = job.sAk == 1;
     if (job.sBk == 1) {
         if (akf) ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, true, true>), grid, dim3(256), 0, st, job);

@@ -117,10 +117,12 @@ __global__ __launch_bounds__(256) void k_skel_dots(Geo g, SkelPtrs E, SkelPtrs E
 // projections of r onto the anisotropic meshes for the next error guess (steps 4.1/4.2: r
 // restricted to M_k is R_k itself), and partial sums of ||r||^2 over owned points.  The step
 // s = max(0, <r,q>/<q,q>) (step 6) is formed by every block from k_skel_dots' partial sums in one
-// fixed order, so all blocks agree bit for bit; block 0 records <r,q>, <q,q> and s in scal.
+// fixed order, so all blocks agree bit for bit; block 0 records <r,q>, <q,q> and s in scal and marks
+// the step's stopping rule pending (FinArgs, applied by the next launch that carries it).
 __global__ __launch_bounds__(256) void k_skel_update(Geo g, double *__restrict__ scal, const double *__restrict__ dots,
                                                      int ndots, SkelPtrs U, SkelPtrs E, SkelPtrs R, SkelPtrs Q,
-                                                     SkelPtrs G, double *partials, const int *gate) {
+                                                     SkelPtrs G, double *partials, IterState *stt,
+                                                     const int *gate) {
     // the stopping flag, the operands of this thread's first point and the partial sums are all
     // loaded before the first barrier; a gated launch writes nothing
     const bool live = !(gate && *gate);
@@ -150,6 +152,7 @@ __global__ __launch_bounds__(256) void k_skel_update(Geo g, double *__restrict__
                 scal[kScalRQ] = rq;
                 scal[kScalQQ] = qq;
                 scal[kScalStep] = sstep;
+                stt->pending = 1;  // the stopping rule on these partial sums is left to a later launch
             }
         }
         __syncthreads();
@@ -216,8 +219,28 @@ void launch_skel_update(const Plan &p, double *const *gather, hipStream_t st) {
     double *G[kMaxD] = {gather[1], gather[2], gather[4]};
     ASDSM_LAUNCH(k_skel_update, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, p.ws.scal, dots_partials(p),
                  3 * dots_tiles(p), skel_ptrs(p.ws.SU), skel_ptrs(E), skel_ptrs(p.ws.SR), skel_ptrs(p.ws.SQ),
-                 skel_ptrs(G), p.ws.partials, p.gate);
-    launch_finalize(p, 3 * tiles, kFinIter, 1, st);
+                 skel_ptrs(G), p.ws.partials, p.ws.state, p.gate);
+}
+
+// The stopping rule of the last skeleton-sparse step, left pending by k_skel_update.
+FinArgs pending_fin_args(const Plan &p) {
+    FinArgs f;
+    f.partials = p.ws.partials;
+    f.nblk = 3 * skel_tiles(p);
+    f.scal = p.ws.scal;
+    f.stt = p.ws.state;
+    f.hist = p.ws.hist;
+    f.step_hist = p.ws.step_hist;
+    f.perm_table = p.ws.perm_table;
+    return f;
+}
+
+__global__ __launch_bounds__(256) void k_finalize_pending(FinArgs f, const int *gate) {
+    finalize_pending(f, !(gate && *gate));
+}
+
+void launch_finalize_pending(const Plan &p, hipStream_t st) {
+    ASDSM_LAUNCH(k_finalize_pending, dim3(1), dim3(256), 0, st, pending_fin_args(p), p.gate);
 }
 
 }  // namespace asdsm

@@ -492,33 +492,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
             return;
         }
         // kFinIter: one refinement step has just produced u_{k+1} and r_{k+1}
-        const double shat = scal[kScalStep];
-        const int it = stt->it + 1;
-        stt->it = it;
-        // the next step's axis permutation (the table holds max_iter < kHistCap entries)
-        if (it < stt->max_iter)
-            for (int j = 0; j < kMaxD; ++j) stt->perm[j] = perm_table[kMaxD * it + j];
-        if (it < kHistCap) hist[it] = rn;
-        if (it - 1 < kHistCap) step_hist[it - 1] = shat;
-        if (!isfinite(rn) || !isfinite(shat)) {
-            stt->done = 1;
-            stt->status = ASDSM_E_NUMERIC;
-            return;
-        }
-        stt->stag = (rn > (1.0 - stt->stag_eta) * stt->rn_prev) ? stt->stag + 1 : 0;
-        stt->rn_prev = rn;
-        // a zero step leaves u unchanged and counts towards the window like any step that does
-        // not reduce ||r|| enough; the next step draws another cross-point choice
-        if (stt->stag_window > 0 && stt->stag >= stt->stag_window) {
-            stt->done = 1;
-            stt->status = ASDSM_STAGNATED;
-        } else if ((bn > 0.0 && rn <= stt->rtol * bn) || (bn == 0.0 && rn == 0.0)) {
-            stt->done = 1;
-            stt->status = ASDSM_OK;
-        } else if (it >= stt->max_iter) {
-            stt->done = 1;
-            stt->status = ASDSM_MAXITER;
-        }
+        finalize_step(t, scal, stt, hist, step_hist, perm_table);
     }
 }
 

@@ -82,6 +82,10 @@ struct GemmJob {
     // non-null for box b: each output tile's block stores the sum of squares of the C values it
     // wrote at norm_out[b][batch * tiles_per_batch + tile index] (the error-guess norms)
     double *norm_out[kMaxD];
+    // 1: one block beyond the tiles applies a pending stopping rule (finalize_pending) while the
+    // tiles run; set only on a launch that no other launch of its step precedes
+    int fin_on;
+    FinArgs fin;
 };
 int gemm_tiles_per_box(const GemmJob &job);  // output tiles of one box (all batches) as launched
 
@@ -187,5 +191,11 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
 void launch_skel_gather(const Plan &p, const double *u, hipStream_t st);
 void launch_skel_dots(const Plan &p, hipStream_t st);
 void launch_skel_update(const Plan &p, double *const *gather, hipStream_t st);
+// k_skel_update leaves the step's stopping rule pending on the device (IterState::pending): the next
+// step's first transform GEMM applies it in one extra block (GemmJob::fin_on), and
+// launch_finalize_pending applies it on its own (a no-op launch when nothing is pending) wherever
+// the loop state is read or no such GEMM follows.
+FinArgs pending_fin_args(const Plan &p);
+void launch_finalize_pending(const Plan &p, hipStream_t st);
 
 }  // namespace asdsm
