@@ -156,7 +156,42 @@ void carry_finalize(Plan &p, GemmJob &j) {
     if (!p.fin_carry) return;
     j.fin_on = 1;
     j.fin = pending_fin_args(p);
+    if (p.fin_res_nblk > 0) {  // the residual sums the fused update has just left
+        j.fin.partials = fused_res_partials(p);
+        j.fin.nblk = p.fin_res_nblk;
+    }
     p.fin_carry = false;
+    p.fin_res_nblk = 0;
+}
+
+// The previous step's skeleton update fused into this forward transform (p.upd_carry): B is the
+// current skeleton residual of each box's mesh instead of the gathered right-hand side, and the
+// launch after it carries the stopping rule on the residual sums it leaves.
+void carry_update(Plan &p, GemmJob &j, const int *slot) {
+    if (!p.upd_carry) return;
+    j.upd_on = 1;
+    UpdArgs &u = j.upd;
+    for (int b = 0; b < j.nbox; ++b) {
+        const int k = slot[b];
+        j.B[b] = sr_cur(p, k);
+        u.R[b] = sr_cur(p, k);
+        u.Rn[b] = sr_next(p, k);
+        u.Q[b] = p.ws.SQ[k];
+        u.E[b] = p.ws.SE[k];
+        u.U[b] = p.ws.SU[k];
+        u.mesh[b] = k;
+    }
+    u.nbox = j.nbox;
+    u.nub = upd_blocks_per_box(p.geo);
+    u.geo = p.geo;
+    u.dots = skel_dots_partials(p);
+    u.ndots = skel_dots_count(p);
+    u.scal = p.ws.scal;
+    u.stt = p.ws.state;
+    u.res_out = fused_res_partials(p);
+    p.upd_carry = false;
+    p.fin_carry = true;
+    p.fin_res_nblk = u.nbox * u.nub;
 }
 
 // Mode transform along canonical position q (a fine axis of extent N_f) of nb boxes of the shape m:
@@ -212,7 +247,7 @@ int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *
 // canonical layout.  norm_slot as in transform_position.
 int transform_pos0_modes_major(Plan &p, const MeshDesc &m, int nb, const double *const *in,
                                const double *const *T, double *const *out, bool fwd, int accum,
-                               const int *norm_slot) {
+                               const int *norm_slot, const int *slot) {
     GemmJob j{};
     j.nbox = nb;
     j.gate = p.gate;
@@ -247,6 +282,7 @@ int transform_pos0_modes_major(Plan &p, const MeshDesc &m, int nb, const double 
         for (int b = 0; b < nb; ++b) j.norm_out[b] = p.norm_partials + (size_t)norm_slot[b] * p.norm_nblk;
     }
     carry_finalize(p, j);
+    if (fwd && accum == 0) carry_update(p, j, slot);
     PhaseTimer t(p, ASDSM_PHASE_TRANSFORM, 1, gemm_flops(j), gemm_bytes(j), "k_gemm_f64");
     if (!launch_gemm(j, p.stream)) return fail(ASDSM_E_ARG, "unsupported transform operand layout");
     return check_launch("transform");
@@ -307,7 +343,7 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
                 }
             const bool norms = !fwd && t == 0 && fuse_norms;
             if (modes_major) {
-                if (int rc = transform_pos0_modes_major(p, m, ng, gs, gT, gd, fwd, acc, norms ? slot : nullptr))
+                if (int rc = transform_pos0_modes_major(p, m, ng, gs, gT, gd, fwd, acc, norms ? slot : nullptr, slot))
                     return rc;
             } else if (int rc = transform_position(p, m, q, ng, gs, gT, gd, acc, norms ? slot : nullptr)) {
                 return rc;
@@ -1243,21 +1279,29 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
 // in adjacent-layer mode), q = A e and <r, q>, <q, q> on the skeleton, and u += s e, r -= s q with
 // the gathers on the skeleton.  The fine u is rebuilt from the skeleton when the loop ends.
 int sparse_step(Plan &p) {
-    // The previous step's stopping rule is still pending on the device (k_skel_update leaves it).
-    // With line-axis meshes (FP64) this step's first launch is a transform GEMM, which applies it in
-    // one extra block beside its tiles; otherwise a launch of its own applies it first.
+    // With the update fused (p.upd_fused), the previous step's update and stopping rule are pending
+    // on the device (k_skel_dots leaves them): this step's forward transform applies the update and
+    // the backward transform, in one extra block, the stopping rule.  Otherwise the previous step's
+    // stopping rule alone is pending (k_skel_update leaves it): with line-axis meshes (FP64) this
+    // step's first launch is a transform GEMM, which applies it in one extra block beside its tiles;
+    // otherwise a launch of its own applies it first.
     const bool carry = p.line_aniso && !p.prec32;
-    if (carry) {
+    if (p.upd_fused) {
+        p.upd_carry = true;
+    } else if (carry) {
         p.fin_carry = true;
     } else {
         PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 0.0, 0.0, "k_finalize_pending");
         launch_finalize_pending(p, p.stream);
     }
     const int erc = error_guess(p);
-    const bool missed = p.fin_carry;
+    const bool missed = p.fin_carry || p.upd_carry;
     p.fin_carry = false;
+    p.upd_carry = false;
+    p.fin_res_nblk = 0;
     if (erc) return erc;
-    if (missed) return fail(ASDSM_E_UNSUPPORTED, "skeleton-sparse step: no transform carried the stopping rule");
+    if (missed) return fail(ASDSM_E_UNSUPPORTED, "skeleton-sparse step: no transform carried the update");
+    if (p.upd_fused) p.sr_par ^= 1;  // the forward transform has written the next residual
     const double skel = aniso_points(p);  // skeleton points counted once per mesh
     {
         PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p), 8.0 * (3.0 * skel), "hole filler (layer mode)");
@@ -1269,7 +1313,7 @@ int sparse_step(Plan &p) {
         launch_skel_dots(p, p.stream);
         if (int rc = check_launch("skeleton dots")) return rc;
     }
-    {
+    if (!p.upd_fused) {
         PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 5.0 * skel, 8.0 * 7.0 * skel, "k_skel_update");
         double *gat[kMaxMeshes];
         gather_pointers(p, gat);
@@ -1277,6 +1321,16 @@ int sparse_step(Plan &p) {
         if (int rc = check_launch("skeleton update")) return rc;
     }
     return ASDSM_OK;
+}
+
+// The skeleton-sparse update can ride on the next forward transform: d = 3 with every anisotropic
+// mesh solved by its line axis at canonical position 1 (one FP64 forward transform GEMM over the
+// three meshes, mode-major) and no refinement sweeps (which would re-read the right-hand side).
+bool sparse_fusable(const Plan &p) {
+    if (!p.sparse || p.d != 3 || !p.line_aniso || p.prec32) return false;
+    for (int k = 0; k < 3; ++k)
+        if (p.line_pos[1u << k] != 1 || p.sweeps[1u << k] != 0 || p.mesh[1u << k].nfine != 2) return false;
+    return true;
 }
 
 // A refinement step with a learned proposal (p.learn_net, bound to this plan, n = N_f): the
@@ -1528,6 +1582,11 @@ int begin_solve(Plan &p, const double *s, const double *g, double *u, const asds
     if (int rc = require_ws(p)) return rc;
     p.prec32 = (opt.precision == ASDSM_PREC_FP32) && p.fp32_ok;
     p.sparse = opt.skeleton != 0;
+    p.upd_fused = sparse_fusable(p);
+    p.upd_carry = false;
+    p.fin_carry = false;
+    p.fin_res_nblk = 0;
+    p.sr_par = 0;
     for (int q = 0; q < ASDSM_NPHASE; ++q) {
         p.phase_ms[q] = 0.0;
         p.phase_launches[q] = 0;
@@ -1601,6 +1660,14 @@ int begin_solve(Plan &p, const double *s, const double *g, double *u, const asds
 // fine residual (so that r and the gathers describe the returned u).  Not gated: it runs whatever
 // the stopping rule did.
 int finish_sparse(Plan &p, double *u) {
+    if (p.upd_fused) {
+        // the last step's update, still pending (gated: nothing to do once the loop has stopped)
+        PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 0.0, 0.0, "k_skel_update");
+        double *gat[kMaxMeshes];
+        gather_pointers(p, gat);
+        launch_skel_update(p, gat, p.stream);
+        if (int rc = check_launch("skeleton update")) return rc;
+    }
     {
         // the last step's stopping rule (gated: nothing to do once the loop has stopped)
         PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 0.0, 0.0, "k_finalize_pending");

@@ -99,6 +99,10 @@ struct Workspace {
     // skeleton-sparse refinement (d = 3), per anisotropic mesh in its canonical layout: u, r and
     // q = A e on the skeleton, and the error guess on the hole layers next to each plane (2 sides)
     double *SU[kMaxD] = {}, *SR[kMaxD] = {}, *SQ[kMaxD] = {}, *EA[kMaxD] = {};
+    // with the update fused into the next forward transform: the second residual buffer (the
+    // transform reads one and writes the other) and the merged error guess, which must outlive the
+    // transform's output in Y
+    double *SR2[kMaxD] = {}, *SE[kMaxD] = {};
     IterState *state = nullptr;  // refinement-loop state
     double *hist = nullptr;      // ||r_k||, k = 0..it
     double *step_hist = nullptr; // s_hat_k
@@ -201,6 +205,14 @@ struct Plan {
     // a skeleton-sparse step is being launched whose first launch, a transform GEMM, applies the
     // previous step's stopping rule (pending on the device); cleared by the launch that carries it
     bool fin_carry = false;
+    // skeleton-sparse loop with the update fused into the next step's forward transform (set per
+    // solve): the merged error guess lives in SE, the residual alternates between SR (sr_par 0) and
+    // SR2 (1); upd_carry marks the step whose forward transform is still to be launched, and
+    // fin_res_nblk > 0 the residual partial sums that the carried stopping rule then reads
+    bool upd_fused = false;
+    bool upd_carry = false;
+    int sr_par = 0;
+    int fin_res_nblk = 0;
 
     // captured refinement graph (two steps: u -> u2 -> u), rebuilt when the iterate pointer changes
     hipStream_t capture_stream = nullptr;
@@ -244,6 +256,14 @@ struct Plan {
     double phase_flops[ASDSM_NPHASE] = {};
     double phase_bytes[ASDSM_NPHASE] = {};
 };
+
+// the merged skeleton values of anisotropic mesh k (the merge's output)
+inline double *merged_buf(const Plan &p, int k) { return p.upd_fused ? p.ws.SE[k] : p.ws.Y[1u << k]; }
+// the skeleton residual of anisotropic mesh k that the next operation reads
+inline double *sr_cur(const Plan &p, int k) { return p.sr_par ? p.ws.SR2[k] : p.ws.SR[k]; }
+inline double *sr_next(const Plan &p, int k) { return p.sr_par ? p.ws.SR[k] : p.ws.SR2[k]; }
+// the residual partial sums of the fused update (behind the other users of the partials area)
+inline double *fused_res_partials(const Plan &p) { return p.ws.partials + 3 * (size_t)p.max_blocks; }
 
 // ---- host plan construction (plan.cpp)
 int build_plan(Plan &p, int d, const double *alpha, const double *beta, int level,

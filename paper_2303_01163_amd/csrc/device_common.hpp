@@ -34,6 +34,31 @@ __device__ __forceinline__ long long canon_offset(const MeshDesc &m, const int *
     return off;
 }
 
+// A flag read with a vector load (device-scope relaxed atomic): the kernels that test it late issue
+// it with their operand loads; a plain load of a uniform address becomes a scalar load, which is
+// waited for together with the kernel arguments, before any other load is issued.
+__device__ __forceinline__ int flag_load(const int *f) {
+    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The stopping flag of the refinement loop (nullptr: none).  No branch on the pointer either: a
+// null gate reads a zero of its own, so the test of the value can wait until it is needed.
+static __device__ int g_gate_open = 0;
+__device__ __forceinline__ int gate_value(const int *gate) { return flag_load(gate ? gate : &g_gate_open); }
+__device__ __forceinline__ bool gate_open(const int *gate) { return gate_value(gate) == 0; }
+// The test of a flag value where it stands: the compiler would otherwise place the comparison (and
+// the wait for the load) where the value was loaded, ahead of the kernel's other loads.
+__device__ __forceinline__ bool flag_clear(int v) {
+    asm volatile("" : "+v"(v));
+    return v == 0;
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads in flight stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Wave64 + LDS tree sum with a fixed order (deterministic for a fixed launch shape).
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double *sh) {

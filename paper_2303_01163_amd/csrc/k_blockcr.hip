@@ -221,7 +221,7 @@ constexpr int kCrMaxPerThread = 16;
 template <int NB, int RB>
 __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
     // the stopping flag is read with the first loads and tested once they have arrived
-    const bool live = !(job.gate && *job.gate);
+    const int gv = gate_value(job.gate);
     extern __shared__ double lds[];
     const int box = blockIdx.y;
     const CrBox &bx = job.box[box];
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
         D[(ml * N + i) * NB + c] = bx.src[mbase[ml] + i * sw + c * sc];
     }
     __syncthreads();
-    if (!live) return;  // block-uniform
+    if (!flag_clear(gv)) return;  // block-uniform
     const int E = 256 / (tmw * RB);
     const int ml = tid / (RB * E), rem = tid % (RB * E), r = rem % RB, eg = rem / RB;
     const bool act = ml < tm && r < NB;

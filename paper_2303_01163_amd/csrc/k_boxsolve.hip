@@ -10,6 +10,7 @@
 //     inverse is precomputed per mode on the host (LU with partial pivoting) and applied here.
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "skel_common.hpp"
 
 namespace asdsm {
 
@@ -27,11 +28,101 @@ namespace asdsm {
 //   A: row l%16, k l/16;  B: k l/16, col l%16;  D[v]: row l/16 + 4v, col l%16.
 // ---------------------------------------------------------------------------------------------
 constexpr int kGemmPrefetch = 4;  // chunks whose loads k_gemm_f64 issues together
+constexpr int kUpdPoints = 4;     // skeleton points per thread of an update block
 
-template <int TM, int TN, int KC, bool BKF, bool AKF>
+// The line search's partial sums of the pending update, (<r,q>, <q,q>) pairs: thread t holds pairs t
+// and t + 256 (zero beyond u.ndots <= 512), loaded at the start of the block so that they arrive
+// with its other operands.
+struct UpdDots {
+    double v[4];
+};
+__device__ __forceinline__ UpdDots upd_load_dots(const UpdArgs &u) {
+    UpdDots d;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int b = (int)threadIdx.x + 256 * it;
+        const int bi = b < u.ndots ? b : 0;
+        d.v[2 * it] = u.dots[2 * bi];
+        d.v[2 * it + 1] = u.dots[2 * bi + 1];
+    }
+    return d;
+}
+
+// The step s = max(0, <r,q>/<q,q>), formed by every block from the same partial sums in the same
+// order as k_skel_update (block_sum's: wave shuffles, then the waves in turn; all blocks agree bit
+// for bit), then the flags (gv the stopping flag, pv the pending flag, both loaded earlier); block 0
+// records <r,q>, <q,q> and s.  Its barriers order LDS only, so the block's operand loads stay in
+// flight while the step is formed.
+__device__ __forceinline__ void upd_step(const UpdArgs &u, const UpdDots &d, int gv, int pv, double &s, bool &pend,
+                                         bool &live) {
+    __shared__ double shu[8], s_sh;
+    // the partial sums are taken here, not where they were loaded (the compiler would otherwise
+    // wait for them there, before the block's other loads are issued)
+    double v[4] = {d.v[0], d.v[1], d.v[2], d.v[3]};
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const bool in = (int)threadIdx.x + 256 * it < u.ndots;
+        a0 += in ? v[2 * it] : 0.0;
+        a1 += in ? v[2 * it + 1] : 0.0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a0 += __shfl_down(a0, off, 64);
+        a1 += __shfl_down(a1, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        shu[wid] = a0;
+        shu[4 + wid] = a1;
+    }
+    lds_barrier();
+    live = flag_clear(gv);
+    pend = live && !flag_clear(pv);
+    if (threadIdx.x == 0) {
+        double rq = 0.0, qq = 0.0;
+        for (int w = 0; w < 4; ++w) rq += shu[w];
+        for (int w = 0; w < 4; ++w) qq += shu[4 + w];
+        const double st = (qq > 0.0) ? rq / qq : 0.0;
+        s_sh = (st > 0.0) ? st : 0.0;
+        if (pend && blockIdx.x == 0) {
+            u.scal[kScalRQ] = rq;
+            u.scal[kScalQQ] = qq;
+            u.scal[kScalStep] = s_sh;
+        }
+    }
+    lds_barrier();
+    s = s_sh;
+}
+
+// Update block xb of the fused launch (u.nub per box, box-major): the skeleton update on its
+// points (skel_update_points) and, while a step is pending, its sum of r_next^2 at res_out[xb].
+__device__ __forceinline__ void upd_block(const UpdArgs &u, int xb, int gv) {
+    const int box = xb / u.nub, blk = xb - box * u.nub;
+    if (box >= u.nbox) return;  // block-uniform
+    const int pv = flag_load(&u.stt->pending);
+    const UpdDots dd = upd_load_dots(u);
+    const double *R = u.R[box];
+    double *Rn = u.Rn[box];
+    const double *Q = u.Q[box];
+    const double *E = u.E[box];
+    double *U = u.U[box];
+    auto ready = [&](double &s, bool &pend, bool &live) { upd_step(u, dd, gv, pv, s, pend, live); };
+    bool pend = false, live = false;
+    double acc = 0.0;
+    skel_update_points<kUpdPoints>(u.geo, u.mesh[box], blk, u.nub, R, Rn, Q, E, U, ready, pend, live, acc);
+    if (pend && live) {  // block-uniform
+        __shared__ double shr[4];
+        const double tot = block_sum<256>(acc, shr);
+        if (threadIdx.x == 0) u.res_out[xb] = tot;
+    }
+}
+
+template <int TM, int TN, int KC, bool BKF, bool AKF, bool UPD = false>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     // the stopping flag is read with the first panel loads and tested once they have arrived
-    const bool live = !(job.gate && *job.gate);
+    const int gv = gate_value(job.gate);
+    bool live = true;
     constexpr int MI = TM / 32, NI = TN / 32;            // MFMA tiles per wave along m and n
     constexpr int LA = TM * KC / 256, LB = KC * TN / 256;  // panel elements per thread
     __shared__ double sA[2][TM][KC + 1];
@@ -42,8 +133,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     const int per = (total + 7) / 8;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if ((int)(blockIdx.x >> 3) >= per || tile >= total) {  // padding (block-uniform)
-        // the block after the tiles: a pending stopping rule, concurrently with the tiles
-        if (job.fin_on && (int)blockIdx.x == 8 * per) finalize_pending(job.fin, live);
+        // the blocks after the tiles, concurrently with them: the skeleton update (UPD), or a
+        // pending stopping rule
+        const int xb = (int)blockIdx.x - 8 * per;
+        if (UPD && xb >= 0) upd_block(job.upd, xb, gv);
+        else if (job.fin_on && xb == 0) finalize_pending(job.fin, gate_open(job.gate));
         return;
     }
     const int z = tile / per_z;
@@ -63,6 +157,27 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
     const int bn0 = BKF ? (t / KC) : (t % TN), bk0 = BKF ? (t % KC) : (t / TN);
     double ra[LA], rb[LB];
     const int nch = (job.K + KC - 1) / KC;
+    // fused skeleton update (UPD): the pending flag is read with the operands (nothing else in this
+    // launch writes it), and q is loaded beside each B element (the current residual r)
+    const int pv = UPD ? flag_load(&job.upd.stt->pending) : 0;
+    UpdDots dd{};
+    if (UPD) dd = upd_load_dots(job.upd);
+    bool pend = false;
+    const double *__restrict__ uQ = UPD ? job.upd.Q[box] : nullptr;
+    double qb[LB];
+    double s_upd = 0.0;
+    // B element j of chunk c becomes r - s q (r while nothing is pending)
+    auto stage_b = [&](int c, int j, double r, double q) -> double {
+        const int n = n0 + (BKF ? bn0 + (256 / KC) * j : bn0);
+        const int kb = c * KC + (BKF ? bk0 : bk0 + (256 / TN) * j);
+        const bool in = n < job.N && kb < job.K;
+        const double b = pend ? r - s_upd * q : r;
+        return in ? b : 0.0;
+    };
+    // the step and the flags, once the operands are in flight
+    auto form_step = [&]() {
+        upd_step(job.upd, dd, gv, pv, s_upd, pend, live);
+    };
     auto gload = [&](int c) {
         const int k0 = c * KC;
 #pragma unroll
@@ -75,10 +190,17 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
         for (int j = 0; j < LB; ++j) {
             const int n = n0 + (BKF ? bn0 + (256 / KC) * j : bn0);
             const int kb = k0 + (BKF ? bk0 : bk0 + (256 / TN) * j);
-            rb[j] = (n < job.N && kb < job.K) ? B[kb * sBk + n * sBn] : 0.0;
+            const bool in = n < job.N && kb < job.K;
+            const int bi = in ? kb * sBk + n * sBn : 0;
+            rb[j] = in ? B[bi] : 0.0;
+            if (UPD) qb[j] = uQ[bi];
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, int c) {
+        if (UPD && c >= 0) {  // c < 0: already staged
+#pragma unroll
+            for (int j = 0; j < LB; ++j) rb[j] = stage_b(c, j, rb[j], qb[j]);
+        }
 #pragma unroll
         for (int j = 0; j < LA; ++j) {
             if (AKF)
@@ -122,6 +244,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
         // (every lane loads every element, an out-of-range one from the operand's first element,
         // and zeroes it: straight-line loads, all in flight together)
         double pa[kGemmPrefetch][LA], pb[kGemmPrefetch][LB];
+        double pq[UPD ? kGemmPrefetch : 1][LB];
 #pragma unroll
         for (int c = 0; c < kGemmPrefetch; ++c) {
             const int k0 = c * KC;
@@ -138,19 +261,30 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
                 const int nn = n0 + (BKF ? bn0 + (256 / KC) * j : bn0);
                 const int kb = k0 + (BKF ? bk0 : bk0 + (256 / TN) * j);
                 const bool in = nn < job.N && kb < job.K;
-                const double x = B[in ? kb * sBk + nn * sBn : 0];
+                const int bi = in ? kb * sBk + nn * sBn : 0;
+                const double x = B[bi];
                 pb[c][j] = in ? x : 0.0;
+                if (UPD) pq[c][j] = uQ[bi];
             }
+        }
+        if (UPD) {
+            form_step();
+#pragma unroll
+            for (int c = 0; c < kGemmPrefetch; ++c)
+#pragma unroll
+                for (int j = 0; j < LB; ++j)
+                    if (c < nch) pb[c][j] = stage_b(c, j, pb[c][j], pq[c][j]);
         }
         auto put = [&](int c) {
 #pragma unroll
             for (int j = 0; j < LA; ++j) ra[j] = pa[c][j];
 #pragma unroll
             for (int j = 0; j < LB; ++j) rb[j] = pb[c][j];
-            lstore(c & 1);
+            lstore(c & 1, -1);
         };
         put(0);
         __syncthreads();
+        if (!UPD) live = flag_clear(gv);
         if (!live) return;  // block-uniform
 #pragma unroll
         for (int c = 0; c < kGemmPrefetch; ++c) {
@@ -162,14 +296,16 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
         }
     } else {
         gload(0);
-        lstore(0);
+        if (UPD) form_step();
+        lstore(0, 0);
         __syncthreads();
+        if (!UPD) live = flag_clear(gv);
         if (!live) return;  // block-uniform
         for (int c = 0; c < nch; ++c) {
             const int buf = c & 1;
             if (c + 1 < nch) gload(c + 1);
             mma(buf);
-            if (c + 1 < nch) lstore(buf ^ 1);
+            if (c + 1 < nch) lstore(buf ^ 1, c + 1);
             __syncthreads();
         }
     }
@@ -201,8 +337,13 @@ template <int TM, int TN, int KC>
 static void launch_gemm_tile(const GemmJob &job, hipStream_t st) {
     const long long tx = (job.N + TN - 1) / TN, ty = (job.M + TM - 1) / TM;
     const long long total = tx * ty * job.nbox * job.nbatch;
-    const dim3 grid((unsigned)(8 * ((total + 7) / 8) + (job.fin_on ? 1 : 0)));
+    const long long extra = job.upd_on ? (long long)job.upd.nbox * job.upd.nub : (job.fin_on ? 1 : 0);
+    const dim3 grid((unsigned)(8 * ((total + 7) / 8) + extra));
     const bool akf = job.sAk == 1;
+    if (job.upd_on) {  // checked by launch_gemm: A and B k-fast
+        ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, true, true, true>), grid, dim3(256), 0, st, job);
+        return;
+    }
     if (job.sBk == 1) {
         if (akf) ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, true, true>), grid, dim3(256), 0, st, job);
         else ASDSM_LAUNCH((k_gemm_f64<TM, TN, KC, true, false>), grid, dim3(256), 0, st, job);
@@ -244,9 +385,21 @@ int gemm_tiles_per_box(const GemmJob &job) {
     return ((job.N + tn - 1) / tn) * ((job.M + tm - 1) / tm) * job.nbatch;
 }
 
+int upd_blocks_per_box(const Geo &g) {
+    const long long per = (long long)g.Nc * g.Nf * g.Nf;
+    return (int)((per + 256 * kUpdPoints - 1) / (256 * kUpdPoints));
+}
+
 bool launch_gemm(const GemmJob &job, hipStream_t st) {
     // operand layouts of the mode transforms: A k-fast or m-fast, B k-fast or n-fast
     if ((job.sAk != 1 && job.sAi != 1) || (job.sBk != 1 && job.sBn != 1)) return false;
+    // the fused skeleton update: k-fast operands, one batch, no accumulation or norms, no carried
+    // stopping rule (that reads what this launch writes)
+    if (job.upd_on && (job.sAk != 1 || job.sBk != 1 || job.nbatch != 1 || job.accum || job.fin_on ||
+                       job.upd.ndots > 512))
+        return false;
+    for (int b = 0; b < job.nbox && job.upd_on; ++b)
+        if (job.norm_out[b]) return false;
     const int tile = gemm_pick_tile(job);
     switch (tile) {
         case kTile64x32: launch_gemm_tile<64, 32, 32>(job, st); break;

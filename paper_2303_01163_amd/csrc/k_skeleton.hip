@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_crosspoints(Geo g, SkelArgs a) {
 __global__ __launch_bounds__(256) void k_crosspoints3(Geo g, SkelArgs a, int nrowblk) {
     // the stopping flag is read with the first loads and tested once they have arrived; a gated
     // launch writes nothing
-    const bool live = !(a.gate && *a.gate);
+    const int gv = gate_value(a.gate);
     __shared__ double row[1024];  // N_f <= 1023
     const int k = blockIdx.y;
     const int Nf = g.Nf, Nc = g.Nc, n = g.n;
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_crosspoints3(Geo g, SkelArgs a, int nro
         if (w < nA) pre[0] = fetch((int)((w / Nc) % Nf), ((int)(w % Nc) + 1) * n - 1, (int)(w / ((long long)Nc * Nf)));
     }
     const XChoice ch = load_choice(a, g);
-    if (!live) return;  // block-uniform
+    if (!flag_clear(gv)) return;  // block-uniform
     const double scale_k = (a.mode == 0) ? 1.0 : inv_of(ch, k);
     if (partA) {
         bool first = true;
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256) void k_merge(Geo g, SkelArgs a) {
 template <int NC>
 __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
     // the stopping flag is read with the first loads and tested once they have arrived
-    const bool live = !(a.gate && *a.gate);
+    const int gv = gate_value(a.gate);
     constexpr int RB = 8;
     constexpr int NA = NC * (RB + NC);  // A: [c_a][the 8 rows, then the N_c coarse rows]
     constexpr int ND = NA + 64 * NC;    // then B: [i_a][c_b]
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(256) void k_merge3(Geo g, SkelArgs a) {
         if (err) cand[h] = cross_candidates(a, g, p, S);  // launch-uniform; used at cross points only
     }
     const XChoice ch = load_choice(a, g);
-    if (!live) return;  // block-uniform
+    if (!flag_clear(gv)) return;  // block-uniform
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
         const int q = t + 256 * j;
@@ -525,7 +525,7 @@ static SkelArgs skel_args(const Plan &p, int mode, const double *const *res) {
     }
     for (int k = 0; k < kMaxD; ++k) {
         a.lines[k] = (k < p.d) ? p.ws.lines[k] : nullptr;
-        a.skel[k] = (k < p.d) ? p.ws.Y[1u << k] : nullptr;
+        a.skel[k] = (k < p.d) ? merged_buf(p, k) : nullptr;
     }
     a.state = p.ws.state;
     a.gate = p.gate;
@@ -1050,13 +1050,6 @@ constexpr int kFMat = 16 * 17;  // one transform matrix in LDS: T[m][k] at m * 1
 
 __host__ __device__ constexpr int fstride(int j) { return j == 0 ? 1 : (j == 1 ? kFS1 : kFS2); }
 
-// Workgroup barrier that orders LDS accesses only: global loads in flight stay in flight.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // In-slab transform along axis J of the slabs of one wave (L the slab axis, P the third axis):
 // A rows l_P, K and the result columns along J; B[k][m] = T[m][k] from the LDS copy of T.  The
 // four slabs' accumulator chains are interleaved.  The slabs are private to the wave, whose LDS
@@ -1119,7 +1112,7 @@ __device__ __forceinline__ double hole_rhs(const Geo &g, const double *fa, int l
 template <int L, bool LAYERS>
 __global__ __launch_bounds__(256, 2) void k_filler_mfma3(Geo g, FillArgs a) {
     // the stopping flag is read with the other loads and tested after the first barrier
-    const bool live = !(a.gate && *a.gate);
+    const int gv = gate_value(a.gate);
     __shared__ double buf[kFBuf];
     __shared__ double fa[6 * 256];
     __shared__ double mats[4 * kFMat];  // W_j0, W_j1, V_j1, V_j0
@@ -1211,7 +1204,7 @@ __global__ __launch_bounds__(256, 2) void k_filler_mfma3(Geo g, FillArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) mats[q * kFMat + (tid >> 4) * 17 + (tid & 15)] = min_ ? mv[q] : 0.0;
     lds_barrier();
-    if (!live) return;  // block-uniform
+    if (!flag_clear(gv)) return;  // block-uniform
     if (la < nh && lb < nh) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
@@ -1297,7 +1290,7 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
     FillArgs a;
     const int d = p.d, nh = p.n - 1;
     for (int j = 0; j < kMaxD; ++j) {
-        a.skel[j] = (j < d) ? (skel ? skel[j] : p.ws.Y[1u << j]) : nullptr;
+        a.skel[j] = (j < d) ? (skel ? skel[j] : merged_buf(p, j)) : nullptr;
         a.adj[j] = (j < d && adj_only) ? p.ws.EA[j] : nullptr;
         a.mk[j] = (j < d) ? p.mesh[1u << j] : MeshDesc();
         a.W[j] = (j < d) ? p.dWh[j] : nullptr;

@@ -14,22 +14,9 @@
 
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "skel_common.hpp"
 
 namespace asdsm {
-
-// Fine index and ownership of point idx of M_K (N_c N_f^2 < 2^31 points: 32-bit arithmetic).
-template <int K>
-__device__ __forceinline__ void skel_point(const Geo &g, int idx, int &x0, int &x1, int &x2, bool &owner) {
-    const int Nf = g.Nf, n = g.n;
-    const unsigned row = (unsigned)idx / (unsigned)Nf;
-    const int a = idx - (int)row * Nf;
-    const int c = (int)(row / (unsigned)Nf);
-    const int b = (int)row - c * Nf;
-    const int cf = (c + 1) * n - 1;
-    if (K == 0) { x0 = cf; x1 = a; x2 = b; owner = true; }
-    if (K == 1) { x0 = a; x1 = cf; x2 = b; owner = !on_coarse(a, n); }
-    if (K == 2) { x0 = a; x1 = b; x2 = cf; owner = !on_coarse(a, n) && !on_coarse(b, n); }
-}
 
 struct SkelPtrs {
     double *p[kMaxD];
@@ -63,7 +50,7 @@ __global__ __launch_bounds__(256) void k_skel_gather(Geo g, const double *__rest
 template <int K>
 __device__ __forceinline__ void skel_dots_mesh(const Geo &g, const double *__restrict__ E, const double *__restrict__ EA,
                                                const double *__restrict__ R, double *__restrict__ Q, double &rq,
-                                               double &qq, int tile, int ntile, bool live) {
+                                               double &qq, int tile, int ntile, int gv) {
     const int Nf = g.Nf;
     const int per = g.Nc * Nf * Nf;
     const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
@@ -91,7 +78,7 @@ __device__ __forceinline__ void skel_dots_mesh(const Geo &g, const double *__res
             q += g.fine[1].a * bm; q += g.fine[1].c * bp;
             q += g.fine[2].a * cm; q += g.fine[2].c * cp;
         }
-        if (live) Q[idx] = q;
+        if (flag_clear(gv)) Q[idx] = q;  // the stopping flag, tested after the first loads
         if (own) {
             rq += R[idx] * q;
             qq += q * q;
@@ -99,18 +86,22 @@ __device__ __forceinline__ void skel_dots_mesh(const Geo &g, const double *__res
     }
 }
 
-// Grid (tiles, 3): blockIdx.y selects the mesh.  Partial sums per block at blockIdx.x + tiles * y.
+// Grid (tiles, 3): blockIdx.y selects the mesh.  Partial sums per block at blockIdx.x + tiles * y;
+// mark (non-null): the update and stopping rule of this step are left pending.
 __global__ __launch_bounds__(256) void k_skel_dots(Geo g, SkelPtrs E, SkelPtrs EA, SkelPtrs R, SkelPtrs Q,
-                                                   double *partials, const int *gate) {
+                                                   double *partials, IterState *mark, const int *gate) {
     // the stopping flag is read with the operands; a gated launch writes nothing
-    const bool live = !(gate && *gate);
+    const int gv = gate_value(gate);
     double rq = 0.0, qq = 0.0;
     const int k = blockIdx.y;
-    if (k == 0) skel_dots_mesh<0>(g, E.p[0], EA.p[0], R.p[0], Q.p[0], rq, qq, blockIdx.x, gridDim.x, live);
-    else if (k == 1) skel_dots_mesh<1>(g, E.p[1], EA.p[1], R.p[1], Q.p[1], rq, qq, blockIdx.x, gridDim.x, live);
-    else skel_dots_mesh<2>(g, E.p[2], EA.p[2], R.p[2], Q.p[2], rq, qq, blockIdx.x, gridDim.x, live);
+    if (k == 0) skel_dots_mesh<0>(g, E.p[0], EA.p[0], R.p[0], Q.p[0], rq, qq, blockIdx.x, gridDim.x, gv);
+    else if (k == 1) skel_dots_mesh<1>(g, E.p[1], EA.p[1], R.p[1], Q.p[1], rq, qq, blockIdx.x, gridDim.x, gv);
+    else skel_dots_mesh<2>(g, E.p[2], EA.p[2], R.p[2], Q.p[2], rq, qq, blockIdx.x, gridDim.x, gv);
+    const bool live = flag_clear(gv);
     double vals[2] = {rq, qq};
     if (live) block_partials<256, 2>(vals, partials, blockIdx.x + (size_t)gridDim.x * blockIdx.y);  // block-uniform
+    // the update this line search defines is left to the next forward transform (mark non-null)
+    if (mark && live && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) mark->pending = 1;
 }
 
 // u += s e and r -= s q on the skeleton (Algorithm 4 step 7 and the residual it implies), the
@@ -125,7 +116,7 @@ __global__ __launch_bounds__(256) void k_skel_update(Geo g, double *__restrict__
                                                      const int *gate) {
     // the stopping flag, the operands of this thread's first point and the partial sums are all
     // loaded before the first barrier; a gated launch writes nothing
-    const bool live = !(gate && *gate);
+    const int gv = gate_value(gate);
     const int per = g.Nc * g.Nf * g.Nf;
     const int k = blockIdx.y;
     double *__restrict__ Uk = (k == 0) ? U.p[0] : (k == 1) ? U.p[1] : U.p[2];
@@ -137,6 +128,7 @@ __global__ __launch_bounds__(256) void k_skel_update(Geo g, double *__restrict__
     const int i0 = idx0 < per ? idx0 : 0;
     const double u0 = Uk[i0], e0 = Ek[i0], r0 = Rk[i0], q0 = Qk[i0];
     __shared__ double sh[4], sstep;
+    bool live;
     {
         double a0 = 0.0, a1 = 0.0;
         for (int b = threadIdx.x; b < ndots; b += 256) {
@@ -145,6 +137,7 @@ __global__ __launch_bounds__(256) void k_skel_update(Geo g, double *__restrict__
         }
         const double rq = block_sum<256>(a0, sh);
         const double qq = block_sum<256>(a1, sh);
+        live = flag_clear(gv);
         if (threadIdx.x == 0) {
             const double st = (qq > 0.0) ? rq / qq : 0.0;
             sstep = (st > 0.0) ? st : 0.0;
@@ -200,6 +193,9 @@ static int dots_tiles(const Plan &p) { return std::min(skel_tiles(p), 128); }
 // the dots partials sit behind the update's own partials (one value per block) in the workspace
 static double *dots_partials(const Plan &p) { return p.ws.partials + 2 * (size_t)p.max_blocks; }
 
+const double *skel_dots_partials(const Plan &p) { return dots_partials(p); }
+int skel_dots_count(const Plan &p) { return 3 * dots_tiles(p); }
+
 void launch_skel_gather(const Plan &p, const double *u, hipStream_t st) {
     const int tiles = skel_tiles(p);
     ASDSM_LAUNCH(k_skel_gather, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, u, p.ws.r, skel_ptrs(p.ws.SU),
@@ -208,17 +204,19 @@ void launch_skel_gather(const Plan &p, const double *u, hipStream_t st) {
 
 void launch_skel_dots(const Plan &p, hipStream_t st) {
     const int tiles = dots_tiles(p);
-    double *E[kMaxD] = {p.ws.Y[1], p.ws.Y[2], p.ws.Y[4]};
+    double *E[kMaxD] = {merged_buf(p, 0), merged_buf(p, 1), merged_buf(p, 2)};
+    double *R[kMaxD] = {sr_cur(p, 0), sr_cur(p, 1), sr_cur(p, 2)};
     ASDSM_LAUNCH(k_skel_dots, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, skel_ptrs(E), skel_ptrs(p.ws.EA),
-                 skel_ptrs(p.ws.SR), skel_ptrs(p.ws.SQ), dots_partials(p), p.gate);
+                 skel_ptrs(R), skel_ptrs(p.ws.SQ), dots_partials(p), p.upd_fused ? p.ws.state : nullptr, p.gate);
 }
 
 void launch_skel_update(const Plan &p, double *const *gather, hipStream_t st) {
     const int tiles = skel_tiles(p);
-    double *E[kMaxD] = {p.ws.Y[1], p.ws.Y[2], p.ws.Y[4]};
+    double *E[kMaxD] = {merged_buf(p, 0), merged_buf(p, 1), merged_buf(p, 2)};
+    double *R[kMaxD] = {sr_cur(p, 0), sr_cur(p, 1), sr_cur(p, 2)};
     double *G[kMaxD] = {gather[1], gather[2], gather[4]};
     ASDSM_LAUNCH(k_skel_update, dim3((unsigned)tiles, 3), dim3(256), 0, st, p.geo, p.ws.scal, dots_partials(p),
-                 3 * dots_tiles(p), skel_ptrs(p.ws.SU), skel_ptrs(E), skel_ptrs(p.ws.SR), skel_ptrs(p.ws.SQ),
+                 3 * dots_tiles(p), skel_ptrs(p.ws.SU), skel_ptrs(E), skel_ptrs(R), skel_ptrs(p.ws.SQ),
                  skel_ptrs(G), p.ws.partials, p.ws.state, p.gate);
 }
 

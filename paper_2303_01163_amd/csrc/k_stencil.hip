@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
                                                   double *hist, double *step_hist, const int *perm_table,
                                                   const int *gate) {
     // the stopping flag is read with the partial sums and tested before anything is written
-    const bool live = !(gate && *gate);
+    const int gv = gate_value(gate);
     __shared__ double sh[4];
     const int tid = threadIdx.x;
     if (mode == kFinDots) {
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
         }
         const double rq = block_sum<256>(a0, sh);
         const double qq = block_sum<256>(a1, sh);
-        if (tid == 0 && live) {
+        if (tid == 0 && flag_clear(gv)) {
             scal[kScalRQ] = rq;
             scal[kScalQQ] = qq;
             const double st = (qq > 0.0) ? rq / qq : 0.0;
@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
 #pragma unroll 8
             for (int b = tid; b < nblk; b += 256) a += partials[(size_t)k * nblk + b];
             const double t = block_sum<256>(a, sh);
-            if (tid == 0 && live) {
+            if (tid == 0 && flag_clear(gv)) {
                 scal[kScalEnorm2 + k] = t;
                 scal[kScalInvNorm + k] = (t > 0.0) ? 1.0 / sqrt(t) : 1.0;
             }
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
 #pragma unroll 8
         for (int b = tid; b < nblk; b += 256) a += partials[b];
         const double t = block_sum<256>(a, sh);
-        if (tid != 0 || !live) return;
+        if (tid != 0 || !flag_clear(gv)) return;
         if (mode == kFinBnorm) {
             scal[kScalBnorm2] = t;
             return;

@@ -67,6 +67,31 @@ struct BoxPtrs {
     double *p[kMaxD];
 };
 
+// The skeleton-sparse update of the previous step (u += s e, r -= s q on the skeleton) carried by
+// the forward transform of the next error guess, whose B operand is that residual (mesh b's
+// canonical layout, B[k, n] at k + N_f n: k the first fine coordinate, n = second + N_f plane).
+// While a step is pending (IterState::pending) every block forms s from the line search's partial
+// sums; the tiles stage r - s q as their operand, and nbox * nub update blocks after the tiles (on
+// the CUs the tiles leave free) store r - s q as the next residual, add s e to u and leave their
+// sums of (r - s q)^2 over owned points at res_out[update block].  With nothing pending the operand
+// is r, copied to the next residual.
+struct UpdArgs {
+    const double *R[kMaxD];     // current residual per box (also the B operand)
+    double *Rn[kMaxD];          // next residual
+    const double *Q[kMaxD];     // q = A e
+    const double *E[kMaxD];     // merged skeleton error guess
+    double *U[kMaxD];           // skeleton iterate (in place)
+    int mesh[kMaxD];            // mesh (coarse axis) of each box: which shared points it owns
+    int nbox, nub;              // boxes, update blocks per box
+    Geo geo;
+    const double *dots;         // line-search partial sums: (<r, q>, <q, q>) pairs
+    int ndots;
+    double *scal;               // <r, q>, <q, q> and s recorded by block 0
+    const IterState *stt;
+    double *res_out;
+};
+int upd_blocks_per_box(const Geo &g);  // update blocks that cover one mesh's skeleton points
+
 // One batched GEMM C = A * B per entry z (up to 3 boxes), FP64 MFMA; element (i, k) of A at
 // A + b*sAb + i*sAi + k*sAk, and likewise for B (k, n) and C (i, n).
 struct GemmJob {
@@ -86,6 +111,8 @@ struct GemmJob {
     // tiles run; set only on a launch that no other launch of its step precedes
     int fin_on;
     FinArgs fin;
+    int upd_on;                // 1: UpdArgs apply (A and B k-fast, one batch)
+    UpdArgs upd;
 };
 int gemm_tiles_per_box(const GemmJob &job);  // output tiles of one box (all batches) as launched
 
@@ -196,6 +223,9 @@ void launch_skel_update(const Plan &p, double *const *gather, hipStream_t st);
 // launch_finalize_pending applies it on its own (a no-op launch when nothing is pending) wherever
 // the loop state is read or no such GEMM follows.
 FinArgs pending_fin_args(const Plan &p);
+// the line search's partial sums that k_skel_dots leaves ((<r, q>, <q, q>) pairs) and their count
+const double *skel_dots_partials(const Plan &p);
+int skel_dots_count(const Plan &p);
 void launch_finalize_pending(const Plan &p, hipStream_t st);
 
 }  // namespace asdsm

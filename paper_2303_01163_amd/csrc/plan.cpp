@@ -508,6 +508,8 @@ void layout_workspace(Plan &p, char *base, bool assign) {
             w.SR[k] = (double *)take(sz * 8);
             w.SQ[k] = (double *)take(sz * 8);
             w.EA[k] = (double *)take(2 * sz * 8);
+            w.SR2[k] = (double *)take(sz * 8);
+            w.SE[k] = (double *)take(sz * 8);
         }
     }
     w.state = (IterState *)take(sizeof(IterState));
