@@ -170,6 +170,9 @@ void carry_finalize(Plan &p, GemmJob &j) {
 void carry_update(Plan &p, GemmJob &j, const int *slot) {
     if (!p.upd_carry) return;
     j.upd_on = 1;
+    // short contractions load every K chunk at once; with q beside the operand a 32 x 64 tile
+    // would hold more loads per wave in flight than the counter allows (63), so take 64 x 32
+    if (j.K <= 128 && j.tile == kTile32x64) j.tile = kTile64x32;
     UpdArgs &u = j.upd;
     for (int b = 0; b < j.nbox; ++b) {
         const int k = slot[b];

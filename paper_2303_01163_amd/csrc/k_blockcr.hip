@@ -217,6 +217,7 @@ __global__ __launch_bounds__(256) void k_block_cr(CrJob job) {
 // so it runs in place; back substitution reads a whole row-block of the equation it overwrites, so
 // its results are held in registers until a barrier.  The solved line is copied to dst at the end.
 constexpr int kCrMaxPerThread = 16;
+constexpr int kCrLd = 5;  // staging loads per thread and array in flight together (k_block_cr2)
 
 template <int NB, int RB>
 __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
@@ -238,10 +239,9 @@ __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
         const long long mode = mode0 + tid;
         mbase[tid] = (mode % bx.mext0) * bx.ms0 + (mode / bx.mext0) * bx.ms1;
     }
+    lds_barrier();  // the offsets (nothing is in flight yet)
     const int mats = tm * L * 3 * MM;
     const double *tsrc = bx.tab + (size_t)mode0 * L * 3 * MM;
-    for (int e = tid; e < mats; e += 256) Mt[e] = tsrc[e];
-    __syncthreads();
     const bool modes_fast = bx.ms0 == 1;
     const long long sw = bx.sw, sc = bx.sc;
     // element t of the coalesced order: modes fastest when they are contiguous, else the line
@@ -258,10 +258,28 @@ __global__ __launch_bounds__(256) void k_block_cr2(CrJob job) {
             c = rest / tm;
         }
     };
-    for (int t = tid; t < tm * N * NB; t += 256) {
-        int ml, i, c;
-        elem(t, ml, i, c);
-        D[(ml * N + i) * NB + c] = bx.src[mbase[ml] + i * sw + c * sc];
+    // the matrices and the lines in rounds of kCrLd values of each per thread: every load of a
+    // round is in flight before the first LDS store (a lane beyond the end reads element 0 and
+    // drops it), so the staging waits for memory once per round instead of once per value
+    const int nline = tm * N * NB;
+    for (int r0 = 0; r0 < mats || r0 < nline; r0 += 256 * kCrLd) {
+        double tv[kCrLd], lv[kCrLd];
+        int li[kCrLd];
+#pragma unroll
+        for (int u = 0; u < kCrLd; ++u) {
+            const int e = r0 + u * 256 + tid;
+            tv[u] = tsrc[e < mats ? e : 0];
+            int ml, i, c;
+            elem(e < nline ? e : 0, ml, i, c);
+            li[u] = (ml * N + i) * NB + c;
+            lv[u] = bx.src[mbase[ml] + i * sw + c * sc];
+        }
+#pragma unroll
+        for (int u = 0; u < kCrLd; ++u) {
+            const int e = r0 + u * 256 + tid;
+            if (e < mats) Mt[e] = tv[u];
+            if (e < nline) D[li[u]] = lv[u];
+        }
     }
     __syncthreads();
     if (!flag_clear(gv)) return;  // block-uniform

@@ -51,37 +51,61 @@ template <int K>
 __device__ __forceinline__ void skel_dots_mesh(const Geo &g, const double *__restrict__ E, const double *__restrict__ EA,
                                                const double *__restrict__ R, double *__restrict__ Q, double &rq,
                                                double &qq, int tile, int ntile, int gv) {
+    constexpr int PPT = 4;  // points per thread whose loads are in flight together
     const int Nf = g.Nf;
     const int per = g.Nc * Nf * Nf;
+    const int stride = ntile * 256;
     const double bsum = g.fine[0].b + g.fine[1].b + g.fine[2].b;
-    for (int idx = tile * 256 + threadIdx.x; idx < per; idx += ntile * 256) {
-        int x0, x1, x2;
-        bool own;
-        skel_point<K>(g, idx, x0, x1, x2, own);
-        const unsigned row = (unsigned)idx / (unsigned)Nf;
-        const int a = idx - (int)row * Nf, b = (int)(row % (unsigned)Nf);
-        // neighbours within the plane (fine axes a, b) and across it (layers)
-        const double am = a > 0 ? E[idx - 1] : 0.0, ap = a < Nf - 1 ? E[idx + 1] : 0.0;
-        const double bm = b > 0 ? E[idx - Nf] : 0.0, bp = b < Nf - 1 ? E[idx + Nf] : 0.0;
-        const double cm = EA[idx], cp = EA[idx + per];
-        double q = bsum * E[idx];
-        if (K == 0) {
-            q += g.fine[0].a * cm; q += g.fine[0].c * cp;
-            q += g.fine[1].a * am; q += g.fine[1].c * ap;
-            q += g.fine[2].a * bm; q += g.fine[2].c * bp;
-        } else if (K == 1) {
-            q += g.fine[0].a * am; q += g.fine[0].c * ap;
-            q += g.fine[1].a * cm; q += g.fine[1].c * cp;
-            q += g.fine[2].a * bm; q += g.fine[2].c * bp;
-        } else {
-            q += g.fine[0].a * am; q += g.fine[0].c * ap;
-            q += g.fine[1].a * bm; q += g.fine[1].c * bp;
-            q += g.fine[2].a * cm; q += g.fine[2].c * cp;
+    for (int base = tile * 256 + threadIdx.x; base < per; base += PPT * stride) {
+        // every operand of the thread's points first (branch-free: a neighbour outside the plane
+        // reads the point itself and is dropped below), then the sums in point order
+        double ec[PPT], am[PPT], ap[PPT], bm[PPT], bp[PPT], cm[PPT], cp[PPT], rr[PPT];
+        unsigned inside[PPT];
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+            const int idx = base + t * stride;
+            const int i = idx < per ? idx : 0;
+            const unsigned row = (unsigned)i / (unsigned)Nf;
+            const int a = i - (int)row * Nf, b = (int)(row % (unsigned)Nf);
+            inside[t] = (a > 0 ? 1u : 0u) | (a < Nf - 1 ? 2u : 0u) | (b > 0 ? 4u : 0u) | (b < Nf - 1 ? 8u : 0u);
+            ec[t] = E[i];
+            am[t] = E[a > 0 ? i - 1 : i];
+            ap[t] = E[a < Nf - 1 ? i + 1 : i];
+            bm[t] = E[b > 0 ? i - Nf : i];
+            bp[t] = E[b < Nf - 1 ? i + Nf : i];
+            cm[t] = EA[i];
+            cp[t] = EA[i + per];
+            rr[t] = R[i];
         }
-        if (flag_clear(gv)) Q[idx] = q;  // the stopping flag, tested after the first loads
-        if (own) {
-            rq += R[idx] * q;
-            qq += q * q;
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+            const int idx = base + t * stride;
+            if (idx >= per) break;
+            int x0, x1, x2;
+            bool own;
+            skel_point<K>(g, idx, x0, x1, x2, own);
+            // neighbours within the plane (fine axes a, b) and across it (layers)
+            const double vam = (inside[t] & 1u) ? am[t] : 0.0, vap = (inside[t] & 2u) ? ap[t] : 0.0;
+            const double vbm = (inside[t] & 4u) ? bm[t] : 0.0, vbp = (inside[t] & 8u) ? bp[t] : 0.0;
+            double q = bsum * ec[t];
+            if (K == 0) {
+                q += g.fine[0].a * cm[t]; q += g.fine[0].c * cp[t];
+                q += g.fine[1].a * vam; q += g.fine[1].c * vap;
+                q += g.fine[2].a * vbm; q += g.fine[2].c * vbp;
+            } else if (K == 1) {
+                q += g.fine[0].a * vam; q += g.fine[0].c * vap;
+                q += g.fine[1].a * cm[t]; q += g.fine[1].c * cp[t];
+                q += g.fine[2].a * vbm; q += g.fine[2].c * vbp;
+            } else {
+                q += g.fine[0].a * vam; q += g.fine[0].c * vap;
+                q += g.fine[1].a * vbm; q += g.fine[1].c * vbp;
+                q += g.fine[2].a * cm[t]; q += g.fine[2].c * cp[t];
+            }
+            if (flag_clear(gv)) Q[idx] = q;  // the stopping flag, tested after the first loads
+            if (own) {
+                rq += rr[t] * q;
+                qq += q * q;
+            }
         }
     }
 }
