@@ -39,6 +39,12 @@ KERNEL_SOURCE = {"k_gemm_f64": "k_boxsolve.hip", "k_update_residual3": "k_stenci
                  "k_skel_dots": "k_sparse.hip", "k_skel_update": "k_sparse.hip", "k_conv_fwd": "k_learn.hip",
                  "k_plane2": "k_boxsolve.hip", "k_block_cr2": "k_blockcr.hip"}
 SKEL_KERNEL = {"update": "k_skel_update (+ the fine residual at the ends)", "dots": "k_skel_dots"}
+# launch kinds of the library's kernel records whose kernel (and variant in the traffic summary)
+# differs from their first word: the forward transform that carries the skeleton update
+# (k_gemm_f64<..., UPD = true>), the filler in layer mode (k_filler_mfma3<L, true>)
+KIND_KERNEL = {"k_gemm_f64": ("k_gemm_f64", "plain"), "k_gemm_f64+upd": ("k_gemm_f64", "upd"),
+               "hole filler (layer mode)": ("k_filler_mfma3", "layers"), "k_block_cr": ("k_block_cr2", "main")}
+RIDGE_FLOP_PER_BYTE = 78.6e12 / 8e12   # FP64 MFMA peak over HBM peak
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_asdsm3d_127.txt")
 PMC_WORKLOAD = ("asdsm-3d-127^3-sinbump-seed0", 3)   # workload and coarse level the counters were taken on
 
@@ -60,10 +66,11 @@ def kernel_digest(kernel):
     return None
 
 
-def pmc_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary, or None when there is none, the kernel's source changed since it was taken, or the
-    timed workload (name, coarse level) is not the one the counters were taken on."""
+def pmc_traffic(kernel, workload, variant="main"):
+    """HBM bytes per launch of `kernel` (its template variant: e.g. the transform with or without
+    the skeleton update) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when
+    there is none, the kernel's source changed since it was taken, or the timed workload (name,
+    coarse level) is not the one the counters were taken on."""
     if tuple(workload) != PMC_WORKLOAD:
         return None
     digest = kernel_digest(kernel)
@@ -74,7 +81,7 @@ def pmc_traffic(kernel, workload):
         if not f or f[0] != kernel:
             continue
         kv = dict(x.split("=", 1) for x in f[1:] if "=" in x)
-        if kv.get("kernel_sha256") == digest:
+        if kv.get("variant", "main") == variant and kv.get("kernel_sha256") == digest:
             return float(kv["bytes_per_launch"])
     return None
 
@@ -93,13 +100,15 @@ def kernel_roofline(kprof, workload):
     """Roofline position of the dominant kernel of a profiled solve: the launch-group kind (one
     kernel per group) with the largest device time; achieved = its algorithmic work per launch
     divided by its average launch duration (HIP event pairs stamped by the kernel itself on the
-    library's stream), against the FP64 MFMA peak for the mode transforms and the hole solves and
-    the HBM peak for the rest."""
+    library's stream), against the FP64 MFMA peak when its algorithmic flops per byte reach the
+    ridge of the two peaks (an MFMA kind: the mode transforms, the hole solves) and the HBM peak
+    otherwise."""
     kernels = [k for k in kprof if not k["name"].startswith("phase:") and k["launches"] > 0]
     dom = max(kernels, key=lambda k: k["ms"])
     avg_ms = dom["ms"] / dom["launches"]
-    base = dom["name"].split()[0]
-    if any(dom["name"].startswith(x) for x in MFMA_KINDS):
+    base, variant = KIND_KERNEL.get(dom["name"], (dom["name"].split()[0], "main"))
+    intensity = dom["flops"] / dom["bytes"] if dom["bytes"] > 0 else float("inf")
+    if any(dom["name"].startswith(x) for x in MFMA_KINDS) and intensity >= RIDGE_FLOP_PER_BYTE:
         per_launch = dom["flops"] / dom["launches"]
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         bound, peak, unit = "mfma", FP64_PEAK_TFLOPS, "TFLOP/s"
@@ -108,10 +117,11 @@ def kernel_roofline(kprof, workload):
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": pmc_traffic(base, workload), "kernel": dom["name"],
+            "frac": achieved / peak, "traffic": pmc_traffic(base, workload, variant), "kernel": dom["name"],
             "launches": dom["launches"], "avg_launch_ms": avg_ms,
             "algorithmic_per_launch": per_launch,
             "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
+            "algorithmic_flop_per_byte": intensity,
             "share_of_profiled_device_time": dom["ms"] / sum(k["ms"] for k in kprof)}
 
 
