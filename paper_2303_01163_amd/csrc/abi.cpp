@@ -416,6 +416,8 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
         if (tm == 0 && job.accum)
             return fail(ASDSM_E_UNSUPPORTED, "line solve: accumulation needs the LDS form");
         job.tm = tm;
+        job.scratch = p.ws.crs;
+        job.scratch_len = p.ws.crs_len;
         const double B = m.block;
         const double pts = (double)nm * nb * job.N * B;
         PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 6.0 * pts * B, 8.0 * (2.0 * pts + 3.0 * nm * nb * job.L * B * B),

@@ -103,6 +103,10 @@ struct Workspace {
     // transform reads one and writes the other) and the merged error guess, which must outlive the
     // transform's output in Y
     double *SR2[kMaxD] = {}, *SE[kMaxD] = {};
+    // back-substitution results of the line solves whose block is too large for the LDS forms
+    // (block_cr_gemm), and its length in doubles
+    double *crs = nullptr;
+    long long crs_len = 0;
     IterState *state = nullptr;  // refinement-loop state
     double *hist = nullptr;      // ||r_k||, k = 0..it
     double *step_hist = nullptr; // s_hat_k

@@ -455,7 +455,117 @@ __global__ __launch_bounds__(256) void k_block_cr_global(CrJob job) {
     }
 }
 
+// dst = src over n doubles (the line solve in place in dst)
+__global__ __launch_bounds__(256) void k_cr_copy(const double *__restrict__ src, double *__restrict__ dst, long long n,
+                                                 const int *gate) {
+    if (!gate_open(gate)) return;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) dst[e] = src[e];
+}
+
+// The back substitution's results T (per mode NB x nel, row r of equation q at r + NB q) into the
+// line at the equations' positions (2q + 1) s - 1.
+__global__ __launch_bounds__(256) void k_cr_scatter(const double *__restrict__ T, double *__restrict__ W, int NB, int nel,
+                                                    long long tstride, long long mstride, long long sw, long long sc,
+                                                    int s, long long nmodes, const int *gate) {
+    if (!gate_open(gate)) return;
+    const long long per = (long long)NB * nel, tot = per * nmodes;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
+        const long long mode = e / per, rem = e - mode * per;
+        const int q = (int)(rem / NB), r = (int)(rem - (long long)q * NB);
+        W[mode * mstride + ((long long)(2 * q + 1) * s - 1) * sw + r * sc] = T[mode * tstride + rem];
+    }
+}
+
 }  // namespace
+
+// The global-memory form as FP64 GEMMs: at each level every kept (forward) or solved (back)
+// equation of every mode applies the same level matrices of its mode, so a level is a batched
+// product over the modes, with the equations as columns (strided in the line).  Forward: f_i -=
+// P f_(i-s) and f_i -= Q f_(i+s) in place (the columns read and written are disjoint).  Back:
+// T = G f_i, T -= P x_(i-s) (all but the first equation), T -= Q x_(i+s) (all but the last), then T
+// into the line.  One mode axis (all modes at a common stride) is required; false otherwise.
+static bool block_cr_gemm(const CrJob &job, hipStream_t st) {
+    const int N = job.N, L = job.L, NB = job.NB;
+    const long long MM = (long long)NB * NB;
+    for (int b = 0; b < job.nbox; ++b) {
+        const CrBox &bx = job.box[b];
+        if (!(bx.nmodes <= bx.mext0 || bx.ms1 == bx.mext0 * bx.ms0)) return false;
+        if ((long long)NB * (1ll << (L - 1)) * bx.nmodes > job.scratch_len) return false;
+    }
+    for (int b = 0; b < job.nbox; ++b) {
+        const CrBox &bx = job.box[b];
+        double *W = bx.dst;
+        const long long ms = bx.nmodes > 1 ? bx.ms0 : 0, sw = bx.sw, sc = bx.sc;
+        if (bx.src != bx.dst) {
+            // the box's lines span [0, extent) of its canonical layout
+            const long long n = (bx.nmodes - 1) * ms + (N - 1) * sw + (NB - 1) * sc + 1;
+            ASDSM_LAUNCH(k_cr_copy, dim3((unsigned)std::min<long long>((n + 255) / 256, 4096)), dim3(256), 0, st,
+                         bx.src, W, n, job.gate);
+        }
+        GemmJob g{};
+        g.nbox = 1;
+        g.gate = job.gate;
+        g.tile = kTileAuto;
+        g.any_layout = 1;
+        g.M = NB;
+        g.K = NB;
+        g.nbatch = (int)bx.nmodes;
+        g.sAb = (long long)L * 3 * MM;
+        g.sAi = NB;
+        g.sAk = 1;
+        g.sBb = ms;
+        g.sBk = sc;
+        g.sCb = ms;
+        g.sCi = sc;
+        for (int l = 0; l <= L - 2; ++l) {  // forward reduction
+            const int s = 1 << l, nkeep = (1 << (L - l - 1)) - 1;
+            g.N = nkeep;
+            g.sBn = 2ll * s * sw;
+            g.sCn = 2ll * s * sw;
+            g.accum = 1;
+            g.neg = 1;
+            g.C[0] = W + (2ll * s - 1) * sw;
+            g.A[0] = bx.tab + ((long long)l * 3 + 1) * MM;  // P
+            g.B[0] = W + ((long long)s - 1) * sw;
+            if (!launch_gemm(g, st)) return false;
+            g.A[0] = bx.tab + ((long long)l * 3 + 2) * MM;  // Q
+            g.B[0] = W + (3ll * s - 1) * sw;
+            if (!launch_gemm(g, st)) return false;
+        }
+        const long long tstride = (long long)NB << (L - 1);
+        for (int l = L - 1; l >= 0; --l) {  // back substitution
+            const int s = 1 << l, nel = 1 << (L - l - 1);
+            GemmJob t = g;
+            t.sBn = 2ll * s * sw;
+            t.sCb = tstride;
+            t.sCi = 1;
+            t.sCn = NB;
+            t.N = nel;
+            t.accum = 0;
+            t.neg = 0;
+            t.A[0] = bx.tab + (long long)l * 3 * MM;  // G
+            t.B[0] = W + ((long long)s - 1) * sw;
+            t.C[0] = job.scratch;
+            if (!launch_gemm(t, st)) return false;
+            if (nel >= 2) {
+                t.N = nel - 1;
+                t.accum = 1;
+                t.neg = 1;
+                t.A[0] = bx.tab + ((long long)l * 3 + 1) * MM;  // P x_(i-s), equations 1 .. nel-1
+                t.B[0] = W + (2ll * s - 1) * sw;
+                t.C[0] = job.scratch + NB;
+                if (!launch_gemm(t, st)) return false;
+                t.A[0] = bx.tab + ((long long)l * 3 + 2) * MM;  // Q x_(i+s), equations 0 .. nel-2
+                t.C[0] = job.scratch;
+                if (!launch_gemm(t, st)) return false;
+            }
+            const long long tot = (long long)NB * nel * bx.nmodes;
+            ASDSM_LAUNCH(k_cr_scatter, dim3((unsigned)std::min<long long>((tot + 255) / 256, 4096)), dim3(256), 0, st,
+                         job.scratch, W, NB, nel, tstride, ms, sw, sc, s, bx.nmodes, job.gate);
+        }
+    }
+    return true;
+}
 
 size_t cr_lds_bytes(int N, int NB, int tm) {
     const int Nk = (N - 1) / 2;
@@ -513,6 +623,7 @@ bool launch_block_cr(const CrJob &job, hipStream_t st) {
         }
     }
     if (job.tm == 0) {  // the global-memory form, in place in dst
+        if (job.scratch && !job.accum && block_cr_gemm(job, st)) return true;
         ASDSM_LAUNCH(k_block_cr_global, dim3((unsigned)maxm, (unsigned)job.nbox), dim3(256), 0, st, job);
         return true;
     }

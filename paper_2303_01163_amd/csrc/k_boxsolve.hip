@@ -321,7 +321,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmJob job) {
                 const int gn = n0 + wn * (TN / 2) + b * 16 + (lane & 15);
                 if (gi < job.M && gn < job.N) {
                     double *cp = C + (long long)gi * job.sCi + (long long)gn * job.sCn;
-                    const double val = job.accum ? *cp + acc[a][b][v] : acc[a][b][v];
+                    const double pr = job.neg ? -acc[a][b][v] : acc[a][b][v];
+                    const double val = job.accum ? *cp + pr : pr;
                     *cp = val;
                     ss += val * val;
                 }
@@ -391,8 +392,9 @@ int upd_blocks_per_box(const Geo &g) {
 }
 
 bool launch_gemm(const GemmJob &job, hipStream_t st) {
-    // operand layouts of the mode transforms: A k-fast or m-fast, B k-fast or n-fast
-    if ((job.sAk != 1 && job.sAi != 1) || (job.sBk != 1 && job.sBn != 1)) return false;
+    // operand layouts of the mode transforms: A k-fast or m-fast, B k-fast or n-fast (any other
+    // strides only when asked for: the kernel indexes them correctly, with uncoalesced panels)
+    if (!job.any_layout && ((job.sAk != 1 && job.sAi != 1) || (job.sBk != 1 && job.sBn != 1))) return false;
     // the fused skeleton update: k-fast operands, one batch, no accumulation or norms, no carried
     // stopping rule (that reads what this launch writes)
     if (job.upd_on && (job.sAk != 1 || job.sBk != 1 || job.nbatch != 1 || job.accum || job.fin_on ||

@@ -54,6 +54,10 @@ struct CrJob {
     int accum;
     int fast;            // 1: the form with the whole line and all levels' matrices in LDS
     const int *gate;
+    // the global-memory form as batched FP64 GEMMs per level (block_cr_gemm), when non-null:
+    // scratch of at least NB * 2^(L-1) * nmodes doubles for the box with the most modes
+    double *scratch;
+    long long scratch_len;
 };
 constexpr size_t kCrMaxLds = 64 * 1024;
 size_t cr_lds_bytes(int N, int NB, int tm);
@@ -101,6 +105,8 @@ struct GemmJob {
     int nbox;
     int M, N, K, nbatch;
     int accum;                 // 1: C += A B, 0: C = A B
+    int neg;                   // 1: the product enters negated (C -= A B, or C = -A B)
+    int any_layout;            // 1: operands with no unit stride are accepted (slow, correct)
     const int *gate;           // return at once when *gate != 0 (may be nullptr)
     long long sAb, sAi, sAk, sBb, sBk, sBn, sCb, sCi, sCn;
     int tile;                  // FP64 tile shape: kTileAuto or one of kGemmTiles (autotuner)

@@ -490,6 +490,17 @@ void layout_workspace(Plan &p, char *base, bool assign) {
             w.W[s] = (double *)take((size_t)p.mesh[s].size * 8);
         }
     }
+    {
+        // line solves with blocks the LDS forms do not take: NB x 2^(L-1) per mode of the mesh
+        long long need = 0;
+        for (unsigned s = 1; s < nm; ++s) {
+            const MeshDesc &m = p.mesh[s];
+            if (p.line_pos[s] < 0 || cr_lds_supported(m.block)) continue;
+            need = std::max(need, (long long)m.block * (1ll << (p.level - 1)) * (m.nmodes / m.ext[p.line_pos[s]]));
+        }
+        w.crs_len = need;
+        w.crs = need ? (double *)take((size_t)need * 8) : nullptr;
+    }
     // cross-point discrepancies of each anisotropic mesh: d=2: Nc*Nc; d=3: parts A, B, R of
     // Nc*Nc*Nf values each; d=4: three plane families and two Boolean-sum remainders of
     // Nc*Nc*Nf*Nf values each
