@@ -135,9 +135,12 @@ typedef struct {
  * matrix); the large work arrays live in a caller-owned workspace (asdsm_set_workspace).
  * A fine axis that fast diagonalisation cannot handle (|cell Peclet| >= 1: complex spectrum; or an
  * eigenvector matrix too ill-conditioned for FP64) is solved along lines by block cyclic reduction
- * (asdsm_line_axes reports which).
- * Errors: ASDSM_E_ARG, ASDSM_E_NESTING, ASDSM_E_UNSUPPORTED (a submesh or the hole boxes with two
- * such axes, or hole boxes too large for one workgroup's LDS), ASDSM_E_NUMERIC (a singular block),
+ * (asdsm_line_axes reports which).  For d = 3, an anisotropic mesh with two such fine axes takes
+ * both on its line solve (the line along one, the other fine axis with the coarse axis as its
+ * N_f N_c-point block, up to 512), and hole boxes with two or three such axes apply the inverse of
+ * their operator densely (holes of up to 7^3 points).
+ * Errors: ASDSM_E_ARG, ASDSM_E_NESTING, ASDSM_E_UNSUPPORTED (two such axes beyond those limits, or
+ * in d = 4; hole boxes too large for one workgroup's LDS), ASDSM_E_NUMERIC (a singular block),
  * ASDSM_E_DEVICE. */
 int asdsm_plan(asdsm_plan_t *out, int d, const double *alpha, const double *beta, int level,
                int coarse_level, uint64_t seed, void *hip_stream);

@@ -308,11 +308,14 @@ int transform_pos0_modes_major(Plan &p, const MeshDesc &m, int nb, const double 
 int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const *in, double *const *out,
                     int accum) {
     const MeshDesc &m = p.mesh[masks[0]];
-    const int nt = m.nfine - 1;  // transformed positions per mesh
+    // transformed positions per mesh (none when both fine axes are on the line solve; the meshes
+    // of one call are all of one kind)
+    const bool block2 = p.line_block2[masks[0]];
+    const int nt = block2 ? 0 : m.nfine - 1;
     int fq[kMaxD][kMaxD];        // [box][t]: the transformed canonical positions, ascending
     for (int b = 0; b < nb; ++b) {
         int t = 0;
-        for (int q = 0; q < m.nfine; ++q)
+        for (int q = 0; q < m.nfine && t < nt; ++q)
             if (q != p.line_pos[masks[b]]) fq[b][t++] = q;
     }
     // forward transforms: in -> Y -> X ... (transform t writes Y for even t, X for odd t)
@@ -378,7 +381,7 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
         job.nbox = nb;
         job.N = p.Nf;
         job.L = p.level;
-        job.NB = m.block;
+        job.NB = cr_block(p, masks[0]);
         job.gate = p.gate;
         job.accum = (nt == 0) ? accum : 0;
         long long nm = 0;
@@ -389,12 +392,14 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
             bx.src = (nt == 0) ? in[b] : D[b];
             bx.dst = (nt == 0) ? out[b] : D[b];
             bx.tab = p.dcr[mk];
-            bx.nmodes = mb.nmodes / mb.ext[p.line_pos[mk]];
+            bx.nmodes = cr_modes(p, mk);
             bx.mext0 = nt >= 1 ? mb.ext[fq[b][0]] : 1;
             bx.ms0 = nt >= 1 ? mb.stride[fq[b][0]] : 0;
             bx.ms1 = nt >= 2 ? mb.stride[fq[b][1]] : 0;
             bx.sw = mb.stride[p.line_pos[mk]];
-            bx.sc = mb.stride[mb.nfine];
+            // the block: the coarse axes, or the second fine axis with them (contiguous after the
+            // line axis at position 0 in either case of line_block2)
+            bx.sc = block2 ? mb.stride[1] : mb.stride[mb.nfine];
             if (modes_major) {  // element (mode, i, c) at mode (N_f N_c) + i + N_f c
                 bx.ms0 = mb.size / mb.ext[0];
                 bx.sw = 1;
@@ -418,7 +423,7 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
         job.tm = tm;
         job.scratch = p.ws.crs;
         job.scratch_len = p.ws.crs_len;
-        const double B = m.block;
+        const double B = job.NB;
         const double pts = (double)nm * nb * job.N * B;
         PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 6.0 * pts * B, 8.0 * (2.0 * pts + 3.0 * nm * nb * job.L * B * B),
                      "k_block_cr");
@@ -539,15 +544,25 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
         if ((kbits >> k) & 1u) ks[nb++] = k;
     if (nb == 0) return ASDSM_OK;
     if (d == 4 || p.line_aniso) {
-        unsigned masks[kMaxD];
-        const double *bin[kMaxD];
-        double *bout[kMaxD];
-        for (int q = 0; q < nb; ++q) {
-            masks[q] = 1u << ks[q];
-            bin[q] = in[ks[q]];
-            bout[q] = out[ks[q]];
+        // the meshes with a transformed fine axis first (their first launch is a transform, which
+        // may carry the previous step's stopping rule), then those with both fine axes on the line
+        for (int kind = 0; kind < 2; ++kind) {
+            unsigned masks[kMaxD];
+            const double *bin[kMaxD];
+            double *bout[kMaxD];
+            int ng = 0;
+            for (int q = 0; q < nb; ++q) {
+                const unsigned mq = 1u << ks[q];
+                if ((int)p.line_block2[mq] != kind) continue;
+                masks[ng] = mq;
+                bin[ng] = in[ks[q]];
+                bout[ng] = out[ks[q]];
+                ++ng;
+            }
+            if (ng == 0) continue;
+            if (int rc = solve_mesh_nd(p, ng, masks, bin, bout, accum)) return rc;
         }
-        return solve_mesh_nd(p, nb, masks, bin, bout, accum);
+        return ASDSM_OK;
     }
     const long long Nf2 = (long long)Nf * Nf;
     GemmJob j{};
@@ -746,15 +761,19 @@ int solve_aniso_refined(Plan &p, unsigned kbits) {
     double *in[kMaxD] = {}, *out[kMaxD] = {};
     int ns = 0, nb = 0;
     unsigned masks[kMaxD];
+    unsigned sweep_bits = 0;  // the meshes that take the sweeps (not those solved on the line alone)
     for (int k = 0; k < p.d; ++k)
         if ((kbits >> k) & 1u) {
             const unsigned m = 1u << k;
-            masks[nb++] = m;
             in[k] = rhs_buf(p, m);
             out[k] = sol_buf(p, m);
+            if (p.line_block2[m]) continue;
+            masks[nb++] = m;
+            sweep_bits |= 1u << k;
             ns = std::max(ns, p.sweeps[m]);
         }
     if (int rc = solve_aniso(p, kbits, in, out, 0)) return rc;
+    kbits = sweep_bits;
     for (int sweep = 0; sweep < ns; ++sweep) {
         BoxResJob job{};
         job.nbox = nb;
@@ -1237,6 +1256,7 @@ int error_guess(Plan &p) {
         if (!fused && p.line_aniso && p.d == 3) {
             fused = true;
             for (int k = 1; k < 3; ++k) fused = fused && p.line_pos[1u << k] == p.line_pos[1u];
+            for (int k = 0; k < 3; ++k) fused = fused && !p.line_block2[1u << k];
         }
         p.norm_partials = fused ? p.ws.partials : nullptr;
         p.norm_nblk = p.Nc * ((p.Nf + 15) / 16);  // the plane kernel's count (the GEMM sets its own)
@@ -1297,7 +1317,9 @@ int sparse_step(Plan &p) {
     // stopping rule alone is pending (k_skel_update leaves it): with line-axis meshes (FP64) this
     // step's first launch is a transform GEMM, which applies it in one extra block beside its tiles;
     // otherwise a launch of its own applies it first.
-    const bool carry = p.line_aniso && !p.prec32;
+    bool transformed = false;  // some anisotropic mesh has a transformed fine axis
+    for (int k = 0; k < p.d; ++k) transformed = transformed || !p.line_block2[1u << k];
+    const bool carry = p.line_aniso && !p.prec32 && transformed;
     if (p.upd_fused) {
         p.upd_carry = true;
     } else if (carry) {

@@ -21,6 +21,7 @@ constexpr int kMaxD = 4;
 constexpr int kMaxMeshes = 1 << kMaxD;
 constexpr int kDenseMaxBlock = 4096;  // coarse points per mode of an intersection-mesh dense solve
 constexpr int kCrMaxBlock = 512;      // coarse points per position of a line solve
+constexpr int kHoleDenseMax = 7;      // largest hole edge whose operator is inverted densely
 
 // Canonical layout of mesh M_S.
 struct MeshDesc {
@@ -165,6 +166,16 @@ struct Plan {
     // reduction (together with the coarse block) instead of being transformed, or -1
     int line_pos[kMaxMeshes] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
     bool line_aniso = false;           // the anisotropic meshes use line axes
+    // d = 3 anisotropic mesh whose two fine axes both defeat fast diagonalisation: its line axis is
+    // canonical position 0 and the block holds the other fine axis with the coarse axis (N_f N_c
+    // points, no mode axes); solved by the GEMM form of the block cyclic reduction
+    bool line_block2[kMaxMeshes] = {};
+    // holes of up to 7^3 points with two or more axes that defeat fast diagonalisation: the hole
+    // operator's inverse, applied densely by the generic filler (host copy while the plan is
+    // built; device copy in the table allocation)
+    bool hole_dense = false;
+    std::vector<double> hole_inv;
+    double *dhinv = nullptr;
     int cr_tm = 0;                     // modes per workgroup of their line solve (0: by size)
     std::vector<double> cr_tab[kMaxMeshes];  // host copies while the plan is built
     double *dcr[kMaxMeshes] = {};      // per mode and level: G, P, Q (device)
@@ -260,6 +271,14 @@ struct Plan {
     double phase_flops[ASDSM_NPHASE] = {};
     double phase_bytes[ASDSM_NPHASE] = {};
 };
+
+// block size and mode count of the line solve of mesh s (line_pos[s] >= 0)
+inline int cr_block(const Plan &p, unsigned s) {
+    return p.line_block2[s] ? p.mesh[s].ext[1] * p.mesh[s].block : p.mesh[s].block;
+}
+inline long long cr_modes(const Plan &p, unsigned s) {
+    return p.line_block2[s] ? 1 : p.mesh[s].nmodes / p.mesh[s].ext[p.line_pos[s]];
+}
 
 // the merged skeleton values of anisotropic mesh k (the merge's output)
 inline double *merged_buf(const Plan &p, int k) { return p.upd_fused ? p.ws.SE[k] : p.ws.Y[1u << k]; }

@@ -601,6 +601,9 @@ struct FillArgs {
     double *adj[kMaxD];  // adjacent-layer mode (k_filler_mfma3): the layers next to each coarse plane
     int adj_only;        // 1: write only those layers (skeleton-sparse refinement), not the fine tile
     const int *gate;
+    // non-null (k_filler, d = 3): the hole operator's inverse, column by column ((n-1)^3 squared),
+    // applied densely instead of the transforms and the line elimination
+    const double *hinv;
 };
 
 template <int D, int NH>
@@ -663,6 +666,18 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
     }
     __syncthreads();
     double *cur = bufA, *oth = bufB;
+    if (a.hinv) {
+        // 2') x = A_hole^-1 f, the inverse read column by column (consecutive threads read
+        // consecutive rows of a column)
+        for (int o = tid; o < npts; o += 256) {
+            double acc = 0.0;
+            for (int q = 0; q < npts; ++q) acc += a.hinv[(size_t)q * npts + o] * cur[q];
+            oth[o] = acc;
+        }
+        __syncthreads();
+        cur = bufB;
+        oth = bufA;
+    }
     // 2) forward transforms
     for (int q = 0; q < a.ntr; ++q) {
         const int j = a.tr[q];
@@ -681,7 +696,7 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
         oth = t;
     }
     // 3) line elimination along the line axis, one thread per line
-    {
+    if (!a.hinv) {
         const int L = a.line_axis;
         const int nlines = npts / nh;
         const Tri t = g.fine[L];
@@ -1306,12 +1321,26 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
     a.out = out;
     a.adj_only = adj_only ? 1 : 0;
     a.gate = p.gate;
+    a.hinv = nullptr;
+    if (p.hole_dense) {  // d = 3, holes of up to 7^3: the dense inverse in the generic filler
+        a.hinv = p.dhinv;
+        a.ntr = 0;
+    }
     int npts = 1;
     for (int j = 0; j < d; ++j) npts *= nh;
     const size_t lds = (size_t)(2 * npts + a.ntr * (2 * nh * nh + nh)) * sizeof(double);
     int tiles = 1;
     for (int j = 0; j < d; ++j) tiles *= (p.Nc + 1);
     const dim3 grid(tiles), blk(256);
+    if (p.hole_dense) {
+        const size_t ldsd = (size_t)2 * npts * sizeof(double);
+        switch (nh) {
+            case 1: ASDSM_LAUNCH((k_filler<3, 1>), grid, blk, ldsd, st, p.geo, a); break;
+            case 3: ASDSM_LAUNCH((k_filler<3, 3>), grid, blk, ldsd, st, p.geo, a); break;
+            default: ASDSM_LAUNCH((k_filler<3, 7>), grid, blk, ldsd, st, p.geo, a); break;
+        }
+        return;
+    }
     if (d == 3 && nh == 15) {
 #define ASDSM_FILL3(LL)                                                                   \
     do {                                                                                  \

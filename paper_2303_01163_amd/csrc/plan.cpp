@@ -356,12 +356,27 @@ static bool build_dense_inverse(Plan &p, unsigned mask) {
 
 // Row-major products and inverse of small dense NB x NB matrices (CR tables).
 static void matmul(int n, const double *A, const double *B, double *C) {
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-            double acc = 0.0;
-            for (int k = 0; k < n; ++k) acc += A[(size_t)i * n + k] * B[(size_t)k * n + j];
-            C[(size_t)i * n + j] = acc;
-        }
+    auto rows = [&](int i0, int i1) {
+        for (int i = i0; i < i1; ++i)
+            for (int j = 0; j < n; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < n; ++k) acc += A[(size_t)i * n + k] * B[(size_t)k * n + j];
+                C[(size_t)i * n + j] = acc;
+            }
+    };
+    // large blocks (the line solves whose block holds a fine axis): rows over host threads
+    const int nt = (n >= 128) ? std::max(1, std::min(16, (int)std::thread::hardware_concurrency())) : 1;
+    if (nt == 1) {
+        rows(0, n);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const int chunk = (n + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+        const int i0 = t * chunk, i1 = std::min(n, i0 + chunk);
+        if (i0 < i1) pool.emplace_back(rows, i0, i1);
+    }
+    for (std::thread &th : pool) th.join();
 }
 
 // Reduced blocks of block cyclic reduction along the line axis of mesh `mask` (k_blockcr.hip): per
@@ -372,15 +387,17 @@ static void matmul(int n, const double *A, const double *B, double *C) {
 static bool build_cr_tables(Plan &p, unsigned mask) {
     const MeshDesc &m = p.mesh[mask];
     const int lp = p.line_pos[mask];
-    const int NB = m.block, L = p.level;
+    const int NB = cr_block(p, mask), L = p.level;
     const size_t MM = (size_t)NB * NB;
-    const long long nmodes = m.nmodes / m.ext[lp];
+    const long long nmodes = cr_modes(p, mask);
     const Tri tw = p.geo.fine[m.ax[lp]];
-    // Kronecker-sum matrix of the coarse axes on the block (coarse canonical order, first fastest)
+    // Kronecker-sum matrix of the block's axes (canonical order, first fastest): the coarse axes,
+    // preceded by the second fine axis when both fine axes are on the line solve (line_block2)
+    const int qb = p.line_block2[mask] ? 1 : m.nfine;  // first canonical position of the block
     std::vector<double> Kc(MM, 0.0);
     long long cs = 1;
-    for (int q = m.nfine; q < m.nd; ++q) {
-        const Tri t = p.geo.coarse[m.ax[q]];
+    for (int q = qb; q < m.nd; ++q) {
+        const Tri t = (q < m.nfine) ? p.geo.fine[m.ax[q]] : p.geo.coarse[m.ax[q]];
         const int e = m.ext[q];
         for (int idx = 0; idx < NB; ++idx) {
             const int pos = (int)((idx / cs) % e);
@@ -390,8 +407,8 @@ static bool build_cr_tables(Plan &p, unsigned mask) {
         }
         cs *= e;
     }
-    int fq[kMaxD], nfq = 0;  // fine positions other than the line axis (the mode axes)
-    for (int q = 0; q < m.nfine; ++q)
+    int fq[kMaxD], nfq = 0;  // fine positions other than the line axis and the block (the mode axes)
+    for (int q = 0; q < std::min(m.nfine, qb); ++q)
         if (q != lp) fq[nfq++] = q;
     std::vector<double> &out = p.cr_tab[mask];
     out.assign((size_t)nmodes * L * 3 * MM, 0.0);
@@ -494,9 +511,8 @@ void layout_workspace(Plan &p, char *base, bool assign) {
         // line solves with blocks the LDS forms do not take: NB x 2^(L-1) per mode of the mesh
         long long need = 0;
         for (unsigned s = 1; s < nm; ++s) {
-            const MeshDesc &m = p.mesh[s];
-            if (p.line_pos[s] < 0 || cr_lds_supported(m.block)) continue;
-            need = std::max(need, (long long)m.block * (1ll << (p.level - 1)) * (m.nmodes / m.ext[p.line_pos[s]]));
+            if (p.line_pos[s] < 0 || cr_lds_supported(cr_block(p, s))) continue;
+            need = std::max(need, (long long)cr_block(p, s) * (1ll << (p.level - 1)) * cr_modes(p, s));
         }
         w.crs_len = need;
         w.crs = need ? (double *)take((size_t)need * 8) : nullptr;
@@ -626,9 +642,32 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         double ch = 1.0;
         for (int j = 0; j < d; ++j)
             if (j != p.hole_line_axis) ch *= cond_h[j];
-        if (!(2.2e-16 * ch <= 1e-12))
-            return fail(ASDSM_E_UNSUPPORTED, "hole boxes: more than one axis too ill-conditioned for "
-                                             "fast diagonalisation (|cell Peclet| near or above 1)");
+        if (!(2.2e-16 * ch <= 1e-12)) {
+            // two or more such axes: holes of up to kHoleDenseMax^3 points (d = 3) take the hole
+            // operator's inverse, applied densely
+            if (d != 3 || p.n - 1 > kHoleDenseMax)
+                return fail(ASDSM_E_UNSUPPORTED, "hole boxes: more than one axis too ill-conditioned for "
+                                                 "fast diagonalisation (|cell Peclet| near or above 1)");
+            p.hole_dense = true;
+        }
+    }
+    if (p.hole_dense) {
+        // the hole operator: the Kronecker sum of the three fine-spacing 1D operators on (n-1)^3
+        // points (x_1 fastest); its inverse, column by column
+        const int nh = p.n - 1, np = nh * nh * nh;
+        std::vector<double> A((size_t)np * np, 0.0);
+        const int st[3] = {1, nh, nh * nh};
+        for (int o = 0; o < np; ++o) {
+            const int l[3] = {o % nh, (o / nh) % nh, o / (nh * nh)};
+            for (int j = 0; j < 3; ++j) {
+                const Tri t = g.fine[j];
+                A[(size_t)o * np + o] += t.b;
+                if (l[j] > 0) A[(size_t)o * np + o - st[j]] += t.a;
+                if (l[j] < nh - 1) A[(size_t)o * np + o + st[j]] += t.c;
+            }
+        }
+        p.hole_inv.assign((size_t)np * np, 0.0);
+        if (!dense_inverse(np, A, p.hole_inv.data())) return fail(ASDSM_E_NUMERIC, "singular hole operator");
     }
     build_spline(p.Nf, p.Nc, p.n, p.h, p.H, p.Sp);
     for (unsigned s = 0; s < (1u << d); ++s) p.mesh[s] = make_mesh(d, p.Nf, p.Nc, s);
@@ -649,6 +688,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     int swA = 0, swB = 0;
     int lineq[kMaxD];
     double condB[kMaxD];
+    bool block2 = false;
     for (int k = 0; k < d; ++k) {
         const MeshDesc &m = p.mesh[1u << k];
         double cA = 1.0;
@@ -664,16 +704,28 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         condB[k] = cB;
         const int a = sweeps_for(cA), b = sweeps_for(cB);
         if (worse(a, swA)) swA = a;
+        if (b < 0) {
+            // both fine axes defeat fast diagonalisation: d = 3 meshes whose block (the second fine
+            // axis with the coarse axis, N_f N_c points) fits the line solve take both on it
+            if (d != 3 || (long long)p.Nf * m.block > kCrMaxBlock)
+                return fail(ASDSM_E_UNSUPPORTED, "a submesh has two fine axes that fast diagonalisation cannot "
+                                                 "handle (|cell Peclet| near or above 1 on two axes) and more "
+                                                 "than " + std::to_string(kCrMaxBlock) + " points per line position");
+            p.line_block2[1u << k] = true;
+            block2 = true;
+            continue;
+        }
         if (worse(b, swB)) swB = b;
     }
-    if (swB < 0)
-        return fail(ASDSM_E_UNSUPPORTED, "a submesh has two fine axes that fast diagonalisation cannot "
-                                         "handle (|cell Peclet| near or above 1 on two axes)");
-    p.line_aniso = worse(swA, swB);
+    p.line_aniso = block2 || worse(swA, swB);
     for (unsigned s = 0; s < kMaxMeshes; ++s) p.line_pos[s] = -1;
     for (int k = 0; k < d; ++k) {
         const unsigned m = 1u << k;
-        if (p.line_aniso) {
+        if (p.line_block2[m]) {
+            p.line_pos[m] = 0;
+            p.fdm_cond[m] = 1.0;
+            p.sweeps[m] = 0;
+        } else if (p.line_aniso) {
             p.line_pos[m] = lineq[k];
             p.fdm_cond[m] = condB[k];
             p.sweeps[m] = swB;
@@ -792,6 +844,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         if (p.line_pos[s] >= 0) oCR[s] = add(p.cr_tab[s]);
         else if (__builtin_popcount(s) >= 2) oD[s] = add(p.dense_inv[s]);
     }
+    const size_t oH = p.hole_dense ? add(p.hole_inv) : 0;
     p.dtab_bytes = off;
     err = hipMalloc(&p.dtab, p.dtab_bytes);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipMalloc(tables): ") + hipGetErrorString(err));
@@ -820,6 +873,8 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         else if (__builtin_popcount(s) >= 2) p.ddense[s] = (double *)(base + oD[s]);
     }
     for (unsigned s = 0; s < kMaxMeshes; ++s) std::vector<double>().swap(p.cr_tab[s]);
+    if (p.hole_dense) p.dhinv = (double *)(base + oH);
+    std::vector<double>().swap(p.hole_inv);
     err = hipHostMalloc((void **)&p.hscal, kScalCount * sizeof(double), hipHostMallocDefault);
     if (err == hipSuccess) err = hipHostMalloc((void **)&p.hstate, sizeof(IterState), hipHostMallocDefault);
     if (err == hipSuccess)

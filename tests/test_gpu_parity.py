@@ -268,8 +268,8 @@ def test_error_codes(torch_dev):
     with pytest.raises(AsdsmError) as e:
         Plan(2, [1.0, 1.0], [0.0, 0.0], 5, 5)
     assert e.value.code == -2
-    with pytest.raises(AsdsmError) as e:              # cell Peclet number 1.25 on two fine axes
-        Plan(3, [1.0, 1.0, 1.0], [80.0, 80.0, 0.0], 5)
+    with pytest.raises(AsdsmError) as e:              # cell Peclet 1.17 on two fine axes at 127^3
+        Plan(3, [1.0, 1.0, 1.0], [300.0, 300.0, 0.0], 7)
     assert e.value.code == -6
     with pytest.raises(AsdsmError) as e:             # d outside 2..4
         Plan(5, [1.0] * 5, [0.0] * 5, 3)
@@ -328,13 +328,60 @@ def test_two_ill_conditioned_axes_use_a_line_axis(torch_dev):
     assert _rel(u.cpu().numpy(), ref.iterates[3].reshape(-1, order="F")) <= TOL_ITER
 
 
-def test_two_complex_axes_are_refused(torch_dev):
-    """Two fine axes with |cell Peclet| > 1 (complex 1D spectra): the submesh with both as fine
-    axes needs two line axes, which the plan does not build; it reports ASDSM_E_UNSUPPORTED instead
-    of returning inaccurate solves."""
+def _two_axes_parity(torch_dev, P, L, Lc, seed):
+    o = Oracle(3, P.alpha, P.beta, L, Lc, seed=seed)
+    pl = _plan(P, L, Lc, seed=seed)
+    rng = np.random.default_rng(5)
+    for S in ((0,), (1,), (2,), (0, 1), (1, 2), (0, 2), (0, 1, 2)):
+        _say("two complex axes: mesh", L, S)
+        mask = sum(1 << j for j in S)
+        rhs = rng.standard_normal(o.grid.mesh_dims(S))
+        x = pl.mesh_solve(mask, _t(torch_dev, _canon(3, S, rhs))).cpu().numpy()
+        assert _rel(_uncanon(o.grid, S, x), o.solve_mesh(S, rhs)) <= TOL_OP, S
+    ref = o.solve(P.s, P.g, max_iter=3, rtol=0, stag_window=0, keep_iterates=True)
+    s, g = _t(torch_dev, P.s_flat()), _t(torch_dev, P.g_flat())
+    for skeleton in (False, True):
+        _say("two complex axes: iterates", L, "skeleton" if skeleton else "fine")
+        for K in (0, 1, 3):
+            u, info = pl.solve(s, g, max_iter=K, rtol=0, stag_window=0, skeleton=skeleton)
+            assert info["iterations"] == K
+            assert _rel(u.cpu().numpy(), ref.iterates[K].reshape(-1, order="F")) <= TOL_ITER, (skeleton, K)
+    return pl
+
+
+def test_two_complex_axes_take_both_on_the_line_solve(torch_dev):
+    """63^3 with two fine axes of cell Peclet 1.02 (complex 1D spectra): the anisotropic mesh with
+    both as fine axes solves along one with the other and the coarse axis as its 441-point block
+    (block cyclic reduction as GEMMs per level), and the holes (7^3, two such axes) apply their
+    operator's inverse; every submesh solve and the iterates, fine-mesh and skeleton-sparse, match
+    the banded-LU oracle."""
+    P = make_problem("sinbump3d", 6, seed=1, alpha=[0.1, 0.1, 0.8], beta=[13.0, -13.0, 1.0])
+    pl = _two_axes_parity(torch_dev, P, 6, 3, 4)
+    assert pl.line_axes()[1 << 2][0] == 0   # M_2: the line along axis 0, axis 1 in the block
+
+
+def test_three_complex_axes_at_31(torch_dev):
+    """31^3 with every axis advection-dominated (cell Peclet 4.7 to 7.8 at h = 1/32, the range of
+    the advection-dominated family): every anisotropic mesh takes both fine axes on its line solve
+    (93-point blocks), the intersection meshes their one fine axis, and the holes (7^3, three such
+    axes) the dense inverse; submesh solves and iterates match the oracle."""
+    P = make_problem("sinbump3d", 5, seed=2, alpha=[0.02, 0.02, 0.02], beta=[10.0, -9.0, 6.0])
+    pl = _two_axes_parity(torch_dev, P, 5, 2, 6)
+    axes = pl.line_axes()
+    for k in range(3):
+        assert axes[1 << k][0] == (1 if k == 0 else 0)   # position 0 of M_k: its first fine axis
+
+
+def test_two_complex_axes_beyond_the_limits_are_refused(torch_dev):
+    """Beyond what is built: two fine axes with |cell Peclet| > 1 at 127^3 (a 127 * 7-point block,
+    holes of 15^3 with two such axes) report ASDSM_E_UNSUPPORTED instead of returning inaccurate
+    solves; so does d = 4 with two such axes."""
     from paper_2303_01163_amd.asdsm import AsdsmError, Plan
     with pytest.raises(AsdsmError) as e:
-        Plan(3, [0.1, 0.1, 0.8], [13.0, -13.0, 1.0], 6)
+        Plan(3, [0.1, 0.1, 0.8], [26.0, -26.0, 1.0], 7)
+    assert e.value.code == -6
+    with pytest.raises(AsdsmError) as e:
+        Plan(4, [0.05, 0.05, 0.8, 0.8], [8.0, -8.0, 1.0, 1.0], 5, 2)
     assert e.value.code == -6
 
 
