@@ -212,23 +212,24 @@ int transform_position(Plan &p, const MeshDesc &m, int q, int nb, const double *
     j.gate = p.gate;
     j.tile = (p.tile_aniso == kTilePlane) ? kTileAuto : p.tile_aniso;
     j.accum = accum;
-    const long long Nf = p.Nf, inner = m.stride[q];
+    // E: the axis' extent (N_f for a fine axis, N_c for a diagonalised coarse axis)
+    const long long E = m.ext[q], inner = m.stride[q];
     if (q == 0) {
-        j.M = (int)(m.size / Nf); j.N = (int)Nf; j.K = (int)Nf; j.nbatch = 1;
+        j.M = (int)(m.size / E); j.N = (int)E; j.K = (int)E; j.nbatch = 1;
         j.sAb = j.sBb = j.sCb = 0;
-        j.sAi = Nf; j.sAk = 1;
-        j.sBk = 1;  j.sBn = Nf;
-        j.sCi = Nf; j.sCn = 1;
+        j.sAi = E; j.sAk = 1;
+        j.sBk = 1;  j.sBn = E;
+        j.sCi = E; j.sCn = 1;
         for (int b = 0; b < nb; ++b) {
             j.A[b] = in[b];
             j.B[b] = T[b];
             j.C[b] = out[b];
         }
     } else {
-        j.M = (int)Nf; j.N = (int)inner; j.K = (int)Nf; j.nbatch = (int)(m.size / (inner * Nf));
-        j.sAb = 0;          j.sAi = Nf;    j.sAk = 1;
-        j.sBb = inner * Nf; j.sBk = inner; j.sBn = 1;
-        j.sCb = inner * Nf; j.sCi = inner; j.sCn = 1;
+        j.M = (int)E; j.N = (int)inner; j.K = (int)E; j.nbatch = (int)(m.size / (inner * E));
+        j.sAb = 0;         j.sAi = E;     j.sAk = 1;
+        j.sBb = inner * E; j.sBk = inner; j.sBn = 1;
+        j.sCb = inner * E; j.sCi = inner; j.sCn = 1;
         for (int b = 0; b < nb; ++b) {
             j.A[b] = T[b];
             j.B[b] = in[b];
@@ -298,6 +299,53 @@ int transform_pos0_modes_major(Plan &p, const MeshDesc &m, int nb, const double 
     return check_launch("transform");
 }
 
+// d = 3 anisotropic meshes whose two fine axes both need the line solve and whose coarse axis is
+// diagonalised (Plan::line_cmodes): forward transform along the coarse axis (canonical position 2,
+// in -> Y), per coarse mode block cyclic reduction along position 0 with position 1 as the block
+// (in place on Y, the GEMM form), backward transform (Y -> out, out += when accum).
+int solve_mesh_cmodes(Plan &p, int nb, const unsigned *masks, const double *const *in, double *const *out,
+                      int accum) {
+    const MeshDesc &m = p.mesh[masks[0]];
+    double *Y[kMaxD];
+    const double *T[kMaxD];
+    for (int b = 0; b < nb; ++b) {
+        Y[b] = p.ws.Y[masks[b]];
+        T[b] = p.dWc[p.mesh[masks[b]].ax[2]];
+    }
+    if (int rc = transform_position(p, m, 2, nb, in, T, Y, 0)) return rc;
+    CrJob job{};
+    job.nbox = nb;
+    job.N = p.Nf;
+    job.L = p.level;
+    job.NB = cr_block(p, masks[0]);
+    job.gate = p.gate;
+    job.scratch = p.ws.crs;
+    job.scratch_len = p.ws.crs_len;
+    for (int b = 0; b < nb; ++b) {
+        const MeshDesc &mb = p.mesh[masks[b]];
+        CrBox &bx = job.box[b];
+        bx.src = bx.dst = Y[b];
+        bx.tab = p.dcr[masks[b]];
+        bx.nmodes = cr_modes(p, masks[b]);
+        bx.mext0 = mb.ext[2];
+        bx.ms0 = mb.stride[2];
+        bx.ms1 = 0;
+        bx.sw = mb.stride[0];
+        bx.sc = mb.stride[1];
+    }
+    {
+        const double B = job.NB, pts = (double)nb * job.box[0].nmodes * job.N * B;
+        PhaseTimer t(p, ASDSM_PHASE_LINE, 1, 6.0 * pts * B, 8.0 * (2.0 * pts + 3.0 * nb * job.box[0].nmodes * job.L * B * B),
+                     "k_block_cr");
+        if (!launch_block_cr(job, p.stream)) return fail(ASDSM_E_ARG, "line solve: unsupported shape");
+        if (int rc = check_launch("block cyclic reduction")) return rc;
+    }
+    for (int b = 0; b < nb; ++b) T[b] = p.dVc[p.mesh[masks[b]].ax[2]];
+    const double *Yc[kMaxD];
+    for (int b = 0; b < nb; ++b) Yc[b] = Y[b];
+    return transform_position(p, m, 2, nb, Yc, T, out, accum);
+}
+
 // Direct solve of nb meshes of one shape that have a line axis (Plan::line_pos, any d): the other
 // fine axes are diagonalised by mode transforms, then block cyclic reduction runs along the line
 // axis with the mesh's coarse block as blocks (k_blockcr.hip), then the backward transforms.
@@ -311,6 +359,7 @@ int solve_mesh_line(Plan &p, int nb, const unsigned *masks, const double *const 
     // transformed positions per mesh (none when both fine axes are on the line solve; the meshes
     // of one call are all of one kind)
     const bool block2 = p.line_block2[masks[0]];
+    if (p.line_cmodes[masks[0]]) return solve_mesh_cmodes(p, nb, masks, in, out, accum);
     const int nt = block2 ? 0 : m.nfine - 1;
     int fq[kMaxD][kMaxD];        // [box][t]: the transformed canonical positions, ascending
     for (int b = 0; b < nb; ++b) {
@@ -544,16 +593,17 @@ int solve_aniso(Plan &p, unsigned kbits, double *const *in, double *const *out, 
         if ((kbits >> k) & 1u) ks[nb++] = k;
     if (nb == 0) return ASDSM_OK;
     if (d == 4 || p.line_aniso) {
-        // the meshes with a transformed fine axis first (their first launch is a transform, which
-        // may carry the previous step's stopping rule), then those with both fine axes on the line
-        for (int kind = 0; kind < 2; ++kind) {
+        // the meshes with a transformed axis first (their first launch is a transform, which may
+        // carry the previous step's stopping rule): a fine axis, then the coarse axis of meshes with
+        // both fine axes on the line; last those that transform nothing (one line solve per mesh)
+        for (int kind = 0; kind < 3; ++kind) {
             unsigned masks[kMaxD];
             const double *bin[kMaxD];
             double *bout[kMaxD];
             int ng = 0;
             for (int q = 0; q < nb; ++q) {
                 const unsigned mq = 1u << ks[q];
-                if ((int)p.line_block2[mq] != kind) continue;
+                if ((p.line_cmodes[mq] ? 1 : p.line_block2[mq] ? 2 : 0) != kind) continue;
                 masks[ng] = mq;
                 bin[ng] = in[ks[q]];
                 bout[ng] = out[ks[q]];
@@ -1256,7 +1306,7 @@ int error_guess(Plan &p) {
         if (!fused && p.line_aniso && p.d == 3) {
             fused = true;
             for (int k = 1; k < 3; ++k) fused = fused && p.line_pos[1u << k] == p.line_pos[1u];
-            for (int k = 0; k < 3; ++k) fused = fused && !p.line_block2[1u << k];
+            for (int k = 0; k < 3; ++k) fused = fused && !p.line_block2[1u << k] && !p.line_cmodes[1u << k];
         }
         p.norm_partials = fused ? p.ws.partials : nullptr;
         p.norm_nblk = p.Nc * ((p.Nf + 15) / 16);  // the plane kernel's count (the GEMM sets its own)

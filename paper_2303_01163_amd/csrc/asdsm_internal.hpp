@@ -170,6 +170,12 @@ struct Plan {
     // canonical position 0 and the block holds the other fine axis with the coarse axis (N_f N_c
     // points, no mode axes); solved by the GEMM form of the block cyclic reduction
     bool line_block2[kMaxMeshes] = {};
+    // d = 3 anisotropic mesh whose two fine axes both defeat fast diagonalisation while its coarse
+    // axis does not: that axis is diagonalised (coarse_spec), and per coarse mode the line solve
+    // runs along canonical position 0 with the other fine axis (N_f points) as its block
+    bool line_cmodes[kMaxMeshes] = {};
+    AxisSpectrum coarse_spec[kMaxD];  // size N_c, for the meshes with line_cmodes
+    double *dWc[kMaxD] = {}, *dVc[kMaxD] = {};
     // holes of up to 7^3 points with two or more axes that defeat fast diagonalisation: the hole
     // operator's inverse, applied densely by the generic filler (host copy while the plan is
     // built; device copy in the table allocation)
@@ -274,9 +280,11 @@ struct Plan {
 
 // block size and mode count of the line solve of mesh s (line_pos[s] >= 0)
 inline int cr_block(const Plan &p, unsigned s) {
+    if (p.line_cmodes[s]) return p.mesh[s].ext[1];
     return p.line_block2[s] ? p.mesh[s].ext[1] * p.mesh[s].block : p.mesh[s].block;
 }
 inline long long cr_modes(const Plan &p, unsigned s) {
+    if (p.line_cmodes[s]) return p.mesh[s].block;
     return p.line_block2[s] ? 1 : p.mesh[s].nmodes / p.mesh[s].ext[p.line_pos[s]];
 }
 

@@ -393,10 +393,12 @@ static bool build_cr_tables(Plan &p, unsigned mask) {
     const Tri tw = p.geo.fine[m.ax[lp]];
     // Kronecker-sum matrix of the block's axes (canonical order, first fastest): the coarse axes,
     // preceded by the second fine axis when both fine axes are on the line solve (line_block2)
-    const int qb = p.line_block2[mask] ? 1 : m.nfine;  // first canonical position of the block
+    const bool cmodes = p.line_cmodes[mask];
+    const int qb = (p.line_block2[mask] || cmodes) ? 1 : m.nfine;  // first canonical position of the block
+    const int qe = cmodes ? 2 : m.nd;                                // one past its last
     std::vector<double> Kc(MM, 0.0);
     long long cs = 1;
-    for (int q = qb; q < m.nd; ++q) {
+    for (int q = qb; q < qe; ++q) {
         const Tri t = (q < m.nfine) ? p.geo.fine[m.ax[q]] : p.geo.coarse[m.ax[q]];
         const int e = m.ext[q];
         for (int idx = 0; idx < NB; ++idx) {
@@ -422,6 +424,7 @@ static bool build_cr_tables(Plan &p, unsigned mask) {
                 rem /= m.ext[fq[t]];
                 sigma += p.fine_spec[m.ax[fq[t]]].mu[mq];
             }
+            if (cmodes) sigma += p.coarse_spec[m.ax[2]].mu[mode];  // the diagonalised coarse axis
             B = Kc;
             std::fill(A.begin(), A.end(), 0.0);
             std::fill(C.begin(), C.end(), 0.0);
@@ -705,13 +708,27 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         const int a = sweeps_for(cA), b = sweeps_for(cB);
         if (worse(a, swA)) swA = a;
         if (b < 0) {
-            // both fine axes defeat fast diagonalisation: d = 3 meshes whose block (the second fine
-            // axis with the coarse axis, N_f N_c points) fits the line solve take both on it
-            if (d != 3 || (long long)p.Nf * m.block > kCrMaxBlock)
-                return fail(ASDSM_E_UNSUPPORTED, "a submesh has two fine axes that fast diagonalisation cannot "
-                                                 "handle (|cell Peclet| near or above 1 on two axes) and more "
-                                                 "than " + std::to_string(kCrMaxBlock) + " points per line position");
-            p.line_block2[1u << k] = true;
+            // both fine axes defeat fast diagonalisation (d = 3): a mesh whose block of the second
+            // fine axis with the coarse axis (N_f N_c points) fits the line solve takes both on it;
+            // else, if the coarse axis can be diagonalised without refinement, each of its modes
+            // leaves a line solve with the second fine axis as the block
+            if (d != 3)
+                return fail(ASDSM_E_UNSUPPORTED, "a d = 4 submesh has two fine axes that fast diagonalisation "
+                                                 "cannot handle (|cell Peclet| near or above 1 on two axes)");
+            if ((long long)p.Nf * m.block <= kCrMaxBlock) {
+                p.line_block2[1u << k] = true;
+            } else {
+                const Tri tc = g.coarse[k];
+                const bool real = std::fabs(beta[k] * p.H / (2.0 * alpha[k])) < 1.0;
+                if (real) spectrum(tc, p.Nc, p.coarse_spec[k]);
+                if (!real || sweeps_for(p.coarse_spec[k].cond) != 0)
+                    return fail(ASDSM_E_UNSUPPORTED, "a submesh has two fine axes that fast diagonalisation "
+                                                     "cannot handle (|cell Peclet| near or above 1 on two axes), "
+                                                     "more than " + std::to_string(kCrMaxBlock) +
+                                                     " points per line position, and a coarse axis that "
+                                                     "cannot be diagonalised either");
+                p.line_cmodes[1u << k] = true;
+            }
             block2 = true;
             continue;
         }
@@ -721,9 +738,9 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     for (unsigned s = 0; s < kMaxMeshes; ++s) p.line_pos[s] = -1;
     for (int k = 0; k < d; ++k) {
         const unsigned m = 1u << k;
-        if (p.line_block2[m]) {
+        if (p.line_block2[m] || p.line_cmodes[m]) {
             p.line_pos[m] = 0;
-            p.fdm_cond[m] = 1.0;
+            p.fdm_cond[m] = p.line_cmodes[m] ? p.coarse_spec[k].cond : 1.0;
             p.sweeps[m] = 0;
         } else if (p.line_aniso) {
             p.line_pos[m] = lineq[k];
@@ -845,6 +862,12 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         else if (__builtin_popcount(s) >= 2) oD[s] = add(p.dense_inv[s]);
     }
     const size_t oH = p.hole_dense ? add(p.hole_inv) : 0;
+    size_t oWc[kMaxD] = {}, oVc[kMaxD] = {};
+    for (int k = 0; k < d; ++k)
+        if (p.line_cmodes[1u << k]) {
+            oWc[k] = add(p.coarse_spec[k].W);
+            oVc[k] = add(p.coarse_spec[k].V);
+        }
     p.dtab_bytes = off;
     err = hipMalloc(&p.dtab, p.dtab_bytes);
     if (err != hipSuccess) return fail(ASDSM_E_DEVICE, std::string("hipMalloc(tables): ") + hipGetErrorString(err));
@@ -874,6 +897,11 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     }
     for (unsigned s = 0; s < kMaxMeshes; ++s) std::vector<double>().swap(p.cr_tab[s]);
     if (p.hole_dense) p.dhinv = (double *)(base + oH);
+    for (int k = 0; k < d; ++k)
+        if (p.line_cmodes[1u << k]) {
+            p.dWc[k] = (double *)(base + oWc[k]);
+            p.dVc[k] = (double *)(base + oVc[k]);
+        }
     std::vector<double>().swap(p.hole_inv);
     err = hipHostMalloc((void **)&p.hscal, kScalCount * sizeof(double), hipHostMallocDefault);
     if (err == hipSuccess) err = hipHostMalloc((void **)&p.hstate, sizeof(IterState), hipHostMallocDefault);

@@ -372,6 +372,17 @@ def test_three_complex_axes_at_31(torch_dev):
         assert axes[1 << k][0] == (1 if k == 0 else 0)   # position 0 of M_k: its first fine axis
 
 
+def test_two_ill_conditioned_axes_at_127_diagonalise_the_coarse_axis(torch_dev):
+    """127^3 with two fine axes at cell Peclet 0.27 (eigenvector matrices of condition ~1e15, past
+    what refinement sweeps recover; the 15^3 holes still take them): the mesh with both as fine axes
+    would need a 127 * 7-point block, so it diagonalises its coarse axis instead and solves, per
+    coarse mode, along one fine axis with the other (127 points) as the block; every submesh solve
+    and the iterates, fine-mesh and skeleton-sparse, match the banded-LU oracle."""
+    P = make_problem("sinbump3d", 7, seed=3, alpha=[0.1, 0.1, 1.0], beta=[7.0, -7.0, 1.0])
+    pl = _two_axes_parity(torch_dev, P, 7, 3, 8)
+    assert pl.line_axes()[1 << 2] == (0, 0)   # M_2: the line along axis 0, no sweeps
+
+
 def test_two_complex_axes_beyond_the_limits_are_refused(torch_dev):
     """Beyond what is built: two fine axes with |cell Peclet| > 1 at 127^3 (a 127 * 7-point block,
     holes of 15^3 with two such axes) report ASDSM_E_UNSUPPORTED instead of returning inaccurate
