@@ -136,8 +136,9 @@ typedef struct {
  * A fine axis that fast diagonalisation cannot handle (|cell Peclet| >= 1: complex spectrum; or an
  * eigenvector matrix too ill-conditioned for FP64) is solved along lines by block cyclic reduction
  * (asdsm_line_axes reports which).  For d = 3, an anisotropic mesh with two such fine axes takes
- * both on its line solve (the line along one, the other fine axis with the coarse axis as its
- * N_f N_c-point block, up to 512), and hole boxes with two or three such axes apply the inverse of
+ * both on its line solve: the line along one, and as its block the other fine axis with the coarse
+ * axis (N_f N_c points, up to 512), or else, when its coarse axis can be diagonalised, the other
+ * fine axis alone per coarse mode; hole boxes with two or three such axes apply the inverse of
  * their operator densely (holes of up to 7^3 points).
  * Errors: ASDSM_E_ARG, ASDSM_E_NESTING, ASDSM_E_UNSUPPORTED (two such axes beyond those limits, or
  * in d = 4; hole boxes too large for one workgroup's LDS), ASDSM_E_NUMERIC (a singular block),
