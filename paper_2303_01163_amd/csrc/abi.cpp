@@ -1273,7 +1273,8 @@ int initial_guess(Plan &p, const double *s, const double *g, double *u) {
     {
         PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
                      8.0 * ((double)p.geo.NF + hole_points(p) + aniso_points(p)));
-        launch_filler(p, p.ws.b, u, p.stream);
+        if (!launch_filler(p, p.ws.b, u, p.stream))
+            return fail(ASDSM_E_ARG, "hole solve: unsupported shape");
         if (int rc = check_launch("filler")) return rc;
     }
     {
@@ -1336,7 +1337,8 @@ int refine_step(Plan &p, const double *u_cur, double *u_next) {
     {
         PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
                      8.0 * ((double)p.geo.NF + aniso_points(p)), "hole filler (error guess)");
-        launch_filler(p, nullptr, p.ws.e, p.stream);
+        if (!launch_filler(p, nullptr, p.ws.e, p.stream))
+            return fail(ASDSM_E_ARG, "hole solve: unsupported shape");
         if (int rc = check_launch("filler")) return rc;
     }
     {
@@ -1389,7 +1391,8 @@ int sparse_step(Plan &p) {
     const double skel = aniso_points(p);  // skeleton points counted once per mesh
     {
         PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p), 8.0 * (3.0 * skel), "hole filler (layer mode)");
-        launch_filler(p, nullptr, nullptr, p.stream, nullptr, true);
+        if (!launch_filler(p, nullptr, nullptr, p.stream, nullptr, true))
+            return fail(ASDSM_E_ARG, "hole solve: unsupported shape");
         if (int rc = check_launch("filler (layers)")) return rc;
     }
     {
@@ -1721,7 +1724,8 @@ int begin_solve(Plan &p, const double *s, const double *g, double *u, const asds
         {
             PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
                          8.0 * (2.0 * (double)p.geo.NF + aniso_points(p)));
-            launch_filler(p, p.ws.b, u, p.stream, p.ws.SU, false);
+            if (!launch_filler(p, p.ws.b, u, p.stream, p.ws.SU, false))
+                return fail(ASDSM_E_ARG, "hole solve: unsupported shape");
             if (int rc = check_launch("resume fill")) return rc;
         }
         PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,
@@ -1762,7 +1766,8 @@ int finish_sparse(Plan &p, double *u) {
     {
         PhaseTimer t(p, ASDSM_PHASE_FILLER, 1, filler_flops(p),
                      8.0 * (2.0 * (double)p.geo.NF + aniso_points(p)));
-        launch_filler(p, p.ws.b, u, p.stream, p.ws.SU, false);
+        if (!launch_filler(p, p.ws.b, u, p.stream, p.ws.SU, false))
+            return fail(ASDSM_E_ARG, "hole solve: unsupported shape");
         if (int rc = check_launch("final fill")) return rc;
     }
     PhaseTimer t(p, ASDSM_PHASE_UPDATE, 1, 2.0 * (2 * p.d + 1) * (double)p.geo.NF,

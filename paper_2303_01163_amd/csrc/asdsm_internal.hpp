@@ -108,6 +108,9 @@ struct Workspace {
     // (block_cr_gemm), and its length in doubles
     double *crs = nullptr;
     long long crs_len = 0;
+    // hole right-hand sides and solutions of the hole line solve (Plan::hole_cr): per hole nh^3
+    // values, the line axis slowest and the block (the other two axes, the lower fastest) fastest
+    double *HB = nullptr;
     IterState *state = nullptr;  // refinement-loop state
     double *hist = nullptr;      // ||r_k||, k = 0..it
     double *step_hist = nullptr; // s_hat_k
@@ -182,6 +185,14 @@ struct Plan {
     bool hole_dense = false;
     std::vector<double> hole_inv;
     double *dhinv = nullptr;
+    // d = 3 holes of 15^3 points with two or more such axes: block cyclic reduction along the hole
+    // line axis with the other two axes (225 points, the lower axis fastest) as its block, one table
+    // (per level G, P, Q) shared by every hole, run as batched GEMMs over the holes (hole_cr_tab:
+    // host copy while the plan is built)
+    bool hole_cr = false;
+    int hole_cr_L = 0;
+    std::vector<double> hole_cr_tab;
+    double *dhcr = nullptr;
     int cr_tm = 0;                     // modes per workgroup of their line solve (0: by size)
     std::vector<double> cr_tab[kMaxMeshes];  // host copies while the plan is built
     double *dcr[kMaxMeshes] = {};      // per mode and level: G, P, Q (device)

@@ -510,7 +510,7 @@ static bool block_cr_gemm(const CrJob &job, hipStream_t st) {
         g.M = NB;
         g.K = NB;
         g.nbatch = (int)bx.nmodes;
-        g.sAb = (long long)L * 3 * MM;
+        g.sAb = job.shared_tab ? 0 : (long long)L * 3 * MM;
         g.sAi = NB;
         g.sAk = 1;
         g.sBb = ms;
@@ -607,6 +607,8 @@ int cr2_modes_per_group(int N, int L, int NB, long long nmodes, int nbox, int wa
 bool cr_lds_supported(int NB) { return NB == 1 || NB == 3 || NB == 7 || NB == 9 || NB == 15; }
 
 bool launch_block_cr(const CrJob &job, hipStream_t st) {
+    if (job.shared_tab)  // only the GEMM form indexes one table for all modes
+        return job.tm == 0 && !job.fast && !job.accum && job.scratch && block_cr_gemm(job, st);
     long long maxm = 0;
     for (int b = 0; b < job.nbox; ++b) maxm = std::max(maxm, job.box[b].nmodes);
     if (job.fast) {

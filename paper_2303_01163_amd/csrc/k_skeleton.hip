@@ -604,6 +604,11 @@ struct FillArgs {
     // non-null (k_filler, d = 3): the hole operator's inverse, column by column ((n-1)^3 squared),
     // applied densely instead of the transforms and the line elimination
     const double *hinv;
+    // hole line solve in global memory (k_filler, d = 3): phase 1 stores each hole's right-hand
+    // side at hbuf (hole-major, the line axis slowest, the lower other axis fastest) and ends;
+    // phase 2 takes the hole values from there; 0: the solve in LDS
+    int hphase;
+    double *hbuf;
 };
 
 template <int D, int NH>
@@ -639,8 +644,19 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
             rem /= (Nc + 1);
         }
     }
+    // offset of hole point o in hbuf (phases 1 and 2, D = 3)
+    auto hoff = [&](int o) -> long long {
+        const int l0 = o % nh, l1 = (o / nh) % nh, l2 = o / (nh * nh);
+        const int la = a.line_axis;
+        const int ll = (la == 0) ? l0 : (la == 1) ? l1 : l2;
+        const int c0 = (la == 0) ? l1 : l0, c1 = (la == 2) ? l1 : l2;
+        return (long long)blockIdx.x * npts + (long long)ll * (nh * nh) + c0 + nh * c1;
+    };
+    if (D == 3 && a.hphase == 2) {
+        for (int o = tid; o < npts; o += 256) bufA[o] = a.hbuf[hoff(o)];
+    }
     // 1) hole right-hand side
-    for (int o = tid; o < npts; o += 256) {
+    for (int o = tid; o < npts && a.hphase != 2; o += 256) {
         int l[kMaxD] = {0, 0, 0, 0}, i[kMaxD] = {0, 0, 0, 0};
         int rem = o;
         for (int j = 0; j < D; ++j) {
@@ -662,8 +678,10 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
                 v -= g.fine[j].c * a.skel[j][canon_offset(a.mk[j], q, n)];
             }
         }
-        bufA[o] = v;
+        if (D == 3 && a.hphase == 1) a.hbuf[hoff(o)] = v;
+        else bufA[o] = v;
     }
+    if (a.hphase == 1) return;
     __syncthreads();
     double *cur = bufA, *oth = bufB;
     if (a.hinv) {
@@ -696,7 +714,7 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
         oth = t;
     }
     // 3) line elimination along the line axis, one thread per line
-    if (!a.hinv) {
+    if (!a.hinv && a.hphase == 0) {
         const int L = a.line_axis;
         const int nlines = npts / nh;
         const Tri t = g.fine[L];
@@ -1300,7 +1318,7 @@ __global__ __launch_bounds__(256, 2) void k_filler_mfma3(Geo g, FillArgs a) {
     }
 }
 
-void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st, double *const *skel,
+bool launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st, double *const *skel,
                    bool adj_only) {
     FillArgs a;
     const int d = p.d, nh = p.n - 1;
@@ -1322,6 +1340,9 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
     a.adj_only = adj_only ? 1 : 0;
     a.gate = p.gate;
     a.hinv = nullptr;
+    a.hphase = 0;
+    a.hbuf = nullptr;
+    if (p.hole_dense || p.hole_cr) a.ntr = 0;
     if (p.hole_dense) {  // d = 3, holes of up to 7^3: the dense inverse in the generic filler
         a.hinv = p.dhinv;
         a.ntr = 0;
@@ -1339,7 +1360,38 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
             case 3: ASDSM_LAUNCH((k_filler<3, 3>), grid, blk, ldsd, st, p.geo, a); break;
             default: ASDSM_LAUNCH((k_filler<3, 7>), grid, blk, ldsd, st, p.geo, a); break;
         }
-        return;
+        return true;
+    }
+    if (p.hole_cr) {
+        // d = 3, holes of 15^3: right-hand sides to HB, block cyclic reduction over all holes in
+        // place (one shared table, the GEMM form), the tiles from HB
+        if (d != 3 || nh != 15 || !p.ws.HB) return false;
+        const size_t ldsd = (size_t)2 * npts * sizeof(double);
+        a.hbuf = p.ws.HB;
+        a.hphase = 1;
+        ASDSM_LAUNCH((k_filler<3, 15>), grid, blk, 0, st, p.geo, a);
+        CrJob job{};
+        job.nbox = 1;
+        job.N = nh;
+        job.L = p.hole_cr_L;
+        job.NB = nh * nh;
+        job.gate = p.gate;
+        job.scratch = p.ws.crs;
+        job.scratch_len = p.ws.crs_len;
+        job.shared_tab = 1;
+        CrBox &bx = job.box[0];
+        bx.src = bx.dst = p.ws.HB;
+        bx.tab = p.dhcr;
+        bx.nmodes = tiles;
+        bx.mext0 = tiles;
+        bx.ms0 = npts;
+        bx.ms1 = (long long)tiles * npts;
+        bx.sw = nh * nh;
+        bx.sc = 1;
+        if (!launch_block_cr(job, st)) return false;
+        a.hphase = 2;
+        ASDSM_LAUNCH((k_filler<3, 15>), grid, blk, ldsd, st, p.geo, a);
+        return true;
     }
     if (d == 3 && nh == 15) {
 #define ASDSM_FILL3(LL)                                                                   \
@@ -1351,7 +1403,7 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
         else if (p.hole_line_axis == 1) ASDSM_FILL3(1);
         else ASDSM_FILL3(2);
 #undef ASDSM_FILL3
-        return;
+        return true;
     }
     if (!adj_only && (d == 3 || d == 4) && (nh == 1 || nh == 3 || nh == 7)) {
 #define ASDSM_FILL_LINES(DD, NHV) ASDSM_LAUNCH((k_filler_lines<DD, NHV>), grid, blk, 0, st, p.geo, a)
@@ -1365,7 +1417,7 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
             else ASDSM_FILL_LINES(4, 7);
         }
 #undef ASDSM_FILL_LINES
-        return;
+        return true;
     }
 #define ASDSM_FILL(DD, NHV) ASDSM_LAUNCH((k_filler<DD, NHV>), grid, blk, lds, st, p.geo, a)
     if (d == 2) {
@@ -1394,6 +1446,7 @@ void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
         }
     }
 #undef ASDSM_FILL
+    return true;
 }
 
 }  // namespace asdsm

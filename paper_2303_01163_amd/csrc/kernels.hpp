@@ -58,6 +58,7 @@ struct CrJob {
     // scratch of at least NB * 2^(L-1) * nmodes doubles for the box with the most modes
     double *scratch;
     long long scratch_len;
+    int shared_tab;      // 1: every mode uses the one table at box[b].tab (GEMM form only)
 };
 constexpr size_t kCrMaxLds = 64 * 1024;
 size_t cr_lds_bytes(int N, int NB, int tm);
@@ -218,7 +219,7 @@ void launch_merge4(const Plan &p, int mode, const double *const *res, hipStream_
 // skel: the merged skeleton values per anisotropic mesh (default: the Y buffers); adj_only: write the
 // hole layers next to each coarse plane into the EA buffers instead of the fine tiles (the error
 // equation of the skeleton-sparse step: bff must be null, the holes' right-hand side is zero)
-void launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st, double *const *skel = nullptr,
+bool launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st, double *const *skel = nullptr,
                    bool adj_only = false);
 // skeleton-sparse refinement (k_sparse.hip)
 void launch_skel_gather(const Plan &p, const double *u, hipStream_t st);

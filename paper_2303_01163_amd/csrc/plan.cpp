@@ -379,6 +379,41 @@ static void matmul(int n, const double *A, const double *B, double *C) {
     for (std::thread &th : pool) th.join();
 }
 
+// The level tables of one system of block cyclic reduction: B_0 = Kc + (b_w + sigma) I, A_0 = a_w I,
+// C_0 = c_w I; per level G, P, Q (row major) into dst, L * 3 * NB^2 doubles.  False on a singular
+// block.
+static bool cr_level_tables(int NB, int L, const std::vector<double> &Kc, Tri tw, double sigma, double *dst0) {
+    const size_t MM = (size_t)NB * NB;
+    std::vector<double> B(Kc), A(MM, 0.0), C(MM, 0.0), G(MM), T1(MM), T2(MM), LU(MM), inv(MM);
+    for (int i = 0; i < NB; ++i) {
+        B[(size_t)i * NB + i] += tw.b + sigma;
+        A[(size_t)i * NB + i] = tw.a;
+        C[(size_t)i * NB + i] = tw.c;
+    }
+    for (int l = 0; l < L; ++l) {
+        LU = B;
+        if (!dense_inverse(NB, LU, inv.data())) return false;
+        for (int i = 0; i < NB; ++i)  // dense_inverse writes column by column
+            for (int j = 0; j < NB; ++j) G[(size_t)i * NB + j] = inv[(size_t)j * NB + i];
+        double *dst = dst0 + (size_t)l * 3 * MM;
+        std::copy(G.begin(), G.end(), dst);
+        matmul(NB, G.data(), A.data(), dst + MM);
+        matmul(NB, G.data(), C.data(), dst + 2 * MM);
+        if (l == L - 1) break;
+        // B -= A G C + C G A;  A = -A G A;  C = -C G C
+        matmul(NB, A.data(), dst + 2 * MM, T1.data());   // A (G C)
+        matmul(NB, C.data(), dst + MM, T2.data());       // C (G A)
+        for (size_t e = 0; e < MM; ++e) B[e] -= T1[e] + T2[e];
+        matmul(NB, A.data(), dst + MM, T1.data());       // A G A
+        matmul(NB, C.data(), dst + 2 * MM, T2.data());   // C G C
+        for (size_t e = 0; e < MM; ++e) {
+            A[e] = -T1[e];
+            C[e] = -T2[e];
+        }
+    }
+    return true;
+}
+
 // Reduced blocks of block cyclic reduction along the line axis of mesh `mask` (k_blockcr.hip): per
 // mode of the other fine axes, B_0 = T_block + (b_w + sigma) I, A_0 = a_w I, C_0 = c_w I and per
 // level G_l = B_l^-1, P_l = G_l A_l, Q_l = G_l C_l, then B_(l+1) = B_l - A_l G_l C_l - C_l G_l A_l,
@@ -415,7 +450,6 @@ static bool build_cr_tables(Plan &p, unsigned mask) {
     std::vector<double> &out = p.cr_tab[mask];
     out.assign((size_t)nmodes * L * 3 * MM, 0.0);
     auto run = [&](long long m0, long long m1, bool *ok) {
-        std::vector<double> B(MM), A(MM), C(MM), G(MM), T1(MM), T2(MM), LU(MM), inv(MM);
         for (long long mode = m0; mode < m1; ++mode) {
             double sigma = 0.0;
             long long rem = mode;
@@ -425,37 +459,9 @@ static bool build_cr_tables(Plan &p, unsigned mask) {
                 sigma += p.fine_spec[m.ax[fq[t]]].mu[mq];
             }
             if (cmodes) sigma += p.coarse_spec[m.ax[2]].mu[mode];  // the diagonalised coarse axis
-            B = Kc;
-            std::fill(A.begin(), A.end(), 0.0);
-            std::fill(C.begin(), C.end(), 0.0);
-            for (int i = 0; i < NB; ++i) {
-                B[(size_t)i * NB + i] += tw.b + sigma;
-                A[(size_t)i * NB + i] = tw.a;
-                C[(size_t)i * NB + i] = tw.c;
-            }
-            for (int l = 0; l < L; ++l) {
-                LU = B;
-                if (!dense_inverse(NB, LU, inv.data())) {
-                    *ok = false;
-                    return;
-                }
-                for (int i = 0; i < NB; ++i)  // dense_inverse writes column by column
-                    for (int j = 0; j < NB; ++j) G[(size_t)i * NB + j] = inv[(size_t)j * NB + i];
-                double *dst = out.data() + ((size_t)mode * L + l) * 3 * MM;
-                std::copy(G.begin(), G.end(), dst);
-                matmul(NB, G.data(), A.data(), dst + MM);
-                matmul(NB, G.data(), C.data(), dst + 2 * MM);
-                if (l == L - 1) break;
-                // B -= A G C + C G A;  A = -A G A;  C = -C G C
-                matmul(NB, A.data(), dst + 2 * MM, T1.data());   // A (G C)
-                matmul(NB, C.data(), dst + MM, T2.data());       // C (G A)
-                for (size_t e = 0; e < MM; ++e) B[e] -= T1[e] + T2[e];
-                matmul(NB, A.data(), dst + MM, T1.data());       // A G A
-                matmul(NB, C.data(), dst + 2 * MM, T2.data());   // C G C
-                for (size_t e = 0; e < MM; ++e) {
-                    A[e] = -T1[e];
-                    C[e] = -T2[e];
-                }
+            if (!cr_level_tables(NB, L, Kc, tw, sigma, out.data() + (size_t)mode * L * 3 * MM)) {
+                *ok = false;
+                return;
             }
         }
     };
@@ -517,8 +523,13 @@ void layout_workspace(Plan &p, char *base, bool assign) {
             if (p.line_pos[s] < 0 || cr_lds_supported(cr_block(p, s))) continue;
             need = std::max(need, (long long)cr_block(p, s) * (1ll << (p.level - 1)) * cr_modes(p, s));
         }
+        long long holes = 1;
+        for (int j = 0; j < p.d; ++j) holes *= p.Nc + 1;
+        const long long nh = p.n - 1;
+        if (p.hole_cr) need = std::max(need, nh * nh * (1ll << (p.hole_cr_L - 1)) * holes);
         w.crs_len = need;
         w.crs = need ? (double *)take((size_t)need * 8) : nullptr;
+        if (p.hole_cr) w.HB = (double *)take((size_t)(holes * nh * nh * nh) * 8);
     }
     // cross-point discrepancies of each anisotropic mesh: d=2: Nc*Nc; d=3: parts A, B, R of
     // Nc*Nc*Nf values each; d=4: three plane families and two Boolean-sum remainders of
@@ -647,12 +658,33 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
             if (j != p.hole_line_axis) ch *= cond_h[j];
         if (!(2.2e-16 * ch <= 1e-12)) {
             // two or more such axes: holes of up to kHoleDenseMax^3 points (d = 3) take the hole
-            // operator's inverse, applied densely
-            if (d != 3 || p.n - 1 > kHoleDenseMax)
+            // operator's inverse, applied densely; holes of 15^3 the hole line solve
+            if (d != 3 || (p.n - 1 > kHoleDenseMax && p.n - 1 != 15))
                 return fail(ASDSM_E_UNSUPPORTED, "hole boxes: more than one axis too ill-conditioned for "
                                                  "fast diagonalisation (|cell Peclet| near or above 1)");
-            p.hole_dense = true;
+            if (p.n - 1 <= kHoleDenseMax) p.hole_dense = true;
+            else p.hole_cr = true;
         }
+    }
+    if (p.hole_cr) {
+        // block cyclic reduction along the hole line axis: the block operator is the Kronecker sum
+        // of the other two axes' fine-spacing operators on nh^2 points (the lower axis fastest)
+        const int nh = p.n - 1, NB = nh * nh, la = p.hole_line_axis;
+        const int ax0 = (la == 0) ? 1 : 0, ax1 = (la == 2) ? 1 : 2;
+        std::vector<double> Kc((size_t)NB * NB, 0.0);
+        for (int o = 0; o < NB; ++o) {
+            const int c0 = o % nh, c1 = o / nh;
+            const Tri t0 = g.fine[ax0], t1 = g.fine[ax1];
+            Kc[(size_t)o * NB + o] = t0.b + t1.b;
+            if (c0 > 0) Kc[(size_t)o * NB + o - 1] = t0.a;
+            if (c0 < nh - 1) Kc[(size_t)o * NB + o + 1] = t0.c;
+            if (c1 > 0) Kc[(size_t)o * NB + o - nh] = t1.a;
+            if (c1 < nh - 1) Kc[(size_t)o * NB + o + nh] = t1.c;
+        }
+        p.hole_cr_L = 4;  // nh = 2^4 - 1
+        p.hole_cr_tab.assign((size_t)p.hole_cr_L * 3 * NB * NB, 0.0);
+        if (!cr_level_tables(NB, p.hole_cr_L, Kc, g.fine[la], 0.0, p.hole_cr_tab.data()))
+            return fail(ASDSM_E_NUMERIC, "singular reduced block of the hole line solve");
     }
     if (p.hole_dense) {
         // the hole operator: the Kronecker sum of the three fine-spacing 1D operators on (n-1)^3
@@ -862,6 +894,7 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
         else if (__builtin_popcount(s) >= 2) oD[s] = add(p.dense_inv[s]);
     }
     const size_t oH = p.hole_dense ? add(p.hole_inv) : 0;
+    const size_t oHC = p.hole_cr ? add(p.hole_cr_tab) : 0;
     size_t oWc[kMaxD] = {}, oVc[kMaxD] = {};
     for (int k = 0; k < d; ++k)
         if (p.line_cmodes[1u << k]) {
@@ -897,12 +930,14 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
     }
     for (unsigned s = 0; s < kMaxMeshes; ++s) std::vector<double>().swap(p.cr_tab[s]);
     if (p.hole_dense) p.dhinv = (double *)(base + oH);
+    if (p.hole_cr) p.dhcr = (double *)(base + oHC);
     for (int k = 0; k < d; ++k)
         if (p.line_cmodes[1u << k]) {
             p.dWc[k] = (double *)(base + oWc[k]);
             p.dVc[k] = (double *)(base + oVc[k]);
         }
     std::vector<double>().swap(p.hole_inv);
+    std::vector<double>().swap(p.hole_cr_tab);
     err = hipHostMalloc((void **)&p.hscal, kScalCount * sizeof(double), hipHostMallocDefault);
     if (err == hipSuccess) err = hipHostMalloc((void **)&p.hstate, sizeof(IterState), hipHostMallocDefault);
     if (err == hipSuccess)

@@ -268,8 +268,8 @@ def test_error_codes(torch_dev):
     with pytest.raises(AsdsmError) as e:
         Plan(2, [1.0, 1.0], [0.0, 0.0], 5, 5)
     assert e.value.code == -2
-    with pytest.raises(AsdsmError) as e:              # cell Peclet 1.17 on two fine axes at 127^3
-        Plan(3, [1.0, 1.0, 1.0], [300.0, 300.0, 0.0], 7)
+    with pytest.raises(AsdsmError) as e:              # cell Peclet 1.17 on every fine axis at 127^3,
+        Plan(3, [1.0, 1.0, 1.0], [300.0, 300.0, 300.0], 7)   # 18.75 on the coarse ones
     assert e.value.code == -6
     with pytest.raises(AsdsmError) as e:             # d outside 2..4
         Plan(5, [1.0] * 5, [0.0] * 5, 3)
@@ -383,13 +383,24 @@ def test_two_ill_conditioned_axes_at_127_diagonalise_the_coarse_axis(torch_dev):
     assert pl.line_axes()[1 << 2] == (0, 0)   # M_2: the line along axis 0, no sweeps
 
 
+def test_two_complex_axes_at_127_holes_take_the_line_solve(torch_dev):
+    """127^3 with two fine axes of cell Peclet 1.02 (complex 1D spectra): the 15^3 holes eliminate
+    along one hole axis with the other two (225 points) as the block, one table for every hole, as
+    batched GEMMs over the holes; the mesh with both as fine axes diagonalises its coarse axis.
+    Every submesh solve and the iterates, fine-mesh and skeleton-sparse (whose layer-mode fill runs
+    the same hole solve), match the banded-LU oracle."""
+    P = make_problem("sinbump3d", 7, seed=4, alpha=[0.1, 0.1, 0.8], beta=[26.0, -26.0, 1.0])
+    pl = _two_axes_parity(torch_dev, P, 7, 3, 9)
+    assert pl.line_axes()[1 << 2] == (0, 0)   # M_2: the line along axis 0, coarse axis diagonalised
+
+
 def test_two_complex_axes_beyond_the_limits_are_refused(torch_dev):
-    """Beyond what is built: two fine axes with |cell Peclet| > 1 at 127^3 (a 127 * 7-point block,
-    holes of 15^3 with two such axes) report ASDSM_E_UNSUPPORTED instead of returning inaccurate
-    solves; so does d = 4 with two such axes."""
+    """Beyond what is built: every axis with |cell Peclet| > 1 at 127^3 (fine and coarse spacing:
+    a 127 * 7-point block whose coarse axis cannot be diagonalised either) reports
+    ASDSM_E_UNSUPPORTED instead of returning inaccurate solves; so does d = 4 with two such axes."""
     from paper_2303_01163_amd.asdsm import AsdsmError, Plan
     with pytest.raises(AsdsmError) as e:
-        Plan(3, [0.1, 0.1, 0.8], [26.0, -26.0, 1.0], 7)
+        Plan(3, [0.1, 0.1, 0.1], [26.0, -26.0, 26.0], 7)
     assert e.value.code == -6
     with pytest.raises(AsdsmError) as e:
         Plan(4, [0.05, 0.05, 0.8, 0.8], [8.0, -8.0, 1.0, 1.0], 5, 2)
