@@ -138,7 +138,7 @@ typedef struct {
  * (asdsm_line_axes reports which).  For d = 3, an anisotropic mesh with two such fine axes takes
  * both on its line solve: the line along one, and as its block the other fine axis with the coarse
  * axis (N_f N_c points, up to 512), or else, when its coarse axis can be diagonalised, the other
- * fine axis alone per coarse mode; hole boxes with two or three such axes apply the inverse of
+ * fine axis alone per coarse mode, or else that N_f N_c block up to 1024 points; hole boxes with two or three such axes apply the inverse of
  * their operator densely (holes of up to 7^3 points) or, holes of 15^3, solve along one hole axis
  * by block cyclic reduction with the other two as the block.
  * Errors: ASDSM_E_ARG, ASDSM_E_NESTING, ASDSM_E_UNSUPPORTED (two such axes beyond those limits, or

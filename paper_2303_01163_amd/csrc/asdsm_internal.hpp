@@ -21,6 +21,9 @@ constexpr int kMaxD = 4;
 constexpr int kMaxMeshes = 1 << kMaxD;
 constexpr int kDenseMaxBlock = 4096;  // coarse points per mode of an intersection-mesh dense solve
 constexpr int kCrMaxBlock = 512;      // coarse points per position of a line solve
+// points per position of a line solve over a fine axis with the coarse axis when that coarse axis
+// cannot be diagonalised either (host-built tables of 3 L NB^2 doubles)
+constexpr int kCrMaxBlock2 = 1024;
 constexpr int kHoleDenseMax = 7;      // largest hole edge whose operator is inverted densely
 
 // Canonical layout of mesh M_S.

@@ -364,7 +364,19 @@ static void matmul(int n, const double *A, const double *B, double *C) {
                 C[(size_t)i * n + j] = acc;
             }
     };
-    // large blocks (the line solves whose block holds a fine axis): rows over host threads
+    // large blocks (the line solves whose block holds a fine axis): rows over host threads, each
+    // row accumulated along B's rows (contiguous loads)
+    auto rows_by_k = [&](int i0, int i1) {
+        for (int i = i0; i < i1; ++i) {
+            double *ci = C + (size_t)i * n;
+            std::fill(ci, ci + n, 0.0);
+            for (int k = 0; k < n; ++k) {
+                const double a = A[(size_t)i * n + k];
+                const double *bk = B + (size_t)k * n;
+                for (int j = 0; j < n; ++j) ci[j] += a * bk[j];
+            }
+        }
+    };
     const int nt = (n >= 128) ? std::max(1, std::min(16, (int)std::thread::hardware_concurrency())) : 1;
     if (nt == 1) {
         rows(0, n);
@@ -374,7 +386,7 @@ static void matmul(int n, const double *A, const double *B, double *C) {
     const int chunk = (n + nt - 1) / nt;
     for (int t = 0; t < nt; ++t) {
         const int i0 = t * chunk, i1 = std::min(n, i0 + chunk);
-        if (i0 < i1) pool.emplace_back(rows, i0, i1);
+        if (i0 < i1) pool.emplace_back(rows_by_k, i0, i1);
     }
     for (std::thread &th : pool) th.join();
 }
@@ -743,7 +755,8 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
             // both fine axes defeat fast diagonalisation (d = 3): a mesh whose block of the second
             // fine axis with the coarse axis (N_f N_c points) fits the line solve takes both on it;
             // else, if the coarse axis can be diagonalised without refinement, each of its modes
-            // leaves a line solve with the second fine axis as the block
+            // leaves a line solve with the second fine axis as the block; else blocks of up to
+            // kCrMaxBlock2 points
             if (d != 3)
                 return fail(ASDSM_E_UNSUPPORTED, "a d = 4 submesh has two fine axes that fast diagonalisation "
                                                  "cannot handle (|cell Peclet| near or above 1 on two axes)");
@@ -753,13 +766,16 @@ int build_plan(Plan &p, int d, const double *alpha, const double *beta, int leve
                 const Tri tc = g.coarse[k];
                 const bool real = std::fabs(beta[k] * p.H / (2.0 * alpha[k])) < 1.0;
                 if (real) spectrum(tc, p.Nc, p.coarse_spec[k]);
-                if (!real || sweeps_for(p.coarse_spec[k].cond) != 0)
+                if (real && sweeps_for(p.coarse_spec[k].cond) == 0)
+                    p.line_cmodes[1u << k] = true;
+                else if ((long long)p.Nf * m.block <= kCrMaxBlock2)
+                    p.line_block2[1u << k] = true;
+                else
                     return fail(ASDSM_E_UNSUPPORTED, "a submesh has two fine axes that fast diagonalisation "
                                                      "cannot handle (|cell Peclet| near or above 1 on two axes), "
-                                                     "more than " + std::to_string(kCrMaxBlock) +
+                                                     "more than " + std::to_string(kCrMaxBlock2) +
                                                      " points per line position, and a coarse axis that "
                                                      "cannot be diagonalised either");
-                p.line_cmodes[1u << k] = true;
             }
             block2 = true;
             continue;

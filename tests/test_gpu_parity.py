@@ -268,8 +268,8 @@ def test_error_codes(torch_dev):
     with pytest.raises(AsdsmError) as e:
         Plan(2, [1.0, 1.0], [0.0, 0.0], 5, 5)
     assert e.value.code == -2
-    with pytest.raises(AsdsmError) as e:              # cell Peclet 1.17 on every fine axis at 127^3,
-        Plan(3, [1.0, 1.0, 1.0], [300.0, 300.0, 300.0], 7)   # 18.75 on the coarse ones
+    with pytest.raises(AsdsmError) as e:              # cell Peclet 1.17 on every fine axis at 255^3,
+        Plan(3, [0.5, 0.5, 0.5], [300.0, 300.0, 300.0], 8)   # 18.75 on the coarse ones
     assert e.value.code == -6
     with pytest.raises(AsdsmError) as e:             # d outside 2..4
         Plan(5, [1.0] * 5, [0.0] * 5, 3)
@@ -394,13 +394,26 @@ def test_two_complex_axes_at_127_holes_take_the_line_solve(torch_dev):
     assert pl.line_axes()[1 << 2] == (0, 0)   # M_2: the line along axis 0, coarse axis diagonalised
 
 
+def test_three_complex_axes_at_127(torch_dev):
+    """127^3 with every axis advection-dominated (cell Peclet 1.02 at h = 1/128, 16 at the coarse
+    spacing): no coarse axis can be diagonalised, so each anisotropic mesh takes its two fine axes
+    and its coarse axis on one line solve (889-point blocks), and the holes (15^3, three such axes)
+    the hole line solve; every submesh solve and the iterates, fine-mesh and skeleton-sparse, match
+    the banded-LU oracle."""
+    P = make_problem("sinbump3d", 7, seed=5, alpha=[0.1, 0.1, 0.1], beta=[26.0, -26.0, 26.0])
+    pl = _two_axes_parity(torch_dev, P, 7, 3, 10)
+    axes = pl.line_axes()
+    for k in range(3):
+        assert axes[1 << k] == (1 if k == 0 else 0, 0)   # position 0 of M_k: its first fine axis
+
+
 def test_two_complex_axes_beyond_the_limits_are_refused(torch_dev):
-    """Beyond what is built: every axis with |cell Peclet| > 1 at 127^3 (fine and coarse spacing:
-    a 127 * 7-point block whose coarse axis cannot be diagonalised either) reports
+    """Beyond what is built: every axis with |cell Peclet| > 1 at 255^3 (fine and coarse spacing:
+    a 255 * 15-point block whose coarse axis cannot be diagonalised either) reports
     ASDSM_E_UNSUPPORTED instead of returning inaccurate solves; so does d = 4 with two such axes."""
     from paper_2303_01163_amd.asdsm import AsdsmError, Plan
     with pytest.raises(AsdsmError) as e:
-        Plan(3, [0.1, 0.1, 0.1], [26.0, -26.0, 26.0], 7)
+        Plan(3, [0.05, 0.05, 0.05], [26.0, -26.0, 26.0], 8)
     assert e.value.code == -6
     with pytest.raises(AsdsmError) as e:
         Plan(4, [0.05, 0.05, 0.8, 0.8], [8.0, -8.0, 1.0, 1.0], 5, 2)
