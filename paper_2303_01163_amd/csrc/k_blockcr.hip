@@ -19,6 +19,9 @@
 // One workgroup holds `tm` consecutive modes: the kept equations of level 0 (half the line) and the
 // current level's matrices are staged in LDS; a thread owns one (mode, equation) row-block at a
 // time, so every level is updated in place without hazards.
+#include <algorithm>
+#include <atomic>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -586,20 +589,43 @@ static int cr_rb(int NB) {
 // modes per workgroup of the fast form, or 0 when it does not apply: 256 threads hold tm * RB rows
 // with at least one equation group, the back substitution's per-thread results fit the register
 // array, and the LDS holds the lines and matrices
+// LDS one workgroup may allocate on the current device (CDNA4: 160 KiB), cached per device
+size_t cr_lds_cap() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return kCrMaxLds;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = (int)kCrMaxLds;
+        v = std::min(v, 160 * 1024);
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return (size_t)std::max(v, (int)kCrMaxLds);
+}
+
 int cr2_modes_per_group(int N, int L, int NB, long long nmodes, int nbox, int want) {
     if (!(NB == 1 || NB == 3 || NB == 7 || NB == 9 || NB == 15)) return 0;
     const int rb = cr_rb(NB);
-    auto valid = [&](int tm) {
-        if (tm < 1 || tm > 8 || (tm & (tm - 1)) || tm * rb > 256) return false;
-        const int E = 256 / (tm * rb);
-        return (1 << (L - 1)) <= E * kCrMaxPerThread && cr2_lds_bytes(N, L, NB, tm) <= kCrMaxLds;
-    };
-    if (want > 0) return valid(want) ? want : 0;
-    for (int tm = 8; tm >= 1; tm /= 2) {
-        if (!valid(tm)) continue;
-        // fewer modes per group while that still leaves under one group per CU
-        if (tm > 1 && (nmodes * nbox + tm - 1) / tm < 256 && cr2_lds_bytes(N, L, NB, tm / 2) <= kCrMaxLds) continue;
-        return tm;
+    // 64 KiB first; the rest of the workgroup LDS only when not even one mode fits that (255 fine
+    // positions with 15-point blocks: 72 KiB per mode), since more LDS per group leaves fewer
+    // groups per CU
+    const size_t caps[2] = {kCrMaxLds, cr_lds_cap()};
+    for (const size_t cap : caps) {
+        auto valid = [&](int tm) {
+            if (tm < 1 || tm > 8 || (tm & (tm - 1)) || tm * rb > 256) return false;
+            const int E = 256 / (tm * rb);
+            return (1 << (L - 1)) <= E * kCrMaxPerThread && cr2_lds_bytes(N, L, NB, tm) <= cap;
+        };
+        if (!valid(1) && !valid(2) && !valid(4) && !valid(8)) continue;
+        if (want > 0) return valid(want) ? want : 0;
+        for (int tm = 8; tm >= 1; tm /= 2) {
+            if (!valid(tm)) continue;
+            // fewer modes per group while that still leaves under one group per CU
+            if (tm > 1 && (nmodes * nbox + tm - 1) / tm < 256 && cr2_lds_bytes(N, L, NB, tm / 2) <= cap) continue;
+            return tm;
+        }
+        return 0;
     }
     return 0;
 }
@@ -614,7 +640,7 @@ bool launch_block_cr(const CrJob &job, hipStream_t st) {
     if (job.fast) {
         const dim3 grid((unsigned)((maxm + job.tm - 1) / job.tm), (unsigned)job.nbox);
         const size_t lds = cr2_lds_bytes(job.N, job.L, job.NB, job.tm);
-        if (lds > kCrMaxLds) return false;
+        if (lds > cr_lds_cap()) return false;
         switch (job.NB) {
             case 1: ASDSM_LAUNCH((k_block_cr2<1, 1>), grid, dim3(256), lds, st, job); return true;
             case 3: ASDSM_LAUNCH((k_block_cr2<3, 4>), grid, dim3(256), lds, st, job); return true;

@@ -61,6 +61,7 @@ struct CrJob {
     int shared_tab;      // 1: every mode uses the one table at box[b].tab (GEMM form only)
 };
 constexpr size_t kCrMaxLds = 64 * 1024;
+size_t cr_lds_cap();  // LDS one workgroup may allocate on the current device (>= kCrMaxLds)
 size_t cr_lds_bytes(int N, int NB, int tm);
 // modes per workgroup of the fast form (want > 0: that count if it is valid), or 0 when the fast
 // form does not apply
