@@ -621,8 +621,10 @@ int cr2_modes_per_group(int N, int L, int NB, long long nmodes, int nbox, int wa
         if (want > 0) return valid(want) ? want : 0;
         for (int tm = 8; tm >= 1; tm /= 2) {
             if (!valid(tm)) continue;
-            // fewer modes per group while that still leaves under one group per CU
+            // fewer modes per group while that still leaves under one group per CU; beyond 64 KiB,
+            // also while two groups would not fit one CU's LDS
             if (tm > 1 && (nmodes * nbox + tm - 1) / tm < 256 && cr2_lds_bytes(N, L, NB, tm / 2) <= cap) continue;
+            if (tm > 1 && cap > kCrMaxLds && 2 * cr2_lds_bytes(N, L, NB, tm) > cap) continue;
             return tm;
         }
         return 0;
