@@ -512,19 +512,37 @@ static bool block_cr_gemm(const CrJob &job, hipStream_t st) {
         g.any_layout = 1;
         g.M = NB;
         g.K = NB;
-        g.nbatch = (int)bx.nmodes;
-        g.sAb = job.shared_tab ? 0 : (long long)L * 3 * MM;
+        g.sAb = 0;
         g.sAi = NB;
         g.sAk = 1;
-        g.sBb = ms;
         g.sBk = sc;
-        g.sCb = ms;
         g.sCi = sc;
+        const long long tstride = (long long)NB << (L - 1);
+        // columns and batches of a level's product: per-mode tables batch over the modes with the
+        // level's equations as columns; one table for every mode (shared_tab) batches over the
+        // equations with the modes as columns, so that each product has many columns
+        const bool shared = job.shared_tab != 0;
+        auto cols = [&](GemmJob &t, int neq, long long b_eq, long long c_eq, long long c_mode) {
+            if (shared) {
+                t.N = (int)bx.nmodes;
+                t.sBn = ms;
+                t.sCn = c_mode;
+                t.nbatch = neq;
+                t.sBb = b_eq;
+                t.sCb = c_eq;
+            } else {
+                t.N = neq;
+                t.sBn = b_eq;
+                t.sCn = c_eq;
+                t.nbatch = (int)bx.nmodes;
+                t.sAb = (long long)L * 3 * MM;
+                t.sBb = ms;
+                t.sCb = c_mode;
+            }
+        };
         for (int l = 0; l <= L - 2; ++l) {  // forward reduction
             const int s = 1 << l, nkeep = (1 << (L - l - 1)) - 1;
-            g.N = nkeep;
-            g.sBn = 2ll * s * sw;
-            g.sCn = 2ll * s * sw;
+            cols(g, nkeep, 2ll * s * sw, 2ll * s * sw, ms);
             g.accum = 1;
             g.neg = 1;
             g.C[0] = W + (2ll * s - 1) * sw;
@@ -535,15 +553,11 @@ static bool block_cr_gemm(const CrJob &job, hipStream_t st) {
             g.B[0] = W + (3ll * s - 1) * sw;
             if (!launch_gemm(g, st)) return false;
         }
-        const long long tstride = (long long)NB << (L - 1);
         for (int l = L - 1; l >= 0; --l) {  // back substitution
             const int s = 1 << l, nel = 1 << (L - l - 1);
             GemmJob t = g;
-            t.sBn = 2ll * s * sw;
-            t.sCb = tstride;
             t.sCi = 1;
-            t.sCn = NB;
-            t.N = nel;
+            cols(t, nel, 2ll * s * sw, NB, tstride);
             t.accum = 0;
             t.neg = 0;
             t.A[0] = bx.tab + (long long)l * 3 * MM;  // G
@@ -551,7 +565,7 @@ static bool block_cr_gemm(const CrJob &job, hipStream_t st) {
             t.C[0] = job.scratch;
             if (!launch_gemm(t, st)) return false;
             if (nel >= 2) {
-                t.N = nel - 1;
+                cols(t, nel - 1, 2ll * s * sw, NB, tstride);
                 t.accum = 1;
                 t.neg = 1;
                 t.A[0] = bx.tab + ((long long)l * 3 + 1) * MM;  // P x_(i-s), equations 1 .. nel-1
