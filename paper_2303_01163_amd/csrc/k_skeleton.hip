@@ -652,10 +652,7 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
         const int c0 = (la == 0) ? l1 : l0, c1 = (la == 2) ? l1 : l2;
         return (long long)blockIdx.x * npts + (long long)ll * (nh * nh) + c0 + nh * c1;
     };
-    if (D == 3 && a.hphase == 2) {
-        for (int o = tid; o < npts; o += 256) bufA[o] = a.hbuf[hoff(o)];
-    }
-    // 1) hole right-hand side
+    // 1) hole right-hand side (phase 2 reads the solved holes from hbuf where it writes the tile)
     for (int o = tid; o < npts && a.hphase != 2; o += 256) {
         int l[kMaxD] = {0, 0, 0, 0}, i[kMaxD] = {0, 0, 0, 0};
         int rem = o;
@@ -788,7 +785,7 @@ __global__ __launch_bounds__(256) void k_filler(Geo g, FillArgs a) {
         if (hole) {
             int lo = 0;
             for (int j = 0; j < D; ++j) lo += l[j] * st[j];
-            v = cur[lo];
+            v = (D == 3 && a.hphase == 2) ? a.hbuf[hoff(lo)] : cur[lo];
         } else {
             int j = 0;
             while (l[j] != n - 1) ++j;
@@ -1366,7 +1363,6 @@ bool launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
         // d = 3, holes of 15^3: right-hand sides to HB, block cyclic reduction over all holes in
         // place (one shared table, the GEMM form), the tiles from HB
         if (d != 3 || nh != 15 || !p.ws.HB) return false;
-        const size_t ldsd = (size_t)2 * npts * sizeof(double);
         a.hbuf = p.ws.HB;
         a.hphase = 1;
         ASDSM_LAUNCH((k_filler<3, 15>), grid, blk, 0, st, p.geo, a);
@@ -1390,7 +1386,7 @@ bool launch_filler(const Plan &p, const double *bff, double *out, hipStream_t st
         bx.sc = 1;
         if (!launch_block_cr(job, st)) return false;
         a.hphase = 2;
-        ASDSM_LAUNCH((k_filler<3, 15>), grid, blk, ldsd, st, p.geo, a);
+        ASDSM_LAUNCH((k_filler<3, 15>), grid, blk, 0, st, p.geo, a);
         return true;
     }
     if (d == 3 && nh == 15) {
